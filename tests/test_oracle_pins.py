@@ -1,0 +1,471 @@
+"""Pins of the FP64 oracle against the paper and against mathematics (no GPU).
+
+Each test checks an oracle function against something other than itself:
+a direct sum, brute-force enumeration, a closed form, an invariant or a
+statistical expectation derived from the paper's definitions.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+import scipy.fft as sfft
+
+import oracle as O
+from synth import catalog as C
+
+
+def rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+# ---------------------------------------------------------------- transforms
+
+def test_forward_dft_matches_direct_sum():
+    n = 6
+    x = rng(1).standard_normal((n, n, n))
+    F = O.forward(x)
+    j = np.arange(n)
+    for nv in [(0, 0, 0), (1, 0, 0), (1, 2, 3), (-2, 1, 1), (2, -1, 2)]:
+        ph = np.exp(-2j * math.pi * (nv[0] * j[:, None, None] + nv[1] * j[None, :, None]
+                                     + nv[2] * j[None, None, :]) / n)
+        direct = np.sum(x * ph)
+        got = O.bispec._lookup(F, n, np.array([nv]))[0]
+        assert abs(got - direct) < 1e-12 * n ** 3
+
+
+def test_shell_field_is_unnormalised_inverse():
+    n = 8
+    spec = np.zeros((n, n, n // 2 + 1), complex)
+    spec[1, 0, 0] = 2.0
+    spec[n - 1, 0, 0] = 2.0  # Hermitian partner
+    D = O.shell_field(spec, np.ones(spec.shape, bool), n)
+    j = np.arange(n)
+    expect = 4.0 * np.cos(2 * math.pi * j / n)
+    assert np.allclose(D[:, 3, 5], expect, atol=1e-12)
+
+
+# ---------------------------------------------------------------- assignment
+
+def test_cic_conserves_mass_and_matches_loop():
+    n = 8
+    r = rng(2)
+    u = [C.quantise_grid_units(r.uniform(0, n, 40), n) for _ in range(3)]
+    w = r.uniform(0.5, 2.0, 40)
+    for shift in (0.0, 0.5):
+        rho = O.assign(*u, n, w, 1, shift)
+        assert abs(rho.sum() - w.sum()) < 1e-12
+        ref = np.zeros((n, n, n))
+        for p in range(40):
+            v = [(float(u[a][p]) + shift) % n for a in range(3)]
+            i0 = [int(math.floor(t)) for t in v]
+            d = [t - i for t, i in zip(v, i0)]
+            for o in itertools.product((0, 1), repeat=3):
+                wt = w[p]
+                for a in range(3):
+                    wt *= d[a] if o[a] else 1 - d[a]
+                ref[(i0[0] + o[0]) % n, (i0[1] + o[1]) % n, (i0[2] + o[2]) % n] += wt
+        assert np.allclose(rho, ref, atol=1e-13)
+
+
+def test_cic_particle_on_node_is_delta_and_ngp_rounds():
+    n = 8
+    rho = O.assign([3.0], [7.0], [0.0], n, None, 1, 0.0)
+    assert rho[3, 7, 0] == 1.0 and rho.sum() == 1.0
+    rho = O.assign([2.5], [2.49], [7.6], n, None, 0, 0.0)
+    assert rho[3, 2, 0] == 1.0
+
+
+def test_compensated_interlaced_point_matches_phase():
+    n = 32
+    u = np.array([[10.3125], [5.75], [21.0625]])
+    spec = []
+    for s in (0.0, 0.5):
+        F = O.forward(O.assign(*u, n, None, 1, s))
+        spec.append(O.compensate(F, n, 1))
+    Fi = O.interlace_combine(spec[0], spec[1], n)
+    fx, fy, fz = O.bispec.half_freq_vectors(n)
+    exact = np.exp(-2j * math.pi * (fx * u[0, 0] + fy * u[1, 0] + fz * u[2, 0]) / n)
+    low = (np.abs(fx) <= 3) & (np.abs(fy) <= 3) & (fz <= 3)
+    low = np.broadcast_to(low, Fi.shape)
+    err_i = np.max(np.abs(Fi - exact)[low])
+    err_0 = np.max(np.abs(spec[0] - exact)[low])
+    # remaining aliases are the even images, |n/(n +- 2N)|^2 ~ 2e-3 per axis and sign
+    assert err_i < 2e-2
+    assert err_i < err_0  # interlacing removes the leading alias
+    wrong = 0.5 * (spec[0] + np.conj(np.exp(1j * math.pi * (fx + fy + fz) / n)) * spec[1])
+    assert np.max(np.abs(wrong - exact)[low]) > 10 * err_i
+
+
+# ---------------------------------------------------------------- LOS moments
+
+@pytest.mark.parametrize("shift", [0.0, 0.5])
+def test_tensor_expansion_matches_direct_legendre(shift):
+    n = 8
+    d = rng(3).standard_normal((n, n, n))
+    obs = np.array([-13.0, -7.0, -20.0])
+    spec = O.spectrum_from_field([d], [shift], n, 4, obs, None)
+    for nv in [(1, 0, 0), (1, 2, 1), (-2, 1, 3), (3, -3, 2), (0, 1, 1)]:
+        for li, ell in enumerate((0, 2, 4)):
+            g = O.bispec._lookup(spec[li], n, np.array([nv]))[0]
+            ref = O.legendre_moments_direct(d, nv, ell, shift, obs)
+            assert abs(g - ref) < 1e-10 * (1 + abs(ref)), (nv, ell, g, ref)
+
+
+def test_plane_parallel_direct_and_far_observer_limit():
+    n = 8
+    d = rng(4).standard_normal((n, n, n))
+    pp = O.spectrum_from_field([d], [0.0], n, 4, None, None)
+    for nv in [(1, 2, 1), (0, 0, 2), (-3, 1, 2)]:
+        for li, ell in enumerate((0, 2, 4)):
+            g = O.bispec._lookup(pp[li], n, np.array([nv]))[0]
+            ref = O.legendre_moments_direct(d, nv, ell, 0.0, None)
+            assert abs(g - ref) < 1e-10 * (1 + abs(ref))
+    far = O.spectrum_from_field([d], [0.0], n, 4, np.array([3.5, 3.5, -1e8]), None)
+    for li in range(3):
+        assert np.max(np.abs(far[li] - pp[li])) < 1e-5 * np.max(np.abs(pp[li]))
+
+
+def test_kaiser_multipole_ratios():
+    n, f = 48, 0.6
+    r = rng(5)
+    n2 = O.n2_grid_half(n)
+    ph = np.exp(2j * math.pi * r.uniform(size=n2.shape))
+    fx, fy, fz = O.bispec.half_freq_vectors(n)
+    kn = np.sqrt(np.maximum(n2, 1))
+    mu = fz / kn
+    g_real = sfft.irfftn(ph, s=(n,) * 3)  # any Hermitian-consistent field
+    g = O.forward(g_real)
+    g = g / np.maximum(np.abs(g), 1e-300)  # unit amplitude, random phase
+    ds = (1 + f * mu ** 2) * g
+    spec = O.spectrum_from_field([sfft.irfftn(ds, s=(n,) * 3)], [0.0], n, 4, None, None)
+    shell = (n2 >= 12 ** 2) & (n2 < 20 ** 2)
+    # half spectrum: nz > 0 entries stand for themselves and their conjugate partner
+    mult = np.broadcast_to(np.where(fz > 0, 2.0, 1.0), n2.shape)[shell]
+    def avg(x):
+        return float(np.sum(x[shell] * mult) / np.sum(mult))
+    p0 = avg(np.real(spec[0] * np.conj(spec[0])))
+    expect = [1 + 2 * f / 3 + f ** 2 / 5, 4 * f / 3 + 4 * f ** 2 / 7, 8 * f ** 2 / 35]
+    for li in range(3):
+        pl = avg(np.real(spec[li] * np.conj(spec[0])))
+        assert abs(pl - expect[li]) < 0.01 * expect[0], (li, pl, expect[li])
+    assert abs(p0 - expect[0]) < 0.01 * expect[0]
+
+
+# ---------------------------------------------------------------- shells
+
+def test_bins_integer_edges_and_isotropy():
+    k0, dk, nb = 3.0, 3.0, 6
+    lo, hi = O.bin_edges4(k0, dk, nb)
+    assert list(lo) == [(2 * (k0 + b * dk) - dk) ** 2 for b in range(nb)]
+    r = np.arange(-20, 21)
+    nx, ny, nz = np.meshgrid(r, r, r, indexing="ij")
+    n2 = nx ** 2 + ny ** 2 + nz ** 2
+    b = O.bin_of_n2(n2, k0, dk, nb)
+    for i in range(nb):
+        sel = b == i
+        k = np.sqrt(n2[sel])
+        assert k.min() >= k0 + i * dk - dk / 2 and k.max() < k0 + i * dk + dk / 2
+        assert int(((3 * nz ** 2 - n2)[sel]).sum()) == 0  # sum of L_2 over a shell vanishes
+    assert b[20, 20, 20] == -1
+
+
+# ---------------------------------------------------------------- closed triangles
+
+def _random_spec(n, seed):
+    return O.forward(rng(seed).standard_normal((n, n, n)))
+
+
+@pytest.mark.parametrize("n,k0,dk,nb", [(8, 1.0, 1.0, 2), (16, 1.5, 1.0, 4), (16, 2.0, 2.0, 2)])
+def test_fft_triple_sum_equals_brute_force_closed_triangles(n, k0, dk, nb):
+    spec = [_random_spec(n, 10 + i) for i in range(2)]
+    lo, hi = O.bin_edges4(k0, dk, nb)
+    tris, T = O.binned_triple_sums(spec, n, n, k0, dk, nb)
+    scale = np.abs(T).max() / n ** 3
+    for ti, (b1, b2, b3) in enumerate(tris):
+        masks = [lambda q, b=b: (4 * q >= lo[b]) & (4 * q < hi[b]) for b in (b1, b2, b3)]
+        for li in range(2):
+            ref = O.closed_triangle_sum_brute([spec[li], spec[0], spec[0]], n, masks, modular=True)
+            got = T[li, ti] / n ** 3
+            assert abs(got - ref.real) < 1e-10 * scale, (b1, b2, b3, li, got, ref)
+            assert abs(ref.imag) < 1e-10 * scale
+
+
+def test_modular_equals_exact_closure_without_alias_and_differs_with():
+    n = 16
+    spec = _random_spec(n, 21)
+    m = [lambda q: (q >= 4) & (q < 25)] * 3  # |n| in [2, 5): 3c = 12 < 16
+    a = O.closed_triangle_sum_brute([spec] * 3, n, m, modular=True)
+    b = O.closed_triangle_sum_brute([spec] * 3, n, m, modular=False)
+    assert abs(a - b) < 1e-9 * abs(a)
+    m = [lambda q: (q >= 16) & (q < 49)] * 3  # |n| in [4, 7): 3c = 18 > 16 wraps
+    a = O.closed_triangle_sum_brute([spec] * 3, n, m, modular=True)
+    b = O.closed_triangle_sum_brute([spec] * 3, n, m, modular=False)
+    assert abs(a - b) > 1e-6 * abs(a)
+
+
+@pytest.mark.parametrize("k0,dk,nb,n", [(2.0, 2.0, 4, 32), (3.0, 3.0, 3, 32), (1.0, 1.0, 5, 16)])
+def test_counts_fft_match_enumeration(k0, dk, nb, n):
+    tris, cnt, resid = O.triangle_counts_fft(n, k0, dk, nb)
+    assert resid < 1e-6
+    brute = O.triangle_counts_brute(k0, dk, nb, tris)
+    assert np.array_equal(cnt, brute)
+    # independence of N' once 3 c < N'
+    _, cnt2, _ = O.triangle_counts_fft(n + 8, k0, dk, nb)
+    assert np.array_equal(cnt, cnt2)
+
+
+def test_counts_golden_c1():
+    """C1 bins (dk = 2, 10 bins): FFT counts against the enumerated golden table."""
+    path = __file__.replace("test_oracle_pins.py", "golden/counts_k2_d2_nb10.txt")
+    gold = np.loadtxt(path, dtype=np.int64, comments="#")
+    tris, cnt, resid = O.triangle_counts_fft(64, 2.0, 2.0, 10)
+    assert resid < 1e-6
+    assert np.array_equal(np.array(tris), gold[:, :3])
+    assert np.array_equal(cnt, gold[:, 3])
+
+
+def test_counts_symmetry_and_continuum():
+    k0, dk, nb = 4.0, 4.0, 4
+    tris, cnt, _ = O.triangle_counts_fft(64, k0, dk, nb)
+    # permutation symmetry: count a triangle in another side order by enumeration
+    lo, hi = O.bin_edges4(k0, dk, nb)
+    t = (3, 2, 1)
+    i = tris.index(t)
+    perm = O.triangle_counts_brute(k0, dk, nb, [(1, 3, 2)])  # not canonical order
+    assert perm[0] == cnt[i]
+    # continuum: N_tri ~ 8 pi^2 c1 c2 c3 dk^3 for a non-degenerate triangle
+    c = [k0 + b * dk for b in t]
+    approx = 8 * math.pi ** 2 * c[0] * c[1] * c[2] * dk ** 3
+    assert abs(cnt[i] / approx - 1) < 0.1
+
+
+def test_crop_identity():
+    n, nr = 32, 20
+    spec = [_random_spec(n, 30)]
+    _, T1 = O.binned_triple_sums(spec, n, n, 2.0, 2.0, 3)
+    _, T2 = O.binned_triple_sums(spec, n, nr, 2.0, 2.0, 3)
+    assert np.allclose(T1 / n ** 3, T2 / nr ** 3, rtol=1e-10, atol=1e-9 * np.abs(T1 / n ** 3).max())
+
+
+# ---------------------------------------------------------------- statistics
+
+def _gaussian_lattice_field(n, seed, power):
+    """Gaussian field with E|g(n)|^2 = N^3 p(n)."""
+    w = rng(seed).standard_normal((n, n, n))
+    W = O.forward(w)
+    return sfft.irfftn(W * np.sqrt(power), s=(n,) * 3)
+
+
+def _stat_setup():
+    n, k0, dk, nb = 24, 2.0, 2.0, 3
+    n2 = O.n2_grid_half(n)
+    k = np.sqrt(np.maximum(n2, 1))
+    p = 1.0 / (1.0 + (k / 4.0) ** 2)
+    p[0, 0, 0] = 0.0
+    return n, k0, dk, nb, p
+
+
+def _zscores(samples, expect):
+    s = np.asarray(samples)
+    m = s.mean(0)
+    se = s.std(0, ddof=1) / math.sqrt(s.shape[0])
+    return (m - expect) / se
+
+
+def test_gaussian_field_bispectrum_zero_mean():
+    n, k0, dk, nb, p = _stat_setup()
+    tris, cnt, _ = O.triangle_counts_fft(n, k0, dk, nb)
+    keep = [i for i in range(len(tris)) if cnt[i] > 0]
+    tk = [tris[i] for i in keep]
+    R = 64
+    out = []
+    for r in range(R):
+        g = _gaussian_lattice_field(n, 100 + r, p)
+        spec = O.spectrum_from_field([g], [0.0], n, 4, None, None)
+        _, T = O.binned_triple_sums(spec, n, n, k0, dk, nb, tk)
+        out.append(O.binned_bispectrum(T, cnt[keep], n, n, 1.0).ravel())
+    z = _zscores(out, 0.0)
+    nu = z.size
+    assert np.max(np.abs(z)) < 5
+    assert abs(np.sum(z ** 2) / nu - 1) < 5 * math.sqrt(2 / nu)
+
+
+def test_quadratic_field_matches_tree_level_closed_form():
+    """delta = g + b2 (g^2 - <g^2>):
+    E[sum_closed delta^l delta delta] = 2 b2 N^3 sum_closed (2l+1) L_l(mu1) [p1p2 + p2p3 + p3p1]
+    (plane parallel, no RSD) to O(b2^3)."""
+    n, k0, dk, nb, p = _stat_setup()
+    b2 = 0.1 / math.sqrt(float(p.sum() * 2) / n ** 3)
+    tris, cnt, _ = O.triangle_counts_fft(n, k0, dk, nb)
+    keep = [i for i in range(len(tris)) if cnt[i] > 0]
+    tk = [tris[i] for i in keep]
+    # expected T / N^3 via weighted unit fields
+    n2 = O.n2_grid_half(n)
+    bins = O.bin_of_n2(n2, k0, dk, nb)
+    fx, fy, fz = O.bispec.half_freq_vectors(n)
+    mu = fz / np.sqrt(np.maximum(n2, 1))
+    def fld(a):
+        return O.shell_field(np.ones(n2.shape, complex) * a, np.ones(n2.shape, bool), n).ravel()
+    expect = np.zeros((3, len(tk)))
+    for li, ell in enumerate((0, 2, 4)):
+        Lw = (2 * ell + 1) * O.bispec.legendre_poly(ell, mu)
+        for ti, (b1, b2_, b3) in enumerate(tk):
+            m1, m2, m3 = (bins == b1), (bins == b2_), (bins == b3)
+            I1p, I1 = fld(Lw * p * m1), fld(Lw * m1)
+            I2p, I2 = fld(p * m2), fld(m2 * 1.0)
+            I3p, I3 = fld(p * m3), fld(m3 * 1.0)
+            s = (np.dot(I1p * I2p, I3) + np.dot(I1 * I2p, I3p) + np.dot(I1p * I2, I3p)) / n ** 3
+            expect[li, ti] = 2 * b2 * n ** 3 * s
+    R = 64
+    out = []
+    for r in range(R):
+        g = _gaussian_lattice_field(n, 500 + r, p)
+        d = g + b2 * (g * g - np.mean(g * g))
+        spec = O.spectrum_from_field([d], [0.0], n, 4, None, None)
+        _, T = O.binned_triple_sums(spec, n, n, k0, dk, nb, tk)
+        out.append((T / n ** 3).ravel())
+    z = _zscores(out, expect.ravel())
+    assert np.max(np.abs(z)) < 5, np.max(np.abs(z))
+    # sensitivity: the expectation is detected far above the noise
+    zz = _zscores(out, 0.0)
+    assert np.max(np.abs(zz)) > 8
+    # a factor-2 error in the closed form would be caught
+    assert np.max(np.abs(_zscores(out, 2 * expect.ravel()))) > 5
+    assert np.max(np.abs(_zscores(out, 0.5 * expect.ravel()))) > 5
+
+
+def test_poisson_shot_noise_formula_unbiased():
+    """Uniform Poisson counts per node-centred cell, NGP, no compensation:
+    E[Pbar] = 1/nbar and E[B0] = 1/nbar^2, so E[B0_sub] = 0."""
+    n, box, lam = 16, 100.0, 0.5
+    k0, dk, nb = 2.0, 2.0, 2
+    tris, cnt, _ = O.triangle_counts_fft(n, k0, dk, nb)
+    keep = [i for i in range(len(tris)) if cnt[i] > 0]
+    tk = [tris[i] for i in keep]
+    nbar = lam * n ** 3 / box ** 3
+    subs, ps, b0 = [], [], []
+    for r in range(80):
+        u = C.poisson_node_catalogue(n, lam, 900 + r)
+        spec, wsum = O.spectrum_from_catalogue(*u, n, 0, None, window=0, compensate_window=False)
+        _, T = O.binned_triple_sums(spec, n, n, k0, dk, nb, tk)
+        B = O.binned_bispectrum(T, cnt[keep], n, n, box)
+        P, _ = O.shell_power(spec[0], n, k0, dk, nb, box)
+        nb_real = wsum / box ** 3
+        subs.append(O.shot_noise_binned(B[0], P, tk, nb_real))
+        ps.append(P * nbar)
+        b0.append(B[0] * nbar ** 2)
+    assert np.max(np.abs(_zscores(ps, 1.0))) < 5
+    assert np.max(np.abs(_zscores(b0, 1.0))) < 5
+    assert np.max(np.abs(_zscores(subs, 0.0))) < 5
+
+
+# ---------------------------------------------------------------- modal
+
+def _modal_geo(n=16):
+    k0, dk, nb = 1.5, 1.0, 4  # modal range [1, 5)
+    P, nm = 3, 10
+    box = 200.0
+    kf = 2 * math.pi / box
+    n2max = 3 * n * n
+    kk = kf * np.sqrt(np.arange(n2max + 1))
+    pfid = 1000.0 / (1 + (kk / 0.1) ** 2) + 50.0
+    return dict(n=n, k0=k0, dk=dk, nb=nb, P=P, nm=nm, box=box, kf=kf, pfid=pfid,
+                kmin=k0 - dk / 2, kmax=k0 + (nb - 1) * dk + dk / 2)
+
+
+def test_mode_table_order():
+    m = O.modal_modes(3, 10)
+    assert [tuple(x) for x in m] == [(0, 0, 0), (0, 0, 1), (0, 1, 1), (0, 0, 2), (1, 1, 1),
+                                     (0, 1, 2), (1, 1, 2), (0, 2, 2), (1, 2, 2), (2, 2, 2)]
+    assert len(O.modal_modes(8, 100)) == 100
+
+
+def test_modal_numerators_match_brute_force():
+    g = _modal_geo()
+    n = g["n"]
+    spec = O.spectrum_from_field([rng(40).standard_normal((n, n, n))], [0.0], n, 2, None, None)
+    modes = O.modal_modes(g["P"], g["nm"])
+    b = O.modal_numerators(spec, n, n, modes, g["P"], g["kmin"], g["kmax"], g["kf"], g["pfid"])
+    n2 = O.n2_grid_half(n)
+    filt = [O.modal_filter(p, n2, g["kmin"], g["kmax"], g["kf"], g["pfid"]) for p in range(g["P"])]
+    fs = {(li, p): spec[li] * filt[p] for li in range(2) for p in range(g["P"])}
+    rng_m = [lambda q: O.bispec.in_modal_range(q, g["kmin"], g["kmax"])] * 3
+    for i, (p, r, s) in enumerate(modes):
+        ref0 = O.closed_triangle_sum_brute([fs[0, p], fs[0, r], fs[0, s]], n, rng_m).real / n ** 9
+        assert abs(b[0, i] - ref0) < 1e-9 * (1e-30 + abs(ref0)) + 1e-12 * np.abs(b[0]).max()
+        ref2 = sum(O.closed_triangle_sum_brute([fs[a, p], fs[bb, r], fs[c, s]], n, rng_m).real
+                   for a, bb, c in [(1, 0, 0), (0, 1, 0), (0, 0, 1)]) / n ** 9
+        assert abs(b[1, i] - ref2) < 1e-9 * abs(ref2) + 1e-12 * np.abs(b[1]).max()
+
+
+def test_gram_matches_enumeration_and_continuum():
+    g = _modal_geo(16)
+    modes = O.modal_modes(g["P"], g["nm"])
+    gam = O.gram_matrix(16, modes, g["P"], g["kmin"], g["kmax"], g["kf"], g["box"])
+    # brute force: V^-2 sum over closed triangles of Q_n Q_m / (k1 k2 k3)
+    cm = 4
+    r = np.arange(-cm, cm + 1)
+    nx, ny, nz = np.meshgrid(r, r, r, indexing="ij")
+    v = np.stack([nx.ravel(), ny.ravel(), nz.ravel()], 1)
+    n2 = (v ** 2).sum(1)
+    v = v[O.bispec.in_modal_range(n2, g["kmin"], g["kmax"])]
+    kn = np.sqrt((v ** 2).sum(1))
+    n3 = -(v[:, None, :] + v[None, :, :])
+    k3 = np.sqrt((n3 ** 2).sum(-1))
+    ok = O.bispec.in_modal_range((n3 ** 2).sum(-1), g["kmin"], g["kmax"])
+    k1 = np.broadcast_to(kn[:, None], k3.shape)[ok]
+    k2 = np.broadcast_to(kn[None, :], k3.shape)[ok]
+    k3 = k3[ok]
+    q = lambda p, k: O.modal_q(p, k, g["kmin"], g["kmax"])
+    def Q(m):
+        return sum(q(x, k1) * q(y, k2) * q(z, k3) for x, y, z in itertools.permutations(tuple(m))) / 6.0
+    Qs = [Q(m) for m in modes]
+    kf = g["kf"]
+    V = g["box"] ** 3
+    brute = np.array([[np.sum(Qs[i] * Qs[j] / (kf ** 3 * k1 * k2 * k3)) for j in range(len(modes))]
+                      for i in range(len(modes))]) / V ** 2
+    assert np.allclose(gam, brute, rtol=1e-9, atol=1e-12 * np.abs(brute).max())
+    # positive definite, so the Cholesky orthonormalisation exists
+    assert np.all(np.linalg.eigvalsh(gam) > 0)
+
+
+def test_gram_continuum_reduction():
+    """Wide shells: the lattice gamma approaches (1/(8 pi^4)) int_V dk1 dk2 dk3 Q_n Q_m."""
+    n, kmin, kmax = 48, 6.0, 14.0
+    box = 2 * math.pi  # k_f = 1
+    modes = O.modal_modes(2, 4)
+    gam = O.gram_matrix(n, modes, 2, kmin, kmax, 1.0, box)
+    # continuum integral on a fine midpoint grid over the tetrapyd
+    m = 120
+    ks = kmin + (np.arange(m) + 0.5) * (kmax - kmin) / m
+    K1, K2, K3 = np.meshgrid(ks, ks, ks, indexing="ij")
+    tet = (2 * np.maximum(np.maximum(K1, K2), K3) <= K1 + K2 + K3)
+    q = lambda p, k: O.modal_q(p, k, kmin, kmax)
+    def Q(mm):
+        return sum(q(a, K1) * q(b, K2) * q(c, K3) for a, b, c in itertools.permutations(mm)) / 6.0
+    dv = ((kmax - kmin) / m) ** 3
+    cont = np.array([[np.sum((Q(a) * Q(b))[tet]) * dv / (8 * math.pi ** 4) for b in modes] for a in modes])
+    V = box ** 3
+    # the lattice gamma carries V^-2 and sums over modes (density V/(2pi)^3 per k-volume)
+    assert np.allclose(gam, cont, rtol=0.06, atol=0.02 * np.abs(cont).max())
+
+
+def test_modal_template_recovery():
+    g = _modal_geo(16)
+    modes = O.modal_modes(g["P"], g["nm"])
+    gam = O.gram_matrix(16, modes, g["P"], g["kmin"], g["kmax"], g["kf"], g["box"])
+    bt = rng(41).standard_normal((3, len(modes)))
+    b = bt @ gam  # numerators of the separable template w^-1 sum beta_n Q_n
+    alpha, beta = O.modal_solve(gam, b)
+    assert np.allclose(beta, bt, rtol=1e-8, atol=1e-8)
+    L = np.linalg.cholesky(gam)
+    assert np.allclose(L @ alpha.T, b.T, rtol=1e-10, atol=1e-12 * np.abs(b).max())
+
+
+def test_batch_covariance_definition():
+    x = rng(43).standard_normal((50, 4))
+    c = O.batch_covariance(x)
+    d = x - x.mean(0)
+    ref = sum(np.outer(d[i], d[i]) for i in range(50)) / 49
+    assert np.allclose(c, ref)
