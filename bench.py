@@ -1,0 +1,253 @@
+#!/usr/bin/env python
+"""Throughput of the bispectrum-multipole + modal estimator on one MI355X.
+
+One step = the whole hot path for one synthetic catalogue resident in HBM:
+CIC assignment to two interlaced 512^3 grids, 2 x 22 forward transforms with
+x-hat line-of-sight weights, Legendre moments l = 0, 2, 4, 90 shell fields and
+24 modal fields (inverse transforms), one triple reduction (binned B_0,2,4 on
+every closed triangle and 100 modal numerators per l), FP64 normalisation,
+shot noise and the Cholesky solves for beta. Geometry (triangle counts, Gram
+matrix) is computed once before the timed region.
+
+Prints one JSON line. `value` is mocks/s of the mixed-precision path
+(--prec, default bf16x3); the FP32 path is timed the same way and reported
+beside it, with the mixed-vs-FP32 difference of B_l and beta.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM = 8.0e12          # B/s
+PEAK_MFMA = {"fp32": 157.3e12, "bf16x3": 2.5e15, "fp16x3": 2.5e15}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def stage_bytes_flops(info, geom, nl, F, fb_batches, rp_entries, npairs, K):
+    """Algorithmic bytes (or flops) per launch of each stage, from the sizes of
+    the arrays each pass must read and write once (complex64 = 8 B, float = 4 B)."""
+    N = geom["n"]
+    Nr = geom["nr"]
+    c = info.c
+    w = 2 * c + 1
+    C1 = c + 1
+    G = geom["ngrid"]
+    L = info.nlos
+    s = {}
+    s["assign"] = (geom["np"] * 12 + G * N ** 3 * 4 * 2, "B")  # read particles, read+write grids (atomics)
+    s["fwd_z"] = (G * N ** 3 * 4 + G * L * N * N * C1 * 8, "B")
+    s["fwd_y"] = (G * L * N * N * C1 * 8 + G * L * N * w * C1 * 8, "B")
+    s["fwd_x"] = (G * L * N * w * C1 * 8 + G * L * w * w * C1 * 8, "B")
+    s["los_combine"] = (G * L * w * w * C1 * 8 + nl * w * w * C1 * 8, "B")
+    per_field = {
+        "inv_x_filter": w * w * C1 * 8 + Nr * w * C1 * 8,
+        "inv_y": Nr * w * C1 * 8 + Nr * Nr * C1 * 8,
+        "inv_z": Nr * Nr * C1 * 8 + Nr ** 3 * 4,
+    }
+    for k, v in per_field.items():
+        s[k] = (v * F / fb_batches, "B")
+    # reduction: one FMA per needed (pair, third) entry per point + pair products
+    s["reduce"] = ((2 * rp_entries + npairs) * K, "flop")
+    s["reduce_read"] = (F * K * 4, "B")
+    return s
+
+
+def cpu_baseline(wl, u, pfid, modes, log_fn):
+    """The FP64 oracle timed on a bounded sample of one 512^3 mock, extrapolated
+    to a full mock: full CIC assignment of both grids; one of the 44 weighted
+    forward transforms; one of the 114 shell/modal inverse transforms; a
+    sample of the triple-sum dot products."""
+    import numpy as np
+    import oracle as O
+    n = wl.n
+    t = {}
+    t0 = time.perf_counter()
+    rho = [O.assign(*u, n, None, 1, s) for s in (0.0, 0.5)]
+    t["assign_2grids"] = time.perf_counter() - t0
+    wsum = float(u[0].size)
+    obs = np.array([-(1500.0 / math.sqrt(3.0)) * n / wl.box] * 3)
+    t0 = time.perf_counter()
+    d = O.density_contrast(rho[0], wsum)
+    xh = O.bispec.node_unit_vectors(n, 0.0, obs)
+    f = O.los_weighted_field(d, (0, 1), xh)
+    F = O.forward(f)
+    t["one_weighted_forward"] = time.perf_counter() - t0
+    del rho, f, xh
+    t0 = time.perf_counter()
+    n2 = O.n2_grid_half(n)
+    bins = O.bin_of_n2(n2, wl.k0, wl.dk, wl.nbins)
+    D1 = O.shell_field(F, bins == 12, n).ravel()
+    t["one_inverse_field"] = time.perf_counter() - t0
+    D2 = O.shell_field(F, bins == 7, n).ravel()
+    reps = 8
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        float(np.dot(D1 * D2, D1))
+    t["one_triple_dot"] = (time.perf_counter() - t0) / reps
+    nl, nb, P = 3, wl.nbins, wl.P
+    nfield = nl * (nb + P)
+    ntri_dots = 3035 * nl + 100 * 10  # binned triangles x l, modal placements
+    per_mock = (t["assign_2grids"] + 44 * t["one_weighted_forward"] + nfield * t["one_inverse_field"]
+                + ntri_dots * t["one_triple_dot"])
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    sample_s = sum(t.values()) + (reps - 1) * t["one_triple_dot"] + t["one_inverse_field"]
+    log_fn("cpu oracle sample timings (s):", {k: round(v, 3) for k, v in t.items()})
+    return {"value": 1.0 / per_mock, "unit": "mocks/s", "cores": cores, "kind": "oracle",
+            "sample": (f"FP64 oracle on one 512^3 mock: CIC assignment of 1e7 particles to 2 grids, 1 of 44 "
+                       f"LOS-weighted forward FFTs, 1 of {nfield} inverse shell FFTs, {reps} of {ntri_dots} "
+                       f"triple-sum dot products; extrapolated per mock ({per_mock:.1f} s/mock, "
+                       f"{sample_s:.1f} s measured)")}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c3_512")
+    ap.add_argument("--prec", default="bf16x3", choices=["bf16x3", "fp16x3", "fp32"])
+    ap.add_argument("--no-fp32", action="store_true", help="skip timing the FP32 path")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1708_05303_amd as B
+    from synth import catalog as C
+
+    wl = C.workload(args.workload)
+    dev = torch.device("cuda:0")
+    log(f"generating catalogue {wl.name} (N={wl.n}, {wl.nparticles} particles)")
+    t0 = time.time()
+    u = C.lognormal_catalogue(wl)
+    log(f"  {u[0].size} particles in {time.time() - t0:.1f} s")
+    obs = C.observer_grid_units(wl)
+    kf = 2 * math.pi / wl.box
+    pin = C.input_power(wl)
+    n2len = 3 * ((wl.nbins + 1) * int(wl.dk) + int(wl.k0) + 2) ** 2
+    k = kf * np.sqrt(np.arange(n2len, dtype=np.float64))
+    pfid = (1 + 2 * wl.f / 3 + wl.f ** 2 / 5) * pin(k) + 1.0 / wl.nbar
+    pfid[0] = pfid[1]
+    plan = B.Plan(n=wl.n, n_reduce=wl.n_reduce, box=wl.box, nbins=wl.nbins, k0=wl.k0, dk=wl.dk, lmax=wl.lmax,
+                  window=wl.window, compensate=1, interlace=wl.interlace, los=wl.los, observer=obs, P=wl.P,
+                  nmodes=wl.nmodes, pfid=pfid, device="cuda:0")
+    log(f"workspace {plan.ws.numel() / 2**30:.1f} GiB; precompute ...")
+    t0 = time.time()
+    plan.precompute()
+    torch.cuda.synchronize()
+    log(f"  precompute {time.time() - t0:.1f} s, {plan.info.ntri} triangles")
+    nl = plan.info.nl
+    ntri = plan.info.ntri
+    ux, uy, uz = (torch.as_tensor(a).to(dev) for a in u)
+    npart = u[0].size
+
+    def outputs():
+        return dict(B=torch.zeros((nl, ntri), dtype=torch.float64, device=dev),
+                    B0=torch.zeros(ntri, dtype=torch.float64, device=dev),
+                    Pb=torch.zeros(wl.nbins, dtype=torch.float64, device=dev),
+                    bn=torch.zeros((nl, wl.nmodes), dtype=torch.float64, device=dev),
+                    al=torch.zeros((nl, wl.nmodes), dtype=torch.float64, device=dev),
+                    be=torch.zeros((nl, wl.nmodes), dtype=torch.float64, device=dev))
+
+    def step(prec, o):
+        B.bsp_bispectrum_multipoles(plan.handle, ux, uy, uz, None, npart, prec, o["B"], o["B0"], o["Pb"], o["bn"],
+                                    o["al"], o["be"])
+
+    def timed(prec, steps, warmup, with_stages):
+        o = outputs()
+        for i in range(warmup):
+            step(prec, o)
+            plan.sync()
+            log(f"  warmup {i + 1}/{warmup} ({args.prec if prec else 'fp32'})")
+        if with_stages:
+            B.bsp_set_timing(plan.handle, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            step(prec, o)
+        plan.sync()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        stages = B.bsp_stage_times(plan.handle) if with_stages else None
+        if with_stages:
+            B.bsp_set_timing(plan.handle, False)
+        log(f"  timed {steps} steps: {dt / steps * 1e3:.2f} ms/step")
+        return dt / steps, o, stages
+
+    prec = B.PRECISIONS[args.prec]
+    t_mix, o_mix, stages = timed(prec, args.steps, args.warmup, True)
+    res = {"metric": "mocks/sec for B_0,2,4 + 100 modal coeffs at 512^3, mixed vs FP32 at stated err",
+           "value": 1.0 / t_mix, "unit": "mocks/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": t_mix * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": {"bf16x3": "f32+bf16x3", "fp16x3": "f32+fp16x3", "fp32": "f32"}[args.prec],
+           "data": "synthetic lognormal mock, Kaiser RSD, seeded",
+           "config": {"workload": f"{wl.name}: N={wl.n}^3 (N'={wl.n_reduce}), {wl.nparticles:.0e} particles, "
+                                  f"CIC+interlace, varying LOS (observer 1500 Mpc/h), l<=4, {wl.nbins} bins "
+                                  f"dk={wl.dk:g}kf, {wl.nmodes} modes P={wl.P}",
+                      "precision": args.prec, "ntri": int(ntri), "particles": int(npart)}}
+    if not args.no_fp32 and args.prec != "fp32":
+        t32, o32, _ = timed(B.BSP_FP32, args.steps, 1, False)
+        res["fp32_mocks_per_sec"] = 1.0 / t32
+        res["fp32_ms_per_step"] = t32 * 1e3
+        res["mixed_over_fp32"] = t32 / t_mix
+
+        def rel(a, b):
+            a, b = a.cpu().numpy(), b.cpu().numpy()
+            return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+        res["err_mixed_vs_fp32"] = {f"B{2 * li}": rel(o_mix["B"][li], o32["B"][li]) for li in range(nl)}
+        res["err_mixed_vs_fp32"].update({f"beta{2 * li}": rel(o_mix["be"][li], o32["be"][li]) for li in range(nl)})
+    # roofline of the dominant kernel, from the event timings of the timed region
+    rp = plan  # schedule sizes
+    K = wl.n_reduce ** 3
+    F = plan.info.nfields_binned + plan.info.nfields_modal
+    geom = dict(n=wl.n, nr=wl.n_reduce, ngrid=2 if wl.interlace else 1, np=npart)
+    nmain_entries = ntri * nl + wl.nmodes * (1 + 3 + 6)
+    npairs = wl.nbins * (wl.nbins + 1) // 2 + 2 * (wl.P * (wl.P + 1) // 2)
+    inv_launches = max(stages["inv_z"][1] // args.steps, 1)
+    sb = stage_bytes_flops(plan.info, geom, nl, F, inv_launches, nmain_entries, npairs, K)
+    per_stage = {}
+    for name, (ms, nlaunch) in stages.items():
+        if nlaunch == 0:
+            continue
+        avg = ms / nlaunch * 1e-3
+        amount, unit = sb[name] if name in sb else (None, None)
+        e = {"ms_per_step": ms / args.steps, "launches_per_step": nlaunch / args.steps, "avg_launch_ms": avg * 1e3}
+        if amount is not None:
+            if unit == "B":
+                e["achieved_GBps"] = amount / avg / 1e9
+                e["frac_hbm"] = amount / avg / PEAK_HBM
+            else:
+                e["achieved_TFLOPs"] = amount / avg / 1e12
+                e["frac_mfma"] = amount / avg / PEAK_MFMA[args.prec]
+        per_stage[name] = e
+    res["stages"] = per_stage
+    dom = max(per_stage, key=lambda k: per_stage[k]["ms_per_step"])
+    d = per_stage[dom]
+    if dom == "reduce":
+        res["roofline"] = {"kernel": "k_reduce", "bound": "mfma", "achieved": d["achieved_TFLOPs"],
+                           "peak": PEAK_MFMA[args.prec] / 1e12, "unit": "TFLOP/s", "frac": d["frac_mfma"],
+                           "traffic": None}
+    else:
+        res["roofline"] = {"kernel": dom, "bound": "hbm", "achieved": d["achieved_GBps"], "peak": PEAK_HBM / 1e9,
+                           "unit": "GB/s", "frac": d["frac_hbm"], "traffic": None}
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample ...")
+        res["cpu_baseline"] = cpu_baseline(wl, u, pfid, None, log)
+    print(json.dumps(res), flush=True)
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

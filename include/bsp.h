@@ -1,0 +1,236 @@
+/*
+ * bsp.h -- C ABI of libbsp, an MI355X (gfx950) implementation of the FFT
+ * bispectrum-multipole and modal estimators of
+ *   D. Regan, "An Inventory of Bispectrum Estimators for Redshift Space
+ *   Distortions", arXiv:1708.05303.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Ownership: every array argument is caller-owned. Pointers documented as
+ *   "device" must point to device memory of the plan's GPU; "host" pointers to
+ *   host memory. The library keeps no reference to any argument after a call
+ *   returns, except the workspace given to bsp_set_workspace.
+ * Asynchrony: compute calls are enqueued on the plan's stream and return at
+ *   once; results are valid after bsp_sync. Host arguments are consumed before
+ *   the call returns.
+ * Errors: argument errors are returned synchronously; the message is available
+ *   from bsp_last_error. Errors found by kernels (particle out of range, count
+ *   residual, Cholesky failure) are latched on the device and returned by the
+ *   next bsp_sync.
+ * Threading: a plan is not thread safe; use one plan per stream.
+ * Memory: bsp_plan_create allocates the plan's small constant tables
+ *   (twiddles, shell and modal filter tables, reduction schedules; a few MB);
+ *   all large scratch comes from the caller's workspace (bsp_workspace_size).
+ *
+ * Lattice conventions
+ * -------------------
+ * Wavevector k = k_f n with integer n, k_f = 2 pi / L, V = L^3.
+ * Forward DFT X(n) = sum_j x(j) exp(-2 pi i n.j / N); inverse
+ * x(j) = sum_n X(n) exp(+2 pi i n.j / N); both unnormalised.
+ * Real grids are [N][N][N] float, z fastest. Standard half spectra are
+ * [N][N][N/2+1] interleaved complex (re, im).
+ * Shell b (b = 0 .. nbins-1) has centre c_b = k0 + b dk in units of k_f and holds
+ * the n with (2 c_b - dk)^2 <= 4 |n|^2 < (2 c_b + dk)^2 (the "q in [k +- dk/2]"
+ * shells of the standard estimator, Sec. 3.1); 2 k0 and dk must be integers.
+ * c = floor(sqrt(n2max)) is the largest |n_a| in any shell; every estimator
+ * output is exact on an N' grid when 3 c < N' (closed triangles never wrap).
+ *
+ * Compact spectra ("delta_l" arguments): the band |n_x|, |n_y| <= c,
+ * 0 <= n_z <= c of a half spectrum, stored complex64 as
+ * [nl][2c+1][2c+1][cz] with index (n_x + c, n_y + c, n_z) and cz = c + 1 rounded
+ * up to a multiple of 16 (entries n_z > c are zero). nl = lmax/2 + 1.
+ */
+#ifndef BSP_H
+#define BSP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bsp_plan_s* bsp_plan;
+
+typedef enum {
+  BSP_OK = 0,
+  BSP_ERR_ARG = 1,       /* null or inconsistent argument */
+  BSP_ERR_SIZE = 2,      /* grid size without a transform kernel (supported: 16,32,64,96,128,192,256,384,512) */
+  BSP_ERR_ALIAS = 3,     /* 3 c >= N': closed triangles would wrap on the N' grid */
+  BSP_ERR_WORKSPACE = 4, /* no workspace, or smaller than bsp_workspace_size */
+  BSP_ERR_HIP = 5,       /* HIP runtime error (message in bsp_last_error) */
+  BSP_ERR_DEVICE = 6,    /* latched by a kernel: particle outside [0,N) or not finite */
+  BSP_ERR_NUMERIC = 7,   /* latched: triangle count residual >= 1e-3, or Cholesky failure */
+  BSP_ERR_STATE = 8      /* call out of order */
+} bsp_status;
+
+typedef enum {
+  BSP_FP32 = 0,   /* FP32 fields, FP32 MFMA products and accumulation */
+  BSP_BF16X3 = 1, /* FP32 fields split hi+lo into bf16; ah*bh + ah*bl + al*bh on bf16 MFMA, FP32 accumulate */
+  BSP_FP16X3 = 2  /* as BF16X3 with fp16 splits of power-of-two scaled fields */
+} bsp_precision;
+
+/* Geometry of one estimator run. */
+typedef struct {
+  int32_t n;           /* assignment / forward-transform grid N */
+  int32_t n_reduce;    /* N' of the inverse transforms and triple sums; 0 means N */
+  double box;          /* side L of the periodic box, Mpc/h */
+  int32_t window;      /* 0 NGP, 1 CIC mass assignment */
+  int32_t compensate;  /* 1: divide by the assignment window prod sinc^p(pi n_a / N) */
+  int32_t interlace;   /* 1: second grid at u + 1/2, combined with phase exp(i pi (nx+ny+nz)/N) */
+  int32_t los;         /* 0: plane parallel along +z; 1: varying, x_hat from the observer */
+  double observer[3];  /* observer position in grid units (los = 1) */
+  int32_t lmax;        /* 0, 2 or 4 */
+  int32_t nbins;       /* number of k shells (<= 64) */
+  double k0, dk;       /* first shell centre and width, units of k_f */
+} bsp_geom;
+
+/* Separable modal basis (Sec. 3.5): q_p(k) = Legendre P_p(t),
+ * t = (2k - kmin - kmax)/(kmax - kmin) on kmin <= k < kmax, the union of the
+ * shells; weight 1/sqrt(k P_fid(k)). */
+typedef struct {
+  int32_t P;             /* number of 1-D functions q_p, p < P */
+  int32_t nmodes;        /* number of 3-D modes Q_n */
+  const int32_t* modes;  /* host [nmodes][3]: (p, r, s), p <= r <= s < P */
+  const double* pfid;    /* host [pfid_len]: P_fid at k = k_f sqrt(m), m = |n|^2, (Mpc/h)^3 */
+  int32_t pfid_len;      /* must exceed the largest |n|^2 in the modal range */
+} bsp_modal_basis;
+
+/* Sizes derived at plan creation. */
+typedef struct {
+  int32_t c, cz, nl, nlos, ngrid, n2max;
+  int32_t ncand;          /* candidate triangles b1 >= b2 >= b3 */
+  int32_t ntri;           /* triangles with nonzero count (valid after bsp_precompute) */
+  int32_t nfields_binned; /* nl * nbins shell fields D^(l)_b */
+  int32_t nfields_modal;  /* nl * P modal fields M^(l)_p */
+  int64_t spec_elems;     /* complex elements of one compact cube: (2c+1)^2 cz */
+} bsp_info;
+
+/* ---------------------------------------------------------------- plans */
+
+/* Validates the geometry (BSP_ERR_ARG, BSP_ERR_SIZE, BSP_ERR_ALIAS) and builds
+ * the constant tables. basis may be NULL (no modal output). stream is a
+ * hipStream_t (NULL: default stream). */
+bsp_status bsp_plan_create(bsp_plan* plan, const bsp_geom* geom, const bsp_modal_basis* basis, void* stream);
+bsp_status bsp_plan_destroy(bsp_plan plan);
+bsp_status bsp_plan_info(bsp_plan plan, bsp_info* info /*host*/);
+/* Message of the last error on this plan (plan may be NULL for bsp_plan_create errors). */
+const char* bsp_last_error(bsp_plan plan);
+/* Bytes of device workspace every call of this plan may use. */
+bsp_status bsp_workspace_size(bsp_plan plan, size_t* bytes /*host*/);
+/* Workspace: device pointer, 256-byte aligned, at least bsp_workspace_size bytes. */
+bsp_status bsp_set_workspace(bsp_plan plan, void* dev, size_t bytes);
+/* Waits for the plan's stream; returns the first latched device error. */
+bsp_status bsp_sync(bsp_plan plan);
+
+/* Geometry-only FP64 precompute on the GPU (once per plan): triangle counts
+ * V_B(k1,k2,k3) of the standard estimator as round(sum_x I I I / N'^3) with
+ * I_b the inverse DFT of the shell indicator (residual checked), and, with a
+ * modal basis, the lattice Gram matrix gamma_nm = <<Q_n|Q_m>> of eqs.
+ * (betaCalc, innerProduct), its Cholesky factor, and the Poisson shot-noise
+ * integrals of the modal numerators. Needs the workspace. Synchronises. */
+bsp_status bsp_precompute(bsp_plan plan);
+/* Host copies of the precompute results (after bsp_precompute):
+ * tri [ntri][3] (b1 >= b2 >= b3, lexicographic), counts [ntri],
+ * gamma [nmodes][nmodes] (may be NULL), chol [nmodes][nmodes] lower (may be NULL). */
+bsp_status bsp_geometry(bsp_plan plan, int32_t* tri, int64_t* counts, double* gamma, double* chol);
+
+/* ---------------------------------------------------------------- steps */
+
+/* Mass assignment (the paper is silent on it). ux, uy, uz, w: device [np]
+ * positions in grid units in [0, N) (w NULL: unit weights). grids: device
+ * [1+interlace][N^3], accumulated into (the caller zeroes them). wsum: device
+ * double[1], accumulated sum of weights. Out-of-range or non-finite positions
+ * are skipped and latch BSP_ERR_DEVICE. */
+bsp_status bsp_grid_assign(bsp_plan plan, const float* ux, const float* uy, const float* uz, const float* w,
+                           int64_t np, float* grids, double* wsum);
+
+/* Full unnormalised 3-D transforms in the standard layouts (forward e^{-i},
+ * inverse e^{+i}), batch of independent grids of size n (any supported size).
+ * in/out: device. c2r expects Hermitian input and uses the workspace. */
+bsp_status bsp_fft_r2c(bsp_plan plan, int32_t n, int32_t batch, const float* in, void* out_c64);
+bsp_status bsp_fft_c2r(bsp_plan plan, int32_t n, int32_t batch, const void* in_c64, float* out);
+
+/* Line-of-sight Legendre moments delta^(l)(n), l = 0, 2, ..., lmax (the LOS
+ * moment field defined with the power-spectrum multipoles, Sec. 2, evaluated
+ * through x-hat product fields so the line of sight may vary): density
+ * contrast rho/rho_bar - 1 of each grid (rho_bar = wsum / N^3), weighting by
+ * x_hat products at the nodes, forward transforms, window compensation,
+ * interlacing, Legendre contraction, delta^(l)(0) = 0.
+ * grids: device [1+interlace][N^3] densities from bsp_grid_assign; wsum: device
+ * double[1]; delta_l: device compact spectra (see top). Uses the workspace. */
+bsp_status bsp_los_moments(bsp_plan plan, const float* grids, const double* wsum, void* delta_l);
+
+/* Same for a caller-made contrast field delta(x) (device [N^3]): no assignment
+ * window is divided out and no interlacing is applied. */
+bsp_status bsp_grid_entry(bsp_plan plan, const float* delta, void* delta_l);
+
+/* Filtered fields on the N' grid: for each filter f, the unnormalised inverse
+ * DFT of (weight * delta^(l)) where filt[f] = {l_index, kind, index}:
+ *   kind 0: shell indicator of bin `index` -> D^(l)_k(x) of eq. (Standard_ell_Estim);
+ *   kind 1: modal weight q_index(k)/sqrt(k P_fid) -> N^3 M^(l)_n(x) of eq. (betaEst).
+ * filt: host [nfilt][3]; fields: device [nfilt][N'^3] float. Uses the workspace. */
+bsp_status bsp_filter_fields(bsp_plan plan, const void* delta_l, int32_t nfilt, const int32_t* filt, float* fields);
+
+/* Triple reduction T[p][s] = sum_x F_{a_p}(x) F_{b_p}(x) F_{t_s}(x) over K points,
+ * the sum over products of three transformed fields of the standard and modal
+ * estimators. fields: device [nfields][K] float (nfields <= 128); pairs: host
+ * [npairs][2]; thirds: host [nthirds] (<= 128); need: host [npairs][nthirds]
+ * uint8 or NULL (all); entries not needed are left 0. T: device double
+ * [npairs][nthirds]. Chunks of K are accumulated in FP32 and combined in FP64.
+ * Uses the workspace. */
+bsp_status bsp_triple_reduce(bsp_plan plan, const float* fields, int32_t nfields, int64_t K, const int32_t* pairs,
+                             int32_t npairs, const int32_t* thirds, int32_t nthirds, const uint8_t* need,
+                             bsp_precision prec, double* T);
+
+/* Modal coefficients beta^l_n = sum_m gamma^-1_nm b^l_m (eqs. betaCalc, betaEst and
+ * the multipole modal coefficients with the even compositions of eqs.
+ * (Bisp_ell, Bisp_ell2)): b^0 = <M0 M0 M0>, b^2 the three (2,0,0) placements,
+ * b^4 the three (4,0,0) and three (0,2,2) placements, <XYZ> = N'^-3 sum_x.
+ * nbar > 0 subtracts the Poisson shot noise of b^0. alpha = L^-1 b (orthonormal
+ * basis), beta = L^-T alpha. bnum, alpha, beta: device double [nl][nmodes].
+ * Requires bsp_precompute and a modal basis. */
+bsp_status bsp_modal_coeffs(bsp_plan plan, const void* delta_l, bsp_precision prec, double nbar, double* bnum,
+                            double* alpha, double* beta);
+
+/* The whole hot path for one catalogue: assignment, LOS moments, shell and
+ * modal fields, one triple reduction, FP64 normalisation.
+ *   B: device double [nl][ntri], B^l = V^2 T^l / (N^9 N'^3 N_tri) (multipole on b1);
+ *   B0sub: device double [ntri] or NULL, B^0 - sum_i Pbar_bi / nbar + 2/nbar^2;
+ *   Pbar: device double [nbins] or NULL, shell power V sum |delta0|^2 / (N^6 N_b);
+ *   bnum, alpha, beta: device double [nl][nmodes] or NULL (need a modal basis).
+ * nbar = wsum / V is used for the shot noise; the catalogue is as in
+ * bsp_grid_assign. Requires bsp_precompute. */
+bsp_status bsp_bispectrum_multipoles(bsp_plan plan, const float* ux, const float* uy, const float* uz,
+                                     const float* w, int64_t np, bsp_precision prec, double* B, double* B0sub,
+                                     double* Pbar, double* bnum, double* alpha, double* beta);
+
+/* The same from a caller-made contrast field delta(x) (device [N^3]); no shot
+ * noise subtraction (B0sub, nbar unused). */
+bsp_status bsp_bispectrum_field(bsp_plan plan, const float* delta, bsp_precision prec, double* B, double* Pbar,
+                                double* bnum, double* alpha, double* beta);
+
+/* ---------------------------------------------------------------- tracing */
+
+/* Stage timers: while enabled, each compute call records a pair of HIP events
+ * on the plan's stream around the launches of every stage:
+ *   0 assignment, 1 forward z pass (r2c + LOS weights), 2 forward y pass,
+ *   3 forward x pass, 4 LOS combination, 5 inverse x pass (shell/modal filter),
+ *   6 inverse y pass, 7 inverse z pass (c2r), 8 triple reduction,
+ *   9 FP64 combination of the reduction partials.
+ * bsp_set_timing(plan, 1) resets and starts, 0 stops (it synchronises).
+ * bsp_stage_times synchronises and returns, per stage, the summed event
+ * milliseconds since the reset (ms: host double[16]) and the number of timed
+ * launches (launches: host int64[16], may be NULL). */
+bsp_status bsp_set_timing(bsp_plan plan, int32_t enable);
+bsp_status bsp_stage_times(bsp_plan plan, double* ms, int64_t* launches);
+
+/* Sample covariance of a batch of coefficient vectors (FP64):
+ * cov = (1/(M-1)) sum_m (x_m - mean)(x_m - mean)^T. x: device [m][d], cov:
+ * device [d][d]. stream: hipStream_t or NULL. */
+bsp_status bsp_batch_covariance(const double* x, int32_t m, int32_t d, double* cov, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BSP_H */

@@ -1,0 +1,1389 @@
+// Host runtime of libbsp: plans (geometry, constant tables, reduction
+// schedules), workspace carving, and the orchestration of the kernels behind
+// the C ABI declared in include/bsp.h.
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/bsp.h"
+#include "bsp_internal.h"
+
+using namespace bsp;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+thread_local std::string g_create_error;
+
+struct ReducePlan {
+  int npairs = 0, nthirds = 0, nrt = 0, nct = 0, ngroups = 0, ntiles = 0, maxr = 0, nfields = 0;
+  std::vector<int32_t> pair_a, pair_b, third, row_mask, tile_index, tile_rc, wave_rows;
+  // device copies (plan-owned or workspace)
+  int32_t* d = nullptr;  // one block holding every array
+  size_t words = 0;
+  int32_t *d_pair_a = nullptr, *d_pair_b = nullptr, *d_third = nullptr, *d_row_mask = nullptr,
+          *d_tile_index = nullptr, *d_tile_rc = nullptr, *d_wave_rows = nullptr;
+  std::vector<int32_t> packed;
+};
+
+// Tiles of 16 pairs x 16 thirds; a tile is needed when any entry is. Row tiles
+// are spread over (group, wave) slots, heaviest first, to balance MFMA work.
+bool build_reduce(ReducePlan& rp, const std::vector<std::array<int, 2>>& pairs, const std::vector<int>& thirds,
+                  const std::vector<uint8_t>& need, int nfields, int maxr_fn(int, int), int prec) {
+  rp = ReducePlan{};
+  rp.npairs = (int)pairs.size();
+  rp.nthirds = (int)thirds.size();
+  rp.nfields = nfields;
+  rp.nrt = (rp.npairs + 15) / 16;
+  rp.nct = (rp.nthirds + 15) / 16;
+  if (rp.nct > 8 || rp.nct == 0 || rp.nrt == 0) return false;
+  rp.maxr = maxr_fn(prec, rp.nct);
+  rp.pair_a.assign(rp.nrt * 16, -1);
+  rp.pair_b.assign(rp.nrt * 16, -1);
+  rp.third.assign(rp.nct * 16, -1);
+  for (int i = 0; i < rp.npairs; ++i) {
+    rp.pair_a[i] = pairs[i][0];
+    rp.pair_b[i] = pairs[i][1];
+  }
+  for (int i = 0; i < rp.nthirds; ++i) rp.third[i] = thirds[i];
+  rp.row_mask.assign(rp.nrt, 0);
+  rp.tile_index.assign(rp.nrt * 8, -1);
+  for (int p = 0; p < rp.npairs; ++p)
+    for (int t = 0; t < rp.nthirds; ++t)
+      if (need.empty() || need[(size_t)p * rp.nthirds + t]) rp.row_mask[p / 16] |= 1 << (t / 16);
+  std::vector<int> active;
+  for (int r = 0; r < rp.nrt; ++r)
+    if (rp.row_mask[r]) {
+      for (int c = 0; c < rp.nct; ++c)
+        if ((rp.row_mask[r] >> c) & 1) {
+          rp.tile_index[r * 8 + c] = rp.ntiles++;
+          rp.tile_rc.push_back(r);
+          rp.tile_rc.push_back(c);
+        }
+      active.push_back(r);
+    }
+  const int waves = reduce_waves_per_group();
+  const int slots_per_group = waves * rp.maxr;
+  rp.ngroups = std::max(1, (int)((active.size() + slots_per_group - 1) / slots_per_group));
+  // longest-processing-time assignment over all waves
+  std::sort(active.begin(), active.end(), [&](int a, int b) {
+    return __builtin_popcount(rp.row_mask[a]) > __builtin_popcount(rp.row_mask[b]);
+  });
+  const int nw = rp.ngroups * waves;
+  std::vector<int> load(nw, 0), cnt(nw, 0);
+  rp.wave_rows.assign((size_t)nw * rp.maxr, -1);
+  for (int r : active) {
+    int best = -1;
+    for (int w = 0; w < nw; ++w)
+      if (cnt[w] < rp.maxr && (best < 0 || load[w] < load[best])) best = w;
+    rp.wave_rows[(size_t)best * rp.maxr + cnt[best]++] = r;
+    load[best] += __builtin_popcount(rp.row_mask[r]);
+  }
+  // pack for one upload
+  rp.packed.clear();
+  auto put = [&](const std::vector<int32_t>& v) {
+    size_t off = rp.packed.size();
+    rp.packed.insert(rp.packed.end(), v.begin(), v.end());
+    while (rp.packed.size() % 64) rp.packed.push_back(0);
+    return off;
+  };
+  size_t o[7];
+  o[0] = put(rp.pair_a);
+  o[1] = put(rp.pair_b);
+  o[2] = put(rp.third);
+  o[3] = put(rp.row_mask);
+  o[4] = put(rp.tile_index);
+  o[5] = put(rp.tile_rc.empty() ? std::vector<int32_t>{0} : rp.tile_rc);
+  o[6] = put(rp.wave_rows);
+  rp.words = rp.packed.size();
+  (void)o;
+  return true;
+}
+
+void bind_reduce(ReducePlan& rp, int32_t* dev) {
+  rp.d = dev;
+  size_t off = 0;
+  auto take = [&](size_t n) {
+    int32_t* p = dev + off;
+    off += n;
+    while (off % 64) ++off;
+    return p;
+  };
+  rp.d_pair_a = take(rp.pair_a.size());
+  rp.d_pair_b = take(rp.pair_b.size());
+  rp.d_third = take(rp.third.size());
+  rp.d_row_mask = take(rp.row_mask.size());
+  rp.d_tile_index = take(rp.tile_index.size());
+  rp.d_tile_rc = take(rp.tile_rc.empty() ? 1 : rp.tile_rc.size());
+  rp.d_wave_rows = take(rp.wave_rows.size());
+}
+
+// Points per workgroup chunk: about 2048 chunks, at least 1024 points, at most
+// 16384 (FP32 accumulation) or 65536 (split products, FP64). Independent of the
+// schedule so that partial storage only grows with the number of tiles.
+int64_t kchunk_for(int prec, int64_t K, int /*ngroups*/) {
+  const int64_t cap = (prec == 0) ? 16384 : 65536;
+  const int64_t target_blocks = 2048;
+  int64_t kc = (K + target_blocks - 1) / target_blocks;
+  kc = (kc + 63) / 64 * 64;
+  kc = std::max<int64_t>(kc, 1024);
+  kc = std::min<int64_t>(kc, cap);
+  return kc;
+}
+
+ReduceDesc make_desc(const ReducePlan& rp, int64_t K, int64_t field_stride, int prec, const float* scale) {
+  ReduceDesc d{};
+  d.nfields = rp.nfields;
+  d.K = K;
+  d.field_stride = field_stride;
+  d.kchunk = (int32_t)kchunk_for(prec, K, rp.ngroups);
+  d.nchunks = (int32_t)((K + d.kchunk - 1) / d.kchunk);
+  d.ngroups = rp.ngroups;
+  d.nct = rp.nct;
+  d.wave_rows = rp.d_wave_rows;
+  d.row_mask = rp.d_row_mask;
+  d.tile_index = rp.d_tile_index;
+  d.tile_rc = rp.d_tile_rc;
+  d.ntiles = rp.ntiles;
+  d.pair_a = rp.d_pair_a;
+  d.pair_b = rp.d_pair_b;
+  d.third = rp.d_third;
+  d.scale = scale;
+  return d;
+}
+
+size_t partial_bytes(const ReducePlan& rp, int64_t K, int prec, size_t elem) {
+  const int64_t kc = kchunk_for(prec, K, rp.ngroups);
+  const int64_t nch = (K + kc - 1) / kc;
+  return (size_t)nch * rp.ntiles * 256 * elem;
+}
+
+}  // namespace
+
+struct bsp_plan_s {
+  bsp_geom g{};
+  hipStream_t stream = nullptr;
+  std::string err;
+  int N = 0, Nr = 0, c = 0, cz = 0, nl = 1, nlos = 1, ngrid = 1, n2max = 0, plane = 1;
+  int nbins = 0;
+  int64_t spec = 0;  // compact cube elements
+  double V = 0, kf = 0, kmin = 0, kmax = 0;
+  // modal basis
+  bool modal = false;
+  int P = 0, nmodes = 0, nU = 0;
+  std::vector<int32_t> modes;
+  std::vector<double> pfid;
+  // geometry
+  std::vector<std::array<int, 3>> cand;
+  std::vector<int64_t> nb_modes;
+  std::vector<int32_t> bin_of_n2;
+  // plan-owned device memory
+  std::vector<void*> allocs;
+  float2* tw32_N = nullptr;
+  float2* tw32_Nr = nullptr;
+  double2* tw64_Nr = nullptr;
+  int32_t* d_bin_of_n2 = nullptr;
+  int64_t* d_nb_modes = nullptr;
+  float* d_tab32 = nullptr;   // rows: nbins shells, P modal weights
+  double* d_tab64 = nullptr;  // rows: nbins shells, nU U_ab, P G_p, P G^P_p
+  int32_t* d_err = nullptr;
+  int32_t* d_ints = nullptr;  // field_ell / field_tab for the main and precompute passes
+  int F = 0;                  // fields of the main pipeline
+  int32_t *d_field_ell = nullptr, *d_field_tab = nullptr;
+  int32_t *d_ones_ell = nullptr, *d_pre_tab = nullptr;  // precompute: all ell 0, table row = index
+  // precompute results
+  bool pre_done = false;
+  std::vector<std::array<int, 3>> tri;
+  std::vector<int64_t> counts;
+  std::vector<double> gamma_h, chol_h;
+  int64_t* d_counts = nullptr;
+  int32_t* d_tri_bins = nullptr;
+  int32_t* d_tri_tidx = nullptr;
+  int32_t* d_combo = nullptr;
+  double* d_L = nullptr;
+  double* d_sn = nullptr;
+  ReducePlan main_rp, cnt_rp, gram_rp, sn_rp;
+  std::vector<int32_t> cnt_tidx, gidx, sidx, tri_tidx, tri_bins, combo;
+  int32_t *d_cnt_tidx = nullptr, *d_gidx = nullptr, *d_sidx = nullptr, *d_urow = nullptr, *d_grow = nullptr;
+  // workspace
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  // stage timers: event pairs recorded around launches while enabled
+  bool timing = false;
+  std::vector<std::array<hipEvent_t, 2>> ev_pool;
+  std::vector<int> ev_stage;
+  size_t ev_used = 0;
+  double stage_ms[16] = {0};
+  int64_t stage_n[16] = {0};
+  // generic triple_reduce staging
+  ReducePlan call_rp;
+  double host_scalar = 0.0;
+
+  ~bsp_plan_s() {
+    for (auto& e : ev_pool) {
+      (void)hipEventDestroy(e[0]);
+      (void)hipEventDestroy(e[1]);
+    }
+    for (void* p : allocs) (void)hipFree(p);
+  }
+};
+
+namespace {
+
+bsp_status fail(bsp_plan p, bsp_status s, const std::string& msg) {
+  if (p) p->err = msg;
+  else g_create_error = msg;
+  return s;
+}
+
+#define HIPCHK(expr)                                                                            \
+  do {                                                                                          \
+    hipError_t e_ = (expr);                                                                     \
+    if (e_ != hipSuccess) return fail(p, BSP_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+// Records an event pair around the launches of one stage when timing is on.
+struct StageTimer {
+  bsp_plan p;
+  int stage;
+  size_t slot = (size_t)-1;
+  StageTimer(bsp_plan pp, int st) : p(pp), stage(st) {
+    if (!p->timing) return;
+    if (p->ev_used == p->ev_pool.size()) {
+      std::array<hipEvent_t, 2> e{};
+      if (hipEventCreate(&e[0]) != hipSuccess || hipEventCreate(&e[1]) != hipSuccess) return;
+      p->ev_pool.push_back(e);
+      p->ev_stage.push_back(st);
+    }
+    slot = p->ev_used++;
+    p->ev_stage[slot] = st;
+    (void)hipEventRecord(p->ev_pool[slot][0], p->stream);
+  }
+  ~StageTimer() {
+    if (slot != (size_t)-1) (void)hipEventRecord(p->ev_pool[slot][1], p->stream);
+  }
+};
+
+template <typename T>
+T* dalloc(bsp_plan p, size_t n) {
+  void* q = nullptr;
+  if (n == 0) n = 1;
+  if (hipMalloc(&q, n * sizeof(T)) != hipSuccess) return nullptr;
+  p->allocs.push_back(q);
+  return reinterpret_cast<T*>(q);
+}
+
+template <typename T>
+T* upload(bsp_plan p, const std::vector<T>& v) {
+  T* d = dalloc<T>(p, v.size());
+  if (!d) return nullptr;
+  if (!v.empty() && hipMemcpy(d, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+  return d;
+}
+
+// exp(-2 pi i j / n), j < n, in double precision
+std::vector<double> twiddles(int n) {
+  std::vector<double> t(2 * (size_t)n);
+  for (int j = 0; j < n; ++j) {
+    // reduce the angle exactly in integers first
+    const long double a = -2.0L * 3.14159265358979323846264338327950288L * (long double)j / (long double)n;
+    t[2 * j] = (double)cosl(a);
+    t[2 * j + 1] = (double)sinl(a);
+  }
+  return t;
+}
+
+double legendre(int p, double t) {
+  double p0 = 1.0, p1 = t;
+  if (p == 0) return p0;
+  for (int k = 1; k < p; ++k) {
+    const double p2 = ((2.0 * k + 1.0) * t * p1 - k * p0) / (k + 1.0);
+    p0 = p1;
+    p1 = p2;
+  }
+  return p1;
+}
+
+// workspace layout -------------------------------------------------------------
+struct Layout {
+  size_t dl, fields, T, small, scratch, total;  // main pipeline
+  size_t s_grid, s_Z, s_Y;                     // forward scratch pieces
+  int fb;                                      // inverse batch
+  size_t pre_ones, pre_fields, pre_T, pre_scratch, pre_total;
+  int fb64;
+};
+
+size_t inv_scratch(const bsp_plan p, int fb, size_t celem) {
+  const size_t w = 2 * (size_t)p->c + 1;
+  return align_up((size_t)fb * p->Nr * w * p->cz * celem) + align_up((size_t)fb * p->Nr * p->Nr * p->cz * celem);
+}
+
+Layout layout(const bsp_plan p) {
+  Layout L{};
+  const size_t w = 2 * (size_t)p->c + 1;
+  const size_t N = p->N, Nr = p->Nr;
+  L.dl = align_up((size_t)p->nl * p->spec * sizeof(float2));
+  L.fields = align_up((size_t)p->F * Nr * Nr * Nr * sizeof(float));
+  L.T = align_up(std::max<size_t>((size_t)p->main_rp.npairs * p->main_rp.nthirds, 1) * sizeof(double));
+  L.small = align_up(4096 * sizeof(double) + (size_t)(p->F + 64) * sizeof(float));
+  L.s_grid = align_up((size_t)p->ngrid * N * N * N * sizeof(float));
+  L.s_Z = align_up((size_t)p->ngrid * p->nlos * N * N * p->cz * sizeof(float2));
+  L.s_Y = align_up((size_t)p->ngrid * p->nlos * N * w * p->cz * sizeof(float2));
+  const size_t fwd = L.s_grid + L.s_Z + L.s_Y;
+  int fb = 2;
+  while (fb + 2 <= std::max(p->F, 2) && inv_scratch(p, fb + 2, sizeof(float2)) <= std::max<size_t>(fwd, 1ull << 31))
+    fb += 2;
+  L.fb = fb;
+  size_t part = 0;
+  if (p->main_rp.ntiles)
+    for (int prec = 0; prec < 3; ++prec)
+      part = std::max(part, partial_bytes(p->main_rp, (int64_t)Nr * Nr * Nr, prec, sizeof(float)));
+  const size_t fullc2r = align_up((size_t)N * N * (N / 2 + 1) * sizeof(float2));
+  L.scratch = std::max({fwd, inv_scratch(p, fb, sizeof(float2)), align_up(part) + align_up(1 << 20), fullc2r});
+  L.total = L.dl + L.fields + L.T + L.small + L.scratch;
+  // FP64 precompute
+  const int nfp = std::max({p->nbins, p->modal ? p->nU : 0, p->modal ? 2 * p->P : 0});
+  L.pre_ones = align_up((size_t)p->spec * sizeof(double2));
+  L.pre_fields = align_up((size_t)nfp * Nr * Nr * Nr * sizeof(double));
+  L.pre_T = align_up((size_t)4096 * 128 * sizeof(double));
+  int fb64 = 2;
+  while (fb64 + 2 <= std::max(nfp, 2) && inv_scratch(p, fb64 + 2, sizeof(double2)) <= std::max<size_t>(fwd, 1ull << 31))
+    fb64 += 2;
+  L.fb64 = fb64;
+  const int64_t K = (int64_t)Nr * Nr * Nr;
+  size_t part64 = partial_bytes(p->cnt_rp, K, 3, sizeof(double));
+  if (p->modal)
+    part64 = std::max({part64, partial_bytes(p->gram_rp, K, 3, sizeof(double)),
+                       partial_bytes(p->sn_rp, K, 3, sizeof(double))});
+  part64 = align_up(std::max<size_t>(part64, p->cand.size() * sizeof(int64_t)));
+  L.pre_scratch = std::max(inv_scratch(p, fb64, sizeof(double2)), part64 + align_up(1 << 20));
+  L.pre_total = L.pre_ones + L.pre_fields + L.pre_T + L.pre_scratch;
+  return L;
+}
+
+bsp_status need_ws(bsp_plan p, size_t bytes) {
+  if (!p->ws) return fail(p, BSP_ERR_WORKSPACE, "no workspace set");
+  if (p->ws_bytes < bytes) return fail(p, BSP_ERR_WORKSPACE, "workspace smaller than required");
+  return BSP_OK;
+}
+
+// ---------------------------------------------------------------- passes
+
+// delta_l (compact) from the forward transforms of the LOS-weighted grids.
+bsp_status forward_moments(bsp_plan p, const float* grids, int ngrid, int contrast, const double* wsum,
+                           int compensate, float2* delta_l, char* scratch) {
+  const Layout L = layout(p);
+  const int N = p->N, c = p->c, cz = p->cz, w = 2 * c + 1;
+  float2* Z = reinterpret_cast<float2*>(scratch);
+  float2* Y = reinterpret_cast<float2*>(scratch + L.s_Z);
+  FwdZDesc fz{};
+  fz.ngrid = ngrid;
+  fz.nlos = p->nlos;
+  fz.contrast = contrast;
+  fz.wsum = wsum;
+  fz.shift[0] = 0.0;
+  fz.shift[1] = 0.5;
+  for (int a = 0; a < 3; ++a) fz.obs[a] = p->g.observer[a];
+  fz.plane = p->plane;
+  fz.cout = c + 1;
+  fz.zs = cz;
+  {
+    StageTimer t(p, 1);
+    HIPCHK(launch_fwd_z_f32(N, grids, Z, fz, p->tw32_N, p->stream));
+  }
+  const int nb = ngrid * p->nlos;
+  PassDesc py{};
+  py.nouter = nb * N;
+  py.in_outer = (int64_t)N * cz;
+  py.out_outer = (int64_t)w * cz;
+  py.in_row = cz;
+  py.out_row = cz;
+  py.ncols = cz;
+  py.in_rows = N;
+  py.in_off = 0;
+  py.out_rows = w;
+  py.out_off = c;
+  {
+    StageTimer t(p, 2);
+    HIPCHK(launch_c2c_f32(N, -1, Z, Y, py, nullptr, p->tw32_N, p->stream));
+  }
+  PassDesc px{};
+  px.nouter = nb;
+  px.in_outer = (int64_t)N * w * cz;
+  px.out_outer = (int64_t)w * w * cz;
+  px.in_row = (int64_t)w * cz;
+  px.out_row = (int64_t)w * cz;
+  px.ncols = w * cz;
+  px.in_rows = N;
+  px.in_off = 0;
+  px.out_rows = w;
+  px.out_off = c;
+  float2* X = Z;  // Z is dead once Y exists
+  {
+    StageTimer t(p, 3);
+    HIPCHK(launch_c2c_f32(N, -1, Y, X, px, nullptr, p->tw32_N, p->stream));
+  }
+  LosDesc ld{};
+  ld.n = N;
+  ld.c = c;
+  ld.cz = cz;
+  ld.ngrid = ngrid;
+  ld.nlos = p->nlos;
+  ld.lmax = p->g.lmax;
+  ld.plane = p->plane;
+  ld.window = p->g.window;
+  ld.compensate = compensate;
+  ld.n2max = p->n2max;
+  {
+    StageTimer t(p, 4);
+    HIPCHK(launch_los_combine(X, delta_l, ld, p->stream));
+  }
+  return BSP_OK;
+}
+
+// Inverse transforms of filtered compact spectra to real fields on N'.
+// field_ell / field_tab index the filter of each output field.
+template <typename T>
+bsp_status inverse_fields(bsp_plan p, const cplx_t<T>* src, int64_t src_ell_stride, int nf,
+                          const int32_t* d_field_ell, const int32_t* d_field_tab, const T* tables, T* out,
+                          char* scratch, int fb) {
+  const int Nr = p->Nr, c = p->c, cz = p->cz, w = 2 * c + 1;
+  using V = cplx_t<T>;
+  V* Xb = reinterpret_cast<V*>(scratch);
+  V* Yb = reinterpret_cast<V*>(scratch + align_up((size_t)fb * Nr * w * cz * sizeof(V)));
+  for (int f0 = 0; f0 < nf; f0 += fb) {
+    const int nb = std::min(fb, nf - f0);
+    FilterDesc fd{};
+    fd.src = src;
+    fd.src_ell_stride = src_ell_stride;
+    fd.field_ell = d_field_ell;
+    fd.tables = tables;
+    fd.field_table = d_field_tab;
+    fd.tablen = p->n2max + 1;
+    fd.c = c;
+    fd.cz = cz;
+    fd.field0 = f0;
+    PassDesc px{};
+    px.nouter = nb;
+    px.in_outer = 0;
+    px.out_outer = (int64_t)Nr * w * cz;
+    px.in_row = (int64_t)w * cz;
+    px.out_row = (int64_t)w * cz;
+    px.ncols = w * cz;
+    px.in_rows = w;
+    px.in_off = c;
+    px.out_rows = Nr;
+    px.out_off = 0;
+    PassDesc py{};
+    py.nouter = nb * Nr;
+    py.in_outer = (int64_t)w * cz;
+    py.out_outer = (int64_t)Nr * cz;
+    py.in_row = cz;
+    py.out_row = cz;
+    py.ncols = cz;
+    py.in_rows = w;
+    py.in_off = c;
+    py.out_rows = Nr;
+    py.out_off = 0;
+    if constexpr (sizeof(T) == 4) {
+      {
+        StageTimer t(p, 5);
+        HIPCHK(launch_c2c_f32(Nr, +1, nullptr, Xb, px, &fd, p->tw32_Nr, p->stream));
+      }
+      {
+        StageTimer t(p, 6);
+        HIPCHK(launch_c2c_f32(Nr, +1, Xb, Yb, py, nullptr, p->tw32_Nr, p->stream));
+      }
+      StageTimer t(p, 7);
+      HIPCHK(launch_inv_z_f32(Nr, Yb, out + (int64_t)f0 * Nr * Nr * Nr, nb, c + 1, cz, (int64_t)Nr * Nr * cz,
+                              (int64_t)Nr * Nr * Nr, p->tw32_Nr, p->stream));
+    } else {
+      HIPCHK(launch_c2c_f64(Nr, +1, nullptr, Xb, px, &fd, p->tw64_Nr, p->stream));
+      HIPCHK(launch_c2c_f64(Nr, +1, Xb, Yb, py, nullptr, p->tw64_Nr, p->stream));
+      HIPCHK(launch_inv_z_f64(Nr, Yb, out + (int64_t)f0 * Nr * Nr * Nr, nb, c + 1, cz, (int64_t)Nr * Nr * cz,
+                              (int64_t)Nr * Nr * Nr, p->tw64_Nr, p->stream));
+    }
+  }
+  return BSP_OK;
+}
+
+template <typename T>
+bsp_status run_reduce(bsp_plan p, const ReducePlan& rp, const T* fields, int64_t K, int prec, const float* scale,
+                      double* Tout, char* scratch, size_t scratch_bytes, double tscale) {
+  const ReduceDesc d = make_desc(rp, K, K, prec, scale);
+  const size_t need = (size_t)d.nchunks * d.ntiles * 256 * sizeof(T);
+  if (need > scratch_bytes) return fail(p, BSP_ERR_WORKSPACE, "workspace too small for reduction partials");
+  HIPCHK(hipMemsetAsync(Tout, 0, (size_t)rp.npairs * rp.nthirds * sizeof(double), p->stream));
+  if (d.ntiles == 0) return BSP_OK;
+  if constexpr (sizeof(T) == 4) {
+    {
+      StageTimer t(p, 8);
+      HIPCHK(launch_reduce(prec, fields, d, reinterpret_cast<float*>(scratch), p->stream));
+    }
+    StageTimer t(p, 9);
+    HIPCHK(launch_combine_partials(scratch, 0, d, rp.npairs, rp.nthirds, Tout, tscale, p->stream));
+  } else {
+    HIPCHK(launch_reduce_f64(fields, d, reinterpret_cast<double*>(scratch), p->stream));
+    HIPCHK(launch_combine_partials(scratch, 1, d, rp.npairs, rp.nthirds, Tout, tscale, p->stream));
+  }
+  return BSP_OK;
+}
+
+// Power-of-two scales so max |field| lies in (64, 128]: pair products stay
+// below fp16's range and the lo parts stay normal.
+__global__ void k_absmax(const float* __restrict__ f, int64_t K, unsigned* __restrict__ out) {
+  const int fi = blockIdx.y;
+  float m = 0.f;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (int64_t)gridDim.x * blockDim.x)
+    m = fmaxf(m, fabsf(f[(int64_t)fi * K + i]));
+  for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+  if ((threadIdx.x & 63) == 0) atomicMax(out + fi, __float_as_uint(m));
+}
+__global__ void k_pow2_scale(const unsigned* __restrict__ mx, int n, float* __restrict__ scale) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float m = __uint_as_float(mx[i]);
+  int e = 0;
+  if (m > 0.f) {
+    frexpf(m, &e);  // m = f 2^e, f in [0.5, 1)
+  }
+  scale[i] = ldexpf(1.0f, 7 - e);
+}
+
+bsp_status field_scales(bsp_plan p, const float* fields, int nf, int64_t K, float* scale, unsigned* tmp) {
+  HIPCHK(hipMemsetAsync(tmp, 0, nf * sizeof(unsigned), p->stream));
+  hipLaunchKernelGGL(k_absmax, dim3(256, nf), dim3(256), 0, p->stream, fields, K, tmp);
+  HIPCHK(hipGetLastError());
+  hipLaunchKernelGGL(k_pow2_scale, dim3((nf + 63) / 64), dim3(64), 0, p->stream, tmp, nf, scale);
+  HIPCHK(hipGetLastError());
+  return BSP_OK;
+}
+
+__global__ void k_fill_ones(double2* __restrict__ x, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) x[i] = double2{1.0, 0.0};
+}
+
+
+bool upload_rp(bsp_plan p, ReducePlan& rp) {
+  int32_t* dm = dalloc<int32_t>(p, rp.words);
+  if (!dm) return false;
+  if (hipMemcpy(dm, rp.packed.data(), rp.words * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess) return false;
+  bind_reduce(rp, dm);
+  return true;
+}
+
+// T[(I_b2 I_b3)][I_b1] for every candidate b1 >= b2 >= b3
+bool build_counts(bsp_plan p) {
+  std::vector<std::array<int, 2>> pr;
+  for (int b2 = 0; b2 < p->nbins; ++b2)
+    for (int b3 = 0; b3 <= b2; ++b3) pr.push_back({b2, b3});
+  std::vector<int> th(p->nbins);
+  for (int b = 0; b < p->nbins; ++b) th[b] = b;
+  std::vector<uint8_t> need(pr.size() * th.size(), 0);
+  for (size_t i = 0; i < pr.size(); ++i)
+    for (int b1 = 0; b1 < p->nbins; ++b1) need[i * th.size() + b1] = b1 >= pr[i][0];
+  if (!build_reduce(p->cnt_rp, pr, th, need, p->nbins, reduce_max_rows_per_wave, 3)) return false;
+  p->cnt_tidx.resize(p->cand.size());
+  for (size_t i = 0; i < p->cand.size(); ++i) {
+    const int b1 = p->cand[i][0], b2 = p->cand[i][1], b3 = p->cand[i][2];
+    p->cnt_tidx[i] = (b2 * (b2 + 1) / 2 + b3) * p->nbins + b1;
+  }
+  return true;
+}
+
+// G(A,B,C) = sum_x U_A U_B U_C for the sorted U-index triples gamma needs
+bool build_gram(bsp_plan p) {
+  const int P = p->P, nm = p->nmodes, nU = p->nU;
+  auto uidx = [&](int a, int b) {
+    if (a > b) std::swap(a, b);
+    return a * P - a * (a - 1) / 2 + (b - a);
+  };
+  std::vector<std::array<int, 2>> pr;
+  std::vector<int> pidx((size_t)nU * nU, -1);
+  for (int A = 0; A < nU; ++A)
+    for (int B = A; B < nU; ++B) {
+      pidx[(size_t)A * nU + B] = (int)pr.size();
+      pr.push_back({A, B});
+    }
+  std::vector<int> th(nU);
+  for (int u = 0; u < nU; ++u) th[u] = u;
+  std::vector<uint8_t> need(pr.size() * nU, 0);
+  p->gidx.assign((size_t)nm * nm * 6, 0);
+  const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+  for (int i = 0; i < nm; ++i)
+    for (int j = 0; j < nm; ++j)
+      for (int t = 0; t < 6; ++t) {
+        int tr[3];
+        for (int a = 0; a < 3; ++a) tr[a] = uidx(p->modes[3 * i + a], p->modes[3 * j + perms[t][a]]);
+        std::sort(tr, tr + 3);
+        const int pi = pidx[(size_t)tr[0] * nU + tr[1]];
+        need[(size_t)pi * nU + tr[2]] = 1;
+        p->gidx[((size_t)i * nm + j) * 6 + t] = pi * nU + tr[2];
+      }
+  return build_reduce(p->gram_rp, pr, th, need, nU, reduce_max_rows_per_wave, 3);
+}
+
+// <G^P_p G_r G_s> (three placements) and <G_p G_r G_s> for every mode
+bool build_sn(bsp_plan p) {
+  const int P = p->P, nm = p->nmodes;
+  std::vector<std::array<int, 2>> pr;
+  std::vector<int> gp((size_t)P * P, -1);
+  for (int a = 0; a < P; ++a)
+    for (int b = a; b < P; ++b) {
+      gp[(size_t)a * P + b] = gp[(size_t)b * P + a] = (int)pr.size();
+      pr.push_back({a, b});
+    }
+  std::vector<int> th(2 * P);
+  for (int a = 0; a < 2 * P; ++a) th[a] = a;
+  std::vector<uint8_t> need(pr.size() * th.size(), 0);
+  p->sidx.assign((size_t)nm * 4, 0);
+  for (int i = 0; i < nm; ++i) {
+    const int a = p->modes[3 * i], b = p->modes[3 * i + 1], cc = p->modes[3 * i + 2];
+    const int e[4][2] = {{gp[(size_t)b * P + cc], P + a}, {gp[(size_t)a * P + cc], P + b},
+                         {gp[(size_t)a * P + b], P + cc}, {gp[(size_t)b * P + cc], a}};
+    for (int k = 0; k < 4; ++k) {
+      need[(size_t)e[k][0] * th.size() + e[k][1]] = 1;
+      p->sidx[4 * i + k] = e[k][0] * (int)th.size() + e[k][1];
+    }
+  }
+  return build_reduce(p->sn_rp, pr, th, need, 2 * P, reduce_max_rows_per_wave, 3);
+}
+
+// Main schedule: pairs (D0_b2 D0_b3, b2 >= b3), (M0_a M0_b), (M2_a M2_b);
+// thirds D^l_b1 interleaved (b1, l), then M^l_s interleaved (s, l).
+// exact: only triangles with nonzero counts; else every candidate.
+bool build_main(bsp_plan p, bool exact) {
+  const int nb = p->nbins, nl = p->nl, P = p->P;
+  std::vector<std::array<int, 2>> pr;
+  std::vector<int> pbin((size_t)nb * nb, -1);
+  for (int b2 = 0; b2 < nb; ++b2)
+    for (int b3 = 0; b3 <= b2; ++b3) {
+      pbin[(size_t)b2 * nb + b3] = (int)pr.size();
+      pr.push_back({b2, b3});
+    }
+  std::vector<int> pm0((size_t)P * P, -1), pm2((size_t)P * P, -1);
+  const int m0 = nl * nb;
+  if (p->modal) {
+    for (int a = 0; a < P; ++a)
+      for (int b = a; b < P; ++b) {
+        pm0[(size_t)a * P + b] = pm0[(size_t)b * P + a] = (int)pr.size();
+        pr.push_back({m0 + a, m0 + b});
+      }
+    if (nl >= 3)
+      for (int a = 0; a < P; ++a)
+        for (int b = a; b < P; ++b) {
+          pm2[(size_t)a * P + b] = pm2[(size_t)b * P + a] = (int)pr.size();
+          pr.push_back({m0 + P + a, m0 + P + b});
+        }
+  }
+  std::vector<int> th;
+  for (int b1 = 0; b1 < nb; ++b1)
+    for (int li = 0; li < nl; ++li) th.push_back(li * nb + b1);
+  if (p->modal)
+    for (int a = 0; a < P; ++a)
+      for (int li = 0; li < nl; ++li) th.push_back(m0 + li * P + a);
+  const int nth = (int)th.size();
+  auto tb = [&](int b1, int li) { return b1 * nl + li; };
+  auto tm = [&](int a, int li) { return nb * nl + a * nl + li; };
+  std::vector<uint8_t> need(pr.size() * nth, 0);
+  const std::vector<std::array<int, 3>>& tris = exact ? p->tri : p->cand;
+  const int ntri = (int)tris.size();
+  p->tri_tidx.assign((size_t)nl * ntri, 0);
+  p->tri_bins.assign(3 * (size_t)ntri, 0);
+  for (int i = 0; i < ntri; ++i) {
+    const int b1 = tris[i][0], b2 = tris[i][1], b3 = tris[i][2];
+    const int pi = pbin[(size_t)b2 * nb + b3];
+    for (int li = 0; li < nl; ++li) {
+      need[(size_t)pi * nth + tb(b1, li)] = 1;
+      p->tri_tidx[(size_t)li * ntri + i] = pi * nth + tb(b1, li);
+    }
+    p->tri_bins[3 * i] = b1;
+    p->tri_bins[3 * i + 1] = b2;
+    p->tri_bins[3 * i + 2] = b3;
+  }
+  p->combo.clear();
+  if (p->modal) {
+    const int nm = p->nmodes;
+    p->combo.assign((size_t)nl * nm * 6, -1);
+    for (int i = 0; i < nm; ++i) {
+      const int a = p->modes[3 * i], b = p->modes[3 * i + 1], cc = p->modes[3 * i + 2];
+      auto put = [&](int li, int slot, int pair, int third) {
+        need[(size_t)pair * nth + third] = 1;
+        p->combo[((size_t)li * nm + i) * 6 + slot] = pair * nth + third;
+      };
+      put(0, 0, pm0[(size_t)a * P + b], tm(cc, 0));
+      if (nl >= 2) {
+        put(1, 0, pm0[(size_t)b * P + cc], tm(a, 1));
+        put(1, 1, pm0[(size_t)a * P + cc], tm(b, 1));
+        put(1, 2, pm0[(size_t)a * P + b], tm(cc, 1));
+      }
+      if (nl >= 3) {
+        put(2, 0, pm0[(size_t)b * P + cc], tm(a, 2));
+        put(2, 1, pm0[(size_t)a * P + cc], tm(b, 2));
+        put(2, 2, pm0[(size_t)a * P + b], tm(cc, 2));
+        put(2, 3, pm2[(size_t)b * P + cc], tm(a, 0));
+        put(2, 4, pm2[(size_t)a * P + cc], tm(b, 0));
+        put(2, 5, pm2[(size_t)a * P + b], tm(cc, 0));
+      }
+    }
+  }
+  return build_reduce(p->main_rp, pr, th, need, p->F, reduce_max_rows_per_wave, 1);
+}
+
+}  // namespace
+
+// =========================================================================== API
+
+extern "C" {
+
+const char* bsp_last_error(bsp_plan p) { return p ? p->err.c_str() : g_create_error.c_str(); }
+
+bsp_status bsp_plan_create(bsp_plan* out, const bsp_geom* g, const bsp_modal_basis* m, void* stream) {
+  bsp_plan p = nullptr;
+  if (!out || !g) return fail(p, BSP_ERR_ARG, "null argument");
+  *out = nullptr;
+  const int Nr = g->n_reduce ? g->n_reduce : g->n;
+  if (!fft_size_supported(g->n) || !fft_size_supported(Nr))
+    return fail(p, BSP_ERR_SIZE, "unsupported grid size");
+  if (g->lmax != 0 && g->lmax != 2 && g->lmax != 4) return fail(p, BSP_ERR_ARG, "lmax must be 0, 2 or 4");
+  if (g->nbins < 1 || g->nbins > 64) return fail(p, BSP_ERR_ARG, "nbins must be in [1, 64]");
+  if (!(g->box > 0) || !(g->dk > 0)) return fail(p, BSP_ERR_ARG, "box and dk must be positive");
+  if (g->window != 0 && g->window != 1) return fail(p, BSP_ERR_ARG, "window must be 0 or 1");
+  const double e0 = 2.0 * g->k0 - g->dk;
+  if (std::fabs(2.0 * g->k0 - std::rint(2.0 * g->k0)) > 1e-9 || std::fabs(g->dk - std::rint(g->dk)) > 1e-9 || e0 <= 0)
+    return fail(p, BSP_ERR_ARG, "2 k0 and dk must be integers with k0 > dk/2");
+  p = new bsp_plan_s();
+  p->g = *g;
+  p->stream = reinterpret_cast<hipStream_t>(stream);
+  p->N = g->n;
+  p->Nr = Nr;
+  p->nbins = g->nbins;
+  p->nl = g->lmax / 2 + 1;
+  p->plane = g->los == 0 ? 1 : 0;
+  p->nlos = p->plane ? 1 : (g->lmax == 0 ? 1 : (g->lmax == 2 ? 7 : 22));
+  p->ngrid = g->interlace ? 2 : 1;
+  p->V = g->box * g->box * g->box;
+  p->kf = 2.0 * M_PI / g->box;
+  p->kmin = g->k0 - 0.5 * g->dk;
+  p->kmax = g->k0 + (g->nbins - 1) * g->dk + 0.5 * g->dk;
+  // shells: (2 c_b - dk)^2 <= 4 n^2 < (2 c_b + dk)^2
+  std::vector<int64_t> lo(g->nbins), hi(g->nbins);
+  for (int b = 0; b < g->nbins; ++b) {
+    const int64_t a = (int64_t)std::llround(2.0 * (g->k0 + b * g->dk) - g->dk);
+    const int64_t z = (int64_t)std::llround(2.0 * (g->k0 + b * g->dk) + g->dk);
+    lo[b] = a * a;
+    hi[b] = z * z;
+  }
+  p->n2max = (int)((hi[g->nbins - 1] - 1) / 4);
+  p->c = (int)std::floor(std::sqrt((double)p->n2max));
+  while ((int64_t)(p->c + 1) * (p->c + 1) <= p->n2max) ++p->c;
+  while ((int64_t)p->c * p->c > p->n2max) --p->c;
+  if (3 * p->c >= Nr || 3 * p->c >= p->N) {
+    delete p;
+    return fail(nullptr, BSP_ERR_ALIAS, "3 c_max >= N': closed triangles would wrap");
+  }
+  p->cz = (p->c + 1 + 15) / 16 * 16;
+  const int w = 2 * p->c + 1;
+  p->spec = (int64_t)w * w * p->cz;
+  p->bin_of_n2.assign(p->n2max + 1, -1);
+  for (int n2 = 0; n2 <= p->n2max; ++n2)
+    for (int b = 0; b < g->nbins; ++b)
+      if (4 * (int64_t)n2 >= lo[b] && 4 * (int64_t)n2 < hi[b]) p->bin_of_n2[n2] = b;
+  // modes per shell over the full lattice, and candidate triangles
+  p->nb_modes.assign(g->nbins, 0);
+  for (int x = -p->c; x <= p->c; ++x)
+    for (int y = -p->c; y <= p->c; ++y)
+      for (int z = -p->c; z <= p->c; ++z) {
+        const int n2 = x * x + y * y + z * z;
+        if (n2 <= p->n2max && p->bin_of_n2[n2] >= 0) p->nb_modes[p->bin_of_n2[n2]]++;
+      }
+  for (int b1 = 0; b1 < g->nbins; ++b1)
+    for (int b2 = 0; b2 <= b1; ++b2)
+      for (int b3 = 0; b3 <= b2; ++b3) p->cand.push_back({b1, b2, b3});
+  // modal basis
+  if (m && m->nmodes > 0) {
+    if (m->P < 1 || m->P > 16 || !m->modes || !m->pfid) {
+      delete p;
+      return fail(nullptr, BSP_ERR_ARG, "bad modal basis");
+    }
+    if (m->pfid_len <= p->n2max) {
+      delete p;
+      return fail(nullptr, BSP_ERR_ARG, "pfid table shorter than the modal range");
+    }
+    p->modal = true;
+    p->P = m->P;
+    p->nmodes = m->nmodes;
+    p->nU = m->P * (m->P + 1) / 2;
+    p->modes.assign(m->modes, m->modes + 3 * (size_t)m->nmodes);
+    for (int i = 0; i < m->nmodes; ++i) {
+      const int a = p->modes[3 * i], b = p->modes[3 * i + 1], cc = p->modes[3 * i + 2];
+      if (!(0 <= a && a <= b && b <= cc && cc < m->P)) {
+        delete p;
+        return fail(nullptr, BSP_ERR_ARG, "modes must satisfy 0 <= p <= r <= s < P");
+      }
+    }
+    p->pfid.assign(m->pfid, m->pfid + m->pfid_len);
+    for (int n2 = 1; n2 <= p->n2max; ++n2)
+      if (p->bin_of_n2[n2] >= 0 && !(p->pfid[n2] > 0)) {
+        delete p;
+        return fail(nullptr, BSP_ERR_ARG, "pfid must be positive on the modal range");
+      }
+  }
+  p->F = p->nl * p->nbins + (p->modal ? p->nl * p->P : 0);
+  if (p->F > 128) {
+    delete p;
+    return fail(nullptr, BSP_ERR_ARG, "more than 128 shell and modal fields");
+  }
+  // ---- device tables
+  auto tw = [&](int n, bool dbl) -> void* {
+    std::vector<double> t = twiddles(n);
+    if (dbl) return upload(p, t);
+    std::vector<float> f(t.begin(), t.end());
+    return upload(p, f);
+  };
+  p->tw32_N = reinterpret_cast<float2*>(tw(p->N, false));
+  p->tw32_Nr = reinterpret_cast<float2*>(tw(p->Nr, false));
+  p->tw64_Nr = reinterpret_cast<double2*>(tw(p->Nr, true));
+  p->d_bin_of_n2 = upload(p, p->bin_of_n2);
+  p->d_nb_modes = upload(p, p->nb_modes);
+  const int tl = p->n2max + 1;
+  std::vector<float> tab32((size_t)(p->nbins + p->P) * tl, 0.f);
+  const int nrow64 = p->nbins + (p->modal ? p->nU + 2 * p->P : 0);
+  std::vector<double> tab64((size_t)nrow64 * tl, 0.0);
+  for (int n2 = 0; n2 < tl; ++n2) {
+    const int b = p->bin_of_n2[n2];
+    if (b >= 0) {
+      tab32[(size_t)b * tl + n2] = 1.f;
+      tab64[(size_t)b * tl + n2] = 1.0;
+    }
+  }
+  if (p->modal) {
+    for (int n2 = 1; n2 < tl; ++n2) {
+      if (p->bin_of_n2[n2] < 0) continue;  // the modal range is the union of the shells
+      const double kn = std::sqrt((double)n2);
+      const double k = p->kf * kn;
+      const double t = (2.0 * kn - p->kmin - p->kmax) / (p->kmax - p->kmin);
+      const double pf = p->pfid[n2];
+      std::vector<double> q(p->P);
+      for (int a = 0; a < p->P; ++a) q[a] = legendre(a, t);
+      for (int a = 0; a < p->P; ++a) tab32[(size_t)(p->nbins + a) * tl + n2] = (float)(q[a] / std::sqrt(k * pf));
+      int u = 0;
+      for (int a = 0; a < p->P; ++a)
+        for (int b = a; b < p->P; ++b, ++u) tab64[(size_t)(p->nbins + u) * tl + n2] = q[a] * q[b] / k;
+      for (int a = 0; a < p->P; ++a) {
+        tab64[(size_t)(p->nbins + p->nU + a) * tl + n2] = q[a] / std::sqrt(k * pf);
+        tab64[(size_t)(p->nbins + p->nU + p->P + a) * tl + n2] = q[a] * std::sqrt(pf / k);
+      }
+    }
+  }
+  p->d_tab32 = upload(p, tab32);
+  p->d_tab64 = upload(p, tab64);
+  // field metadata: main pipeline fields, then the precompute identity map
+  std::vector<int32_t> fe(p->F), ft(p->F);
+  for (int li = 0; li < p->nl; ++li)
+    for (int b = 0; b < p->nbins; ++b) {
+      fe[li * p->nbins + b] = li;
+      ft[li * p->nbins + b] = b;
+    }
+  if (p->modal)
+    for (int li = 0; li < p->nl; ++li)
+      for (int a = 0; a < p->P; ++a) {
+        fe[p->nl * p->nbins + li * p->P + a] = li;
+        ft[p->nl * p->nbins + li * p->P + a] = p->nbins + a;
+      }
+  p->d_field_ell = upload(p, fe);
+  p->d_field_tab = upload(p, ft);
+  std::vector<int32_t> zeros(std::max(nrow64, 1), 0), iota(std::max(nrow64, 1));
+  for (int i = 0; i < (int)iota.size(); ++i) iota[i] = i;
+  p->d_ones_ell = upload(p, zeros);
+  p->d_pre_tab = upload(p, iota);
+  p->d_err = dalloc<int32_t>(p, 1);
+  bool ok = build_counts(p) && upload_rp(p, p->cnt_rp) && (p->d_cnt_tidx = upload(p, p->cnt_tidx)) != nullptr;
+  if (ok && p->modal) {
+    std::vector<int32_t> urow(p->nU), grow(2 * p->P);
+    for (int u = 0; u < p->nU; ++u) urow[u] = p->nbins + u;
+    for (int a = 0; a < 2 * p->P; ++a) grow[a] = p->nbins + p->nU + a;
+    ok = build_gram(p) && upload_rp(p, p->gram_rp) && build_sn(p) && upload_rp(p, p->sn_rp) &&
+         (p->d_gidx = upload(p, p->gidx)) && (p->d_sidx = upload(p, p->sidx)) && (p->d_urow = upload(p, urow)) &&
+         (p->d_grow = upload(p, grow)) && (p->d_L = dalloc<double>(p, (size_t)p->nmodes * p->nmodes)) &&
+         (p->d_sn = dalloc<double>(p, 2 * (size_t)p->nmodes));
+  }
+  ok = ok && build_main(p, false);  // candidate schedule: bounds the workspace before the counts exist
+  if (!ok) {
+    delete p;
+    return fail(nullptr, BSP_ERR_ARG, "reduction schedule could not be built (too many fields or modes)");
+  }
+  if (!p->tw32_N || !p->tw32_Nr || !p->tw64_Nr || !p->d_bin_of_n2 || !p->d_tab32 || !p->d_tab64 || !p->d_err ||
+      !p->d_field_ell || !p->d_field_tab || !p->d_ones_ell || !p->d_pre_tab || !p->d_nb_modes) {
+    delete p;
+    return fail(nullptr, BSP_ERR_HIP, "device allocation of plan tables failed");
+  }
+  if (hipMemset(p->d_err, 0, sizeof(int32_t)) != hipSuccess) {
+    delete p;
+    return fail(nullptr, BSP_ERR_HIP, "hipMemset failed");
+  }
+  *out = p;
+  return BSP_OK;
+}
+
+bsp_status bsp_plan_destroy(bsp_plan p) {
+  if (!p) return BSP_ERR_ARG;
+  (void)hipStreamSynchronize(p->stream);
+  delete p;
+  return BSP_OK;
+}
+
+bsp_status bsp_plan_info(bsp_plan p, bsp_info* info) {
+  if (!p || !info) return fail(p, BSP_ERR_ARG, "null argument");
+  info->c = p->c;
+  info->cz = p->cz;
+  info->nl = p->nl;
+  info->nlos = p->nlos;
+  info->ngrid = p->ngrid;
+  info->n2max = p->n2max;
+  info->ncand = (int32_t)p->cand.size();
+  info->ntri = (int32_t)p->tri.size();
+  info->nfields_binned = p->nl * p->nbins;
+  info->nfields_modal = p->modal ? p->nl * p->P : 0;
+  info->spec_elems = p->spec;
+  return BSP_OK;
+}
+
+bsp_status bsp_workspace_size(bsp_plan p, size_t* bytes) {
+  if (!p || !bytes) return fail(p, BSP_ERR_ARG, "null argument");
+  // before bsp_precompute the main schedule covers every candidate triangle,
+  // a superset of the final one, so this bound stays valid afterwards
+  const Layout L = layout(p);
+  *bytes = std::max(L.total, L.pre_total);
+  return BSP_OK;
+}
+
+bsp_status bsp_set_workspace(bsp_plan p, void* dev, size_t bytes) {
+  if (!p) return BSP_ERR_ARG;
+  if (dev && (reinterpret_cast<uintptr_t>(dev) % ALIGN)) return fail(p, BSP_ERR_ARG, "workspace must be 256-byte aligned");
+  p->ws = reinterpret_cast<char*>(dev);
+  p->ws_bytes = dev ? bytes : 0;
+  return BSP_OK;
+}
+
+bsp_status bsp_sync(bsp_plan p) {
+  if (!p) return BSP_ERR_ARG;
+  HIPCHK(hipStreamSynchronize(p->stream));
+  int32_t e = 0;
+  HIPCHK(hipMemcpy(&e, p->d_err, sizeof(e), hipMemcpyDeviceToHost));
+  if (e) {
+    HIPCHK(hipMemset(p->d_err, 0, sizeof(int32_t)));
+    if (e & 1) return fail(p, BSP_ERR_DEVICE, "particle outside [0, N) or not finite");
+    if (e & 4) return fail(p, BSP_ERR_NUMERIC, "triangle count residual >= 1e-3");
+    if (e & 8) return fail(p, BSP_ERR_NUMERIC, "Gram matrix not positive definite");
+    return fail(p, BSP_ERR_DEVICE, "device error");
+  }
+  return BSP_OK;
+}
+
+bsp_status bsp_grid_assign(bsp_plan p, const float* ux, const float* uy, const float* uz, const float* w, int64_t np,
+                           float* grids, double* wsum) {
+  if (!p || (np > 0 && (!ux || !uy || !uz)) || !grids || !wsum || np < 0) return fail(p, BSP_ERR_ARG, "null argument");
+  HIPCHK(launch_assign(ux, uy, uz, w, np, p->N, p->g.window, p->g.interlace, grids, wsum, p->d_err, p->stream));
+  return BSP_OK;
+}
+
+bsp_status bsp_fft_r2c(bsp_plan p, int32_t n, int32_t batch, const float* in, void* out_c64) {
+  if (!p || !in || !out_c64 || batch < 1) return fail(p, BSP_ERR_ARG, "bad argument");
+  if (!fft_size_supported(n)) return fail(p, BSP_ERR_SIZE, "unsupported size");
+  const float2* tw = (n == p->N) ? p->tw32_N : (n == p->Nr ? p->tw32_Nr : nullptr);
+  if (!tw) return fail(p, BSP_ERR_SIZE, "size must be the plan's N or N'");
+  const int h = n / 2 + 1;
+  float2* out = reinterpret_cast<float2*>(out_c64);
+  FwdZDesc fz{};
+  fz.ngrid = batch;
+  fz.nlos = 1;
+  fz.contrast = 0;
+  fz.plane = 1;
+  fz.cout = h;
+  fz.zs = h;
+  HIPCHK(launch_fwd_z_f32(n, in, out, fz, tw, p->stream));
+  PassDesc py{};
+  py.nouter = batch * n;
+  py.in_outer = py.out_outer = (int64_t)n * h;
+  py.in_row = py.out_row = h;
+  py.ncols = h;
+  py.in_rows = py.out_rows = n;
+  HIPCHK(launch_c2c_f32(n, -1, out, out, py, nullptr, tw, p->stream));
+  PassDesc px{};
+  px.nouter = batch;
+  px.in_outer = px.out_outer = (int64_t)n * n * h;
+  px.in_row = px.out_row = (int64_t)n * h;
+  px.ncols = n * h;
+  px.in_rows = px.out_rows = n;
+  HIPCHK(launch_c2c_f32(n, -1, out, out, px, nullptr, tw, p->stream));
+  return BSP_OK;
+}
+
+bsp_status bsp_fft_c2r(bsp_plan p, int32_t n, int32_t batch, const void* in_c64, float* out) {
+  if (!p || !in_c64 || !out || batch < 1) return fail(p, BSP_ERR_ARG, "bad argument");
+  if (!fft_size_supported(n)) return fail(p, BSP_ERR_SIZE, "unsupported size");
+  const float2* tw = (n == p->N) ? p->tw32_N : (n == p->Nr ? p->tw32_Nr : nullptr);
+  if (!tw) return fail(p, BSP_ERR_SIZE, "size must be the plan's N or N'");
+  const int h = n / 2 + 1;
+  const size_t one = (size_t)n * n * h * sizeof(float2);
+  bsp_status s = need_ws(p, one);
+  if (s != BSP_OK) return s;
+  const float2* in = reinterpret_cast<const float2*>(in_c64);
+  float2* tmp = reinterpret_cast<float2*>(p->ws);
+  for (int b = 0; b < batch; ++b) {
+    PassDesc px{};
+    px.nouter = 1;
+    px.in_outer = px.out_outer = 0;
+    px.in_row = px.out_row = (int64_t)n * h;
+    px.ncols = n * h;
+    px.in_rows = px.out_rows = n;
+    HIPCHK(launch_c2c_f32(n, +1, in + (size_t)b * n * n * h, tmp, px, nullptr, tw, p->stream));
+    PassDesc py{};
+    py.nouter = n;
+    py.in_outer = py.out_outer = (int64_t)n * h;
+    py.in_row = py.out_row = h;
+    py.ncols = h;
+    py.in_rows = py.out_rows = n;
+    HIPCHK(launch_c2c_f32(n, +1, tmp, tmp, py, nullptr, tw, p->stream));
+    HIPCHK(launch_inv_z_f32(n, tmp, out + (size_t)b * n * n * n, 1, h, h, 0, 0, tw, p->stream));
+  }
+  return BSP_OK;
+}
+
+bsp_status bsp_los_moments(bsp_plan p, const float* grids, const double* wsum, void* delta_l) {
+  if (!p || !grids || !wsum || !delta_l) return fail(p, BSP_ERR_ARG, "null argument");
+  const Layout L = layout(p);
+  bsp_status s = need_ws(p, L.s_grid + L.s_Z + L.s_Y);
+  if (s != BSP_OK) return s;
+  return forward_moments(p, grids, p->ngrid, 1, wsum, p->g.compensate, reinterpret_cast<float2*>(delta_l), p->ws);
+}
+
+bsp_status bsp_grid_entry(bsp_plan p, const float* delta, void* delta_l) {
+  if (!p || !delta || !delta_l) return fail(p, BSP_ERR_ARG, "null argument");
+  const Layout L = layout(p);
+  bsp_status s = need_ws(p, L.s_Z + L.s_Y);
+  if (s != BSP_OK) return s;
+  return forward_moments(p, delta, 1, 0, nullptr, 0, reinterpret_cast<float2*>(delta_l), p->ws);
+}
+
+bsp_status bsp_filter_fields(bsp_plan p, const void* delta_l, int32_t nfilt, const int32_t* filt, float* fields) {
+  if (!p || !delta_l || !filt || !fields || nfilt < 1) return fail(p, BSP_ERR_ARG, "bad argument");
+  std::vector<int32_t> fe(nfilt), ft(nfilt);
+  for (int i = 0; i < nfilt; ++i) {
+    const int li = filt[3 * i], kind = filt[3 * i + 1], idx = filt[3 * i + 2];
+    if (li < 0 || li >= p->nl) return fail(p, BSP_ERR_ARG, "ell index out of range");
+    if (kind == 0) {
+      if (idx < 0 || idx >= p->nbins) return fail(p, BSP_ERR_ARG, "bin index out of range");
+      ft[i] = idx;
+    } else if (kind == 1) {
+      if (!p->modal || idx < 0 || idx >= p->P) return fail(p, BSP_ERR_ARG, "modal index out of range");
+      ft[i] = p->nbins + idx;
+    } else {
+      return fail(p, BSP_ERR_ARG, "filter kind must be 0 or 1");
+    }
+    fe[i] = li;
+  }
+  const Layout L = layout(p);
+  const size_t meta = align_up(2 * (size_t)nfilt * sizeof(int32_t));
+  const int fb = std::min(L.fb, (nfilt + 1) / 2 * 2);
+  bsp_status s = need_ws(p, meta + inv_scratch(p, fb, sizeof(float2)));
+  if (s != BSP_OK) return s;
+  int32_t* dmeta = reinterpret_cast<int32_t*>(p->ws);
+  std::vector<int32_t> both(fe);
+  both.insert(both.end(), ft.begin(), ft.end());
+  HIPCHK(hipMemcpyAsync(dmeta, both.data(), both.size() * sizeof(int32_t), hipMemcpyHostToDevice, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return inverse_fields<float>(p, reinterpret_cast<const float2*>(delta_l), p->spec, nfilt, dmeta, dmeta + nfilt,
+                               p->d_tab32, fields, p->ws + meta, fb);
+}
+
+bsp_status bsp_triple_reduce(bsp_plan p, const float* fields, int32_t nfields, int64_t K, const int32_t* pairs,
+                             int32_t npairs, const int32_t* thirds, int32_t nthirds, const uint8_t* need,
+                             bsp_precision prec, double* T) {
+  if (!p || !fields || !pairs || !thirds || !T || nfields < 1 || nfields > 128 || npairs < 1 || nthirds < 1 ||
+      nthirds > 128 || K < 1)
+    return fail(p, BSP_ERR_ARG, "bad argument");
+  if (prec < BSP_FP32 || prec > BSP_FP16X3) return fail(p, BSP_ERR_ARG, "bad precision");
+  std::vector<std::array<int, 2>> pr(npairs);
+  for (int i = 0; i < npairs; ++i) {
+    pr[i] = {pairs[2 * i], pairs[2 * i + 1]};
+    if (pr[i][0] < 0 || pr[i][0] >= nfields || pr[i][1] < 0 || pr[i][1] >= nfields)
+      return fail(p, BSP_ERR_ARG, "pair field out of range");
+  }
+  std::vector<int> th(thirds, thirds + nthirds);
+  for (int t : th)
+    if (t < 0 || t >= nfields) return fail(p, BSP_ERR_ARG, "third field out of range");
+  std::vector<uint8_t> nd;
+  if (need) nd.assign(need, need + (size_t)npairs * nthirds);
+  if (!build_reduce(p->call_rp, pr, th, nd, nfields, reduce_max_rows_per_wave, (int)prec))
+    return fail(p, BSP_ERR_ARG, "reduction shape not supported");
+  const size_t meta = align_up(p->call_rp.words * sizeof(int32_t));
+  const size_t sc = align_up((size_t)nfields * sizeof(float)) * 2;
+  const size_t part = partial_bytes(p->call_rp, K, (int)prec, sizeof(float));
+  bsp_status s = need_ws(p, meta + sc + part);
+  if (s != BSP_OK) return s;
+  int32_t* dm = reinterpret_cast<int32_t*>(p->ws);
+  HIPCHK(hipMemcpyAsync(dm, p->call_rp.packed.data(), p->call_rp.words * sizeof(int32_t), hipMemcpyHostToDevice,
+                        p->stream));
+  bind_reduce(p->call_rp, dm);
+  float* scale = nullptr;
+  if (prec == BSP_FP16X3) {
+    scale = reinterpret_cast<float*>(p->ws + meta);
+    s = field_scales(p, fields, nfields, K, scale, reinterpret_cast<unsigned*>(p->ws + meta + sc / 2));
+    if (s != BSP_OK) return s;
+  }
+  s = run_reduce<float>(p, p->call_rp, fields, K, (int)prec, scale, T, p->ws + meta + sc, p->ws_bytes - meta - sc, 1.0);
+  if (s != BSP_OK) return s;
+  HIPCHK(hipStreamSynchronize(p->stream));  // host staging of the schedule stays valid until here
+  return BSP_OK;
+}
+
+// ---------------------------------------------------------------- precompute
+
+bsp_status bsp_precompute(bsp_plan p) {
+  if (!p) return BSP_ERR_ARG;
+  const Layout L = layout(p);
+  bsp_status s = need_ws(p, L.pre_total);
+  if (s != BSP_OK) return s;
+  const int Nr = p->Nr;
+  const int64_t K = (int64_t)Nr * Nr * Nr;
+  char* ws = p->ws;
+  double2* ones = reinterpret_cast<double2*>(ws);
+  double* f64 = reinterpret_cast<double*>(ws + L.pre_ones);
+  double* T64 = reinterpret_cast<double*>(ws + L.pre_ones + L.pre_fields);
+  char* scr = ws + L.pre_ones + L.pre_fields + L.pre_T;
+  const size_t scr_bytes = p->ws_bytes - (L.pre_ones + L.pre_fields + L.pre_T);
+  hipLaunchKernelGGL(k_fill_ones, dim3((unsigned)((p->spec + 255) / 256)), dim3(256), 0, p->stream, ones, p->spec);
+  HIPCHK(hipGetLastError());
+  // --- triangle counts: I_b for every shell, T[(b2,b3)][b1] over the candidates
+  s = inverse_fields<double>(p, ones, 0, p->nbins, p->d_ones_ell, p->d_pre_tab, p->d_tab64, f64, scr, L.fb64);
+  if (s != BSP_OK) return s;
+  s = run_reduce<double>(p, p->cnt_rp, f64, K, 3, nullptr, T64, scr, scr_bytes, 1.0);
+  if (s != BSP_OK) return s;
+  int64_t* dc = reinterpret_cast<int64_t*>(scr);
+  HIPCHK(launch_counts_finalize(T64, p->d_cnt_tidx, (int)p->cand.size(), 1.0 / (double)K, dc, p->d_err, p->stream));
+  s = bsp_sync(p);
+  if (s != BSP_OK) return s;
+  std::vector<int64_t> cc(p->cand.size());
+  HIPCHK(hipMemcpy(cc.data(), dc, cc.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+  p->tri.clear();
+  p->counts.clear();
+  for (size_t i = 0; i < cc.size(); ++i)
+    if (cc[i] > 0) {
+      p->tri.push_back(p->cand[i]);
+      p->counts.push_back(cc[i]);
+    }
+  // --- modal geometry: Gram matrix, Cholesky factor, shot-noise integrals
+  if (p->modal) {
+    const int nm = p->nmodes;
+    s = inverse_fields<double>(p, ones, 0, p->nU, p->d_ones_ell, p->d_urow, p->d_tab64, f64, scr, L.fb64);
+    if (s != BSP_OK) return s;
+    s = run_reduce<double>(p, p->gram_rp, f64, K, 3, nullptr, T64, scr, scr_bytes, 1.0);
+    if (s != BSP_OK) return s;
+    HIPCHK(launch_gram_assemble(T64, p->d_gidx, nm, 1.0 / (6.0 * p->V * p->V * (double)K), p->d_L, p->stream));
+    HIPCHK(hipStreamSynchronize(p->stream));
+    p->gamma_h.resize((size_t)nm * nm);
+    HIPCHK(hipMemcpy(p->gamma_h.data(), p->d_L, p->gamma_h.size() * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(launch_cholesky(p->d_L, nm, p->d_err, p->stream));
+    s = bsp_sync(p);
+    if (s != BSP_OK) return s;
+    p->chol_h.resize((size_t)nm * nm);
+    HIPCHK(hipMemcpy(p->chol_h.data(), p->d_L, p->chol_h.size() * sizeof(double), hipMemcpyDeviceToHost));
+    s = inverse_fields<double>(p, ones, 0, 2 * p->P, p->d_ones_ell, p->d_grow, p->d_tab64, f64, scr, L.fb64);
+    if (s != BSP_OK) return s;
+    s = run_reduce<double>(p, p->sn_rp, f64, K, 3, nullptr, T64, scr, scr_bytes, 1.0);
+    if (s != BSP_OK) return s;
+    HIPCHK(launch_sn_assemble(T64, p->d_sidx, nm, 1.0 / (p->V * p->V * (double)K), p->d_sn, p->stream));
+    s = bsp_sync(p);
+    if (s != BSP_OK) return s;
+  }
+  // --- main reduction schedule restricted to triangles with nonzero counts
+  if (!build_main(p, true)) return fail(p, BSP_ERR_ARG, "main reduction shape not supported");
+  if (!upload_rp(p, p->main_rp)) return fail(p, BSP_ERR_HIP, "allocation failed");
+  p->d_counts = upload(p, p->counts);
+  p->d_tri_tidx = upload(p, p->tri_tidx);
+  p->d_tri_bins = upload(p, p->tri_bins);
+  if (p->modal) p->d_combo = upload(p, p->combo);
+  if (!p->d_counts || !p->d_tri_tidx || !p->d_tri_bins || (p->modal && !p->d_combo))
+    return fail(p, BSP_ERR_HIP, "allocation failed");
+  p->pre_done = true;
+  return BSP_OK;
+}
+
+bsp_status bsp_geometry(bsp_plan p, int32_t* tri, int64_t* counts, double* gamma, double* chol) {
+  if (!p) return BSP_ERR_ARG;
+  if (!p->pre_done) return fail(p, BSP_ERR_STATE, "bsp_precompute has not run");
+  for (size_t i = 0; i < p->tri.size(); ++i) {
+    if (tri)
+      for (int a = 0; a < 3; ++a) tri[3 * i + a] = p->tri[i][a];
+    if (counts) counts[i] = p->counts[i];
+  }
+  if (gamma && p->modal) std::memcpy(gamma, p->gamma_h.data(), p->gamma_h.size() * sizeof(double));
+  if (chol && p->modal) std::memcpy(chol, p->chol_h.data(), p->chol_h.size() * sizeof(double));
+  return BSP_OK;
+}
+
+// ---------------------------------------------------------------- estimators
+
+namespace {
+
+// fields -> T -> B, Pbar, modal numerators and coefficients (everything after delta_l)
+bsp_status estimate_from_spectrum(bsp_plan p, const float2* dl, bsp_precision prec, const double* nbar_dev,
+                                  double* B, double* B0sub, double* Pbar, double* bnum, double* alpha, double* beta,
+                                  bool binned, bool modal_out) {
+  const Layout L = layout(p);
+  const int Nr = p->Nr;
+  const int64_t K = (int64_t)Nr * Nr * Nr;
+  char* ws = p->ws;
+  float* fields = reinterpret_cast<float*>(ws + L.dl);
+  double* T = reinterpret_cast<double*>(ws + L.dl + L.fields);
+  double* small = reinterpret_cast<double*>(ws + L.dl + L.fields + L.T);
+  double* psum = small;               // [64]
+  double* bn_tmp = small + 64;        // [3 * 128]
+  double* al_tmp = small + 64 + 384;  // [3 * 128]
+  double* be_tmp = small + 64 + 768;  // [3 * 128]
+  float* scale = reinterpret_cast<float*>(small + 2048);
+  unsigned* tmpu = reinterpret_cast<unsigned*>(small + 3072);
+  char* scr = ws + L.dl + L.fields + L.T + L.small;
+  const size_t scr_bytes = p->ws_bytes - (L.dl + L.fields + L.T + L.small);
+  bsp_status s = inverse_fields<float>(p, dl, p->spec, p->F, p->d_field_ell, p->d_field_tab, p->d_tab32, fields, scr,
+                                       L.fb);
+  if (s != BSP_OK) return s;
+  const float* sc = nullptr;
+  if (prec == BSP_FP16X3) {
+    s = field_scales(p, fields, p->F, K, scale, tmpu);
+    if (s != BSP_OK) return s;
+    sc = scale;
+  }
+  s = run_reduce<float>(p, p->main_rp, fields, K, (int)prec, sc, T, scr, scr_bytes, 1.0);
+  if (s != BSP_OK) return s;
+  HIPCHK(hipMemsetAsync(psum, 0, 64 * sizeof(double), p->stream));
+  HIPCHK(launch_shell_power(dl, p->c, p->cz, p->d_bin_of_n2, p->n2max, p->nbins, psum, p->stream));
+  const double N = p->N;
+  if (binned && B) {
+    const double norm_b = p->V * p->V / (std::pow(N, 9) * (double)K);
+    const double pnorm = p->V / std::pow(N, 6);
+    HIPCHK(launch_binned_finalize(T, p->d_tri_tidx, (int)p->tri.size(), p->nl, p->d_counts, psum, p->d_nb_modes,
+                                  p->nbins, p->d_tri_bins, norm_b, pnorm, nbar_dev, B, B0sub, Pbar, p->stream));
+  } else if (Pbar) {
+    const double pnorm = p->V / std::pow(N, 6);
+    HIPCHK(launch_binned_finalize(T, p->d_tri_tidx, 0, p->nl, p->d_counts, psum, p->d_nb_modes, p->nbins,
+                                  p->d_tri_bins, 0.0, pnorm, nullptr, B, nullptr, Pbar, p->stream));
+  }
+  if (modal_out && p->modal) {
+    const int nm = p->nmodes;
+    double* bo = bnum ? bnum : bn_tmp;
+    double* ao = alpha ? alpha : al_tmp;
+    double* beo = beta ? beta : be_tmp;
+    if (nm > 128) return fail(p, BSP_ERR_ARG, "more than 128 modes");
+    const double scale_b = 1.0 / ((double)K * std::pow(N, 9));
+    HIPCHK(launch_modal_assemble(T, p->d_combo, nm, p->nl, scale_b, p->d_sn, nbar_dev, bo, p->stream));
+    HIPCHK(launch_tri_solve(p->d_L, nm, p->nl, bo, ao, beo, p->stream));
+  }
+  return BSP_OK;
+}
+
+}  // namespace
+
+bsp_status bsp_modal_coeffs(bsp_plan p, const void* delta_l, bsp_precision prec, double nbar, double* bnum,
+                            double* alpha, double* beta) {
+  if (!p || !delta_l) return fail(p, BSP_ERR_ARG, "null argument");
+  if (!p->modal) return fail(p, BSP_ERR_STATE, "plan has no modal basis");
+  if (!p->pre_done) return fail(p, BSP_ERR_STATE, "bsp_precompute has not run");
+  if (prec < BSP_FP32 || prec > BSP_FP16X3) return fail(p, BSP_ERR_ARG, "bad precision");
+  const Layout L = layout(p);
+  bsp_status s = need_ws(p, L.total);
+  if (s != BSP_OK) return s;
+  double* nb = reinterpret_cast<double*>(p->ws + L.dl + L.fields + L.T) + 4000;
+  p->host_scalar = nbar;
+  HIPCHK(hipMemcpyAsync(nb, &p->host_scalar, sizeof(double), hipMemcpyHostToDevice, p->stream));
+  return estimate_from_spectrum(p, reinterpret_cast<const float2*>(delta_l), prec, nbar > 0 ? nb : nullptr, nullptr,
+                                nullptr, nullptr, bnum, alpha, beta, false, true);
+}
+
+bsp_status bsp_bispectrum_multipoles(bsp_plan p, const float* ux, const float* uy, const float* uz, const float* w,
+                                     int64_t np, bsp_precision prec, double* B, double* B0sub, double* Pbar,
+                                     double* bnum, double* alpha, double* beta) {
+  if (!p || !ux || !uy || !uz || !B || np < 1) return fail(p, BSP_ERR_ARG, "bad argument");
+  if (!p->pre_done) return fail(p, BSP_ERR_STATE, "bsp_precompute has not run");
+  if (prec < BSP_FP32 || prec > BSP_FP16X3) return fail(p, BSP_ERR_ARG, "bad precision");
+  const Layout L = layout(p);
+  bsp_status s = need_ws(p, L.total);
+  if (s != BSP_OK) return s;
+  char* scr = p->ws + L.dl + L.fields + L.T + L.small;
+  double* small = reinterpret_cast<double*>(p->ws + L.dl + L.fields + L.T);
+  double* wsum = small + 4000;
+  double* nbar = small + 4001;
+  float* grids = reinterpret_cast<float*>(scr);
+  float2* dl = reinterpret_cast<float2*>(p->ws);
+  HIPCHK(hipMemsetAsync(grids, 0, (size_t)p->ngrid * p->N * p->N * p->N * sizeof(float), p->stream));
+  HIPCHK(hipMemsetAsync(wsum, 0, sizeof(double), p->stream));
+  {
+    StageTimer t(p, 0);
+    HIPCHK(launch_assign(ux, uy, uz, w, np, p->N, p->g.window, p->g.interlace, grids, wsum, p->d_err, p->stream));
+  }
+  HIPCHK(launch_scale_scalar(wsum, 1.0 / p->V, nbar, p->stream));
+  s = forward_moments(p, grids, p->ngrid, 1, wsum, p->g.compensate, dl, scr + L.s_grid);
+  if (s != BSP_OK) return s;
+  return estimate_from_spectrum(p, dl, prec, nbar, B, B0sub, Pbar, bnum, alpha, beta, true, true);
+}
+
+bsp_status bsp_bispectrum_field(bsp_plan p, const float* delta, bsp_precision prec, double* B, double* Pbar,
+                                double* bnum, double* alpha, double* beta) {
+  if (!p || !delta || !B) return fail(p, BSP_ERR_ARG, "bad argument");
+  if (!p->pre_done) return fail(p, BSP_ERR_STATE, "bsp_precompute has not run");
+  if (prec < BSP_FP32 || prec > BSP_FP16X3) return fail(p, BSP_ERR_ARG, "bad precision");
+  const Layout L = layout(p);
+  bsp_status s = need_ws(p, L.total);
+  if (s != BSP_OK) return s;
+  char* scr = p->ws + L.dl + L.fields + L.T + L.small;
+  float2* dl = reinterpret_cast<float2*>(p->ws);
+  s = forward_moments(p, delta, 1, 0, nullptr, 0, dl, scr);
+  if (s != BSP_OK) return s;
+  return estimate_from_spectrum(p, dl, prec, nullptr, B, nullptr, Pbar, bnum, alpha, beta, true, true);
+}
+
+bsp_status bsp_set_timing(bsp_plan p, int32_t enable) {
+  if (!p) return BSP_ERR_ARG;
+  HIPCHK(hipStreamSynchronize(p->stream));
+  p->timing = enable != 0;
+  p->ev_used = 0;
+  for (int i = 0; i < 16; ++i) {
+    p->stage_ms[i] = 0.0;
+    p->stage_n[i] = 0;
+  }
+  return BSP_OK;
+}
+
+bsp_status bsp_stage_times(bsp_plan p, double* ms, int64_t* launches) {
+  if (!p || !ms) return fail(p, BSP_ERR_ARG, "null argument");
+  HIPCHK(hipStreamSynchronize(p->stream));
+  for (size_t i = 0; i < p->ev_used; ++i) {
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, p->ev_pool[i][0], p->ev_pool[i][1]));
+    p->stage_ms[p->ev_stage[i]] += t;
+    p->stage_n[p->ev_stage[i]] += 1;
+  }
+  p->ev_used = 0;
+  for (int i = 0; i < 16; ++i) {
+    ms[i] = p->stage_ms[i];
+    if (launches) launches[i] = p->stage_n[i];
+  }
+  return BSP_OK;
+}
+
+bsp_status bsp_batch_covariance(const double* x, int32_t m, int32_t d, double* cov, void* stream) {
+  bsp_plan p = nullptr;
+  if (!x || !cov || m < 2 || d < 1) return fail(p, BSP_ERR_ARG, "bad argument");
+  HIPCHK(launch_covariance(x, m, d, cov, reinterpret_cast<hipStream_t>(stream)));
+  return BSP_OK;
+}
+
+}  // extern "C"

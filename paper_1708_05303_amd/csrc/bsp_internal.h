@@ -1,0 +1,142 @@
+// Internal declarations shared by the HIP translation units of libbsp.
+// Not part of the public C ABI (see include/bsp.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstddef>
+
+namespace bsp {
+
+// ---------------------------------------------------------------- complex
+template <typename T> struct cplx_of;
+template <> struct cplx_of<float> { using type = float2; };
+template <> struct cplx_of<double> { using type = double2; };
+template <typename T> using cplx_t = typename cplx_of<T>::type;
+
+template <typename V> __device__ __forceinline__ V cadd(V a, V b) { return V{a.x + b.x, a.y + b.y}; }
+template <typename V> __device__ __forceinline__ V csub(V a, V b) { return V{a.x - b.x, a.y - b.y}; }
+template <typename V> __device__ __forceinline__ V cmul(V a, V b) {
+  return V{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename V> __device__ __forceinline__ V cconj(V a) { return V{a.x, -a.y}; }
+template <typename V, typename T> __device__ __forceinline__ V cscale(V a, T s) { return V{a.x * s, a.y * s}; }
+
+// ---------------------------------------------------------------- launch params
+
+// Strided column pass of a 3-D transform (see fft.hip).
+struct PassDesc {
+  int64_t in_outer, out_outer;   // element stride between outer batches
+  int64_t in_row, out_row;       // element stride between consecutive rows of the FFT axis
+  int32_t ncols;                 // contiguous inner columns per row
+  int32_t in_rows, in_off;       // input row r holds FFT index (r - in_off) mod N
+  int32_t out_rows, out_off;     // output row r receives FFT index (r - out_off) mod N
+  int32_t nouter;
+};
+
+// Shell / modal filter applied while loading the first inverse pass.
+struct FilterDesc {
+  const void* src;               // compact delta_l cube(s)
+  int64_t src_ell_stride;        // elements between ell cubes
+  const int32_t* field_ell;      // [nfields] ell slot of each field
+  const void* tables;            // [rows][tablen] weights by |n|^2 (float for FP32 passes, double for FP64)
+  const int32_t* field_table;    // [nfields] table row of each field
+  int32_t tablen;                // n2max + 1
+  int32_t c;                     // half width of the compact cube
+  int32_t cz;                    // padded kz extent
+  int32_t field0;                // first field of this launch
+};
+
+// Forward z pass with line-of-sight weighting.
+struct FwdZDesc {
+  int32_t ngrid, nlos;           // grids (1 or 2), LOS fields per grid (1, 7, 22)
+  int32_t contrast;              // 1: input is a density, form rho / rho_bar - 1
+  const double* wsum;            // sum of weights (device), used when contrast
+  double shift[2];               // node offset of each grid (0, 1/2)
+  double obs[3];                 // observer, grid units
+  int32_t plane;                 // 1: plane parallel (no weights)
+  int32_t cout, zs;              // kz kept, kz stride of the output
+};
+
+struct ReduceDesc {
+  int32_t nfields;               // fields in the stack (<= 128)
+  int64_t K;                     // points per field
+  int64_t field_stride;          // elements between fields
+  int32_t kchunk;                // points per workgroup chunk (multiple of 64)
+  int32_t nchunks;
+  int32_t ngroups;               // row-tile groups (grid.y)
+  int32_t nct;                   // column tiles of 16 thirds (<= 8)
+  const int32_t* wave_rows;      // [ngroups][8 waves][maxr] row tile ids, -1 none
+  const int32_t* row_mask;       // [nrt] bit c set: column tile c needed
+  const int32_t* tile_index;     // [nrt][8] compact tile id, -1 if not needed
+  const int32_t* tile_rc;        // [ntiles][2] row tile, column tile
+  int32_t ntiles;
+  const int32_t* pair_a;         // [nrt*16] field of the first pair factor (-1 pad)
+  const int32_t* pair_b;         // [nrt*16]
+  const int32_t* third;          // [nct*16] (-1 pad)
+  const float* scale;            // [nfields] power-of-two scales (FP16 path) or null
+};
+
+// ---------------------------------------------------------------- launchers
+// FFT passes (fft.hip). Return hipError_t of the launch.
+hipError_t launch_fwd_z_f32(int n, const float* in, float2* out, const FwdZDesc& d,
+                            const float2* tw, hipStream_t s);
+hipError_t launch_fwd_z_f64(int n, const double* in, double2* out, const FwdZDesc& d,
+                            const double2* tw, hipStream_t s);
+hipError_t launch_c2c_f32(int n, int sign, const float2* in, float2* out, const PassDesc& p,
+                          const FilterDesc* f, const float2* tw, hipStream_t s);
+hipError_t launch_c2c_f64(int n, int sign, const double2* in, double2* out, const PassDesc& p,
+                          const FilterDesc* f, const double2* tw, hipStream_t s);
+hipError_t launch_inv_z_f32(int n, const float2* in, float* out, int nfields, int cin, int zs,
+                            int64_t in_field, int64_t out_field, const float2* tw, hipStream_t s);
+hipError_t launch_inv_z_f64(int n, const double2* in, double* out, int nfields, int cin, int zs,
+                            int64_t in_field, int64_t out_field, const double2* tw, hipStream_t s);
+bool fft_size_supported(int n);
+
+// Assignment (assign.hip).
+hipError_t launch_assign(const float* ux, const float* uy, const float* uz, const float* w,
+                         int64_t np, int n, int window, int interlace, float* grids,
+                         double* wsum, int32_t* err, hipStream_t s);
+
+// LOS combination and shell sums (los.hip).
+struct LosDesc {
+  int32_t n, c, cz, ngrid, nlos, lmax, plane, window, compensate;
+  int32_t n2max;
+};
+hipError_t launch_los_combine(const float2* X, float2* delta_l, const LosDesc& d, hipStream_t s);
+hipError_t launch_los_combine_f64(const double2* X, double2* delta_l, const LosDesc& d, hipStream_t s);
+hipError_t launch_shell_power(const float2* delta0, int c, int cz, const int32_t* bin_of_n2,
+                              int n2max, int nbins, double* psum, hipStream_t s);
+
+// Triple reduction (reduce.hip).
+hipError_t launch_reduce(int prec, const float* fields, const ReduceDesc& d, float* partials,
+                         hipStream_t s);
+hipError_t launch_reduce_f64(const double* fields, const ReduceDesc& d, double* partials,
+                             hipStream_t s);
+hipError_t launch_combine_partials(const void* partials, int is_f64, const ReduceDesc& d,
+                                   int npairs, int nthirds, double* T, double tscale,
+                                   hipStream_t s);
+int reduce_waves_per_group();
+int reduce_max_rows_per_wave(int prec, int nct);
+
+// FP64 finishing kernels (fp64.hip).
+hipError_t launch_binned_finalize(const double* T, const int32_t* tri_tidx, int ntri, int nl,
+                                  const int64_t* counts, const double* psum, const int64_t* nb_modes,
+                                  int nbins, const int32_t* tri_bins, double norm_b, double pnorm,
+                                  const double* nbar, double* B, double* B0sub, double* Pbar, hipStream_t s);
+hipError_t launch_counts_finalize(const double* T, const int32_t* tidx, int ntri, double inv_k,
+                                  int64_t* counts, int32_t* err, hipStream_t s);
+hipError_t launch_modal_assemble(const double* T, const int32_t* combo, int nmodes, int nl,
+                                 double scale, const double* sn, const double* nbar, double* bnum,
+                                 hipStream_t s);
+hipError_t launch_gram_assemble(const double* T, const int32_t* gidx, int nmodes, double scale,
+                                double* gamma, hipStream_t s);
+hipError_t launch_sn_assemble(const double* T, const int32_t* sidx, int nmodes, double scale,
+                              double* sn, hipStream_t s);
+hipError_t launch_cholesky(double* A, int n, int32_t* err, hipStream_t s);
+hipError_t launch_tri_solve(const double* L, int n, int nrhs, const double* b, double* alpha,
+                            double* beta, hipStream_t s);
+hipError_t launch_covariance(const double* x, int m, int d, double* cov, hipStream_t s);
+hipError_t launch_scale_scalar(const double* x, double scale, double* y, hipStream_t s);
+
+}  // namespace bsp

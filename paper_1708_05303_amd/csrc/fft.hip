@@ -1,0 +1,445 @@
+// Radix-2/3/4/8 Stockham FFTs staged in LDS, and the three kinds of passes a
+// pruned 3-D transform is built from:
+//
+//   fwd_z : real lines along z -> half-complex, two real lines packed per
+//           complex transform; optionally forms the density contrast and the
+//           line-of-sight weights x_i x_j ..., so that one read of the grid
+//           feeds every weighted field delta(x) prod x_hat (the LOS moment field
+//           of the power-spectrum section of the paper, expanded in x-hat
+//           products).
+//   c2c   : a strided column pass along y or x; a workgroup owns W consecutive
+//           inner columns (one 128-byte row segment) and all N rows, so every
+//           global access is a coalesced row segment. Input and output rows may
+//           be pruned to the band |n| <= c the estimator needs; the shell or
+//           modal filter of the inverse transforms (the D^(l)_k and M^(l)_n
+//           fields of the standard and modal estimators) can be applied while
+//           loading.
+//   inv_z : half-complex -> real lines along z, two fields per complex
+//           transform (Hermitian fill of the missing half).
+//
+// Twiddles come from a per-length table exp(-2 pi i j / N) built on the host
+// in double precision and staged through LDS.
+#include "bsp_internal.h"
+
+namespace bsp {
+
+constexpr int pick_radix(int m) {
+  return (m % 8 == 0) ? 8 : (m % 4 == 0) ? 4 : (m % 2 == 0) ? 2 : (m % 3 == 0) ? 3 : 1;
+}
+constexpr int radix_at(int n, int s) {
+  int m = n;
+  for (int i = 0; i < s; ++i) m /= pick_radix(m);
+  return pick_radix(m);
+}
+constexpr int nstages(int n) {
+  int c = 0, m = n;
+  while (m > 1) {
+    m /= pick_radix(m);
+    ++c;
+  }
+  return c;
+}
+
+// multiply by SIGN * i
+template <int SIGN, typename V> __device__ __forceinline__ V mul_si(V a) {
+  if constexpr (SIGN < 0) return V{a.y, -a.x};
+  else return V{-a.y, a.x};
+}
+
+template <int R, int SIGN, typename V> __device__ __forceinline__ void butterfly(V* v) {
+  using T = decltype(v[0].x);
+  if constexpr (R == 2) {
+    V a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  } else if constexpr (R == 3) {
+    const T h = (T)0.86602540378443864676;  // sqrt(3)/2
+    V t1 = cadd(v[1], v[2]);
+    V t2 = V{v[0].x - (T)0.5 * t1.x, v[0].y - (T)0.5 * t1.y};
+    V d = csub(v[1], v[2]);
+    V t3 = mul_si<SIGN>(V{h * d.x, h * d.y});
+    v[0] = cadd(v[0], t1);
+    v[1] = cadd(t2, t3);
+    v[2] = csub(t2, t3);
+  } else if constexpr (R == 4) {
+    V a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
+    V a2 = cadd(v[1], v[3]), a3 = mul_si<SIGN>(csub(v[1], v[3]));
+    v[0] = cadd(a0, a2);
+    v[2] = csub(a0, a2);
+    v[1] = cadd(a1, a3);
+    v[3] = csub(a1, a3);
+  } else if constexpr (R == 8) {
+    const T r2 = (T)0.70710678118654752440;
+    V e[4] = {v[0], v[2], v[4], v[6]};
+    V o[4] = {v[1], v[3], v[5], v[7]};
+    butterfly<4, SIGN>(e);
+    butterfly<4, SIGN>(o);
+    // o[k] *= exp(SIGN i pi k / 4)
+    V o1 = V{r2 * o[1].x, r2 * o[1].y};
+    o1 = cadd(o1, mul_si<SIGN>(o1));
+    V o2 = mul_si<SIGN>(o[2]);
+    V o3 = mul_si<SIGN>(V{r2 * o[3].x, r2 * o[3].y});
+    o3 = cadd(o3, mul_si<SIGN>(o3));
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);
+    v[5] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);
+    v[6] = csub(e[2], o2);
+    v[3] = cadd(e[3], o3);
+    v[7] = csub(e[3], o3);
+  }
+}
+
+// One length-N transform held in buf[0..N) (LDS), computed by NT threads with
+// thread index t. All threads of the block must call this (it synchronises).
+// Stage s with sub-length NS: butterfly b reads b + r N/R, twiddles by
+// W_{NS R}^{r (b mod NS)}, and writes (b/NS) NS R + (b mod NS) + r NS.
+template <typename V, int N, int SIGN, int NT, int S, int NS>
+__device__ __forceinline__ void fft_stages(V* __restrict__ buf, const V* __restrict__ tw, int t) {
+  if constexpr (S < nstages(N)) {
+    constexpr int R = radix_at(N, S);
+    constexpr int NB = N / R;
+    constexpr int PER = (NB + NT - 1) / NT;
+    V v[PER][R];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int b = t + i * NT;
+      if ((NB % NT == 0) || b < NB) {
+        const int k = b % NS;
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[i][r] = buf[b + r * NB];
+        if constexpr (NS > 1) {
+#pragma unroll
+          for (int r = 1; r < R; ++r) {
+            V w = tw[r * k * (N / (NS * R))];
+            if constexpr (SIGN > 0) w.y = -w.y;
+            v[i][r] = cmul(v[i][r], w);
+          }
+        }
+        butterfly<R, SIGN>(v[i]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int b = t + i * NT;
+      if ((NB % NT == 0) || b < NB) {
+        const int k = b % NS;
+        const int d = (b / NS) * NS * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) buf[d + r * NS] = v[i][r];
+      }
+    }
+    __syncthreads();
+    fft_stages<V, N, SIGN, NT, S + 1, NS * R>(buf, tw, t);
+  }
+}
+
+// exponents (x, y, z) of the x-hat product of each LOS field: the empty
+// product, the 6 sorted pairs and the 15 sorted quadruples over {x, y, z}.
+__constant__ int8_t c_los_exp[22][3] = {
+    {0, 0, 0},
+    {2, 0, 0}, {1, 1, 0}, {1, 0, 1}, {0, 2, 0}, {0, 1, 1}, {0, 0, 2},
+    {4, 0, 0}, {3, 1, 0}, {3, 0, 1}, {2, 2, 0}, {2, 1, 1}, {2, 0, 2}, {1, 3, 0},
+    {1, 2, 1}, {1, 1, 2}, {1, 0, 3}, {0, 4, 0}, {0, 3, 1}, {0, 2, 2}, {0, 1, 3},
+    {0, 0, 4}};
+
+template <typename T> __device__ __forceinline__ T ipow(T x, int e) {
+  T r = (T)1;
+  for (int i = 0; i < e; ++i) r *= x;
+  return r;
+}
+
+// ---------------------------------------------------------------- fwd_z
+// grid: blockIdx.x -> group of L lines (x*N + y), blockIdx.y -> input grid.
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_fwd_z(const T* __restrict__ in, cplx_t<T>* __restrict__ out,
+                                               FwdZDesc d, const cplx_t<T>* __restrict__ twg) {
+  using V = cplx_t<T>;
+  constexpr int NT = (N >= 8) ? N / 8 : 1;
+  constexpr int L = 256 / NT;
+  constexpr int PAD = N + 1;
+  constexpr int E = N / NT;
+  __shared__ V buf[L * PAD];
+  __shared__ V tw[N];
+  for (int i = threadIdx.x; i < N; i += L * NT) tw[i] = twg[i];
+  const int ll = threadIdx.x / NT, t = threadIdx.x % NT;
+  const int64_t nlines = (int64_t)N * N;
+  const int64_t line = (int64_t)blockIdx.x * L + ll;
+  const bool valid = line < nlines;
+  const int g = blockIdx.y;
+  const int x = valid ? (int)(line / N) : 0, y = valid ? (int)(line % N) : 0;
+  T scale = (T)1, sub = (T)0;
+  if (d.contrast) {
+    scale = (T)((double)N * (double)N * (double)N / d.wsum[0]);
+    sub = (T)1;
+  }
+  const T* src = in + (int64_t)g * N * N * N + line * N;
+  T rv[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) rv[e] = valid ? src[t + e * NT] * scale - sub : (T)0;
+  T hx[E], hy[E], hz[E];
+  if (!d.plane) {
+    const T s = (T)d.shift[g];
+    const T rx = (T)x - s - (T)d.obs[0];
+    const T ry = (T)y - s - (T)d.obs[1];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const T rz = (T)(t + e * NT) - s - (T)d.obs[2];
+      const T inv = (T)1 / sqrt(rx * rx + ry * ry + rz * rz);
+      hx[e] = rx * inv;
+      hy[e] = ry * inv;
+      hz[e] = rz * inv;
+    }
+  }
+  __syncthreads();  // twiddles staged
+  V* b = buf + ll * PAD;
+  const int npair = (d.nlos + 1) / 2;
+  for (int p = 0; p < npair; ++p) {
+    const int f0 = 2 * p, f1 = 2 * p + 1;
+    const bool has1 = f1 < d.nlos;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      T w0 = (T)1, w1 = (T)0;
+      if (!d.plane) {
+        w0 = ipow(hx[e], c_los_exp[f0][0]) * ipow(hy[e], c_los_exp[f0][1]) * ipow(hz[e], c_los_exp[f0][2]);
+        if (has1)
+          w1 = ipow(hx[e], c_los_exp[f1][0]) * ipow(hy[e], c_los_exp[f1][1]) * ipow(hz[e], c_los_exp[f1][2]);
+      }
+      b[t + e * NT] = V{w0 * rv[e], w1 * rv[e]};
+    }
+    __syncthreads();
+    fft_stages<V, N, -1, NT, 0, 1>(b, tw, t);
+    if (valid) {
+      V* o0 = out + (((int64_t)g * d.nlos + f0) * nlines + line) * d.zs;
+      V* o1 = out + (((int64_t)g * d.nlos + f1) * nlines + line) * d.zs;
+      for (int k = t; k < d.cout; k += NT) {
+        const V zk = b[k], zm = b[(N - k) % N];
+        o0[k] = V{(zk.x + zm.x) * (T)0.5, (zk.y - zm.y) * (T)0.5};
+        if (has1) o1[k] = V{(zk.y + zm.y) * (T)0.5, (zm.x - zk.x) * (T)0.5};
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- c2c
+// grid: blockIdx.x -> column tile of W, blockIdx.y (+ gridDim.y * blockIdx.z) -> outer batch.
+template <typename T, int N, int W, int SIGN, bool FILT>
+__global__ __launch_bounds__(256) void k_c2c(const cplx_t<T>* __restrict__ in, cplx_t<T>* __restrict__ out,
+                                             PassDesc p, FilterDesc f, const cplx_t<T>* __restrict__ twg) {
+  using V = cplx_t<T>;
+  constexpr int NT = 256 / W;
+  constexpr int PAD = N + 1;
+  __shared__ V buf[W * PAD];
+  __shared__ V tw[N];
+  for (int i = threadIdx.x; i < N; i += 256) tw[i] = twg[i];
+  const int outer = blockIdx.y + gridDim.y * blockIdx.z;
+  if (outer >= p.nouter) return;  // uniform per block
+  const int c = threadIdx.x % W, j0 = threadIdx.x / W;
+  const int col = blockIdx.x * W + c;
+  const bool cv = col < p.ncols;
+  const V* src;
+  const T* tab = nullptr;
+  int fny = 0, fnz = 0;
+  bool fz_ok = true;
+  if constexpr (FILT) {
+    const int field = f.field0 + outer;
+    src = reinterpret_cast<const V*>(f.src) + (int64_t)f.field_ell[field] * f.src_ell_stride;
+    tab = reinterpret_cast<const T*>(f.tables) + (int64_t)f.field_table[field] * f.tablen;
+    fny = col / f.cz - f.c;
+    fnz = col % f.cz;
+    fz_ok = fnz <= f.c;
+  } else {
+    src = in + (int64_t)outer * p.in_outer;
+  }
+  V* dst = out + (int64_t)outer * p.out_outer;
+  for (int pos = j0; pos < N; pos += NT) {
+    const int r = (pos + p.in_off) % N;
+    V v = V{(T)0, (T)0};
+    if (cv && r < p.in_rows) {
+      if constexpr (FILT) {
+        if (fz_ok) {
+          const int nx = r - f.c;
+          const int n2 = nx * nx + fny * fny + fnz * fnz;
+          if (n2 < f.tablen) {
+            const T wgt = tab[n2];
+            if (wgt != (T)0) {
+              v = src[(int64_t)r * p.in_row + col];
+              v.x *= wgt;
+              v.y *= wgt;
+            }
+          }
+        }
+      } else {
+        v = src[(int64_t)r * p.in_row + col];
+      }
+    }
+    buf[c * PAD + pos] = v;
+  }
+  __syncthreads();
+  fft_stages<V, N, SIGN, NT, 0, 1>(buf + c * PAD, tw, j0);
+  if (cv) {
+    for (int r = j0; r < p.out_rows; r += NT) {
+      const int pos = (r - p.out_off + N) % N;
+      dst[(int64_t)r * p.out_row + col] = buf[c * PAD + pos];
+    }
+  }
+}
+
+// ---------------------------------------------------------------- inv_z
+// grid: blockIdx.x -> group of L lines, blockIdx.y -> field pair.
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_inv_z(const cplx_t<T>* __restrict__ in, T* __restrict__ out, int nfields,
+                                               int cin, int zs, int64_t in_field, int64_t out_field,
+                                               const cplx_t<T>* __restrict__ twg) {
+  using V = cplx_t<T>;
+  constexpr int NT = (N >= 8) ? N / 8 : 1;
+  constexpr int L = 256 / NT;
+  constexpr int PAD = N + 1;
+  __shared__ V buf[L * PAD];
+  __shared__ V tw[N];
+  for (int i = threadIdx.x; i < N; i += L * NT) tw[i] = twg[i];
+  const int ll = threadIdx.x / NT, t = threadIdx.x % NT;
+  const int64_t nlines = (int64_t)N * N;
+  const int64_t line = (int64_t)blockIdx.x * L + ll;
+  const bool valid = line < nlines;
+  const int f0 = 2 * blockIdx.y, f1 = f0 + 1;
+  const bool has1 = f1 < nfields;
+  const V* a = in + (int64_t)f0 * in_field + (valid ? line : 0) * zs;
+  const V* bb = in + (int64_t)f1 * in_field + (valid ? line : 0) * zs;
+  V* b = buf + ll * PAD;
+  for (int pos = t; pos < N; pos += NT) {
+    V z = V{(T)0, (T)0};
+    if (valid) {
+      if (pos < cin) {
+        const V A = a[pos];
+        const V B = has1 ? bb[pos] : V{(T)0, (T)0};
+        if (pos == 0 || 2 * pos == N) z = V{A.x, B.x};
+        else z = V{A.x - B.y, A.y + B.x};
+      } else if (pos > N - cin) {
+        const int k = N - pos;
+        const V A = a[k];
+        const V B = has1 ? bb[k] : V{(T)0, (T)0};
+        z = V{A.x + B.y, B.x - A.y};
+      }
+    }
+    b[pos] = z;
+  }
+  __syncthreads();
+  fft_stages<V, N, +1, NT, 0, 1>(b, tw, t);
+  if (valid) {
+    T* o0 = out + (int64_t)f0 * out_field + line * N;
+    T* o1 = out + (int64_t)f1 * out_field + line * N;
+    for (int pos = t; pos < N; pos += NT) {
+      o0[pos] = b[pos].x;
+      if (has1) o1[pos] = b[pos].y;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+
+bool fft_size_supported(int n) {
+  switch (n) {
+    case 16: case 32: case 64: case 96: case 128: case 192: case 256: case 384: case 512:
+      return true;
+    default:
+      return false;
+  }
+}
+
+#define BSP_FOR_SIZES(X) X(16) X(32) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
+
+template <typename T>
+static hipError_t fwd_z_impl(int n, const T* in, cplx_t<T>* out, const FwdZDesc& d, const cplx_t<T>* tw,
+                             hipStream_t s) {
+#define CASE(NN)                                                                        \
+  case NN: {                                                                            \
+    constexpr int NT = (NN >= 8) ? NN / 8 : 1;                                          \
+    constexpr int L = 256 / NT;                                                         \
+    dim3 grid((unsigned)(((int64_t)NN * NN + L - 1) / L), (unsigned)d.ngrid);           \
+    hipLaunchKernelGGL((k_fwd_z<T, NN>), grid, dim3(L * NT), 0, s, in, out, d, tw);     \
+    return hipGetLastError();                                                           \
+  }
+  switch (n) { BSP_FOR_SIZES(CASE) }
+#undef CASE
+  return hipErrorInvalidValue;
+}
+
+template <typename T, int N, int W>
+static hipError_t c2c_launch(int sign, const cplx_t<T>* in, cplx_t<T>* out, const PassDesc& p,
+                             const FilterDesc* f, const cplx_t<T>* tw, hipStream_t s) {
+  const unsigned tiles = (unsigned)((p.ncols + W - 1) / W);
+  unsigned gy = (unsigned)p.nouter, gz = 1;
+  while (gy > 65535) {
+    gz *= 2;
+    gy = (unsigned)((p.nouter + gz - 1) / gz);
+  }
+  dim3 grid(tiles, gy, gz);
+  FilterDesc fd{};
+  if (f) fd = *f;
+  if (sign < 0) {
+    if (f) hipLaunchKernelGGL((k_c2c<T, N, W, -1, true>), grid, dim3(256), 0, s, in, out, p, fd, tw);
+    else hipLaunchKernelGGL((k_c2c<T, N, W, -1, false>), grid, dim3(256), 0, s, in, out, p, fd, tw);
+  } else {
+    if (f) hipLaunchKernelGGL((k_c2c<T, N, W, +1, true>), grid, dim3(256), 0, s, in, out, p, fd, tw);
+    else hipLaunchKernelGGL((k_c2c<T, N, W, +1, false>), grid, dim3(256), 0, s, in, out, p, fd, tw);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t inv_z_impl(int n, const cplx_t<T>* in, T* out, int nfields, int cin, int zs,
+                             int64_t in_field, int64_t out_field, const cplx_t<T>* tw, hipStream_t s) {
+#define CASE(NN)                                                                                  \
+  case NN: {                                                                                      \
+    constexpr int NT = (NN >= 8) ? NN / 8 : 1;                                                    \
+    constexpr int L = 256 / NT;                                                                   \
+    dim3 grid((unsigned)(((int64_t)NN * NN + L - 1) / L), (unsigned)((nfields + 1) / 2));         \
+    hipLaunchKernelGGL((k_inv_z<T, NN>), grid, dim3(L * NT), 0, s, in, out, nfields, cin, zs,     \
+                       in_field, out_field, tw);                                                  \
+    return hipGetLastError();                                                                     \
+  }
+  switch (n) { BSP_FOR_SIZES(CASE) }
+#undef CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_fwd_z_f32(int n, const float* in, float2* out, const FwdZDesc& d, const float2* tw,
+                            hipStream_t s) {
+  return fwd_z_impl<float>(n, in, out, d, tw, s);
+}
+hipError_t launch_fwd_z_f64(int n, const double* in, double2* out, const FwdZDesc& d, const double2* tw,
+                            hipStream_t s) {
+  return fwd_z_impl<double>(n, in, out, d, tw, s);
+}
+
+hipError_t launch_c2c_f32(int n, int sign, const float2* in, float2* out, const PassDesc& p,
+                          const FilterDesc* f, const float2* tw, hipStream_t s) {
+#define CASE(NN) \
+  case NN: return c2c_launch<float, NN, 16>(sign, in, out, p, f, tw, s);
+  switch (n) { BSP_FOR_SIZES(CASE) }
+#undef CASE
+  return hipErrorInvalidValue;
+}
+hipError_t launch_c2c_f64(int n, int sign, const double2* in, double2* out, const PassDesc& p,
+                          const FilterDesc* f, const double2* tw, hipStream_t s) {
+#define CASE(NN) \
+  case NN: return c2c_launch<double, NN, 8>(sign, in, out, p, f, tw, s);
+  switch (n) { BSP_FOR_SIZES(CASE) }
+#undef CASE
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_inv_z_f32(int n, const float2* in, float* out, int nfields, int cin, int zs,
+                            int64_t in_field, int64_t out_field, const float2* tw, hipStream_t s) {
+  return inv_z_impl<float>(n, in, out, nfields, cin, zs, in_field, out_field, tw, s);
+}
+hipError_t launch_inv_z_f64(int n, const double2* in, double* out, int nfields, int cin, int zs,
+                            int64_t in_field, int64_t out_field, const double2* tw, hipStream_t s) {
+  return inv_z_impl<double>(n, in, out, nfields, cin, zs, in_field, out_field, tw, s);
+}
+
+}  // namespace bsp

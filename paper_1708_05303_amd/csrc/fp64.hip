@@ -1,0 +1,234 @@
+// FP64 finishing kernels: normalisation of the binned multipoles and their
+// shot noise, rounding of the triangle counts, assembly of the modal
+// numerators and of the Gram matrix from triple sums, the Cholesky
+// factorisation gamma = L L^T and the two triangular solves, and the sample
+// covariance over a batch of mocks.
+#include "bsp_internal.h"
+
+namespace bsp {
+
+// B^l_i = norm_b T^l_i / N_tri,i  (norm_b = V^2 / (N^9 N'^3)): the lattice form of
+// (1/V_B) sum_closed delta delta delta / V of the standard estimator.
+// Pbar_b = pnorm psum_b / N_b (pnorm = V / N^6); B0sub = B^0 - sum Pbar / nbar + 2 / nbar^2.
+__global__ void k_binned_finalize(const double* __restrict__ T, const int32_t* __restrict__ tri_tidx, int ntri,
+                                  int nl, const int64_t* __restrict__ counts, const double* __restrict__ psum,
+                                  const int64_t* __restrict__ nb_modes, int nbins,
+                                  const int32_t* __restrict__ tri_bins, double norm_b, double pnorm,
+                                  const double* __restrict__ nbar_p, double* __restrict__ B,
+                                  double* __restrict__ B0sub, double* __restrict__ Pbar) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (Pbar && i < nbins) Pbar[i] = nb_modes[i] > 0 ? pnorm * psum[i] / (double)nb_modes[i] : 0.0;
+  if (i >= ntri) return;
+  const double inv = 1.0 / (double)counts[i];
+  for (int l = 0; l < nl; ++l) B[(int64_t)l * ntri + i] = norm_b * T[tri_tidx[(int64_t)l * ntri + i]] * inv;
+  const double nbar = nbar_p ? nbar_p[0] : 0.0;
+  if (B0sub && nbar > 0.0) {
+    double ps = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      const int b = tri_bins[3 * i + a];
+      ps += nb_modes[b] > 0 ? pnorm * psum[b] / (double)nb_modes[b] : 0.0;
+    }
+    B0sub[i] = B[i] - ps / nbar + 2.0 / (nbar * nbar);
+  }
+}
+
+// counts_i = round(T_i / N'^3); bit 2 of err if any |T/N'^3 - round| >= 1e-3.
+__global__ void k_counts_finalize(const double* __restrict__ T, const int32_t* __restrict__ tidx, int ntri,
+                                  double inv_k, int64_t* __restrict__ counts, int32_t* __restrict__ err) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ntri) return;
+  const double c = T[tidx[i]] * inv_k;
+  const double r = rint(c);
+  counts[i] = (int64_t)r;
+  if (!(fabs(c - r) < 1e-3)) atomicOr(err, 4);
+}
+
+// bnum[l][m] = scale sum_{j<6, combo >= 0} T[combo[l][m][j]]  (minus shot noise for l = 0)
+__global__ void k_modal_assemble(const double* __restrict__ T, const int32_t* __restrict__ combo, int nmodes,
+                                 int nl, double scale, const double* __restrict__ sn,
+                                 const double* __restrict__ nbar_p, double* __restrict__ bnum) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nl * nmodes) return;
+  double s = 0.0;
+  for (int j = 0; j < 6; ++j) {
+    const int t = combo[6 * i + j];
+    if (t >= 0) s += T[t];
+  }
+  s *= scale;
+  const double nbar = nbar_p ? nbar_p[0] : 0.0;
+  if (i < nmodes && sn && nbar > 0.0) s -= 3.0 / nbar * sn[i] - 2.0 / (nbar * nbar) * sn[nmodes + i];
+  bnum[i] = s;
+}
+
+// gamma[n][m] = scale sum_{tau in S3} T[gidx[n][m][tau]]
+__global__ void k_gram_assemble(const double* __restrict__ T, const int32_t* __restrict__ gidx, int nmodes,
+                                double scale, double* __restrict__ gamma) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nmodes * nmodes) return;
+  double s = 0.0;
+  for (int j = 0; j < 6; ++j) s += T[gidx[6 * i + j]];
+  gamma[i] = s * scale;
+}
+
+// sn[0][m] = scale (T[a] + T[b] + T[c]) / 3, sn[1][m] = scale T[d]
+__global__ void k_sn_assemble(const double* __restrict__ T, const int32_t* __restrict__ sidx, int nmodes,
+                              double scale, double* __restrict__ sn) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nmodes) return;
+  sn[i] = scale * (T[sidx[4 * i]] + T[sidx[4 * i + 1]] + T[sidx[4 * i + 2]]) / 3.0;
+  sn[nmodes + i] = scale * T[sidx[4 * i + 3]];
+}
+
+// In-place Cholesky of a symmetric positive-definite n x n matrix (row major),
+// lower factor left in place, upper triangle zeroed. One workgroup.
+__global__ __launch_bounds__(256) void k_cholesky(double* __restrict__ A, int n, int32_t* __restrict__ err) {
+  __shared__ double diag;
+  __shared__ int fail;
+  if (threadIdx.x == 0) fail = 0;
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    if (threadIdx.x == 0) {
+      double d = A[(int64_t)j * n + j];
+      for (int k = 0; k < j; ++k) d -= A[(int64_t)j * n + k] * A[(int64_t)j * n + k];
+      if (!(d > 0.0)) {
+        fail = 1;
+        d = 1.0;
+      }
+      diag = sqrt(d);
+      A[(int64_t)j * n + j] = diag;
+    }
+    __syncthreads();
+    for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) {
+      double s = A[(int64_t)i * n + j];
+      for (int k = 0; k < j; ++k) s -= A[(int64_t)i * n + k] * A[(int64_t)j * n + k];
+      A[(int64_t)i * n + j] = s / diag;
+    }
+    __syncthreads();
+  }
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x)
+    if (idx % n > idx / n) A[idx] = 0.0;
+  if (threadIdx.x == 0 && fail) atomicOr(err, 8);
+}
+
+// alpha = L^-1 b, beta = L^-T alpha for nrhs right-hand sides (one workgroup each).
+__global__ __launch_bounds__(256) void k_tri_solve(const double* __restrict__ L, int n, const double* __restrict__ b,
+                                                   double* __restrict__ alpha, double* __restrict__ beta) {
+  const int r = blockIdx.x;
+  const double* bb = b + (int64_t)r * n;
+  double* al = alpha + (int64_t)r * n;
+  double* be = beta + (int64_t)r * n;
+  __shared__ double red[256];
+  for (int i = 0; i < n; ++i) {
+    double s = 0.0;
+    for (int k = threadIdx.x; k < i; k += blockDim.x) s += L[(int64_t)i * n + k] * al[k];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+      if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) al[i] = (bb[i] - red[0]) / L[(int64_t)i * n + i];
+    __syncthreads();
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double s = 0.0;
+    for (int k = i + 1 + threadIdx.x; k < n; k += blockDim.x) s += L[(int64_t)k * n + i] * be[k];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+      if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) be[i] = (al[i] - red[0]) / L[(int64_t)i * n + i];
+    __syncthreads();
+  }
+}
+
+// cov[i][j] = sum_m (x_mi - mean_i)(x_mj - mean_j) / (M - 1), x row major [M][D].
+__global__ void k_covariance(const double* __restrict__ x, int m, int d, double* __restrict__ cov) {
+  const int i = blockIdx.y * blockDim.y + threadIdx.y;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d || j >= d) return;
+  double mi = 0.0, mj = 0.0;
+  for (int k = 0; k < m; ++k) {
+    mi += x[(int64_t)k * d + i];
+    mj += x[(int64_t)k * d + j];
+  }
+  mi /= m;
+  mj /= m;
+  double s = 0.0;
+  for (int k = 0; k < m; ++k) s += (x[(int64_t)k * d + i] - mi) * (x[(int64_t)k * d + j] - mj);
+  cov[(int64_t)i * d + j] = s / (double)(m - 1);
+}
+
+// nbar = wsum * scale (scale = 1/V), so no host round trip is needed.
+__global__ void k_scale_scalar(const double* __restrict__ x, double scale, double* __restrict__ y) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) y[0] = x[0] * scale;
+}
+
+static unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+hipError_t launch_binned_finalize(const double* T, const int32_t* tri_tidx, int ntri, int nl, const int64_t* counts,
+                                  const double* psum, const int64_t* nb_modes, int nbins, const int32_t* tri_bins,
+                                  double norm_b, double pnorm, const double* nbar, double* B, double* B0sub,
+                                  double* Pbar, hipStream_t s) {
+  const int n = ntri > nbins ? ntri : nbins;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_binned_finalize, dim3(nblk(n, 256)), dim3(256), 0, s, T, tri_tidx, ntri, nl, counts, psum,
+                     nb_modes, nbins, tri_bins, norm_b, pnorm, nbar, B, B0sub, Pbar);
+  return hipGetLastError();
+}
+
+hipError_t launch_counts_finalize(const double* T, const int32_t* tidx, int ntri, double inv_k, int64_t* counts,
+                                  int32_t* err, hipStream_t s) {
+  if (ntri <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_counts_finalize, dim3(nblk(ntri, 256)), dim3(256), 0, s, T, tidx, ntri, inv_k, counts, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_modal_assemble(const double* T, const int32_t* combo, int nmodes, int nl, double scale,
+                                 const double* sn, const double* nbar, double* bnum, hipStream_t s) {
+  if (nmodes <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_modal_assemble, dim3(nblk((int64_t)nl * nmodes, 256)), dim3(256), 0, s, T, combo, nmodes,
+                     nl, scale, sn, nbar, bnum);
+  return hipGetLastError();
+}
+
+hipError_t launch_gram_assemble(const double* T, const int32_t* gidx, int nmodes, double scale, double* gamma,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_gram_assemble, dim3(nblk((int64_t)nmodes * nmodes, 256)), dim3(256), 0, s, T, gidx, nmodes,
+                     scale, gamma);
+  return hipGetLastError();
+}
+
+hipError_t launch_sn_assemble(const double* T, const int32_t* sidx, int nmodes, double scale, double* sn,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_sn_assemble, dim3(nblk(nmodes, 256)), dim3(256), 0, s, T, sidx, nmodes, scale, sn);
+  return hipGetLastError();
+}
+
+hipError_t launch_cholesky(double* A, int n, int32_t* err, hipStream_t s) {
+  hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(256), 0, s, A, n, err);
+  return hipGetLastError();
+}
+
+hipError_t launch_tri_solve(const double* L, int n, int nrhs, const double* b, double* alpha, double* beta,
+                            hipStream_t s) {
+  if (nrhs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tri_solve, dim3(nrhs), dim3(256), 0, s, L, n, b, alpha, beta);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_scalar(const double* x, double scale, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_scalar, dim3(1), dim3(64), 0, s, x, scale, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_covariance(const double* x, int m, int d, double* cov, hipStream_t s) {
+  dim3 blk(16, 16);
+  dim3 grid(nblk(d, 16), nblk(d, 16));
+  hipLaunchKernelGGL(k_covariance, grid, blk, 0, s, x, m, d, cov);
+  return hipGetLastError();
+}
+
+}  // namespace bsp

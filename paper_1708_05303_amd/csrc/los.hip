@@ -1,0 +1,164 @@
+// Line-of-sight Legendre moments delta^(l)(k), l = 0, 2, 4, from the transforms
+// of the x-hat-weighted fields, and the shell sums of |delta^(0)|^2.
+//
+// The LOS moment field of the paper's power-spectrum section is
+//   delta^(l)(k) = (2l+1) int d^3x e^{-ik.x} delta(x) L_l(k_hat . x_hat);
+// with mu = k_hat . x_hat, L_2 = (3 mu^2 - 1)/2 and L_4 = (35 mu^4 - 30 mu^2 + 3)/8,
+// so with A2 = FT[delta mu^2] = sum_{i<=j} m_ij k_i k_j F_ij and
+// A4 = FT[delta mu^4] = sum_{i<=j<=k<=l} m k_i k_j k_k k_l F_ijkl (m the
+// multinomial multiplicities):
+//   delta^0 = F, delta^2 = 5 (3 A2 - F) / 2, delta^4 = 9 (35 A4 - 30 A2 + 3 F) / 8.
+// The mass-assignment window is divided out (CIC: prod sinc^2(pi n_a / N)) and
+// two interlaced grids are averaged after the half-cell phase
+// exp(i pi (nx + ny + nz) / N) is applied to the shifted one.
+#include "bsp_internal.h"
+
+namespace bsp {
+
+__constant__ int8_t c_exp[22][3] = {
+    {0, 0, 0},
+    {2, 0, 0}, {1, 1, 0}, {1, 0, 1}, {0, 2, 0}, {0, 1, 1}, {0, 0, 2},
+    {4, 0, 0}, {3, 1, 0}, {3, 0, 1}, {2, 2, 0}, {2, 1, 1}, {2, 0, 2}, {1, 3, 0},
+    {1, 2, 1}, {1, 1, 2}, {1, 0, 3}, {0, 4, 0}, {0, 3, 1}, {0, 2, 2}, {0, 1, 3},
+    {0, 0, 4}};
+__constant__ double c_mult[22] = {1, 1, 2, 2, 1, 2, 1, 1, 4, 4, 6, 12, 6, 4, 12, 12, 4, 1, 4, 6, 4, 1};
+
+__device__ __forceinline__ double dpow(double x, int e) {
+  double r = 1.0;
+  for (int i = 0; i < e; ++i) r *= x;
+  return r;
+}
+
+__device__ __forceinline__ double sinc_pi(int n, int N) {
+  if (n == 0) return 1.0;
+  const double a = M_PI * (double)n / (double)N;
+  return sin(a) / a;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_los_combine(const cplx_t<T>* __restrict__ X, cplx_t<T>* __restrict__ dl,
+                                                     LosDesc d) {
+  using V = cplx_t<T>;
+  const int w = 2 * d.c + 1;
+  const int64_t cube = (int64_t)w * w * d.cz;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= cube) return;
+  const int nl = d.lmax / 2 + 1;
+  const int kz = (int)(idx % d.cz);
+  const int64_t rest = idx / d.cz;
+  const int iy = (int)(rest % w), ix = (int)(rest / w);
+  const int nx = ix - d.c, ny = iy - d.c, nz = kz;
+  const int n2 = nx * nx + ny * ny + nz * nz;
+  if (kz > d.c || n2 == 0 || n2 > d.n2max) {
+    for (int l = 0; l < nl; ++l) dl[l * cube + idx] = V{(T)0, (T)0};
+    return;
+  }
+  double comp = 1.0;
+  if (d.compensate) {
+    double wv = sinc_pi(nx, d.n) * sinc_pi(ny, d.n) * sinc_pi(nz, d.n);
+    if (d.window == 1) wv *= wv;
+    comp = 1.0 / wv;
+  }
+  double2 fac[2];
+  fac[0] = double2{comp / d.ngrid, 0.0};
+  {
+    const double ph = M_PI * (double)(nx + ny + nz) / (double)d.n;
+    fac[1] = double2{comp / d.ngrid * cos(ph), comp / d.ngrid * sin(ph)};
+  }
+  auto F = [&](int t) -> double2 {
+    double2 s{0.0, 0.0};
+    for (int g = 0; g < d.ngrid; ++g) {
+      const V x = X[((int64_t)g * d.nlos + t) * cube + idx];
+      s.x += fac[g].x * (double)x.x - fac[g].y * (double)x.y;
+      s.y += fac[g].x * (double)x.y + fac[g].y * (double)x.x;
+    }
+    return s;
+  };
+  const double inv = 1.0 / sqrt((double)n2);
+  const double kh[3] = {nx * inv, ny * inv, nz * inv};
+  const double2 F0 = F(0);
+  dl[idx] = V{(T)F0.x, (T)F0.y};
+  if (d.lmax < 2) return;
+  double2 A2{0.0, 0.0};
+  if (d.plane) {
+    const double m = kh[2] * kh[2];
+    A2 = double2{m * F0.x, m * F0.y};
+  } else {
+    for (int t = 1; t <= 6; ++t) {
+      const double m = c_mult[t] * dpow(kh[0], c_exp[t][0]) * dpow(kh[1], c_exp[t][1]) * dpow(kh[2], c_exp[t][2]);
+      const double2 f = F(t);
+      A2.x += m * f.x;
+      A2.y += m * f.y;
+    }
+  }
+  dl[cube + idx] = V{(T)(2.5 * (3.0 * A2.x - F0.x)), (T)(2.5 * (3.0 * A2.y - F0.y))};
+  if (d.lmax < 4) return;
+  double2 A4{0.0, 0.0};
+  if (d.plane) {
+    const double m = kh[2] * kh[2] * kh[2] * kh[2];
+    A4 = double2{m * F0.x, m * F0.y};
+  } else {
+    for (int t = 7; t <= 21; ++t) {
+      const double m = c_mult[t] * dpow(kh[0], c_exp[t][0]) * dpow(kh[1], c_exp[t][1]) * dpow(kh[2], c_exp[t][2]);
+      const double2 f = F(t);
+      A4.x += m * f.x;
+      A4.y += m * f.y;
+    }
+  }
+  dl[2 * cube + idx] = V{(T)(1.125 * (35.0 * A4.x - 30.0 * A2.x + 3.0 * F0.x)),
+                         (T)(1.125 * (35.0 * A4.y - 30.0 * A2.y + 3.0 * F0.y))};
+}
+
+// psum[b] += sum over the compact half cube of mult * |delta0|^2, mult = 2 for kz > 0
+// (the conjugate partner at -n is not stored).
+__global__ __launch_bounds__(256) void k_shell_power(const float2* __restrict__ d0, int c, int cz,
+                                                     const int32_t* __restrict__ bin_of_n2, int n2max,
+                                                     int nbins, double* __restrict__ psum) {
+  extern __shared__ double hist[];
+  for (int b = threadIdx.x; b < nbins; b += blockDim.x) hist[b] = 0.0;
+  __syncthreads();
+  const int w = 2 * c + 1;
+  const int64_t cube = (int64_t)w * w * cz;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < cube;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int kz = (int)(idx % cz);
+    if (kz > c) continue;
+    const int64_t rest = idx / cz;
+    const int ny = (int)(rest % w) - c, nx = (int)(rest / w) - c;
+    const int n2 = nx * nx + ny * ny + kz * kz;
+    if (n2 > n2max) continue;
+    const int b = bin_of_n2[n2];
+    if (b < 0) continue;
+    const float2 v = d0[idx];
+    const double p = (double)v.x * v.x + (double)v.y * v.y;
+    atomicAdd(&hist[b], kz == 0 ? p : 2.0 * p);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < nbins; b += blockDim.x)
+    if (hist[b] != 0.0) unsafeAtomicAdd(&psum[b], hist[b]);
+}
+
+hipError_t launch_los_combine(const float2* X, float2* delta_l, const LosDesc& d, hipStream_t s) {
+  const int64_t cube = (int64_t)(2 * d.c + 1) * (2 * d.c + 1) * d.cz;
+  hipLaunchKernelGGL((k_los_combine<float>), dim3((unsigned)((cube + 255) / 256)), dim3(256), 0, s, X, delta_l, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_los_combine_f64(const double2* X, double2* delta_l, const LosDesc& d, hipStream_t s) {
+  const int64_t cube = (int64_t)(2 * d.c + 1) * (2 * d.c + 1) * d.cz;
+  hipLaunchKernelGGL((k_los_combine<double>), dim3((unsigned)((cube + 255) / 256)), dim3(256), 0, s, X, delta_l,
+                     d);
+  return hipGetLastError();
+}
+
+hipError_t launch_shell_power(const float2* delta0, int c, int cz, const int32_t* bin_of_n2, int n2max,
+                              int nbins, double* psum, hipStream_t s) {
+  const int64_t cube = (int64_t)(2 * c + 1) * (2 * c + 1) * cz;
+  int64_t blocks = (cube + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_shell_power, dim3((unsigned)blocks), dim3(256), nbins * sizeof(double), s, delta0, c, cz,
+                     bin_of_n2, n2max, nbins, psum);
+  return hipGetLastError();
+}
+
+}  // namespace bsp

@@ -1,0 +1,332 @@
+// Triple reduction T[p, s] = sum_x F_a(p)(x) F_b(p)(x) F_s(x) written as a GEMM
+// over the spatial points x (the K dimension): rows are pair products
+// (F_a F_b)(x), columns are third fields F_s(x).
+//
+// This is the "three dimensional integral over products of FFTs" of the
+// standard estimator (its FFT form and the multipole form with D^(l)_k) and the
+// integral of M M M of the modal estimator, both in Sec. 3 of the paper.
+//
+// Structure: a workgroup (4 waves, one per SIMD) owns a chunk of K points and a group of
+// row tiles; each wave owns up to MAXR row tiles of 16 pairs and every needed
+// 16-wide column tile of thirds, with the accumulators resident in registers.
+// Points stream through LDS in stages of 64 (double buffered, one
+// barrier per stage). Tiles whose outputs no triangle needs are skipped (the
+// output is block sparse: a pair (b2, b3) only meets thirds b1 >= b2 that close
+// a triangle).
+//
+// Precision modes (rows x cols per MFMA, points per MFMA):
+//   0 FP32 : v_mfma 16x16x4 f32, exact FP32 products
+//   1 BF16X3: a = ah + al, b = bh + bl (bf16 round-to-nearest-even splits of the
+//            FP32 values), T += ah bh + ah bl + al bh on 16x16x32 bf16 MFMA
+//   2 FP16X3: the same with fp16 splits of fields scaled by powers of two
+//   3 FP64 : v_mfma 16x16x4 f64 (geometry precompute)
+// Each workgroup writes its chunk's partial tiles; a second kernel sums the
+// chunks in FP64.
+#include "bsp_internal.h"
+
+namespace bsp {
+
+constexpr int WAVES = 4;
+constexpr int NTHR = WAVES * 64;
+constexpr int KS = 64;  // points per LDS stage
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+template <int PREC> struct RT;
+template <> struct RT<0> { using T = float; using acc = f32x4; static constexpr int KK = 8; };
+template <> struct RT<1> { using T = float; using acc = f32x4; static constexpr int KK = 8; };
+template <> struct RT<2> { using T = float; using acc = f32x4; static constexpr int KK = 8; };
+template <> struct RT<3> { using T = double; using acc = f64x4; static constexpr int KK = 2; };
+
+template <int PREC, int MAXR, int MAXC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_reduce(const typename RT<PREC>::T* __restrict__ fields, ReduceDesc d,
+                                                typename RT<PREC>::T* __restrict__ partials) {
+  using T = typename RT<PREC>::T;
+  using ACC = typename RT<PREC>::acc;
+  constexpr int KK = RT<PREC>::KK;      // consecutive points per lane per k-step
+  constexpr int KSTEP = 4 * KK;         // points per k-step
+  constexpr int LDW = KS + (16 / (int)sizeof(T));  // padded LDS row
+  constexpr int EPV = 16 / (int)sizeof(T);         // elements per 16-byte vector
+  using VEC = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+  constexpr int MAXV = (128 * KS / EPV + NTHR - 1) / NTHR;  // vectors per thread per stage (<= 128 fields)
+
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* lds = reinterpret_cast<T*>(smem_raw);
+  const int nrow_lds = d.nfields + 1;  // last row stays zero
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int q = lane >> 4, r16 = lane & 15;
+  const int chunk = blockIdx.x, group = blockIdx.y;
+  const int64_t k0 = (int64_t)chunk * d.kchunk;
+  int64_t k1 = k0 + d.kchunk;
+  if (k1 > d.K) k1 = d.K;
+  const int nst = (int)((k1 - k0 + KS - 1) / KS);
+
+  // wave-uniform row tiles and their column masks
+  int rows[MAXR], masks[MAXR];
+#pragma unroll
+  for (int r = 0; r < MAXR; ++r) {
+    rows[r] = d.wave_rows[(group * WAVES + wave) * MAXR + r];
+    masks[r] = rows[r] >= 0 ? d.row_mask[rows[r]] : 0;
+  }
+  int pa[MAXR], pb[MAXR];
+  float sab[MAXR];
+#pragma unroll
+  for (int r = 0; r < MAXR; ++r) {
+    const int pr = rows[r] * 16 + r16;
+    const int a = rows[r] >= 0 ? d.pair_a[pr] : -1;
+    const int b = rows[r] >= 0 ? d.pair_b[pr] : -1;
+    pa[r] = a >= 0 ? a : d.nfields;
+    pb[r] = b >= 0 ? b : d.nfields;
+    sab[r] = (d.scale && a >= 0 && b >= 0) ? d.scale[a] * d.scale[b] : 1.0f;
+  }
+  int th[MAXC];
+  float ss[MAXC];
+#pragma unroll
+  for (int c = 0; c < MAXC; ++c) {
+    const int s = c < d.nct ? d.third[c * 16 + r16] : -1;
+    th[c] = s >= 0 ? s : d.nfields;
+    ss[c] = (d.scale && s >= 0) ? d.scale[s] : 1.0f;
+  }
+  int colmask_any = 0;
+#pragma unroll
+  for (int r = 0; r < MAXR; ++r) colmask_any |= masks[r];
+
+  ACC acc[MAXR][MAXC];
+#pragma unroll
+  for (int r = 0; r < MAXR; ++r)
+#pragma unroll
+    for (int c = 0; c < MAXC; ++c)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc[r][c][i] = (T)0;
+
+  // zero rows of both buffers
+  for (int i = threadIdx.x; i < LDW; i += blockDim.x) {
+    lds[(int64_t)d.nfields * LDW + i] = (T)0;
+    lds[(int64_t)(nrow_lds + d.nfields) * LDW + i] = (T)0;
+  }
+
+  const int nvec = d.nfields * (KS / EPV);
+  VEC stage_regs[MAXV];
+  auto gload = [&](int st) {
+    const int64_t kb = k0 + (int64_t)st * KS;
+    // 16-byte vector loads only when every field row stays 16-byte aligned
+    const bool full = (kb + KS <= k1) && (d.field_stride % EPV == 0);
+#pragma unroll
+    for (int v = 0; v < MAXV; ++v) {
+      const int vi = threadIdx.x + v * NTHR;
+      VEC val{};
+      if (vi < nvec) {
+        const int f = vi / (KS / EPV), e = (vi % (KS / EPV)) * EPV;
+        const T* src = fields + (int64_t)f * d.field_stride + kb + e;
+        if (full) {
+          val = *reinterpret_cast<const VEC*>(src);
+        } else {
+          T tmp[EPV];
+#pragma unroll
+          for (int j = 0; j < EPV; ++j) tmp[j] = (kb + e + j < k1) ? src[j] : (T)0;
+          val = *reinterpret_cast<VEC*>(tmp);
+        }
+      }
+      stage_regs[v] = val;
+    }
+  };
+  auto sstore = [&](int buf) {
+    T* base = lds + (int64_t)buf * nrow_lds * LDW;
+#pragma unroll
+    for (int v = 0; v < MAXV; ++v) {
+      const int vi = threadIdx.x + v * NTHR;
+      if (vi < nvec) {
+        const int f = vi / (KS / EPV), e = (vi % (KS / EPV)) * EPV;
+        *reinterpret_cast<VEC*>(base + (int64_t)f * LDW + e) = stage_regs[v];
+      }
+    }
+  };
+
+  if (nst > 0) {
+    gload(0);
+    sstore(0);
+  }
+  __syncthreads();
+  for (int st = 0; st < nst; ++st) {
+    const int cur = st & 1;
+    if (st + 1 < nst) gload(st + 1);
+    const T* base = lds + (int64_t)cur * nrow_lds * LDW;
+    if (colmask_any) {
+#pragma unroll 1
+      for (int ks = 0; ks < KS / KSTEP; ++ks) {
+        const int off = ks * KSTEP + q * KK;
+        // pair-product fragments of every row tile of this wave
+        T av[MAXR][KK];
+#pragma unroll
+        for (int r = 0; r < MAXR; ++r) {
+#pragma unroll
+          for (int j = 0; j < KK; ++j) av[r][j] = base[pa[r] * LDW + off + j] * base[pb[r] * LDW + off + j];
+          if constexpr (PREC == 2) {
+#pragma unroll
+            for (int j = 0; j < KK; ++j) av[r][j] *= sab[r];
+          }
+        }
+        if constexpr (PREC == 0 || PREC == 3) {
+#pragma unroll
+          for (int c = 0; c < MAXC; ++c) {
+            if (!((colmask_any >> c) & 1)) continue;
+            T bv[KK];
+#pragma unroll
+            for (int j = 0; j < KK; ++j) bv[j] = base[th[c] * LDW + off + j];
+#pragma unroll
+            for (int r = 0; r < MAXR; ++r) {
+              if (!((masks[r] >> c) & 1)) continue;
+#pragma unroll
+              for (int j = 0; j < KK; ++j) {
+                if constexpr (PREC == 0)
+                  acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[r][j], bv[j], acc[r][c], 0, 0, 0);
+                else
+                  acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[r][j], bv[j], acc[r][c], 0, 0, 0);
+              }
+            }
+          }
+        } else {
+          using H = typename std::conditional<PREC == 1, __bf16, _Float16>::type;
+          using H8 = typename std::conditional<PREC == 1, bf16x8, f16x8>::type;
+          H8 ah[MAXR], al[MAXR];
+#pragma unroll
+          for (int r = 0; r < MAXR; ++r)
+#pragma unroll
+            for (int j = 0; j < KK; ++j) {
+              const H h = (H)av[r][j];
+              ah[r][j] = h;
+              al[r][j] = (H)(av[r][j] - (float)h);
+            }
+#pragma unroll
+          for (int c = 0; c < MAXC; ++c) {
+            if (!((colmask_any >> c) & 1)) continue;
+            H8 bh, bl;
+#pragma unroll
+            for (int j = 0; j < KK; ++j) {
+              float x = base[th[c] * LDW + off + j];
+              if constexpr (PREC == 2) x *= ss[c];
+              const H h = (H)x;
+              bh[j] = h;
+              bl[j] = (H)(x - (float)h);
+            }
+#pragma unroll
+            for (int r = 0; r < MAXR; ++r) {
+              if (!((masks[r] >> c) & 1)) continue;
+              if constexpr (PREC == 1) {
+                acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[r], bh, acc[r][c], 0, 0, 0);
+                acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[r], bl, acc[r][c], 0, 0, 0);
+                acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[r], bh, acc[r][c], 0, 0, 0);
+              } else {
+                acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[r], bh, acc[r][c], 0, 0, 0);
+                acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[r], bl, acc[r][c], 0, 0, 0);
+                acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[r], bh, acc[r][c], 0, 0, 0);
+              }
+            }
+          }
+        }
+      }
+    }
+    if (st + 1 < nst) sstore(cur ^ 1);
+    __syncthreads();
+  }
+
+  // partial tiles of this chunk: lane holds rows 4q + i, column r16
+#pragma unroll
+  for (int r = 0; r < MAXR; ++r) {
+    if (masks[r] == 0) continue;
+#pragma unroll
+    for (int c = 0; c < MAXC; ++c) {
+      if (!((masks[r] >> c) & 1)) continue;
+      const int tile = d.tile_index[rows[r] * 8 + c];
+      T* out = partials + ((int64_t)chunk * d.ntiles + tile) * 256;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) out[(4 * q + i) * 16 + r16] = acc[r][c][i];
+    }
+  }
+}
+
+// Sum chunk partials in FP64 and scatter to T[pair][third] (T zeroed before).
+template <typename PT>
+__global__ __launch_bounds__(256) void k_combine(const PT* __restrict__ partials, int nchunks, int ntiles,
+                                                 int chunks_per_block, const int32_t* __restrict__ tile_rc,
+                                                 int npairs, int nthirds, const int32_t* __restrict__ pair_a,
+                                                 const int32_t* __restrict__ pair_b,
+                                                 const int32_t* __restrict__ third, const float* __restrict__ scale,
+                                                 double tscale, double* __restrict__ T) {
+  const int tile = blockIdx.x;
+  const int e = threadIdx.x;
+  const int c0 = blockIdx.y * chunks_per_block;
+  int c1 = c0 + chunks_per_block;
+  if (c1 > nchunks) c1 = nchunks;
+  double s = 0.0;
+  for (int c = c0; c < c1; ++c) s += (double)partials[((int64_t)c * ntiles + tile) * 256 + e];
+  const int pr = tile_rc[2 * tile] * 16 + e / 16;
+  const int th = tile_rc[2 * tile + 1] * 16 + e % 16;
+  if (pr < npairs && th < nthirds) {
+    double f = tscale;
+    if (scale) f /= (double)scale[pair_a[pr]] * (double)scale[pair_b[pr]] * (double)scale[third[th]];
+    unsafeAtomicAdd(&T[(int64_t)pr * nthirds + th], s * f);
+  }
+}
+
+int reduce_waves_per_group() { return WAVES; }
+// rows per wave for a given number of column tiles (register budget of one wave per SIMD)
+int reduce_max_rows_per_wave(int prec, int nct) {
+  if (prec == 3) return 4;
+  return nct > 4 ? 5 : 8;
+}
+
+template <int PREC, int MAXR, int MAXR8>
+static hipError_t reduce_dispatch(const void* fields, const ReduceDesc& d, void* partials, hipStream_t s) {
+  using T = typename RT<PREC>::T;
+  const size_t lds = (size_t)2 * (d.nfields + 1) * (KS + 16 / sizeof(T)) * sizeof(T);
+  dim3 grid((unsigned)d.nchunks, (unsigned)d.ngroups);
+  const T* f = reinterpret_cast<const T*>(fields);
+  T* p = reinterpret_cast<T*>(partials);
+  if (d.nct <= 1)
+    hipLaunchKernelGGL((k_reduce<PREC, MAXR, 1>), grid, dim3(NTHR), lds, s, f, d, p);
+  else if (d.nct <= 2)
+    hipLaunchKernelGGL((k_reduce<PREC, MAXR, 2>), grid, dim3(NTHR), lds, s, f, d, p);
+  else if (d.nct <= 4)
+    hipLaunchKernelGGL((k_reduce<PREC, MAXR, 4>), grid, dim3(NTHR), lds, s, f, d, p);
+  else if (d.nct <= 8)
+    hipLaunchKernelGGL((k_reduce<PREC, MAXR8, 8>), grid, dim3(NTHR), lds, s, f, d, p);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(int prec, const float* fields, const ReduceDesc& d, float* partials, hipStream_t s) {
+  if (d.nfields > 128) return hipErrorInvalidValue;
+  switch (prec) {
+    case 0: return reduce_dispatch<0, 8, 5>(fields, d, partials, s);
+    case 1: return reduce_dispatch<1, 8, 5>(fields, d, partials, s);
+    case 2: return reduce_dispatch<2, 8, 5>(fields, d, partials, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_reduce_f64(const double* fields, const ReduceDesc& d, double* partials, hipStream_t s) {
+  if (d.nfields > 128) return hipErrorInvalidValue;
+  return reduce_dispatch<3, 4, 4>(fields, d, partials, s);
+}
+
+hipError_t launch_combine_partials(const void* partials, int is_f64, const ReduceDesc& d, int npairs, int nthirds,
+                                   double* T, double tscale, hipStream_t s) {
+  const int cpb = 64;
+  dim3 grid((unsigned)d.ntiles, (unsigned)((d.nchunks + cpb - 1) / cpb));
+  if (is_f64)
+    hipLaunchKernelGGL((k_combine<double>), grid, dim3(256), 0, s, reinterpret_cast<const double*>(partials),
+                       d.nchunks, d.ntiles, cpb, d.tile_rc, npairs, nthirds, d.pair_a, d.pair_b, d.third, d.scale,
+                       tscale, T);
+  else
+    hipLaunchKernelGGL((k_combine<float>), grid, dim3(256), 0, s, reinterpret_cast<const float*>(partials),
+                       d.nchunks, d.ntiles, cpb, d.tile_rc, npairs, nthirds, d.pair_a, d.pair_b, d.third, d.scale,
+                       tscale, T);
+  return hipGetLastError();
+}
+
+}  // namespace bsp

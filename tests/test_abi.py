@@ -1,0 +1,68 @@
+"""The C-ABI library loads, exports every symbol include/bsp.h declares, and
+rejects invalid geometries before touching a GPU (no compute calls here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1708_05303_amd as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "bsp.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(bsp_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_header_declares_the_binding_names():
+    assert declared_symbols() == sorted(B.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = B.lib()
+    for name in declared_symbols():
+        assert hasattr(lib, name), name
+        assert isinstance(getattr(lib, name), ctypes._CFuncPtr)
+
+
+def _geom(**kw):
+    g = B.Geom()
+    d = dict(n=64, n_reduce=0, box=1000.0, window=1, compensate=1, interlace=0, los=0, lmax=0, nbins=10,
+             k0=2.0, dk=2.0)
+    d.update(kw)
+    for k, v in d.items():
+        setattr(g, k, v)
+    return g
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(n=100), 2),                    # no transform kernel for 100
+    (dict(lmax=3), 1),                   # lmax must be 0, 2, 4
+    (dict(nbins=12), 3),                 # 3 c = 3 * 24 >= 64
+    (dict(k0=2.25), 1),                  # 2 k0 must be an integer
+    (dict(nbins=0), 1),
+    (dict(box=-1.0), 1),
+    (dict(n=64, n_reduce=48), 2),        # 48 is not a supported size
+    (dict(n=128, n_reduce=32, nbins=6), 3),  # c = 13: 3c >= 32
+])
+def test_plan_create_rejects_invalid_geometry(kw, status):
+    with pytest.raises(B.BspError) as e:
+        B.bsp_plan_create(_geom(**kw))
+    assert e.value.status == status
+    assert B.lib().bsp_last_error(None)
+
+
+def test_modal_basis_validation():
+    import numpy as np
+    modes = np.array([[0, 0, 0], [0, 2, 1]], np.int32)  # second is not sorted
+    pf = np.ones(2000)
+    b = B.ModalBasis()
+    b.P, b.nmodes, b.pfid_len = 3, 2, pf.size
+    b.modes = modes.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    b.pfid = pf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    with pytest.raises(B.BspError) as e:
+        B.bsp_plan_create(_geom(), b)
+    assert e.value.status == 1

@@ -1,0 +1,309 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle, small sizes.
+
+Every comparison runs the GPU on seeded synthetic inputs and the oracle on the
+same inputs; tolerances follow the arithmetic: FP32 path 1e-5 normwise,
+split-precision products 1e-3 on B_l and 1e-4 on beta_n, integers exact.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from synth import catalog as C
+from tests.gpu_helpers import compact_to_half, gpu_cube_to_numpy, half_to_compact, pfid_table, rel_norm
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1708_05303_amd as B  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def dev(a, dtype=torch.float32):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device=DEV, dtype=dtype)
+
+
+# ---------------------------------------------------------------- transforms
+
+@pytest.mark.parametrize("n", [16, 32, 64, 96, 128, 192])
+def test_fft_r2c_c2r_against_oracle(n):
+    say("fft", n)
+    plan = B.Plan(n=n, box=100.0, nbins=1, k0=1.0, dk=1.0)
+    x = rng(n).standard_normal((2, n, n, n))
+    xi = dev(x)
+    out = torch.zeros((2, n, n, n // 2 + 1, 2), dtype=torch.float32, device=DEV)
+    B.bsp_fft_r2c(plan.handle, n, 2, xi, out)
+    back = torch.zeros((2, n, n, n), dtype=torch.float32, device=DEV)
+    B.bsp_fft_c2r(plan.handle, n, 2, out, back)
+    plan.sync()
+    o = out.cpu().numpy()
+    got = o[..., 0] + 1j * o[..., 1]
+    for b in range(2):
+        ref = O.forward(x[b])
+        assert rel_norm(np.stack([got[b].real, got[b].imag]), np.stack([ref.real, ref.imag])) < 2e-6
+    assert rel_norm(back.cpu().numpy(), x * n ** 3) < 2e-6
+
+
+# ---------------------------------------------------------------- assignment
+
+@pytest.mark.parametrize("window,interlace", [(1, 0), (1, 1), (0, 1)])
+def test_grid_assign_against_oracle(window, interlace):
+    say("assign", window, interlace)
+    n = 32
+    r = rng(7)
+    u = [C.quantise_grid_units(r.uniform(0, n, 20000), n) for _ in range(3)]
+    w = r.uniform(0.5, 1.5, 20000).astype(np.float32)
+    plan = B.Plan(n=n, box=100.0, nbins=1, k0=1.0, dk=1.0, window=window, interlace=interlace)
+    grids = torch.zeros((1 + interlace, n, n, n), dtype=torch.float32, device=DEV)
+    wsum = torch.zeros(1, dtype=torch.float64, device=DEV)
+    B.bsp_grid_assign(plan.handle, dev(u[0]), dev(u[1]), dev(u[2]), dev(w), u[0].size, grids, wsum)
+    plan.sync()
+    g = grids.cpu().numpy()
+    for s in range(1 + interlace):
+        ref = O.assign(*u, n, w.astype(np.float64), window, 0.5 * s)
+        assert np.max(np.abs(g[s] - ref)) < 2e-6 * np.max(ref) + 1e-6
+    assert abs(wsum.item() - float(w.astype(np.float64).sum())) < 1e-6 * w.sum()
+
+
+def test_grid_assign_rejects_out_of_range():
+    say("assign-out-of-range")
+    n = 16
+    plan = B.Plan(n=n, box=100.0, nbins=1, k0=1.0, dk=1.0)
+    ux = np.array([1.0, 16.0, 3.0], np.float32)  # 16.0 is outside [0, 16)
+    grids = torch.zeros((1, n, n, n), dtype=torch.float32, device=DEV)
+    wsum = torch.zeros(1, dtype=torch.float64, device=DEV)
+    B.bsp_grid_assign(plan.handle, dev(ux), dev(ux), dev(ux), None, 3, grids, wsum)
+    with pytest.raises(B.BspError) as e:
+        plan.sync()
+    assert e.value.status == 6
+    assert abs(grids.sum().item() - 2.0) < 1e-6
+
+
+# ---------------------------------------------------------------- LOS moments
+
+def _catalogue(n, npart, seed, clustered=True):
+    if clustered:
+        wl = C.Workload("t", n, n, 200.0, npart, -1.5, 0.5, 0.5, 1, 1, 0, 4, 4, 2.0, 3, 10, seed)
+        return C.lognormal_catalogue(wl, observer=np.array([-300.0, -200.0, -250.0]))
+    return C.uniform_catalogue(n, npart, seed)
+
+
+@pytest.mark.parametrize("los,interlace,lmax", [(0, 0, 4), (1, 0, 4), (1, 1, 4), (1, 1, 2), (0, 1, 0)])
+def test_los_moments_against_oracle(los, interlace, lmax):
+    say("los", los, interlace, lmax)
+    n = 32
+    obs = np.array([-300.0, -200.0, -250.0])
+    u = _catalogue(n, 30000, 11)
+    plan = B.Plan(n=n, box=200.0, nbins=4, k0=2.0, dk=2.0, lmax=lmax, interlace=interlace, los=los,
+                  observer=obs)
+    info = plan.info
+    grids = torch.zeros((1 + interlace, n, n, n), dtype=torch.float32, device=DEV)
+    wsum = torch.zeros(1, dtype=torch.float64, device=DEV)
+    B.bsp_grid_assign(plan.handle, dev(u[0]), dev(u[1]), dev(u[2]), None, u[0].size, grids, wsum)
+    dl = plan.spectrum_buffer()
+    B.bsp_los_moments(plan.handle, grids, wsum, dl)
+    plan.sync()
+    got = gpu_cube_to_numpy(dl, info.nl, info.spec_elems)
+    spec, _ = O.spectrum_from_catalogue(*u, n, lmax, obs if los else None, window=1, interlace=interlace)
+    for li in range(info.nl):
+        idx, vals, _ = compact_to_half(got[li], n, info.c, info.cz, info.n2max)
+        ref = spec[li][idx]
+        ref = np.where((idx[0] == 0) & (idx[1] == 0) & (idx[2] == 0), 0, ref)
+        e = rel_norm(np.stack([vals.real, vals.imag]), np.stack([ref.real, ref.imag]))
+        assert e < 2e-5, (li, e)
+
+
+def test_grid_entry_against_oracle():
+    say("grid-entry")
+    n = 32
+    d = rng(12).standard_normal((n, n, n))
+    obs = np.array([-40.0, -30.0, -55.0])
+    plan = B.Plan(n=n, box=200.0, nbins=4, k0=2.0, dk=2.0, lmax=4, los=1, observer=obs)
+    info = plan.info
+    dl = plan.spectrum_buffer()
+    B.bsp_grid_entry(plan.handle, dev(d), dl)
+    plan.sync()
+    got = gpu_cube_to_numpy(dl, info.nl, info.spec_elems)
+    spec = O.spectrum_from_field([d], [0.0], n, 4, obs, None)
+    for li in range(3):
+        idx, vals, _ = compact_to_half(got[li], n, info.c, info.cz, info.n2max)
+        ref = np.where((idx[0] == 0) & (idx[1] == 0) & (idx[2] == 0), 0, spec[li][idx])
+        assert rel_norm(np.stack([vals.real, vals.imag]), np.stack([ref.real, ref.imag])) < 2e-5
+
+
+# ---------------------------------------------------------------- filtered fields
+
+def test_filter_fields_against_oracle():
+    say("filter")
+    n, nr = 32, 32
+    k0, dk, nb, P = 2.0, 2.0, 4, 3
+    box = 200.0
+    d = rng(13).standard_normal((n, n, n))
+    spec = O.spectrum_from_field([d], [0.0], n, 2, None, None)
+    wl = C.Workload("t", n, nr, box, 10000, -1.5, 0.5, 0.5, 0, 1, 0, 2, nb, dk, P, 10, 1)
+    n2len = 3 * n * n
+    pf = pfid_table(wl, n2len)
+    plan = B.Plan(n=n, box=box, nbins=nb, k0=k0, dk=dk, lmax=2, P=P, nmodes=4, pfid=pf)
+    info = plan.info
+    cube = np.stack([half_to_compact(s, n, info.c, info.cz, info.n2max) for s in spec])
+    dl = dev(np.stack([cube.real, cube.imag], -1).reshape(info.nl, -1, 2))
+    filt = [(li, 0, b) for li in range(2) for b in range(nb)] + [(li, 1, p) for li in range(2) for p in range(P)]
+    fields = torch.zeros((len(filt), nr, nr, nr), dtype=torch.float32, device=DEV)
+    B.bsp_filter_fields(plan.handle, dl, filt, fields)
+    plan.sync()
+    got = fields.cpu().numpy()
+    n2 = O.n2_grid_half(nr)
+    bins = O.bin_of_n2(n2, k0, dk, nb)
+    kf = 2 * math.pi / box
+    M = [O.modal_fields(s, n, nr, P, k0 - dk / 2, k0 + (nb - 0.5) * dk, kf, pf) * n ** 3 for s in spec]
+    for i, (li, kind, idx) in enumerate(filt):
+        if kind == 0:
+            ref = O.shell_field(spec[li], bins == idx, nr)
+        else:
+            ref = M[li][idx].reshape(nr, nr, nr)
+        assert rel_norm(got[i], ref) < 1e-5, (li, kind, idx)
+
+
+# ---------------------------------------------------------------- triple reduction
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-5), (1, 1e-4), (2, 1e-5)])
+@pytest.mark.parametrize("K", [64 * 64 * 64, 50_011])
+def test_triple_reduce_definition(prec, tol, K):
+    say("reduce", prec, K)
+    r = rng(20 + prec)
+    nf = 21
+    F = r.standard_normal((nf, K)).astype(np.float32) * r.uniform(0.5, 3e3, (nf, 1)).astype(np.float32)
+    pairs = np.array([(a, b) for a in range(nf) for b in range(a, nf)][::3], np.int32)
+    thirds = np.arange(0, nf, 1, dtype=np.int32)[::-1].copy()
+    need = (r.uniform(size=(len(pairs), len(thirds))) < 0.4).astype(np.uint8)
+    plan = B.Plan(n=16, box=100.0, nbins=1, k0=1.0, dk=1.0, workspace=False)
+    ws = torch.empty(1 << 28, dtype=torch.uint8, device=DEV)
+    B.bsp_set_workspace(plan.handle, ws, ws.numel())
+    T = torch.zeros((len(pairs), len(thirds)), dtype=torch.float64, device=DEV)
+    B.bsp_triple_reduce(plan.handle, dev(F), nf, K, pairs, thirds, need, prec, T)
+    plan.sync()
+    got = T.cpu().numpy()
+    F64 = F.astype(np.float64)
+    ref = np.array([[np.dot(F64[a] * F64[b], F64[t]) for t in thirds] for a, b in pairs])
+    ref = ref * need
+    assert np.all(got[need == 0] == 0)
+    # the sums are noise dominated: compare with the scale of the summed terms
+    scale = np.sqrt(np.array([[np.dot((F64[a] * F64[b]) ** 2, F64[t] ** 2) for t in thirds] for a, b in pairs]))
+    err = np.abs(got - ref)[need == 1] / scale[need == 1]
+    assert np.sqrt(np.mean(err ** 2)) < tol, np.sqrt(np.mean(err ** 2))
+
+
+# ---------------------------------------------------------------- geometry precompute
+
+def _plan_c1(**kw):
+    wl = C.workload("c1_64")
+    n2len = 3 * wl.n ** 2
+    pf = pfid_table(wl, n2len)
+    args = dict(n=wl.n, box=wl.box, nbins=wl.nbins, k0=wl.k0, dk=wl.dk, lmax=0, window=1, interlace=0, los=0,
+                P=wl.P, nmodes=wl.nmodes, pfid=pf)
+    args.update(kw)
+    return wl, pf, B.Plan(**args)
+
+
+def test_precompute_counts_gram_shot_noise():
+    say("precompute-c1")
+    wl, pf, plan = _plan_c1()
+    plan.precompute()
+    path = __file__.replace("test_gpu_parity.py", "golden/counts_k2_d2_nb10.txt")
+    gold = np.loadtxt(path, dtype=np.int64, comments="#")
+    gold = gold[gold[:, 3] > 0]
+    assert np.array_equal(plan.tri, gold[:, :3])
+    assert np.array_equal(plan.counts, gold[:, 3])
+    modes = O.modal_modes(wl.P, wl.nmodes)
+    kf = 2 * math.pi / wl.box
+    gam = O.gram_matrix(wl.n, modes, wl.P, wl.kmin, wl.kmax, kf, wl.box)
+    assert rel_norm(plan.gamma, gam) < 1e-10
+    assert rel_norm(plan.chol, np.linalg.cholesky(gam)) < 1e-9
+
+
+# ---------------------------------------------------------------- end to end
+
+def _run_gpu(plan, u, prec, nl, nmodes):
+    ntri = plan.info.ntri
+    Bt = torch.zeros((nl, ntri), dtype=torch.float64, device=DEV)
+    B0 = torch.zeros(ntri, dtype=torch.float64, device=DEV)
+    Pb = torch.zeros(plan.geom.nbins, dtype=torch.float64, device=DEV)
+    bn = torch.zeros((nl, max(nmodes, 1)), dtype=torch.float64, device=DEV)
+    al = torch.zeros_like(bn)
+    be = torch.zeros_like(bn)
+    B.bsp_bispectrum_multipoles(plan.handle, dev(u[0]), dev(u[1]), dev(u[2]), None, u[0].size, prec, Bt, B0, Pb,
+                                bn if nmodes else None, al if nmodes else None, be if nmodes else None)
+    plan.sync()
+    return {k: v.cpu().numpy() for k, v in dict(B=Bt, B0_sub=B0, Pbar=Pb, bnum=bn, alpha=al, beta=be).items()}
+
+
+@pytest.fixture(scope="module")
+def c1_case():
+    wl, pf, plan = _plan_c1()
+    plan.precompute()
+    u = C.lognormal_catalogue(wl)
+    spec, wsum = O.spectrum_from_catalogue(*u, wl.n, 0, None, window=1, interlace=0)
+    geo = O.Geometry(wl.n, wl.n, wl.box, 0, wl.nbins, wl.k0, wl.dk, wl.P, wl.nmodes, pf)
+    ref = O.estimate(spec, geo, nbar=wsum / wl.box ** 3)
+    return wl, plan, u, ref
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_end_to_end_c1_monopole(c1_case, prec):
+    say("e2e-c1", prec)
+    wl, plan, u, ref = c1_case
+    got = _run_gpu(plan, u, prec, 1, wl.nmodes)
+    assert np.array_equal(plan.tri, ref["tris"])
+    assert np.array_equal(plan.counts, ref["counts"])
+    tb, tbeta = (1e-5, 1e-5) if prec == 0 else (1e-3, 1e-4)
+    assert rel_norm(got["Pbar"], ref["Pbar"]) < 1e-5
+    assert rel_norm(got["B"], ref["B"]) < tb
+    assert rel_norm(got["B0_sub"], ref["B0_sub"]) < tb
+    assert rel_norm(got["bnum"][0], ref["bnum_sub0"]) < tbeta
+    assert rel_norm(got["beta"], ref["beta"]) < tbeta
+    assert rel_norm(got["alpha"], ref["alpha"]) < tbeta
+
+
+@pytest.fixture(scope="module")
+def los_case():
+    n, box = 64, 400.0
+    wl = C.Workload("los64", n, n, box, 120_000, -1.5, 0.6, 0.6, 1, 1, 1, 4, 6, 3.0, 4, 20, 77)
+    obs = C.observer_grid_units(wl)
+    pf = pfid_table(wl, 3 * n * n)
+    plan = B.Plan(n=n, box=box, nbins=wl.nbins, k0=wl.k0, dk=wl.dk, lmax=4, window=1, interlace=1, los=1,
+                  observer=obs, P=wl.P, nmodes=wl.nmodes, pfid=pf)
+    plan.precompute()
+    u = C.lognormal_catalogue(wl)
+    spec, wsum = O.spectrum_from_catalogue(*u, n, 4, obs, window=1, interlace=1)
+    geo = O.Geometry(n, n, box, 4, wl.nbins, wl.k0, wl.dk, wl.P, wl.nmodes, pf)
+    ref = O.estimate(spec, geo, nbar=wsum / box ** 3)
+    return wl, plan, u, ref
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_end_to_end_varying_los_interlaced(los_case, prec):
+    say("e2e-los", prec)
+    wl, plan, u, ref = los_case
+    got = _run_gpu(plan, u, prec, 3, wl.nmodes)
+    assert np.array_equal(plan.counts, ref["counts"])
+    tb, tbeta = (1e-5, 1e-5) if prec == 0 else (1e-3, 1e-4)
+    for li in range(3):
+        assert rel_norm(got["B"][li], ref["B"][li]) < tb, li
+        assert rel_norm(got["beta"][li], ref["beta"][li]) < tbeta, li
+    assert rel_norm(got["B0_sub"], ref["B0_sub"]) < tb
+    assert rel_norm(got["Pbar"], ref["Pbar"]) < 1e-5
