@@ -176,9 +176,10 @@ bsp_status bsp_filter_fields(bsp_plan plan, const void* delta_l, int32_t nfilt, 
  * the sum over products of three transformed fields of the standard and modal
  * estimators. fields: device [nfields][K] float (nfields <= 128); pairs: host
  * [npairs][2]; thirds: host [nthirds] (<= 128); need: host [npairs][nthirds]
- * uint8 or NULL (all); entries not needed are left 0. T: device double
- * [npairs][nthirds]. Chunks of K are accumulated in FP32 and combined in FP64.
- * Uses the workspace. */
+ * uint8 or NULL (all). The reduction works on tiles of 16 pairs x 16 thirds:
+ * every entry of a tile holding a needed entry is computed, entries of other
+ * tiles are 0. T: device double [npairs][nthirds]. Chunks of K are
+ * accumulated in FP32 and combined in FP64. Uses the workspace. */
 bsp_status bsp_triple_reduce(bsp_plan plan, const float* fields, int32_t nfields, int64_t K, const int32_t* pairs,
                              int32_t npairs, const int32_t* thirds, int32_t nthirds, const uint8_t* need,
                              bsp_precision prec, double* T);

@@ -233,7 +233,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     __syncthreads();
   }
 
-  // partial tiles of this chunk: lane holds rows 4q + i, column r16
+  // partial tiles of this chunk, column r16 of the tile; the f32 16x16x4 and
+  // 16x16x32 results hold rows 4q + i in lane group q, the f64 16x16x4 result
+  // holds rows q + 4i.
 #pragma unroll
   for (int r = 0; r < MAXR; ++r) {
     if (masks[r] == 0) continue;
@@ -243,7 +245,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
       const int tile = d.tile_index[rows[r] * 8 + c];
       T* out = partials + ((int64_t)chunk * d.ntiles + tile) * 256;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) out[(4 * q + i) * 16 + r16] = acc[r][c][i];
+      for (int i = 0; i < 4; ++i) {
+        const int row = (PREC == 3) ? (q + 4 * i) : (4 * q + i);
+        out[row * 16 + r16] = acc[r][c][i];
+      }
     }
   }
 }
