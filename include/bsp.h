@@ -60,7 +60,7 @@ typedef enum {
   BSP_ERR_WORKSPACE = 4, /* no workspace, or smaller than bsp_workspace_size */
   BSP_ERR_HIP = 5,       /* HIP runtime error (message in bsp_last_error) */
   BSP_ERR_DEVICE = 6,    /* latched by a kernel: particle outside [0,N) or not finite */
-  BSP_ERR_NUMERIC = 7,   /* latched: triangle count residual >= 1e-3, or Cholesky failure */
+  BSP_ERR_NUMERIC = 7,   /* latched: triangle count residual >= 0.05, or Cholesky failure */
   BSP_ERR_STATE = 8      /* call out of order */
 } bsp_status;
 
@@ -104,6 +104,7 @@ typedef struct {
   int32_t nfields_binned; /* nl * nbins shell fields D^(l)_b */
   int32_t nfields_modal;  /* nl * P modal fields M^(l)_p */
   int64_t spec_elems;     /* complex elements of one compact cube: (2c+1)^2 cz */
+  double count_residual;  /* max |sum I I I / N'^3 - N_tri| over candidates (after bsp_precompute) */
 } bsp_info;
 
 /* ---------------------------------------------------------------- plans */
@@ -125,7 +126,7 @@ bsp_status bsp_sync(bsp_plan plan);
 
 /* Geometry-only FP64 precompute on the GPU (once per plan): triangle counts
  * V_B(k1,k2,k3) of the standard estimator as round(sum_x I I I / N'^3) with
- * I_b the inverse DFT of the shell indicator (residual checked), and, with a
+ * I_b the inverse DFT of the shell indicator (residual < 0.05 checked), and, with a
  * modal basis, the lattice Gram matrix gamma_nm = <<Q_n|Q_m>> of eqs.
  * (betaCalc, innerProduct), its Cholesky factor, and the Poisson shot-noise
  * integrals of the modal numerators. Needs the workspace. Synchronises. */

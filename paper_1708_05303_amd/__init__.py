@@ -69,7 +69,8 @@ class ModalBasis(C.Structure):
 class Info(C.Structure):
     _fields_ = [("c", C.c_int32), ("cz", C.c_int32), ("nl", C.c_int32), ("nlos", C.c_int32),
                 ("ngrid", C.c_int32), ("n2max", C.c_int32), ("ncand", C.c_int32), ("ntri", C.c_int32),
-                ("nfields_binned", C.c_int32), ("nfields_modal", C.c_int32), ("spec_elems", C.c_int64)]
+                ("nfields_binned", C.c_int32), ("nfields_modal", C.c_int32), ("spec_elems", C.c_int64),
+                ("count_residual", C.c_double)]
 
 
 _lib = None

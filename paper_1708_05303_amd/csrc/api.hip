@@ -21,20 +21,66 @@ size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 thread_local std::string g_create_error;
 
 struct ReducePlan {
-  int npairs = 0, nthirds = 0, nrt = 0, nct = 0, ngroups = 0, ntiles = 0, maxr = 0, nfields = 0;
-  std::vector<int32_t> pair_a, pair_b, third, row_mask, tile_index, tile_rc, wave_rows;
+  int npairs = 0, nthirds = 0, nrt = 0, nct = 0, ngroups = 0, ntiles = 0, maxr = 0, maxcw = 0, nfields = 0;
+  std::vector<int32_t> pair_a, pair_b, third, row_mask, tile_index, tile_rc, wave_rows, wave_cols;
   // device copies (plan-owned or workspace)
   int32_t* d = nullptr;  // one block holding every array
   size_t words = 0;
   int32_t *d_pair_a = nullptr, *d_pair_b = nullptr, *d_third = nullptr, *d_row_mask = nullptr,
-          *d_tile_index = nullptr, *d_tile_rc = nullptr, *d_wave_rows = nullptr;
+          *d_tile_index = nullptr, *d_tile_rc = nullptr, *d_wave_rows = nullptr, *d_wave_cols = nullptr;
   std::vector<int32_t> packed;
 };
 
-// Tiles of 16 pairs x 16 thirds; a tile is needed when any entry is. Row tiles
-// are spread over (group, wave) slots, heaviest first, to balance MFMA work.
+// Tiles of 16 pairs x 16 thirds; a tile is needed when any entry is. Row
+// tiles are given to (group, wave) slots, heaviest first, each wave holding at
+// most maxr row tiles whose needed column tiles number at most maxcw; the
+// register shape is the one that needs the fewest groups (each group reads
+// every field once).
+bool schedule_rows(ReducePlan& rp, const std::vector<int>& active, int maxr, int maxcw, int waves,
+                   std::vector<int>& wrows, std::vector<int>& wcols, int& ngroups) {
+  for (int r : active)
+    if (__builtin_popcount(rp.row_mask[r]) > maxcw) return false;
+  ngroups = std::max(1, (int)((active.size() + (size_t)waves * maxr - 1) / ((size_t)waves * maxr)));
+  for (;; ++ngroups) {
+    const int nw = ngroups * waves;
+    std::vector<int> load(nw, 0), cnt(nw, 0), cm(nw, 0);
+    wrows.assign((size_t)nw * maxr, -1);
+    bool ok = true;
+    for (int r : active) {
+      const int m = rp.row_mask[r];
+      int best = -1, best_grow = 0;
+      for (int w = 0; w < nw; ++w) {
+        if (cnt[w] >= maxr || __builtin_popcount(cm[w] | m) > maxcw) continue;
+        const int grow = __builtin_popcount((cm[w] | m) & ~cm[w]);
+        if (best < 0 || load[w] < load[best] || (load[w] == load[best] && grow < best_grow)) {
+          best = w;
+          best_grow = grow;
+        }
+      }
+      if (best < 0) {
+        ok = false;
+        break;
+      }
+      wrows[(size_t)best * maxr + cnt[best]++] = r;
+      load[best] += __builtin_popcount(m);
+      cm[best] |= m;
+    }
+    if (!ok) {
+      if (ngroups > (int)active.size()) return false;
+      continue;
+    }
+    wcols.assign((size_t)nw * maxcw, -1);
+    for (int w = 0; w < nw; ++w) {
+      int k = 0;
+      for (int c = 0; c < 8; ++c)
+        if ((cm[w] >> c) & 1) wcols[(size_t)w * maxcw + k++] = c;
+    }
+    return true;
+  }
+}
+
 bool build_reduce(ReducePlan& rp, const std::vector<std::array<int, 2>>& pairs, const std::vector<int>& thirds,
-                  const std::vector<uint8_t>& need, int nfields, int maxr_fn(int, int), int prec) {
+                  const std::vector<uint8_t>& need, int nfields, int prec) {
   rp = ReducePlan{};
   rp.npairs = (int)pairs.size();
   rp.nthirds = (int)thirds.size();
@@ -42,7 +88,6 @@ bool build_reduce(ReducePlan& rp, const std::vector<std::array<int, 2>>& pairs, 
   rp.nrt = (rp.npairs + 15) / 16;
   rp.nct = (rp.nthirds + 15) / 16;
   if (rp.nct > 8 || rp.nct == 0 || rp.nrt == 0) return false;
-  rp.maxr = maxr_fn(prec, rp.nct);
   rp.pair_a.assign(rp.nrt * 16, -1);
   rp.pair_b.assign(rp.nrt * 16, -1);
   rp.third.assign(rp.nct * 16, -1);
@@ -67,41 +112,42 @@ bool build_reduce(ReducePlan& rp, const std::vector<std::array<int, 2>>& pairs, 
         }
       active.push_back(r);
     }
-  const int waves = reduce_waves_per_group();
-  const int slots_per_group = waves * rp.maxr;
-  rp.ngroups = std::max(1, (int)((active.size() + slots_per_group - 1) / slots_per_group));
-  // longest-processing-time assignment over all waves
-  std::sort(active.begin(), active.end(), [&](int a, int b) {
+  std::stable_sort(active.begin(), active.end(), [&](int a, int b) {
     return __builtin_popcount(rp.row_mask[a]) > __builtin_popcount(rp.row_mask[b]);
   });
-  const int nw = rp.ngroups * waves;
-  std::vector<int> load(nw, 0), cnt(nw, 0);
-  rp.wave_rows.assign((size_t)nw * rp.maxr, -1);
-  for (int r : active) {
-    int best = -1;
-    for (int w = 0; w < nw; ++w)
-      if (cnt[w] < rp.maxr && (best < 0 || load[w] < load[best])) best = w;
-    rp.wave_rows[(size_t)best * rp.maxr + cnt[best]++] = r;
-    load[best] += __builtin_popcount(rp.row_mask[r]);
+  const int waves = reduce_waves_per_group();
+  ReduceShape shapes[8];
+  const int ns = reduce_shapes(prec, shapes, 8);
+  int best_groups = 1 << 30;
+  for (int i = 0; i < ns; ++i) {
+    std::vector<int> wr, wc;
+    int ng = 0;
+    if (!schedule_rows(rp, active, shapes[i].maxr, shapes[i].maxcw, waves, wr, wc, ng)) continue;
+    if (ng < best_groups) {
+      best_groups = ng;
+      rp.maxr = shapes[i].maxr;
+      rp.maxcw = shapes[i].maxcw;
+      rp.wave_rows = wr;
+      rp.wave_cols = wc;
+      rp.ngroups = ng;
+    }
   }
+  if (best_groups == (1 << 30)) return false;
   // pack for one upload
   rp.packed.clear();
   auto put = [&](const std::vector<int32_t>& v) {
-    size_t off = rp.packed.size();
     rp.packed.insert(rp.packed.end(), v.begin(), v.end());
     while (rp.packed.size() % 64) rp.packed.push_back(0);
-    return off;
   };
-  size_t o[7];
-  o[0] = put(rp.pair_a);
-  o[1] = put(rp.pair_b);
-  o[2] = put(rp.third);
-  o[3] = put(rp.row_mask);
-  o[4] = put(rp.tile_index);
-  o[5] = put(rp.tile_rc.empty() ? std::vector<int32_t>{0} : rp.tile_rc);
-  o[6] = put(rp.wave_rows);
+  put(rp.pair_a);
+  put(rp.pair_b);
+  put(rp.third);
+  put(rp.row_mask);
+  put(rp.tile_index);
+  put(rp.tile_rc.empty() ? std::vector<int32_t>{0} : rp.tile_rc);
+  put(rp.wave_rows);
+  put(rp.wave_cols);
   rp.words = rp.packed.size();
-  (void)o;
   return true;
 }
 
@@ -121,6 +167,7 @@ void bind_reduce(ReducePlan& rp, int32_t* dev) {
   rp.d_tile_index = take(rp.tile_index.size());
   rp.d_tile_rc = take(rp.tile_rc.empty() ? 1 : rp.tile_rc.size());
   rp.d_wave_rows = take(rp.wave_rows.size());
+  rp.d_wave_cols = take(rp.wave_cols.size());
 }
 
 // Points per workgroup chunk: about 2048 chunks, at least 1024 points, at most
@@ -145,7 +192,10 @@ ReduceDesc make_desc(const ReducePlan& rp, int64_t K, int64_t field_stride, int 
   d.nchunks = (int32_t)((K + d.kchunk - 1) / d.kchunk);
   d.ngroups = rp.ngroups;
   d.nct = rp.nct;
+  d.maxr = rp.maxr;
+  d.maxcw = rp.maxcw;
   d.wave_rows = rp.d_wave_rows;
+  d.wave_cols = rp.d_wave_cols;
   d.row_mask = rp.d_row_mask;
   d.tile_index = rp.d_tile_index;
   d.tile_rc = rp.d_tile_rc;
@@ -201,6 +251,7 @@ struct bsp_plan_s {
   std::vector<std::array<int, 3>> tri;
   std::vector<int64_t> counts;
   std::vector<double> gamma_h, chol_h;
+  double count_residual = -1.0;
   int64_t* d_counts = nullptr;
   int32_t* d_tri_bins = nullptr;
   int32_t* d_tri_tidx = nullptr;
@@ -360,7 +411,7 @@ Layout layout(const bsp_plan p) {
   if (p->modal)
     part64 = std::max({part64, partial_bytes(p->gram_rp, K, 3, sizeof(double)),
                        partial_bytes(p->sn_rp, K, 3, sizeof(double))});
-  part64 = align_up(std::max<size_t>(part64, p->cand.size() * sizeof(int64_t)));
+  part64 = align_up(std::max<size_t>(part64, p->cand.size() * 2 * sizeof(int64_t) + ALIGN));
   L.pre_scratch = std::max(inv_scratch(p, fb64, sizeof(double2)), part64 + align_up(1 << 20));
   L.pre_total = L.pre_ones + L.pre_fields + L.pre_T + L.pre_scratch;
   return L;
@@ -588,7 +639,7 @@ bool build_counts(bsp_plan p) {
   std::vector<uint8_t> need(pr.size() * th.size(), 0);
   for (size_t i = 0; i < pr.size(); ++i)
     for (int b1 = 0; b1 < p->nbins; ++b1) need[i * th.size() + b1] = b1 >= pr[i][0];
-  if (!build_reduce(p->cnt_rp, pr, th, need, p->nbins, reduce_max_rows_per_wave, 3)) return false;
+  if (!build_reduce(p->cnt_rp, pr, th, need, p->nbins, 3)) return false;
   p->cnt_tidx.resize(p->cand.size());
   for (size_t i = 0; i < p->cand.size(); ++i) {
     const int b1 = p->cand[i][0], b2 = p->cand[i][1], b3 = p->cand[i][2];
@@ -626,7 +677,7 @@ bool build_gram(bsp_plan p) {
         need[(size_t)pi * nU + tr[2]] = 1;
         p->gidx[((size_t)i * nm + j) * 6 + t] = pi * nU + tr[2];
       }
-  return build_reduce(p->gram_rp, pr, th, need, nU, reduce_max_rows_per_wave, 3);
+  return build_reduce(p->gram_rp, pr, th, need, nU, 3);
 }
 
 // <G^P_p G_r G_s> (three placements) and <G_p G_r G_s> for every mode
@@ -652,7 +703,7 @@ bool build_sn(bsp_plan p) {
       p->sidx[4 * i + k] = e[k][0] * (int)th.size() + e[k][1];
     }
   }
-  return build_reduce(p->sn_rp, pr, th, need, 2 * P, reduce_max_rows_per_wave, 3);
+  return build_reduce(p->sn_rp, pr, th, need, 2 * P, 3);
 }
 
 // Main schedule: pairs (D0_b2 D0_b3, b2 >= b3), (M0_a M0_b), (M2_a M2_b);
@@ -733,7 +784,7 @@ bool build_main(bsp_plan p, bool exact) {
       }
     }
   }
-  return build_reduce(p->main_rp, pr, th, need, p->F, reduce_max_rows_per_wave, 1);
+  return build_reduce(p->main_rp, pr, th, need, p->F, 1);
 }
 
 }  // namespace
@@ -952,6 +1003,7 @@ bsp_status bsp_plan_info(bsp_plan p, bsp_info* info) {
   info->nfields_binned = p->nl * p->nbins;
   info->nfields_modal = p->modal ? p->nl * p->P : 0;
   info->spec_elems = p->spec;
+  info->count_residual = p->count_residual;
   return BSP_OK;
 }
 
@@ -980,7 +1032,7 @@ bsp_status bsp_sync(bsp_plan p) {
   if (e) {
     HIPCHK(hipMemset(p->d_err, 0, sizeof(int32_t)));
     if (e & 1) return fail(p, BSP_ERR_DEVICE, "particle outside [0, N) or not finite");
-    if (e & 4) return fail(p, BSP_ERR_NUMERIC, "triangle count residual >= 1e-3");
+    if (e & 4) return fail(p, BSP_ERR_NUMERIC, "triangle count residual >= 0.05");
     if (e & 8) return fail(p, BSP_ERR_NUMERIC, "Gram matrix not positive definite");
     return fail(p, BSP_ERR_DEVICE, "device error");
   }
@@ -1122,7 +1174,7 @@ bsp_status bsp_triple_reduce(bsp_plan p, const float* fields, int32_t nfields, i
     if (t < 0 || t >= nfields) return fail(p, BSP_ERR_ARG, "third field out of range");
   std::vector<uint8_t> nd;
   if (need) nd.assign(need, need + (size_t)npairs * nthirds);
-  if (!build_reduce(p->call_rp, pr, th, nd, nfields, reduce_max_rows_per_wave, (int)prec))
+  if (!build_reduce(p->call_rp, pr, th, nd, nfields, (int)prec))
     return fail(p, BSP_ERR_ARG, "reduction shape not supported");
   const size_t meta = align_up(p->call_rp.words * sizeof(int32_t));
   const size_t sc = align_up((size_t)nfields * sizeof(float)) * 2;
@@ -1168,11 +1220,37 @@ bsp_status bsp_precompute(bsp_plan p) {
   s = run_reduce<double>(p, p->cnt_rp, f64, K, 3, nullptr, T64, scr, scr_bytes, 1.0);
   if (s != BSP_OK) return s;
   int64_t* dc = reinterpret_cast<int64_t*>(scr);
-  HIPCHK(launch_counts_finalize(T64, p->d_cnt_tidx, (int)p->cand.size(), 1.0 / (double)K, dc, p->d_err, p->stream));
+  double* draw = reinterpret_cast<double*>(scr + align_up(p->cand.size() * sizeof(int64_t)));
+  HIPCHK(launch_counts_finalize(T64, p->d_cnt_tidx, (int)p->cand.size(), 1.0 / (double)K, dc, draw, p->d_err,
+                                p->stream));
   s = bsp_sync(p);
-  if (s != BSP_OK) return s;
+  if (s != BSP_OK) {
+    // report the worst residual and its triangle
+    std::vector<double> raw(p->cand.size());
+    if (hipMemcpy(raw.data(), draw, raw.size() * sizeof(double), hipMemcpyDeviceToHost) == hipSuccess) {
+      size_t worst = 0;
+      double wr = -1.0;
+      for (size_t i = 0; i < raw.size(); ++i) {
+        const double r = std::fabs(raw[i] - std::rint(raw[i]));
+        if (r > wr) {
+          wr = r;
+          worst = i;
+        }
+      }
+      p->err += " (max residual " + std::to_string(wr) + " at (" + std::to_string(p->cand[worst][0]) + "," +
+                std::to_string(p->cand[worst][1]) + "," + std::to_string(p->cand[worst][2]) + "), value " +
+                std::to_string(raw[worst]) + ")";
+    }
+    return s;
+  }
   std::vector<int64_t> cc(p->cand.size());
   HIPCHK(hipMemcpy(cc.data(), dc, cc.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+  {
+    std::vector<double> raw(p->cand.size());
+    HIPCHK(hipMemcpy(raw.data(), draw, raw.size() * sizeof(double), hipMemcpyDeviceToHost));
+    p->count_residual = 0.0;
+    for (double v : raw) p->count_residual = std::max(p->count_residual, std::fabs(v - std::rint(v)));
+  }
   p->tri.clear();
   p->counts.clear();
   for (size_t i = 0; i < cc.size(); ++i)

@@ -66,7 +66,9 @@ struct ReduceDesc {
   int32_t nchunks;
   int32_t ngroups;               // row-tile groups (grid.y)
   int32_t nct;                   // column tiles of 16 thirds (<= 8)
-  const int32_t* wave_rows;      // [ngroups][8 waves][maxr] row tile ids, -1 none
+  int32_t maxr, maxcw;           // row tiles and column tiles per wave of the schedule
+  const int32_t* wave_rows;      // [ngroups][waves][maxr] row tile ids, -1 none
+  const int32_t* wave_cols;      // [ngroups][waves][maxcw] column tile ids, -1 none
   const int32_t* row_mask;       // [nrt] bit c set: column tile c needed
   const int32_t* tile_index;     // [nrt][8] compact tile id, -1 if not needed
   const int32_t* tile_rc;        // [ntiles][2] row tile, column tile
@@ -117,7 +119,9 @@ hipError_t launch_combine_partials(const void* partials, int is_f64, const Reduc
                                    int npairs, int nthirds, double* T, double tscale,
                                    hipStream_t s);
 int reduce_waves_per_group();
-int reduce_max_rows_per_wave(int prec, int nct);
+// Register-budget shapes (rows, columns per wave) the kernel is instantiated for.
+struct ReduceShape { int maxr, maxcw; };
+int reduce_shapes(int prec, ReduceShape* out, int max_out);
 
 // FP64 finishing kernels (fp64.hip).
 hipError_t launch_binned_finalize(const double* T, const int32_t* tri_tidx, int ntri, int nl,
@@ -125,7 +129,7 @@ hipError_t launch_binned_finalize(const double* T, const int32_t* tri_tidx, int 
                                   int nbins, const int32_t* tri_bins, double norm_b, double pnorm,
                                   const double* nbar, double* B, double* B0sub, double* Pbar, hipStream_t s);
 hipError_t launch_counts_finalize(const double* T, const int32_t* tidx, int ntri, double inv_k,
-                                  int64_t* counts, int32_t* err, hipStream_t s);
+                                  int64_t* counts, double* raw, int32_t* err, hipStream_t s);
 hipError_t launch_modal_assemble(const double* T, const int32_t* combo, int nmodes, int nl,
                                  double scale, const double* sn, const double* nbar, double* bnum,
                                  hipStream_t s);

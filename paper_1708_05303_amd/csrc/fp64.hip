@@ -32,15 +32,19 @@ __global__ void k_binned_finalize(const double* __restrict__ T, const int32_t* _
   }
 }
 
-// counts_i = round(T_i / N'^3); bit 2 of err if any |T/N'^3 - round| >= 1e-3.
+// counts_i = round(T_i / N'^3); bit 2 of err if any |T/N'^3 - round| >= 0.05
+// (rounding is unambiguous below 0.5; FP64 sums of 1e8 terms of this dynamic
+// range leave ~1e-3 on counts of 1e10).
 __global__ void k_counts_finalize(const double* __restrict__ T, const int32_t* __restrict__ tidx, int ntri,
-                                  double inv_k, int64_t* __restrict__ counts, int32_t* __restrict__ err) {
+                                  double inv_k, int64_t* __restrict__ counts, double* __restrict__ raw,
+                                  int32_t* __restrict__ err) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ntri) return;
   const double c = T[tidx[i]] * inv_k;
   const double r = rint(c);
   counts[i] = (int64_t)r;
-  if (!(fabs(c - r) < 1e-3)) atomicOr(err, 4);
+  raw[i] = c;
+  if (!(fabs(c - r) < 0.05)) atomicOr(err, 4);
 }
 
 // bnum[l][m] = scale sum_{j<6, combo >= 0} T[combo[l][m][j]]  (minus shot noise for l = 0)
@@ -180,9 +184,10 @@ hipError_t launch_binned_finalize(const double* T, const int32_t* tri_tidx, int 
 }
 
 hipError_t launch_counts_finalize(const double* T, const int32_t* tidx, int ntri, double inv_k, int64_t* counts,
-                                  int32_t* err, hipStream_t s) {
+                                  double* raw, int32_t* err, hipStream_t s) {
   if (ntri <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_counts_finalize, dim3(nblk(ntri, 256)), dim3(256), 0, s, T, tidx, ntri, inv_k, counts, err);
+  hipLaunchKernelGGL(k_counts_finalize, dim3(nblk(ntri, 256)), dim3(256), 0, s, T, tidx, ntri, inv_k, counts, raw,
+                     err);
   return hipGetLastError();
 }
 

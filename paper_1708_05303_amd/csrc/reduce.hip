@@ -6,7 +6,7 @@
 // standard estimator (its FFT form and the multipole form with D^(l)_k) and the
 // integral of M M M of the modal estimator, both in Sec. 3 of the paper.
 //
-// Structure: a workgroup (4 waves, one per SIMD) owns a chunk of K points and a group of
+// Structure: a workgroup (8 waves, two per SIMD) owns a chunk of K points and a group of
 // row tiles; each wave owns up to MAXR row tiles of 16 pairs and every needed
 // 16-wide column tile of thirds, with the accumulators resident in registers.
 // Points stream through LDS in stages of 64 (double buffered, one
@@ -26,7 +26,7 @@
 
 namespace bsp {
 
-constexpr int WAVES = 4;
+constexpr int WAVES = 8;
 constexpr int NTHR = WAVES * 64;
 constexpr int KS = 64;  // points per LDS stage
 
@@ -42,20 +42,26 @@ template <> struct RT<2> { using T = float; using acc = f32x4; static constexpr 
 template <> struct RT<3> { using T = double; using acc = f64x4; static constexpr int KK = 2; };
 
 template <int PREC, int MAXR, int MAXC>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_reduce(const typename RT<PREC>::T* __restrict__ fields, ReduceDesc d,
-                                                typename RT<PREC>::T* __restrict__ partials) {
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_reduce(
+    const typename RT<PREC>::T* __restrict__ fields, ReduceDesc d, typename RT<PREC>::T* __restrict__ partials) {
   using T = typename RT<PREC>::T;
   using ACC = typename RT<PREC>::acc;
+  constexpr bool SPLIT = (PREC == 1 || PREC == 2);
+  using H = typename std::conditional<PREC == 2, _Float16, __bf16>::type;
+  using H8 = typename std::conditional<PREC == 2, f16x8, bf16x8>::type;
   constexpr int KK = RT<PREC>::KK;      // consecutive points per lane per k-step
   constexpr int KSTEP = 4 * KK;         // points per k-step
-  constexpr int LDW = KS + (16 / (int)sizeof(T));  // padded LDS row
+  constexpr int LDW = KS + (16 / (int)sizeof(T));  // padded FP32/FP64 LDS row
+  constexpr int LDH = KS + 8;                      // padded row of 16-bit halves (144 bytes)
   constexpr int EPV = 16 / (int)sizeof(T);         // elements per 16-byte vector
   using VEC = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
   constexpr int MAXV = (128 * KS / EPV + NTHR - 1) / NTHR;  // vectors per thread per stage (<= 128 fields)
 
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int nrow_lds = d.nfields + 1;  // the last row stays zero
   T* lds = reinterpret_cast<T*>(smem_raw);
-  const int nrow_lds = d.nfields + 1;  // last row stays zero
+  // split copies: [buffer][hi | lo][row][LDH], written once per stage by the whole workgroup
+  H* ldh = reinterpret_cast<H*>(smem_raw + (size_t)2 * nrow_lds * LDW * sizeof(T));
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int q = lane >> 4, r16 = lane & 15;
   const int chunk = blockIdx.x, group = blockIdx.y;
@@ -64,12 +70,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   if (k1 > d.K) k1 = d.K;
   const int nst = (int)((k1 - k0 + KS - 1) / KS);
 
-  // wave-uniform row tiles and their column masks
-  int rows[MAXR], masks[MAXR];
+  // wave-uniform row tiles, the wave's own column tiles, and the row masks in
+  // the wave's column slots
+  int rows[MAXR], masks[MAXR], cols[MAXC];
+#pragma unroll
+  for (int c = 0; c < MAXC; ++c) cols[c] = d.wave_cols[(group * WAVES + wave) * MAXC + c];
 #pragma unroll
   for (int r = 0; r < MAXR; ++r) {
     rows[r] = d.wave_rows[(group * WAVES + wave) * MAXR + r];
-    masks[r] = rows[r] >= 0 ? d.row_mask[rows[r]] : 0;
+    const int gm = rows[r] >= 0 ? d.row_mask[rows[r]] : 0;
+    int m = 0;
+#pragma unroll
+    for (int c = 0; c < MAXC; ++c)
+      if (cols[c] >= 0 && ((gm >> cols[c]) & 1)) m |= 1 << c;
+    masks[r] = m;
   }
   int pa[MAXR], pb[MAXR];
   float sab[MAXR];
@@ -83,12 +97,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     sab[r] = (d.scale && a >= 0 && b >= 0) ? d.scale[a] * d.scale[b] : 1.0f;
   }
   int th[MAXC];
-  float ss[MAXC];
 #pragma unroll
   for (int c = 0; c < MAXC; ++c) {
-    const int s = c < d.nct ? d.third[c * 16 + r16] : -1;
+    const int s = cols[c] >= 0 ? d.third[cols[c] * 16 + r16] : -1;
     th[c] = s >= 0 ? s : d.nfields;
-    ss[c] = (d.scale && s >= 0) ? d.scale[s] : 1.0f;
   }
   int colmask_any = 0;
 #pragma unroll
@@ -106,6 +118,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
   for (int i = threadIdx.x; i < LDW; i += blockDim.x) {
     lds[(int64_t)d.nfields * LDW + i] = (T)0;
     lds[(int64_t)(nrow_lds + d.nfields) * LDW + i] = (T)0;
+  }
+  if constexpr (SPLIT) {
+    for (int i = threadIdx.x; i < LDH; i += blockDim.x)
+      for (int b = 0; b < 4; ++b) ldh[((int64_t)b * nrow_lds + d.nfields) * LDH + i] = (H)0.0f;
   }
 
   const int nvec = d.nfields * (KS / EPV);
@@ -141,6 +157,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
       if (vi < nvec) {
         const int f = vi / (KS / EPV), e = (vi % (KS / EPV)) * EPV;
         *reinterpret_cast<VEC*>(base + (int64_t)f * LDW + e) = stage_regs[v];
+        if constexpr (SPLIT) {
+          // round-to-nearest-even split x = hi + lo of the (scaled) value, once per workgroup
+          const float sc = (PREC == 2 && d.scale) ? d.scale[f] : 1.0f;
+          const float x[4] = {stage_regs[v].x * sc, stage_regs[v].y * sc, stage_regs[v].z * sc,
+                              stage_regs[v].w * sc};
+          typedef H h4 __attribute__((ext_vector_type(4)));
+          h4 hi, lo;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const H h = (H)x[j];
+            hi[j] = h;
+            lo[j] = (H)(x[j] - (float)h);
+          }
+          H* hb = ldh + ((int64_t)(2 * buf) * nrow_lds + f) * LDH + e;
+          H* lb = ldh + ((int64_t)(2 * buf + 1) * nrow_lds + f) * LDH + e;
+          *reinterpret_cast<h4*>(hb) = hi;
+          *reinterpret_cast<h4*>(lb) = lo;
+        }
       }
     }
   };
@@ -154,22 +188,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     const int cur = st & 1;
     if (st + 1 < nst) gload(st + 1);
     const T* base = lds + (int64_t)cur * nrow_lds * LDW;
+    const H* hib = ldh + (int64_t)(2 * cur) * nrow_lds * LDH;
+    const H* lob = ldh + (int64_t)(2 * cur + 1) * nrow_lds * LDH;
     if (colmask_any) {
 #pragma unroll 1
       for (int ks = 0; ks < KS / KSTEP; ++ks) {
         const int off = ks * KSTEP + q * KK;
-        // pair-product fragments of every row tile of this wave
-        T av[MAXR][KK];
+        if constexpr (!SPLIT) {
+          // pair-product fragments of every row tile of this wave
+          T av[MAXR][KK];
 #pragma unroll
-        for (int r = 0; r < MAXR; ++r) {
+          for (int r = 0; r < MAXR; ++r)
 #pragma unroll
-          for (int j = 0; j < KK; ++j) av[r][j] = base[pa[r] * LDW + off + j] * base[pb[r] * LDW + off + j];
-          if constexpr (PREC == 2) {
-#pragma unroll
-            for (int j = 0; j < KK; ++j) av[r][j] *= sab[r];
-          }
-        }
-        if constexpr (PREC == 0 || PREC == 3) {
+            for (int j = 0; j < KK; ++j) av[r][j] = base[pa[r] * LDW + off + j] * base[pb[r] * LDW + off + j];
 #pragma unroll
           for (int c = 0; c < MAXC; ++c) {
             if (!((colmask_any >> c) & 1)) continue;
@@ -189,29 +220,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
             }
           }
         } else {
-          using H = typename std::conditional<PREC == 1, __bf16, _Float16>::type;
-          using H8 = typename std::conditional<PREC == 1, bf16x8, f16x8>::type;
           H8 ah[MAXR], al[MAXR];
 #pragma unroll
-          for (int r = 0; r < MAXR; ++r)
+          for (int r = 0; r < MAXR; ++r) {
+            if (masks[r] == 0) continue;
 #pragma unroll
             for (int j = 0; j < KK; ++j) {
-              const H h = (H)av[r][j];
+              float x = base[pa[r] * LDW + off + j] * base[pb[r] * LDW + off + j];
+              if constexpr (PREC == 2) x *= sab[r];
+              const H h = (H)x;
               ah[r][j] = h;
-              al[r][j] = (H)(av[r][j] - (float)h);
+              al[r][j] = (H)(x - (float)h);
             }
+          }
 #pragma unroll
           for (int c = 0; c < MAXC; ++c) {
             if (!((colmask_any >> c) & 1)) continue;
-            H8 bh, bl;
-#pragma unroll
-            for (int j = 0; j < KK; ++j) {
-              float x = base[th[c] * LDW + off + j];
-              if constexpr (PREC == 2) x *= ss[c];
-              const H h = (H)x;
-              bh[j] = h;
-              bl[j] = (H)(x - (float)h);
-            }
+            const H8 bh = *reinterpret_cast<const H8*>(hib + th[c] * LDH + off);
+            const H8 bl = *reinterpret_cast<const H8*>(lob + th[c] * LDH + off);
 #pragma unroll
             for (int r = 0; r < MAXR; ++r) {
               if (!((masks[r] >> c) & 1)) continue;
@@ -242,7 +268,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
 #pragma unroll
     for (int c = 0; c < MAXC; ++c) {
       if (!((masks[r] >> c) & 1)) continue;
-      const int tile = d.tile_index[rows[r] * 8 + c];
+      const int tile = d.tile_index[rows[r] * 8 + cols[c]];
       T* out = partials + ((int64_t)chunk * d.ntiles + tile) * 256;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
@@ -279,44 +305,52 @@ __global__ __launch_bounds__(256) void k_combine(const PT* __restrict__ partials
 
 int reduce_waves_per_group() { return WAVES; }
 // rows per wave for a given number of column tiles (register budget of one wave per SIMD)
-int reduce_max_rows_per_wave(int prec, int nct) {
-  if (prec == 3) return 4;
-  return nct > 4 ? 5 : 8;
+// (rows, columns) per wave: 8 waves, two per SIMD, 256 registers per lane;
+// the FP32 accumulators of rows x columns tiles take 4 registers each.
+int reduce_shapes(int prec, ReduceShape* out, int max_out) {
+  static const ReduceShape f32[] = {{8, 1}, {8, 2}, {6, 4}, {5, 6}, {4, 8}};
+  static const ReduceShape f64[] = {{4, 1}, {4, 2}, {4, 4}, {2, 8}};
+  const ReduceShape* t = prec == 3 ? f64 : f32;
+  const int n = prec == 3 ? 4 : 5;
+  for (int i = 0; i < n && i < max_out; ++i) out[i] = t[i];
+  return n;
 }
 
-template <int PREC, int MAXR, int MAXR8>
+template <int PREC>
 static hipError_t reduce_dispatch(const void* fields, const ReduceDesc& d, void* partials, hipStream_t s) {
   using T = typename RT<PREC>::T;
-  const size_t lds = (size_t)2 * (d.nfields + 1) * (KS + 16 / sizeof(T)) * sizeof(T);
+  size_t lds = (size_t)2 * (d.nfields + 1) * (KS + 16 / sizeof(T)) * sizeof(T);
+  if (PREC == 1 || PREC == 2) lds += (size_t)4 * (d.nfields + 1) * (KS + 8) * 2;
   dim3 grid((unsigned)d.nchunks, (unsigned)d.ngroups);
   const T* f = reinterpret_cast<const T*>(fields);
   T* p = reinterpret_cast<T*>(partials);
-  if (d.nct <= 1)
-    hipLaunchKernelGGL((k_reduce<PREC, MAXR, 1>), grid, dim3(NTHR), lds, s, f, d, p);
-  else if (d.nct <= 2)
-    hipLaunchKernelGGL((k_reduce<PREC, MAXR, 2>), grid, dim3(NTHR), lds, s, f, d, p);
-  else if (d.nct <= 4)
-    hipLaunchKernelGGL((k_reduce<PREC, MAXR, 4>), grid, dim3(NTHR), lds, s, f, d, p);
-  else if (d.nct <= 8)
-    hipLaunchKernelGGL((k_reduce<PREC, MAXR8, 8>), grid, dim3(NTHR), lds, s, f, d, p);
-  else
-    return hipErrorInvalidValue;
-  return hipGetLastError();
+#define RCASE(R, C)                                                                       \
+  if (d.maxr == R && d.maxcw == C) {                                                      \
+    hipLaunchKernelGGL((k_reduce<PREC, R, C>), grid, dim3(NTHR), lds, s, f, d, p);        \
+    return hipGetLastError();                                                             \
+  }
+  if constexpr (PREC == 3) {
+    RCASE(4, 1) RCASE(4, 2) RCASE(4, 4) RCASE(2, 8)
+  } else {
+    RCASE(8, 1) RCASE(8, 2) RCASE(6, 4) RCASE(5, 6) RCASE(4, 8)
+  }
+#undef RCASE
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_reduce(int prec, const float* fields, const ReduceDesc& d, float* partials, hipStream_t s) {
   if (d.nfields > 128) return hipErrorInvalidValue;
   switch (prec) {
-    case 0: return reduce_dispatch<0, 8, 5>(fields, d, partials, s);
-    case 1: return reduce_dispatch<1, 8, 5>(fields, d, partials, s);
-    case 2: return reduce_dispatch<2, 8, 5>(fields, d, partials, s);
+    case 0: return reduce_dispatch<0>(fields, d, partials, s);
+    case 1: return reduce_dispatch<1>(fields, d, partials, s);
+    case 2: return reduce_dispatch<2>(fields, d, partials, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_reduce_f64(const double* fields, const ReduceDesc& d, double* partials, hipStream_t s) {
   if (d.nfields > 128) return hipErrorInvalidValue;
-  return reduce_dispatch<3, 4, 4>(fields, d, partials, s);
+  return reduce_dispatch<3>(fields, d, partials, s);
 }
 
 hipError_t launch_combine_partials(const void* partials, int is_f64, const ReduceDesc& d, int npairs, int nthirds,

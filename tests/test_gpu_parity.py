@@ -40,7 +40,7 @@ def dev(a, dtype=torch.float32):
 
 # ---------------------------------------------------------------- transforms
 
-@pytest.mark.parametrize("n", [16, 32, 64, 96, 128, 192])
+@pytest.mark.parametrize("n", [16, 32, 64, 96, 128, 192, 256, 384, 512])
 def test_fft_r2c_c2r_against_oracle(n):
     say("fft", n)
     plan = B.Plan(n=n, box=100.0, nbins=1, k0=1.0, dk=1.0)
