@@ -244,6 +244,8 @@ struct bsp_plan_s {
   int32_t* d_err = nullptr;
   int32_t* d_ints = nullptr;  // field_ell / field_tab for the main and precompute passes
   int F = 0;                  // fields of the main pipeline
+  std::vector<int> row_c;     // largest |n_a| kept by each filter table row (tab64 row numbering)
+  std::vector<int> field_c;   // per main-pipeline field
   int32_t *d_field_ell = nullptr, *d_field_tab = nullptr;
   int32_t *d_ones_ell = nullptr, *d_pre_tab = nullptr;  // precompute: all ell 0, table row = index
   // precompute results
@@ -417,6 +419,14 @@ Layout layout(const bsp_plan p) {
   return L;
 }
 
+// Inner columns are one contiguous run (no 2-D sub-block).
+void set1d(PassDesc& d) {
+  d.ncz = d.ncols;
+  d.in_j0 = 0;
+  d.in_js = 0;
+  d.out_js = 0;
+}
+
 bsp_status need_ws(bsp_plan p, size_t bytes) {
   if (!p->ws) return fail(p, BSP_ERR_WORKSPACE, "no workspace set");
   if (p->ws_bytes < bytes) return fail(p, BSP_ERR_WORKSPACE, "workspace smaller than required");
@@ -459,6 +469,7 @@ bsp_status forward_moments(bsp_plan p, const float* grids, int ngrid, int contra
   py.in_off = 0;
   py.out_rows = w;
   py.out_off = c;
+  set1d(py);
   {
     StageTimer t(p, 2);
     HIPCHK(launch_c2c_f32(N, -1, Z, Y, py, nullptr, p->tw32_N, p->stream));
@@ -474,6 +485,7 @@ bsp_status forward_moments(bsp_plan p, const float* grids, int ngrid, int contra
   px.in_off = 0;
   px.out_rows = w;
   px.out_off = c;
+  set1d(px);
   float2* X = Z;  // Z is dead once Y exists
   {
     StageTimer t(p, 3);
@@ -498,17 +510,22 @@ bsp_status forward_moments(bsp_plan p, const float* grids, int ngrid, int contra
 }
 
 // Inverse transforms of filtered compact spectra to real fields on N'.
-// field_ell / field_tab index the filter of each output field.
+// field_ell / field_tab index the filter of each output field; cf[f] is the
+// largest |n_a| the filter of field f keeps. A batch of fields is transformed
+// on the band |n_a| <= c_b of its widest filter, so narrow shells move little data.
 template <typename T>
 bsp_status inverse_fields(bsp_plan p, const cplx_t<T>* src, int64_t src_ell_stride, int nf,
                           const int32_t* d_field_ell, const int32_t* d_field_tab, const T* tables, T* out,
-                          char* scratch, int fb) {
+                          char* scratch, int fb, const std::vector<int>& cf) {
   const int Nr = p->Nr, c = p->c, cz = p->cz, w = 2 * c + 1;
   using V = cplx_t<T>;
   V* Xb = reinterpret_cast<V*>(scratch);
   V* Yb = reinterpret_cast<V*>(scratch + align_up((size_t)fb * Nr * w * cz * sizeof(V)));
   for (int f0 = 0; f0 < nf; f0 += fb) {
     const int nb = std::min(fb, nf - f0);
+    int cb = 0;
+    for (int f = f0; f < f0 + nb; ++f) cb = std::max(cb, cf[f]);
+    const int czb = (cb + 1 + 15) / 16 * 16, wb = 2 * cb + 1;
     FilterDesc fd{};
     fd.src = src;
     fd.src_ell_stride = src_ell_stride;
@@ -517,30 +534,36 @@ bsp_status inverse_fields(bsp_plan p, const cplx_t<T>* src, int64_t src_ell_stri
     fd.field_table = d_field_tab;
     fd.tablen = p->n2max + 1;
     fd.c = c;
+    fd.row0 = c - cb;
     fd.cz = cz;
     fd.field0 = f0;
     PassDesc px{};
     px.nouter = nb;
     px.in_outer = 0;
-    px.out_outer = (int64_t)Nr * w * cz;
+    px.out_outer = (int64_t)Nr * wb * czb;
     px.in_row = (int64_t)w * cz;
-    px.out_row = (int64_t)w * cz;
-    px.ncols = w * cz;
-    px.in_rows = w;
-    px.in_off = c;
+    px.out_row = (int64_t)wb * czb;
+    px.ncols = wb * czb;
+    px.ncz = czb;
+    px.in_j0 = c - cb;
+    px.in_js = cz;
+    px.out_js = czb;
+    px.in_rows = wb;
+    px.in_off = cb;
     px.out_rows = Nr;
     px.out_off = 0;
     PassDesc py{};
     py.nouter = nb * Nr;
-    py.in_outer = (int64_t)w * cz;
-    py.out_outer = (int64_t)Nr * cz;
-    py.in_row = cz;
-    py.out_row = cz;
-    py.ncols = cz;
-    py.in_rows = w;
-    py.in_off = c;
+    py.in_outer = (int64_t)wb * czb;
+    py.out_outer = (int64_t)Nr * czb;
+    py.in_row = czb;
+    py.out_row = czb;
+    py.ncols = czb;
+    py.in_rows = wb;
+    py.in_off = cb;
     py.out_rows = Nr;
     py.out_off = 0;
+    set1d(py);
     if constexpr (sizeof(T) == 4) {
       {
         StageTimer t(p, 5);
@@ -551,12 +574,12 @@ bsp_status inverse_fields(bsp_plan p, const cplx_t<T>* src, int64_t src_ell_stri
         HIPCHK(launch_c2c_f32(Nr, +1, Xb, Yb, py, nullptr, p->tw32_Nr, p->stream));
       }
       StageTimer t(p, 7);
-      HIPCHK(launch_inv_z_f32(Nr, Yb, out + (int64_t)f0 * Nr * Nr * Nr, nb, c + 1, cz, (int64_t)Nr * Nr * cz,
+      HIPCHK(launch_inv_z_f32(Nr, Yb, out + (int64_t)f0 * Nr * Nr * Nr, nb, cb + 1, czb, (int64_t)Nr * Nr * czb,
                               (int64_t)Nr * Nr * Nr, p->tw32_Nr, p->stream));
     } else {
       HIPCHK(launch_c2c_f64(Nr, +1, nullptr, Xb, px, &fd, p->tw64_Nr, p->stream));
       HIPCHK(launch_c2c_f64(Nr, +1, Xb, Yb, py, nullptr, p->tw64_Nr, p->stream));
-      HIPCHK(launch_inv_z_f64(Nr, Yb, out + (int64_t)f0 * Nr * Nr * Nr, nb, c + 1, cz, (int64_t)Nr * Nr * cz,
+      HIPCHK(launch_inv_z_f64(Nr, Yb, out + (int64_t)f0 * Nr * Nr * Nr, nb, cb + 1, czb, (int64_t)Nr * Nr * czb,
                               (int64_t)Nr * Nr * Nr, p->tw64_Nr, p->stream));
     }
   }
@@ -711,12 +734,13 @@ bool build_sn(bsp_plan p) {
 // exact: only triangles with nonzero counts; else every candidate.
 bool build_main(bsp_plan p, bool exact) {
   const int nb = p->nbins, nl = p->nl, P = p->P;
+  // field numbering: D^(l)_b = b * nl + l, M^(l)_a = nl * nb + a * nl + l
   std::vector<std::array<int, 2>> pr;
   std::vector<int> pbin((size_t)nb * nb, -1);
   for (int b2 = 0; b2 < nb; ++b2)
     for (int b3 = 0; b3 <= b2; ++b3) {
       pbin[(size_t)b2 * nb + b3] = (int)pr.size();
-      pr.push_back({b2, b3});
+      pr.push_back({b2 * nl, b3 * nl});
     }
   std::vector<int> pm0((size_t)P * P, -1), pm2((size_t)P * P, -1);
   const int m0 = nl * nb;
@@ -724,21 +748,21 @@ bool build_main(bsp_plan p, bool exact) {
     for (int a = 0; a < P; ++a)
       for (int b = a; b < P; ++b) {
         pm0[(size_t)a * P + b] = pm0[(size_t)b * P + a] = (int)pr.size();
-        pr.push_back({m0 + a, m0 + b});
+        pr.push_back({m0 + a * nl, m0 + b * nl});
       }
     if (nl >= 3)
       for (int a = 0; a < P; ++a)
         for (int b = a; b < P; ++b) {
           pm2[(size_t)a * P + b] = pm2[(size_t)b * P + a] = (int)pr.size();
-          pr.push_back({m0 + P + a, m0 + P + b});
+          pr.push_back({m0 + a * nl + 1, m0 + b * nl + 1});
         }
   }
   std::vector<int> th;
   for (int b1 = 0; b1 < nb; ++b1)
-    for (int li = 0; li < nl; ++li) th.push_back(li * nb + b1);
+    for (int li = 0; li < nl; ++li) th.push_back(b1 * nl + li);
   if (p->modal)
     for (int a = 0; a < P; ++a)
-      for (int li = 0; li < nl; ++li) th.push_back(m0 + li * P + a);
+      for (int li = 0; li < nl; ++li) th.push_back(m0 + a * nl + li);
   const int nth = (int)th.size();
   auto tb = [&](int b1, int li) { return b1 * nl + li; };
   auto tm = [&](int a, int li) { return nb * nl + a * nl + li; };
@@ -936,17 +960,27 @@ bsp_status bsp_plan_create(bsp_plan* out, const bsp_geom* g, const bsp_modal_bas
   p->d_tab32 = upload(p, tab32);
   p->d_tab64 = upload(p, tab64);
   // field metadata: main pipeline fields, then the precompute identity map
+  // main fields: shell fields D^(l)_b at b * nl + l (so consecutive fields
+  // widen with b), then modal fields M^(l)_a at nl * nbins + a * nl + l
+  p->row_c.assign(nrow64, p->c);
+  for (int b = 0; b < p->nbins; ++b) {
+    int cb = 0;
+    while ((int64_t)(cb + 1) * (cb + 1) * 4 < hi[b]) ++cb;  // largest integer with 4 cb^2 < (2 c_b + dk)^2
+    p->row_c[b] = cb;
+  }
   std::vector<int32_t> fe(p->F), ft(p->F);
-  for (int li = 0; li < p->nl; ++li)
-    for (int b = 0; b < p->nbins; ++b) {
-      fe[li * p->nbins + b] = li;
-      ft[li * p->nbins + b] = b;
+  p->field_c.assign(p->F, p->c);
+  for (int b = 0; b < p->nbins; ++b)
+    for (int li = 0; li < p->nl; ++li) {
+      fe[b * p->nl + li] = li;
+      ft[b * p->nl + li] = b;
+      p->field_c[b * p->nl + li] = p->row_c[b];
     }
   if (p->modal)
-    for (int li = 0; li < p->nl; ++li)
-      for (int a = 0; a < p->P; ++a) {
-        fe[p->nl * p->nbins + li * p->P + a] = li;
-        ft[p->nl * p->nbins + li * p->P + a] = p->nbins + a;
+    for (int a = 0; a < p->P; ++a)
+      for (int li = 0; li < p->nl; ++li) {
+        fe[p->nl * p->nbins + a * p->nl + li] = li;
+        ft[p->nl * p->nbins + a * p->nl + li] = p->nbins + a;
       }
   p->d_field_ell = upload(p, fe);
   p->d_field_tab = upload(p, ft);
@@ -1067,6 +1101,7 @@ bsp_status bsp_fft_r2c(bsp_plan p, int32_t n, int32_t batch, const float* in, vo
   py.in_row = py.out_row = h;
   py.ncols = h;
   py.in_rows = py.out_rows = n;
+  set1d(py);
   HIPCHK(launch_c2c_f32(n, -1, out, out, py, nullptr, tw, p->stream));
   PassDesc px{};
   px.nouter = batch;
@@ -1074,6 +1109,7 @@ bsp_status bsp_fft_r2c(bsp_plan p, int32_t n, int32_t batch, const float* in, vo
   px.in_row = px.out_row = (int64_t)n * h;
   px.ncols = n * h;
   px.in_rows = px.out_rows = n;
+  set1d(px);
   HIPCHK(launch_c2c_f32(n, -1, out, out, px, nullptr, tw, p->stream));
   return BSP_OK;
 }
@@ -1096,6 +1132,7 @@ bsp_status bsp_fft_c2r(bsp_plan p, int32_t n, int32_t batch, const void* in_c64,
     px.in_row = px.out_row = (int64_t)n * h;
     px.ncols = n * h;
     px.in_rows = px.out_rows = n;
+    set1d(px);
     HIPCHK(launch_c2c_f32(n, +1, in + (size_t)b * n * n * h, tmp, px, nullptr, tw, p->stream));
     PassDesc py{};
     py.nouter = n;
@@ -1103,6 +1140,7 @@ bsp_status bsp_fft_c2r(bsp_plan p, int32_t n, int32_t batch, const void* in_c64,
     py.in_row = py.out_row = h;
     py.ncols = h;
     py.in_rows = py.out_rows = n;
+    set1d(py);
     HIPCHK(launch_c2c_f32(n, +1, tmp, tmp, py, nullptr, tw, p->stream));
     HIPCHK(launch_inv_z_f32(n, tmp, out + (size_t)b * n * n * n, 1, h, h, 0, 0, tw, p->stream));
   }
@@ -1152,8 +1190,10 @@ bsp_status bsp_filter_fields(bsp_plan p, const void* delta_l, int32_t nfilt, con
   both.insert(both.end(), ft.begin(), ft.end());
   HIPCHK(hipMemcpyAsync(dmeta, both.data(), both.size() * sizeof(int32_t), hipMemcpyHostToDevice, p->stream));
   HIPCHK(hipStreamSynchronize(p->stream));
+  std::vector<int> cf(nfilt);
+  for (int i = 0; i < nfilt; ++i) cf[i] = p->row_c[ft[i]];
   return inverse_fields<float>(p, reinterpret_cast<const float2*>(delta_l), p->spec, nfilt, dmeta, dmeta + nfilt,
-                               p->d_tab32, fields, p->ws + meta, fb);
+                               p->d_tab32, fields, p->ws + meta, fb, cf);
 }
 
 bsp_status bsp_triple_reduce(bsp_plan p, const float* fields, int32_t nfields, int64_t K, const int32_t* pairs,
@@ -1215,7 +1255,8 @@ bsp_status bsp_precompute(bsp_plan p) {
   hipLaunchKernelGGL(k_fill_ones, dim3((unsigned)((p->spec + 255) / 256)), dim3(256), 0, p->stream, ones, p->spec);
   HIPCHK(hipGetLastError());
   // --- triangle counts: I_b for every shell, T[(b2,b3)][b1] over the candidates
-  s = inverse_fields<double>(p, ones, 0, p->nbins, p->d_ones_ell, p->d_pre_tab, p->d_tab64, f64, scr, L.fb64);
+  s = inverse_fields<double>(p, ones, 0, p->nbins, p->d_ones_ell, p->d_pre_tab, p->d_tab64, f64, scr, L.fb64,
+                             std::vector<int>(p->row_c.begin(), p->row_c.begin() + p->nbins));
   if (s != BSP_OK) return s;
   s = run_reduce<double>(p, p->cnt_rp, f64, K, 3, nullptr, T64, scr, scr_bytes, 1.0);
   if (s != BSP_OK) return s;
@@ -1261,7 +1302,8 @@ bsp_status bsp_precompute(bsp_plan p) {
   // --- modal geometry: Gram matrix, Cholesky factor, shot-noise integrals
   if (p->modal) {
     const int nm = p->nmodes;
-    s = inverse_fields<double>(p, ones, 0, p->nU, p->d_ones_ell, p->d_urow, p->d_tab64, f64, scr, L.fb64);
+    s = inverse_fields<double>(p, ones, 0, p->nU, p->d_ones_ell, p->d_urow, p->d_tab64, f64, scr, L.fb64,
+                               std::vector<int>(p->nU, p->c));
     if (s != BSP_OK) return s;
     s = run_reduce<double>(p, p->gram_rp, f64, K, 3, nullptr, T64, scr, scr_bytes, 1.0);
     if (s != BSP_OK) return s;
@@ -1274,7 +1316,8 @@ bsp_status bsp_precompute(bsp_plan p) {
     if (s != BSP_OK) return s;
     p->chol_h.resize((size_t)nm * nm);
     HIPCHK(hipMemcpy(p->chol_h.data(), p->d_L, p->chol_h.size() * sizeof(double), hipMemcpyDeviceToHost));
-    s = inverse_fields<double>(p, ones, 0, 2 * p->P, p->d_ones_ell, p->d_grow, p->d_tab64, f64, scr, L.fb64);
+    s = inverse_fields<double>(p, ones, 0, 2 * p->P, p->d_ones_ell, p->d_grow, p->d_tab64, f64, scr, L.fb64,
+                               std::vector<int>(2 * p->P, p->c));
     if (s != BSP_OK) return s;
     s = run_reduce<double>(p, p->sn_rp, f64, K, 3, nullptr, T64, scr, scr_bytes, 1.0);
     if (s != BSP_OK) return s;
@@ -1332,7 +1375,7 @@ bsp_status estimate_from_spectrum(bsp_plan p, const float2* dl, bsp_precision pr
   char* scr = ws + L.dl + L.fields + L.T + L.small;
   const size_t scr_bytes = p->ws_bytes - (L.dl + L.fields + L.T + L.small);
   bsp_status s = inverse_fields<float>(p, dl, p->spec, p->F, p->d_field_ell, p->d_field_tab, p->d_tab32, fields, scr,
-                                       L.fb);
+                                       L.fb, p->field_c);
   if (s != BSP_OK) return s;
   const float* sc = nullptr;
   if (prec == BSP_FP16X3) {

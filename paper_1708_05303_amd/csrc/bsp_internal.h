@@ -28,7 +28,9 @@ template <typename V, typename T> __device__ __forceinline__ V cscale(V a, T s) 
 struct PassDesc {
   int64_t in_outer, out_outer;   // element stride between outer batches
   int64_t in_row, out_row;       // element stride between consecutive rows of the FFT axis
-  int32_t ncols;                 // contiguous inner columns per row
+  int32_t ncols;                 // inner columns per row
+  int32_t ncz;                   // columns are runs of ncz: col = jj * ncz + kz
+  int32_t in_j0, in_js, out_js;  // input inner offset (jj + in_j0) * in_js + kz, output jj * out_js + kz
   int32_t in_rows, in_off;       // input row r holds FFT index (r - in_off) mod N
   int32_t out_rows, out_off;     // output row r receives FFT index (r - out_off) mod N
   int32_t nouter;
@@ -43,6 +45,7 @@ struct FilterDesc {
   const int32_t* field_table;    // [nfields] table row of each field
   int32_t tablen;                // n2max + 1
   int32_t c;                     // half width of the compact cube
+  int32_t row0;                  // first source row (the batch reads rows row0 .. row0 + in_rows - 1)
   int32_t cz;                    // padded kz extent
   int32_t field0;                // first field of this launch
 };

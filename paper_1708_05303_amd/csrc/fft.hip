@@ -138,22 +138,62 @@ __device__ __forceinline__ void fft_stages(V* __restrict__ buf, const V* __restr
 
 // exponents (x, y, z) of the x-hat product of each LOS field: the empty
 // product, the 6 sorted pairs and the 15 sorted quadruples over {x, y, z}.
-__constant__ int8_t c_los_exp[22][3] = {
+constexpr int8_t c_los_exp[22][3] = {
     {0, 0, 0},
     {2, 0, 0}, {1, 1, 0}, {1, 0, 1}, {0, 2, 0}, {0, 1, 1}, {0, 0, 2},
     {4, 0, 0}, {3, 1, 0}, {3, 0, 1}, {2, 2, 0}, {2, 1, 1}, {2, 0, 2}, {1, 3, 0},
     {1, 2, 1}, {1, 1, 2}, {1, 0, 3}, {0, 4, 0}, {0, 3, 1}, {0, 2, 2}, {0, 1, 3},
     {0, 0, 4}};
 
-template <typename T> __device__ __forceinline__ T ipow(T x, int e) {
-  T r = (T)1;
-  for (int i = 0; i < e; ++i) r *= x;
-  return r;
+template <int E, typename T> __device__ __forceinline__ T ipow(T x) {
+  if constexpr (E == 0) return (T)1;
+  else if constexpr (E == 1) return x;
+  else if constexpr (E == 2) return x * x;
+  else if constexpr (E == 3) return x * x * x;
+  else return (x * x) * (x * x);
+}
+
+template <int F, typename T> __device__ __forceinline__ T los_weight(T hx, T hy, T hz) {
+  return ipow<c_los_exp[F][0]>(hx) * ipow<c_los_exp[F][1]>(hy) * ipow<c_los_exp[F][2]>(hz);
+}
+
+// One packed pair (F0, F0+1) of LOS fields for every line of the block, then
+// the next pair; the field indices are compile-time so the weights unroll.
+template <int F0, int NLOS, typename T, typename V, int N, int NT, int E, int PAD>
+__device__ __forceinline__ void fwd_z_pairs(V* b, const V* tw, int t, const T* rv, const T* hx, const T* hy,
+                                            const T* hz, bool plane, bool valid, V* out_g, int64_t nlines,
+                                            int64_t line, int cout, int zs) {
+  if constexpr (F0 < NLOS) {
+    constexpr bool HAS1 = F0 + 1 < NLOS;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      T w0 = (T)1, w1 = (T)0;
+      if (!plane) {
+        w0 = los_weight<F0>(hx[e], hy[e], hz[e]);
+        if constexpr (HAS1) w1 = los_weight<(HAS1 ? F0 + 1 : 0)>(hx[e], hy[e], hz[e]);
+      }
+      b[t + e * NT] = V{w0 * rv[e], w1 * rv[e]};
+    }
+    __syncthreads();
+    fft_stages<V, N, -1, NT, 0, 1>(b, tw, t);
+    if (valid) {
+      V* o0 = out_g + ((int64_t)F0 * nlines + line) * zs;
+      V* o1 = out_g + ((int64_t)(F0 + 1) * nlines + line) * zs;
+      for (int k = t; k < cout; k += NT) {
+        const V zk = b[k], zm = b[(N - k) % N];
+        o0[k] = V{(zk.x + zm.x) * (T)0.5, (zk.y - zm.y) * (T)0.5};
+        if constexpr (HAS1) o1[k] = V{(zk.y + zm.y) * (T)0.5, (zm.x - zk.x) * (T)0.5};
+      }
+    }
+    __syncthreads();
+    fwd_z_pairs<F0 + 2, NLOS, T, V, N, NT, E, PAD>(b, tw, t, rv, hx, hy, hz, plane, valid, out_g, nlines, line,
+                                                   cout, zs);
+  }
 }
 
 // ---------------------------------------------------------------- fwd_z
 // grid: blockIdx.x -> group of L lines (x*N + y), blockIdx.y -> input grid.
-template <typename T, int N>
+template <typename T, int N, int NLOS>
 __global__ __launch_bounds__(256) void k_fwd_z(const T* __restrict__ in, cplx_t<T>* __restrict__ out,
                                                FwdZDesc d, const cplx_t<T>* __restrict__ twg) {
   using V = cplx_t<T>;
@@ -175,7 +215,7 @@ __global__ __launch_bounds__(256) void k_fwd_z(const T* __restrict__ in, cplx_t<
     scale = (T)((double)N * (double)N * (double)N / d.wsum[0]);
     sub = (T)1;
   }
-  const T* src = in + (int64_t)g * N * N * N + line * N;
+  const T* src = in + (int64_t)g * N * N * N + (valid ? line : 0) * N;
   T rv[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) rv[e] = valid ? src[t + e * NT] * scale - sub : (T)0;
@@ -195,43 +235,24 @@ __global__ __launch_bounds__(256) void k_fwd_z(const T* __restrict__ in, cplx_t<
   }
   __syncthreads();  // twiddles staged
   V* b = buf + ll * PAD;
-  const int npair = (d.nlos + 1) / 2;
-  for (int p = 0; p < npair; ++p) {
-    const int f0 = 2 * p, f1 = 2 * p + 1;
-    const bool has1 = f1 < d.nlos;
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      T w0 = (T)1, w1 = (T)0;
-      if (!d.plane) {
-        w0 = ipow(hx[e], c_los_exp[f0][0]) * ipow(hy[e], c_los_exp[f0][1]) * ipow(hz[e], c_los_exp[f0][2]);
-        if (has1)
-          w1 = ipow(hx[e], c_los_exp[f1][0]) * ipow(hy[e], c_los_exp[f1][1]) * ipow(hz[e], c_los_exp[f1][2]);
-      }
-      b[t + e * NT] = V{w0 * rv[e], w1 * rv[e]};
-    }
-    __syncthreads();
-    fft_stages<V, N, -1, NT, 0, 1>(b, tw, t);
-    if (valid) {
-      V* o0 = out + (((int64_t)g * d.nlos + f0) * nlines + line) * d.zs;
-      V* o1 = out + (((int64_t)g * d.nlos + f1) * nlines + line) * d.zs;
-      for (int k = t; k < d.cout; k += NT) {
-        const V zk = b[k], zm = b[(N - k) % N];
-        o0[k] = V{(zk.x + zm.x) * (T)0.5, (zk.y - zm.y) * (T)0.5};
-        if (has1) o1[k] = V{(zk.y + zm.y) * (T)0.5, (zm.x - zk.x) * (T)0.5};
-      }
-    }
-    __syncthreads();
-  }
+  V* out_g = out + (int64_t)g * NLOS * nlines * d.zs;
+  fwd_z_pairs<0, NLOS, T, V, N, NT, E, PAD>(b, tw, t, rv, hx, hy, hz, d.plane != 0, valid, out_g, nlines, line,
+                                            d.cout, d.zs);
 }
 
 // ---------------------------------------------------------------- c2c
 // grid: blockIdx.x -> column tile of W, blockIdx.y (+ gridDim.y * blockIdx.z) -> outer batch.
+// Inner columns are runs of ncz: column col = jj * ncz + kz reads inner offset
+// (jj + in_j0) * in_js + kz and writes jj * out_js + kz (a sub-block of a 2-D
+// inner layout; 1-D when ncz >= ncols). Every global load of the tile is issued
+// before the LDS writes, so each thread keeps N/NT loads in flight.
 template <typename T, int N, int W, int SIGN, bool FILT>
 __global__ __launch_bounds__(256) void k_c2c(const cplx_t<T>* __restrict__ in, cplx_t<T>* __restrict__ out,
                                              PassDesc p, FilterDesc f, const cplx_t<T>* __restrict__ twg) {
   using V = cplx_t<T>;
   constexpr int NT = 256 / W;
   constexpr int PAD = N + 1;
+  constexpr int E = (N + NT - 1) / NT;
   __shared__ V buf[W * PAD];
   __shared__ V tw[N];
   for (int i = threadIdx.x; i < N; i += 256) tw[i] = twg[i];
@@ -240,50 +261,60 @@ __global__ __launch_bounds__(256) void k_c2c(const cplx_t<T>* __restrict__ in, c
   const int c = threadIdx.x % W, j0 = threadIdx.x / W;
   const int col = blockIdx.x * W + c;
   const bool cv = col < p.ncols;
+  const int jj = cv ? col / p.ncz : 0, kz = cv ? col % p.ncz : 0;
+  const int64_t icol = (int64_t)(jj + p.in_j0) * p.in_js + kz;
+  const int64_t ocol = (int64_t)jj * p.out_js + kz;
   const V* src;
   const T* tab = nullptr;
-  int fny = 0, fnz = 0;
+  int fny = 0;
   bool fz_ok = true;
   if constexpr (FILT) {
     const int field = f.field0 + outer;
-    src = reinterpret_cast<const V*>(f.src) + (int64_t)f.field_ell[field] * f.src_ell_stride;
+    src = reinterpret_cast<const V*>(f.src) + (int64_t)f.field_ell[field] * f.src_ell_stride +
+          (int64_t)f.row0 * p.in_row;
     tab = reinterpret_cast<const T*>(f.tables) + (int64_t)f.field_table[field] * f.tablen;
-    fny = col / f.cz - f.c;
-    fnz = col % f.cz;
-    fz_ok = fnz <= f.c;
+    fny = jj + p.in_j0 - f.c;
+    fz_ok = kz <= f.c;
   } else {
     src = in + (int64_t)outer * p.in_outer;
   }
   V* dst = out + (int64_t)outer * p.out_outer;
-  for (int pos = j0; pos < N; pos += NT) {
-    const int r = (pos + p.in_off) % N;
-    V v = V{(T)0, (T)0};
-    if (cv && r < p.in_rows) {
-      if constexpr (FILT) {
-        if (fz_ok) {
-          const int nx = r - f.c;
-          const int n2 = nx * nx + fny * fny + fnz * fnz;
-          if (n2 < f.tablen) {
+  V v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int pos = j0 + e * NT;
+    v[e] = V{(T)0, (T)0};
+    if ((N % NT == 0 || pos < N) && cv) {
+      const int r = (pos + p.in_off) % N;
+      if (r < p.in_rows) {
+        if constexpr (FILT) {
+          const int nx = r - p.in_off;
+          const int n2 = nx * nx + fny * fny + kz * kz;
+          if (fz_ok && n2 < f.tablen) {
             const T wgt = tab[n2];
             if (wgt != (T)0) {
-              v = src[(int64_t)r * p.in_row + col];
-              v.x *= wgt;
-              v.y *= wgt;
+              const V x = src[(int64_t)r * p.in_row + icol];
+              v[e] = V{x.x * wgt, x.y * wgt};
             }
           }
+        } else {
+          v[e] = src[(int64_t)r * p.in_row + icol];
         }
-      } else {
-        v = src[(int64_t)r * p.in_row + col];
       }
     }
-    buf[c * PAD + pos] = v;
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int pos = j0 + e * NT;
+    if (N % NT == 0 || pos < N) buf[c * PAD + pos] = v[e];
   }
   __syncthreads();
   fft_stages<V, N, SIGN, NT, 0, 1>(buf + c * PAD, tw, j0);
   if (cv) {
+#pragma unroll 4
     for (int r = j0; r < p.out_rows; r += NT) {
       const int pos = (r - p.out_off + N) % N;
-      dst[(int64_t)r * p.out_row + col] = buf[c * PAD + pos];
+      dst[(int64_t)r * p.out_row + ocol] = buf[c * PAD + pos];
     }
   }
 }
@@ -360,7 +391,10 @@ static hipError_t fwd_z_impl(int n, const T* in, cplx_t<T>* out, const FwdZDesc&
     constexpr int NT = (NN >= 8) ? NN / 8 : 1;                                          \
     constexpr int L = 256 / NT;                                                         \
     dim3 grid((unsigned)(((int64_t)NN * NN + L - 1) / L), (unsigned)d.ngrid);           \
-    hipLaunchKernelGGL((k_fwd_z<T, NN>), grid, dim3(L * NT), 0, s, in, out, d, tw);     \
+    if (d.nlos == 1) hipLaunchKernelGGL((k_fwd_z<T, NN, 1>), grid, dim3(L * NT), 0, s, in, out, d, tw);   \
+    else if (d.nlos == 7) hipLaunchKernelGGL((k_fwd_z<T, NN, 7>), grid, dim3(L * NT), 0, s, in, out, d, tw); \
+    else if (d.nlos == 22) hipLaunchKernelGGL((k_fwd_z<T, NN, 22>), grid, dim3(L * NT), 0, s, in, out, d, tw); \
+    else return hipErrorInvalidValue;                                                   \
     return hipGetLastError();                                                           \
   }
   switch (n) { BSP_FOR_SIZES(CASE) }
