@@ -31,35 +31,6 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def stage_bytes_flops(info, geom, nl, F, fb_batches, rp_entries, npairs, K):
-    """Algorithmic bytes (or flops) per launch of each stage, from the sizes of
-    the arrays each pass must read and write once (complex64 = 8 B, float = 4 B)."""
-    N = geom["n"]
-    Nr = geom["nr"]
-    c = info.c
-    w = 2 * c + 1
-    C1 = c + 1
-    G = geom["ngrid"]
-    L = info.nlos
-    s = {}
-    s["assign"] = (geom["np"] * 12 + G * N ** 3 * 4 * 2, "B")  # read particles, read+write grids (atomics)
-    s["fwd_z"] = (G * N ** 3 * 4 + G * L * N * N * C1 * 8, "B")
-    s["fwd_y"] = (G * L * N * N * C1 * 8 + G * L * N * w * C1 * 8, "B")
-    s["fwd_x"] = (G * L * N * w * C1 * 8 + G * L * w * w * C1 * 8, "B")
-    s["los_combine"] = (G * L * w * w * C1 * 8 + nl * w * w * C1 * 8, "B")
-    per_field = {
-        "inv_x_filter": w * w * C1 * 8 + Nr * w * C1 * 8,
-        "inv_y": Nr * w * C1 * 8 + Nr * Nr * C1 * 8,
-        "inv_z": Nr * Nr * C1 * 8 + Nr ** 3 * 4,
-    }
-    for k, v in per_field.items():
-        s[k] = (v * F / fb_batches, "B")
-    # reduction: one FMA per needed (pair, third) entry per point + pair products
-    s["reduce"] = ((2 * rp_entries + npairs) * K, "flop")
-    s["reduce_read"] = (F * K * 4, "B")
-    return s
-
-
 def cpu_baseline(wl, u, pfid, modes, log_fn):
     """The FP64 oracle timed on a bounded sample of one 512^3 mock, extrapolated
     to a full mock: full CIC assignment of both grids; one of the 44 weighted
@@ -210,40 +181,38 @@ def main():
         res["err_mixed_vs_fp32"] = {f"B{2 * li}": rel(o_mix["B"][li], o32["B"][li]) for li in range(nl)}
         # modal coefficients compared in the norm of the inner product (alpha = L^T beta)
         res["err_mixed_vs_fp32"].update({f"alpha{2 * li}": rel(o_mix["al"][li], o32["al"][li]) for li in range(nl)})
-    # roofline of the dominant kernel, from the event timings of the timed region
-    rp = plan  # schedule sizes
-    K = wl.n_reduce ** 3
-    F = plan.info.nfields_binned + plan.info.nfields_modal
-    geom = dict(n=wl.n, nr=wl.n_reduce, ngrid=2 if wl.interlace else 1, np=npart)
-    nmain_entries = ntri * nl + wl.nmodes * (1 + 3 + 6)
-    npairs = wl.nbins * (wl.nbins + 1) // 2 + 2 * (wl.P * (wl.P + 1) // 2)
-    inv_launches = max(stages["inv_z"][1] // args.steps, 1)
-    sb = stage_bytes_flops(plan.info, geom, nl, F, inv_launches, nmain_entries, npairs, K)
+    # roofline of the dominant kernel, from the event timings of the timed region; the
+    # library accumulates each timed launch's algorithmic bytes (flops for the reduction)
     per_stage = {}
-    for name, (ms, nlaunch) in stages.items():
+    for name, (ms, nlaunch, amount) in stages.items():
         if nlaunch == 0:
             continue
         avg = ms / nlaunch * 1e-3
-        amount, unit = sb[name] if name in sb else (None, None)
+        per_launch = amount / nlaunch
         e = {"ms_per_step": ms / args.steps, "launches_per_step": nlaunch / args.steps, "avg_launch_ms": avg * 1e3}
-        if amount is not None:
-            if unit == "B":
-                e["achieved_GBps"] = amount / avg / 1e9
-                e["frac_hbm"] = amount / avg / PEAK_HBM
-            else:
-                e["achieved_TFLOPs"] = amount / avg / 1e12
-                e["frac_mfma"] = amount / avg / PEAK_MFMA[args.prec]
+        if name == "reduce":
+            e["algorithmic_flop_per_launch"] = per_launch
+            e["achieved_TFLOPs"] = per_launch / avg / 1e12
+            e["frac_mfma"] = per_launch / avg / PEAK_MFMA[args.prec]
+        elif amount > 0:
+            e["algorithmic_bytes_per_launch"] = per_launch
+            e["achieved_GBps"] = per_launch / avg / 1e9
+            e["frac_hbm"] = per_launch / avg / PEAK_HBM
         per_stage[name] = e
     res["stages"] = per_stage
     dom = max(per_stage, key=lambda k: per_stage[k]["ms_per_step"])
     d = per_stage[dom]
+    kernel_of = {"assign": "k_assign", "fwd_z": "k_fwd_z", "fwd_y": "k_c2c", "fwd_x": "k_c2c",
+                 "los_combine": "k_los_combine", "inv_x_filter": "k_c2c (filter)", "inv_y": "k_c2c",
+                 "inv_z": "k_inv_z", "reduce": "k_reduce"}
     if dom == "reduce":
-        res["roofline"] = {"kernel": "k_reduce", "bound": "mfma", "achieved": d["achieved_TFLOPs"],
+        res["roofline"] = {"kernel": kernel_of[dom], "stage": dom, "bound": "mfma", "achieved": d["achieved_TFLOPs"],
                            "peak": PEAK_MFMA[args.prec] / 1e12, "unit": "TFLOP/s", "frac": d["frac_mfma"],
                            "traffic": None}
     else:
-        res["roofline"] = {"kernel": dom, "bound": "hbm", "achieved": d["achieved_GBps"], "peak": PEAK_HBM / 1e9,
-                           "unit": "GB/s", "frac": d["frac_hbm"], "traffic": None}
+        res["roofline"] = {"kernel": kernel_of.get(dom, dom), "stage": dom, "bound": "hbm",
+                           "achieved": d["achieved_GBps"], "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                           "frac": d["frac_hbm"], "traffic": None}
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         res["cpu_baseline"] = cpu_baseline(wl, u, pfid, None, log)

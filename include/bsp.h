@@ -222,10 +222,14 @@ bsp_status bsp_bispectrum_field(bsp_plan plan, const float* delta, bsp_precision
  *   9 FP64 combination of the reduction partials.
  * bsp_set_timing(plan, 1) resets and starts, 0 stops (it synchronises).
  * bsp_stage_times synchronises and returns, per stage, the summed event
- * milliseconds since the reset (ms: host double[16]) and the number of timed
- * launches (launches: host int64[16], may be NULL). */
+ * milliseconds since the reset (ms: host double[16]), the number of timed
+ * launches (launches: host int64[16], may be NULL) and the summed algorithmic
+ * amount of the timed launches (amount: host double[16], may be NULL): bytes
+ * each pass must read and write once on the band it keeps (stages 0-7), or
+ * flops of the needed triple products (stage 8: two per needed entry per
+ * point plus one per pair per point). */
 bsp_status bsp_set_timing(bsp_plan plan, int32_t enable);
-bsp_status bsp_stage_times(bsp_plan plan, double* ms, int64_t* launches);
+bsp_status bsp_stage_times(bsp_plan plan, double* ms, int64_t* launches, double* amount);
 
 /* Sample covariance of a batch of coefficient vectors (FP64):
  * cov = (1/(M-1)) sum_m (x_m - mean)(x_m - mean)^T. x: device [m][d], cov:

@@ -106,7 +106,7 @@ def lib():
         "bsp_bispectrum_field": [_vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp],
         "bsp_batch_covariance": [_vp, _i32, _i32, _vp, _vp],
         "bsp_set_timing": [_vp, _i32],
-        "bsp_stage_times": [_vp, _vp, _vp],
+        "bsp_stage_times": [_vp, _vp, _vp, _vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -251,11 +251,13 @@ def bsp_set_timing(plan, enable: bool):
 
 
 def bsp_stage_times(plan):
-    """{stage name: (milliseconds summed, launches)} since bsp_set_timing(plan, True)."""
+    """{stage name: (milliseconds summed, launches, algorithmic bytes or flops summed)}
+    since bsp_set_timing(plan, True)."""
     ms = np.zeros(16)
     n = np.zeros(16, np.int64)
-    _check(lib().bsp_stage_times(plan, ms.ctypes.data, n.ctypes.data), plan)
-    return {STAGES[i]: (float(ms[i]), int(n[i])) for i in range(len(STAGES))}
+    amt = np.zeros(16)
+    _check(lib().bsp_stage_times(plan, ms.ctypes.data, n.ctypes.data, amt.ctypes.data), plan)
+    return {STAGES[i]: (float(ms[i]), int(n[i]), float(amt[i])) for i in range(len(STAGES))}
 
 
 # ---------------------------------------------------------------- convenience

@@ -22,6 +22,7 @@ thread_local std::string g_create_error;
 
 struct ReducePlan {
   int npairs = 0, nthirds = 0, nrt = 0, nct = 0, ngroups = 0, ntiles = 0, maxr = 0, maxcw = 0, nfields = 0;
+  int64_t needed = 0;  // needed (pair, third) entries
   std::vector<int32_t> pair_a, pair_b, third, row_mask, tile_index, tile_rc, wave_rows, wave_cols;
   // device copies (plan-owned or workspace)
   int32_t* d = nullptr;  // one block holding every array
@@ -100,7 +101,10 @@ bool build_reduce(ReducePlan& rp, const std::vector<std::array<int, 2>>& pairs, 
   rp.tile_index.assign(rp.nrt * 8, -1);
   for (int p = 0; p < rp.npairs; ++p)
     for (int t = 0; t < rp.nthirds; ++t)
-      if (need.empty() || need[(size_t)p * rp.nthirds + t]) rp.row_mask[p / 16] |= 1 << (t / 16);
+      if (need.empty() || need[(size_t)p * rp.nthirds + t]) {
+        rp.row_mask[p / 16] |= 1 << (t / 16);
+        rp.needed++;
+      }
   std::vector<int> active;
   for (int r = 0; r < rp.nrt; ++r)
     if (rp.row_mask[r]) {
@@ -273,6 +277,7 @@ struct bsp_plan_s {
   size_t ev_used = 0;
   double stage_ms[16] = {0};
   int64_t stage_n[16] = {0};
+  double stage_amount[16] = {0};
   // generic triple_reduce staging
   ReducePlan call_rp;
   double host_scalar = 0.0;
@@ -305,8 +310,10 @@ struct StageTimer {
   bsp_plan p;
   int stage;
   size_t slot = (size_t)-1;
-  StageTimer(bsp_plan pp, int st) : p(pp), stage(st) {
+  // amount: algorithmic bytes (or flops for the reduction) of the timed launch
+  StageTimer(bsp_plan pp, int st, double amount = 0.0) : p(pp), stage(st) {
     if (!p->timing) return;
+    p->stage_amount[st] += amount;
     if (p->ev_used == p->ev_pool.size()) {
       std::array<hipEvent_t, 2> e{};
       if (hipEventCreate(&e[0]) != hipSuccess || hipEventCreate(&e[1]) != hipSuccess) return;
@@ -453,8 +460,10 @@ bsp_status forward_moments(bsp_plan p, const float* grids, int ngrid, int contra
   fz.plane = p->plane;
   fz.cout = c + 1;
   fz.zs = cz;
+  const double C1 = c + 1.0, W1 = w;
   {
-    StageTimer t(p, 1);
+    // reads the grids, writes c+1 kz modes per line of every LOS field
+    StageTimer t(p, 1, (double)ngrid * N * N * N * 4.0 + (double)ngrid * p->nlos * N * N * C1 * 8.0);
     HIPCHK(launch_fwd_z_f32(N, grids, Z, fz, p->tw32_N, p->stream));
   }
   const int nb = ngrid * p->nlos;
@@ -471,7 +480,7 @@ bsp_status forward_moments(bsp_plan p, const float* grids, int ngrid, int contra
   py.out_off = c;
   set1d(py);
   {
-    StageTimer t(p, 2);
+    StageTimer t(p, 2, (double)nb * N * C1 * 8.0 * (N + W1));
     HIPCHK(launch_c2c_f32(N, -1, Z, Y, py, nullptr, p->tw32_N, p->stream));
   }
   PassDesc px{};
@@ -488,7 +497,7 @@ bsp_status forward_moments(bsp_plan p, const float* grids, int ngrid, int contra
   set1d(px);
   float2* X = Z;  // Z is dead once Y exists
   {
-    StageTimer t(p, 3);
+    StageTimer t(p, 3, (double)nb * W1 * C1 * 8.0 * (N + W1));
     HIPCHK(launch_c2c_f32(N, -1, Y, X, px, nullptr, p->tw32_N, p->stream));
   }
   LosDesc ld{};
@@ -503,7 +512,7 @@ bsp_status forward_moments(bsp_plan p, const float* grids, int ngrid, int contra
   ld.compensate = compensate;
   ld.n2max = p->n2max;
   {
-    StageTimer t(p, 4);
+    StageTimer t(p, 4, (double)W1 * W1 * C1 * 8.0 * (nb + p->nl));
     HIPCHK(launch_los_combine(X, delta_l, ld, p->stream));
   }
   return BSP_OK;
@@ -565,15 +574,17 @@ bsp_status inverse_fields(bsp_plan p, const cplx_t<T>* src, int64_t src_ell_stri
     py.out_off = 0;
     set1d(py);
     if constexpr (sizeof(T) == 4) {
+      // algorithmic bytes: the band |n_a| <= c_b read once, each pass output written once
+      const double cb1 = cb + 1.0, wb1 = wb;
       {
-        StageTimer t(p, 5);
+        StageTimer t(p, 5, nb * (wb1 * wb1 * cb1 + (double)Nr * wb1 * cb1) * 8.0);
         HIPCHK(launch_c2c_f32(Nr, +1, nullptr, Xb, px, &fd, p->tw32_Nr, p->stream));
       }
       {
-        StageTimer t(p, 6);
+        StageTimer t(p, 6, nb * ((double)Nr * wb1 * cb1 + (double)Nr * Nr * cb1) * 8.0);
         HIPCHK(launch_c2c_f32(Nr, +1, Xb, Yb, py, nullptr, p->tw32_Nr, p->stream));
       }
-      StageTimer t(p, 7);
+      StageTimer t(p, 7, nb * ((double)Nr * Nr * cb1 * 8.0 + (double)Nr * Nr * Nr * 4.0));
       HIPCHK(launch_inv_z_f32(Nr, Yb, out + (int64_t)f0 * Nr * Nr * Nr, nb, cb + 1, czb, (int64_t)Nr * Nr * czb,
                               (int64_t)Nr * Nr * Nr, p->tw32_Nr, p->stream));
     } else {
@@ -596,7 +607,8 @@ bsp_status run_reduce(bsp_plan p, const ReducePlan& rp, const T* fields, int64_t
   if (d.ntiles == 0) return BSP_OK;
   if constexpr (sizeof(T) == 4) {
     {
-      StageTimer t(p, 8);
+      // algorithmic flops: one multiply-add per needed (pair, third) entry per point, one multiply per pair
+      StageTimer t(p, 8, (2.0 * rp.needed + rp.npairs) * (double)K);
       HIPCHK(launch_reduce(prec, fields, d, reinterpret_cast<float*>(scratch), p->stream));
     }
     StageTimer t(p, 9);
@@ -1447,7 +1459,7 @@ bsp_status bsp_bispectrum_multipoles(bsp_plan p, const float* ux, const float* u
   HIPCHK(hipMemsetAsync(grids, 0, (size_t)p->ngrid * p->N * p->N * p->N * sizeof(float), p->stream));
   HIPCHK(hipMemsetAsync(wsum, 0, sizeof(double), p->stream));
   {
-    StageTimer t(p, 0);
+    StageTimer t(p, 0, (double)np * 12.0 + (double)p->ngrid * p->N * p->N * p->N * 8.0);
     HIPCHK(launch_assign(ux, uy, uz, w, np, p->N, p->g.window, p->g.interlace, grids, wsum, p->d_err, p->stream));
   }
   HIPCHK(launch_scale_scalar(wsum, 1.0 / p->V, nbar, p->stream));
@@ -1479,11 +1491,12 @@ bsp_status bsp_set_timing(bsp_plan p, int32_t enable) {
   for (int i = 0; i < 16; ++i) {
     p->stage_ms[i] = 0.0;
     p->stage_n[i] = 0;
+    p->stage_amount[i] = 0.0;
   }
   return BSP_OK;
 }
 
-bsp_status bsp_stage_times(bsp_plan p, double* ms, int64_t* launches) {
+bsp_status bsp_stage_times(bsp_plan p, double* ms, int64_t* launches, double* amount) {
   if (!p || !ms) return fail(p, BSP_ERR_ARG, "null argument");
   HIPCHK(hipStreamSynchronize(p->stream));
   for (size_t i = 0; i < p->ev_used; ++i) {
@@ -1496,6 +1509,7 @@ bsp_status bsp_stage_times(bsp_plan p, double* ms, int64_t* launches) {
   for (int i = 0; i < 16; ++i) {
     ms[i] = p->stage_ms[i];
     if (launches) launches[i] = p->stage_n[i];
+    if (amount) amount[i] = p->stage_amount[i];
   }
   return BSP_OK;
 }

@@ -22,7 +22,7 @@
 //   3 FP64 : v_mfma 16x16x4 f64 (geometry precompute)
 // Each workgroup writes its chunk's partial tiles; a second kernel sums the
 // chunks in FP64.
-#include "bsp_internal.h"
+#include "tile_mfma.h"
 
 namespace bsp {
 
@@ -30,28 +30,14 @@ constexpr int WAVES = 8;
 constexpr int NTHR = WAVES * 64;
 constexpr int KS = 64;  // points per LDS stage
 
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
-
-template <int PREC> struct RT;
-template <> struct RT<0> { using T = float; using acc = f32x4; static constexpr int KK = 8; };
-template <> struct RT<1> { using T = float; using acc = f32x4; static constexpr int KK = 8; };
-template <> struct RT<2> { using T = float; using acc = f32x4; static constexpr int KK = 8; };
-template <> struct RT<3> { using T = double; using acc = f64x4; static constexpr int KK = 2; };
-
 template <int PREC, int MAXR, int MAXC>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_reduce(
     const typename RT<PREC>::T* __restrict__ fields, ReduceDesc d, typename RT<PREC>::T* __restrict__ partials) {
-  using T = typename RT<PREC>::T;
-  using ACC = typename RT<PREC>::acc;
-  constexpr bool SPLIT = (PREC == 1 || PREC == 2);
-  using H = typename std::conditional<PREC == 2, _Float16, __bf16>::type;
-  using H8 = typename std::conditional<PREC == 2, f16x8, bf16x8>::type;
-  constexpr int KK = RT<PREC>::KK;      // consecutive points per lane per k-step
-  constexpr int KSTEP = 4 * KK;         // points per k-step
-  constexpr int LDW = KS + (16 / (int)sizeof(T));  // padded FP32/FP64 LDS row
+  using WT = WaveTiles<PREC, MAXR, MAXC, WAVES>;
+  using T = typename WT::T;
+  using H = typename WT::H;
+  constexpr bool SPLIT = WT::SPLIT;
+  constexpr int LDW = KS + (16 / (int)sizeof(T));  // padded full-precision LDS row
   constexpr int LDH = KS + 8;                      // padded row of 16-bit halves (144 bytes)
   constexpr int EPV = 16 / (int)sizeof(T);         // elements per 16-byte vector
   using VEC = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
@@ -70,49 +56,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   if (k1 > d.K) k1 = d.K;
   const int nst = (int)((k1 - k0 + KS - 1) / KS);
 
-  // wave-uniform row tiles, the wave's own column tiles, and the row masks in
-  // the wave's column slots
-  int rows[MAXR], masks[MAXR], cols[MAXC];
-#pragma unroll
-  for (int c = 0; c < MAXC; ++c) cols[c] = d.wave_cols[(group * WAVES + wave) * MAXC + c];
-#pragma unroll
-  for (int r = 0; r < MAXR; ++r) {
-    rows[r] = d.wave_rows[(group * WAVES + wave) * MAXR + r];
-    const int gm = rows[r] >= 0 ? d.row_mask[rows[r]] : 0;
-    int m = 0;
-#pragma unroll
-    for (int c = 0; c < MAXC; ++c)
-      if (cols[c] >= 0 && ((gm >> cols[c]) & 1)) m |= 1 << c;
-    masks[r] = m;
-  }
-  int pa[MAXR], pb[MAXR];
-  float sab[MAXR];
-#pragma unroll
-  for (int r = 0; r < MAXR; ++r) {
-    const int pr = rows[r] * 16 + r16;
-    const int a = rows[r] >= 0 ? d.pair_a[pr] : -1;
-    const int b = rows[r] >= 0 ? d.pair_b[pr] : -1;
-    pa[r] = a >= 0 ? a : d.nfields;
-    pb[r] = b >= 0 ? b : d.nfields;
-    sab[r] = (d.scale && a >= 0 && b >= 0) ? d.scale[a] * d.scale[b] : 1.0f;
-  }
-  int th[MAXC];
-#pragma unroll
-  for (int c = 0; c < MAXC; ++c) {
-    const int s = cols[c] >= 0 ? d.third[cols[c] * 16 + r16] : -1;
-    th[c] = s >= 0 ? s : d.nfields;
-  }
-  int colmask_any = 0;
-#pragma unroll
-  for (int r = 0; r < MAXR; ++r) colmask_any |= masks[r];
-
-  ACC acc[MAXR][MAXC];
-#pragma unroll
-  for (int r = 0; r < MAXR; ++r)
-#pragma unroll
-    for (int c = 0; c < MAXC; ++c)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) acc[r][c][i] = (T)0;
+  WT wt;
+  wt.init(d, group, wave, r16);
 
   // zero rows of both buffers
   for (int i = threadIdx.x; i < LDW; i += blockDim.x) {
@@ -190,93 +135,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const T* base = lds + (int64_t)cur * nrow_lds * LDW;
     const H* hib = ldh + (int64_t)(2 * cur) * nrow_lds * LDH;
     const H* lob = ldh + (int64_t)(2 * cur + 1) * nrow_lds * LDH;
-    if (colmask_any) {
+    if (wt.colmask_any) {
 #pragma unroll 1
-      for (int ks = 0; ks < KS / KSTEP; ++ks) {
-        const int off = ks * KSTEP + q * KK;
-        if constexpr (!SPLIT) {
-          // pair-product fragments of every row tile of this wave
-          T av[MAXR][KK];
-#pragma unroll
-          for (int r = 0; r < MAXR; ++r)
-#pragma unroll
-            for (int j = 0; j < KK; ++j) av[r][j] = base[pa[r] * LDW + off + j] * base[pb[r] * LDW + off + j];
-#pragma unroll
-          for (int c = 0; c < MAXC; ++c) {
-            if (!((colmask_any >> c) & 1)) continue;
-            T bv[KK];
-#pragma unroll
-            for (int j = 0; j < KK; ++j) bv[j] = base[th[c] * LDW + off + j];
-#pragma unroll
-            for (int r = 0; r < MAXR; ++r) {
-              if (!((masks[r] >> c) & 1)) continue;
-#pragma unroll
-              for (int j = 0; j < KK; ++j) {
-                if constexpr (PREC == 0)
-                  acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[r][j], bv[j], acc[r][c], 0, 0, 0);
-                else
-                  acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[r][j], bv[j], acc[r][c], 0, 0, 0);
-              }
-            }
-          }
-        } else {
-          H8 ah[MAXR], al[MAXR];
-#pragma unroll
-          for (int r = 0; r < MAXR; ++r) {
-            if (masks[r] == 0) continue;
-#pragma unroll
-            for (int j = 0; j < KK; ++j) {
-              float x = base[pa[r] * LDW + off + j] * base[pb[r] * LDW + off + j];
-              if constexpr (PREC == 2) x *= sab[r];
-              const H h = (H)x;
-              ah[r][j] = h;
-              al[r][j] = (H)(x - (float)h);
-            }
-          }
-#pragma unroll
-          for (int c = 0; c < MAXC; ++c) {
-            if (!((colmask_any >> c) & 1)) continue;
-            const H8 bh = *reinterpret_cast<const H8*>(hib + th[c] * LDH + off);
-            const H8 bl = *reinterpret_cast<const H8*>(lob + th[c] * LDH + off);
-#pragma unroll
-            for (int r = 0; r < MAXR; ++r) {
-              if (!((masks[r] >> c) & 1)) continue;
-              if constexpr (PREC == 1) {
-                acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[r], bh, acc[r][c], 0, 0, 0);
-                acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[r], bl, acc[r][c], 0, 0, 0);
-                acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[r], bh, acc[r][c], 0, 0, 0);
-              } else {
-                acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[r], bh, acc[r][c], 0, 0, 0);
-                acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah[r], bl, acc[r][c], 0, 0, 0);
-                acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al[r], bh, acc[r][c], 0, 0, 0);
-              }
-            }
-          }
-        }
-      }
+      for (int ks = 0; ks < KS / WT::KSTEP; ++ks) wt.kstep(base, hib, lob, LDW, LDH, ks * WT::KSTEP + q * WT::KK);
     }
     if (st + 1 < nst) sstore(cur ^ 1);
     __syncthreads();
   }
-
-  // partial tiles of this chunk, column r16 of the tile; the f32 16x16x4 and
-  // 16x16x32 results hold rows 4q + i in lane group q, the f64 16x16x4 result
-  // holds rows q + 4i.
-#pragma unroll
-  for (int r = 0; r < MAXR; ++r) {
-    if (masks[r] == 0) continue;
-#pragma unroll
-    for (int c = 0; c < MAXC; ++c) {
-      if (!((masks[r] >> c) & 1)) continue;
-      const int tile = d.tile_index[rows[r] * 8 + cols[c]];
-      T* out = partials + ((int64_t)chunk * d.ntiles + tile) * 256;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int row = (PREC == 3) ? (q + 4 * i) : (4 * q + i);
-        out[row * 16 + r16] = acc[r][c][i];
-      }
-    }
-  }
+  wt.store(d, partials, chunk, q, r16);
 }
 
 // Sum chunk partials in FP64 and scatter to T[pair][third] (T zeroed before).

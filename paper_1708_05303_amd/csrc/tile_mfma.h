@@ -1,0 +1,191 @@
+// Register-resident 16x16 output tiles of the triple-reduction GEMM and the
+// MFMA k-step over one LDS stage, shared by the reduction over materialised
+// fields (reduce.hip) and the reduction fused with the last inverse
+// transform pass (fused.hip).
+//
+// A wave owns up to MAXR row tiles (16 pair products each) and up to MAXC
+// column tiles (16 third fields each) of its own; a row's needed columns are
+// a bit mask over the wave's column slots.
+#pragma once
+
+#include "bsp_internal.h"
+
+namespace bsp {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+// Split eight floats into 16-bit high parts and the 16-bit rounding of their
+// remainders, two values per conversion; each pair is kept as one 32-bit word
+// (int vectors survive control flow without being split into 16-bit pieces).
+template <typename H2>
+__device__ __forceinline__ void split8(const float* x, i32x4& hi, i32x4& lo) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const f32x2 v{x[2 * j], x[2 * j + 1]};
+    const H2 h = __builtin_convertvector(v, H2);
+    const f32x2 hf = __builtin_convertvector(h, f32x2);
+    const f32x2 rem{v.x - hf.x, v.y - hf.y};
+    hi[j] = __builtin_bit_cast(int, h);
+    lo[j] = __builtin_bit_cast(int, __builtin_convertvector(rem, H2));
+  }
+}
+
+// PREC 0 FP32, 1 BF16 hi+lo, 2 FP16 hi+lo, 3 FP64.
+template <int PREC> struct RT;
+template <> struct RT<0> { using T = float; using acc = f32x4; static constexpr int KK = 8; };
+template <> struct RT<1> { using T = float; using acc = f32x4; static constexpr int KK = 8; };
+template <> struct RT<2> { using T = float; using acc = f32x4; static constexpr int KK = 8; };
+template <> struct RT<3> { using T = double; using acc = f64x4; static constexpr int KK = 2; };
+
+template <int PREC, int MAXR, int MAXC, int WAVES> struct WaveTiles {
+  using T = typename RT<PREC>::T;
+  using ACC = typename RT<PREC>::acc;
+  static constexpr bool SPLIT = (PREC == 1 || PREC == 2);
+  using H = typename std::conditional<PREC == 2, _Float16, __bf16>::type;
+  using H8 = typename std::conditional<PREC == 2, f16x8, bf16x8>::type;
+  using H2 = typename std::conditional<PREC == 2, f16x2, bf16x2>::type;
+  static constexpr int KK = RT<PREC>::KK;
+  static constexpr int KSTEP = 4 * KK;
+
+  int rows[MAXR], masks[MAXR], cols[MAXC];
+  int pa[MAXR], pb[MAXR], th[MAXC];
+  float sab[MAXR];
+  int colmask_any;
+  ACC acc[MAXR][MAXC];
+
+  // The tile lists are wave-uniform: reading them through a uniform wave index
+  // keeps them in scalar registers and the block-sparse skips scalar branches.
+  __device__ __forceinline__ void init(const ReduceDesc& d, int group, int wave_in, int r16) {
+    const int wave = __builtin_amdgcn_readfirstlane(wave_in);
+#pragma unroll
+    for (int c = 0; c < MAXC; ++c) cols[c] = d.wave_cols[(group * WAVES + wave) * MAXC + c];
+#pragma unroll
+    for (int r = 0; r < MAXR; ++r) {
+      rows[r] = d.wave_rows[(group * WAVES + wave) * MAXR + r];
+      const int gm = rows[r] >= 0 ? d.row_mask[rows[r]] : 0;
+      int m = 0;
+#pragma unroll
+      for (int c = 0; c < MAXC; ++c)
+        if (cols[c] >= 0 && ((gm >> cols[c]) & 1)) m |= 1 << c;
+      masks[r] = __builtin_amdgcn_readfirstlane(m);
+    }
+#pragma unroll
+    for (int r = 0; r < MAXR; ++r) {
+      const int pr = rows[r] * 16 + r16;
+      const int a = rows[r] >= 0 ? d.pair_a[pr] : -1;
+      const int b = rows[r] >= 0 ? d.pair_b[pr] : -1;
+      pa[r] = a >= 0 ? a : d.nfields;
+      pb[r] = b >= 0 ? b : d.nfields;
+      sab[r] = (d.scale && a >= 0 && b >= 0) ? d.scale[a] * d.scale[b] : 1.0f;
+    }
+#pragma unroll
+    for (int c = 0; c < MAXC; ++c) {
+      const int s = cols[c] >= 0 ? d.third[cols[c] * 16 + r16] : -1;
+      th[c] = s >= 0 ? s : d.nfields;
+    }
+    colmask_any = 0;
+#pragma unroll
+    for (int r = 0; r < MAXR; ++r) colmask_any |= masks[r];
+#pragma unroll
+    for (int r = 0; r < MAXR; ++r)
+#pragma unroll
+      for (int c = 0; c < MAXC; ++c)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[r][c][i] = (T)0;
+  }
+
+  // One k-step of KSTEP points at point offset `off` (= k-step base + q * KK):
+  // base holds the fields at full precision ([row][LDW]); hib / lob their
+  // bf16 or fp16 splits ([row][LDH]) when SPLIT.
+  __device__ __forceinline__ void kstep(const T* __restrict__ base, const H* __restrict__ hib,
+                                        const H* __restrict__ lob, int LDW, int LDH, int off) {
+    if constexpr (!SPLIT) {
+      T av[MAXR][KK];
+#pragma unroll
+      for (int r = 0; r < MAXR; ++r)
+#pragma unroll
+        for (int j = 0; j < KK; ++j) av[r][j] = base[pa[r] * LDW + off + j] * base[pb[r] * LDW + off + j];
+#pragma unroll
+      for (int c = 0; c < MAXC; ++c) {
+        if (!((colmask_any >> c) & 1)) continue;
+        T bv[KK];
+#pragma unroll
+        for (int j = 0; j < KK; ++j) bv[j] = base[th[c] * LDW + off + j];
+#pragma unroll
+        for (int r = 0; r < MAXR; ++r) {
+          if (!((masks[r] >> c) & 1)) continue;
+#pragma unroll
+          for (int j = 0; j < KK; ++j) {
+            if constexpr (PREC == 0)
+              acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[r][j], bv[j], acc[r][c], 0, 0, 0);
+            else
+              acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[r][j], bv[j], acc[r][c], 0, 0, 0);
+          }
+        }
+      }
+    } else {
+      i32x4 ah[MAXR], al[MAXR];
+#pragma unroll
+      for (int r = 0; r < MAXR; ++r) {
+        // empty rows read the zero row: no branch, no value carried across steps
+        float x[KK];
+#pragma unroll
+        for (int j = 0; j < KK; ++j) {
+          x[j] = base[pa[r] * LDW + off + j] * base[pb[r] * LDW + off + j];
+          if constexpr (PREC == 2) x[j] *= sab[r];
+        }
+        split8<H2>(x, ah[r], al[r]);
+      }
+#pragma unroll
+      for (int c = 0; c < MAXC; ++c) {
+        if (!((colmask_any >> c) & 1)) continue;
+        const H8 bh = *reinterpret_cast<const H8*>(hib + th[c] * LDH + off);
+        const H8 bl = *reinterpret_cast<const H8*>(lob + th[c] * LDH + off);
+#pragma unroll
+        for (int r = 0; r < MAXR; ++r) {
+          if (!((masks[r] >> c) & 1)) continue;
+          const H8 a_h = __builtin_bit_cast(H8, ah[r]), a_l = __builtin_bit_cast(H8, al[r]);
+          if constexpr (PREC == 1) {
+            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, bh, acc[r][c], 0, 0, 0);
+            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, bl, acc[r][c], 0, 0, 0);
+            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_l, bh, acc[r][c], 0, 0, 0);
+          } else {
+            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_h, bh, acc[r][c], 0, 0, 0);
+            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_h, bl, acc[r][c], 0, 0, 0);
+            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_l, bh, acc[r][c], 0, 0, 0);
+          }
+        }
+      }
+    }
+  }
+
+  // Partial tiles of one chunk, column r16 of each tile; the f32 16x16x4 and
+  // 16x16x32 results hold rows 4q + i in lane group q, the f64 16x16x4 result
+  // holds rows q + 4i.
+  __device__ __forceinline__ void store(const ReduceDesc& d, T* __restrict__ partials, int chunk, int q, int r16) {
+#pragma unroll
+    for (int r = 0; r < MAXR; ++r) {
+      if (masks[r] == 0) continue;
+#pragma unroll
+      for (int c = 0; c < MAXC; ++c) {
+        if (!((masks[r] >> c) & 1)) continue;
+        const int tile = d.tile_index[rows[r] * 8 + cols[c]];
+        T* out = partials + ((int64_t)chunk * d.ntiles + tile) * 256;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = (PREC == 3) ? (q + 4 * i) : (4 * q + i);
+          out[row * 16 + r16] = acc[r][c][i];
+        }
+      }
+    }
+  }
+};
+
+}  // namespace bsp
