@@ -79,6 +79,57 @@ def cpu_baseline(wl, u, pfid, modes, log_fn):
                        f"{sample_s:.1f} s measured)")}
 
 
+# HIP sources each kernel is built from; a counter summary is used only while
+# these are unchanged since it was taken
+KERNEL_SOURCES = {"k_reduce": ["reduce.hip", "tile_mfma.h", "bsp_internal.h"],
+                  "k_inv_z": ["fft.hip", "bsp_internal.h"], "k_c2c": ["fft.hip", "bsp_internal.h"],
+                  "k_fused": ["fused.hip", "tile_mfma.h", "bsp_internal.h"]}
+
+
+def kernel_source_hash(kernel):
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES.get(kernel, []):
+        with open(os.path.join(ROOT, "paper_1708_05303_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the committed FETCH_SIZE / WRITE_SIZE summary of
+    this kernel and workload (profiles/<kernel>_<workload>_traffic.txt), or None
+    when there is none or the kernel's sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.txt")
+    if kernel not in KERNEL_SOURCES or not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line:
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_sha256_16") != kernel_source_hash(kernel):
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration(nbytes, reps):
+    """Plain device-to-device copies of a known size, for scaling the HBM
+    counters (FETCH_SIZE, WRITE_SIZE) of a profiled run to bytes."""
+    import torch
+    n = nbytes // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "reps": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -88,7 +139,12 @@ def main():
     ap.add_argument("--prec", default="bf16x3", choices=["bf16x3", "fp16x3", "fp32"])
     ap.add_argument("--no-fp32", action="store_true", help="skip timing the FP32 path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run plain device copies of BYTES bytes (counter calibration) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration, 3)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}), flush=True)
@@ -168,7 +224,9 @@ def main():
            "config": {"workload": f"{wl.name}: N={wl.n}^3 (N'={wl.n_reduce}), {wl.nparticles:.0e} particles, "
                                   f"CIC+interlace, varying LOS (observer 1500 Mpc/h), l<=4, {wl.nbins} bins "
                                   f"dk={wl.dk:g}kf, {wl.nmodes} modes P={wl.P}",
-                      "precision": args.prec, "ntri": int(ntri), "particles": int(npart)}}
+                      "precision": args.prec, "ntri": int(ntri), "particles": int(npart),
+                      "reduce_schedule": {k: int(getattr(plan.info, "reduce_" + k)) for k in
+                                          ("pairs", "thirds", "tiles", "groups", "maxr", "maxcw", "needed")}}}
     if not args.no_fp32 and args.prec != "fp32":
         t32, o32, _ = timed(B.BSP_FP32, args.steps, 1, False)
         res["fp32_mocks_per_sec"] = 1.0 / t32
@@ -178,9 +236,13 @@ def main():
         def rel(a, b):
             a, b = a.cpu().numpy(), b.cpu().numpy()
             return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
-        res["err_mixed_vs_fp32"] = {f"B{2 * li}": rel(o_mix["B"][li], o32["B"][li]) for li in range(nl)}
-        # modal coefficients compared in the norm of the inner product (alpha = L^T beta)
-        res["err_mixed_vs_fp32"].update({f"alpha{2 * li}": rel(o_mix["al"][li], o32["al"][li]) for li in range(nl)})
+        err = {f"B{2 * li}": rel(o_mix["B"][li], o32["B"][li]) for li in range(nl)}
+        # modal numerators b_n (the reduction's output); beta = gamma^-1 b inherits the
+        # condition number of the lattice Gram matrix, reported beside it
+        err.update({f"bnum{2 * li}": rel(o_mix["bn"][li], o32["bn"][li]) for li in range(nl)})
+        err.update({f"beta{2 * li}": rel(o_mix["be"][li], o32["be"][li]) for li in range(nl)})
+        res["err_mixed_vs_fp32"] = err
+        res["gram_condition"] = plan.gram_condition()
     # roofline of the dominant kernel, from the event timings of the timed region; the
     # library accumulates each timed launch's algorithmic bytes (flops for the reduction)
     per_stage = {}
@@ -205,14 +267,15 @@ def main():
     kernel_of = {"assign": "k_assign", "fwd_z": "k_fwd_z", "fwd_y": "k_c2c", "fwd_x": "k_c2c",
                  "los_combine": "k_los_combine", "inv_x_filter": "k_c2c (filter)", "inv_y": "k_c2c",
                  "inv_z": "k_inv_z", "reduce": "k_reduce"}
+    traffic = measured_traffic(kernel_of.get(dom, dom).split()[0], wl.name)
     if dom == "reduce":
         res["roofline"] = {"kernel": kernel_of[dom], "stage": dom, "bound": "mfma", "achieved": d["achieved_TFLOPs"],
                            "peak": PEAK_MFMA[args.prec] / 1e12, "unit": "TFLOP/s", "frac": d["frac_mfma"],
-                           "traffic": None}
+                           "traffic": traffic}
     else:
         res["roofline"] = {"kernel": kernel_of.get(dom, dom), "stage": dom, "bound": "hbm",
                            "achieved": d["achieved_GBps"], "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                           "frac": d["frac_hbm"], "traffic": None}
+                           "frac": d["frac_hbm"], "traffic": traffic}
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         res["cpu_baseline"] = cpu_baseline(wl, u, pfid, None, log)

@@ -105,6 +105,14 @@ typedef struct {
   int32_t nfields_modal;  /* nl * P modal fields M^(l)_p */
   int64_t spec_elems;     /* complex elements of one compact cube: (2c+1)^2 cz */
   double count_residual;  /* max |sum I I I / N'^3 - N_tri| over candidates (after bsp_precompute) */
+  /* schedule of the main triple reduction (16 x 16 tiles of pair products x
+     third fields; after bsp_precompute it covers the nonzero triangles only) */
+  int32_t reduce_pairs;   /* pair products F_a F_b */
+  int32_t reduce_thirds;  /* third fields */
+  int32_t reduce_tiles;   /* 16 x 16 tiles computed */
+  int32_t reduce_groups;  /* workgroups per point chunk */
+  int32_t reduce_maxr, reduce_maxcw; /* row tiles, column tiles per wave */
+  int64_t reduce_needed;  /* (pair, third) entries the estimators use */
 } bsp_info;
 
 /* ---------------------------------------------------------------- plans */

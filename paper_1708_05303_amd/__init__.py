@@ -70,7 +70,9 @@ class Info(C.Structure):
     _fields_ = [("c", C.c_int32), ("cz", C.c_int32), ("nl", C.c_int32), ("nlos", C.c_int32),
                 ("ngrid", C.c_int32), ("n2max", C.c_int32), ("ncand", C.c_int32), ("ntri", C.c_int32),
                 ("nfields_binned", C.c_int32), ("nfields_modal", C.c_int32), ("spec_elems", C.c_int64),
-                ("count_residual", C.c_double)]
+                ("count_residual", C.c_double), ("reduce_pairs", C.c_int32), ("reduce_thirds", C.c_int32),
+                ("reduce_tiles", C.c_int32), ("reduce_groups", C.c_int32), ("reduce_maxr", C.c_int32),
+                ("reduce_maxcw", C.c_int32), ("reduce_needed", C.c_int64)]
 
 
 _lib = None
@@ -313,6 +315,15 @@ class Plan:
         self.info = bsp_plan_info(self.handle)
         self.tri, self.counts, self.gamma, self.chol = bsp_geometry(self.handle, self.info.ntri, self.nmodes)
         return self
+
+    def gram_condition(self):
+        """2-norm condition number of the lattice Gram matrix gamma (after
+        precompute; None without a modal basis). beta = gamma^-1 b amplifies
+        relative errors of the numerators b by up to this factor."""
+        if self.gamma is None or self.nmodes == 0:
+            return None
+        import numpy as np
+        return float(np.linalg.cond(np.asarray(self.gamma)))
 
     def sync(self):
         bsp_sync(self.handle)

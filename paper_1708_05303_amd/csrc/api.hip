@@ -346,14 +346,33 @@ T* upload(bsp_plan p, const std::vector<T>& v) {
   return d;
 }
 
-// exp(-2 pi i j / n), j < n, in double precision
+// Twiddles of the length-n LDS transforms in the order the butterfly passes
+// read them: the pass with sub-length ns and radix r (radices 8, 4, 2, 3 taken
+// greedily, as the kernels do) holds W_{ns r}^{q k} = exp(-2 pi i q k n / (ns r) / n)
+// for q = 1 .. r-1, k < ns at entry (ns - 1) + (q - 1) ns + k; n - 1 entries in all.
+int twiddle_exponent(int n, int i) {
+  int ns = 1, m = n;
+  while (m > 1) {
+    const int r = (m % 8 == 0) ? 8 : (m % 4 == 0) ? 4 : (m % 2 == 0) ? 2 : 3;
+    if (i < ns * r - 1) {
+      const int j = i - (ns - 1);
+      return (j / ns + 1) * (j % ns) * (n / (ns * r));
+    }
+    ns *= r;
+    m /= r;
+  }
+  return 0;
+}
+
+// exp(-2 pi i e(j) / n) for the pass-ordered exponents e(j), double precision
 std::vector<double> twiddles(int n) {
   std::vector<double> t(2 * (size_t)n);
-  for (int j = 0; j < n; ++j) {
-    // reduce the angle exactly in integers first
+  for (int jj = 0; jj < n; ++jj) {
+    const int j = twiddle_exponent(n, jj);
+    // the exponent is an exact integer; one rounding of the angle
     const long double a = -2.0L * 3.14159265358979323846264338327950288L * (long double)j / (long double)n;
-    t[2 * j] = (double)cosl(a);
-    t[2 * j + 1] = (double)sinl(a);
+    t[2 * jj] = (double)cosl(a);
+    t[2 * jj + 1] = (double)sinl(a);
   }
   return t;
 }
@@ -1050,6 +1069,14 @@ bsp_status bsp_plan_info(bsp_plan p, bsp_info* info) {
   info->nfields_modal = p->modal ? p->nl * p->P : 0;
   info->spec_elems = p->spec;
   info->count_residual = p->count_residual;
+  const ReducePlan& m = p->main_rp;
+  info->reduce_pairs = m.npairs;
+  info->reduce_thirds = m.nthirds;
+  info->reduce_tiles = m.ntiles;
+  info->reduce_groups = m.ngroups;
+  info->reduce_maxr = m.maxr;
+  info->reduce_maxcw = m.maxcw;
+  info->reduce_needed = m.needed;
   return BSP_OK;
 }
 

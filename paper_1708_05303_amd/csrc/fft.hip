@@ -18,7 +18,10 @@
 //           transform (Hermitian fill of the missing half).
 //
 // Twiddles come from a per-length table exp(-2 pi i j / N) built on the host
-// in double precision and staged through LDS.
+// in double precision, in the order the butterfly passes read them, and
+// staged through LDS.
+// The z-line kernels address their line buffers through a bank swizzle
+// (swz), which keeps the strided stores of the first passes conflict-free.
 #include "bsp_internal.h"
 
 namespace bsp {
@@ -38,6 +41,20 @@ constexpr int nstages(int n) {
     ++c;
   }
   return c;
+}
+
+// LDS twiddles are stored pass by pass: the pass with sub-length NS and radix R
+// reads W_{NS R}^{r k} (r = 1 .. R-1, k < NS) at (NS - 1) + (r - 1) NS + k, so
+// the lanes of a pass read consecutive entries; the host builds the table in
+// this order (N - 1 entries).
+
+// Bank swizzle of a line buffer: XOR of the low five index bits with bits
+// 3..7. A permutation of [0, N) for every supported N (multiples of 32, or
+// below 32), it spreads the stride-R stores of the early passes over distinct
+// banks for 8- and 16-byte elements.
+template <int SWZ> __device__ __forceinline__ int swz(int i) {
+  if constexpr (SWZ) return i ^ ((i >> 3) & 31);
+  else return i;
 }
 
 // multiply by SIGN * i
@@ -95,7 +112,7 @@ template <int R, int SIGN, typename V> __device__ __forceinline__ void butterfly
 // thread index t. All threads of the block must call this (it synchronises).
 // Stage s with sub-length NS: butterfly b reads b + r N/R, twiddles by
 // W_{NS R}^{r (b mod NS)}, and writes (b/NS) NS R + (b mod NS) + r NS.
-template <typename V, int N, int SIGN, int NT, int S, int NS>
+template <typename V, int N, int SIGN, int NT, int S, int NS, int SWZ>
 __device__ __forceinline__ void fft_stages(V* __restrict__ buf, const V* __restrict__ tw, int t) {
   if constexpr (S < nstages(N)) {
     constexpr int R = radix_at(N, S);
@@ -108,11 +125,11 @@ __device__ __forceinline__ void fft_stages(V* __restrict__ buf, const V* __restr
       if ((NB % NT == 0) || b < NB) {
         const int k = b % NS;
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[i][r] = buf[b + r * NB];
+        for (int r = 0; r < R; ++r) v[i][r] = buf[swz<SWZ>(b + r * NB)];
         if constexpr (NS > 1) {
 #pragma unroll
           for (int r = 1; r < R; ++r) {
-            V w = tw[r * k * (N / (NS * R))];
+            V w = tw[(NS - 1) + (r - 1) * NS + k];
             if constexpr (SIGN > 0) w.y = -w.y;
             v[i][r] = cmul(v[i][r], w);
           }
@@ -128,11 +145,11 @@ __device__ __forceinline__ void fft_stages(V* __restrict__ buf, const V* __restr
         const int k = b % NS;
         const int d = (b / NS) * NS * R + k;
 #pragma unroll
-        for (int r = 0; r < R; ++r) buf[d + r * NS] = v[i][r];
+        for (int r = 0; r < R; ++r) buf[swz<SWZ>(d + r * NS)] = v[i][r];
       }
     }
     __syncthreads();
-    fft_stages<V, N, SIGN, NT, S + 1, NS * R>(buf, tw, t);
+    fft_stages<V, N, SIGN, NT, S + 1, NS * R, SWZ>(buf, tw, t);
   }
 }
 
@@ -172,15 +189,15 @@ __device__ __forceinline__ void fwd_z_pairs(V* b, const V* tw, int t, const T* r
         w0 = los_weight<F0>(hx[e], hy[e], hz[e]);
         if constexpr (HAS1) w1 = los_weight<(HAS1 ? F0 + 1 : 0)>(hx[e], hy[e], hz[e]);
       }
-      b[t + e * NT] = V{w0 * rv[e], w1 * rv[e]};
+      b[swz<1>(t + e * NT)] = V{w0 * rv[e], w1 * rv[e]};
     }
     __syncthreads();
-    fft_stages<V, N, -1, NT, 0, 1>(b, tw, t);
+    fft_stages<V, N, -1, NT, 0, 1, 1>(b, tw, t);
     if (valid) {
       V* o0 = out_g + ((int64_t)F0 * nlines + line) * zs;
       V* o1 = out_g + ((int64_t)(F0 + 1) * nlines + line) * zs;
       for (int k = t; k < cout; k += NT) {
-        const V zk = b[k], zm = b[(N - k) % N];
+        const V zk = b[swz<1>(k)], zm = b[swz<1>((N - k) % N)];
         o0[k] = V{(zk.x + zm.x) * (T)0.5, (zk.y - zm.y) * (T)0.5};
         if constexpr (HAS1) o1[k] = V{(zk.y + zm.y) * (T)0.5, (zm.x - zk.x) * (T)0.5};
       }
@@ -309,7 +326,7 @@ __global__ __launch_bounds__(256) void k_c2c(const cplx_t<T>* __restrict__ in, c
     if (N % NT == 0 || pos < N) buf[c * PAD + pos] = v[e];
   }
   __syncthreads();
-  fft_stages<V, N, SIGN, NT, 0, 1>(buf + c * PAD, tw, j0);
+  fft_stages<V, N, SIGN, NT, 0, 1, 0>(buf + c * PAD, tw, j0);
   if (cv) {
 #pragma unroll 4
     for (int r = j0; r < p.out_rows; r += NT) {
@@ -329,6 +346,7 @@ __global__ __launch_bounds__(256) void k_inv_z(const cplx_t<T>* __restrict__ in,
   constexpr int NT = (N >= 8) ? N / 8 : 1;
   constexpr int L = 256 / NT;
   constexpr int PAD = N + 1;
+  constexpr int SW = 1;  // bank swizzle of the line buffers
   __shared__ V buf[L * PAD];
   __shared__ V tw[N];
   for (int i = threadIdx.x; i < N; i += L * NT) tw[i] = twg[i];
@@ -356,16 +374,17 @@ __global__ __launch_bounds__(256) void k_inv_z(const cplx_t<T>* __restrict__ in,
         z = V{A.x + B.y, B.x - A.y};
       }
     }
-    b[pos] = z;
+    b[swz<SW>(pos)] = z;
   }
   __syncthreads();
-  fft_stages<V, N, +1, NT, 0, 1>(b, tw, t);
+  fft_stages<V, N, +1, NT, 0, 1, SW>(b, tw, t);
   if (valid) {
     T* o0 = out + (int64_t)f0 * out_field + line * N;
     T* o1 = out + (int64_t)f1 * out_field + line * N;
     for (int pos = t; pos < N; pos += NT) {
-      o0[pos] = b[pos].x;
-      if (has1) o1[pos] = b[pos].y;
+      const V v = b[swz<SW>(pos)];
+      o0[pos] = v.x;
+      if (has1) o1[pos] = v.y;
     }
   }
 }
