@@ -109,7 +109,7 @@ typedef struct {
      third fields; after bsp_precompute it covers the nonzero triangles only) */
   int32_t reduce_pairs;   /* pair products F_a F_b */
   int32_t reduce_thirds;  /* third fields */
-  int32_t reduce_tiles;   /* 16 x 16 tiles computed */
+  int32_t reduce_tiles;   /* needed 16 x 16 tiles */
   int32_t reduce_groups;  /* workgroups per point chunk */
   int32_t reduce_maxr, reduce_maxcw; /* row tiles, column tiles per wave */
   int64_t reduce_needed;  /* (pair, third) entries the estimators use */

@@ -121,8 +121,8 @@ bool build_reduce(ReducePlan& rp, const std::vector<std::array<int, 2>>& pairs, 
   });
   const int waves = reduce_waves_per_group();
   ReduceShape shapes[8];
-  const int ns = reduce_shapes(prec, shapes, 8);
   int best_groups = 1 << 30;
+  const int ns = reduce_shapes(prec, shapes, 8);
   for (int i = 0; i < ns; ++i) {
     std::vector<int> wr, wc;
     int ng = 0;

@@ -6,7 +6,7 @@
 // standard estimator (its FFT form and the multipole form with D^(l)_k) and the
 // integral of M M M of the modal estimator, both in Sec. 3 of the paper.
 //
-// Structure: a workgroup (8 waves, two per SIMD) owns a chunk of K points and a group of
+// Structure: a workgroup (12 waves, three per SIMD) owns a chunk of K points and a group of
 // row tiles; each wave owns up to MAXR row tiles of 16 pairs and every needed
 // 16-wide column tile of thirds, with the accumulators resident in registers.
 // Points stream through LDS in stages of 64 (double buffered, one
@@ -26,12 +26,12 @@
 
 namespace bsp {
 
-constexpr int WAVES = 8;
+constexpr int WAVES = 12;
 constexpr int NTHR = WAVES * 64;
 constexpr int KS = 64;  // points per LDS stage
 
 template <int PREC, int MAXR, int MAXC>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_reduce(
+__global__ __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_reduce(
     const typename RT<PREC>::T* __restrict__ fields, ReduceDesc d, typename RT<PREC>::T* __restrict__ partials) {
   using WT = WaveTiles<PREC, MAXR, MAXC, WAVES>;
   using T = typename WT::T;
@@ -107,18 +107,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
           const float sc = (PREC == 2 && d.scale) ? d.scale[f] : 1.0f;
           const float x[4] = {stage_regs[v].x * sc, stage_regs[v].y * sc, stage_regs[v].z * sc,
                               stage_regs[v].w * sc};
-          typedef H h4 __attribute__((ext_vector_type(4)));
-          h4 hi, lo;
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const H h = (H)x[j];
-            hi[j] = h;
-            lo[j] = (H)(x[j] - (float)h);
-          }
+          int2 hi, lo;
+          split4<typename WT::H2>(x, hi, lo);
           H* hb = ldh + ((int64_t)(2 * buf) * nrow_lds + f) * LDH + e;
           H* lb = ldh + ((int64_t)(2 * buf + 1) * nrow_lds + f) * LDH + e;
-          *reinterpret_cast<h4*>(hb) = hi;
-          *reinterpret_cast<h4*>(lb) = lo;
+          *reinterpret_cast<int2*>(hb) = hi;
+          *reinterpret_cast<int2*>(lb) = lo;
         }
       }
     }
@@ -170,12 +164,11 @@ __global__ __launch_bounds__(256) void k_combine(const PT* __restrict__ partials
 }
 
 int reduce_waves_per_group() { return WAVES; }
-// rows per wave for a given number of column tiles (register budget of one wave per SIMD)
-// (rows, columns) per wave: 8 waves, two per SIMD, 256 registers per lane;
-// the FP32 accumulators of rows x columns tiles take 4 registers each.
+// (rows, columns) per wave: 12 waves, three per SIMD, 168 registers per lane;
+// the FP32 accumulators of rows x columns tiles take 4 registers each (FP64: 8).
 int reduce_shapes(int prec, ReduceShape* out, int max_out) {
-  static const ReduceShape f32[] = {{8, 1}, {8, 2}, {6, 4}, {5, 6}, {4, 8}};
-  static const ReduceShape f64[] = {{4, 1}, {4, 2}, {4, 4}, {2, 8}};
+  static const ReduceShape f32[] = {{5, 1}, {6, 2}, {4, 4}, {3, 6}, {2, 8}};
+  static const ReduceShape f64[] = {{4, 1}, {4, 2}, {2, 4}, {1, 8}};
   const ReduceShape* t = prec == 3 ? f64 : f32;
   const int n = prec == 3 ? 4 : 5;
   for (int i = 0; i < n && i < max_out; ++i) out[i] = t[i];
@@ -196,9 +189,9 @@ static hipError_t reduce_dispatch(const void* fields, const ReduceDesc& d, void*
     return hipGetLastError();                                                             \
   }
   if constexpr (PREC == 3) {
-    RCASE(4, 1) RCASE(4, 2) RCASE(4, 4) RCASE(2, 8)
+    RCASE(4, 1) RCASE(4, 2) RCASE(2, 4) RCASE(1, 8)
   } else {
-    RCASE(8, 1) RCASE(8, 2) RCASE(6, 4) RCASE(5, 6) RCASE(4, 8)
+    RCASE(5, 1) RCASE(6, 2) RCASE(4, 4) RCASE(3, 6) RCASE(2, 8)
   }
 #undef RCASE
   return hipErrorInvalidValue;

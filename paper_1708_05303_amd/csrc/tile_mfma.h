@@ -44,6 +44,23 @@ template <> struct RT<1> { using T = float; using acc = f32x4; static constexpr 
 template <> struct RT<2> { using T = float; using acc = f32x4; static constexpr int KK = 8; };
 template <> struct RT<3> { using T = double; using acc = f64x4; static constexpr int KK = 2; };
 
+// The same split for four floats (two packed words each).
+template <typename H2>
+__device__ __forceinline__ void split4(const float* x, int2& hi, int2& lo) {
+  int h[2], l[2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const f32x2 v{x[2 * j], x[2 * j + 1]};
+    const H2 hv = __builtin_convertvector(v, H2);
+    const f32x2 hf = __builtin_convertvector(hv, f32x2);
+    const f32x2 rem{v.x - hf.x, v.y - hf.y};
+    h[j] = __builtin_bit_cast(int, hv);
+    l[j] = __builtin_bit_cast(int, __builtin_convertvector(rem, H2));
+  }
+  hi = int2{h[0], h[1]};
+  lo = int2{l[0], l[1]};
+}
+
 template <int PREC, int MAXR, int MAXC, int WAVES> struct WaveTiles {
   using T = typename RT<PREC>::T;
   using ACC = typename RT<PREC>::acc;

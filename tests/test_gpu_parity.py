@@ -213,6 +213,38 @@ def test_triple_reduce_definition(prec, tol, K):
     assert np.sqrt(np.mean(err ** 2)) < tol, np.sqrt(np.mean(err ** 2))
 
 
+@pytest.mark.parametrize("prec,tol", [(0, 1e-5), (1, 1e-4), (2, 1e-5)])
+def test_triple_reduce_many_row_tiles(prec, tol):
+    # 120 fields, every pair a <= b (454 row tiles) and a banded need pattern:
+    # the schedules span several workgroup groups and dense per-wave blocks
+    say("reduce many", prec)
+    r = rng(40 + prec)
+    nf, K = 120, 4096 + 37
+    F = r.standard_normal((nf, K)).astype(np.float32) * r.uniform(0.5, 3e3, (nf, 1)).astype(np.float32)
+    pairs = np.array([(a, b) for a in range(nf) for b in range(a, nf)], np.int32)
+    thirds = np.arange(nf, dtype=np.int32)
+    band = np.abs(pairs[:, :1] + pairs[:, 1:2] - 2 * thirds[None, :]) < 24
+    need = (band & (r.uniform(size=band.shape) < 0.7)).astype(np.uint8)
+    plan = B.Plan(n=16, box=100.0, nbins=1, k0=1.0, dk=1.0, workspace=False)
+    ws = torch.empty(1 << 29, dtype=torch.uint8, device=DEV)
+    B.bsp_set_workspace(plan.handle, ws, ws.numel())
+    T = torch.zeros((len(pairs), len(thirds)), dtype=torch.float64, device=DEV)
+    B.bsp_triple_reduce(plan.handle, dev(F), nf, K, pairs, thirds, need, prec, T)
+    plan.sync()
+    got = T.cpu().numpy()
+    F64 = F.astype(np.float64)
+    P2 = F64[pairs[:, 0]] * F64[pairs[:, 1]]
+    ref = P2 @ F64[thirds].T
+    scale = np.sqrt((P2 ** 2) @ (F64[thirds] ** 2).T)
+    tile_need = np.zeros_like(need)
+    for i in range(0, need.shape[0], 16):
+        for j in range(0, need.shape[1], 16):
+            tile_need[i:i + 16, j:j + 16] = need[i:i + 16, j:j + 16].any()
+    assert np.all(got[tile_need == 0] == 0)
+    err = np.abs(got - ref)[tile_need == 1] / scale[tile_need == 1]
+    assert np.sqrt(np.mean(err ** 2)) < tol and err.max() < 50 * tol, (np.sqrt(np.mean(err ** 2)), err.max())
+
+
 # ---------------------------------------------------------------- geometry precompute
 
 def _plan_c1(**kw):
