@@ -24,11 +24,14 @@ struct ReducePlan {
   int npairs = 0, nthirds = 0, nrt = 0, nct = 0, ngroups = 0, ntiles = 0, maxr = 0, maxcw = 0, nfields = 0;
   int64_t needed = 0;  // needed (pair, third) entries
   std::vector<int32_t> pair_a, pair_b, third, row_mask, tile_index, tile_rc, wave_rows, wave_cols;
+  int npf = 0;                               // fields that are pair factors
+  std::vector<int32_t> pf_row, pair_ra, pair_rb;  // their rows; pairs by row
   // device copies (plan-owned or workspace)
   int32_t* d = nullptr;  // one block holding every array
   size_t words = 0;
   int32_t *d_pair_a = nullptr, *d_pair_b = nullptr, *d_third = nullptr, *d_row_mask = nullptr,
           *d_tile_index = nullptr, *d_tile_rc = nullptr, *d_wave_rows = nullptr, *d_wave_cols = nullptr;
+  int32_t *d_pf_row = nullptr, *d_pair_ra = nullptr, *d_pair_rb = nullptr;
   std::vector<int32_t> packed;
 };
 
@@ -97,6 +100,18 @@ bool build_reduce(ReducePlan& rp, const std::vector<std::array<int, 2>>& pairs, 
     rp.pair_b[i] = pairs[i][1];
   }
   for (int i = 0; i < rp.nthirds; ++i) rp.third[i] = thirds[i];
+  // rows of the pair factors, in order of first use
+  rp.pf_row.assign(std::max(nfields, 1), -1);
+  rp.pair_ra.assign(rp.nrt * 16, -1);
+  rp.pair_rb.assign(rp.nrt * 16, -1);
+  rp.npf = 0;
+  for (int i = 0; i < rp.npairs; ++i)
+    for (int k = 0; k < 2; ++k) {
+      const int f = pairs[i][k];
+      if (f < 0 || f >= nfields) return false;
+      if (rp.pf_row[f] < 0) rp.pf_row[f] = rp.npf++;
+      (k ? rp.pair_rb : rp.pair_ra)[i] = rp.pf_row[f];
+    }
   rp.row_mask.assign(rp.nrt, 0);
   rp.tile_index.assign(rp.nrt * 8, -1);
   for (int p = 0; p < rp.npairs; ++p)
@@ -151,6 +166,9 @@ bool build_reduce(ReducePlan& rp, const std::vector<std::array<int, 2>>& pairs, 
   put(rp.tile_rc.empty() ? std::vector<int32_t>{0} : rp.tile_rc);
   put(rp.wave_rows);
   put(rp.wave_cols);
+  put(rp.pf_row);
+  put(rp.pair_ra);
+  put(rp.pair_rb);
   rp.words = rp.packed.size();
   return true;
 }
@@ -172,6 +190,9 @@ void bind_reduce(ReducePlan& rp, int32_t* dev) {
   rp.d_tile_rc = take(rp.tile_rc.empty() ? 1 : rp.tile_rc.size());
   rp.d_wave_rows = take(rp.wave_rows.size());
   rp.d_wave_cols = take(rp.wave_cols.size());
+  rp.d_pf_row = take(rp.pf_row.size());
+  rp.d_pair_ra = take(rp.pair_ra.size());
+  rp.d_pair_rb = take(rp.pair_rb.size());
 }
 
 // Points per workgroup chunk: about 2048 chunks, at least 1024 points, at most
@@ -208,6 +229,10 @@ ReduceDesc make_desc(const ReducePlan& rp, int64_t K, int64_t field_stride, int 
   d.pair_b = rp.d_pair_b;
   d.third = rp.d_third;
   d.scale = scale;
+  d.npf = rp.npf;
+  d.pf_row = rp.d_pf_row;
+  d.pair_ra = rp.d_pair_ra;
+  d.pair_rb = rp.d_pair_rb;
   return d;
 }
 

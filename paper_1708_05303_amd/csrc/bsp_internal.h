@@ -80,6 +80,11 @@ struct ReduceDesc {
   const int32_t* pair_b;         // [nrt*16]
   const int32_t* third;          // [nct*16] (-1 pad)
   const float* scale;            // [nfields] power-of-two scales (FP16 path) or null
+  // pair factors: split precisions keep full-precision LDS rows for these only
+  int32_t npf;                   // fields that appear as a pair factor
+  const int32_t* pf_row;         // [nfields] full-precision row of each field, -1 if none
+  const int32_t* pair_ra;        // [nrt*16] row of pair_a (-1 pad)
+  const int32_t* pair_rb;        // [nrt*16] row of pair_b (-1 pad)
 };
 
 // ---------------------------------------------------------------- launchers

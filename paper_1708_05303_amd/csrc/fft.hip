@@ -57,6 +57,30 @@ template <int SWZ> __device__ __forceinline__ int swz(int i) {
   else return i;
 }
 
+// Synchronisation between the LDS passes of one transform. When the NT = N/8
+// threads of a z line divide 64 (power-of-two N), a line lives inside one wave;
+// a wave's LDS instructions complete in order, so the passes only need the
+// compiler kept from reordering them (WAVE = 1). Lines of N = 96, 192, 384
+// straddle waves, and column tiles span the whole workgroup: both take a
+// workgroup barrier.
+template <int WAVE> __device__ __forceinline__ void lds_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+// Line groups per workgroup of the z-line kernels: one twiddle staging serves
+// LZ_GROUPS x (256 / (N/8)) lines.
+constexpr int LZ_GROUPS = 8;
+constexpr int FZ_GROUPS = 1;     // line groups per workgroup of the forward z pass
+constexpr int FZ_WAVE_SYNC = 1;  // wave-level sync of the forward z pass (power-of-two N)
+// 1 when the lines of a z-line kernel of length N never straddle waves.
+constexpr int line_in_wave(int n) { return (64 % ((n >= 8) ? n / 8 : 1)) == 0 ? 1 : 0; }
+
 // multiply by SIGN * i
 template <int SIGN, typename V> __device__ __forceinline__ V mul_si(V a) {
   if constexpr (SIGN < 0) return V{a.y, -a.x};
@@ -112,7 +136,7 @@ template <int R, int SIGN, typename V> __device__ __forceinline__ void butterfly
 // thread index t. All threads of the block must call this (it synchronises).
 // Stage s with sub-length NS: butterfly b reads b + r N/R, twiddles by
 // W_{NS R}^{r (b mod NS)}, and writes (b/NS) NS R + (b mod NS) + r NS.
-template <typename V, int N, int SIGN, int NT, int S, int NS, int SWZ>
+template <typename V, int N, int SIGN, int NT, int S, int NS, int SWZ, int WAVE>
 __device__ __forceinline__ void fft_stages(V* __restrict__ buf, const V* __restrict__ tw, int t) {
   if constexpr (S < nstages(N)) {
     constexpr int R = radix_at(N, S);
@@ -137,7 +161,7 @@ __device__ __forceinline__ void fft_stages(V* __restrict__ buf, const V* __restr
         butterfly<R, SIGN>(v[i]);
       }
     }
-    __syncthreads();
+    lds_sync<WAVE>();
 #pragma unroll
     for (int i = 0; i < PER; ++i) {
       const int b = t + i * NT;
@@ -148,8 +172,8 @@ __device__ __forceinline__ void fft_stages(V* __restrict__ buf, const V* __restr
         for (int r = 0; r < R; ++r) buf[swz<SWZ>(d + r * NS)] = v[i][r];
       }
     }
-    __syncthreads();
-    fft_stages<V, N, SIGN, NT, S + 1, NS * R, SWZ>(buf, tw, t);
+    lds_sync<WAVE>();
+    fft_stages<V, N, SIGN, NT, S + 1, NS * R, SWZ, WAVE>(buf, tw, t);
   }
 }
 
@@ -191,8 +215,8 @@ __device__ __forceinline__ void fwd_z_pairs(V* b, const V* tw, int t, const T* r
       }
       b[swz<1>(t + e * NT)] = V{w0 * rv[e], w1 * rv[e]};
     }
-    __syncthreads();
-    fft_stages<V, N, -1, NT, 0, 1, 1>(b, tw, t);
+    lds_sync<FZ_WAVE_SYNC && line_in_wave(N)>();
+    fft_stages<V, N, -1, NT, 0, 1, 1, FZ_WAVE_SYNC && line_in_wave(N)>(b, tw, t);
     if (valid) {
       V* o0 = out_g + ((int64_t)F0 * nlines + line) * zs;
       V* o1 = out_g + ((int64_t)(F0 + 1) * nlines + line) * zs;
@@ -202,14 +226,14 @@ __device__ __forceinline__ void fwd_z_pairs(V* b, const V* tw, int t, const T* r
         if constexpr (HAS1) o1[k] = V{(zk.y + zm.y) * (T)0.5, (zm.x - zk.x) * (T)0.5};
       }
     }
-    __syncthreads();
+    lds_sync<FZ_WAVE_SYNC && line_in_wave(N)>();
     fwd_z_pairs<F0 + 2, NLOS, T, V, N, NT, E, PAD>(b, tw, t, rv, hx, hy, hz, plane, valid, out_g, nlines, line,
                                                    cout, zs);
   }
 }
 
 // ---------------------------------------------------------------- fwd_z
-// grid: blockIdx.x -> group of L lines (x*N + y), blockIdx.y -> input grid.
+// grid: blockIdx.x -> LZ_GROUPS consecutive groups of L lines (line = x*N + y), blockIdx.y -> input grid.
 template <typename T, int N, int NLOS>
 __global__ __launch_bounds__(256) void k_fwd_z(const T* __restrict__ in, cplx_t<T>* __restrict__ out,
                                                FwdZDesc d, const cplx_t<T>* __restrict__ twg) {
@@ -223,38 +247,40 @@ __global__ __launch_bounds__(256) void k_fwd_z(const T* __restrict__ in, cplx_t<
   for (int i = threadIdx.x; i < N; i += L * NT) tw[i] = twg[i];
   const int ll = threadIdx.x / NT, t = threadIdx.x % NT;
   const int64_t nlines = (int64_t)N * N;
-  const int64_t line = (int64_t)blockIdx.x * L + ll;
-  const bool valid = line < nlines;
   const int g = blockIdx.y;
-  const int x = valid ? (int)(line / N) : 0, y = valid ? (int)(line % N) : 0;
   T scale = (T)1, sub = (T)0;
   if (d.contrast) {
     scale = (T)((double)N * (double)N * (double)N / d.wsum[0]);
     sub = (T)1;
   }
-  const T* src = in + (int64_t)g * N * N * N + (valid ? line : 0) * N;
-  T rv[E];
-#pragma unroll
-  for (int e = 0; e < E; ++e) rv[e] = valid ? src[t + e * NT] * scale - sub : (T)0;
-  T hx[E], hy[E], hz[E];
-  if (!d.plane) {
-    const T s = (T)d.shift[g];
-    const T rx = (T)x - s - (T)d.obs[0];
-    const T ry = (T)y - s - (T)d.obs[1];
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const T rz = (T)(t + e * NT) - s - (T)d.obs[2];
-      const T inv = (T)1 / sqrt(rx * rx + ry * ry + rz * rz);
-      hx[e] = rx * inv;
-      hy[e] = ry * inv;
-      hz[e] = rz * inv;
-    }
-  }
   __syncthreads();  // twiddles staged
   V* b = buf + ll * PAD;
   V* out_g = out + (int64_t)g * NLOS * nlines * d.zs;
-  fwd_z_pairs<0, NLOS, T, V, N, NT, E, PAD>(b, tw, t, rv, hx, hy, hz, d.plane != 0, valid, out_g, nlines, line,
-                                            d.cout, d.zs);
+  for (int rep = 0; rep < FZ_GROUPS; ++rep) {
+    const int64_t line = ((int64_t)blockIdx.x * FZ_GROUPS + rep) * L + ll;
+    const bool valid = line < nlines;
+    const int x = valid ? (int)(line / N) : 0, y = valid ? (int)(line % N) : 0;
+    const T* src = in + (int64_t)g * N * N * N + (valid ? line : 0) * N;
+    T rv[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) rv[e] = valid ? src[t + e * NT] * scale - sub : (T)0;
+    T hx[E], hy[E], hz[E];
+    if (!d.plane) {
+      const T s = (T)d.shift[g];
+      const T rx = (T)x - s - (T)d.obs[0];
+      const T ry = (T)y - s - (T)d.obs[1];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const T rz = (T)(t + e * NT) - s - (T)d.obs[2];
+        const T inv = (T)1 / sqrt(rx * rx + ry * ry + rz * rz);
+        hx[e] = rx * inv;
+        hy[e] = ry * inv;
+        hz[e] = rz * inv;
+      }
+    }
+    fwd_z_pairs<0, NLOS, T, V, N, NT, E, PAD>(b, tw, t, rv, hx, hy, hz, d.plane != 0, valid, out_g, nlines, line,
+                                              d.cout, d.zs);
+  }
 }
 
 // ---------------------------------------------------------------- c2c
@@ -326,7 +352,7 @@ __global__ __launch_bounds__(256) void k_c2c(const cplx_t<T>* __restrict__ in, c
     if (N % NT == 0 || pos < N) buf[c * PAD + pos] = v[e];
   }
   __syncthreads();
-  fft_stages<V, N, SIGN, NT, 0, 1, 0>(buf + c * PAD, tw, j0);
+  fft_stages<V, N, SIGN, NT, 0, 1, 0, 0>(buf + c * PAD, tw, j0);
   if (cv) {
 #pragma unroll 4
     for (int r = j0; r < p.out_rows; r += NT) {
@@ -337,7 +363,7 @@ __global__ __launch_bounds__(256) void k_c2c(const cplx_t<T>* __restrict__ in, c
 }
 
 // ---------------------------------------------------------------- inv_z
-// grid: blockIdx.x -> group of L lines, blockIdx.y -> field pair.
+// grid: blockIdx.x -> LZ_GROUPS consecutive groups of L lines, blockIdx.y -> field pair.
 template <typename T, int N>
 __global__ __launch_bounds__(256) void k_inv_z(const cplx_t<T>* __restrict__ in, T* __restrict__ out, int nfields,
                                                int cin, int zs, int64_t in_field, int64_t out_field,
@@ -352,40 +378,44 @@ __global__ __launch_bounds__(256) void k_inv_z(const cplx_t<T>* __restrict__ in,
   for (int i = threadIdx.x; i < N; i += L * NT) tw[i] = twg[i];
   const int ll = threadIdx.x / NT, t = threadIdx.x % NT;
   const int64_t nlines = (int64_t)N * N;
-  const int64_t line = (int64_t)blockIdx.x * L + ll;
-  const bool valid = line < nlines;
   const int f0 = 2 * blockIdx.y, f1 = f0 + 1;
   const bool has1 = f1 < nfields;
-  const V* a = in + (int64_t)f0 * in_field + (valid ? line : 0) * zs;
-  const V* bb = in + (int64_t)f1 * in_field + (valid ? line : 0) * zs;
   V* b = buf + ll * PAD;
-  for (int pos = t; pos < N; pos += NT) {
-    V z = V{(T)0, (T)0};
+  __syncthreads();  // twiddles staged
+  for (int rep = 0; rep < LZ_GROUPS; ++rep) {
+    const int64_t line = ((int64_t)blockIdx.x * LZ_GROUPS + rep) * L + ll;
+    const bool valid = line < nlines;
+    const V* a = in + (int64_t)f0 * in_field + (valid ? line : 0) * zs;
+    const V* bb = in + (int64_t)f1 * in_field + (valid ? line : 0) * zs;
+    for (int pos = t; pos < N; pos += NT) {
+      V z = V{(T)0, (T)0};
+      if (valid) {
+        if (pos < cin) {
+          const V A = a[pos];
+          const V B = has1 ? bb[pos] : V{(T)0, (T)0};
+          if (pos == 0 || 2 * pos == N) z = V{A.x, B.x};
+          else z = V{A.x - B.y, A.y + B.x};
+        } else if (pos > N - cin) {
+          const int k = N - pos;
+          const V A = a[k];
+          const V B = has1 ? bb[k] : V{(T)0, (T)0};
+          z = V{A.x + B.y, B.x - A.y};
+        }
+      }
+      b[swz<SW>(pos)] = z;
+    }
+    lds_sync<line_in_wave(N)>();
+    fft_stages<V, N, +1, NT, 0, 1, SW, line_in_wave(N)>(b, tw, t);
     if (valid) {
-      if (pos < cin) {
-        const V A = a[pos];
-        const V B = has1 ? bb[pos] : V{(T)0, (T)0};
-        if (pos == 0 || 2 * pos == N) z = V{A.x, B.x};
-        else z = V{A.x - B.y, A.y + B.x};
-      } else if (pos > N - cin) {
-        const int k = N - pos;
-        const V A = a[k];
-        const V B = has1 ? bb[k] : V{(T)0, (T)0};
-        z = V{A.x + B.y, B.x - A.y};
+      T* o0 = out + (int64_t)f0 * out_field + line * N;
+      T* o1 = out + (int64_t)f1 * out_field + line * N;
+      for (int pos = t; pos < N; pos += NT) {
+        const V v = b[swz<SW>(pos)];
+        o0[pos] = v.x;
+        if (has1) o1[pos] = v.y;
       }
     }
-    b[swz<SW>(pos)] = z;
-  }
-  __syncthreads();
-  fft_stages<V, N, +1, NT, 0, 1, SW>(b, tw, t);
-  if (valid) {
-    T* o0 = out + (int64_t)f0 * out_field + line * N;
-    T* o1 = out + (int64_t)f1 * out_field + line * N;
-    for (int pos = t; pos < N; pos += NT) {
-      const V v = b[swz<SW>(pos)];
-      o0[pos] = v.x;
-      if (has1) o1[pos] = v.y;
-    }
+    lds_sync<line_in_wave(N)>();  // the next line reuses the buffer
   }
 }
 
@@ -409,7 +439,7 @@ static hipError_t fwd_z_impl(int n, const T* in, cplx_t<T>* out, const FwdZDesc&
   case NN: {                                                                            \
     constexpr int NT = (NN >= 8) ? NN / 8 : 1;                                          \
     constexpr int L = 256 / NT;                                                         \
-    dim3 grid((unsigned)(((int64_t)NN * NN + L - 1) / L), (unsigned)d.ngrid);           \
+    dim3 grid((unsigned)(((int64_t)NN * NN + L * FZ_GROUPS - 1) / (L * FZ_GROUPS)), (unsigned)d.ngrid); \
     if (d.nlos == 1) hipLaunchKernelGGL((k_fwd_z<T, NN, 1>), grid, dim3(L * NT), 0, s, in, out, d, tw);   \
     else if (d.nlos == 7) hipLaunchKernelGGL((k_fwd_z<T, NN, 7>), grid, dim3(L * NT), 0, s, in, out, d, tw); \
     else if (d.nlos == 22) hipLaunchKernelGGL((k_fwd_z<T, NN, 22>), grid, dim3(L * NT), 0, s, in, out, d, tw); \
@@ -450,7 +480,7 @@ static hipError_t inv_z_impl(int n, const cplx_t<T>* in, T* out, int nfields, in
   case NN: {                                                                                      \
     constexpr int NT = (NN >= 8) ? NN / 8 : 1;                                                    \
     constexpr int L = 256 / NT;                                                                   \
-    dim3 grid((unsigned)(((int64_t)NN * NN + L - 1) / L), (unsigned)((nfields + 1) / 2));         \
+    dim3 grid((unsigned)(((int64_t)NN * NN + L * LZ_GROUPS - 1) / (L * LZ_GROUPS)), (unsigned)((nfields + 1) / 2)); \
     hipLaunchKernelGGL((k_inv_z<T, NN>), grid, dim3(L * NT), 0, s, in, out, nfields, cin, zs,     \
                        in_field, out_field, tw);                                                  \
     return hipGetLastError();                                                                     \

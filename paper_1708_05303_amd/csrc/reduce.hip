@@ -28,9 +28,18 @@ namespace bsp {
 
 constexpr int WAVES = 12;
 constexpr int NTHR = WAVES * 64;
-constexpr int KS = 64;  // points per LDS stage
+// LDS bytes of one workgroup for KS points per stage (two stage buffers).
+template <int PREC, int KS>
+size_t reduce_lds_bytes(const ReduceDesc& d) {
+  constexpr bool SPLIT = (PREC == 1 || PREC == 2);
+  const size_t elem = PREC == 3 ? 8 : 4;
+  const size_t nfull = (SPLIT ? d.npf : d.nfields) + 1;
+  size_t b = 2 * nfull * (KS + 16 / elem) * elem;
+  if (SPLIT) b += (size_t)4 * (d.nfields + 1) * (KS + 8) * 2;
+  return b;
+}
 
-template <int PREC, int MAXR, int MAXC>
+template <int PREC, int MAXR, int MAXC, int KS>
 __global__ __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_reduce(
     const typename RT<PREC>::T* __restrict__ fields, ReduceDesc d, typename RT<PREC>::T* __restrict__ partials) {
   using WT = WaveTiles<PREC, MAXR, MAXC, WAVES>;
@@ -38,15 +47,19 @@ __global__ __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
   using H = typename WT::H;
   constexpr bool SPLIT = WT::SPLIT;
   constexpr int LDW = KS + (16 / (int)sizeof(T));  // padded full-precision LDS row
-  constexpr int LDH = KS + 8;                      // padded row of 16-bit halves (144 bytes)
+  constexpr int LDH = KS + 8;                      // padded row of 16-bit halves
   constexpr int EPV = 16 / (int)sizeof(T);         // elements per 16-byte vector
   using VEC = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
   constexpr int MAXV = (128 * KS / EPV + NTHR - 1) / NTHR;  // vectors per thread per stage (<= 128 fields)
 
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int nrow_lds = d.nfields + 1;  // the last row stays zero
+  // full-precision rows: the pair factors (split precisions: thirds come from the
+  // hi / lo rows) or every field; the last row stays zero
+  const int nfull = SPLIT ? d.npf : d.nfields;
+  const int nrow_lds = nfull + 1;
+  const int nrow_h = d.nfields + 1;
   T* lds = reinterpret_cast<T*>(smem_raw);
-  // split copies: [buffer][hi | lo][row][LDH], written once per stage by the whole workgroup
+  // split copies: [buffer][hi | lo][field][LDH], written once per stage by the whole workgroup
   H* ldh = reinterpret_cast<H*>(smem_raw + (size_t)2 * nrow_lds * LDW * sizeof(T));
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int q = lane >> 4, r16 = lane & 15;
@@ -61,12 +74,12 @@ __global__ __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
 
   // zero rows of both buffers
   for (int i = threadIdx.x; i < LDW; i += blockDim.x) {
-    lds[(int64_t)d.nfields * LDW + i] = (T)0;
-    lds[(int64_t)(nrow_lds + d.nfields) * LDW + i] = (T)0;
+    lds[(int64_t)nfull * LDW + i] = (T)0;
+    lds[(int64_t)(nrow_lds + nfull) * LDW + i] = (T)0;
   }
   if constexpr (SPLIT) {
     for (int i = threadIdx.x; i < LDH; i += blockDim.x)
-      for (int b = 0; b < 4; ++b) ldh[((int64_t)b * nrow_lds + d.nfields) * LDH + i] = (H)0.0f;
+      for (int b = 0; b < 4; ++b) ldh[((int64_t)b * nrow_h + d.nfields) * LDH + i] = (H)0.0f;
   }
 
   const int nvec = d.nfields * (KS / EPV);
@@ -94,6 +107,14 @@ __global__ __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
       stage_regs[v] = val;
     }
   };
+  // full-precision row of each staged vector's field (constant per thread)
+  int frow[MAXV];
+#pragma unroll
+  for (int v = 0; v < MAXV; ++v) {
+    const int vi = threadIdx.x + v * NTHR;
+    const int f = vi < nvec ? vi / (KS / EPV) : 0;
+    frow[v] = SPLIT ? d.pf_row[f] : f;
+  }
   auto sstore = [&](int buf) {
     T* base = lds + (int64_t)buf * nrow_lds * LDW;
 #pragma unroll
@@ -101,7 +122,7 @@ __global__ __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
       const int vi = threadIdx.x + v * NTHR;
       if (vi < nvec) {
         const int f = vi / (KS / EPV), e = (vi % (KS / EPV)) * EPV;
-        *reinterpret_cast<VEC*>(base + (int64_t)f * LDW + e) = stage_regs[v];
+        if (frow[v] >= 0) *reinterpret_cast<VEC*>(base + (int64_t)frow[v] * LDW + e) = stage_regs[v];
         if constexpr (SPLIT) {
           // round-to-nearest-even split x = hi + lo of the (scaled) value, once per workgroup
           const float sc = (PREC == 2 && d.scale) ? d.scale[f] : 1.0f;
@@ -109,8 +130,8 @@ __global__ __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
                               stage_regs[v].w * sc};
           int2 hi, lo;
           split4<typename WT::H2>(x, hi, lo);
-          H* hb = ldh + ((int64_t)(2 * buf) * nrow_lds + f) * LDH + e;
-          H* lb = ldh + ((int64_t)(2 * buf + 1) * nrow_lds + f) * LDH + e;
+          H* hb = ldh + ((int64_t)(2 * buf) * nrow_h + f) * LDH + e;
+          H* lb = ldh + ((int64_t)(2 * buf + 1) * nrow_h + f) * LDH + e;
           *reinterpret_cast<int2*>(hb) = hi;
           *reinterpret_cast<int2*>(lb) = lo;
         }
@@ -127,8 +148,8 @@ __global__ __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
     const int cur = st & 1;
     if (st + 1 < nst) gload(st + 1);
     const T* base = lds + (int64_t)cur * nrow_lds * LDW;
-    const H* hib = ldh + (int64_t)(2 * cur) * nrow_lds * LDH;
-    const H* lob = ldh + (int64_t)(2 * cur + 1) * nrow_lds * LDH;
+    const H* hib = ldh + (int64_t)(2 * cur) * nrow_h * LDH;
+    const H* lob = ldh + (int64_t)(2 * cur + 1) * nrow_h * LDH;
     if (wt.colmask_any) {
 #pragma unroll 1
       for (int ks = 0; ks < KS / WT::KSTEP; ++ks) wt.kstep(base, hib, lob, LDW, LDH, ks * WT::KSTEP + q * WT::KK);
@@ -175,17 +196,16 @@ int reduce_shapes(int prec, ReduceShape* out, int max_out) {
   return n;
 }
 
-template <int PREC>
-static hipError_t reduce_dispatch(const void* fields, const ReduceDesc& d, void* partials, hipStream_t s) {
+template <int PREC, int KS>
+static hipError_t reduce_dispatch_ks(const void* fields, const ReduceDesc& d, void* partials, hipStream_t s) {
   using T = typename RT<PREC>::T;
-  size_t lds = (size_t)2 * (d.nfields + 1) * (KS + 16 / sizeof(T)) * sizeof(T);
-  if (PREC == 1 || PREC == 2) lds += (size_t)4 * (d.nfields + 1) * (KS + 8) * 2;
+  const size_t lds = reduce_lds_bytes<PREC, KS>(d);
   dim3 grid((unsigned)d.nchunks, (unsigned)d.ngroups);
   const T* f = reinterpret_cast<const T*>(fields);
   T* p = reinterpret_cast<T*>(partials);
 #define RCASE(R, C)                                                                       \
   if (d.maxr == R && d.maxcw == C) {                                                      \
-    hipLaunchKernelGGL((k_reduce<PREC, R, C>), grid, dim3(NTHR), lds, s, f, d, p);        \
+    hipLaunchKernelGGL((k_reduce<PREC, R, C, KS>), grid, dim3(NTHR), lds, s, f, d, p);    \
     return hipGetLastError();                                                             \
   }
   if constexpr (PREC == 3) {
@@ -195,6 +215,16 @@ static hipError_t reduce_dispatch(const void* fields, const ReduceDesc& d, void*
   }
 #undef RCASE
   return hipErrorInvalidValue;
+}
+
+constexpr size_t LDS_LIMIT = 160 * 1024;
+
+template <int PREC>
+static hipError_t reduce_dispatch(const void* fields, const ReduceDesc& d, void* partials, hipStream_t s) {
+  // 96-point stages (fewer barriers) need more staging registers than the
+  // 168-register budget of three waves per SIMD leaves: 64 points throughout
+  if (reduce_lds_bytes<PREC, 64>(d) > LDS_LIMIT) return hipErrorInvalidValue;
+  return reduce_dispatch_ks<PREC, 64>(fields, d, partials, s);
 }
 
 hipError_t launch_reduce(int prec, const float* fields, const ReduceDesc& d, float* partials, hipStream_t s) {

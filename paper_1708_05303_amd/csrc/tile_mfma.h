@@ -93,14 +93,20 @@ template <int PREC, int MAXR, int MAXC, int WAVES> struct WaveTiles {
         if (cols[c] >= 0 && ((gm >> cols[c]) & 1)) m |= 1 << c;
       masks[r] = __builtin_amdgcn_readfirstlane(m);
     }
+    // pair factors index the full-precision rows: only the pair-factor fields
+    // (row npf stays zero) when SPLIT, every field (row nfields zero) otherwise
+    const int32_t* ra = SPLIT ? d.pair_ra : d.pair_a;
+    const int32_t* rb = SPLIT ? d.pair_rb : d.pair_b;
+    const int zrow = SPLIT ? d.npf : d.nfields;
 #pragma unroll
     for (int r = 0; r < MAXR; ++r) {
       const int pr = rows[r] * 16 + r16;
-      const int a = rows[r] >= 0 ? d.pair_a[pr] : -1;
-      const int b = rows[r] >= 0 ? d.pair_b[pr] : -1;
-      pa[r] = a >= 0 ? a : d.nfields;
-      pb[r] = b >= 0 ? b : d.nfields;
-      sab[r] = (d.scale && a >= 0 && b >= 0) ? d.scale[a] * d.scale[b] : 1.0f;
+      const int a = rows[r] >= 0 ? ra[pr] : -1;
+      const int b = rows[r] >= 0 ? rb[pr] : -1;
+      pa[r] = a >= 0 ? a : zrow;
+      pb[r] = b >= 0 ? b : zrow;
+      const int fa = rows[r] >= 0 ? d.pair_a[pr] : -1, fb = rows[r] >= 0 ? d.pair_b[pr] : -1;
+      sab[r] = (d.scale && fa >= 0 && fb >= 0) ? d.scale[fa] * d.scale[fb] : 1.0f;
     }
 #pragma unroll
     for (int c = 0; c < MAXC; ++c) {
