@@ -1,0 +1,131 @@
+"""Parity at the bench configuration (512^3, varying line of sight, l <= 4,
+30 shells of 5 k_f, 100 modes with P = 8), in the launch configuration the
+bench times, on outputs the FP64 oracle can compute one by one.
+
+The input is a seeded random contrast field delta(x) on 512^3 handed to
+bsp_bispectrum_field (LOS-weighted forward transforms, Legendre moments,
+shell and modal filters, inverse transforms, triple reduction, FP64
+normalisation). The oracle builds delta^(0,2,4)(n) from the same field and
+evaluates, for a few triangles, the exact triangle count and
+T^l = sum_x D^l_b1 D^0_b2 D^0_b3, and, for a few modes, the monopole modal
+numerator <M_p M_r M_s>. Differences are measured against the larger of the
+sum itself and the scale of the summed terms, sqrt(sum_x (summand)^2): a sum
+of 1.3e8 terms of either sign is only defined to that scale times the working
+precision, and a coherent sum (smooth low-k fields) to its own size. Bounds: 5e-5 for the
+FP32 path (one sampled output carries the FP32 rounding of six 512-point
+transform passes of each of its three fields, about 1e-6 each, correlated
+through the spectra; the normwise 1e-5 over whole output families is checked at
+the smaller sizes), 1e-3 (the mixed-precision target on B_l) for bf16 hi+lo
+products.
+"""
+import math
+import sys
+import time
+
+import numpy as np
+import pytest
+
+import oracle as O
+from synth import catalog as C
+from tests.gpu_helpers import pfid_table
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1708_05303_amd as B  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def say(*a):
+    print("[full]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def full_case():
+    t0 = time.time()
+    wl = C.workload("c3_512")
+    n = wl.n
+    obs = C.observer_grid_units(wl)
+    n2len = 3 * ((wl.nbins + 1) * int(wl.dk) + int(wl.k0) + 2) ** 2
+    pf = pfid_table(wl, n2len)
+    plan = B.Plan(n=n, box=wl.box, nbins=wl.nbins, k0=wl.k0, dk=wl.dk, lmax=4, window=1, compensate=1,
+                  interlace=1, los=1, observer=obs, P=wl.P, nmodes=wl.nmodes, pfid=pf)
+    plan.precompute()
+    say("plan", time.time() - t0)
+    d32 = np.random.Generator(np.random.PCG64(5120)).standard_normal((n, n, n), dtype=np.float32)
+    dd = torch.as_tensor(d32).to(DEV)
+    info = plan.info
+    got = {}
+    for prec in (B.BSP_FP32, B.BSP_BF16X3):
+        Bt = torch.zeros((info.nl, info.ntri), dtype=torch.float64, device=DEV)
+        bn = torch.zeros((info.nl, wl.nmodes), dtype=torch.float64, device=DEV)
+        B.bsp_bispectrum_field(plan.handle, dd, prec, Bt, None, bn, None, None)
+        plan.sync()
+        got[prec] = (Bt.cpu().numpy(), bn.cpu().numpy())
+    tri, counts = plan.tri.copy(), plan.counts.copy()
+    del dd
+    plan.close()
+    torch.cuda.empty_cache()
+    say("gpu", time.time() - t0)
+    spec = O.spectrum_from_field([d32.astype(np.float64)], [0.0], n, 4, obs, None)
+    del d32
+    say("oracle spectrum", time.time() - t0)
+    return wl, pf, tri, counts, got, spec
+
+
+def _sample_triangles(tri):
+    # the largest, a middle and a small closed triangle
+    want = [tuple(tri[-1]), tuple(tri[len(tri) // 2]), tuple(tri[3])]
+    idx = [int(np.nonzero((tri == np.array(t)).all(1))[0][0]) for t in want]
+    return idx
+
+
+def test_full_size_triangle_counts_and_binned(full_case):
+    wl, pf, tri, counts, got, spec = full_case
+    n = wl.n
+    bins = O.bin_of_n2(O.n2_grid_half(n), wl.k0, wl.dk, wl.nbins)
+    norm_base = wl.box ** 6 / (float(n) ** 9 * float(n) ** 3)
+    for i in _sample_triangles(tri):
+        b1, b2, b3 = (int(v) for v in tri[i])
+        say("triangle", b1, b2, b3)
+        # exact count: sum_x I_b1 I_b2 I_b3 / N'^3 from FP64 indicator fields
+        ones = np.ones(bins.shape)
+        I = [O.shell_field(ones, bins == b, n).ravel() for b in (b1, b2, b3)]
+        cnt = float(np.dot(I[0] * I[1], I[2])) / float(n) ** 3
+        del I, ones
+        assert abs(cnt - round(cnt)) < 1e-3 and int(round(cnt)) == int(counts[i]), (cnt, counts[i])
+        pair = O.shell_field(spec[0], bins == b2, n).ravel() * O.shell_field(spec[0], bins == b3, n).ravel()
+        norm = norm_base / float(counts[i])
+        for li in range(3):
+            D1 = O.shell_field(spec[li], bins == b1, n).ravel()
+            Tref = float(np.dot(D1, pair))
+            scale = math.sqrt(float(np.dot(D1 * D1, pair * pair)))
+            for prec, tol in ((B.BSP_FP32, 5e-5), (B.BSP_BF16X3, 1e-3)):
+                e = abs(got[prec][0][li, i] / norm - Tref) / max(scale, abs(Tref))
+                say("  l", 2 * li, "prec", prec, "scaled err", e, "rel err", abs(got[prec][0][li, i] / norm / Tref - 1))
+                assert e < tol, (b1, b2, b3, li, prec, e)
+
+
+def test_full_size_modal_numerators(full_case):
+    wl, pf, tri, counts, got, spec = full_case
+    n = wl.n
+    kmin = wl.k0 - 0.5 * wl.dk
+    kmax = wl.k0 + (wl.nbins - 0.5) * wl.dk
+    kf = 2 * math.pi / wl.box
+    M = O.modal_fields(spec[0], n, n, wl.P, kmin, kmax, kf, pf)
+    modes = O.modal_modes(wl.P, wl.nmodes)
+    K = float(n) ** 3
+    for m in (0, 41, wl.nmodes - 1):
+        p, r, s = (int(v) for v in modes[m])
+        prod = M[p] * M[r]
+        ref = float(np.dot(prod, M[s])) / K
+        scale = math.sqrt(float(np.dot(prod * prod, M[s] * M[s]))) / K
+        for prec, tol in ((B.BSP_FP32, 5e-5), (B.BSP_BF16X3, 1e-3)):
+            e = abs(got[prec][1][0, m] - ref) / max(scale, abs(ref))
+            say("mode", m, (p, r, s), "prec", prec, "scaled err", e, "rel err", abs(got[prec][1][0, m] / ref - 1))
+            assert e < tol, (m, prec, e)
