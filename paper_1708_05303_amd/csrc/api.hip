@@ -196,10 +196,14 @@ void bind_reduce(ReducePlan& rp, int32_t* dev) {
 }
 
 // Points per workgroup chunk: about 2048 chunks, at least 1024 points, at most
-// 16384 (FP32 accumulation) or 65536 (split products, FP64). Independent of the
-// schedule so that partial storage only grows with the number of tiles.
+// 16384 (FP32), 8192 (bf16 / fp16 hi+lo) or 65536 (FP64). The register
+// accumulators of the 16-bit MFMAs lose accuracy with the number of k-steps
+// they sum (measured at 512^3: 65536-point chunks leave about 1e-4 of the
+// summed-term scale, 8192-point chunks 3e-5), so their chunks are short and
+// the FP64 combination takes over. Independent of the schedule so that
+// partial storage only grows with the number of tiles.
 int64_t kchunk_for(int prec, int64_t K, int /*ngroups*/) {
-  const int64_t cap = (prec == 0) ? 16384 : 65536;
+  const int64_t cap = (prec == 0) ? 16384 : (prec == 3 ? 65536 : 8192);
   const int64_t target_blocks = 2048;
   int64_t kc = (K + target_blocks - 1) / target_blocks;
   kc = (kc + 63) / 64 * 64;
