@@ -239,6 +239,28 @@ bsp_status bsp_bispectrum_field(bsp_plan plan, const float* delta, bsp_precision
 bsp_status bsp_set_timing(bsp_plan plan, int32_t enable);
 bsp_status bsp_stage_times(bsp_plan plan, double* ms, int64_t* launches, double* amount);
 
+/* A batch of mocks for covariance estimates (Sec. 3.5, closing remark: the
+ * modal coefficients of many realisations give the covariance of the
+ * estimator). Mock m runs the whole path of bsp_bispectrum_multipoles on
+ * plans[mock_plan[m]]: plans of different assignment grids N share one
+ * reduction geometry (N', shells, modal basis), so every mock yields outputs
+ * of the same shape. Outputs: B_all device [nmocks][nl][ntri]; beta_all device
+ * [nmocks][nl*nmodes] (shot-noise-subtracted beta^l, l-major, as in
+ * bsp_bispectrum_multipoles); cov device [D][D], D = nl*nmodes, the FP64
+ * sample covariance of the beta_all rows. mock_plan, np: host [nmocks];
+ * ux, uy, uz, w (w nullable, entries nullable): host arrays [nmocks] of device
+ * pointers to the catalogues. Every plan needs bsp_precompute, a modal basis
+ * and its own workspace (plans sharing a workspace must share a stream).
+ * Mocks run in order, each on its plan's stream; the call synchronises every
+ * plan before enqueueing the covariance on plans[0]'s stream (valid after
+ * bsp_sync(plans[0])). Errors: BSP_ERR_ARG if the plans' output shapes
+ * differ, nmocks < 2 or an index is out of range; the first failing mock's
+ * status otherwise (its message via bsp_last_error(plans[0])). */
+bsp_status bsp_batch_run(const bsp_plan* plans, int32_t nplans, const int32_t* mock_plan, int32_t nmocks,
+                         const float* const* ux, const float* const* uy, const float* const* uz,
+                         const float* const* w, const int64_t* np, bsp_precision prec, double* B_all,
+                         double* beta_all, double* cov);
+
 /* Sample covariance of a batch of coefficient vectors (FP64):
  * cov = (1/(M-1)) sum_m (x_m - mean)(x_m - mean)^T. x: device [m][d], cov:
  * device [d][d]. stream: hipStream_t or NULL. */

@@ -21,7 +21,8 @@ __all__ = [
     "bsp_plan_info", "bsp_workspace_size", "bsp_set_workspace", "bsp_sync", "bsp_precompute",
     "bsp_geometry", "bsp_grid_assign", "bsp_fft_r2c", "bsp_fft_c2r", "bsp_los_moments", "bsp_grid_entry",
     "bsp_filter_fields", "bsp_triple_reduce", "bsp_modal_coeffs", "bsp_bispectrum_multipoles",
-    "bsp_bispectrum_field", "bsp_batch_covariance", "bsp_set_timing", "bsp_stage_times", "STAGES", "EXPORTED",
+    "bsp_bispectrum_field", "bsp_batch_run", "bsp_batch_covariance", "bsp_set_timing", "bsp_stage_times",
+    "STAGES", "EXPORTED",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -37,8 +38,8 @@ EXPORTED = [
     "bsp_plan_create", "bsp_plan_destroy", "bsp_plan_info", "bsp_last_error", "bsp_workspace_size",
     "bsp_set_workspace", "bsp_sync", "bsp_precompute", "bsp_geometry", "bsp_grid_assign", "bsp_fft_r2c",
     "bsp_fft_c2r", "bsp_los_moments", "bsp_grid_entry", "bsp_filter_fields", "bsp_triple_reduce",
-    "bsp_modal_coeffs", "bsp_bispectrum_multipoles", "bsp_bispectrum_field", "bsp_batch_covariance",
-    "bsp_set_timing", "bsp_stage_times",
+    "bsp_modal_coeffs", "bsp_bispectrum_multipoles", "bsp_bispectrum_field", "bsp_batch_run",
+    "bsp_batch_covariance", "bsp_set_timing", "bsp_stage_times",
 ]
 STAGES = ["assign", "fwd_z", "fwd_y", "fwd_x", "los_combine", "inv_x_filter", "inv_y", "inv_z", "reduce",
           "reduce_combine"]
@@ -106,6 +107,7 @@ def lib():
         "bsp_modal_coeffs": [_vp, _vp, _i32, _d, _vp, _vp, _vp],
         "bsp_bispectrum_multipoles": [_vp, _vp, _vp, _vp, _vp, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp],
         "bsp_bispectrum_field": [_vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp],
+        "bsp_batch_run": [_vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp],
         "bsp_batch_covariance": [_vp, _i32, _i32, _vp, _vp],
         "bsp_set_timing": [_vp, _i32],
         "bsp_stage_times": [_vp, _vp, _vp, _vp],
@@ -242,6 +244,22 @@ def bsp_bispectrum_multipoles(plan, ux, uy, uz, w, np_, prec, B, B0sub=None, Pba
 def bsp_bispectrum_field(plan, delta, prec, B, Pbar=None, bnum=None, alpha=None, beta=None):
     _check(lib().bsp_bispectrum_field(plan, _dptr(delta), prec, _dptr(B), _dptr(Pbar), _dptr(bnum), _dptr(alpha),
                                       _dptr(beta)), plan)
+
+
+def bsp_batch_run(plans, mock_plan, ux, uy, uz, w, np_, prec, B_all, beta_all, cov):
+    """plans: list of plan handles; mock_plan, np_: per-mock ints; ux, uy, uz, w:
+    per-mock float32 device tensors (w None or a list with None entries)."""
+    import torch
+    nm, npl = len(mock_plan), len(plans)
+    P = (C.c_void_p * npl)(*[h.value if isinstance(h, C.c_void_p) else h for h in plans])
+    mp = (C.c_int32 * nm)(*[int(i) for i in mock_plan])
+    NP = (C.c_int64 * nm)(*[int(v) for v in np_])
+
+    def ptrs(ts):
+        return (C.c_void_p * nm)(*[_dptr(t, torch.float32) for t in ts])
+    W = None if w is None else ptrs(w)
+    _check(lib().bsp_batch_run(P, npl, mp, nm, ptrs(ux), ptrs(uy), ptrs(uz), W, NP, prec, _dptr(B_all),
+                               _dptr(beta_all), _dptr(cov)), plans[0])
 
 
 def bsp_batch_covariance(x, m, d, cov, stream: int = 0):

@@ -1609,6 +1609,49 @@ bsp_status bsp_stage_times(bsp_plan p, double* ms, int64_t* launches, double* am
   return BSP_OK;
 }
 
+bsp_status bsp_batch_run(const bsp_plan* plans, int32_t nplans, const int32_t* mock_plan, int32_t nmocks,
+                         const float* const* ux, const float* const* uy, const float* const* uz,
+                         const float* const* w, const int64_t* np, bsp_precision prec, double* B_all,
+                         double* beta_all, double* cov) {
+  if (!plans || nplans < 1 || !mock_plan || nmocks < 2 || !ux || !uy || !uz || !np || !B_all || !beta_all || !cov)
+    return fail(nullptr, BSP_ERR_ARG, "bad argument");
+  bsp_plan p0 = plans[0];
+  if (!p0) return fail(nullptr, BSP_ERR_ARG, "null plan");
+  // every plan must produce outputs of the same shape: nl, triangles and modes
+  for (int i = 0; i < nplans; ++i) {
+    bsp_plan q = plans[i];
+    if (!q) return fail(p0, BSP_ERR_ARG, "null plan");
+    if (!q->pre_done) return fail(p0, BSP_ERR_STATE, "bsp_precompute has not run on every plan");
+    if (!q->modal || q->nl != p0->nl || q->nmodes != p0->nmodes || q->tri.size() != p0->tri.size())
+      return fail(p0, BSP_ERR_ARG, "plans differ in multipoles, triangles or modes (or have no modal basis)");
+  }
+  for (int m = 0; m < nmocks; ++m)
+    if (mock_plan[m] < 0 || mock_plan[m] >= nplans) return fail(p0, BSP_ERR_ARG, "mock plan index out of range");
+  const int64_t ntri = (int64_t)p0->tri.size();
+  const int64_t D = (int64_t)p0->nl * p0->nmodes;
+  for (int m = 0; m < nmocks; ++m) {
+    bsp_plan q = plans[mock_plan[m]];
+    const bsp_status s = bsp_bispectrum_multipoles(q, ux[m], uy[m], uz[m], w ? w[m] : nullptr, np[m], prec,
+                                                   B_all + (int64_t)m * p0->nl * ntri, nullptr, nullptr, nullptr,
+                                                   nullptr, beta_all + (int64_t)m * D);
+    if (s != BSP_OK) {
+      if (q != p0) p0->err = q->err;
+      return s;
+    }
+  }
+  // the covariance runs on the first plan's stream once every mock is done
+  for (int i = 0; i < nplans; ++i) {
+    const bsp_status s = bsp_sync(plans[i]);
+    if (s != BSP_OK) {
+      if (plans[i] != p0) p0->err = plans[i]->err;
+      return s;
+    }
+  }
+  bsp_plan p = p0;
+  HIPCHK(launch_covariance(beta_all, nmocks, (int)D, cov, p0->stream));
+  return BSP_OK;
+}
+
 bsp_status bsp_batch_covariance(const double* x, int32_t m, int32_t d, double* cov, void* stream) {
   bsp_plan p = nullptr;
   if (!x || !cov || m < 2 || d < 1) return fail(p, BSP_ERR_ARG, "bad argument");

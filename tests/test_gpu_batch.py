@@ -1,0 +1,124 @@
+"""The uneven batch for covariances (Sec. 3.5, closing remark), through the C ABI.
+
+Mocks on assignment grids of 128, 192, 256 and 384 points per side share one
+reduction geometry (N' = 128, 20 shells of 2 k_f, l <= 4, 50 modes with P = 6),
+run through bsp_batch_run in bf16 hi+lo, and are checked mock by mock against
+the FP64 oracle; the FP64 covariance of the beta rows is checked against the
+oracle's definition on the same rows.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from synth import catalog as C
+from tests.gpu_helpers import pfid_table, rel_norm
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_1708_05303_amd as B  # noqa: E402
+
+DEV = torch.device("cuda:0")
+
+
+def say(*a):
+    print("[batch]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def test_batch_covariance_against_oracle():
+    say("covariance kernel")
+    r = np.random.Generator(np.random.PCG64(77))
+    x = r.standard_normal((37, 150)) * r.uniform(0.1, 10.0, 150) + r.uniform(-5, 5, 150)
+    xd = torch.as_tensor(x, device=DEV)
+    cov = torch.zeros((150, 150), dtype=torch.float64, device=DEV)
+    B.bsp_batch_covariance(xd, 37, 150, cov)
+    torch.cuda.synchronize()
+    assert rel_norm(cov.cpu().numpy(), O.batch_covariance(x)) < 1e-13
+
+
+def test_batch_covariance_rejects_single_mock():
+    cov = torch.zeros((4, 4), dtype=torch.float64, device=DEV)
+    x = torch.zeros((1, 4), dtype=torch.float64, device=DEV)
+    with pytest.raises(B.BspError):
+        B.bsp_batch_covariance(x, 1, 4, cov)
+
+
+@pytest.fixture(scope="module")
+def uneven_batch():
+    sizes = [128, 192, 256, 384]
+    mocks = [(0, 128), (1, 192), (2, 256), (3, 384), (4, 128)]  # (seed offset, grid)
+    ref_wl = C.batch_workload(0, 256)
+    pf = pfid_table(ref_wl, 3 * 128 ** 2)
+    plans = {}
+    for n in sizes:
+        wl = C.batch_workload(0, n)
+        plans[n] = B.Plan(n=n, n_reduce=wl.n_reduce, box=wl.box, nbins=wl.nbins, k0=wl.k0, dk=wl.dk, lmax=wl.lmax,
+                          window=wl.window, interlace=wl.interlace, los=wl.los, observer=C.observer_grid_units(wl),
+                          P=wl.P, nmodes=wl.nmodes, pfid=pf)
+        plans[n].precompute()
+    cats, refs = [], []
+    for m, n in mocks:
+        wl = C.batch_workload(m, n)
+        u = C.lognormal_catalogue(wl)
+        obs = C.observer_grid_units(wl)
+        spec, wsum = O.spectrum_from_catalogue(*u, n, wl.lmax, obs, window=wl.window, interlace=wl.interlace)
+        geo = O.Geometry(n, wl.n_reduce, wl.box, wl.lmax, wl.nbins, wl.k0, wl.dk, wl.P, wl.nmodes, pf)
+        refs.append(O.estimate(spec, geo, nbar=wsum / wl.box ** 3))
+        cats.append(u)
+        say("oracle mock", m, n)
+    info = plans[128].info
+    nl, nm = info.nl, C.batch_workload(0, 128).nmodes
+    order = [sizes.index(n) for _, n in mocks]
+    dv = [[torch.as_tensor(u[a]).to(DEV) for u in cats] for a in range(3)]
+    B_all = torch.zeros((len(mocks), nl, info.ntri), dtype=torch.float64, device=DEV)
+    beta_all = torch.zeros((len(mocks), nl * nm), dtype=torch.float64, device=DEV)
+    cov = torch.zeros((nl * nm, nl * nm), dtype=torch.float64, device=DEV)
+    B.bsp_batch_run([plans[n].handle for n in sizes], order, dv[0], dv[1], dv[2], None,
+                    [u[0].size for u in cats], B.BSP_BF16X3, B_all, beta_all, cov)
+    plans[128].sync()
+    counts = {n: plans[n].counts.copy() for n in sizes}
+    out = (B_all.cpu().numpy(), beta_all.cpu().numpy(), cov.cpu().numpy())
+    for p in plans.values():
+        p.close()
+    return mocks, refs, counts, out, nl, nm
+
+
+def test_uneven_batch_against_oracle(uneven_batch):
+    mocks, refs, counts, (B_all, beta_all, cov), nl, nm = uneven_batch
+    for n, c in counts.items():
+        assert np.array_equal(c, refs[0]["counts"]), n
+    for i, (m, n) in enumerate(mocks):
+        ref = refs[i]
+        for li in range(nl):
+            e = rel_norm(B_all[i, li], ref["B"][li])
+            say("mock", m, "n", n, "l", 2 * li, "B err", e)
+            assert e < 1e-3, (m, li, e)
+        kL = np.linalg.cond(np.linalg.cholesky(ref["gamma"]))
+        for li in range(nl):
+            e = rel_norm(beta_all[i, li * nm:(li + 1) * nm], ref["beta"][li])
+            say("mock", m, "l", 2 * li, "beta err", e, "kappa(L)", kL)
+            assert e < max(1e-4, kL * 1e-4), (m, li, e)
+    assert rel_norm(cov, O.batch_covariance(beta_all)) < 1e-12
+
+
+def test_batch_run_rejects_mismatched_plans():
+    a = B.Plan(n=32, box=200.0, nbins=4, k0=2.0, dk=2.0, lmax=0, P=3, nmodes=4,
+               pfid=np.full(3 * 32 * 32, 1e3))
+    b = B.Plan(n=32, box=200.0, nbins=4, k0=2.0, dk=2.0, lmax=2, P=3, nmodes=4,
+               pfid=np.full(3 * 32 * 32, 1e3))
+    a.precompute()
+    b.precompute()
+    u = [torch.full((10,), 3.0, device=DEV) for _ in range(2)]
+    Ball = torch.zeros((2, 3, 64), dtype=torch.float64, device=DEV)
+    beta = torch.zeros((2, 12), dtype=torch.float64, device=DEV)
+    cov = torch.zeros((12, 12), dtype=torch.float64, device=DEV)
+    with pytest.raises(B.BspError):
+        B.bsp_batch_run([a.handle, b.handle], [0, 1], u, u, u, None, [10, 10], B.BSP_FP32, Ball, beta, cov)
+    a.close()
+    b.close()
