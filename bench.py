@@ -87,16 +87,21 @@ def cpu_baseline(wl, u, ntri, log_fn):
 # HIP sources each kernel is built from; a counter summary is used only while
 # these are unchanged since it was taken
 KERNEL_SOURCES = {"k_reduce": ["reduce.hip", "tile_mfma.h", "bsp_internal.h"],
-                  "k_inv_z": ["fft.hip", "bsp_internal.h"], "k_c2c": ["fft.hip", "bsp_internal.h"],
-                  "k_fused": ["fused.hip", "tile_mfma.h", "bsp_internal.h"]}
+                  "k_inv_z": ["fft.hip", "bsp_internal.h"], "k_c2c": ["fft.hip", "bsp_internal.h"]}
 
 
 def kernel_source_hash(kernel):
+    """Hash of the kernel's sources with comments and whitespace removed, so that
+    only a change of code (not of its comments) retires a counter summary."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES.get(kernel, []):
-        with open(os.path.join(ROOT, "paper_1708_05303_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1708_05303_amd", "csrc", f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

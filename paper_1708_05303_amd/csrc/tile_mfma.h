@@ -1,7 +1,6 @@
 // Register-resident 16x16 output tiles of the triple-reduction GEMM and the
-// MFMA k-step over one LDS stage, shared by the reduction over materialised
-// fields (reduce.hip) and the reduction fused with the last inverse
-// transform pass (fused.hip).
+// MFMA k-step over one LDS stage of the reduction over materialised fields
+// (reduce.hip).
 //
 // A wave owns up to MAXR row tiles (16 pair products each) and up to MAXC
 // column tiles (16 third fields each) of its own; a row's needed columns are
