@@ -1183,7 +1183,14 @@ bsp_status bsp_sync(bsp_plan p) {
 bsp_status bsp_grid_assign(bsp_plan p, const float* ux, const float* uy, const float* uz, const float* w, int64_t np,
                            float* grids, double* wsum) {
   if (!p || (np > 0 && (!ux || !uy || !uz)) || !grids || !wsum || np < 0) return fail(p, BSP_ERR_ARG, "null argument");
-  HIPCHK(launch_assign(ux, uy, uz, w, np, p->N, p->g.window, p->g.interlace, grids, wsum, p->d_err, p->stream));
+  // sorted, tiled accumulation when the grid tiles and the workspace holds the
+  // sorted catalogue; global atomics otherwise
+  const size_t tb = assign_tiled_bytes(np, p->N);
+  if (tb && p->ws && tb <= p->ws_bytes)
+    HIPCHK(launch_assign_tiled(ux, uy, uz, w, np, p->N, p->g.window, p->g.interlace, 1, grids, wsum, p->d_err, p->ws,
+                               p->ws_bytes, p->stream));
+  else
+    HIPCHK(launch_assign(ux, uy, uz, w, np, p->N, p->g.window, p->g.interlace, grids, wsum, p->d_err, p->stream));
   return BSP_OK;
 }
 
@@ -1551,11 +1558,18 @@ bsp_status bsp_bispectrum_multipoles(bsp_plan p, const float* ux, const float* u
   double* nbar = small + 4001;
   float* grids = reinterpret_cast<float*>(scr);
   float2* dl = reinterpret_cast<float2*>(p->ws);
-  HIPCHK(hipMemsetAsync(grids, 0, (size_t)p->ngrid * p->N * p->N * p->N * sizeof(float), p->stream));
   HIPCHK(hipMemsetAsync(wsum, 0, sizeof(double), p->stream));
   {
-    StageTimer t(p, 0, (double)np * 12.0 + (double)p->ngrid * p->N * p->N * p->N * 8.0);
-    HIPCHK(launch_assign(ux, uy, uz, w, np, p->N, p->g.window, p->g.interlace, grids, wsum, p->d_err, p->stream));
+    // algorithmic minimum: the catalogue read once, each grid node written once
+    StageTimer t(p, 0, (double)np * (w ? 16.0 : 12.0) + (double)p->ngrid * p->N * p->N * p->N * 4.0);
+    const size_t tb = assign_tiled_bytes(np, p->N);
+    if (tb && tb <= L.scratch - L.s_grid) {
+      HIPCHK(launch_assign_tiled(ux, uy, uz, w, np, p->N, p->g.window, p->g.interlace, 0, grids, wsum, p->d_err,
+                                 scr + L.s_grid, L.scratch - L.s_grid, p->stream));
+    } else {
+      HIPCHK(hipMemsetAsync(grids, 0, (size_t)p->ngrid * p->N * p->N * p->N * sizeof(float), p->stream));
+      HIPCHK(launch_assign(ux, uy, uz, w, np, p->N, p->g.window, p->g.interlace, grids, wsum, p->d_err, p->stream));
+    }
   }
   HIPCHK(launch_scale_scalar(wsum, 1.0 / p->V, nbar, p->stream));
   s = forward_moments(p, grids, p->ngrid, 1, wsum, p->g.compensate, dl, scr + L.s_grid);

@@ -79,6 +79,225 @@ __global__ __launch_bounds__(256) void k_assign(const float* __restrict__ ux, co
   if (bad) atomicOr(err, 1);
 }
 
+// ---------------------------------------------------------------------------
+// Tiled assignment without global atomics: particles are counted and sorted by
+// the 8 x 8 x TZ tile of their node floor(x); one workgroup per tile gathers
+// the particles of its own tile and of the 7 tiles below it (a CIC or NGP
+// cloud, also on the grid shifted by half a cell, reaches at most two nodes
+// past floor(x)), sums their weights into LDS and writes its nodes once.
+// Needs N divisible by 8 and by TZ with at least two tiles along each axis.
+
+constexpr int TXY = 8;
+
+__device__ __forceinline__ bool valid_particle(float x, float y, float z, float wt, float fn) {
+  return x >= 0.0f && x < fn && y >= 0.0f && y < fn && z >= 0.0f && z < fn && wt == wt;
+}
+
+__global__ __launch_bounds__(256) void k_tile_count(const float* __restrict__ ux, const float* __restrict__ uy,
+                                                    const float* __restrict__ uz, const float* __restrict__ w,
+                                                    int64_t np, int n, int ntx, int ntz, int tz,
+                                                    int32_t* __restrict__ count, double* __restrict__ wsum,
+                                                    int32_t* __restrict__ err) {
+  const float fn = (float)n;
+  double acc = 0.0;
+  int bad = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
+    const float x = ux[i], y = uy[i], z = uz[i];
+    const float wt = w ? w[i] : 1.0f;
+    if (!valid_particle(x, y, z, wt, fn)) {
+      bad = 1;
+      continue;
+    }
+    acc += (double)wt;
+    const int key = (((int)x / TXY) * ntx + (int)y / TXY) * ntz + (int)z / tz;
+    atomicAdd(count + key, 1);
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && red[0] != 0.0) unsafeAtomicAdd(wsum, red[0]);
+  if (bad) atomicOr(err, 1);
+}
+
+// Exclusive prefix sum of count[0..nt) into offs[0..nt] and cursor[0..nt), one
+// workgroup of 1024 threads, each scanning a contiguous run.
+__global__ __launch_bounds__(1024) void k_tile_scan(const int32_t* __restrict__ count, int nt,
+                                                     int32_t* __restrict__ offs, int32_t* __restrict__ cursor) {
+  __shared__ int32_t part[1024];
+  const int t = threadIdx.x;
+  const int per = (nt + 1023) / 1024;
+  const int b = t * per, e = min(nt, b + per);
+  int s = 0;
+  for (int i = b; i < e; ++i) s += count[i];
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int v = t >= off ? part[t - off] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int run = part[t] - s;
+  for (int i = b; i < e; ++i) {
+    offs[i] = run;
+    cursor[i] = run;
+    run += count[i];
+  }
+  if (t == 1023) offs[nt] = part[1023];
+}
+
+__global__ __launch_bounds__(256) void k_tile_scatter(const float* __restrict__ ux, const float* __restrict__ uy,
+                                                      const float* __restrict__ uz, const float* __restrict__ w,
+                                                      int64_t np, int n, int ntx, int ntz, int tz,
+                                                      int32_t* __restrict__ cursor, float4* __restrict__ sorted) {
+  const float fn = (float)n;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
+    const float x = ux[i], y = uy[i], z = uz[i];
+    const float wt = w ? w[i] : 1.0f;
+    if (!valid_particle(x, y, z, wt, fn)) continue;
+    const int key = (((int)x / TXY) * ntx + (int)y / TXY) * ntz + (int)z / tz;
+    const int pos = atomicAdd(cursor + key, 1);
+    sorted[pos] = make_float4(x, y, z, wt);
+  }
+}
+
+template <int WINDOW, int TZ>
+__global__ __launch_bounds__(256) void k_assign_tiles(const float4* __restrict__ sorted,
+                                                      const int32_t* __restrict__ offs, int n, int ntx, int ntz,
+                                                      int interlace, int accumulate, float* __restrict__ grids) {
+  constexpr int CELLS = TXY * TXY * TZ;
+  __shared__ float acc[2][CELLS];
+  const int tile = blockIdx.x;
+  const int tzi = tile % ntz, txy = tile / ntz, tyi = txy % ntx, txi = txy / ntx;
+  const int x0 = txi * TXY, y0 = tyi * TXY, z0 = tzi * TZ;
+  for (int i = threadIdx.x; i < 2 * CELLS; i += 256) (&acc[0][0])[i] = 0.0f;
+  __syncthreads();
+  const float fn = (float)n;
+  for (int nb = 0; nb < 8; ++nb) {
+    const int ax = txi - ((nb >> 2) & 1), ay = tyi - ((nb >> 1) & 1), az = tzi - (nb & 1);
+    const int k = ((ax < 0 ? ax + ntx : ax) * ntx + (ay < 0 ? ay + ntx : ay)) * ntz + (az < 0 ? az + ntz : az);
+    const int e = offs[k + 1];
+    for (int i = offs[k] + threadIdx.x; i < e; i += 256) {
+      const float4 pt = sorted[i];
+      for (int s = 0; s <= interlace; ++s) {
+        float vx = pt.x, vy = pt.y, vz = pt.z;
+        if (s) {
+          vx += 0.5f;
+          vy += 0.5f;
+          vz += 0.5f;
+          if (vx >= fn) vx -= fn;
+          if (vy >= fn) vy -= fn;
+          if (vz >= fn) vz -= fn;
+        }
+        if constexpr (WINDOW == 0) {
+          int ix = (int)floorf(vx + 0.5f), iy = (int)floorf(vy + 0.5f), iz = (int)floorf(vz + 0.5f);
+          if (ix >= n) ix -= n;
+          if (iy >= n) iy -= n;
+          if (iz >= n) iz -= n;
+          const int lx = ix - x0, ly = iy - y0, lz = iz - z0;
+          if ((unsigned)lx < (unsigned)TXY && (unsigned)ly < (unsigned)TXY && (unsigned)lz < (unsigned)TZ)
+            atomicAdd(&acc[s][(lx * TXY + ly) * TZ + lz], pt.w);
+        } else {
+          const int ix = (int)floorf(vx), iy = (int)floorf(vy), iz = (int)floorf(vz);
+          const float dx = vx - (float)ix, dy = vy - (float)iy, dz = vz - (float)iz;
+          const float wx[2] = {1.0f - dx, dx}, wy[2] = {1.0f - dy, dy}, wz[2] = {1.0f - dz, dz};
+#pragma unroll
+          for (int a = 0; a < 2; ++a) {
+            int cx = ix + a;
+            if (cx == n) cx = 0;
+            const int lx = cx - x0;
+            if ((unsigned)lx >= (unsigned)TXY) continue;
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+              int cy = iy + b;
+              if (cy == n) cy = 0;
+              const int ly = cy - y0;
+              if ((unsigned)ly >= (unsigned)TXY) continue;
+              const float wab = pt.w * wx[a] * wy[b];
+#pragma unroll
+              for (int c = 0; c < 2; ++c) {
+                int cz = iz + c;
+                if (cz == n) cz = 0;
+                const int lz = cz - z0;
+                if ((unsigned)lz < (unsigned)TZ) atomicAdd(&acc[s][(lx * TXY + ly) * TZ + lz], wab * wz[c]);
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // one float4 of a z row per thread
+  const int64_t n3 = (int64_t)n * n * n;
+  for (int s = 0; s <= interlace; ++s) {
+    float* g = grids + (int64_t)s * n3;
+    for (int v = threadIdx.x; v < CELLS / 4; v += 256) {
+      const int c = v * 4;
+      const int lz = c % TZ, ly = (c / TZ) % TXY, lx = c / (TZ * TXY);
+      float4* dst = reinterpret_cast<float4*>(g + ((int64_t)(x0 + lx) * n + (y0 + ly)) * n + z0 + lz);
+      float4 val = make_float4(acc[s][c], acc[s][c + 1], acc[s][c + 2], acc[s][c + 3]);
+      if (accumulate) {
+        const float4 old = *dst;
+        val.x += old.x;
+        val.y += old.y;
+        val.z += old.z;
+        val.w += old.w;
+      }
+      *dst = val;
+    }
+  }
+}
+
+static int tile_tz(int n) {
+  if (n % TXY != 0 || n / TXY < 2) return 0;
+  for (int tz = 64; tz >= 8; tz >>= 1)
+    if (n % tz == 0 && n / tz >= 2) return tz;
+  return 0;
+}
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t assign_tiled_bytes(int64_t np, int n) {
+  const int tz = tile_tz(n);
+  if (!tz || np <= 0 || np > (int64_t)INT32_MAX) return 0;
+  const int64_t nt = (int64_t)(n / TXY) * (n / TXY) * (n / tz);
+  return align256((size_t)np * sizeof(float4)) + 3 * align256((size_t)(nt + 1) * sizeof(int32_t));
+}
+
+hipError_t launch_assign_tiled(const float* ux, const float* uy, const float* uz, const float* w, int64_t np, int n,
+                               int window, int interlace, int accumulate, float* grids, double* wsum, int32_t* err,
+                               void* scratch, size_t scratch_bytes, hipStream_t s) {
+  const int tz = tile_tz(n);
+  const size_t need = assign_tiled_bytes(np, n);
+  if (!tz || need == 0 || need > scratch_bytes || !scratch || interlace < 0 || interlace > 1)
+    return hipErrorInvalidValue;
+  const int ntx = n / TXY, ntz = n / tz;
+  const int nt = ntx * ntx * ntz;
+  char* base = reinterpret_cast<char*>(scratch);
+  float4* sorted = reinterpret_cast<float4*>(base);
+  int32_t* count = reinterpret_cast<int32_t*>(base + align256((size_t)np * sizeof(float4)));
+  int32_t* offs = count + align256((size_t)(nt + 1) * sizeof(int32_t)) / sizeof(int32_t);
+  int32_t* cursor = offs + align256((size_t)(nt + 1) * sizeof(int32_t)) / sizeof(int32_t);
+  hipError_t e = hipMemsetAsync(count, 0, (size_t)nt * sizeof(int32_t), s);
+  if (e != hipSuccess) return e;
+  int64_t blocks = (np + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(k_tile_count, dim3((unsigned)blocks), dim3(256), 0, s, ux, uy, uz, w, np, n, ntx, ntz, tz, count,
+                     wsum, err);
+  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, count, nt, offs, cursor);
+  hipLaunchKernelGGL(k_tile_scatter, dim3((unsigned)blocks), dim3(256), 0, s, ux, uy, uz, w, np, n, ntx, ntz, tz,
+                     cursor, sorted);
+#define TCASE(WIN, TZV)                                                                                         if (window == WIN && tz == TZV) {                                                                               hipLaunchKernelGGL((k_assign_tiles<WIN, TZV>), dim3((unsigned)nt), dim3(256), 0, s, sorted, offs, n, ntx,                        ntz, interlace, accumulate, grids);                                                        return hipGetLastError();                                                                                   }
+  TCASE(0, 64) TCASE(0, 32) TCASE(0, 16) TCASE(0, 8) TCASE(1, 64) TCASE(1, 32) TCASE(1, 16) TCASE(1, 8)
+#undef TCASE
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_assign(const float* ux, const float* uy, const float* uz, const float* w, int64_t np,
                          int n, int window, int interlace, float* grids, double* wsum, int32_t* err,
                          hipStream_t s) {

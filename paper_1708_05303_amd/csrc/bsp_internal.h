@@ -107,6 +107,14 @@ bool fft_size_supported(int n);
 hipError_t launch_assign(const float* ux, const float* uy, const float* uz, const float* w,
                          int64_t np, int n, int window, int interlace, float* grids,
                          double* wsum, int32_t* err, hipStream_t s);
+// Tiled assignment (no global atomics on the grids): bytes of scratch it needs
+// for np particles on an N^3 grid, 0 when N does not tile; accumulate = 0
+// overwrites the grids, 1 adds to them. Returns hipErrorInvalidValue when N
+// does not tile or the scratch is too small (nothing is launched then).
+size_t assign_tiled_bytes(int64_t np, int n);
+hipError_t launch_assign_tiled(const float* ux, const float* uy, const float* uz, const float* w, int64_t np, int n,
+                               int window, int interlace, int accumulate, float* grids, double* wsum, int32_t* err,
+                               void* scratch, size_t scratch_bytes, hipStream_t s);
 
 // LOS combination and shell sums (los.hip).
 struct LosDesc {

@@ -61,23 +61,43 @@ def test_fft_r2c_c2r_against_oracle(n):
 
 # ---------------------------------------------------------------- assignment
 
-@pytest.mark.parametrize("window,interlace", [(1, 0), (1, 1), (0, 1)])
-def test_grid_assign_against_oracle(window, interlace):
-    say("assign", window, interlace)
-    n = 32
-    r = rng(7)
-    u = [C.quantise_grid_units(r.uniform(0, n, 20000), n) for _ in range(3)]
-    w = r.uniform(0.5, 1.5, 20000).astype(np.float32)
-    plan = B.Plan(n=n, box=100.0, nbins=1, k0=1.0, dk=1.0, window=window, interlace=interlace)
-    grids = torch.zeros((1 + interlace, n, n, n), dtype=torch.float32, device=DEV)
+def _tiled_assign_bytes(npart, n):
+    """Scratch the sorted, tiled assignment needs (8 x 8 x tz tiles)."""
+    tz = next(t for t in (64, 32, 16, 8) if n % t == 0 and n // t >= 2)
+    nt = (n // 8) ** 2 * (n // tz)
+    up = lambda b: (b + 255) // 256 * 256
+    return up(npart * 16) + 3 * up((nt + 1) * 4)
+
+
+@pytest.mark.parametrize("n,window,interlace,tiled", [
+    (32, 1, 0, False), (32, 1, 1, False), (32, 0, 1, False),
+    (16, 1, 1, True), (32, 1, 0, True), (32, 1, 1, True), (32, 0, 1, True), (64, 1, 1, True), (96, 1, 1, True),
+    (96, 0, 0, True)])
+def test_grid_assign_against_oracle(n, window, interlace, tiled):
+    """Global-atomic assignment (no workspace) and the sorted, tiled one (with a
+    workspace) against the oracle, adding into grids that already hold 0.25;
+    particles also sit on tile edges and just below N (wrap-around)."""
+    say("assign", n, window, interlace, "tiled" if tiled else "atomic")
+    r = rng(7 + n)
+    npart = 20000 if n >= 32 else 3000
+    u = [C.quantise_grid_units(r.uniform(0, n, npart), n) for _ in range(3)]
+    edges = np.array([0.0, 7.999755859375, 8.0, n - 2.0 ** -12, n - 0.5, 15.999755859375], np.float32)
+    for a in range(3):
+        u[a][:36] = np.tile(edges, 6)[(np.arange(36) * (a + 1)) % 36]
+    w = r.uniform(0.5, 1.5, npart).astype(np.float32)
+    plan = B.Plan(n=n, box=100.0, nbins=1, k0=1.0, dk=1.0, window=window, interlace=interlace, workspace=tiled)
+    if tiled:
+        assert B.bsp_workspace_size(plan.handle) >= _tiled_assign_bytes(npart, n)
+    grids = torch.full((1 + interlace, n, n, n), 0.25, dtype=torch.float32, device=DEV)
     wsum = torch.zeros(1, dtype=torch.float64, device=DEV)
     B.bsp_grid_assign(plan.handle, dev(u[0]), dev(u[1]), dev(u[2]), dev(w), u[0].size, grids, wsum)
     plan.sync()
     g = grids.cpu().numpy()
     for s in range(1 + interlace):
-        ref = O.assign(*u, n, w.astype(np.float64), window, 0.5 * s)
-        assert np.max(np.abs(g[s] - ref)) < 2e-6 * np.max(ref) + 1e-6
+        ref = O.assign(*u, n, w.astype(np.float64), window, 0.5 * s) + 0.25
+        assert np.max(np.abs(g[s] - ref)) < 2e-6 * np.max(ref) + 1e-6, s
     assert abs(wsum.item() - float(w.astype(np.float64).sum())) < 1e-6 * w.sum()
+    plan.close()
 
 
 def test_grid_assign_rejects_out_of_range():
