@@ -128,16 +128,24 @@ def measured_traffic(kernel, workload):
 
 def copy_calibration(nbytes, reps):
     """Plain device-to-device copies of a known size, for scaling the HBM
-    counters (FETCH_SIZE, WRITE_SIZE) of a profiled run to bytes."""
+    counters (FETCH_SIZE, WRITE_SIZE) of a profiled run to bytes; also the
+    copy rate (read + write bytes per second), the practical ceiling of
+    streaming passes."""
     import torch
     n = nbytes // 4
     a = torch.ones(n, dtype=torch.float32, device="cuda:0")
     b = torch.empty_like(a)
     torch.cuda.synchronize()
+    best = float("inf")
     for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
         b.copy_(a)
-    torch.cuda.synchronize()
-    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "reps": reps}), flush=True)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "reps": reps,
+                      "best_s": best, "copy_GBps": 2 * n * 4 / best / 1e9}), flush=True)
 
 
 def main():

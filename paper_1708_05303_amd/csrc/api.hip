@@ -274,6 +274,8 @@ struct bsp_plan_s {
   int64_t* d_nb_modes = nullptr;
   float* d_tab32 = nullptr;   // rows: nbins shells, P modal weights
   double* d_tab64 = nullptr;  // rows: nbins shells, nU U_ab, P G_p, P G^P_p
+  int32_t* d_rng32 = nullptr;  // [rows][3] nonzero |n|^2 range and unit flag of each tab32 row
+  int32_t* d_rng64 = nullptr;  // the same for tab64
   int32_t* d_err = nullptr;
   int32_t* d_ints = nullptr;  // field_ell / field_tab for the main and precompute passes
   int F = 0;                  // fields of the main pipeline
@@ -597,14 +599,39 @@ std::vector<std::array<int, 2>> inverse_batches(int nf, int fb, int Nr, const st
   return out;
 }
 
+// Range of |n|^2 outside which a filter table row is zero, and whether it is
+// exactly 1 inside (shell indicators): [rows][3] = lo, hi, unit.
+template <typename T>
+std::vector<int32_t> row_ranges(const std::vector<T>& tab, int tl) {
+  const size_t rows = tab.size() / tl;
+  std::vector<int32_t> r(rows * 3, 0);
+  for (size_t row = 0; row < rows; ++row) {
+    const T* t = tab.data() + row * tl;
+    int lo = tl, hi = 0;
+    for (int n2 = 0; n2 < tl; ++n2)
+      if (t[n2] != (T)0) {
+        lo = std::min(lo, n2);
+        hi = n2 + 1;
+      }
+    if (hi == 0) lo = 0;
+    int unit = hi > lo ? 1 : 0;
+    for (int n2 = lo; n2 < hi; ++n2)
+      if (t[n2] != (T)1) unit = 0;
+    r[row * 3] = lo;
+    r[row * 3 + 1] = hi;
+    r[row * 3 + 2] = unit;
+  }
+  return r;
+}
+
 // Inverse transforms of filtered compact spectra to real fields on N'.
 // field_ell / field_tab index the filter of each output field; cf[f] is the
 // largest |n_a| the filter of field f keeps. A batch of fields is transformed
 // on the band |n_a| <= c_b of its widest filter, so narrow shells move little data.
 template <typename T>
 bsp_status inverse_fields(bsp_plan p, const cplx_t<T>* src, int64_t src_ell_stride, int nf,
-                          const int32_t* d_field_ell, const int32_t* d_field_tab, const T* tables, T* out,
-                          char* scratch, int fb, const std::vector<int>& cf) {
+                          const int32_t* d_field_ell, const int32_t* d_field_tab, const T* tables,
+                          const int32_t* row_range, T* out, char* scratch, int fb, const std::vector<int>& cf) {
   const int Nr = p->Nr, c = p->c, cz = p->cz, w = 2 * c + 1;
   using V = cplx_t<T>;
   V* Xb = reinterpret_cast<V*>(scratch);
@@ -620,6 +647,7 @@ bsp_status inverse_fields(bsp_plan p, const cplx_t<T>* src, int64_t src_ell_stri
     fd.field_ell = d_field_ell;
     fd.tables = tables;
     fd.field_table = d_field_tab;
+    fd.row_range = row_range;
     fd.tablen = p->n2max + 1;
     fd.c = c;
     fd.row0 = c - cb;
@@ -1058,6 +1086,8 @@ bsp_status bsp_plan_create(bsp_plan* out, const bsp_geom* g, const bsp_modal_bas
   }
   p->d_tab32 = upload(p, tab32);
   p->d_tab64 = upload(p, tab64);
+  p->d_rng32 = upload(p, row_ranges(tab32, tl));
+  p->d_rng64 = upload(p, row_ranges(tab64, tl));
   // field metadata: main pipeline fields, then the precompute identity map
   // main fields: shell fields D^(l)_b at b * nl + l (so consecutive fields
   // widen with b), then modal fields M^(l)_a at nl * nbins + a * nl + l
@@ -1103,7 +1133,8 @@ bsp_status bsp_plan_create(bsp_plan* out, const bsp_geom* g, const bsp_modal_bas
     delete p;
     return fail(nullptr, BSP_ERR_ARG, "reduction schedule could not be built (too many fields or modes)");
   }
-  if (!p->tw32_N || !p->tw32_Nr || !p->tw64_Nr || !p->d_bin_of_n2 || !p->d_tab32 || !p->d_tab64 || !p->d_err ||
+  if (!p->tw32_N || !p->tw32_Nr || !p->tw64_Nr || !p->d_bin_of_n2 || !p->d_tab32 || !p->d_tab64 || !p->d_rng32 ||
+      !p->d_rng64 || !p->d_err ||
       !p->d_field_ell || !p->d_field_tab || !p->d_ones_ell || !p->d_pre_tab || !p->d_nb_modes) {
     delete p;
     return fail(nullptr, BSP_ERR_HIP, "device allocation of plan tables failed");
@@ -1307,7 +1338,7 @@ bsp_status bsp_filter_fields(bsp_plan p, const void* delta_l, int32_t nfilt, con
   std::vector<int> cf(nfilt);
   for (int i = 0; i < nfilt; ++i) cf[i] = p->row_c[ft[i]];
   return inverse_fields<float>(p, reinterpret_cast<const float2*>(delta_l), p->spec, nfilt, dmeta, dmeta + nfilt,
-                               p->d_tab32, fields, p->ws + meta, fb, cf);
+                               p->d_tab32, p->d_rng32, fields, p->ws + meta, fb, cf);
 }
 
 bsp_status bsp_triple_reduce(bsp_plan p, const float* fields, int32_t nfields, int64_t K, const int32_t* pairs,
@@ -1369,7 +1400,7 @@ bsp_status bsp_precompute(bsp_plan p) {
   hipLaunchKernelGGL(k_fill_ones, dim3((unsigned)((p->spec + 255) / 256)), dim3(256), 0, p->stream, ones, p->spec);
   HIPCHK(hipGetLastError());
   // --- triangle counts: I_b for every shell, T[(b2,b3)][b1] over the candidates
-  s = inverse_fields<double>(p, ones, 0, p->nbins, p->d_ones_ell, p->d_pre_tab, p->d_tab64, f64, scr, L.fb64,
+  s = inverse_fields<double>(p, ones, 0, p->nbins, p->d_ones_ell, p->d_pre_tab, p->d_tab64, p->d_rng64, f64, scr, L.fb64,
                              std::vector<int>(p->row_c.begin(), p->row_c.begin() + p->nbins));
   if (s != BSP_OK) return s;
   s = run_reduce<double>(p, p->cnt_rp, f64, K, 3, nullptr, T64, scr, scr_bytes, 1.0);
@@ -1416,7 +1447,7 @@ bsp_status bsp_precompute(bsp_plan p) {
   // --- modal geometry: Gram matrix, Cholesky factor, shot-noise integrals
   if (p->modal) {
     const int nm = p->nmodes;
-    s = inverse_fields<double>(p, ones, 0, p->nU, p->d_ones_ell, p->d_urow, p->d_tab64, f64, scr, L.fb64,
+    s = inverse_fields<double>(p, ones, 0, p->nU, p->d_ones_ell, p->d_urow, p->d_tab64, p->d_rng64, f64, scr, L.fb64,
                                std::vector<int>(p->nU, p->c));
     if (s != BSP_OK) return s;
     s = run_reduce<double>(p, p->gram_rp, f64, K, 3, nullptr, T64, scr, scr_bytes, 1.0);
@@ -1430,7 +1461,7 @@ bsp_status bsp_precompute(bsp_plan p) {
     if (s != BSP_OK) return s;
     p->chol_h.resize((size_t)nm * nm);
     HIPCHK(hipMemcpy(p->chol_h.data(), p->d_L, p->chol_h.size() * sizeof(double), hipMemcpyDeviceToHost));
-    s = inverse_fields<double>(p, ones, 0, 2 * p->P, p->d_ones_ell, p->d_grow, p->d_tab64, f64, scr, L.fb64,
+    s = inverse_fields<double>(p, ones, 0, 2 * p->P, p->d_ones_ell, p->d_grow, p->d_tab64, p->d_rng64, f64, scr, L.fb64,
                                std::vector<int>(2 * p->P, p->c));
     if (s != BSP_OK) return s;
     s = run_reduce<double>(p, p->sn_rp, f64, K, 3, nullptr, T64, scr, scr_bytes, 1.0);
@@ -1488,7 +1519,7 @@ bsp_status estimate_from_spectrum(bsp_plan p, const float2* dl, bsp_precision pr
   unsigned* tmpu = reinterpret_cast<unsigned*>(small + 3072);
   char* scr = ws + L.dl + L.fields + L.T + L.small;
   const size_t scr_bytes = p->ws_bytes - (L.dl + L.fields + L.T + L.small);
-  bsp_status s = inverse_fields<float>(p, dl, p->spec, p->F, p->d_field_ell, p->d_field_tab, p->d_tab32, fields, scr,
+  bsp_status s = inverse_fields<float>(p, dl, p->spec, p->F, p->d_field_ell, p->d_field_tab, p->d_tab32, p->d_rng32, fields, scr,
                                        L.fb, p->field_c);
   if (s != BSP_OK) return s;
   const float* sc = nullptr;

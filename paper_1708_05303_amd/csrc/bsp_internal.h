@@ -43,6 +43,8 @@ struct FilterDesc {
   const int32_t* field_ell;      // [nfields] ell slot of each field
   const void* tables;            // [rows][tablen] weights by |n|^2 (float for FP32 passes, double for FP64)
   const int32_t* field_table;    // [nfields] table row of each field
+  const int32_t* row_range;      // [rows][3]: lo, hi, unit: the row is zero outside lo <= |n|^2 < hi,
+                                 // and exactly 1 inside when unit
   int32_t tablen;                // n2max + 1
   int32_t c;                     // half width of the compact cube
   int32_t row0;                  // first source row (the batch reads rows row0 .. row0 + in_rows - 1)

@@ -309,13 +309,17 @@ __global__ __launch_bounds__(256) void k_c2c(const cplx_t<T>* __restrict__ in, c
   const int64_t ocol = (int64_t)jj * p.out_js + kz;
   const V* src;
   const T* tab = nullptr;
-  int fny = 0;
+  int fny = 0, lo2 = 0, hi2 = 0, unit = 0;
   bool fz_ok = true;
   if constexpr (FILT) {
     const int field = f.field0 + outer;
     src = reinterpret_cast<const V*>(f.src) + (int64_t)f.field_ell[field] * f.src_ell_stride +
           (int64_t)f.row0 * p.in_row;
-    tab = reinterpret_cast<const T*>(f.tables) + (int64_t)f.field_table[field] * f.tablen;
+    const int row = f.field_table[field];
+    tab = reinterpret_cast<const T*>(f.tables) + (int64_t)row * f.tablen;
+    lo2 = f.row_range[3 * row];
+    hi2 = f.row_range[3 * row + 1];
+    unit = f.row_range[3 * row + 2];
     fny = jj + p.in_j0 - f.c;
     fz_ok = kz <= f.c;
   } else {
@@ -331,14 +335,14 @@ __global__ __launch_bounds__(256) void k_c2c(const cplx_t<T>* __restrict__ in, c
       const int r = (pos + p.in_off) % N;
       if (r < p.in_rows) {
         if constexpr (FILT) {
+          // the range test needs no memory, so the spectrum and weight loads
+          // issue together (the filter is zero outside [lo2, hi2))
           const int nx = r - p.in_off;
           const int n2 = nx * nx + fny * fny + kz * kz;
-          if (fz_ok && n2 < f.tablen) {
-            const T wgt = tab[n2];
-            if (wgt != (T)0) {
-              const V x = src[(int64_t)r * p.in_row + icol];
-              v[e] = V{x.x * wgt, x.y * wgt};
-            }
+          if (fz_ok && n2 >= lo2 && n2 < hi2) {
+            const V x = src[(int64_t)r * p.in_row + icol];
+            const T wgt = unit ? (T)1 : tab[n2];
+            v[e] = V{x.x * wgt, x.y * wgt};
           }
         } else {
           v[e] = src[(int64_t)r * p.in_row + icol];
