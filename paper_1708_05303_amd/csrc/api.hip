@@ -280,6 +280,10 @@ struct bsp_plan_s {
   int32_t* d_ints = nullptr;  // field_ell / field_tab for the main and precompute passes
   int F = 0;                  // fields of the main pipeline
   std::vector<int> row_c;     // largest |n_a| kept by each filter table row (tab64 row numbering)
+  // per tab32 row: modes of the compact half cube the filter keeps, and the
+  // (n_y, n_z) columns it leaves nonzero (algorithmic bytes of the inverse passes)
+  std::vector<int64_t> row_support32, row_cols32;
+  std::vector<int32_t> field_row32;  // tab32 row of each main pipeline field
   std::vector<int> field_c;   // per main-pipeline field
   int32_t *d_field_ell = nullptr, *d_field_tab = nullptr;
   int32_t *d_ones_ell = nullptr, *d_pre_tab = nullptr;  // precompute: all ell 0, table row = index
@@ -631,7 +635,8 @@ std::vector<int32_t> row_ranges(const std::vector<T>& tab, int tl) {
 template <typename T>
 bsp_status inverse_fields(bsp_plan p, const cplx_t<T>* src, int64_t src_ell_stride, int nf,
                           const int32_t* d_field_ell, const int32_t* d_field_tab, const T* tables,
-                          const int32_t* row_range, T* out, char* scratch, int fb, const std::vector<int>& cf) {
+                          const int32_t* row_range, T* out, char* scratch, int fb, const std::vector<int>& cf,
+                          const int32_t* frow32 = nullptr) {
   const int Nr = p->Nr, c = p->c, cz = p->cz, w = 2 * c + 1;
   using V = cplx_t<T>;
   V* Xb = reinterpret_cast<V*>(scratch);
@@ -681,14 +686,22 @@ bsp_status inverse_fields(bsp_plan p, const cplx_t<T>* src, int64_t src_ell_stri
     py.out_off = 0;
     set1d(py);
     if constexpr (sizeof(T) == 4) {
-      // algorithmic bytes: each field's own band |n_a| <= c_f read once and each
-      // pass output on that band written once (batching on the widest band of a
-      // batch is the kernels' overhead, not part of the minimum)
+      // algorithmic bytes: the modes each field's filter keeps read once, the
+      // (n_y, n_z) columns it leaves nonzero written by the x pass and read by the
+      // y pass (the kernels also move the zero columns of the band), the y pass
+      // output on the field's own band |n_z| <= c_f written once and read by the
+      // z pass, and the real field written once (batching on the widest band of
+      // a batch is the kernels' overhead, not part of the minimum)
       double a5 = 0.0, a6 = 0.0, a7 = 0.0;
       for (int f = f0; f < f0 + nb; ++f) {
         const double c1 = cf[f] + 1.0, w1 = 2.0 * cf[f] + 1.0;
-        a5 += (w1 * w1 * c1 + (double)Nr * w1 * c1) * 8.0;
-        a6 += ((double)Nr * w1 * c1 + (double)Nr * Nr * c1) * 8.0;
+        double sup = w1 * w1 * c1, cols = w1 * c1;
+        if (frow32) {
+          sup = (double)p->row_support32[frow32[f]];
+          cols = (double)p->row_cols32[frow32[f]];
+        }
+        a5 += (sup + (double)Nr * cols) * 8.0;
+        a6 += ((double)Nr * cols + (double)Nr * Nr * c1) * 8.0;
         a7 += (double)Nr * Nr * c1 * 8.0 + (double)Nr * Nr * Nr * 4.0;
       }
       {
@@ -1088,6 +1101,29 @@ bsp_status bsp_plan_create(bsp_plan* out, const bsp_geom* g, const bsp_modal_bas
   p->d_tab64 = upload(p, tab64);
   p->d_rng32 = upload(p, row_ranges(tab32, tl));
   p->d_rng64 = upload(p, row_ranges(tab64, tl));
+  {
+    // lattice points of the compact half cube (n_z >= 0) and of the (n_y, n_z)
+    // column plane by |n|^2, summed over each row's nonzero range
+    std::vector<int64_t> h3(tl, 0), h2(tl, 0);
+    const int c = p->c;
+    for (int ny = -c; ny <= c; ++ny)
+      for (int nz = 0; nz <= c; ++nz) {
+        const int64_t m = (int64_t)ny * ny + (int64_t)nz * nz;
+        if (m < tl) h2[m]++;
+        for (int nx = -c; nx <= c; ++nx) {
+          const int64_t n2 = m + (int64_t)nx * nx;
+          if (n2 < tl) h3[n2]++;
+        }
+      }
+    const std::vector<int32_t> r32 = row_ranges(tab32, tl);
+    const size_t rows = r32.size() / 3;
+    p->row_support32.assign(rows, 0);
+    p->row_cols32.assign(rows, 0);
+    for (size_t row = 0; row < rows; ++row) {
+      for (int n2 = r32[3 * row]; n2 < r32[3 * row + 1]; ++n2) p->row_support32[row] += h3[n2];
+      for (int m = 0; m < r32[3 * row + 1]; ++m) p->row_cols32[row] += h2[m];
+    }
+  }
   // field metadata: main pipeline fields, then the precompute identity map
   // main fields: shell fields D^(l)_b at b * nl + l (so consecutive fields
   // widen with b), then modal fields M^(l)_a at nl * nbins + a * nl + l
@@ -1113,6 +1149,7 @@ bsp_status bsp_plan_create(bsp_plan* out, const bsp_geom* g, const bsp_modal_bas
       }
   p->d_field_ell = upload(p, fe);
   p->d_field_tab = upload(p, ft);
+  p->field_row32 = ft;
   std::vector<int32_t> zeros(std::max(nrow64, 1), 0), iota(std::max(nrow64, 1));
   for (int i = 0; i < (int)iota.size(); ++i) iota[i] = i;
   p->d_ones_ell = upload(p, zeros);
@@ -1338,7 +1375,7 @@ bsp_status bsp_filter_fields(bsp_plan p, const void* delta_l, int32_t nfilt, con
   std::vector<int> cf(nfilt);
   for (int i = 0; i < nfilt; ++i) cf[i] = p->row_c[ft[i]];
   return inverse_fields<float>(p, reinterpret_cast<const float2*>(delta_l), p->spec, nfilt, dmeta, dmeta + nfilt,
-                               p->d_tab32, p->d_rng32, fields, p->ws + meta, fb, cf);
+                               p->d_tab32, p->d_rng32, fields, p->ws + meta, fb, cf, ft.data());
 }
 
 bsp_status bsp_triple_reduce(bsp_plan p, const float* fields, int32_t nfields, int64_t K, const int32_t* pairs,
@@ -1520,7 +1557,7 @@ bsp_status estimate_from_spectrum(bsp_plan p, const float2* dl, bsp_precision pr
   char* scr = ws + L.dl + L.fields + L.T + L.small;
   const size_t scr_bytes = p->ws_bytes - (L.dl + L.fields + L.T + L.small);
   bsp_status s = inverse_fields<float>(p, dl, p->spec, p->F, p->d_field_ell, p->d_field_tab, p->d_tab32, p->d_rng32, fields, scr,
-                                       L.fb, p->field_c);
+                                       L.fb, p->field_c, p->field_row32.data());
   if (s != BSP_OK) return s;
   const float* sc = nullptr;
   if (prec == BSP_FP16X3) {
