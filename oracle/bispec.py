@@ -39,7 +39,7 @@ __all__ = [
     "legendre_moments", "legendre_moments_direct", "bin_edges4", "bin_of_n2",
     "n2_grid_half", "shell_field", "triangle_list", "triangle_counts_fft",
     "triangle_counts_brute", "closed_triangle_sum_brute", "binned_triple_sums",
-    "binned_bispectrum", "shell_power", "shot_noise_binned", "modal_modes",
+    "binned_bispectrum", "shell_power", "power_multipoles", "shot_noise_binned", "modal_modes",
     "modal_q", "modal_filter", "modal_fields", "modal_numerators", "gram_matrix",
     "modal_solve", "modal_shot_noise", "batch_covariance", "spectrum_from_catalogue",
     "spectrum_from_field", "estimate", "Geometry", "n2_max_of",
@@ -486,6 +486,33 @@ def shell_power(spec0: np.ndarray, n: int, k0: float, dk: float, nb: int, box: f
         sel = bins == b
         Nb[b] = int(round(m[sel].sum()))
         P[b] = V * float((p[sel] * m[sel]).sum()) / (float(n) ** 6 * Nb[b])
+    return P, Nb
+
+
+def power_multipoles(spec_l: Sequence[np.ndarray], n: int, k0: float, dk: float, nb: int, box: float):
+    """Power-spectrum multipoles of Sec. 2, eq. (PowSpecMultipole): the shell
+    average over directions of delta^(l)(k) delta^(0)(-k) / V, on the lattice
+    P^(l)_b = V sum_{n in b} Re[delta^(l)(n) conj(delta^(0)(n))] / (N^6 N_b)
+    over the full lattice (delta^(0)(-n) = conj delta^(0)(n) for a real field;
+    the pair n, -n of the half spectrum contributes twice the real part).
+    spec_l: half spectra [nl][n][n][n//2+1] from spectrum_from_field. Raw: no
+    shot-noise term (the paper gives none). Returns (P [nl][nb], N_b)."""
+    n2 = n2_grid_half(n)
+    bins = bin_of_n2(n2, k0, dk, nb)
+    mult = np.full(n // 2 + 1, 2.0)
+    mult[0] = 1.0
+    if n % 2 == 0:
+        mult[-1] = 1.0
+    m = np.broadcast_to(mult[None, None, :], n2.shape)
+    V = box ** 3
+    P = np.zeros((len(spec_l), nb))
+    Nb = np.empty(nb, np.int64)
+    for b in range(nb):
+        sel = bins == b
+        Nb[b] = int(round(m[sel].sum()))
+        for li, s in enumerate(spec_l):
+            prod = np.real(s[sel] * np.conj(spec_l[0][sel]))
+            P[li, b] = V * float((prod * m[sel]).sum()) / (float(n) ** 6 * Nb[b]) if Nb[b] else 0.0
     return P, Nb
 
 

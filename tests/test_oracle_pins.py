@@ -152,6 +152,64 @@ def test_kaiser_multipole_ratios():
     assert abs(p0 - expect[0]) < 0.01 * expect[0]
 
 
+# ---------------------------------------------------------------- power-spectrum multipoles
+
+def test_power_multipoles_kaiser():
+    """eq. (PowSpecMultipole) on a Kaiser field (1 + f mu^2) g with |g| = 1 and
+    a line of sight along z: the shell averages approach the closed forms
+    1 + 2f/3 + f^2/5, 4f/3 + 4f^2/7, 8f^2/35 (times V / N^6)."""
+    n, f, box = 48, 0.6, 300.0
+    r = rng(15)
+    n2 = O.n2_grid_half(n)
+    fx, fy, fz = O.bispec.half_freq_vectors(n)
+    kn = np.sqrt(np.maximum(n2, 1))
+    g = O.forward(sfft.irfftn(np.exp(2j * math.pi * r.uniform(size=n2.shape)), s=(n,) * 3))
+    g = g / np.maximum(np.abs(g), 1e-300)
+    ds = (1 + f * (fz / kn) ** 2) * g
+    spec = O.spectrum_from_field([sfft.irfftn(ds, s=(n,) * 3)], [0.0], n, 4, None, None)
+    P, Nb = O.power_multipoles(spec, n, 14.0, 4.0, 2, box)
+    expect = [1 + 2 * f / 3 + f ** 2 / 5, 4 * f / 3 + 4 * f ** 2 / 7, 8 * f ** 2 / 35]
+    scale = float(n) ** 6 / box ** 3
+    for b in range(2):
+        assert Nb[b] > 3000
+        for li in range(3):
+            assert abs(P[li, b] * scale - expect[li]) < 0.015 * expect[0], (b, li, P[li, b] * scale)
+
+
+def test_power_multipoles_full_lattice_brute():
+    """Half-spectrum multiplicities and normalisation against a direct sum over
+    the full lattice with explicit Legendre weights (plane-parallel LOS along z):
+    delta^(l)(n) = (2l+1) L_l(n_z/|n|) delta(n)."""
+    n, box, k0, dk, nb = 16, 100.0, 2.0, 2.0, 3
+    d = rng(21).standard_normal((n, n, n))
+    spec = O.spectrum_from_field([d], [0.0], n, 4, None, None)
+    P, Nb = O.power_multipoles(spec, n, k0, dk, nb, box)
+    F = np.fft.fftn(d)
+    fr = np.fft.fftfreq(n, 1.0 / n)
+    nx, ny, nz = np.meshgrid(fr, fr, fr, indexing="ij")
+    n2 = (nx ** 2 + ny ** 2 + nz ** 2).astype(np.int64)
+    mu = nz / np.sqrt(np.maximum(n2, 1))
+    leg = [np.ones_like(mu), 0.5 * (3 * mu ** 2 - 1), (35 * mu ** 4 - 30 * mu ** 2 + 3) / 8]
+    bins = O.bin_of_n2(n2, k0, dk, nb)
+    for b in range(nb):
+        sel = bins == b
+        assert int(sel.sum()) == int(Nb[b])
+        for li in range(3):
+            dl = (4 * li + 1) * leg[li][sel] * F[sel]
+            ref = box ** 3 * float(np.sum(np.real(dl * np.conj(F[sel])))) / (float(n) ** 6 * sel.sum())
+            assert abs(P[li, b] - ref) <= 1e-11 * max(abs(ref), abs(P[0, b])), (b, li, P[li, b], ref)
+
+
+def test_power_multipole_monopole_is_shell_power():
+    n, box = 16, 100.0
+    d = rng(22).standard_normal((n, n, n))
+    spec = O.spectrum_from_field([d], [0.0], n, 2, None, None)
+    P, Nb = O.power_multipoles(spec, n, 2.0, 2.0, 3, box)
+    P0, Nb0 = O.shell_power(spec[0], n, 2.0, 2.0, 3, box)
+    assert np.array_equal(Nb, Nb0)
+    assert np.allclose(P[0], P0, rtol=1e-13, atol=0)
+
+
 # ---------------------------------------------------------------- shells
 
 def test_bins_integer_edges_and_isotropy():
