@@ -126,6 +126,37 @@ def measured_traffic(kernel, workload):
         return None
 
 
+def power_multipoles_leg(B, torch, plan, wl, ux, uy, uz, npart, pbar_path, log_fn, reps=20):
+    """Power-spectrum multipoles (Sec. 2, eq. PowSpecMultipole) of the bench
+    catalogue: its LOS moment spectra come from the step entry points (grid
+    assignment, LOS moments), then the shell sums are timed alone over `reps`
+    calls. P^(0) is checked against the shell power the whole path returns."""
+    import numpy as np
+    dev = ux.device
+    nl = plan.info.nl
+    grids = torch.zeros((1 + wl.interlace, wl.n, wl.n, wl.n), dtype=torch.float32, device=dev)
+    wsum = torch.zeros(1, dtype=torch.float64, device=dev)
+    B.bsp_grid_assign(plan.handle, ux, uy, uz, None, npart, grids, wsum)
+    dl = plan.spectrum_buffer()
+    B.bsp_los_moments(plan.handle, grids, wsum, dl)
+    Pl = torch.zeros((nl, wl.nbins), dtype=torch.float64, device=dev)
+    B.bsp_power_multipoles(plan.handle, dl, Pl)
+    plan.sync()
+    del grids
+    B.bsp_set_timing(plan.handle, True)
+    for _ in range(reps):
+        B.bsp_power_multipoles(plan.handle, dl, Pl)
+    ms, n, amt = B.bsp_stage_times(plan.handle)["power_multipoles"]
+    B.bsp_set_timing(plan.handle, False)
+    avg_s = ms / n * 1e-3
+    p0 = Pl[0].cpu().numpy()
+    pb = pbar_path.cpu().numpy()
+    log_fn(f"power multipoles: {avg_s * 1e3:.3f} ms per call")
+    return {"ms": avg_s * 1e3, "launches": n, "algorithmic_bytes": amt / n, "achieved_GBps": amt / n / avg_s / 1e9,
+            "frac_hbm": amt / n / avg_s / PEAK_HBM, "P0_vs_path_Pbar": float(np.linalg.norm(p0 - pb) / np.linalg.norm(pb)),
+            "P_l_first_bins": [[float(x) for x in Pl[li, :3].cpu().numpy()] for li in range(nl)]}
+
+
 def copy_calibration(nbytes, reps):
     """Plain device-to-device copies of a known size, for scaling the HBM
     counters (FETCH_SIZE, WRITE_SIZE) of a profiled run to bytes; also the
@@ -294,6 +325,7 @@ def main():
         res["roofline"] = {"kernel": kernel_of.get(dom, dom), "stage": dom, "bound": "hbm",
                            "achieved": d["achieved_GBps"], "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                            "frac": d["frac_hbm"], "traffic": traffic}
+    res["power_multipoles"] = power_multipoles_leg(B, torch, plan, wl, ux, uy, uz, npart, o_mix["Pb"], log)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         res["cpu_baseline"] = cpu_baseline(wl, u, int(ntri), log)

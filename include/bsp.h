@@ -222,18 +222,28 @@ bsp_status bsp_bispectrum_field(bsp_plan plan, const float* delta, bsp_precision
 
 /* ---------------------------------------------------------------- tracing */
 
+/* Power-spectrum multipoles (Sec. 2, eq. PowSpecMultipole): the shell average
+ * over directions of delta^(l)(k) delta^(0)(-k) / V, on the lattice
+ *   P[l][b] = V sum_{n in shell b} Re[delta^(l)(n) conj(delta^(0)(n))] / (N^6 N_b)
+ * over the full lattice (N_b modes in shell b; the n_z > 0 half of the compact
+ * spectrum stands for the pairs n, -n). delta_l: device, the compact spectrum
+ * [nl][spec] that bsp_los_moments writes. P: device double [nl][nbins]. Raw: no
+ * shot-noise term (the paper gives none; P[0] equals the Pbar output of
+ * bsp_bispectrum_multipoles). Uses nl * nbins doubles of the workspace. */
+bsp_status bsp_power_multipoles(bsp_plan plan, const void* delta_l, double* P);
+
 /* Stage timers: while enabled, each compute call records a pair of HIP events
  * on the plan's stream around the launches of every stage:
  *   0 assignment, 1 forward z pass (r2c + LOS weights), 2 forward y pass,
  *   3 forward x pass, 4 LOS combination, 5 inverse x pass (shell/modal filter),
  *   6 inverse y pass, 7 inverse z pass (c2r), 8 triple reduction,
- *   9 FP64 combination of the reduction partials.
+ *   9 FP64 combination of the reduction partials, 10 power-spectrum multipoles.
  * bsp_set_timing(plan, 1) resets and starts, 0 stops (it synchronises).
  * bsp_stage_times synchronises and returns, per stage, the summed event
  * milliseconds since the reset (ms: host double[16]), the number of timed
  * launches (launches: host int64[16], may be NULL) and the summed algorithmic
  * amount of the timed launches (amount: host double[16], may be NULL): bytes
- * each pass must read and write once on the band it keeps (stages 0-7), or
+ * each pass must read and write once on the band it keeps (stages 0-7, 10), or
  * flops of the needed triple products (stage 8: two per needed entry per
  * point plus one per pair per point). */
 bsp_status bsp_set_timing(bsp_plan plan, int32_t enable);

@@ -1673,6 +1673,21 @@ bsp_status bsp_set_timing(bsp_plan p, int32_t enable) {
   return BSP_OK;
 }
 
+bsp_status bsp_power_multipoles(bsp_plan p, const void* delta_l, double* P) {
+  if (!p || !delta_l || !P) return fail(p, BSP_ERR_ARG, "null argument");
+  bsp_status s = need_ws(p, align_up((size_t)p->nl * p->nbins * sizeof(double)));
+  if (s != BSP_OK) return s;
+  double* psum = reinterpret_cast<double*>(p->ws);
+  // algorithmic bytes: every moment's spectrum read once at the shell modes
+  double modes = 0.0;
+  for (int b = 0; b < p->nbins; ++b) modes += (double)p->row_support32[b];
+  StageTimer t(p, 10, modes * p->nl * 8.0);
+  HIPCHK(launch_power_multipoles(reinterpret_cast<const float2*>(delta_l), p->spec, p->nl, p->c, p->cz,
+                                 p->d_bin_of_n2, p->n2max, p->nbins, p->d_nb_modes, p->V / std::pow((double)p->N, 6),
+                                 psum, P, p->stream));
+  return BSP_OK;
+}
+
 bsp_status bsp_stage_times(bsp_plan p, double* ms, int64_t* launches, double* amount) {
   if (!p || !ms) return fail(p, BSP_ERR_ARG, "null argument");
   HIPCHK(hipStreamSynchronize(p->stream));

@@ -138,6 +138,64 @@ __global__ __launch_bounds__(256) void k_shell_power(const float2* __restrict__ 
     if (hist[b] != 0.0) unsafeAtomicAdd(&psum[b], hist[b]);
 }
 
+// Power-spectrum multipoles (Sec. 2, eq. PowSpecMultipole): per shell b and
+// moment l, sum over the full lattice of Re[delta^(l)(n) conj(delta^(0)(n))];
+// the compact cube holds n_z >= 0, so n_z > 0 entries stand for the pair n, -n.
+__global__ __launch_bounds__(256) void k_power_multipoles(const float2* __restrict__ dl, int64_t ell_stride, int nl,
+                                                          int c, int cz, const int32_t* __restrict__ bin_of_n2,
+                                                          int n2max, int nbins, double* __restrict__ psum) {
+  extern __shared__ double hist[];  // [nl][nbins]
+  for (int b = threadIdx.x; b < nl * nbins; b += blockDim.x) hist[b] = 0.0;
+  __syncthreads();
+  const int w = 2 * c + 1;
+  const int64_t cube = (int64_t)w * w * cz;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < cube;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int kz = (int)(idx % cz);
+    if (kz > c) continue;
+    const int64_t rest = idx / cz;
+    const int ny = (int)(rest % w) - c, nx = (int)(rest / w) - c;
+    const int n2 = nx * nx + ny * ny + kz * kz;
+    if (n2 > n2max) continue;
+    const int b = bin_of_n2[n2];
+    if (b < 0) continue;
+    const double m = kz == 0 ? 1.0 : 2.0;
+    const float2 d0 = dl[idx];
+    for (int li = 0; li < nl; ++li) {
+      const float2 v = li ? dl[li * ell_stride + idx] : d0;
+      atomicAdd(&hist[li * nbins + b], m * ((double)v.x * d0.x + (double)v.y * d0.y));
+    }
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < nl * nbins; b += blockDim.x)
+    if (hist[b] != 0.0) unsafeAtomicAdd(&psum[b], hist[b]);
+}
+
+// P^(l)_b = scale * psum[l][b] / N_b (scale = V / N^6).
+__global__ void k_power_finalize(const double* __restrict__ psum, int nl, int nbins,
+                                 const int64_t* __restrict__ nb_modes, double scale, double* __restrict__ P) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nl * nbins) return;
+  const int64_t nm = nb_modes[i % nbins];
+  P[i] = nm > 0 ? scale * psum[i] / (double)nm : 0.0;
+}
+
+hipError_t launch_power_multipoles(const float2* delta_l, int64_t ell_stride, int nl, int c, int cz,
+                                   const int32_t* bin_of_n2, int n2max, int nbins, const int64_t* nb_modes,
+                                   double scale, double* psum, double* P, hipStream_t s) {
+  if (nl < 1 || nbins < 1 || (size_t)nl * nbins * sizeof(double) > 64 * 1024) return hipErrorInvalidValue;
+  hipError_t e = hipMemsetAsync(psum, 0, (size_t)nl * nbins * sizeof(double), s);
+  if (e != hipSuccess) return e;
+  const int64_t cube = (int64_t)(2 * c + 1) * (2 * c + 1) * cz;
+  int64_t blocks = (cube + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_power_multipoles, dim3((unsigned)blocks), dim3(256), (size_t)nl * nbins * sizeof(double), s,
+                     delta_l, ell_stride, nl, c, cz, bin_of_n2, n2max, nbins, psum);
+  hipLaunchKernelGGL(k_power_finalize, dim3((unsigned)((nl * nbins + 255) / 256)), dim3(256), 0, s, psum, nl, nbins,
+                     nb_modes, scale, P);
+  return hipGetLastError();
+}
+
 hipError_t launch_los_combine(const float2* X, float2* delta_l, const LosDesc& d, hipStream_t s) {
   const int64_t cube = (int64_t)(2 * d.c + 1) * (2 * d.c + 1) * d.cz;
   hipLaunchKernelGGL((k_los_combine<float>), dim3((unsigned)((cube + 255) / 256)), dim3(256), 0, s, X, delta_l, d);

@@ -148,6 +148,43 @@ def test_los_moments_against_oracle(los, interlace, lmax):
         assert e < 2e-5, (li, e)
 
 
+@pytest.mark.parametrize("los,interlace,lmax", [(0, 0, 4), (1, 1, 4), (1, 0, 2)])
+def test_power_multipoles_against_oracle(los, interlace, lmax):
+    """eq. (PowSpecMultipole) from the LOS moment spectra of a clustered
+    redshift-space catalogue, against the FP64 oracle (bins of 2 k_f)."""
+    say("power-multipoles", los, interlace, lmax)
+    n, box, k0, dk, nb = 32, 200.0, 2.0, 2.0, 5
+    obs = np.array([-300.0, -200.0, -250.0])
+    u = _catalogue(n, 30000, 13)
+    plan = B.Plan(n=n, box=box, nbins=nb, k0=k0, dk=dk, lmax=lmax, interlace=interlace, los=los, observer=obs)
+    info = plan.info
+    grids = torch.zeros((1 + interlace, n, n, n), dtype=torch.float32, device=DEV)
+    wsum = torch.zeros(1, dtype=torch.float64, device=DEV)
+    B.bsp_grid_assign(plan.handle, dev(u[0]), dev(u[1]), dev(u[2]), None, u[0].size, grids, wsum)
+    dl = plan.spectrum_buffer()
+    B.bsp_los_moments(plan.handle, grids, wsum, dl)
+    P = torch.zeros((info.nl, nb), dtype=torch.float64, device=DEV)
+    B.bsp_power_multipoles(plan.handle, dl, P)
+    plan.sync()
+    got = P.cpu().numpy()
+    spec, _ = O.spectrum_from_catalogue(*u, n, lmax, obs if los else None, window=1, interlace=interlace)
+    ref, _ = O.power_multipoles(spec, n, k0, dk, nb, box)
+    s0 = np.linalg.norm(ref[0])
+    for li in range(info.nl):
+        e = np.linalg.norm(got[li] - ref[li]) / max(np.linalg.norm(ref[li]), 0.01 * s0)
+        say("  l", 2 * li, "err", e)
+        assert e < 2e-5, (li, e)
+    plan.close()
+
+
+def test_power_multipoles_rejects_null():
+    plan = B.Plan(n=16, box=100.0, nbins=2, k0=2.0, dk=2.0)
+    P = torch.zeros((1, 2), dtype=torch.float64, device=DEV)
+    with pytest.raises(B.BspError):
+        B.bsp_power_multipoles(plan.handle, None, P)
+    plan.close()
+
+
 def test_grid_entry_against_oracle():
     say("grid-entry")
     n = 32
