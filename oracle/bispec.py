@@ -39,7 +39,7 @@ __all__ = [
     "legendre_moments", "legendre_moments_direct", "bin_edges4", "bin_of_n2",
     "n2_grid_half", "shell_field", "triangle_list", "triangle_counts_fft",
     "triangle_counts_brute", "closed_triangle_sum_brute", "binned_triple_sums",
-    "binned_bispectrum", "shell_power", "power_multipoles", "shot_noise_binned", "modal_modes",
+    "binned_bispectrum", "shell_power", "power_multipoles", "skew_spectra", "shot_noise_binned", "modal_modes",
     "modal_q", "modal_filter", "modal_fields", "modal_numerators", "gram_matrix",
     "modal_solve", "modal_shot_noise", "batch_covariance", "spectrum_from_catalogue",
     "spectrum_from_field", "estimate", "Geometry", "n2_max_of",
@@ -514,6 +514,40 @@ def power_multipoles(spec_l: Sequence[np.ndarray], n: int, k0: float, dk: float,
             prod = np.real(s[sel] * np.conj(spec_l[0][sel]))
             P[li, b] = V * float((prod * m[sel]).sum()) / (float(n) ** 6 * Nb[b]) if Nb[b] else 0.0
     return P, Nb
+
+
+def skew_spectra(spec_l: Sequence[np.ndarray], n: int, nr: int, k0: float, dk: float, nb: int, box: float):
+    """Skew-spectrum multipoles S_{*,l} of Sec. 3.2 (the estimator after
+    eq. skewspecQ, with Q the convolution delta^(0) * delta^(0)): the shell
+    average over directions of [delta^(0) * delta^(0)](-k) delta^(l)(k) / V.
+
+    The product is formed in real space: d(x) is the unnormalised inverse DFT at
+    N' of delta^(0) kept on the union of the bins, Q(n) = DFT[d^2](n) at N'
+    (no wrap-around for |n_a| <= c while 3 c < N'), and on the lattice
+      S^l_b = V sum_{n in b} Re[conj(Q(n)) delta^(l)(n)] / (N^9 N'^3 N_b)
+    over the full lattice (the 1/V and the band are readings; with them
+    S^l_b N_b = V / (N^9 N'^3) sum_{b2, b3} T^l(b, b2, b3), the discrete form of
+    S = int d^3q / (2 pi)^3 B(k, q, |k + q|)). Returns (S [nl][nb], N_b)."""
+    n2 = n2_grid_half(nr)
+    bins = bin_of_n2(n2, k0, dk, nb)
+    specs = [_crop_spec(s, n, nr) for s in spec_l]
+    d = shell_field(specs[0], bins >= 0, nr)
+    Q = forward(d * d)
+    mult = np.full(nr // 2 + 1, 2.0)
+    mult[0] = 1.0
+    if nr % 2 == 0:
+        mult[-1] = 1.0
+    m = np.broadcast_to(mult[None, None, :], n2.shape)
+    V = box ** 3
+    S = np.zeros((len(specs), nb))
+    Nb = np.empty(nb, np.int64)
+    for b in range(nb):
+        sel = bins == b
+        Nb[b] = int(round(m[sel].sum()))
+        for li, sp in enumerate(specs):
+            prod = np.real(np.conj(Q[sel]) * sp[sel])
+            S[li, b] = V * float((prod * m[sel]).sum()) / (float(n) ** 9 * float(nr) ** 3 * Nb[b]) if Nb[b] else 0.0
+    return S, Nb
 
 
 def shot_noise_binned(B0: np.ndarray, Pbar: np.ndarray, tris, nbar: float) -> np.ndarray:

@@ -210,6 +210,73 @@ def test_power_multipole_monopole_is_shell_power():
     assert np.allclose(P[0], P0, rtol=1e-13, atol=0)
 
 
+# ---------------------------------------------------------------- skew spectra
+
+def test_skew_spectra_sum_rule():
+    """S^l_b N_b = V / (N^9 N'^3) sum over all (b2, b3) of the binned triple sums
+    T^l(b, b2, b3) = sum_x D^l_b D^0_b2 D^0_b3 (the skew spectrum integrates the
+    bispectrum over the other two sides), with N != N' and a varying LOS."""
+    n, nr, box, k0, dk, nb = 32, 24, 200.0, 2.0, 2.0, 3
+    r = rng(31)
+    d = r.standard_normal((n, n, n))
+    obs = np.array([-40.0, -30.0, -55.0])
+    spec = O.spectrum_from_field([d], [0.0], n, 4, obs, None)
+    S, Nb = O.skew_spectra(spec, n, nr, k0, dk, nb, box)
+    tris = [(b, b2, b3) for b in range(nb) for b2 in range(nb) for b3 in range(nb)]
+    _, T = O.binned_triple_sums(spec, n, nr, k0, dk, nb, tris)
+    V = box ** 3
+    for li in range(3):
+        for b in range(nb):
+            rhs = V * T[li, b * nb * nb:(b + 1) * nb * nb].sum() / (float(n) ** 9 * float(nr) ** 3)
+            scale = V * np.abs(T[li, b * nb * nb:(b + 1) * nb * nb]).sum() / (float(n) ** 9 * float(nr) ** 3)
+            assert abs(S[li, b] * Nb[b] - rhs) <= 1e-10 * scale, (li, b)
+
+
+def test_skew_spectra_brute_convolution():
+    """Q(n) = N'^3 sum_q delta^0(q) delta^0(n - q) over q and n - q in the bins'
+    union, summed directly over the full lattice (plane-parallel LOS)."""
+    n, box, k0, dk, nb = 16, 100.0, 2.0, 2.0, 2
+    d = rng(32).standard_normal((n, n, n))
+    spec = O.spectrum_from_field([d], [0.0], n, 2, None, None)
+    S, Nb = O.skew_spectra(spec, n, n, k0, dk, nb, box)
+    fr = np.fft.fftfreq(n, 1.0 / n).astype(int)
+    F0 = np.fft.fftn(d)
+    # delta^(2) on the full lattice: (5) L_2(n_z / |n|) delta(n) for a LOS along z
+    nx, ny, nz = np.meshgrid(fr, fr, fr, indexing="ij")
+    n2 = nx ** 2 + ny ** 2 + nz ** 2
+    mu2 = nz ** 2 / np.maximum(n2, 1)
+    F2 = 5 * 0.5 * (3 * mu2 - 1) * F0
+    bins = O.bin_of_n2(n2, k0, dk, nb)
+    band = np.argwhere(bins >= 0)
+    V = box ** 3
+    for b in range(nb):
+        acc = [0.0, 0.0]
+        for (i, j, k) in np.argwhere(bins == b):
+            q = 0.0j
+            for (a, bb, cc) in band:
+                i2, j2, k2 = (i - a) % n, (j - bb) % n, (k - cc) % n
+                if bins[i2, j2, k2] >= 0:
+                    q += F0[a, bb, cc] * F0[i2, j2, k2]
+            Q = float(n) ** 3 * q
+            acc[0] += float(np.real(np.conj(Q) * F0[i, j, k]))
+            acc[1] += float(np.real(np.conj(Q) * F2[i, j, k]))
+        for li in range(2):
+            ref = V * acc[li] / (float(n) ** 12 * Nb[b])
+            assert abs(S[li, b] - ref) <= 1e-9 * abs(V * acc[0] / (float(n) ** 12 * Nb[b])), (b, li, S[li, b], ref)
+
+
+def test_skew_spectra_vanish_without_closed_triangles():
+    """A single plane wave at |n| = 5: delta^(l) lives on n = +-5 x-hat, the
+    square of the band-limited field only on 0 and +-10 x-hat, so no triangle
+    closes and S = 0 on every shell."""
+    n, box, k0, dk, nb = 32, 100.0, 2.0, 2.0, 5
+    x = np.arange(n)
+    d = np.cos(2 * np.pi * 5 * x / n)[:, None, None] * np.ones((1, n, n))
+    spec = O.spectrum_from_field([d], [0.0], n, 2, None, None)
+    S, _ = O.skew_spectra(spec, n, n, k0, dk, nb, box)
+    assert np.max(np.abs(S)) < 1e-12 * (float(n) ** 3)
+
+
 # ---------------------------------------------------------------- shells
 
 def test_bins_integer_edges_and_isotropy():
