@@ -126,11 +126,12 @@ def measured_traffic(kernel, workload):
         return None
 
 
-def power_multipoles_leg(B, torch, plan, wl, ux, uy, uz, npart, pbar_path, log_fn, reps=20):
-    """Power-spectrum multipoles (Sec. 2, eq. PowSpecMultipole) of the bench
-    catalogue: its LOS moment spectra come from the step entry points (grid
-    assignment, LOS moments), then the shell sums are timed alone over `reps`
-    calls. P^(0) is checked against the shell power the whole path returns."""
+def spectra_legs(B, torch, plan, wl, ux, uy, uz, npart, pbar_path, log_fn, reps=20, skew_reps=5):
+    """Power-spectrum multipoles (Sec. 2, eq. PowSpecMultipole) and skew-spectrum
+    multipoles (Sec. 3.2) of the bench catalogue: its LOS moment spectra come
+    from the step entry points (grid assignment, LOS moments), then each
+    estimator is timed alone (`reps` and `skew_reps` calls). P^(0) is checked
+    against the shell power the whole path returns."""
     import numpy as np
     dev = ux.device
     nl = plan.info.nl
@@ -152,9 +153,23 @@ def power_multipoles_leg(B, torch, plan, wl, ux, uy, uz, npart, pbar_path, log_f
     p0 = Pl[0].cpu().numpy()
     pb = pbar_path.cpu().numpy()
     log_fn(f"power multipoles: {avg_s * 1e3:.3f} ms per call")
-    return {"ms": avg_s * 1e3, "launches": n, "algorithmic_bytes": amt / n, "achieved_GBps": amt / n / avg_s / 1e9,
-            "frac_hbm": amt / n / avg_s / PEAK_HBM, "P0_vs_path_Pbar": float(np.linalg.norm(p0 - pb) / np.linalg.norm(pb)),
-            "P_l_first_bins": [[float(x) for x in Pl[li, :3].cpu().numpy()] for li in range(nl)]}
+    pm = {"ms": avg_s * 1e3, "launches": n, "algorithmic_bytes": amt / n, "achieved_GBps": amt / n / avg_s / 1e9,
+          "frac_hbm": amt / n / avg_s / PEAK_HBM, "P0_vs_path_Pbar": float(np.linalg.norm(p0 - pb) / np.linalg.norm(pb)),
+          "P_l_first_bins": [[float(x) for x in Pl[li, :3].cpu().numpy()] for li in range(nl)]}
+    Sl = torch.zeros((nl, wl.nbins), dtype=torch.float64, device=dev)
+    B.bsp_skew_spectra(plan.handle, dl, Sl)
+    plan.sync()
+    B.bsp_set_timing(plan.handle, True)
+    for _ in range(skew_reps):
+        B.bsp_skew_spectra(plan.handle, dl, Sl)
+    ms, n, amt = B.bsp_stage_times(plan.handle)["skew_spectra"]
+    B.bsp_set_timing(plan.handle, False)
+    avg_s = ms / n * 1e-3
+    log_fn(f"skew spectra: {avg_s * 1e3:.3f} ms per call")
+    sk = {"ms": avg_s * 1e3, "launches": n, "algorithmic_bytes": amt / n, "achieved_GBps": amt / n / avg_s / 1e9,
+          "frac_hbm": amt / n / avg_s / PEAK_HBM,
+          "S_l_first_bins": [[float(x) for x in Sl[li, :3].cpu().numpy()] for li in range(nl)]}
+    return pm, sk
 
 
 def copy_calibration(nbytes, reps):
@@ -325,7 +340,7 @@ def main():
         res["roofline"] = {"kernel": kernel_of.get(dom, dom), "stage": dom, "bound": "hbm",
                            "achieved": d["achieved_GBps"], "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                            "frac": d["frac_hbm"], "traffic": traffic}
-    res["power_multipoles"] = power_multipoles_leg(B, torch, plan, wl, ux, uy, uz, npart, o_mix["Pb"], log)
+    res["power_multipoles"], res["skew_spectra"] = spectra_legs(B, torch, plan, wl, ux, uy, uz, npart, o_mix["Pb"], log)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         res["cpu_baseline"] = cpu_baseline(wl, u, int(ntri), log)

@@ -232,18 +232,34 @@ bsp_status bsp_bispectrum_field(bsp_plan plan, const float* delta, bsp_precision
  * bsp_bispectrum_multipoles). Uses nl * nbins doubles of the workspace. */
 bsp_status bsp_power_multipoles(bsp_plan plan, const void* delta_l, double* P);
 
+/* Skew-spectrum multipoles (Sec. 3.2, the estimator after eq. skewspecQ with
+ * the convolution as quadratic form): the shell average over directions of
+ * [delta^(0) * delta^(0)](-k) delta^(l)(k) / V. The monopole kept on the union
+ * of the shells is transformed to real space at N' (unnormalised, as the
+ * bispectrum fields), squared, and transformed back to the compact cube
+ * (no wrap-around while 3 c < N'):
+ *   S[l][b] = V sum_{n in shell b} Re[delta^(l)(n) conj(Q(n))] / (N^9 N'^3 N_b),
+ *   Q = DFT_N'[d^2], d = IDFT_N'[delta^(0) on the shells].
+ * The 1/V (absent from the printed estimator, present in its defining relation
+ * and in the power-spectrum estimator) and the band are readings; with them
+ * S[l][b] N_b = V / (N^9 N'^3) sum over all (b2, b3) of the triple sums
+ * sum_x D^l_b D^0_b2 D^0_b3. delta_l: device, the compact spectrum [nl][spec]
+ * of bsp_los_moments. S: device double [nl][nbins]. Uses the workspace. */
+bsp_status bsp_skew_spectra(bsp_plan plan, const void* delta_l, double* S);
+
 /* Stage timers: while enabled, each compute call records a pair of HIP events
  * on the plan's stream around the launches of every stage:
  *   0 assignment, 1 forward z pass (r2c + LOS weights), 2 forward y pass,
  *   3 forward x pass, 4 LOS combination, 5 inverse x pass (shell/modal filter),
  *   6 inverse y pass, 7 inverse z pass (c2r), 8 triple reduction,
- *   9 FP64 combination of the reduction partials, 10 power-spectrum multipoles.
+ *   9 FP64 combination of the reduction partials, 10 power-spectrum multipoles,
+ *   11 skew spectra (the whole call; its transforms also count in stages 5-7).
  * bsp_set_timing(plan, 1) resets and starts, 0 stops (it synchronises).
  * bsp_stage_times synchronises and returns, per stage, the summed event
  * milliseconds since the reset (ms: host double[16]), the number of timed
  * launches (launches: host int64[16], may be NULL) and the summed algorithmic
  * amount of the timed launches (amount: host double[16], may be NULL): bytes
- * each pass must read and write once on the band it keeps (stages 0-7, 10), or
+ * each pass must read and write once on the band it keeps (stages 0-7, 10, 11), or
  * flops of the needed triple products (stage 8: two per needed entry per
  * point plus one per pair per point). */
 bsp_status bsp_set_timing(bsp_plan plan, int32_t enable);

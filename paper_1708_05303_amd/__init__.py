@@ -21,8 +21,8 @@ __all__ = [
     "bsp_plan_info", "bsp_workspace_size", "bsp_set_workspace", "bsp_sync", "bsp_precompute",
     "bsp_geometry", "bsp_grid_assign", "bsp_fft_r2c", "bsp_fft_c2r", "bsp_los_moments", "bsp_grid_entry",
     "bsp_filter_fields", "bsp_triple_reduce", "bsp_modal_coeffs", "bsp_bispectrum_multipoles",
-    "bsp_bispectrum_field", "bsp_batch_run", "bsp_batch_covariance", "bsp_power_multipoles", "bsp_set_timing",
-    "bsp_stage_times", "STAGES", "EXPORTED",
+    "bsp_bispectrum_field", "bsp_batch_run", "bsp_batch_covariance", "bsp_power_multipoles", "bsp_skew_spectra",
+    "bsp_set_timing", "bsp_stage_times", "STAGES", "EXPORTED",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -39,10 +39,10 @@ EXPORTED = [
     "bsp_set_workspace", "bsp_sync", "bsp_precompute", "bsp_geometry", "bsp_grid_assign", "bsp_fft_r2c",
     "bsp_fft_c2r", "bsp_los_moments", "bsp_grid_entry", "bsp_filter_fields", "bsp_triple_reduce",
     "bsp_modal_coeffs", "bsp_bispectrum_multipoles", "bsp_bispectrum_field", "bsp_batch_run",
-    "bsp_batch_covariance", "bsp_power_multipoles", "bsp_set_timing", "bsp_stage_times",
+    "bsp_batch_covariance", "bsp_power_multipoles", "bsp_skew_spectra", "bsp_set_timing", "bsp_stage_times",
 ]
 STAGES = ["assign", "fwd_z", "fwd_y", "fwd_x", "los_combine", "inv_x_filter", "inv_y", "inv_z", "reduce",
-          "reduce_combine", "power_multipoles"]
+          "reduce_combine", "power_multipoles", "skew_spectra"]
 
 
 class BspError(RuntimeError):
@@ -110,6 +110,7 @@ def lib():
         "bsp_batch_run": [_vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp],
         "bsp_batch_covariance": [_vp, _i32, _i32, _vp, _vp],
         "bsp_power_multipoles": [_vp, _vp, _vp],
+        "bsp_skew_spectra": [_vp, _vp, _vp],
         "bsp_set_timing": [_vp, _i32],
         "bsp_stage_times": [_vp, _vp, _vp, _vp],
     }
@@ -269,6 +270,10 @@ def bsp_batch_covariance(x, m, d, cov, stream: int = 0):
 
 def bsp_power_multipoles(plan, delta_l, P):
     _check(lib().bsp_power_multipoles(plan, _dptr(delta_l), _dptr(P)), plan)
+
+
+def bsp_skew_spectra(plan, delta_l, S):
+    _check(lib().bsp_skew_spectra(plan, _dptr(delta_l), _dptr(S)), plan)
 
 
 def bsp_set_timing(plan, enable: bool):

@@ -284,6 +284,8 @@ struct bsp_plan_s {
   // (n_y, n_z) columns it leaves nonzero (algorithmic bytes of the inverse passes)
   std::vector<int64_t> row_support32, row_cols32;
   std::vector<int32_t> field_row32;  // tab32 row of each main pipeline field
+  int32_t band_row32 = 0;            // tab32 row of the union of the shells
+  int32_t* d_band_meta = nullptr;    // {0, band_row32}: l slot and table row of the band-limited monopole
   std::vector<int> field_c;   // per main-pipeline field
   int32_t *d_field_ell = nullptr, *d_field_tab = nullptr;
   int32_t *d_ones_ell = nullptr, *d_pre_tab = nullptr;  // precompute: all ell 0, table row = index
@@ -1068,13 +1070,15 @@ bsp_status bsp_plan_create(bsp_plan* out, const bsp_geom* g, const bsp_modal_bas
   p->d_bin_of_n2 = upload(p, p->bin_of_n2);
   p->d_nb_modes = upload(p, p->nb_modes);
   const int tl = p->n2max + 1;
-  std::vector<float> tab32((size_t)(p->nbins + p->P) * tl, 0.f);
+  // tab32 rows: nbins shells, P modal weights, then the union of the shells
+  std::vector<float> tab32((size_t)(p->nbins + p->P + 1) * tl, 0.f);
   const int nrow64 = p->nbins + (p->modal ? p->nU + 2 * p->P : 0);
   std::vector<double> tab64((size_t)nrow64 * tl, 0.0);
   for (int n2 = 0; n2 < tl; ++n2) {
     const int b = p->bin_of_n2[n2];
     if (b >= 0) {
       tab32[(size_t)b * tl + n2] = 1.f;
+      tab32[(size_t)(p->nbins + p->P) * tl + n2] = 1.f;
       tab64[(size_t)b * tl + n2] = 1.0;
     }
   }
@@ -1150,6 +1154,8 @@ bsp_status bsp_plan_create(bsp_plan* out, const bsp_geom* g, const bsp_modal_bas
   p->d_field_ell = upload(p, fe);
   p->d_field_tab = upload(p, ft);
   p->field_row32 = ft;
+  p->band_row32 = p->nbins + p->P;
+  p->d_band_meta = upload(p, std::vector<int32_t>{0, p->band_row32});
   std::vector<int32_t> zeros(std::max(nrow64, 1), 0), iota(std::max(nrow64, 1));
   for (int i = 0; i < (int)iota.size(); ++i) iota[i] = i;
   p->d_ones_ell = upload(p, zeros);
@@ -1171,7 +1177,7 @@ bsp_status bsp_plan_create(bsp_plan* out, const bsp_geom* g, const bsp_modal_bas
     return fail(nullptr, BSP_ERR_ARG, "reduction schedule could not be built (too many fields or modes)");
   }
   if (!p->tw32_N || !p->tw32_Nr || !p->tw64_Nr || !p->d_bin_of_n2 || !p->d_tab32 || !p->d_tab64 || !p->d_rng32 ||
-      !p->d_rng64 || !p->d_err ||
+      !p->d_rng64 || !p->d_band_meta || !p->d_err ||
       !p->d_field_ell || !p->d_field_tab || !p->d_ones_ell || !p->d_pre_tab || !p->d_nb_modes) {
     delete p;
     return fail(nullptr, BSP_ERR_HIP, "device allocation of plan tables failed");
@@ -1682,9 +1688,82 @@ bsp_status bsp_power_multipoles(bsp_plan p, const void* delta_l, double* P) {
   double modes = 0.0;
   for (int b = 0; b < p->nbins; ++b) modes += (double)p->row_support32[b];
   StageTimer t(p, 10, modes * p->nl * 8.0);
-  HIPCHK(launch_power_multipoles(reinterpret_cast<const float2*>(delta_l), p->spec, p->nl, p->c, p->cz,
-                                 p->d_bin_of_n2, p->n2max, p->nbins, p->d_nb_modes, p->V / std::pow((double)p->N, 6),
-                                 psum, P, p->stream));
+  const float2* dl = reinterpret_cast<const float2*>(delta_l);
+  HIPCHK(launch_shell_cross(dl, p->spec, p->nl, dl, p->c, p->cz, p->d_bin_of_n2, p->n2max, p->nbins, p->d_nb_modes,
+                            p->V / std::pow((double)p->N, 6), psum, P, p->stream));
+  return BSP_OK;
+}
+
+bsp_status bsp_skew_spectra(bsp_plan p, const void* delta_l, double* S) {
+  if (!p || !delta_l || !S) return fail(p, BSP_ERR_ARG, "null argument");
+  const int Nr = p->Nr, c = p->c, cz = p->cz, w = 2 * c + 1;
+  const size_t dbytes = align_up((size_t)Nr * Nr * Nr * sizeof(float));
+  const size_t zb = align_up((size_t)Nr * Nr * cz * sizeof(float2)), yb = align_up((size_t)Nr * w * cz * sizeof(float2));
+  const size_t scr = std::max(inv_scratch(p, 2, sizeof(float2)), zb + yb);
+  const size_t acc = align_up((size_t)p->nl * p->nbins * sizeof(double));
+  bsp_status s = need_ws(p, dbytes + scr + acc);
+  if (s != BSP_OK) return s;
+  float* d = reinterpret_cast<float*>(p->ws);
+  char* sc = p->ws + dbytes;
+  double* psum = reinterpret_cast<double*>(p->ws + dbytes + scr);
+  const float2* dl = reinterpret_cast<const float2*>(delta_l);
+  // algorithmic bytes of the passes: the band-limited monopole's inverse
+  // transform (its modes read, nonzero columns, y output, real field written),
+  // the square (read + write), the pruned forward transform of the square to
+  // the compact cube, and the shell sums (nl moments and the partner spectrum)
+  const double C1 = c + 1.0, W1 = w, R = Nr, sup = (double)p->row_support32[p->band_row32],
+               cols = (double)p->row_cols32[p->band_row32];
+  const double amount = (sup + 2.0 * R * cols + 2.0 * R * R * C1) * 8.0 + R * R * R * 4.0 + R * R * R * 8.0 +
+                        R * R * R * 4.0 + R * R * C1 * 8.0 + R * C1 * 8.0 * (R + W1) + W1 * C1 * 8.0 * (R + W1) +
+                        (p->nl + 1.0) * sup * 8.0;
+  StageTimer t(p, 11, amount);
+  // d(x): unnormalised inverse DFT at N' of delta^(0) kept on the union of the shells
+  const std::vector<int> cf{c};
+  s = inverse_fields<float>(p, dl, p->spec, 1, p->d_band_meta, p->d_band_meta + 1, p->d_tab32, p->d_rng32, d, sc, 2,
+                            cf, &p->band_row32);
+  if (s != BSP_OK) return s;
+  HIPCHK(launch_square(d, (int64_t)Nr * Nr * Nr, p->stream));
+  // Q = DFT[d^2] at N', pruned to the compact cube |n_a| <= c
+  float2* Z = reinterpret_cast<float2*>(sc);
+  float2* Y = reinterpret_cast<float2*>(sc + zb);
+  FwdZDesc fz{};
+  fz.ngrid = 1;
+  fz.nlos = 1;
+  fz.contrast = 0;
+  fz.plane = 1;
+  fz.cout = c + 1;
+  fz.zs = cz;
+  HIPCHK(launch_fwd_z_f32(Nr, d, Z, fz, p->tw32_Nr, p->stream));
+  PassDesc py{};
+  py.nouter = Nr;
+  py.in_outer = (int64_t)Nr * cz;
+  py.out_outer = (int64_t)w * cz;
+  py.in_row = cz;
+  py.out_row = cz;
+  py.ncols = cz;
+  py.in_rows = Nr;
+  py.in_off = 0;
+  py.out_rows = w;
+  py.out_off = c;
+  set1d(py);
+  HIPCHK(launch_c2c_f32(Nr, -1, Z, Y, py, nullptr, p->tw32_Nr, p->stream));
+  PassDesc px{};
+  px.nouter = 1;
+  px.in_outer = (int64_t)Nr * w * cz;
+  px.out_outer = (int64_t)w * w * cz;
+  px.in_row = (int64_t)w * cz;
+  px.out_row = (int64_t)w * cz;
+  px.ncols = w * cz;
+  px.in_rows = Nr;
+  px.in_off = 0;
+  px.out_rows = w;
+  px.out_off = c;
+  set1d(px);
+  float2* X = Z;  // Z is dead once Y exists
+  HIPCHK(launch_c2c_f32(Nr, -1, Y, X, px, nullptr, p->tw32_Nr, p->stream));
+  // S^l_b = V sum_{n in b} Re[delta^(l) conj Q] / (N^9 N'^3 N_b)
+  HIPCHK(launch_shell_cross(dl, p->spec, p->nl, X, c, cz, p->d_bin_of_n2, p->n2max, p->nbins, p->d_nb_modes,
+                            p->V / (std::pow((double)p->N, 9) * std::pow((double)Nr, 3)), psum, S, p->stream));
   return BSP_OK;
 }
 

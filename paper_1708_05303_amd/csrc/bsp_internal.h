@@ -127,11 +127,14 @@ hipError_t launch_los_combine(const float2* X, float2* delta_l, const LosDesc& d
 hipError_t launch_los_combine_f64(const double2* X, double2* delta_l, const LosDesc& d, hipStream_t s);
 hipError_t launch_shell_power(const float2* delta0, int c, int cz, const int32_t* bin_of_n2,
                               int n2max, int nbins, double* psum, hipStream_t s);
-// Power-spectrum multipoles P[l][b] = scale * sum_{n in b} Re[delta^(l) conj delta^(0)] / N_b
-// over the full lattice (psum: device scratch of nl * nbins doubles).
-hipError_t launch_power_multipoles(const float2* delta_l, int64_t ell_stride, int nl, int c, int cz,
-                                   const int32_t* bin_of_n2, int n2max, int nbins, const int64_t* nb_modes,
-                                   double scale, double* psum, double* P, hipStream_t s);
+// Shell cross sums out[l][b] = scale * sum_{n in b} Re[delta^(l)(n) conj X(n)] / N_b over
+// the full lattice, X a compact spectrum of the delta^(l) layout (psum: device
+// scratch of nl * nbins doubles).
+hipError_t launch_shell_cross(const float2* delta_l, int64_t ell_stride, int nl, const float2* partner, int c, int cz,
+                              const int32_t* bin_of_n2, int n2max, int nbins, const int64_t* nb_modes, double scale,
+                              double* psum, double* out, hipStream_t s);
+// x <- x^2 over n floats (n a multiple of 4, x 16-byte aligned).
+hipError_t launch_square(float* x, int64_t n, hipStream_t s);
 
 // Triple reduction (reduce.hip).
 hipError_t launch_reduce(int prec, const float* fields, const ReduceDesc& d, float* partials,

@@ -138,12 +138,15 @@ __global__ __launch_bounds__(256) void k_shell_power(const float2* __restrict__ 
     if (hist[b] != 0.0) unsafeAtomicAdd(&psum[b], hist[b]);
 }
 
-// Power-spectrum multipoles (Sec. 2, eq. PowSpecMultipole): per shell b and
-// moment l, sum over the full lattice of Re[delta^(l)(n) conj(delta^(0)(n))];
-// the compact cube holds n_z >= 0, so n_z > 0 entries stand for the pair n, -n.
-__global__ __launch_bounds__(256) void k_power_multipoles(const float2* __restrict__ dl, int64_t ell_stride, int nl,
-                                                          int c, int cz, const int32_t* __restrict__ bin_of_n2,
-                                                          int n2max, int nbins, double* __restrict__ psum) {
+// Shell cross sums of the compact spectra: per shell b and moment l, the sum
+// over the full lattice of Re[delta^(l)(n) conj(X(n))], with X = delta^(0) for
+// the power-spectrum multipoles (Sec. 2, eq. PowSpecMultipole) or the transform
+// of the squared monopole field for the skew spectra (Sec. 3.2). The compact
+// cube holds n_z >= 0, so n_z > 0 entries stand for the pair n, -n.
+__global__ __launch_bounds__(256) void k_shell_cross(const float2* __restrict__ dl, int64_t ell_stride, int nl,
+                                                     const float2* __restrict__ partner, int c, int cz,
+                                                     const int32_t* __restrict__ bin_of_n2, int n2max, int nbins,
+                                                     double* __restrict__ psum) {
   extern __shared__ double hist[];  // [nl][nbins]
   for (int b = threadIdx.x; b < nl * nbins; b += blockDim.x) hist[b] = 0.0;
   __syncthreads();
@@ -160,10 +163,10 @@ __global__ __launch_bounds__(256) void k_power_multipoles(const float2* __restri
     const int b = bin_of_n2[n2];
     if (b < 0) continue;
     const double m = kz == 0 ? 1.0 : 2.0;
-    const float2 d0 = dl[idx];
+    const float2 x = partner[idx];
     for (int li = 0; li < nl; ++li) {
-      const float2 v = li ? dl[li * ell_stride + idx] : d0;
-      atomicAdd(&hist[li * nbins + b], m * ((double)v.x * d0.x + (double)v.y * d0.y));
+      const float2 v = dl[li * ell_stride + idx];
+      atomicAdd(&hist[li * nbins + b], m * ((double)v.x * x.x + (double)v.y * x.y));
     }
   }
   __syncthreads();
@@ -171,8 +174,8 @@ __global__ __launch_bounds__(256) void k_power_multipoles(const float2* __restri
     if (hist[b] != 0.0) unsafeAtomicAdd(&psum[b], hist[b]);
 }
 
-// P^(l)_b = scale * psum[l][b] / N_b (scale = V / N^6).
-__global__ void k_power_finalize(const double* __restrict__ psum, int nl, int nbins,
+// out[l][b] = scale * psum[l][b] / N_b.
+__global__ void k_shell_finalize(const double* __restrict__ psum, int nl, int nbins,
                                  const int64_t* __restrict__ nb_modes, double scale, double* __restrict__ P) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nl * nbins) return;
@@ -180,19 +183,40 @@ __global__ void k_power_finalize(const double* __restrict__ psum, int nl, int nb
   P[i] = nm > 0 ? scale * psum[i] / (double)nm : 0.0;
 }
 
-hipError_t launch_power_multipoles(const float2* delta_l, int64_t ell_stride, int nl, int c, int cz,
-                                   const int32_t* bin_of_n2, int n2max, int nbins, const int64_t* nb_modes,
-                                   double scale, double* psum, double* P, hipStream_t s) {
+hipError_t launch_shell_cross(const float2* delta_l, int64_t ell_stride, int nl, const float2* partner, int c, int cz,
+                              const int32_t* bin_of_n2, int n2max, int nbins, const int64_t* nb_modes, double scale,
+                              double* psum, double* P, hipStream_t s) {
   if (nl < 1 || nbins < 1 || (size_t)nl * nbins * sizeof(double) > 64 * 1024) return hipErrorInvalidValue;
   hipError_t e = hipMemsetAsync(psum, 0, (size_t)nl * nbins * sizeof(double), s);
   if (e != hipSuccess) return e;
   const int64_t cube = (int64_t)(2 * c + 1) * (2 * c + 1) * cz;
   int64_t blocks = (cube + 255) / 256;
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_power_multipoles, dim3((unsigned)blocks), dim3(256), (size_t)nl * nbins * sizeof(double), s,
-                     delta_l, ell_stride, nl, c, cz, bin_of_n2, n2max, nbins, psum);
-  hipLaunchKernelGGL(k_power_finalize, dim3((unsigned)((nl * nbins + 255) / 256)), dim3(256), 0, s, psum, nl, nbins,
+  hipLaunchKernelGGL(k_shell_cross, dim3((unsigned)blocks), dim3(256), (size_t)nl * nbins * sizeof(double), s,
+                     delta_l, ell_stride, nl, partner, c, cz, bin_of_n2, n2max, nbins, psum);
+  hipLaunchKernelGGL(k_shell_finalize, dim3((unsigned)((nl * nbins + 255) / 256)), dim3(256), 0, s, psum, nl, nbins,
                      nb_modes, scale, P);
+  return hipGetLastError();
+}
+
+// x <- x^2 elementwise (the real-space product of the skew spectrum).
+__global__ __launch_bounds__(256) void k_square(float4* __restrict__ x, int64_t n4) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (int64_t)gridDim.x * blockDim.x) {
+    float4 v = x[i];
+    v.x *= v.x;
+    v.y *= v.y;
+    v.z *= v.z;
+    v.w *= v.w;
+    x[i] = v;
+  }
+}
+
+hipError_t launch_square(float* x, int64_t n, hipStream_t s) {
+  if (n % 4 != 0 || (reinterpret_cast<uintptr_t>(x) & 15) != 0) return hipErrorInvalidValue;
+  const int64_t n4 = n / 4;
+  int64_t blocks = (n4 + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(k_square, dim3((unsigned)blocks), dim3(256), 0, s, reinterpret_cast<float4*>(x), n4);
   return hipGetLastError();
 }
 
