@@ -39,7 +39,8 @@ __all__ = [
     "legendre_moments", "legendre_moments_direct", "bin_edges4", "bin_of_n2",
     "n2_grid_half", "shell_field", "triangle_list", "triangle_counts_fft",
     "triangle_counts_brute", "closed_triangle_sum_brute", "binned_triple_sums",
-    "binned_bispectrum", "shell_power", "power_multipoles", "skew_spectra", "shot_noise_binned", "modal_modes",
+    "binned_bispectrum", "shell_power", "power_multipoles", "skew_spectra", "integrated_bispectrum",
+    "shot_noise_binned", "modal_modes",
     "modal_q", "modal_filter", "modal_fields", "modal_numerators", "gram_matrix",
     "modal_solve", "modal_shot_noise", "batch_covariance", "spectrum_from_catalogue",
     "spectrum_from_field", "estimate", "Geometry", "n2_max_of",
@@ -548,6 +549,66 @@ def skew_spectra(spec_l: Sequence[np.ndarray], n: int, nr: int, k0: float, dk: f
             prod = np.real(np.conj(Q[sel]) * sp[sel])
             S[li, b] = V * float((prod * m[sel]).sum()) / (float(n) ** 9 * float(nr) ** 3 * Nb[b]) if Nb[b] else 0.0
     return S, Nb
+
+
+def integrated_bispectrum(delta: np.ndarray, s: int, lmax: int, observer, window, box: float,
+                          k0: float, dk: float, nb: int):
+    """Integrated bispectrum multipoles of Sec. 3.4 (eq. integBisp and the RSD
+    estimator that follows it): iB^(l)(k) = (1/N_s) sum_i P^(l)_i(k) dbar^(0)_i
+    over the N_s = s^3 cubic sub-volumes of side M = N/s.
+
+    delta: density contrast on the N^3 grid (nodes at integer coordinates).
+    For sub-volume i with nodes origin_i + [0, M)^3:
+      F_i = DFT_M of delta on the sub-volume (unnormalised), divided by the
+            assignment window at the sub-volume frequencies (same cell size);
+            window None: no compensation;
+      dbar_i = F_i(0) / M^3, the mean overdensity of the sub-volume;
+      P^(l)_i(k_b) = V_s sum_{n in b} (2l+1) L_l(nhat . e_i) |F_i(n)|^2 / (M^6 N_b)
+            over the full lattice, V_s = (L / s)^3, the power-spectrum multipole
+            with a single line of sight e_i per sub-volume: the unit vector from
+            the observer to the sub-volume centre origin_i + (M - 1)/2 (z when
+            observer is None). The local line of sight is a reading (the
+            sub-volumes are small, so the plane-parallel form applies inside).
+    Bins (k0, dk, nb) are in units of the sub-volume fundamental 2 pi s / L.
+    Returns (iB [nl][nb], P [N_s][nl][nb], dbar [N_s], N_b)."""
+    n = delta.shape[0]
+    assert n % s == 0
+    m = n // s
+    nl = lmax // 2 + 1
+    n2 = n2_grid_half(m)
+    bins = bin_of_n2(n2, k0, dk, nb)
+    fx, fy, fz = half_freq_vectors(m)
+    kn = np.sqrt(np.maximum(n2, 1)).astype(np.float64)
+    mult = np.full(m // 2 + 1, 2.0)
+    mult[0] = 1.0
+    if m % 2 == 0:
+        mult[-1] = 1.0
+    mm = np.broadcast_to(mult[None, None, :], n2.shape)
+    Nb = np.array([int(round(mm[bins == b].sum())) for b in range(nb)], np.int64)
+    Vs = (box / s) ** 3
+    W = window_half(m, window) if window is not None else None
+    P = np.zeros((s ** 3, nl, nb))
+    dbar = np.zeros(s ** 3)
+    for i in range(s ** 3):
+        ox, oy, oz = (i // (s * s)) * m, ((i // s) % s) * m, (i % s) * m
+        F = forward(delta[ox:ox + m, oy:oy + m, oz:oz + m])
+        dbar[i] = float(np.real(F[0, 0, 0])) / float(m) ** 3
+        if W is not None:
+            F = F / W
+        if observer is None:
+            e = np.array([0.0, 0.0, 1.0])
+        else:
+            cvec = np.array([ox, oy, oz], np.float64) + 0.5 * (m - 1) - np.asarray(observer, np.float64)
+            e = cvec / np.linalg.norm(cvec)
+        mu = (fx * e[0] + fy * e[1] + fz * e[2]) / kn
+        p2 = np.abs(F) ** 2 * mm
+        for li in range(nl):
+            wl = (4 * li + 1) * legendre_poly(2 * li, mu) * p2
+            for b in range(nb):
+                sel = bins == b
+                P[i, li, b] = Vs * float(wl[sel].sum()) / (float(m) ** 6 * Nb[b]) if Nb[b] else 0.0
+    iB = np.einsum("ilb,i->lb", P, dbar) / s ** 3
+    return iB, P, dbar, Nb
 
 
 def shot_noise_binned(B0: np.ndarray, Pbar: np.ndarray, tris, nbar: float) -> np.ndarray:

@@ -277,6 +277,82 @@ def test_skew_spectra_vanish_without_closed_triangles():
     assert np.max(np.abs(S)) < 1e-12 * (float(n) ** 3)
 
 
+# ---------------------------------------------------------------- integrated bispectrum
+
+def test_integrated_bispectrum_single_volume_is_power_multipole():
+    """With one sub-volume and a line of sight along z, P^(l)_1 is the
+    power-spectrum multipole of the whole box (the LOS moment route through
+    the x-hat tensors gives (2l+1) L_l(mu) delta(n) in that limit)."""
+    n, box, k0, dk, nb = 16, 100.0, 2.0, 2.0, 3
+    d = rng(41).standard_normal((n, n, n))
+    iB, P, dbar, Nb = O.integrated_bispectrum(d, 1, 4, None, None, box, k0, dk, nb)
+    spec = O.spectrum_from_field([d], [0.0], n, 4, None, None)
+    Pref, Nb2 = O.power_multipoles(spec, n, k0, dk, nb, box)
+    assert np.array_equal(Nb, Nb2)
+    assert np.allclose(P[0], Pref, rtol=1e-11, atol=1e-11 * np.abs(Pref).max())
+    assert abs(dbar[0] - d.mean()) < 1e-14
+    assert np.allclose(iB, Pref * d.mean(), rtol=1e-11, atol=1e-11 * np.abs(Pref).max())
+
+
+def test_integrated_bispectrum_tiled_volume():
+    """A 2 x 2 x 2 tiling of one block, shifted by a different constant in each
+    copy: every sub-volume has the block's spectrum away from n = 0, so with a
+    line of sight along z iB = P_block * mean(dbar_i)."""
+    m, box, k0, dk, nb = 8, 80.0, 1.0, 1.0, 3
+    r = rng(42)
+    g = r.standard_normal((m, m, m))
+    d = np.tile(g, (2, 2, 2))
+    offs = r.uniform(-0.5, 0.5, 8)
+    for i in range(8):
+        ox, oy, oz = (i // 4) * m, ((i // 2) % 2) * m, (i % 2) * m
+        d[ox:ox + m, oy:oy + m, oz:oz + m] += offs[i]
+    iB, P, dbar, _ = O.integrated_bispectrum(d, 2, 4, None, 1, box, k0, dk, nb)
+    _, Pb, _, _ = O.integrated_bispectrum(g, 1, 4, None, 1, box / 2, k0, dk, nb)
+    assert np.allclose(dbar, g.mean() + offs, atol=1e-13)
+    for i in range(8):
+        assert np.allclose(P[i], Pb[0], rtol=1e-11, atol=1e-11 * np.abs(Pb).max())
+    assert np.allclose(iB, Pb[0] * dbar.mean(), rtol=1e-11, atol=1e-11 * np.abs(Pb).max())
+
+
+def test_integrated_bispectrum_brute_subvolume():
+    """One sub-volume of a varying-LOS, CIC-compensated run against a direct DFT
+    sum with explicit Legendre weights and window."""
+    n, s, box, k0, dk, nb = 16, 2, 100.0, 1.0, 1.0, 3
+    m = n // s
+    d = rng(43).standard_normal((n, n, n))
+    obs = np.array([-20.0, -35.0, -10.0])
+    iB, P, dbar, Nb = O.integrated_bispectrum(d, s, 4, obs, 1, box, k0, dk, nb)
+    i = 5
+    ox, oy, oz = (i // 4) * m, ((i // 2) % 2) * m, (i % 2) * m
+    blk = d[ox:ox + m, oy:oy + m, oz:oz + m]
+    e = np.array([ox, oy, oz]) + 0.5 * (m - 1) - obs
+    e = e / np.linalg.norm(e)
+    j = np.arange(m)
+    fr = np.fft.fftfreq(m, 1.0 / m)
+    acc = np.zeros((3, nb))
+    cnt = np.zeros(nb)
+    for a in fr:
+        for b in fr:
+            for c in fr:
+                q2 = int(a * a + b * b + c * c)
+                bb = O.bin_of_n2(np.array([q2]), k0, dk, nb)[0]
+                if bb < 0:
+                    continue
+                ph = np.exp(-2j * np.pi * (a * j[:, None, None] + b * j[None, :, None] + c * j[None, None, :]) / m)
+                F = np.sum(blk * ph)
+                win = (np.sinc(a / m) * np.sinc(b / m) * np.sinc(c / m)) ** 2
+                mu = (a * e[0] + b * e[1] + c * e[2]) / math.sqrt(q2)
+                leg = [1.0, 0.5 * (3 * mu * mu - 1), (35 * mu ** 4 - 30 * mu * mu + 3) / 8]
+                for li in range(3):
+                    acc[li, bb] += (4 * li + 1) * leg[li] * abs(F / win) ** 2
+                cnt[bb] += 1
+    Vs = (box / s) ** 3
+    assert np.array_equal(cnt.astype(np.int64), Nb)
+    ref = Vs * acc / (float(m) ** 6 * cnt[None, :])
+    assert np.allclose(P[i], ref, rtol=1e-10, atol=1e-10 * np.abs(ref).max())
+    assert abs(dbar[i] - blk.mean()) < 1e-14
+
+
 # ---------------------------------------------------------------- shells
 
 def test_bins_integer_edges_and_isotropy():
