@@ -126,12 +126,14 @@ def measured_traffic(kernel, workload):
         return None
 
 
-def spectra_legs(B, torch, plan, wl, ux, uy, uz, npart, pbar_path, log_fn, reps=20, skew_reps=5):
-    """Power-spectrum multipoles (Sec. 2, eq. PowSpecMultipole) and skew-spectrum
-    multipoles (Sec. 3.2) of the bench catalogue: its LOS moment spectra come
-    from the step entry points (grid assignment, LOS moments), then each
-    estimator is timed alone (`reps` and `skew_reps` calls). P^(0) is checked
-    against the shell power the whole path returns."""
+def spectra_legs(B, torch, plan, wl, ux, uy, uz, npart, pbar_path, log_fn, reps=20, skew_reps=5, ib_reps=3,
+                 ib_s=8, ib_nbins=20):
+    """Power-spectrum multipoles (Sec. 2, eq. PowSpecMultipole), skew-spectrum
+    multipoles (Sec. 3.2) and integrated bispectrum multipoles (Sec. 3.4, ib_s^3
+    sub-volumes, ib_nbins shells of one sub-volume fundamental) of the bench
+    catalogue: its grids and LOS moment spectra come from the step entry points
+    (grid assignment, LOS moments), then each estimator is timed alone. P^(0)
+    is checked against the shell power the whole path returns."""
     import numpy as np
     dev = ux.device
     nl = plan.info.nl
@@ -143,7 +145,6 @@ def spectra_legs(B, torch, plan, wl, ux, uy, uz, npart, pbar_path, log_fn, reps=
     Pl = torch.zeros((nl, wl.nbins), dtype=torch.float64, device=dev)
     B.bsp_power_multipoles(plan.handle, dl, Pl)
     plan.sync()
-    del grids
     B.bsp_set_timing(plan.handle, True)
     for _ in range(reps):
         B.bsp_power_multipoles(plan.handle, dl, Pl)
@@ -169,7 +170,21 @@ def spectra_legs(B, torch, plan, wl, ux, uy, uz, npart, pbar_path, log_fn, reps=
     sk = {"ms": avg_s * 1e3, "launches": n, "algorithmic_bytes": amt / n, "achieved_GBps": amt / n / avg_s / 1e9,
           "frac_hbm": amt / n / avg_s / PEAK_HBM,
           "S_l_first_bins": [[float(x) for x in Sl[li, :3].cpu().numpy()] for li in range(nl)]}
-    return pm, sk
+    del dl
+    iB = torch.zeros((nl, ib_nbins), dtype=torch.float64, device=dev)
+    B.bsp_integrated_bispectrum(plan.handle, grids[0], wsum, ib_s, 1.0, 1.0, ib_nbins, iB)
+    B.bsp_set_timing(plan.handle, True)
+    for _ in range(ib_reps):
+        B.bsp_integrated_bispectrum(plan.handle, grids[0], wsum, ib_s, 1.0, 1.0, ib_nbins, iB)
+    ms, n, amt = B.bsp_stage_times(plan.handle)["integrated_bispectrum"]
+    B.bsp_set_timing(plan.handle, False)
+    avg_s = ms / n * 1e-3
+    log_fn(f"integrated bispectrum: {avg_s * 1e3:.3f} ms per call")
+    ib = {"ms": avg_s * 1e3, "launches": n, "subvolumes": ib_s ** 3, "subvolume_side": wl.n // ib_s,
+          "algorithmic_bytes": amt / n, "achieved_GBps": amt / n / avg_s / 1e9, "frac_hbm": amt / n / avg_s / PEAK_HBM,
+          "iB_l_first_bins": [[float(x) for x in iB[li, :3].cpu().numpy()] for li in range(nl)]}
+    del grids
+    return pm, sk, ib
 
 
 def copy_calibration(nbytes, reps):
@@ -340,7 +355,8 @@ def main():
         res["roofline"] = {"kernel": kernel_of.get(dom, dom), "stage": dom, "bound": "hbm",
                            "achieved": d["achieved_GBps"], "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                            "frac": d["frac_hbm"], "traffic": traffic}
-    res["power_multipoles"], res["skew_spectra"] = spectra_legs(B, torch, plan, wl, ux, uy, uz, npart, o_mix["Pb"], log)
+    res["power_multipoles"], res["skew_spectra"], res["integrated_bispectrum"] = spectra_legs(
+        B, torch, plan, wl, ux, uy, uz, npart, o_mix["Pb"], log)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         res["cpu_baseline"] = cpu_baseline(wl, u, int(ntri), log)

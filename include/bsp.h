@@ -247,19 +247,43 @@ bsp_status bsp_power_multipoles(bsp_plan plan, const void* delta_l, double* P);
  * of bsp_los_moments. S: device double [nl][nbins]. Uses the workspace. */
 bsp_status bsp_skew_spectra(bsp_plan plan, const void* delta_l, double* S);
 
+/* Integrated bispectrum multipoles (Sec. 3.4, eq. integBisp and the RSD
+ * estimator after it): the N^3 grid is cut into s^3 cubic sub-volumes of side
+ * M = N / s (M a supported transform size); for each, dbar_i = its mean
+ * overdensity and P^(l)_i(k) = its power-spectrum multipoles with a single
+ * line of sight e_i, the unit vector from the observer to the sub-volume
+ * centre (z for plane-parallel plans; a reading: inside a small sub-volume the
+ * plane-parallel form applies):
+ *   P[i][l][b] = V_s sum_{n in b} (2l+1) L_l(nhat . e_i) |F_i(n) / W(n)|^2 / (M^6 N_b),
+ * F_i the unnormalised DFT of the sub-volume's contrast, W the plan's
+ * assignment window at the sub-volume frequencies (when the plan compensates),
+ * V_s = V / s^3, and iB[l][b] = (1/s^3) sum_i P[i][l][b] dbar[i]. Shells
+ * (2 c_b - dk)^2 <= 4 |n|^2 < (2 c_b + dk)^2, c_b = k0 + b dk, in units of the
+ * sub-volume fundamental 2 pi s / L (2 k0 and dk integers; every shell below
+ * |n| = M / 2). grid: device [N^3], the plan's first grid (interlacing is not
+ * used); wsum: device double[1]: the grid is a density rho and
+ * delta = rho N^3 / wsum - 1, or NULL: the grid is already a contrast.
+ * iB: device double [nl][nbins]; Psub: device double [s^3][nl][nbins] or NULL;
+ * dbar: device double [s^3] or NULL. Sub-volume i has origin
+ * M (i / s^2, (i / s) mod s, i mod s). Uses the workspace (about 3 N^3 floats);
+ * synchronises. */
+bsp_status bsp_integrated_bispectrum(bsp_plan plan, const float* grid, const double* wsum, int32_t s, double k0,
+                                     double dk, int32_t nbins, double* iB, double* Psub, double* dbar);
+
 /* Stage timers: while enabled, each compute call records a pair of HIP events
  * on the plan's stream around the launches of every stage:
  *   0 assignment, 1 forward z pass (r2c + LOS weights), 2 forward y pass,
  *   3 forward x pass, 4 LOS combination, 5 inverse x pass (shell/modal filter),
  *   6 inverse y pass, 7 inverse z pass (c2r), 8 triple reduction,
  *   9 FP64 combination of the reduction partials, 10 power-spectrum multipoles,
- *   11 skew spectra (the whole call; its transforms also count in stages 5-7).
+ *   11 skew spectra (the whole call; its transforms also count in stages 5-7),
+ *   12 integrated bispectrum (the whole call).
  * bsp_set_timing(plan, 1) resets and starts, 0 stops (it synchronises).
  * bsp_stage_times synchronises and returns, per stage, the summed event
  * milliseconds since the reset (ms: host double[16]), the number of timed
  * launches (launches: host int64[16], may be NULL) and the summed algorithmic
  * amount of the timed launches (amount: host double[16], may be NULL): bytes
- * each pass must read and write once on the band it keeps (stages 0-7, 10, 11), or
+ * each pass must read and write once on the band it keeps (stages 0-7, 10-12), or
  * flops of the needed triple products (stage 8: two per needed entry per
  * point plus one per pair per point). */
 bsp_status bsp_set_timing(bsp_plan plan, int32_t enable);

@@ -22,7 +22,7 @@ __all__ = [
     "bsp_geometry", "bsp_grid_assign", "bsp_fft_r2c", "bsp_fft_c2r", "bsp_los_moments", "bsp_grid_entry",
     "bsp_filter_fields", "bsp_triple_reduce", "bsp_modal_coeffs", "bsp_bispectrum_multipoles",
     "bsp_bispectrum_field", "bsp_batch_run", "bsp_batch_covariance", "bsp_power_multipoles", "bsp_skew_spectra",
-    "bsp_set_timing", "bsp_stage_times", "STAGES", "EXPORTED",
+    "bsp_integrated_bispectrum", "bsp_set_timing", "bsp_stage_times", "STAGES", "EXPORTED",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -39,10 +39,11 @@ EXPORTED = [
     "bsp_set_workspace", "bsp_sync", "bsp_precompute", "bsp_geometry", "bsp_grid_assign", "bsp_fft_r2c",
     "bsp_fft_c2r", "bsp_los_moments", "bsp_grid_entry", "bsp_filter_fields", "bsp_triple_reduce",
     "bsp_modal_coeffs", "bsp_bispectrum_multipoles", "bsp_bispectrum_field", "bsp_batch_run",
-    "bsp_batch_covariance", "bsp_power_multipoles", "bsp_skew_spectra", "bsp_set_timing", "bsp_stage_times",
+    "bsp_batch_covariance", "bsp_power_multipoles", "bsp_skew_spectra", "bsp_integrated_bispectrum",
+    "bsp_set_timing", "bsp_stage_times",
 ]
 STAGES = ["assign", "fwd_z", "fwd_y", "fwd_x", "los_combine", "inv_x_filter", "inv_y", "inv_z", "reduce",
-          "reduce_combine", "power_multipoles", "skew_spectra"]
+          "reduce_combine", "power_multipoles", "skew_spectra", "integrated_bispectrum"]
 
 
 class BspError(RuntimeError):
@@ -111,6 +112,7 @@ def lib():
         "bsp_batch_covariance": [_vp, _i32, _i32, _vp, _vp],
         "bsp_power_multipoles": [_vp, _vp, _vp],
         "bsp_skew_spectra": [_vp, _vp, _vp],
+        "bsp_integrated_bispectrum": [_vp, _vp, _vp, _i32, _d, _d, _i32, _vp, _vp, _vp],
         "bsp_set_timing": [_vp, _i32],
         "bsp_stage_times": [_vp, _vp, _vp, _vp],
     }
@@ -274,6 +276,11 @@ def bsp_power_multipoles(plan, delta_l, P):
 
 def bsp_skew_spectra(plan, delta_l, S):
     _check(lib().bsp_skew_spectra(plan, _dptr(delta_l), _dptr(S)), plan)
+
+
+def bsp_integrated_bispectrum(plan, grid, wsum, s, k0, dk, nbins, iB, Psub=None, dbar=None):
+    _check(lib().bsp_integrated_bispectrum(plan, _dptr(grid), _dptr(wsum), int(s), float(k0), float(dk), int(nbins),
+                                           _dptr(iB), _dptr(Psub), _dptr(dbar)), plan)
 
 
 def bsp_set_timing(plan, enable: bool):

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <string>
+#include <map>
 #include <vector>
 
 #include "../../include/bsp.h"
@@ -285,6 +286,7 @@ struct bsp_plan_s {
   std::vector<int64_t> row_support32, row_cols32;
   std::vector<int32_t> field_row32;  // tab32 row of each main pipeline field
   int32_t band_row32 = 0;            // tab32 row of the union of the shells
+  std::map<int, float2*> tw32_other;  // FP32 twiddles of other transform sizes, made on first use
   int32_t* d_band_meta = nullptr;    // {0, band_row32}: l slot and table row of the band-limited monopole
   std::vector<int> field_c;   // per main-pipeline field
   int32_t *d_field_ell = nullptr, *d_field_tab = nullptr;
@@ -1268,13 +1270,23 @@ bsp_status bsp_grid_assign(bsp_plan p, const float* ux, const float* uy, const f
   return BSP_OK;
 }
 
-bsp_status bsp_fft_r2c(bsp_plan p, int32_t n, int32_t batch, const float* in, void* out_c64) {
-  if (!p || !in || !out_c64 || batch < 1) return fail(p, BSP_ERR_ARG, "bad argument");
-  if (!fft_size_supported(n)) return fail(p, BSP_ERR_SIZE, "unsupported size");
-  const float2* tw = (n == p->N) ? p->tw32_N : (n == p->Nr ? p->tw32_Nr : nullptr);
-  if (!tw) return fail(p, BSP_ERR_SIZE, "size must be the plan's N or N'");
+// FP32 twiddles of a supported transform size (the plan's N and N' are built
+// with the plan, other sizes on first use and kept with it).
+const float2* tw32_for(bsp_plan p, int n) {
+  if (n == p->N) return p->tw32_N;
+  if (n == p->Nr) return p->tw32_Nr;
+  auto it = p->tw32_other.find(n);
+  if (it != p->tw32_other.end()) return it->second;
+  const std::vector<double> t = twiddles(n);
+  std::vector<float> f(t.begin(), t.end());
+  float2* d = reinterpret_cast<float2*>(upload(p, f));
+  if (d) p->tw32_other[n] = d;
+  return d;
+}
+
+// Unnormalised r2c of `batch` contiguous n^3 grids into [batch][n][n][n/2+1].
+bsp_status r2c_batch(bsp_plan p, int n, int batch, const float* in, float2* out, const float2* tw) {
   const int h = n / 2 + 1;
-  float2* out = reinterpret_cast<float2*>(out_c64);
   FwdZDesc fz{};
   fz.ngrid = batch;
   fz.nlos = 1;
@@ -1300,6 +1312,14 @@ bsp_status bsp_fft_r2c(bsp_plan p, int32_t n, int32_t batch, const float* in, vo
   set1d(px);
   HIPCHK(launch_c2c_f32(n, -1, out, out, px, nullptr, tw, p->stream));
   return BSP_OK;
+}
+
+bsp_status bsp_fft_r2c(bsp_plan p, int32_t n, int32_t batch, const float* in, void* out_c64) {
+  if (!p || !in || !out_c64 || batch < 1 || batch > 65535) return fail(p, BSP_ERR_ARG, "bad argument");
+  if (!fft_size_supported(n)) return fail(p, BSP_ERR_SIZE, "unsupported size");
+  const float2* tw = (n == p->N) ? p->tw32_N : (n == p->Nr ? p->tw32_Nr : nullptr);
+  if (!tw) return fail(p, BSP_ERR_SIZE, "size must be the plan's N or N'");
+  return r2c_batch(p, n, batch, in, reinterpret_cast<float2*>(out_c64), tw);
 }
 
 bsp_status bsp_fft_c2r(bsp_plan p, int32_t n, int32_t batch, const void* in_c64, float* out) {
@@ -1764,6 +1784,78 @@ bsp_status bsp_skew_spectra(bsp_plan p, const void* delta_l, double* S) {
   // S^l_b = V sum_{n in b} Re[delta^(l) conj Q] / (N^9 N'^3 N_b)
   HIPCHK(launch_shell_cross(dl, p->spec, p->nl, X, c, cz, p->d_bin_of_n2, p->n2max, p->nbins, p->d_nb_modes,
                             p->V / (std::pow((double)p->N, 9) * std::pow((double)Nr, 3)), psum, S, p->stream));
+  return BSP_OK;
+}
+
+bsp_status bsp_integrated_bispectrum(bsp_plan p, const float* grid, const double* wsum, int32_t s, double k0,
+                                     double dk, int32_t nbins, double* iB, double* Psub, double* dbar) {
+  if (!p || !grid || !iB || s < 1 || nbins < 1 || !(dk > 0.0) || !(k0 > 0.0))
+    return fail(p, BSP_ERR_ARG, "bad argument");
+  const int N = p->N;
+  if (N % s != 0) return fail(p, BSP_ERR_SIZE, "s must divide N");
+  const int m = N / s, ns = s * s * s;
+  if (!fft_size_supported(m) || m % 4 != 0) return fail(p, BSP_ERR_SIZE, "unsupported sub-volume size N / s");
+  if (ns > 65535) return fail(p, BSP_ERR_SIZE, "too many sub-volumes");
+  // sub-volume shells (units of 2 pi s / L): (2 c_b - dk)^2 <= 4 n^2 < (2 c_b + dk)^2, 2 k0 and dk integers
+  std::vector<int64_t> lo(nbins), hi(nbins);
+  for (int b = 0; b < nbins; ++b) {
+    const double a = 2.0 * (k0 + b * dk) - dk, z = 2.0 * (k0 + b * dk) + dk;
+    if (std::fabs(a - std::round(a)) > 1e-9 || std::fabs(z - std::round(z)) > 1e-9 || a < 0)
+      return fail(p, BSP_ERR_ARG, "2 k0 and dk must be integers");
+    lo[b] = (int64_t)std::llround(a) * std::llround(a);
+    hi[b] = (int64_t)std::llround(z) * std::llround(z);
+  }
+  const int n2max = (int)((hi[nbins - 1] - 1) / 4);
+  if ((int64_t)4 * n2max >= (int64_t)m * m) return fail(p, BSP_ERR_SIZE, "sub-volume shells reach |n| >= M / 2");
+  std::vector<int32_t> bin(n2max + 1, -1);
+  for (int n2 = 0; n2 <= n2max; ++n2)
+    for (int b = 0; b < nbins; ++b)
+      if (4 * (int64_t)n2 >= lo[b] && 4 * (int64_t)n2 < hi[b]) bin[n2] = b;
+  // modes per shell over the full lattice of the sub-volume
+  std::vector<int64_t> nbm(nbins, 0);
+  int cm = 0;
+  while ((int64_t)(cm + 1) * (cm + 1) <= n2max) ++cm;
+  for (int x = -cm; x <= cm; ++x)
+    for (int y = -cm; y <= cm; ++y)
+      for (int z = -cm; z <= cm; ++z) {
+        const int64_t n2 = (int64_t)x * x + (int64_t)y * y + (int64_t)z * z;
+        if (n2 <= n2max && bin[n2] >= 0) nbm[bin[n2]]++;
+      }
+  const int nl = p->nl;
+  const int h = m / 2 + 1;
+  const size_t gbytes = align_up((size_t)N * N * N * sizeof(float));
+  const size_t fbytes = align_up((size_t)ns * m * m * h * sizeof(float2));
+  const size_t pbytes = align_up((size_t)ns * nl * nbins * sizeof(double));
+  const size_t dbytes = align_up((size_t)ns * sizeof(double));
+  const size_t tbytes = align_up(bin.size() * sizeof(int32_t)) + align_up(nbm.size() * sizeof(int64_t));
+  bsp_status st = need_ws(p, gbytes + fbytes + pbytes + dbytes + tbytes);
+  if (st != BSP_OK) return st;
+  const float2* tw = tw32_for(p, m);
+  if (!tw) return fail(p, BSP_ERR_HIP, "twiddle table allocation failed");
+  float* sub = reinterpret_cast<float*>(p->ws);
+  float2* F = reinterpret_cast<float2*>(p->ws + gbytes);
+  double* psum = reinterpret_cast<double*>(p->ws + gbytes + fbytes);
+  double* db = dbar ? dbar : reinterpret_cast<double*>(p->ws + gbytes + fbytes + pbytes);
+  int32_t* dbin = reinterpret_cast<int32_t*>(p->ws + gbytes + fbytes + pbytes + dbytes);
+  int64_t* dnb = reinterpret_cast<int64_t*>(p->ws + gbytes + fbytes + pbytes + dbytes + align_up(bin.size() * 4));
+  HIPCHK(hipMemcpyAsync(dbin, bin.data(), bin.size() * sizeof(int32_t), hipMemcpyHostToDevice, p->stream));
+  HIPCHK(hipMemcpyAsync(dnb, nbm.data(), nbm.size() * sizeof(int64_t), hipMemcpyHostToDevice, p->stream));
+  HIPCHK(hipMemsetAsync(psum, 0, (size_t)ns * nl * nbins * sizeof(double), p->stream));
+  // algorithmic bytes: the grid read once, each transform pass's input and
+  // output once, the sub-volume spectra read once by the shell sums
+  const double R = (double)N * N * N, H = (double)ns * m * m * h * 8.0;
+  {
+    StageTimer t(p, 12, R * 4.0 + R * 4.0 * 2.0 + H * 6.0 + H);
+    HIPCHK(launch_gather_subvolumes(grid, wsum, N, s, sub, p->stream));
+    st = r2c_batch(p, m, ns, sub, F, tw);
+    if (st != BSP_OK) return st;
+    HIPCHK(launch_subvolume_shells(F, m, s, p->plane, p->g.observer, p->g.compensate ? p->g.window : -1, nl, dbin,
+                                   n2max, nbins, psum, db, p->stream));
+    const double Vs = p->V / ((double)s * s * s);
+    HIPCHK(launch_subvolume_finalize(psum, db, ns, nl, nbins, dnb, Vs / std::pow((double)m, 6), iB, Psub,
+                                     p->stream));
+  }
+  HIPCHK(hipStreamSynchronize(p->stream));  // the host tables above are read by the copies
   return BSP_OK;
 }
 

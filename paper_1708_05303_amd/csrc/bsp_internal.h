@@ -136,6 +136,16 @@ hipError_t launch_shell_cross(const float2* delta_l, int64_t ell_stride, int nl,
 // x <- x^2 over n floats (n a multiple of 4, x 16-byte aligned).
 hipError_t launch_square(float* x, int64_t n, hipStream_t s);
 
+// Integrated bispectrum (ib.hip): sub-volume gather (contrast when wsum),
+// per-sub-volume shell sums with the local line of sight (window -1: none,
+// 0: NGP, 1: CIC), and the average iB[l][b] = (1/N_s) sum_i P[i][l][b] dbar[i].
+hipError_t launch_gather_subvolumes(const float* grid, const double* wsum, int n, int s, float* out, hipStream_t st);
+hipError_t launch_subvolume_shells(const float2* F, int m, int s, int plane, const double* obs, int window, int nl,
+                                   const int32_t* bin_of_n2, int n2max, int nbins, double* psum, double* dbar,
+                                   hipStream_t st);
+hipError_t launch_subvolume_finalize(const double* psum, const double* dbar, int ns, int nl, int nbins,
+                                     const int64_t* nb_modes, double scale, double* iB, double* P, hipStream_t st);
+
 // Triple reduction (reduce.hip).
 hipError_t launch_reduce(int prec, const float* fields, const ReduceDesc& d, float* partials,
                          hipStream_t s);

@@ -1,0 +1,151 @@
+// Integrated bispectrum multipoles (Sec. 3.4, eq. integBisp and the RSD
+// estimator after it): the grid is cut into s^3 cubic sub-volumes of side
+// M = N / s; each sub-volume's mean overdensity dbar_i and power-spectrum
+// multipoles P^(l)_i(k) are formed from one batched real-to-complex transform
+// of all sub-volumes, and iB^(l)(k) = (1/N_s) sum_i P^(l)_i(k) dbar_i.
+//
+// Inside a sub-volume the line of sight is the single unit vector e_i from
+// the observer to the sub-volume centre (z for plane-parallel plans), so
+// P^(l)_i needs no line-of-sight weighted transforms:
+//   P^(l)_i(k_b) = V_s sum_{n in b} (2l+1) L_l(nhat . e_i) |F_i(n) / W(n)|^2 / (M^6 N_b).
+#include "bsp_internal.h"
+
+namespace bsp {
+
+// out[i][x][y][z] (sub-volume i, local node) = delta of the grid at the
+// sub-volume origin + (x, y, z); delta = rho N^3 / wsum - 1 when wsum is given.
+__global__ __launch_bounds__(256) void k_gather_subvolumes(const float* __restrict__ grid,
+                                                           const double* __restrict__ wsum, int n, int s, int m,
+                                                           float* __restrict__ out) {
+  const int64_t m3 = (int64_t)m * m * m;
+  const int64_t total4 = (int64_t)s * s * s * m3 / 4;
+  float scale = 1.0f, sub = 0.0f;
+  if (wsum) {
+    scale = (float)((double)n * (double)n * (double)n / wsum[0]);
+    sub = 1.0f;
+  }
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total4;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = i * 4;
+    const int64_t box = e / m3;
+    const int64_t r = e % m3;
+    const int lx = (int)(r / ((int64_t)m * m)), ly = (int)((r / m) % m), lz = (int)(r % m);
+    const int bx = (int)(box / ((int64_t)s * s)), by = (int)((box / s) % s), bz = (int)(box % s);
+    const float4 v = *reinterpret_cast<const float4*>(grid + ((int64_t)(bx * m + lx) * n + (by * m + ly)) * n +
+                                                      bz * m + lz);
+    *reinterpret_cast<float4*>(out + e) =
+        make_float4(v.x * scale - sub, v.y * scale - sub, v.z * scale - sub, v.w * scale - sub);
+  }
+}
+
+// Shell sums of one sub-volume per blockIdx.y over its half spectrum
+// [m][m][h]; psum[i][l][b] += mult (2l+1) L_l(mu) |F / W|^2, dbar[i] = F(0) / m^3.
+__global__ __launch_bounds__(256) void k_subvolume_shells(const float2* __restrict__ F, int m, int s, int plane,
+                                                          double ox, double oy, double oz, int window, int nl,
+                                                          const int32_t* __restrict__ bin_of_n2, int n2max,
+                                                          int nbins, double* __restrict__ psum,
+                                                          double* __restrict__ dbar) {
+  extern __shared__ double hist[];  // [nl][nbins]
+  for (int b = threadIdx.x; b < nl * nbins; b += blockDim.x) hist[b] = 0.0;
+  const int box = blockIdx.y;
+  const int h = m / 2 + 1;
+  // line of sight of this sub-volume: observer to its centre
+  double ex = 0.0, ey = 0.0, ez = 1.0;
+  if (!plane) {
+    const int bx = box / (s * s), by = (box / s) % s, bz = box % s;
+    const double half = 0.5 * (m - 1);
+    ex = bx * (double)m + half - ox;
+    ey = by * (double)m + half - oy;
+    ez = bz * (double)m + half - oz;
+    const double inv = 1.0 / sqrt(ex * ex + ey * ey + ez * ez);
+    ex *= inv;
+    ey *= inv;
+    ez *= inv;
+  }
+  __syncthreads();
+  const float2* Fi = F + (int64_t)box * m * m * h;
+  const int64_t total = (int64_t)m * m * h;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int kz = (int)(idx % h);
+    const int64_t rest = idx / h;
+    const int iy = (int)(rest % m), ix = (int)(rest / m);
+    const int nx = ix <= m / 2 ? ix : ix - m, ny = iy <= m / 2 ? iy : iy - m;
+    const int n2 = nx * nx + ny * ny + kz * kz;
+    if (n2 == 0) {
+      dbar[box] = (double)Fi[0].x / ((double)m * m * m);
+      continue;
+    }
+    if (n2 > n2max) continue;
+    const int b = bin_of_n2[n2];
+    if (b < 0) continue;
+    const float2 v = Fi[idx];
+    double p = (double)v.x * v.x + (double)v.y * v.y;
+    if (window >= 0) {
+      // assignment window at the sub-volume frequencies (same cell size)
+      const double pi = 3.14159265358979323846;
+      auto sinc = [&](int a) { return a == 0 ? 1.0 : sin(pi * a / m) / (pi * a / m); };
+      double w = sinc(nx) * sinc(ny) * sinc(kz);
+      if (window == 1) w *= w;
+      p /= w * w;
+    }
+    const double mult = (kz == 0 || 2 * kz == m) ? 1.0 : 2.0;
+    const double mu = (nx * ex + ny * ey + kz * ez) / sqrt((double)n2);
+    const double mu2 = mu * mu;
+    const double L[3] = {1.0, 0.5 * (3.0 * mu2 - 1.0), (35.0 * mu2 * mu2 - 30.0 * mu2 + 3.0) / 8.0};
+    for (int li = 0; li < nl; ++li) atomicAdd(&hist[li * nbins + b], mult * (4 * li + 1) * L[li] * p);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < nl * nbins; b += blockDim.x)
+    if (hist[b] != 0.0) unsafeAtomicAdd(&psum[(int64_t)box * nl * nbins + b], hist[b]);
+}
+
+// iB[l][b] = (1/N_s) sum_i P[i][l][b] dbar[i], P = scale psum / N_b (optionally stored).
+__global__ void k_subvolume_finalize(const double* __restrict__ psum, const double* __restrict__ dbar, int ns,
+                                     int nl, int nbins, const int64_t* __restrict__ nb_modes, double scale,
+                                     double* __restrict__ iB, double* __restrict__ P) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= nl * nbins) return;
+  const int64_t nm = nb_modes[j % nbins];
+  const double f = nm > 0 ? scale / (double)nm : 0.0;
+  double acc = 0.0;
+  for (int i = 0; i < ns; ++i) {
+    const double pv = f * psum[(int64_t)i * nl * nbins + j];
+    if (P) P[(int64_t)i * nl * nbins + j] = pv;
+    acc += pv * dbar[i];
+  }
+  iB[j] = acc / ns;
+}
+
+hipError_t launch_gather_subvolumes(const float* grid, const double* wsum, int n, int s, float* out, hipStream_t st) {
+  if (s < 1 || n % s != 0 || (n / s) % 4 != 0) return hipErrorInvalidValue;
+  const int m = n / s;
+  const int64_t total4 = (int64_t)n * n * n / 4;
+  int64_t blocks = (total4 + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_gather_subvolumes, dim3((unsigned)blocks), dim3(256), 0, st, grid, wsum, n, s, m, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_subvolume_shells(const float2* F, int m, int s, int plane, const double* obs, int window, int nl,
+                                   const int32_t* bin_of_n2, int n2max, int nbins, double* psum, double* dbar,
+                                   hipStream_t st) {
+  const int ns = s * s * s;
+  if (ns > 65535 || nl < 1 || nl > 3 || (size_t)nl * nbins * sizeof(double) > 64 * 1024) return hipErrorInvalidValue;
+  const int64_t total = (int64_t)m * m * (m / 2 + 1);
+  int64_t bx = (total + 255) / 256;
+  if (bx > 256) bx = 256;
+  hipLaunchKernelGGL(k_subvolume_shells, dim3((unsigned)bx, (unsigned)ns), dim3(256),
+                     (size_t)nl * nbins * sizeof(double), st, F, m, s, plane, obs[0], obs[1], obs[2], window, nl,
+                     bin_of_n2, n2max, nbins, psum, dbar);
+  return hipGetLastError();
+}
+
+hipError_t launch_subvolume_finalize(const double* psum, const double* dbar, int ns, int nl, int nbins,
+                                     const int64_t* nb_modes, double scale, double* iB, double* P, hipStream_t st) {
+  hipLaunchKernelGGL(k_subvolume_finalize, dim3((unsigned)((nl * nbins + 63) / 64)), dim3(64), 0, st, psum, dbar, ns,
+                     nl, nbins, nb_modes, scale, iB, P);
+  return hipGetLastError();
+}
+
+}  // namespace bsp
