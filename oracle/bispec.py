@@ -38,7 +38,7 @@ __all__ = [
     "los_weighted_field", "forward", "compensate", "interlace_combine",
     "legendre_moments", "legendre_moments_direct", "bin_edges4", "bin_of_n2",
     "n2_grid_half", "shell_field", "triangle_list", "triangle_counts_fft",
-    "triangle_counts_brute", "closed_triangle_sum_brute", "binned_triple_sums",
+    "triangle_counts_brute", "closed_triangle_sum_brute", "binned_triple_sums", "binned_triple_sums_full",
     "binned_bispectrum", "shell_power", "power_multipoles", "skew_spectra", "integrated_bispectrum",
     "shot_noise_binned", "modal_modes",
     "modal_q", "modal_filter", "modal_fields", "modal_numerators", "gram_matrix",
@@ -457,6 +457,28 @@ def binned_triple_sums(spec_l: Sequence[np.ndarray], n: int, nr: int, k0: float,
         for li in range(len(specs)):
             T[li, i] = np.dot(D[li][b1], pair)
     return tris, T
+
+
+def binned_triple_sums_full(spec_l: Sequence[np.ndarray], n: int, nr: int, k0: float, dk: float,
+                            nb: int, tris=None):
+    """T^(l1 l2 l3)(b1,b2,b3) = sum_x D^l1_b1 D^l2_b2 D^l3_b3 over the N'^3 grid.
+
+    The general Legendre decomposition of Sec. 3 (B^(l1 l2 l3), one multipole
+    per side), in the FFT form of eq. (Standard_ell_Estim) with each side's
+    field built from its own LOS moment delta^(l_i) (the line of sight at x for
+    every side, as for B^(l) = B^(l00)). Combination index (l1 nl + l2) nl + l3
+    over l_i = 0, 2, ..., 2 (nl - 1). Returns (tris, combos, T [nl^3][ntri])."""
+    tris = triangle_list(nb) if tris is None else tris
+    bins = bin_of_n2(n2_grid_half(nr), k0, dk, nb)
+    specs = [_crop_spec(s, n, nr) for s in spec_l]
+    D = [np.stack([shell_field(sp, bins == b, nr).ravel() for b in range(nb)]) for sp in specs]
+    nl = len(specs)
+    combos = [(l1, l2, l3) for l1 in range(nl) for l2 in range(nl) for l3 in range(nl)]
+    T = np.empty((len(combos), len(tris)))
+    for i, (b1, b2, b3) in enumerate(tris):
+        for ci, (l1, l2, l3) in enumerate(combos):
+            T[ci, i] = np.dot(D[l1][b1], D[l2][b2] * D[l3][b3])
+    return tris, combos, T
 
 
 def binned_bispectrum(T: np.ndarray, counts: np.ndarray, n: int, nr: int, box: float):

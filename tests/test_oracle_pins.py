@@ -392,6 +392,27 @@ def test_fft_triple_sum_equals_brute_force_closed_triangles(n, k0, dk, nb):
             assert abs(ref.imag) < 1e-10 * scale
 
 
+@pytest.mark.parametrize("n,k0,dk,nb", [(8, 1.0, 1.0, 2), (16, 2.0, 2.0, 2)])
+def test_full_multipole_triple_sums_brute_force(n, k0, dk, nb):
+    """T^(l1 l2 l3) against the closed-triangle sum with a different spectrum
+    on each side; l2 = l3 = 0 reproduces the B^(l) triple sums."""
+    spec = [_random_spec(n, 20 + i) for i in range(3)]
+    lo, hi = O.bin_edges4(k0, dk, nb)
+    tris, combos, T = O.binned_triple_sums_full(spec, n, n, k0, dk, nb)
+    _, T1 = O.binned_triple_sums(spec, n, n, k0, dk, nb)
+    scale = np.abs(T).max() / n ** 3
+    for li in range(3):
+        assert np.allclose(T[combos.index((li, 0, 0))], T1[li], rtol=0, atol=1e-12 * np.abs(T1).max())
+    for ti, (b1, b2, b3) in enumerate(tris):
+        masks = [lambda q, b=b: (4 * q >= lo[b]) & (4 * q < hi[b]) for b in (b1, b2, b3)]
+        for ci, (l1, l2, l3) in enumerate(combos):
+            ref = O.closed_triangle_sum_brute([spec[l1], spec[l2], spec[l3]], n, masks, modular=True)
+            assert abs(T[ci, ti] / n ** 3 - ref.real) < 1e-10 * scale, (b1, b2, b3, l1, l2, l3)
+        if b2 == b3:
+            for (l1, l2, l3) in combos:
+                assert abs(T[combos.index((l1, l2, l3)), ti] - T[combos.index((l1, l3, l2)), ti]) < 1e-10 * scale * n ** 3
+
+
 def test_modular_equals_exact_closure_without_alias_and_differs_with():
     n = 16
     spec = _random_spec(n, 21)
