@@ -126,14 +126,16 @@ def measured_traffic(kernel, workload):
         return None
 
 
-def spectra_legs(B, torch, plan, wl, ux, uy, uz, npart, pbar_path, log_fn, reps=20, skew_reps=5, ib_reps=3,
-                 ib_s=8, ib_nbins=20):
+def spectra_legs(B, torch, plan, wl, ux, uy, uz, npart, pbar_path, b_path, prec, log_fn, reps=20, skew_reps=5,
+                 ib_reps=3, ib_s=8, ib_nbins=20, full_reps=2):
     """Power-spectrum multipoles (Sec. 2, eq. PowSpecMultipole), skew-spectrum
     multipoles (Sec. 3.2) and integrated bispectrum multipoles (Sec. 3.4, ib_s^3
     sub-volumes, ib_nbins shells of one sub-volume fundamental) of the bench
     catalogue: its grids and LOS moment spectra come from the step entry points
     (grid assignment, LOS moments), then each estimator is timed alone. P^(0)
-    is checked against the shell power the whole path returns."""
+    is checked against the shell power the whole path returns. The full
+    multipoles B^(l1 l2 l3) (Sec. 3) are timed on the same spectra, and their
+    B^(l00) checked against the whole path's B^l."""
     import numpy as np
     dev = ux.device
     nl = plan.info.nl
@@ -170,7 +172,24 @@ def spectra_legs(B, torch, plan, wl, ux, uy, uz, npart, pbar_path, log_fn, reps=
     sk = {"ms": avg_s * 1e3, "launches": n, "algorithmic_bytes": amt / n, "achieved_GBps": amt / n / avg_s / 1e9,
           "frac_hbm": amt / n / avg_s / PEAK_HBM,
           "S_l_first_bins": [[float(x) for x in Sl[li, :3].cpu().numpy()] for li in range(nl)]}
-    del dl
+    ntri = plan.info.ntri
+    Bf = torch.zeros((nl ** 3, ntri), dtype=torch.float64, device=dev)
+    B.bsp_bispectrum_full(plan.handle, dl, prec, Bf)  # builds the schedule
+    plan.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(full_reps):
+        B.bsp_bispectrum_full(plan.handle, dl, prec, Bf)
+    plan.sync()
+    torch.cuda.synchronize()
+    full_ms = (time.perf_counter() - t0) / full_reps * 1e3
+    bp = b_path.cpu().numpy()
+    bf = Bf.cpu().numpy()
+    l00 = [bf[(li * nl) * nl] for li in range(nl)]
+    log_fn(f"full multipoles: {full_ms:.1f} ms per call")
+    full = {"ms": full_ms, "combinations": nl ** 3, "triangles": int(ntri),
+            "B_l00_vs_path_B_l": [float(np.linalg.norm(l00[li] - bp[li]) / np.linalg.norm(bp[li])) for li in range(nl)]}
+    del dl, Bf
     iB = torch.zeros((nl, ib_nbins), dtype=torch.float64, device=dev)
     B.bsp_integrated_bispectrum(plan.handle, grids[0], wsum, ib_s, 1.0, 1.0, ib_nbins, iB)
     B.bsp_set_timing(plan.handle, True)
@@ -184,7 +203,7 @@ def spectra_legs(B, torch, plan, wl, ux, uy, uz, npart, pbar_path, log_fn, reps=
           "algorithmic_bytes": amt / n, "achieved_GBps": amt / n / avg_s / 1e9, "frac_hbm": amt / n / avg_s / PEAK_HBM,
           "iB_l_first_bins": [[float(x) for x in iB[li, :3].cpu().numpy()] for li in range(nl)]}
     del grids
-    return pm, sk, ib
+    return pm, sk, ib, full
 
 
 def copy_calibration(nbytes, reps):
@@ -355,8 +374,8 @@ def main():
         res["roofline"] = {"kernel": kernel_of.get(dom, dom), "stage": dom, "bound": "hbm",
                            "achieved": d["achieved_GBps"], "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                            "frac": d["frac_hbm"], "traffic": traffic}
-    res["power_multipoles"], res["skew_spectra"], res["integrated_bispectrum"] = spectra_legs(
-        B, torch, plan, wl, ux, uy, uz, npart, o_mix["Pb"], log)
+    res["power_multipoles"], res["skew_spectra"], res["integrated_bispectrum"], res["bispectrum_full"] = \
+        spectra_legs(B, torch, plan, wl, ux, uy, uz, npart, o_mix["Pb"], o_mix["B"], prec, log)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         res["cpu_baseline"] = cpu_baseline(wl, u, int(ntri), log)

@@ -270,6 +270,18 @@ bsp_status bsp_skew_spectra(bsp_plan plan, const void* delta_l, double* S);
 bsp_status bsp_integrated_bispectrum(bsp_plan plan, const float* grid, const double* wsum, int32_t s, double k0,
                                      double dk, int32_t nbins, double* iB, double* Psub, double* dbar);
 
+/* Full bispectrum multipoles B^(l1 l2 l3) (Sec. 3, the general Legendre
+ * decomposition with one multipole per side) in the FFT form of eq.
+ * (Standard_ell_Estim): each side's field D^(l_i)_{b_i} comes from its own LOS
+ * moment delta^(l_i), T = sum_x D^l1_b1 D^l2_b2 D^l3_b3 and
+ * B = V^2 T / (N^9 N'^3 N_tri) over the plan's triangles b1 >= b2 >= b3 (so
+ * B^(l00) is the B^l of bsp_bispectrum_multipoles). delta_l: device compact
+ * spectrum [nl][spec] of bsp_los_moments; B: device double [nl^3][ntri] with
+ * combination (l1 nl + l2) nl + l3 (l = 0, 2, ...). After bsp_precompute; the
+ * first call builds the schedule; the reduction's chunks are lengthened until
+ * its partial sums fit the workspace. Uses the workspace. */
+bsp_status bsp_bispectrum_full(bsp_plan plan, const void* delta_l, bsp_precision prec, double* B);
+
 /* Stage timers: while enabled, each compute call records a pair of HIP events
  * on the plan's stream around the launches of every stage:
  *   0 assignment, 1 forward z pass (r2c + LOS weights), 2 forward y pass,

@@ -22,7 +22,8 @@ __all__ = [
     "bsp_geometry", "bsp_grid_assign", "bsp_fft_r2c", "bsp_fft_c2r", "bsp_los_moments", "bsp_grid_entry",
     "bsp_filter_fields", "bsp_triple_reduce", "bsp_modal_coeffs", "bsp_bispectrum_multipoles",
     "bsp_bispectrum_field", "bsp_batch_run", "bsp_batch_covariance", "bsp_power_multipoles", "bsp_skew_spectra",
-    "bsp_integrated_bispectrum", "bsp_set_timing", "bsp_stage_times", "STAGES", "EXPORTED",
+    "bsp_integrated_bispectrum", "bsp_bispectrum_full", "bsp_set_timing", "bsp_stage_times", "STAGES",
+    "EXPORTED",
 ]
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -40,7 +41,7 @@ EXPORTED = [
     "bsp_fft_c2r", "bsp_los_moments", "bsp_grid_entry", "bsp_filter_fields", "bsp_triple_reduce",
     "bsp_modal_coeffs", "bsp_bispectrum_multipoles", "bsp_bispectrum_field", "bsp_batch_run",
     "bsp_batch_covariance", "bsp_power_multipoles", "bsp_skew_spectra", "bsp_integrated_bispectrum",
-    "bsp_set_timing", "bsp_stage_times",
+    "bsp_bispectrum_full", "bsp_set_timing", "bsp_stage_times",
 ]
 STAGES = ["assign", "fwd_z", "fwd_y", "fwd_x", "los_combine", "inv_x_filter", "inv_y", "inv_z", "reduce",
           "reduce_combine", "power_multipoles", "skew_spectra", "integrated_bispectrum"]
@@ -113,6 +114,7 @@ def lib():
         "bsp_power_multipoles": [_vp, _vp, _vp],
         "bsp_skew_spectra": [_vp, _vp, _vp],
         "bsp_integrated_bispectrum": [_vp, _vp, _vp, _i32, _d, _d, _i32, _vp, _vp, _vp],
+        "bsp_bispectrum_full": [_vp, _vp, _i32, _vp],
         "bsp_set_timing": [_vp, _i32],
         "bsp_stage_times": [_vp, _vp, _vp, _vp],
     }
@@ -281,6 +283,10 @@ def bsp_skew_spectra(plan, delta_l, S):
 def bsp_integrated_bispectrum(plan, grid, wsum, s, k0, dk, nbins, iB, Psub=None, dbar=None):
     _check(lib().bsp_integrated_bispectrum(plan, _dptr(grid), _dptr(wsum), int(s), float(k0), float(dk), int(nbins),
                                            _dptr(iB), _dptr(Psub), _dptr(dbar)), plan)
+
+
+def bsp_bispectrum_full(plan, delta_l, prec, B):
+    _check(lib().bsp_bispectrum_full(plan, _dptr(delta_l), int(prec), _dptr(B)), plan)
 
 
 def bsp_set_timing(plan, enable: bool):

@@ -213,12 +213,14 @@ int64_t kchunk_for(int prec, int64_t K, int /*ngroups*/) {
   return kc;
 }
 
-ReduceDesc make_desc(const ReducePlan& rp, int64_t K, int64_t field_stride, int prec, const float* scale) {
+// kc_min: a longer chunk (multiple of 64) when the partials must fit a given space.
+ReduceDesc make_desc(const ReducePlan& rp, int64_t K, int64_t field_stride, int prec, const float* scale,
+                     int64_t kc_min = 0) {
   ReduceDesc d{};
   d.nfields = rp.nfields;
   d.K = K;
   d.field_stride = field_stride;
-  d.kchunk = (int32_t)kchunk_for(prec, K, rp.ngroups);
+  d.kchunk = (int32_t)std::max<int64_t>(kchunk_for(prec, K, rp.ngroups), kc_min);
   d.nchunks = (int32_t)((K + d.kchunk - 1) / d.kchunk);
   d.ngroups = rp.ngroups;
   d.nct = rp.nct;
@@ -304,6 +306,9 @@ struct bsp_plan_s {
   double* d_L = nullptr;
   double* d_sn = nullptr;
   ReducePlan main_rp, cnt_rp, gram_rp, sn_rp;
+  ReducePlan full_rp;                // B^(l1 l2 l3): every (l2, l3) pair of shell fields, made on first use
+  bool full_built = false;
+  int32_t* d_full_tidx = nullptr;    // [nl^3][ntri] index of each output in T
   std::vector<int32_t> cnt_tidx, gidx, sidx, tri_tidx, tri_bins, combo;
   int32_t *d_cnt_tidx = nullptr, *d_gidx = nullptr, *d_sidx = nullptr, *d_urow = nullptr, *d_grow = nullptr;
   // workspace
@@ -731,8 +736,8 @@ bsp_status inverse_fields(bsp_plan p, const cplx_t<T>* src, int64_t src_ell_stri
 
 template <typename T>
 bsp_status run_reduce(bsp_plan p, const ReducePlan& rp, const T* fields, int64_t K, int prec, const float* scale,
-                      double* Tout, char* scratch, size_t scratch_bytes, double tscale) {
-  const ReduceDesc d = make_desc(rp, K, K, prec, scale);
+                      double* Tout, char* scratch, size_t scratch_bytes, double tscale, int64_t kc_min = 0) {
+  const ReduceDesc d = make_desc(rp, K, K, prec, scale, kc_min);
   const size_t need = (size_t)d.nchunks * d.ntiles * 256 * sizeof(T);
   if (need > scratch_bytes) return fail(p, BSP_ERR_WORKSPACE, "workspace too small for reduction partials");
   HIPCHK(hipMemsetAsync(Tout, 0, (size_t)rp.npairs * rp.nthirds * sizeof(double), p->stream));
@@ -1856,6 +1861,96 @@ bsp_status bsp_integrated_bispectrum(bsp_plan p, const float* grid, const double
                                      p->stream));
   }
   HIPCHK(hipStreamSynchronize(p->stream));  // the host tables above are read by the copies
+  return BSP_OK;
+}
+
+// Reduction schedule of B^(l1 l2 l3) over the shell fields D^l_b (field b nl + l):
+// pairs (D^l2_b2 D^l3_b3, b2 >= b3; for b2 = b3 only l2 <= l3, the other order
+// is the same product) in b2-major order, thirds D^l1_b1, every combination of
+// each triangle with a nonzero count.
+bool build_full(bsp_plan p) {
+  const int nb = p->nbins, nl = p->nl, nsh = nb * nl;
+  std::vector<std::array<int, 2>> pr;
+  std::vector<int> pidx((size_t)nsh * nsh, -1);
+  for (int b2 = 0; b2 < nb; ++b2)
+    for (int b3 = 0; b3 <= b2; ++b3)
+      for (int l2 = 0; l2 < nl; ++l2)
+        for (int l3 = 0; l3 < nl; ++l3) {
+          if (b2 == b3 && l3 < l2) continue;
+          const int f2 = b2 * nl + l2, f3 = b3 * nl + l3;
+          pidx[(size_t)f2 * nsh + f3] = pidx[(size_t)f3 * nsh + f2] = (int)pr.size();
+          pr.push_back({f2, f3});
+        }
+  std::vector<int> th(nsh);
+  for (int f = 0; f < nsh; ++f) th[f] = f;
+  const int ntri = (int)p->tri.size();
+  std::vector<uint8_t> need(pr.size() * nsh, 0);
+  std::vector<int32_t> tidx((size_t)nl * nl * nl * ntri, 0);
+  for (int i = 0; i < ntri; ++i) {
+    const int b1 = p->tri[i][0], b2 = p->tri[i][1], b3 = p->tri[i][2];
+    for (int l1 = 0; l1 < nl; ++l1)
+      for (int l2 = 0; l2 < nl; ++l2)
+        for (int l3 = 0; l3 < nl; ++l3) {
+          const int pair = pidx[(size_t)(b2 * nl + l2) * nsh + (b3 * nl + l3)];
+          const int third = b1 * nl + l1;
+          if (pair < 0) return false;
+          need[(size_t)pair * nsh + third] = 1;
+          tidx[((size_t)(l1 * nl + l2) * nl + l3) * ntri + i] = pair * nsh + third;
+        }
+  }
+  if (!build_reduce(p->full_rp, pr, th, need, nsh, 1)) return false;
+  if (!upload_rp(p, p->full_rp)) return false;
+  p->d_full_tidx = upload(p, tidx);
+  if (!p->d_full_tidx) return false;
+  p->full_built = true;
+  return true;
+}
+
+bsp_status bsp_bispectrum_full(bsp_plan p, const void* delta_l, bsp_precision prec, double* B) {
+  if (!p || !delta_l || !B) return fail(p, BSP_ERR_ARG, "null argument");
+  if (!p->pre_done) return fail(p, BSP_ERR_STATE, "bsp_precompute has not run");
+  if (prec < BSP_FP32 || prec > BSP_FP16X3) return fail(p, BSP_ERR_ARG, "bad precision");
+  if (!p->full_built && !build_full(p)) return fail(p, BSP_ERR_ARG, "full multipole reduction shape not supported");
+  const Layout L = layout(p);
+  bsp_status s = need_ws(p, L.total);
+  if (s != BSP_OK) return s;
+  const int Nr = p->Nr, nl = p->nl, nsh = p->nbins * nl;
+  const int64_t K = (int64_t)Nr * Nr * Nr;
+  char* ws = p->ws;
+  float* fields = reinterpret_cast<float*>(ws + L.dl);
+  double* small = reinterpret_cast<double*>(ws + L.dl + L.fields + L.T);
+  float* scale = reinterpret_cast<float*>(small + 2048);
+  unsigned* tmpu = reinterpret_cast<unsigned*>(small + 3072);
+  char* scr = ws + L.dl + L.fields + L.T + L.small;
+  const size_t scr_bytes = p->ws_bytes - (L.dl + L.fields + L.T + L.small);
+  // the shell fields D^l_b (the first nbins nl fields of the main numbering)
+  s = inverse_fields<float>(p, reinterpret_cast<const float2*>(delta_l), p->spec, nsh, p->d_field_ell,
+                            p->d_field_tab, p->d_tab32, p->d_rng32, fields, scr, L.fb, p->field_c,
+                            p->field_row32.data());
+  if (s != BSP_OK) return s;
+  const float* sc = nullptr;
+  if (prec == BSP_FP16X3) {
+    s = field_scales(p, fields, nsh, K, scale, tmpu);
+    if (s != BSP_OK) return s;
+    sc = scale;
+  }
+  const ReducePlan& rp = p->full_rp;
+  double* T = reinterpret_cast<double*>(scr);
+  const size_t tb = align_up((size_t)rp.npairs * rp.nthirds * sizeof(double));
+  if (scr_bytes <= tb) return fail(p, BSP_ERR_WORKSPACE, "workspace too small for the full multipoles");
+  // chunks long enough for the partials of every tile to fit the scratch
+  const size_t avail = scr_bytes - tb;
+  const int64_t per_chunk = (int64_t)rp.ntiles * 256 * (int64_t)sizeof(float);
+  const int64_t max_chunks = std::max<int64_t>(1, (int64_t)(avail / std::max<int64_t>(per_chunk, 1)));
+  int64_t kc_min = (K + max_chunks - 1) / max_chunks;
+  kc_min = (kc_min + 63) / 64 * 64;
+  s = run_reduce<float>(p, rp, fields, K, (int)prec, sc, T, scr + tb, avail, 1.0, kc_min);
+  if (s != BSP_OK) return s;
+  const double N = p->N;
+  const double norm_b = p->V * p->V / (std::pow(N, 9) * (double)K);
+  HIPCHK(launch_binned_finalize(T, p->d_full_tidx, (int)p->tri.size(), nl * nl * nl, p->d_counts, nullptr,
+                                p->d_nb_modes, p->nbins, p->d_tri_bins, norm_b, 0.0, nullptr, B, nullptr, nullptr,
+                                p->stream));
   return BSP_OK;
 }
 

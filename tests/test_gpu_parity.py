@@ -267,6 +267,48 @@ def test_integrated_bispectrum_rejects_bad_geometry():
     plan.close()
 
 
+@pytest.mark.parametrize("prec,tol", [(B.BSP_FP32, 1e-5), (B.BSP_BF16X3, 1e-3)])
+def test_bispectrum_full_against_oracle(prec, tol):
+    """B^(l1 l2 l3) for every combination (one LOS moment per side) against the
+    FP64 oracle; B^(l00) also against the whole path's B^l."""
+    say("bispectrum-full", prec)
+    n, box, k0, dk, nb = 32, 200.0, 2.0, 2.0, 4
+    obs = np.array([-300.0, -200.0, -250.0])
+    u = _catalogue(n, 30000, 23)
+    plan = B.Plan(n=n, box=box, nbins=nb, k0=k0, dk=dk, lmax=4, interlace=1, los=1, observer=obs)
+    plan.precompute()
+    info = plan.info
+    grids = torch.zeros((2, n, n, n), dtype=torch.float32, device=DEV)
+    wsum = torch.zeros(1, dtype=torch.float64, device=DEV)
+    B.bsp_grid_assign(plan.handle, dev(u[0]), dev(u[1]), dev(u[2]), None, u[0].size, grids, wsum)
+    dl = plan.spectrum_buffer()
+    B.bsp_los_moments(plan.handle, grids, wsum, dl)
+    nl, ntri = info.nl, info.ntri
+    Bf = torch.zeros((nl ** 3, ntri), dtype=torch.float64, device=DEV)
+    B.bsp_bispectrum_full(plan.handle, dl, prec, Bf)
+    Bl = torch.zeros((nl, ntri), dtype=torch.float64, device=DEV)
+    ux, uy, uz = dev(u[0]), dev(u[1]), dev(u[2])
+    B.bsp_bispectrum_multipoles(plan.handle, ux, uy, uz, None, u[0].size, prec, Bl, None, None, None, None, None)
+    plan.sync()
+    got, path = Bf.cpu().numpy(), Bl.cpu().numpy()
+    tris = [tuple(int(v) for v in t) for t in plan.tri]
+    counts = plan.counts.copy()
+    spec, _ = O.spectrum_from_catalogue(*u, n, 4, obs, window=1, interlace=1)
+    _, combos, T = O.binned_triple_sums_full(spec, n, n, k0, dk, nb, tris)
+    ref = O.binned_bispectrum(T, counts, n, n, box)
+    s0 = np.linalg.norm(ref[0])
+    worst = 0.0
+    for ci in range(nl ** 3):
+        e = np.linalg.norm(got[ci] - ref[ci]) / max(np.linalg.norm(ref[ci]), 0.01 * s0)
+        worst = max(worst, e)
+        assert e < tol, (combos[ci], e)
+    for li in range(nl):
+        ci = combos.index((li, 0, 0))
+        assert np.linalg.norm(got[ci] - path[li]) <= tol * max(np.linalg.norm(path[li]), 0.01 * s0), li
+    say("  worst combination error", worst)
+    plan.close()
+
+
 def test_grid_entry_against_oracle():
     say("grid-entry")
     n = 32
