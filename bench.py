@@ -237,6 +237,8 @@ def main():
     ap.add_argument("--prec", default="bf16x3", choices=["bf16x3", "fp16x3", "fp32"])
     ap.add_argument("--no-fp32", action="store_true", help="skip timing the FP32 path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the power-spectrum, skew-spectrum, integrated and full multipole legs")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run plain device copies of BYTES bytes (counter calibration) and exit")
     args = ap.parse_args()
@@ -374,8 +376,9 @@ def main():
         res["roofline"] = {"kernel": kernel_of.get(dom, dom), "stage": dom, "bound": "hbm",
                            "achieved": d["achieved_GBps"], "peak": PEAK_HBM / 1e9, "unit": "GB/s",
                            "frac": d["frac_hbm"], "traffic": traffic}
-    res["power_multipoles"], res["skew_spectra"], res["integrated_bispectrum"], res["bispectrum_full"] = \
-        spectra_legs(B, torch, plan, wl, ux, uy, uz, npart, o_mix["Pb"], o_mix["B"], prec, log)
+    if not args.no_legs:
+        res["power_multipoles"], res["skew_spectra"], res["integrated_bispectrum"], res["bispectrum_full"] = \
+            spectra_legs(B, torch, plan, wl, ux, uy, uz, npart, o_mix["Pb"], o_mix["B"], prec, log)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         res["cpu_baseline"] = cpu_baseline(wl, u, int(ntri), log)
