@@ -129,3 +129,67 @@ def test_full_size_modal_numerators(full_case):
             e = abs(got[prec][1][0, m] - ref) / max(scale, abs(ref))
             say("mode", m, (p, r, s), "prec", prec, "scaled err", e, "rel err", abs(got[prec][1][0, m] / ref - 1))
             assert e < tol, (m, prec, e)
+
+
+@pytest.fixture(scope="module")
+def spectra_case():
+    """The bench plan's LOS moments of a seeded white-noise contrast field
+    (bsp_grid_entry), then the power-spectrum multipoles, skew spectra and
+    integrated bispectrum (8^3 sub-volumes of 64^3, 20 shells of one
+    sub-volume fundamental) on the GPU, and the same from the FP64 oracle."""
+    t0 = time.time()
+    wl = C.workload("c3_512")
+    n = wl.n
+    obs = C.observer_grid_units(wl)
+    plan = B.Plan(n=n, box=wl.box, nbins=wl.nbins, k0=wl.k0, dk=wl.dk, lmax=4, window=1, compensate=1,
+                  interlace=1, los=1, observer=obs)
+    info = plan.info
+    d32 = np.random.Generator(np.random.PCG64(5121)).standard_normal((n, n, n), dtype=np.float32)
+    dd = torch.as_tensor(d32).to(DEV)
+    dl = plan.spectrum_buffer()
+    B.bsp_grid_entry(plan.handle, dd, dl)
+    P = torch.zeros((info.nl, wl.nbins), dtype=torch.float64, device=DEV)
+    S = torch.zeros((info.nl, wl.nbins), dtype=torch.float64, device=DEV)
+    s, ibn = 8, 20
+    iB = torch.zeros((info.nl, ibn), dtype=torch.float64, device=DEV)
+    Ps = torch.zeros((s ** 3, info.nl, ibn), dtype=torch.float64, device=DEV)
+    B.bsp_power_multipoles(plan.handle, dl, P)
+    B.bsp_skew_spectra(plan.handle, dl, S)
+    B.bsp_integrated_bispectrum(plan.handle, dd, None, s, 1.0, 1.0, ibn, iB, Ps, None)
+    plan.sync()
+    got = (P.cpu().numpy(), S.cpu().numpy(), iB.cpu().numpy(), Ps.cpu().numpy())
+    del dd, dl
+    plan.close()
+    torch.cuda.empty_cache()
+    say("spectra gpu", time.time() - t0)
+    d64 = d32.astype(np.float64)
+    del d32
+    spec = O.spectrum_from_field([d64], [0.0], n, 4, obs, None)
+    Pref, _ = O.power_multipoles(spec, n, wl.k0, wl.dk, wl.nbins, wl.box)
+    Sref, _ = O.skew_spectra(spec, n, n, wl.k0, wl.dk, wl.nbins, wl.box)
+    del spec
+    iBref, Psref, dbar, _ = O.integrated_bispectrum(d64, s, 4, obs, 1, wl.box, 1.0, 1.0, ibn)
+    say("spectra oracle", time.time() - t0)
+    return got, (Pref, Sref, iBref, Psref, dbar)
+
+
+def test_full_size_power_and_skew_spectra(spectra_case):
+    (P, S, _, _), (Pref, Sref, _, _, _) = spectra_case
+    for name, g, r, tol in (("P", P, Pref, 1e-5), ("S", S, Sref, 1e-4)):
+        s0 = np.linalg.norm(r[0])
+        for li in range(r.shape[0]):
+            e = np.linalg.norm(g[li] - r[li]) / max(np.linalg.norm(r[li]), 0.01 * s0)
+            say(name, "l", 2 * li, "err", e)
+            assert e < tol, (name, li, e)
+
+
+def test_full_size_integrated_bispectrum(spectra_case):
+    (_, _, iB, Ps), (_, _, iBref, Psref, dbar) = spectra_case
+    ns = Ps.shape[0]
+    for li in range(iB.shape[0]):
+        e = np.linalg.norm(Ps[:, li] - Psref[:, li]) / max(np.linalg.norm(Psref[:, li]),
+                                                           0.01 * np.linalg.norm(Psref[:, 0]))
+        scale = np.linalg.norm(np.abs(Psref[:, li]).T @ np.abs(dbar)) / ns
+        ei = np.linalg.norm(iB[li] - iBref[li]) / scale
+        say("iB l", 2 * li, "P err", e, "iB err / term scale", ei)
+        assert e < 1e-5 and ei < 1e-5, (li, e, ei)
