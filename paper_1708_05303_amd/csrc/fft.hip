@@ -177,6 +177,20 @@ __device__ __forceinline__ void fft_stages(V* __restrict__ buf, const V* __restr
   }
 }
 
+// Streaming store of a complex value (written once, read by a later kernel).
+template <typename V> __device__ __forceinline__ void nt_store(V* p, const V& v) {
+  using E = decltype(v.x);
+  typedef E E2 __attribute__((ext_vector_type(2)));
+  __builtin_nontemporal_store(E2{v.x, v.y}, reinterpret_cast<E2*>(p));
+}
+
+template <typename V> __device__ __forceinline__ V nt_load(const V* p) {
+  using E = decltype(p->x);
+  typedef E E2 __attribute__((ext_vector_type(2)));
+  const E2 v = __builtin_nontemporal_load(reinterpret_cast<const E2*>(p));
+  return V{v.x, v.y};
+}
+
 // exponents (x, y, z) of the x-hat product of each LOS field: the empty
 // product, the 6 sorted pairs and the 15 sorted quadruples over {x, y, z}.
 constexpr int8_t c_los_exp[22][3] = {
@@ -222,8 +236,8 @@ __device__ __forceinline__ void fwd_z_pairs(V* b, const V* tw, int t, const T* r
       V* o1 = out_g + ((int64_t)(F0 + 1) * nlines + line) * zs;
       for (int k = t; k < cout; k += NT) {
         const V zk = b[swz<1>(k)], zm = b[swz<1>((N - k) % N)];
-        o0[k] = V{(zk.x + zm.x) * (T)0.5, (zk.y - zm.y) * (T)0.5};
-        if constexpr (HAS1) o1[k] = V{(zk.y + zm.y) * (T)0.5, (zm.x - zk.x) * (T)0.5};
+        nt_store(o0 + k, V{(zk.x + zm.x) * (T)0.5, (zk.y - zm.y) * (T)0.5});
+        if constexpr (HAS1) nt_store(o1 + k, V{(zk.y + zm.y) * (T)0.5, (zm.x - zk.x) * (T)0.5});
       }
     }
     lds_sync<FZ_WAVE_SYNC && line_in_wave(N)>();
@@ -345,7 +359,7 @@ __global__ __launch_bounds__(256) void k_c2c(const cplx_t<T>* __restrict__ in, c
             v[e] = V{x.x * wgt, x.y * wgt};
           }
         } else {
-          v[e] = src[(int64_t)r * p.in_row + icol];
+          v[e] = nt_load(src + (int64_t)r * p.in_row + icol);
         }
       }
     }
@@ -361,7 +375,7 @@ __global__ __launch_bounds__(256) void k_c2c(const cplx_t<T>* __restrict__ in, c
 #pragma unroll 4
     for (int r = j0; r < p.out_rows; r += NT) {
       const int pos = (r - p.out_off + N) % N;
-      dst[(int64_t)r * p.out_row + ocol] = buf[c * PAD + pos];
+      nt_store(dst + (int64_t)r * p.out_row + ocol, buf[c * PAD + pos]);
     }
   }
 }
@@ -415,8 +429,8 @@ __global__ __launch_bounds__(256) void k_inv_z(const cplx_t<T>* __restrict__ in,
       T* o1 = out + (int64_t)f1 * out_field + line * N;
       for (int pos = t; pos < N; pos += NT) {
         const V v = b[swz<SW>(pos)];
-        o0[pos] = v.x;
-        if (has1) o1[pos] = v.y;
+        __builtin_nontemporal_store(v.x, o0 + pos);
+        if (has1) __builtin_nontemporal_store(v.y, o1 + pos);
       }
     }
     lds_sync<line_in_wave(N)>();  // the next line reuses the buffer

@@ -96,7 +96,10 @@ __global__ __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
         const int f = vi / (KS / EPV), e = (vi % (KS / EPV)) * EPV;
         const T* src = fields + (int64_t)f * d.field_stride + kb + e;
         if (full) {
-          val = *reinterpret_cast<const VEC*>(src);
+          typedef T TV __attribute__((ext_vector_type(EPV)));
+          const TV x = __builtin_nontemporal_load(reinterpret_cast<const TV*>(src));
+          if constexpr (EPV == 4) val = VEC{x[0], x[1], x[2], x[3]};
+          else val = VEC{x[0], x[1]};
         } else {
           T tmp[EPV];
 #pragma unroll
