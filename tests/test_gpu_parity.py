@@ -302,9 +302,10 @@ def test_bispectrum_full_against_oracle(prec, tol):
         e = np.linalg.norm(got[ci] - ref[ci]) / max(np.linalg.norm(ref[ci]), 0.01 * s0)
         worst = max(worst, e)
         assert e < tol, (combos[ci], e)
+    # two GPU results, each within tol of the oracle: their difference is bounded by 2 tol
     for li in range(nl):
         ci = combos.index((li, 0, 0))
-        assert np.linalg.norm(got[ci] - path[li]) <= tol * max(np.linalg.norm(path[li]), 0.01 * s0), li
+        assert np.linalg.norm(got[ci] - path[li]) <= 2 * tol * max(np.linalg.norm(path[li]), 0.01 * s0), li
     say("  worst combination error", worst)
     plan.close()
 
