@@ -114,6 +114,38 @@ def test_grid_assign_rejects_out_of_range():
     assert abs(grids.sum().item() - 2.0) < 1e-6
 
 
+def test_grid_assign_empty_catalogue():
+    """Zero particles: both assignment paths leave the grids and the weight sum alone."""
+    for tiled in (False, True):
+        say("assign-empty", tiled)
+        n = 32
+        plan = B.Plan(n=n, box=100.0, nbins=1, k0=1.0, dk=1.0, interlace=1, workspace=tiled)
+        grids = torch.full((2, n, n, n), 0.5, dtype=torch.float32, device=DEV)
+        wsum = torch.zeros(1, dtype=torch.float64, device=DEV)
+        e = torch.zeros(1, dtype=torch.float32, device=DEV)
+        B.bsp_grid_assign(plan.handle, e, e, e, None, 0, grids, wsum)
+        plan.sync()
+        assert bool(torch.all(grids == 0.5)) and wsum.item() == 0.0
+        plan.close()
+
+
+def test_whole_path_rejects_empty_catalogue():
+    plan = B.Plan(n=32, box=100.0, nbins=2, k0=2.0, dk=2.0)
+    e = torch.zeros(1, dtype=torch.float32, device=DEV)
+    Bt = torch.zeros((1, 4), dtype=torch.float64, device=DEV)
+    with pytest.raises(B.BspError):
+        B.bsp_bispectrum_multipoles(plan.handle, e, e, e, None, 0, B.BSP_FP32, Bt)
+    plan.close()
+
+
+def test_plan_rejects_wrapping_triangles():
+    """Shells up to |n| = 13 on a 32-point grid: closed triangles of the largest
+    shells would wrap around (3 c >= N'), so the plan is refused."""
+    with pytest.raises(B.BspError) as e:
+        B.Plan(n=32, box=100.0, nbins=6, k0=2.0, dk=2.0)
+    assert e.value.status == 3
+
+
 # ---------------------------------------------------------------- LOS moments
 
 def _catalogue(n, npart, seed, clustered=True):
@@ -538,3 +570,33 @@ def test_end_to_end_varying_los_interlaced(los_case, prec):
     _check_modal(got, ref, tbeta, 3)
     assert rel_norm(got["B0_sub"], ref["B0_sub"]) < tb
     assert rel_norm(got["Pbar"], ref["Pbar"]) < 1e-5
+
+
+@pytest.fixture(scope="module")
+def n96_case():
+    """96 points per side (z lines straddle waves: the transforms keep their
+    workgroup barriers), varying LOS, interlacing, l <= 2, 8 shells of 3 k_f."""
+    n, box = 96, 300.0
+    wl = C.Workload("n96", n, n, box, 150_000, -1.5, 0.6, 0.6, 1, 1, 1, 2, 8, 3.0, 0, 0, 96)
+    obs = C.observer_grid_units(wl)
+    plan = B.Plan(n=n, box=box, nbins=wl.nbins, k0=wl.k0, dk=wl.dk, lmax=2, window=1, interlace=1, los=1,
+                  observer=obs)
+    plan.precompute()
+    u = C.lognormal_catalogue(wl)
+    spec, wsum = O.spectrum_from_catalogue(*u, n, 2, obs, window=1, interlace=1)
+    geo = O.Geometry(n, n, box, 2, wl.nbins, wl.k0, wl.dk)
+    ref = O.estimate(spec, geo, nbar=wsum / box ** 3)
+    return wl, plan, u, ref
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_end_to_end_n96(n96_case, prec):
+    say("e2e-n96", prec)
+    wl, plan, u, ref = n96_case
+    got = _run_gpu(plan, u, prec, 2, 0)
+    assert np.array_equal(plan.counts, ref["counts"])
+    tb = 1e-5 if prec == 0 else 1e-3
+    for li in range(2):
+        assert rel_norm(got["B"][li], ref["B"][li]) < tb, li
+    assert rel_norm(got["Pbar"], ref["Pbar"]) < 1e-5
+    assert rel_norm(got["B0_sub"], ref["B0_sub"]) < tb
