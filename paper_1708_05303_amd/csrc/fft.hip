@@ -340,6 +340,16 @@ __global__ __launch_bounds__(256) void k_c2c(const cplx_t<T>* __restrict__ in, c
     src = in + (int64_t)outer * p.in_outer;
   }
   V* dst = out + (int64_t)outer * p.out_outer;
+  if constexpr (FILT) {
+    // a column with ny^2 + kz^2 >= hi (or kz beyond the cube) is zero after the
+    // filter for every nx; a tile of such columns only writes its zeros
+    const bool colnz = cv && fz_ok && fny * fny + kz * kz < hi2;
+    if (!__syncthreads_or(colnz)) {
+      if (cv)
+        for (int r = j0; r < p.out_rows; r += NT) nt_store(dst + (int64_t)r * p.out_row + ocol, V{(T)0, (T)0});
+      return;
+    }
+  }
   V v[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
