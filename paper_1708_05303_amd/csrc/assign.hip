@@ -248,7 +248,8 @@ __global__ __launch_bounds__(256) void k_assign_tiles(const float4* __restrict__
         val.z += old.z;
         val.w += old.w;
       }
-      *dst = val;
+      typedef float F4 __attribute__((ext_vector_type(4)));
+      __builtin_nontemporal_store(F4{val.x, val.y, val.z, val.w}, reinterpret_cast<F4*>(dst));
     }
   }
 }

@@ -68,7 +68,10 @@ __global__ __launch_bounds__(256) void k_los_combine(const cplx_t<T>* __restrict
   auto F = [&](int t) -> double2 {
     double2 s{0.0, 0.0};
     for (int g = 0; g < d.ngrid; ++g) {
-      const V x = X[((int64_t)g * d.nlos + t) * cube + idx];
+      using E = decltype(X->x);
+      typedef E E2 __attribute__((ext_vector_type(2)));
+      const E2 xv = __builtin_nontemporal_load(reinterpret_cast<const E2*>(X + ((int64_t)g * d.nlos + t) * cube + idx));
+      const V x = V{xv.x, xv.y};
       s.x += fac[g].x * (double)x.x - fac[g].y * (double)x.y;
       s.y += fac[g].x * (double)x.y + fac[g].y * (double)x.x;
     }
