@@ -19,8 +19,11 @@
  *   next bsp_sync.
  * Threading: a plan is not thread safe; use one plan per stream.
  * Memory: bsp_plan_create allocates the plan's small constant tables
- *   (twiddles, shell and modal filter tables, reduction schedules; a few MB);
- *   all large scratch comes from the caller's workspace (bsp_workspace_size).
+ *   (twiddles, shell and modal filter tables, reduction schedules; a few MB),
+ *   and the first bsp_bispectrum_full or bsp_integrated_bispectrum call adds
+ *   its own (the full-multipole schedule, sub-volume twiddles; kept with the
+ *   plan); all large scratch comes from the caller's workspace
+ *   (bsp_workspace_size). Calls that synchronise say so.
  *
  * Lattice conventions
  * -------------------
