@@ -181,7 +181,8 @@ bsp_status bsp_grid_entry(bsp_plan plan, const float* delta, void* delta_l);
  * DFT of (weight * delta^(l)) where filt[f] = {l_index, kind, index}:
  *   kind 0: shell indicator of bin `index` -> D^(l)_k(x) of eq. (Standard_ell_Estim);
  *   kind 1: modal weight q_index(k)/sqrt(k P_fid) -> N^3 M^(l)_n(x) of eq. (betaEst).
- * filt: host [nfilt][3]; fields: device [nfilt][N'^3] float. Uses the workspace. */
+ * filt: host [nfilt][3]; fields: device [nfilt][N'^3] float. Uses the workspace;
+ * synchronises once (after copying the filter list to the device). */
 bsp_status bsp_filter_fields(bsp_plan plan, const void* delta_l, int32_t nfilt, const int32_t* filt, float* fields);
 
 /* Triple reduction T[p][s] = sum_x F_{a_p}(x) F_{b_p}(x) F_{t_s}(x) over K points,
