@@ -582,6 +582,31 @@ def test_poisson_shot_noise_formula_unbiased():
     assert np.max(np.abs(_zscores(subs, 0.0))) < 5
 
 
+def test_modal_shot_noise_unbiased_for_poisson_points():
+    """Unclustered Poisson points (NGP, no compensation) with the fiducial power
+    equal to their total power 1/nbar: the modal shot-noise term of b^0 is its
+    whole expectation, E[b^0_m - b^SN_m] = 0 (then G^P = G / nbar and the term is
+    <GGG> / nbar^2, the Poisson three-point function projected on the modes).
+    The average over the three positions of the P-weighted factor cannot show
+    here (constant P_fid); the coefficients and the normalisation do: doubling
+    the term is rejected."""
+    n, box, lam = 16, 200.0, 0.5
+    k0, dk, nb, P = 1.5, 1.0, 4, 3
+    kmin, kmax = k0 - dk / 2, k0 + (nb - 1) * dk + dk / 2
+    kf = 2 * math.pi / box
+    modes = O.modal_modes(P, 10)
+    nbar = lam * n ** 3 / box ** 3
+    pfid = np.full(3 * n * n + 1, 1.0 / nbar)
+    sn = O.modal_shot_noise(n, modes, P, kmin, kmax, kf, box, pfid, nbar)
+    b0 = []
+    for r in range(120):
+        u = C.poisson_node_catalogue(n, lam, 1900 + r)
+        spec, wsum = O.spectrum_from_catalogue(*u, n, 0, None, window=0, compensate_window=False)
+        b0.append(O.modal_numerators(spec, n, n, modes, P, kmin, kmax, kf, pfid)[0])
+    assert np.max(np.abs(_zscores(b0, sn))) < 5
+    assert np.max(np.abs(_zscores(b0, 2 * sn))) > 5
+
+
 # ---------------------------------------------------------------- modal
 
 def _modal_geo(n=16):
