@@ -607,6 +607,54 @@ def test_modal_shot_noise_unbiased_for_poisson_points():
     assert np.max(np.abs(_zscores(b0, 2 * sn))) > 5
 
 
+def test_modal_shot_noise_unbiased_for_poisson_sampled_gaussian_field():
+    """A weak Gaussian field (power P_g steep in k, rms 0.1) Poisson-sampled at the
+    nodes has the three-point function [P_g(k1) + P_g(k2) + P_g(k3)] / nbar +
+    1 / nbar^2 and no other; with P_fid = P_g + 1/nbar the modal shot-noise term
+    is again the whole expectation of b^0. P_fid varies with k, so the average
+    over the three positions of its P-weighted factor matters: a one-position
+    version of that factor is rejected on the asymmetric modes."""
+    n, box, lam = 16, 200.0, 2.0
+    k0, dk, nb, P = 1.5, 1.0, 4, 3
+    kmin, kmax = k0 - dk / 2, k0 + (nb - 1) * dk + dk / 2
+    kf = 2 * math.pi / box
+    V = box ** 3
+    modes = O.modal_modes(P, 10)
+    nbar = lam * n ** 3 / V
+    n2 = O.n2_grid_half(n)
+    k = kf * np.sqrt(np.maximum(n2, 1))
+    mult = np.broadcast_to(np.where(np.arange(n // 2 + 1) == 0, 1.0, 2.0), n2.shape)
+    shape = np.where(n2 > 0, (k / kf) ** -2.5, 0.0)
+    amp = 0.01 / (float((shape * mult).sum()) / V)  # rms 0.1
+    Pg = amp * shape
+    kk = kf * np.sqrt(np.arange(3 * n * n + 1))
+    pfid = amp * (np.maximum(kk, kf) / kf) ** -2.5 + 1.0 / nbar
+    sn = O.modal_shot_noise(n, modes, P, kmin, kmax, kf, box, pfid, nbar)
+    rng = np.random.Generator(np.random.PCG64(2024))
+    b0 = []
+    for _ in range(1000):
+        g = sfft.irfftn(sfft.rfftn(rng.standard_normal((n, n, n))) * np.sqrt(n ** 3 * Pg / V), s=(n,) * 3)
+        rho = rng.poisson(lam * np.clip(1 + g, 0, None)).astype(np.float64)
+        spec = O.spectrum_from_field([O.density_contrast(rho, rho.sum())], [0.0], n, 0, None, None)
+        b0.append(O.modal_numerators(spec, n, n, modes, P, kmin, kmax, kf, pfid)[0])
+    assert np.max(np.abs(_zscores(b0, sn))) < 5
+    assert np.max(np.abs(_zscores(b0, 2 * sn))) > 5
+    # negative control: the P-weighted factor at the first position only
+    kn = np.sqrt(n2.astype(np.float64))
+    ok = O.bispec.in_modal_range(n2, kmin, kmax)
+    kph = np.where(ok, kf * kn, 1.0)
+    pf = np.where(ok, pfid[np.minimum(n2, len(pfid) - 1)], 1.0)
+    G, GP = [], []
+    for p in range(P):
+        q = np.where(ok, O.bispec.modal_q(p, kn, kmin, kmax), 0.0)
+        G.append(sfft.irfftn(q / np.sqrt(kph * pf), s=(n,) * 3).ravel() * float(n) ** 3)
+        GP.append(sfft.irfftn(q * np.sqrt(pf / kph), s=(n,) * 3).ravel() * float(n) ** 3)
+    norm = 1.0 / (V ** 2 * float(n) ** 3)
+    one = np.array([norm * (3.0 / nbar * np.dot(GP[p] * G[r], G[s]) - 2.0 / nbar ** 2 * np.dot(G[p] * G[r], G[s]))
+                    for (p, r, s) in modes])
+    assert np.max(np.abs(_zscores(b0, one))) > 5
+
+
 # ---------------------------------------------------------------- modal
 
 def _modal_geo(n=16):
