@@ -258,6 +258,7 @@ struct bsp_plan_s {
   int N = 0, Nr = 0, c = 0, cz = 0, nl = 1, nlos = 1, ngrid = 1, n2max = 0, plane = 1;
   int nbins = 0;
   int64_t spec = 0;  // compact cube elements
+  int64_t kept = 0;  // stored modes with 0 < n2 <= n2max (kz >= 0)
   double V = 0, kf = 0, kmin = 0, kmax = 0;
   // modal basis
   bool modal = false;
@@ -575,7 +576,9 @@ bsp_status forward_moments(bsp_plan p, const float* grids, int ngrid, int contra
   ld.compensate = compensate;
   ld.n2max = p->n2max;
   {
-    StageTimer t(p, 4, (double)W1 * W1 * C1 * 8.0 * (nb + p->nl));
+    // the weighted spectra are read only inside the sphere n2 <= n2max; the
+    // moments are written over the compact box (zeros outside the sphere)
+    StageTimer t(p, 4, 8.0 * ((double)p->kept * nb + W1 * W1 * C1 * p->nl));
     HIPCHK(launch_los_combine(X, delta_l, ld, p->stream));
   }
   return BSP_OK;
@@ -1015,6 +1018,16 @@ bsp_status bsp_plan_create(bsp_plan* out, const bsp_geom* g, const bsp_modal_bas
   p->cz = (p->c + 1 + 15) / 16 * 16;
   const int w = 2 * p->c + 1;
   p->spec = (int64_t)w * w * p->cz;
+  p->kept = -1;  // the origin
+  for (int nx = -p->c; nx <= p->c; ++nx)
+    for (int ny = -p->c; ny <= p->c; ++ny) {
+      const int64_t r = (int64_t)p->n2max - nx * nx - ny * ny;
+      if (r < 0) continue;
+      int kz = (int)std::sqrt((double)r);
+      while ((int64_t)(kz + 1) * (kz + 1) <= r) ++kz;
+      while ((int64_t)kz * kz > r) --kz;
+      p->kept += std::min(kz, p->c) + 1;
+    }
   p->bin_of_n2.assign(p->n2max + 1, -1);
   for (int n2 = 0; n2 <= p->n2max; ++n2)
     for (int b = 0; b < g->nbins; ++b)

@@ -80,8 +80,10 @@ __global__ __launch_bounds__(256) void k_assign(const float* __restrict__ ux, co
 }
 
 // ---------------------------------------------------------------------------
-// Tiled assignment without global atomics: particles are counted and sorted by
-// the 8 x 8 x TZ tile of their node floor(x); one workgroup per tile gathers
+// Tiled assignment without global atomics on the grids: particles are counted
+// by the 8 x 8 x TZ tile of their node floor(x) (the count's atomic returns each
+// particle's rank within its tile, kept for the scatter) and placed at their
+// tile's offset plus that rank; one workgroup per tile gathers
 // the particles of its own tile and of the 7 tiles below it (a CIC or NGP
 // cloud, also on the grid shifted by half a cell, reaches at most two nodes
 // past floor(x)), sums their weights into LDS and writes its nodes once.
@@ -96,8 +98,8 @@ __device__ __forceinline__ bool valid_particle(float x, float y, float z, float 
 __global__ __launch_bounds__(256) void k_tile_count(const float* __restrict__ ux, const float* __restrict__ uy,
                                                     const float* __restrict__ uz, const float* __restrict__ w,
                                                     int64_t np, int n, int ntx, int ntz, int tz,
-                                                    int32_t* __restrict__ count, double* __restrict__ wsum,
-                                                    int32_t* __restrict__ err) {
+                                                    int32_t* __restrict__ count, int32_t* __restrict__ rank,
+                                                    double* __restrict__ wsum, int32_t* __restrict__ err) {
   const float fn = (float)n;
   double acc = 0.0;
   int bad = 0;
@@ -110,7 +112,7 @@ __global__ __launch_bounds__(256) void k_tile_count(const float* __restrict__ ux
     }
     acc += (double)wt;
     const int key = (((int)x / TXY) * ntx + (int)y / TXY) * ntz + (int)z / tz;
-    atomicAdd(count + key, 1);
+    rank[i] = atomicAdd(count + key, 1);
   }
   __shared__ double red[256];
   red[threadIdx.x] = acc;
@@ -123,10 +125,10 @@ __global__ __launch_bounds__(256) void k_tile_count(const float* __restrict__ ux
   if (bad) atomicOr(err, 1);
 }
 
-// Exclusive prefix sum of count[0..nt) into offs[0..nt] and cursor[0..nt), one
-// workgroup of 1024 threads, each scanning a contiguous run.
+// Exclusive prefix sum of count[0..nt) into offs[0..nt], one workgroup of 1024
+// threads, each scanning a contiguous run.
 __global__ __launch_bounds__(1024) void k_tile_scan(const int32_t* __restrict__ count, int nt,
-                                                     int32_t* __restrict__ offs, int32_t* __restrict__ cursor) {
+                                                     int32_t* __restrict__ offs) {
   __shared__ int32_t part[1024];
   const int t = threadIdx.x;
   const int per = (nt + 1023) / 1024;
@@ -144,7 +146,6 @@ __global__ __launch_bounds__(1024) void k_tile_scan(const int32_t* __restrict__ 
   int run = part[t] - s;
   for (int i = b; i < e; ++i) {
     offs[i] = run;
-    cursor[i] = run;
     run += count[i];
   }
   if (t == 1023) offs[nt] = part[1023];
@@ -153,15 +154,15 @@ __global__ __launch_bounds__(1024) void k_tile_scan(const int32_t* __restrict__ 
 __global__ __launch_bounds__(256) void k_tile_scatter(const float* __restrict__ ux, const float* __restrict__ uy,
                                                       const float* __restrict__ uz, const float* __restrict__ w,
                                                       int64_t np, int n, int ntx, int ntz, int tz,
-                                                      int32_t* __restrict__ cursor, float4* __restrict__ sorted) {
+                                                      const int32_t* __restrict__ offs,
+                                                      const int32_t* __restrict__ rank, float4* __restrict__ sorted) {
   const float fn = (float)n;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
     const float x = ux[i], y = uy[i], z = uz[i];
     const float wt = w ? w[i] : 1.0f;
     if (!valid_particle(x, y, z, wt, fn)) continue;
     const int key = (((int)x / TXY) * ntx + (int)y / TXY) * ntz + (int)z / tz;
-    const int pos = atomicAdd(cursor + key, 1);
-    sorted[pos] = make_float4(x, y, z, wt);
+    sorted[offs[key] + rank[i]] = make_float4(x, y, z, wt);
   }
 }
 
@@ -267,7 +268,8 @@ size_t assign_tiled_bytes(int64_t np, int n) {
   const int tz = tile_tz(n);
   if (!tz || np <= 0 || np > (int64_t)INT32_MAX) return 0;
   const int64_t nt = (int64_t)(n / TXY) * (n / TXY) * (n / tz);
-  return align256((size_t)np * sizeof(float4)) + 3 * align256((size_t)(nt + 1) * sizeof(int32_t));
+  return align256((size_t)np * sizeof(float4)) + 2 * align256((size_t)(nt + 1) * sizeof(int32_t)) +
+         align256((size_t)np * sizeof(int32_t));
 }
 
 hipError_t launch_assign_tiled(const float* ux, const float* uy, const float* uz, const float* w, int64_t np, int n,
@@ -283,16 +285,16 @@ hipError_t launch_assign_tiled(const float* ux, const float* uy, const float* uz
   float4* sorted = reinterpret_cast<float4*>(base);
   int32_t* count = reinterpret_cast<int32_t*>(base + align256((size_t)np * sizeof(float4)));
   int32_t* offs = count + align256((size_t)(nt + 1) * sizeof(int32_t)) / sizeof(int32_t);
-  int32_t* cursor = offs + align256((size_t)(nt + 1) * sizeof(int32_t)) / sizeof(int32_t);
+  int32_t* rank = offs + align256((size_t)(nt + 1) * sizeof(int32_t)) / sizeof(int32_t);
   hipError_t e = hipMemsetAsync(count, 0, (size_t)nt * sizeof(int32_t), s);
   if (e != hipSuccess) return e;
   int64_t blocks = (np + 255) / 256;
   if (blocks > 16384) blocks = 16384;
   hipLaunchKernelGGL(k_tile_count, dim3((unsigned)blocks), dim3(256), 0, s, ux, uy, uz, w, np, n, ntx, ntz, tz, count,
-                     wsum, err);
-  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, count, nt, offs, cursor);
+                     rank, wsum, err);
+  hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, count, nt, offs);
   hipLaunchKernelGGL(k_tile_scatter, dim3((unsigned)blocks), dim3(256), 0, s, ux, uy, uz, w, np, n, ntx, ntz, tz,
-                     cursor, sorted);
+                     offs, rank, sorted);
 #define TCASE(WIN, TZV)                                                                                         if (window == WIN && tz == TZV) {                                                                               hipLaunchKernelGGL((k_assign_tiles<WIN, TZV>), dim3((unsigned)nt), dim3(256), 0, s, sorted, offs, n, ntx,                        ntz, interlace, accumulate, grids);                                                        return hipGetLastError();                                                                                   }
   TCASE(0, 64) TCASE(0, 32) TCASE(0, 16) TCASE(0, 8) TCASE(1, 64) TCASE(1, 32) TCASE(1, 16) TCASE(1, 8)
 #undef TCASE

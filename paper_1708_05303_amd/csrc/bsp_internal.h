@@ -124,7 +124,6 @@ struct LosDesc {
   int32_t n2max;
 };
 hipError_t launch_los_combine(const float2* X, float2* delta_l, const LosDesc& d, hipStream_t s);
-hipError_t launch_los_combine_f64(const double2* X, double2* delta_l, const LosDesc& d, hipStream_t s);
 hipError_t launch_shell_power(const float2* delta0, int c, int cz, const int32_t* bin_of_n2,
                               int n2max, int nbins, double* psum, hipStream_t s);
 // Shell cross sums out[l][b] = scale * sum_{n in b} Re[delta^(l)(n) conj X(n)] / N_b over

@@ -215,8 +215,8 @@ template <int F, typename T> __device__ __forceinline__ T los_weight(T hx, T hy,
 // One packed pair (F0, F0+1) of LOS fields for every line of the block, then
 // the next pair; the field indices are compile-time so the weights unroll.
 template <int F0, int NLOS, typename T, typename V, int N, int NT, int E, int PAD>
-__device__ __forceinline__ void fwd_z_pairs(V* b, const V* tw, int t, const T* rv, const T* hx, const T* hy,
-                                            const T* hz, bool plane, bool valid, V* out_g, int64_t nlines,
+__device__ __forceinline__ void fwd_z_pairs(V* b, const V* tw, int t, const T* rv, T rx, T ry, T sh, T oz,
+                                            const T* inv, bool plane, bool valid, V* out_g, int64_t nlines,
                                             int64_t line, int cout, int zs) {
   if constexpr (F0 < NLOS) {
     constexpr bool HAS1 = F0 + 1 < NLOS;
@@ -224,8 +224,10 @@ __device__ __forceinline__ void fwd_z_pairs(V* b, const V* tw, int t, const T* r
     for (int e = 0; e < E; ++e) {
       T w0 = (T)1, w1 = (T)0;
       if (!plane) {
-        w0 = los_weight<F0>(hx[e], hy[e], hz[e]);
-        if constexpr (HAS1) w1 = los_weight<(HAS1 ? F0 + 1 : 0)>(hx[e], hy[e], hz[e]);
+        // x_hat of node z = t + e NT, rebuilt from its 1 / |r| (fewer live registers)
+        const T hx = rx * inv[e], hy = ry * inv[e], hz = ((T)(t + e * NT) - sh - oz) * inv[e];
+        w0 = los_weight<F0>(hx, hy, hz);
+        if constexpr (HAS1) w1 = los_weight<(HAS1 ? F0 + 1 : 0)>(hx, hy, hz);
       }
       b[swz<1>(t + e * NT)] = V{w0 * rv[e], w1 * rv[e]};
     }
@@ -241,16 +243,18 @@ __device__ __forceinline__ void fwd_z_pairs(V* b, const V* tw, int t, const T* r
       }
     }
     lds_sync<FZ_WAVE_SYNC && line_in_wave(N)>();
-    fwd_z_pairs<F0 + 2, NLOS, T, V, N, NT, E, PAD>(b, tw, t, rv, hx, hy, hz, plane, valid, out_g, nlines, line,
-                                                   cout, zs);
+    fwd_z_pairs<F0 + 2, NLOS, T, V, N, NT, E, PAD>(b, tw, t, rv, rx, ry, sh, oz, inv, plane, valid, out_g, nlines,
+                                                   line, cout, zs);
   }
 }
 
 // ---------------------------------------------------------------- fwd_z
 // grid: blockIdx.x -> LZ_GROUPS consecutive groups of L lines (line = x*N + y), blockIdx.y -> input grid.
+// FP32 power-of-two sizes are held to 96 registers (five waves per SIMD); the
+// radix-3 sizes and FP64 would spill there.
 template <typename T, int N, int NLOS>
-__global__ __launch_bounds__(256) void k_fwd_z(const T* __restrict__ in, cplx_t<T>* __restrict__ out,
-                                               FwdZDesc d, const cplx_t<T>* __restrict__ twg) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && (N & (N - 1)) == 0 ? 5 : 1)))
+void k_fwd_z(const T* __restrict__ in, cplx_t<T>* __restrict__ out, FwdZDesc d, const cplx_t<T>* __restrict__ twg) {
   using V = cplx_t<T>;
   constexpr int NT = (N >= 8) ? N / 8 : 1;
   constexpr int L = 256 / NT;
@@ -278,22 +282,20 @@ __global__ __launch_bounds__(256) void k_fwd_z(const T* __restrict__ in, cplx_t<
     T rv[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) rv[e] = valid ? src[t + e * NT] * scale - sub : (T)0;
-    T hx[E], hy[E], hz[E];
+    T inv[E];
+    T rx = (T)0, ry = (T)0;
+    const T sh = (T)d.shift[g], oz = (T)d.obs[2];
     if (!d.plane) {
-      const T s = (T)d.shift[g];
-      const T rx = (T)x - s - (T)d.obs[0];
-      const T ry = (T)y - s - (T)d.obs[1];
+      rx = (T)x - sh - (T)d.obs[0];
+      ry = (T)y - sh - (T)d.obs[1];
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        const T rz = (T)(t + e * NT) - s - (T)d.obs[2];
-        const T inv = (T)1 / sqrt(rx * rx + ry * ry + rz * rz);
-        hx[e] = rx * inv;
-        hy[e] = ry * inv;
-        hz[e] = rz * inv;
+        const T rz = (T)(t + e * NT) - sh - oz;
+        inv[e] = (T)1 / sqrt(rx * rx + ry * ry + rz * rz);
       }
     }
-    fwd_z_pairs<0, NLOS, T, V, N, NT, E, PAD>(b, tw, t, rv, hx, hy, hz, d.plane != 0, valid, out_g, nlines, line,
-                                              d.cout, d.zs);
+    fwd_z_pairs<0, NLOS, T, V, N, NT, E, PAD>(b, tw, t, rv, rx, ry, sh, oz, inv, d.plane != 0, valid, out_g, nlines,
+                                              line, d.cout, d.zs);
   }
 }
 

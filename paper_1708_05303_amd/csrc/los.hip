@@ -15,13 +15,16 @@
 
 namespace bsp {
 
-__constant__ int8_t c_exp[22][3] = {
+// Exponents of (x_hat, y_hat, z_hat) and multinomial multiplicities of the 22
+// weighted fields: 1, the 6 of mu^2 (i <= j), the 15 of mu^4 (i <= j <= k <= l).
+// Compile-time tables: the kernel's loops over them unroll and the powers fold.
+constexpr int8_t kMonoExp[22][3] = {
     {0, 0, 0},
     {2, 0, 0}, {1, 1, 0}, {1, 0, 1}, {0, 2, 0}, {0, 1, 1}, {0, 0, 2},
     {4, 0, 0}, {3, 1, 0}, {3, 0, 1}, {2, 2, 0}, {2, 1, 1}, {2, 0, 2}, {1, 3, 0},
     {1, 2, 1}, {1, 1, 2}, {1, 0, 3}, {0, 4, 0}, {0, 3, 1}, {0, 2, 2}, {0, 1, 3},
     {0, 0, 4}};
-__constant__ double c_mult[22] = {1, 1, 2, 2, 1, 2, 1, 1, 4, 4, 6, 12, 6, 4, 12, 12, 4, 1, 4, 6, 4, 1};
+constexpr double kMonoMult[22] = {1, 1, 2, 2, 1, 2, 1, 1, 4, 4, 6, 12, 6, 4, 12, 12, 4, 1, 4, 6, 4, 1};
 
 __device__ __forceinline__ double dpow(double x, int e) {
   double r = 1.0;
@@ -35,10 +38,14 @@ __device__ __forceinline__ double sinc_pi(int n, int N) {
   return sin(a) / a;
 }
 
-template <typename T>
+// One mode per thread. NLOS weighted fields per grid (1, 7 or 22) and NG grids
+// are template parameters so that all NG x NLOS loads of a mode are issued
+// before its arithmetic.
+template <typename T, int NLOS, int NG>
 __global__ __launch_bounds__(256) void k_los_combine(const cplx_t<T>* __restrict__ X, cplx_t<T>* __restrict__ dl,
                                                      LosDesc d) {
   using V = cplx_t<T>;
+  typedef T T2 __attribute__((ext_vector_type(2)));
   const int w = 2 * d.c + 1;
   const int64_t cube = (int64_t)w * w * d.cz;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -53,6 +60,12 @@ __global__ __launch_bounds__(256) void k_los_combine(const cplx_t<T>* __restrict
     for (int l = 0; l < nl; ++l) dl[l * cube + idx] = V{(T)0, (T)0};
     return;
   }
+  T2 xv[NG][NLOS];
+#pragma unroll
+  for (int g = 0; g < NG; ++g)
+#pragma unroll
+    for (int t = 0; t < NLOS; ++t)
+      xv[g][t] = __builtin_nontemporal_load(reinterpret_cast<const T2*>(X + ((int64_t)g * NLOS + t) * cube + idx));
   double comp = 1.0;
   if (d.compensate) {
     double wv = sinc_pi(nx, d.n) * sinc_pi(ny, d.n) * sinc_pi(nz, d.n);
@@ -60,35 +73,42 @@ __global__ __launch_bounds__(256) void k_los_combine(const cplx_t<T>* __restrict
     comp = 1.0 / wv;
   }
   double2 fac[2];
-  fac[0] = double2{comp / d.ngrid, 0.0};
-  {
+  fac[0] = double2{comp / NG, 0.0};
+  if constexpr (NG == 2) {
     const double ph = M_PI * (double)(nx + ny + nz) / (double)d.n;
-    fac[1] = double2{comp / d.ngrid * cos(ph), comp / d.ngrid * sin(ph)};
+    fac[1] = double2{comp / NG * cos(ph), comp / NG * sin(ph)};
   }
   auto F = [&](int t) -> double2 {
     double2 s{0.0, 0.0};
-    for (int g = 0; g < d.ngrid; ++g) {
-      using E = decltype(X->x);
-      typedef E E2 __attribute__((ext_vector_type(2)));
-      const E2 xv = __builtin_nontemporal_load(reinterpret_cast<const E2*>(X + ((int64_t)g * d.nlos + t) * cube + idx));
-      const V x = V{xv.x, xv.y};
-      s.x += fac[g].x * (double)x.x - fac[g].y * (double)x.y;
-      s.y += fac[g].x * (double)x.y + fac[g].y * (double)x.x;
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+      s.x += fac[g].x * (double)xv[g][t].x - fac[g].y * (double)xv[g][t].y;
+      s.y += fac[g].x * (double)xv[g][t].y + fac[g].y * (double)xv[g][t].x;
     }
     return s;
   };
   const double inv = 1.0 / sqrt((double)n2);
   const double kh[3] = {nx * inv, ny * inv, nz * inv};
+  auto mono = [&](int t) -> double {
+    double m = kMonoMult[t];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int e = 0; e < kMonoExp[t][a]; ++e) m *= kh[a];
+    return m;
+  };
   const double2 F0 = F(0);
   dl[idx] = V{(T)F0.x, (T)F0.y};
   if (d.lmax < 2) return;
   double2 A2{0.0, 0.0};
-  if (d.plane) {
+  if constexpr (NLOS == 1) {
+    // plane-parallel: mu = k_hat . z_hat for every node
     const double m = kh[2] * kh[2];
     A2 = double2{m * F0.x, m * F0.y};
   } else {
+#pragma unroll
     for (int t = 1; t <= 6; ++t) {
-      const double m = c_mult[t] * dpow(kh[0], c_exp[t][0]) * dpow(kh[1], c_exp[t][1]) * dpow(kh[2], c_exp[t][2]);
+      const double m = mono(t);
       const double2 f = F(t);
       A2.x += m * f.x;
       A2.y += m * f.y;
@@ -97,12 +117,13 @@ __global__ __launch_bounds__(256) void k_los_combine(const cplx_t<T>* __restrict
   dl[cube + idx] = V{(T)(2.5 * (3.0 * A2.x - F0.x)), (T)(2.5 * (3.0 * A2.y - F0.y))};
   if (d.lmax < 4) return;
   double2 A4{0.0, 0.0};
-  if (d.plane) {
+  if constexpr (NLOS == 1) {
     const double m = kh[2] * kh[2] * kh[2] * kh[2];
     A4 = double2{m * F0.x, m * F0.y};
-  } else {
+  } else if constexpr (NLOS == 22) {
+#pragma unroll
     for (int t = 7; t <= 21; ++t) {
-      const double m = c_mult[t] * dpow(kh[0], c_exp[t][0]) * dpow(kh[1], c_exp[t][1]) * dpow(kh[2], c_exp[t][2]);
+      const double m = mono(t);
       const double2 f = F(t);
       A4.x += m * f.x;
       A4.y += m * f.y;
@@ -223,18 +244,29 @@ hipError_t launch_square(float* x, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_los_combine(const float2* X, float2* delta_l, const LosDesc& d, hipStream_t s) {
+// The field count must match the moments asked for: one field (lmax 0, or a
+// plane-parallel line of sight), 7 (lmax 2) or 22 (lmax 4).
+template <typename T>
+static hipError_t los_combine_impl(const cplx_t<T>* X, cplx_t<T>* delta_l, const LosDesc& d, hipStream_t s) {
+  if (d.ngrid < 1 || d.ngrid > 2 || d.lmax < 0 || d.lmax > 4) return hipErrorInvalidValue;
+  const bool ok = d.nlos == 1 ? (d.plane || d.lmax == 0) : (d.nlos == 7 ? d.lmax <= 2 : d.nlos == 22);
+  if (!ok) return hipErrorInvalidValue;
   const int64_t cube = (int64_t)(2 * d.c + 1) * (2 * d.c + 1) * d.cz;
-  hipLaunchKernelGGL((k_los_combine<float>), dim3((unsigned)((cube + 255) / 256)), dim3(256), 0, s, X, delta_l, d);
-  return hipGetLastError();
+  const dim3 grid((unsigned)((cube + 255) / 256));
+#define LCASE(NL, G)                                                                                   \
+  if (d.nlos == NL && d.ngrid == G) {                                                                  \
+    hipLaunchKernelGGL((k_los_combine<T, NL, G>), grid, dim3(256), 0, s, X, delta_l, d);              \
+    return hipGetLastError();                                                                          \
+  }
+  LCASE(1, 1) LCASE(1, 2) LCASE(7, 1) LCASE(7, 2) LCASE(22, 1) LCASE(22, 2)
+#undef LCASE
+  return hipErrorInvalidValue;
 }
 
-hipError_t launch_los_combine_f64(const double2* X, double2* delta_l, const LosDesc& d, hipStream_t s) {
-  const int64_t cube = (int64_t)(2 * d.c + 1) * (2 * d.c + 1) * d.cz;
-  hipLaunchKernelGGL((k_los_combine<double>), dim3((unsigned)((cube + 255) / 256)), dim3(256), 0, s, X, delta_l,
-                     d);
-  return hipGetLastError();
+hipError_t launch_los_combine(const float2* X, float2* delta_l, const LosDesc& d, hipStream_t s) {
+  return los_combine_impl<float>(X, delta_l, d, s);
 }
+
 
 hipError_t launch_shell_power(const float2* delta0, int c, int cz, const int32_t* bin_of_n2, int n2max,
                               int nbins, double* psum, hipStream_t s) {
