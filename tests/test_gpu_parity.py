@@ -66,7 +66,7 @@ def _tiled_assign_bytes(npart, n):
     tz = next(t for t in (64, 32, 16, 8) if n % t == 0 and n // t >= 2)
     nt = (n // 8) ** 2 * (n // tz)
     up = lambda b: (b + 255) // 256 * 256
-    return up(npart * 16) + 3 * up((nt + 1) * 4)
+    return up(npart * 16) + 2 * up((nt + 1) * 4) + up(npart * 4)
 
 
 @pytest.mark.parametrize("n,window,interlace,tiled", [
@@ -97,6 +97,43 @@ def test_grid_assign_against_oracle(n, window, interlace, tiled):
         ref = O.assign(*u, n, w.astype(np.float64), window, 0.5 * s) + 0.25
         assert np.max(np.abs(g[s] - ref)) < 2e-6 * np.max(ref) + 1e-6, s
     assert abs(wsum.item() - float(w.astype(np.float64).sum())) < 1e-6 * w.sum()
+    plan.close()
+
+
+def test_grid_assign_tiled_clustered_with_invalid_particles():
+    """Sorted, tiled assignment of a clustered catalogue (most particles in a
+    cube straddling tile edges, many tiles empty) with invalid entries mixed in
+    (outside [0, N) or a NaN weight): the count and the scatter skip the same
+    particles, the valid ones match the oracle and the error is latched."""
+    say("assign-tiled-clustered-invalid")
+    n = 32
+    r = rng(41)
+    npart = 30000
+    hot = int(0.8 * npart)
+    u = [np.concatenate([r.uniform(7.0, 9.5, hot), r.uniform(0, n, npart - hot)]) for _ in range(3)]
+    u = [C.quantise_grid_units(a, n) for a in u]
+    w = r.uniform(0.5, 1.5, npart).astype(np.float32)
+    bad = np.array([5, 777, 12345, 29999])
+    u[0][bad[0]] = float(n)
+    u[1][bad[1]] = -0.5
+    w[bad[2]] = np.nan
+    u[2][bad[3]] = float(n) + 3.0
+    ok = np.ones(npart, bool)
+    ok[bad] = False
+    plan = B.Plan(n=n, box=100.0, nbins=1, k0=1.0, dk=1.0, window=1, interlace=1, workspace=True)
+    assert B.bsp_workspace_size(plan.handle) >= _tiled_assign_bytes(npart, n)
+    grids = torch.zeros((2, n, n, n), dtype=torch.float32, device=DEV)
+    wsum = torch.zeros(1, dtype=torch.float64, device=DEV)
+    B.bsp_grid_assign(plan.handle, dev(u[0]), dev(u[1]), dev(u[2]), dev(w), npart, grids, wsum)
+    with pytest.raises(B.BspError) as e:
+        plan.sync()
+    assert e.value.status == 6
+    g = grids.cpu().numpy()
+    wv = w[ok].astype(np.float64)
+    for s in range(2):
+        ref = O.assign(u[0][ok], u[1][ok], u[2][ok], n, wv, 1, 0.5 * s)
+        assert np.max(np.abs(g[s] - ref)) < 2e-6 * np.max(ref), s
+    assert abs(wsum.item() - wv.sum()) < 1e-6 * wv.sum()
     plan.close()
 
 
