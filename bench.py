@@ -24,7 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM = 8.0e12          # B/s
-PEAK_MFMA = {"fp32": 157.3e12, "bf16x3": 2.5e15, "fp16x3": 2.5e15}
+PEAK_MFMA = {"fp32": 157.3e12, "bf16x3": 2.5e15, "fp16x3": 2.5e15, "bf16x1": 2.5e15}
 
 
 def log(*a):
@@ -234,7 +234,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c3_512")
-    ap.add_argument("--prec", default="bf16x3", choices=["bf16x3", "fp16x3", "fp32"])
+    ap.add_argument("--prec", default="bf16x3", choices=["bf16x3", "fp16x3", "fp32", "bf16x1"],
+                    help="reduction precision (bf16x1: error study, hi parts only)")
     ap.add_argument("--no-fp32", action="store_true", help="skip timing the FP32 path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-legs", action="store_true",
@@ -319,7 +320,7 @@ def main():
     res = {"metric": "mocks/sec for B_0,2,4 + 100 modal coeffs at 512^3, mixed vs FP32 at stated err",
            "value": 1.0 / t_mix, "unit": "mocks/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": t_mix * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": {"bf16x3": "f32+bf16x3", "fp16x3": "f32+fp16x3", "fp32": "f32"}[args.prec],
+           "dtype": {"bf16x3": "f32+bf16x3", "fp16x3": "f32+fp16x3", "fp32": "f32", "bf16x1": "f32+bf16"}[args.prec],
            "data": "synthetic lognormal mock, Kaiser RSD, seeded",
            "config": {"workload": f"{wl.name}: N={wl.n}^3 (N'={wl.n_reduce}), {wl.nparticles:.0e} particles, "
                                   f"CIC+interlace, varying LOS (observer 1500 Mpc/h), l<=4, {wl.nbins} bins "
@@ -356,6 +357,13 @@ def main():
             e["algorithmic_flop_per_launch"] = per_launch
             e["achieved_TFLOPs"] = per_launch / avg / 1e12
             e["frac_mfma"] = per_launch / avg / PEAK_MFMA[args.prec]
+            # MFMA work as issued: every entry of every needed 16 x 16 tile, one
+            # product per point (FP32, bf16 hi only) or the three split products
+            nprod = 3 if args.prec in ("bf16x3", "fp16x3") else 1
+            issued = int(plan.info.reduce_tiles) * 256 * 2 * nprod * float(wl.n_reduce) ** 3
+            e["issued_mfma_flop_per_launch"] = issued
+            e["issued_TFLOPs"] = issued / avg / 1e12
+            e["frac_mfma_issued"] = issued / avg / PEAK_MFMA[args.prec]
         elif amount > 0:
             e["algorithmic_bytes_per_launch"] = per_launch
             e["achieved_GBps"] = per_launch / avg / 1e9

@@ -70,7 +70,8 @@ typedef enum {
 typedef enum {
   BSP_FP32 = 0,   /* FP32 fields, FP32 MFMA products and accumulation */
   BSP_BF16X3 = 1, /* FP32 fields split hi+lo into bf16; ah*bh + ah*bl + al*bh on bf16 MFMA, FP32 accumulate */
-  BSP_FP16X3 = 2  /* as BF16X3 with fp16 splits of power-of-two scaled fields */
+  BSP_FP16X3 = 2, /* as BF16X3 with fp16 splits of power-of-two scaled fields */
+  BSP_BF16X1 = 3  /* error study only: one bf16 MFMA per tile, ah*bh (no lo parts), FP32 accumulate */
 } bsp_precision;
 
 /* Geometry of one estimator run. */

@@ -17,7 +17,7 @@ import numpy as np
 
 __all__ = [
     "BspError", "BspLibraryMissing", "Geom", "ModalBasis", "Info", "lib", "Plan",
-    "BSP_FP32", "BSP_BF16X3", "BSP_FP16X3", "PRECISIONS", "bsp_plan_create", "bsp_plan_destroy",
+    "BSP_FP32", "BSP_BF16X3", "BSP_FP16X3", "BSP_BF16X1", "PRECISIONS", "bsp_plan_create", "bsp_plan_destroy",
     "bsp_plan_info", "bsp_workspace_size", "bsp_set_workspace", "bsp_sync", "bsp_precompute",
     "bsp_geometry", "bsp_grid_assign", "bsp_fft_r2c", "bsp_fft_c2r", "bsp_los_moments", "bsp_grid_entry",
     "bsp_filter_fields", "bsp_triple_reduce", "bsp_modal_coeffs", "bsp_bispectrum_multipoles",
@@ -29,8 +29,8 @@ __all__ = [
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libbsp.so")
 
-BSP_FP32, BSP_BF16X3, BSP_FP16X3 = 0, 1, 2
-PRECISIONS = {"fp32": BSP_FP32, "bf16x3": BSP_BF16X3, "fp16x3": BSP_FP16X3}
+BSP_FP32, BSP_BF16X3, BSP_FP16X3, BSP_BF16X1 = 0, 1, 2, 3
+PRECISIONS = {"fp32": BSP_FP32, "bf16x3": BSP_BF16X3, "fp16x3": BSP_FP16X3, "bf16x1": BSP_BF16X1}
 STATUS = {0: "BSP_OK", 1: "BSP_ERR_ARG", 2: "BSP_ERR_SIZE", 3: "BSP_ERR_ALIAS", 4: "BSP_ERR_WORKSPACE",
           5: "BSP_ERR_HIP", 6: "BSP_ERR_DEVICE", 7: "BSP_ERR_NUMERIC", 8: "BSP_ERR_STATE"}
 

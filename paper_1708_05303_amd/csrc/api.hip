@@ -203,6 +203,10 @@ void bind_reduce(ReducePlan& rp, int32_t* dev) {
 // summed-term scale, 8192-point chunks 3e-5), so their chunks are short and
 // the FP64 combination takes over. Independent of the schedule so that
 // partial storage only grows with the number of tiles.
+// Kernel precision code of a public precision: the kernels number FP64 3 (the
+// geometry precompute), so the bf16 hi-only error-study mode is 4 there.
+int kprec(bsp_precision prec) { return prec == BSP_BF16X1 ? 4 : (int)prec; }
+
 int64_t kchunk_for(int prec, int64_t K, int /*ngroups*/) {
   const int64_t cap = (prec == 0) ? 16384 : (prec == 3 ? 65536 : 8192);
   const int64_t target_blocks = 2048;
@@ -1428,7 +1432,7 @@ bsp_status bsp_triple_reduce(bsp_plan p, const float* fields, int32_t nfields, i
   if (!p || !fields || !pairs || !thirds || !T || nfields < 1 || nfields > 128 || npairs < 1 || nthirds < 1 ||
       nthirds > 128 || K < 1)
     return fail(p, BSP_ERR_ARG, "bad argument");
-  if (prec < BSP_FP32 || prec > BSP_FP16X3) return fail(p, BSP_ERR_ARG, "bad precision");
+  if (prec < BSP_FP32 || prec > BSP_BF16X1) return fail(p, BSP_ERR_ARG, "bad precision");
   std::vector<std::array<int, 2>> pr(npairs);
   for (int i = 0; i < npairs; ++i) {
     pr[i] = {pairs[2 * i], pairs[2 * i + 1]};
@@ -1440,11 +1444,11 @@ bsp_status bsp_triple_reduce(bsp_plan p, const float* fields, int32_t nfields, i
     if (t < 0 || t >= nfields) return fail(p, BSP_ERR_ARG, "third field out of range");
   std::vector<uint8_t> nd;
   if (need) nd.assign(need, need + (size_t)npairs * nthirds);
-  if (!build_reduce(p->call_rp, pr, th, nd, nfields, (int)prec))
+  if (!build_reduce(p->call_rp, pr, th, nd, nfields, kprec(prec)))
     return fail(p, BSP_ERR_ARG, "reduction shape not supported");
   const size_t meta = align_up(p->call_rp.words * sizeof(int32_t));
   const size_t sc = align_up((size_t)nfields * sizeof(float)) * 2;
-  const size_t part = partial_bytes(p->call_rp, K, (int)prec, sizeof(float));
+  const size_t part = partial_bytes(p->call_rp, K, kprec(prec), sizeof(float));
   bsp_status s = need_ws(p, meta + sc + part);
   if (s != BSP_OK) return s;
   int32_t* dm = reinterpret_cast<int32_t*>(p->ws);
@@ -1457,7 +1461,7 @@ bsp_status bsp_triple_reduce(bsp_plan p, const float* fields, int32_t nfields, i
     s = field_scales(p, fields, nfields, K, scale, reinterpret_cast<unsigned*>(p->ws + meta + sc / 2));
     if (s != BSP_OK) return s;
   }
-  s = run_reduce<float>(p, p->call_rp, fields, K, (int)prec, scale, T, p->ws + meta + sc, p->ws_bytes - meta - sc, 1.0);
+  s = run_reduce<float>(p, p->call_rp, fields, K, kprec(prec), scale, T, p->ws + meta + sc, p->ws_bytes - meta - sc, 1.0);
   if (s != BSP_OK) return s;
   HIPCHK(hipStreamSynchronize(p->stream));  // host staging of the schedule stays valid until here
   return BSP_OK;
@@ -1609,7 +1613,7 @@ bsp_status estimate_from_spectrum(bsp_plan p, const float2* dl, bsp_precision pr
     if (s != BSP_OK) return s;
     sc = scale;
   }
-  s = run_reduce<float>(p, p->main_rp, fields, K, (int)prec, sc, T, scr, scr_bytes, 1.0);
+  s = run_reduce<float>(p, p->main_rp, fields, K, kprec(prec), sc, T, scr, scr_bytes, 1.0);
   if (s != BSP_OK) return s;
   HIPCHK(hipMemsetAsync(psum, 0, 64 * sizeof(double), p->stream));
   HIPCHK(launch_shell_power(dl, p->c, p->cz, p->d_bin_of_n2, p->n2max, p->nbins, psum, p->stream));
@@ -1644,7 +1648,7 @@ bsp_status bsp_modal_coeffs(bsp_plan p, const void* delta_l, bsp_precision prec,
   if (!p || !delta_l) return fail(p, BSP_ERR_ARG, "null argument");
   if (!p->modal) return fail(p, BSP_ERR_STATE, "plan has no modal basis");
   if (!p->pre_done) return fail(p, BSP_ERR_STATE, "bsp_precompute has not run");
-  if (prec < BSP_FP32 || prec > BSP_FP16X3) return fail(p, BSP_ERR_ARG, "bad precision");
+  if (prec < BSP_FP32 || prec > BSP_BF16X1) return fail(p, BSP_ERR_ARG, "bad precision");
   const Layout L = layout(p);
   bsp_status s = need_ws(p, L.total);
   if (s != BSP_OK) return s;
@@ -1660,7 +1664,7 @@ bsp_status bsp_bispectrum_multipoles(bsp_plan p, const float* ux, const float* u
                                      double* bnum, double* alpha, double* beta) {
   if (!p || !ux || !uy || !uz || !B || np < 1) return fail(p, BSP_ERR_ARG, "bad argument");
   if (!p->pre_done) return fail(p, BSP_ERR_STATE, "bsp_precompute has not run");
-  if (prec < BSP_FP32 || prec > BSP_FP16X3) return fail(p, BSP_ERR_ARG, "bad precision");
+  if (prec < BSP_FP32 || prec > BSP_BF16X1) return fail(p, BSP_ERR_ARG, "bad precision");
   const Layout L = layout(p);
   bsp_status s = need_ws(p, L.total);
   if (s != BSP_OK) return s;
@@ -1693,7 +1697,7 @@ bsp_status bsp_bispectrum_field(bsp_plan p, const float* delta, bsp_precision pr
                                 double* bnum, double* alpha, double* beta) {
   if (!p || !delta || !B) return fail(p, BSP_ERR_ARG, "bad argument");
   if (!p->pre_done) return fail(p, BSP_ERR_STATE, "bsp_precompute has not run");
-  if (prec < BSP_FP32 || prec > BSP_FP16X3) return fail(p, BSP_ERR_ARG, "bad precision");
+  if (prec < BSP_FP32 || prec > BSP_BF16X1) return fail(p, BSP_ERR_ARG, "bad precision");
   const Layout L = layout(p);
   bsp_status s = need_ws(p, L.total);
   if (s != BSP_OK) return s;
@@ -1922,7 +1926,7 @@ bool build_full(bsp_plan p) {
 bsp_status bsp_bispectrum_full(bsp_plan p, const void* delta_l, bsp_precision prec, double* B) {
   if (!p || !delta_l || !B) return fail(p, BSP_ERR_ARG, "null argument");
   if (!p->pre_done) return fail(p, BSP_ERR_STATE, "bsp_precompute has not run");
-  if (prec < BSP_FP32 || prec > BSP_FP16X3) return fail(p, BSP_ERR_ARG, "bad precision");
+  if (prec < BSP_FP32 || prec > BSP_BF16X1) return fail(p, BSP_ERR_ARG, "bad precision");
   if (!p->full_built && !build_full(p)) return fail(p, BSP_ERR_ARG, "full multipole reduction shape not supported");
   const Layout L = layout(p);
   bsp_status s = need_ws(p, L.total);
@@ -1957,7 +1961,7 @@ bsp_status bsp_bispectrum_full(bsp_plan p, const void* delta_l, bsp_precision pr
   const int64_t max_chunks = std::max<int64_t>(1, (int64_t)(avail / std::max<int64_t>(per_chunk, 1)));
   int64_t kc_min = (K + max_chunks - 1) / max_chunks;
   kc_min = (kc_min + 63) / 64 * 64;
-  s = run_reduce<float>(p, rp, fields, K, (int)prec, sc, T, scr + tb, avail, 1.0, kc_min);
+  s = run_reduce<float>(p, rp, fields, K, kprec(prec), sc, T, scr + tb, avail, 1.0, kc_min);
   if (s != BSP_OK) return s;
   const double N = p->N;
   const double norm_b = p->V * p->V / (std::pow(N, 9) * (double)K);

@@ -20,6 +20,7 @@
 //            FP32 values), T += ah bh + ah bl + al bh on 16x16x32 bf16 MFMA
 //   2 FP16X3: the same with fp16 splits of fields scaled by powers of two
 //   3 FP64 : v_mfma 16x16x4 f64 (geometry precompute)
+//   4 BF16X1: T += ah bh only (error study: what the lo parts buy)
 // Each workgroup writes its chunk's partial tiles; a second kernel sums the
 // chunks in FP64.
 #include "tile_mfma.h"
@@ -31,7 +32,7 @@ constexpr int NTHR = WAVES * 64;
 // LDS bytes of one workgroup for KS points per stage (two stage buffers).
 template <int PREC, int KS>
 size_t reduce_lds_bytes(const ReduceDesc& d) {
-  constexpr bool SPLIT = (PREC == 1 || PREC == 2);
+  constexpr bool SPLIT = (PREC == 1 || PREC == 2 || PREC == 4);
   const size_t elem = PREC == 3 ? 8 : 4;
   const size_t nfull = (SPLIT ? d.npf : d.nfields) + 1;
   size_t b = 2 * nfull * (KS + 16 / elem) * elem;
@@ -236,6 +237,7 @@ hipError_t launch_reduce(int prec, const float* fields, const ReduceDesc& d, flo
     case 0: return reduce_dispatch<0>(fields, d, partials, s);
     case 1: return reduce_dispatch<1>(fields, d, partials, s);
     case 2: return reduce_dispatch<2>(fields, d, partials, s);
+    case 4: return reduce_dispatch<4>(fields, d, partials, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -36,12 +36,13 @@ __device__ __forceinline__ void split8(const float* x, i32x4& hi, i32x4& lo) {
   }
 }
 
-// PREC 0 FP32, 1 BF16 hi+lo, 2 FP16 hi+lo, 3 FP64.
+// PREC 0 FP32, 1 BF16 hi+lo, 2 FP16 hi+lo, 3 FP64, 4 BF16 hi only (error study).
 template <int PREC> struct RT;
 template <> struct RT<0> { using T = float; using acc = f32x4; static constexpr int KK = 8; };
 template <> struct RT<1> { using T = float; using acc = f32x4; static constexpr int KK = 8; };
 template <> struct RT<2> { using T = float; using acc = f32x4; static constexpr int KK = 8; };
 template <> struct RT<3> { using T = double; using acc = f64x4; static constexpr int KK = 2; };
+template <> struct RT<4> { using T = float; using acc = f32x4; static constexpr int KK = 8; };
 
 // The same split for four floats (two packed words each).
 template <typename H2>
@@ -63,7 +64,7 @@ __device__ __forceinline__ void split4(const float* x, int2& hi, int2& lo) {
 template <int PREC, int MAXR, int MAXC, int WAVES> struct WaveTiles {
   using T = typename RT<PREC>::T;
   using ACC = typename RT<PREC>::acc;
-  static constexpr bool SPLIT = (PREC == 1 || PREC == 2);
+  static constexpr bool SPLIT = (PREC == 1 || PREC == 2 || PREC == 4);
   using H = typename std::conditional<PREC == 2, _Float16, __bf16>::type;
   using H8 = typename std::conditional<PREC == 2, f16x8, bf16x8>::type;
   using H2 = typename std::conditional<PREC == 2, f16x2, bf16x2>::type;
@@ -178,6 +179,8 @@ template <int PREC, int MAXR, int MAXC, int WAVES> struct WaveTiles {
             acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, bh, acc[r][c], 0, 0, 0);
             acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, bl, acc[r][c], 0, 0, 0);
             acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_l, bh, acc[r][c], 0, 0, 0);
+          } else if constexpr (PREC == 4) {
+            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, bh, acc[r][c], 0, 0, 0);
           } else {
             acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_h, bh, acc[r][c], 0, 0, 0);
             acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_h, bl, acc[r][c], 0, 0, 0);

@@ -477,6 +477,36 @@ def test_triple_reduce_definition(prec, tol, K):
     assert np.sqrt(np.mean(err ** 2)) < tol, np.sqrt(np.mean(err ** 2))
 
 
+def test_triple_reduce_bf16x1_error_study():
+    """BSP_BF16X1 keeps only the bf16 hi parts: each term carries the roundings
+    of its pair product and its third to 8-bit significands, each at most 2^-9
+    relative and about 2^-9 / sqrt(3) in rms. These errors are zero-mean and
+    independent between terms, so the error against the definition is near
+    sqrt(2/3) 2^-9 = 1.6e-3 of the summed-term scale (below 2^-8) and far above
+    that of the hi+lo path on the same input."""
+    say("reduce bf16x1")
+    r = rng(77)
+    nf, K = 21, 50_011
+    F = r.standard_normal((nf, K)).astype(np.float32) * r.uniform(0.5, 3e3, (nf, 1)).astype(np.float32)
+    pairs = np.array([(a, b) for a in range(nf) for b in range(a, nf)][::3], np.int32)
+    thirds = np.arange(nf, dtype=np.int32)
+    plan = B.Plan(n=16, box=100.0, nbins=1, k0=1.0, dk=1.0, workspace=False)
+    ws = torch.empty(1 << 28, dtype=torch.uint8, device=DEV)
+    B.bsp_set_workspace(plan.handle, ws, ws.numel())
+    F64 = F.astype(np.float64)
+    ref = np.array([[np.dot(F64[a] * F64[b], F64[t]) for t in thirds] for a, b in pairs])
+    scale = np.sqrt(np.array([[np.dot((F64[a] * F64[b]) ** 2, F64[t] ** 2) for t in thirds] for a, b in pairs]))
+    err = {}
+    for prec in (B.BSP_BF16X1, B.BSP_BF16X3):
+        T = torch.zeros((len(pairs), len(thirds)), dtype=torch.float64, device=DEV)
+        B.bsp_triple_reduce(plan.handle, dev(F), nf, K, pairs, thirds, None, prec, T)
+        plan.sync()
+        err[prec] = np.sqrt(np.mean((np.abs(T.cpu().numpy() - ref) / scale) ** 2))
+    assert 2e-4 < err[B.BSP_BF16X1] < 2.0 ** -8, err
+    assert err[B.BSP_BF16X1] > 20 * err[B.BSP_BF16X3], err
+    plan.close()
+
+
 @pytest.mark.parametrize("prec,tol", [(0, 1e-5), (1, 1e-4), (2, 1e-5)])
 def test_triple_reduce_many_row_tiles(prec, tol):
     # 120 fields, every pair a <= b (454 row tiles) and a banded need pattern:
