@@ -231,8 +231,8 @@ def copy_calibration(nbytes, reps):
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c3_512")
     ap.add_argument("--prec", default="bf16x3", choices=["bf16x3", "fp16x3", "fp32", "bf16x1"],
                     help="reduction precision (bf16x1: error study, hi parts only)")
