@@ -26,12 +26,6 @@ constexpr int8_t kMonoExp[22][3] = {
     {0, 0, 4}};
 constexpr double kMonoMult[22] = {1, 1, 2, 2, 1, 2, 1, 1, 4, 4, 6, 12, 6, 4, 12, 12, 4, 1, 4, 6, 4, 1};
 
-__device__ __forceinline__ double dpow(double x, int e) {
-  double r = 1.0;
-  for (int i = 0; i < e; ++i) r *= x;
-  return r;
-}
-
 __device__ __forceinline__ double sinc_pi(int n, int N) {
   if (n == 0) return 1.0;
   const double a = M_PI * (double)n / (double)N;
