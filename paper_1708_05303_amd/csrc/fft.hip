@@ -305,16 +305,16 @@ void k_fwd_z(const T* __restrict__ in, cplx_t<T>* __restrict__ out, FwdZDesc d, 
 // (jj + in_j0) * in_js + kz and writes jj * out_js + kz (a sub-block of a 2-D
 // inner layout; 1-D when ncz >= ncols). Every global load of the tile is issued
 // before the LDS writes, so each thread keeps N/NT loads in flight.
-template <typename T, int N, int W, int SIGN, bool FILT>
-__global__ __launch_bounds__(256) void k_c2c(const cplx_t<T>* __restrict__ in, cplx_t<T>* __restrict__ out,
+template <typename T, int N, int W, int SIGN, bool FILT, int BT>
+__global__ __launch_bounds__(BT) void k_c2c(const cplx_t<T>* __restrict__ in, cplx_t<T>* __restrict__ out,
                                              PassDesc p, FilterDesc f, const cplx_t<T>* __restrict__ twg) {
   using V = cplx_t<T>;
-  constexpr int NT = 256 / W;
+  constexpr int NT = BT / W;
   constexpr int PAD = N + 1;
   constexpr int E = (N + NT - 1) / NT;
   __shared__ V buf[W * PAD];
   __shared__ V tw[N];
-  for (int i = threadIdx.x; i < N; i += 256) tw[i] = twg[i];
+  for (int i = threadIdx.x; i < N; i += BT) tw[i] = twg[i];
   const int outer = blockIdx.y + gridDim.y * blockIdx.z;
   if (outer >= p.nouter) return;  // uniform per block
   const int c = threadIdx.x % W, j0 = threadIdx.x / W;
@@ -493,12 +493,16 @@ static hipError_t c2c_launch(int sign, const cplx_t<T>* in, cplx_t<T>* out, cons
   dim3 grid(tiles, gy, gz);
   FilterDesc fd{};
   if (f) fd = *f;
+  // 512 threads per FP32 workgroup (32 per column): the 16-column tile's 70 KB
+  // of LDS allows two workgroups per CU, so this doubles the waves a CU keeps
+  // in flight (FP64 tiles of 8 columns keep 256)
+  constexpr int BT = sizeof(T) == 4 ? 512 : 256;
   if (sign < 0) {
-    if (f) hipLaunchKernelGGL((k_c2c<T, N, W, -1, true>), grid, dim3(256), 0, s, in, out, p, fd, tw);
-    else hipLaunchKernelGGL((k_c2c<T, N, W, -1, false>), grid, dim3(256), 0, s, in, out, p, fd, tw);
+    if (f) hipLaunchKernelGGL((k_c2c<T, N, W, -1, true, BT>), grid, dim3(BT), 0, s, in, out, p, fd, tw);
+    else hipLaunchKernelGGL((k_c2c<T, N, W, -1, false, BT>), grid, dim3(BT), 0, s, in, out, p, fd, tw);
   } else {
-    if (f) hipLaunchKernelGGL((k_c2c<T, N, W, +1, true>), grid, dim3(256), 0, s, in, out, p, fd, tw);
-    else hipLaunchKernelGGL((k_c2c<T, N, W, +1, false>), grid, dim3(256), 0, s, in, out, p, fd, tw);
+    if (f) hipLaunchKernelGGL((k_c2c<T, N, W, +1, true, BT>), grid, dim3(BT), 0, s, in, out, p, fd, tw);
+    else hipLaunchKernelGGL((k_c2c<T, N, W, +1, false, BT>), grid, dim3(BT), 0, s, in, out, p, fd, tw);
   }
   return hipGetLastError();
 }
