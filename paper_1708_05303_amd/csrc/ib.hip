@@ -40,15 +40,30 @@ __global__ __launch_bounds__(256) void k_gather_subvolumes(const float* __restri
 
 // Shell sums of one sub-volume per blockIdx.y over its half spectrum
 // [m][m][h]; psum[i][l][b] += mult (2l+1) L_l(mu) |F / W|^2, dbar[i] = F(0) / m^3.
+// Each thread walks whole k_z lines: |n|^2 grows along a line, so the current
+// shell's sums stay in registers and go to the workgroup's LDS histogram only
+// when the shell changes; the window factors come from a per-axis table.
 __global__ __launch_bounds__(256) void k_subvolume_shells(const float2* __restrict__ F, int m, int s, int plane,
                                                           double ox, double oy, double oz, int window, int nl,
                                                           const int32_t* __restrict__ bin_of_n2, int n2max,
                                                           int nbins, double* __restrict__ psum,
                                                           double* __restrict__ dbar) {
-  extern __shared__ double hist[];  // [nl][nbins]
-  for (int b = threadIdx.x; b < nl * nbins; b += blockDim.x) hist[b] = 0.0;
-  const int box = blockIdx.y;
+  extern __shared__ double smem[];
+  double* hist = smem;                     // [nl][nbins]
+  double* wtab = smem + nl * nbins;        // [m / 2 + 1]: 1 / W of one axis at |a|
   const int h = m / 2 + 1;
+  for (int b = threadIdx.x; b < nl * nbins; b += blockDim.x) hist[b] = 0.0;
+  for (int a = threadIdx.x; a < h; a += blockDim.x) {
+    double w = 1.0;
+    if (window >= 0 && a > 0) {
+      // assignment window at the sub-volume frequencies (same cell size)
+      const double x = 3.14159265358979323846 * a / m;
+      w = sin(x) / x;
+      if (window == 1) w *= w;
+    }
+    wtab[a] = 1.0 / w;
+  }
+  const int box = blockIdx.y;
   // line of sight of this sub-volume: observer to its centre
   double ex = 0.0, ey = 0.0, ez = 1.0;
   if (!plane) {
@@ -64,57 +79,73 @@ __global__ __launch_bounds__(256) void k_subvolume_shells(const float2* __restri
   }
   __syncthreads();
   const float2* Fi = F + (int64_t)box * m * m * h;
-  const int64_t total = (int64_t)m * m * h;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int kz = (int)(idx % h);
-    const int64_t rest = idx / h;
-    const int iy = (int)(rest % m), ix = (int)(rest / m);
+  double acc[3] = {0.0, 0.0, 0.0};
+  int cur = -1;
+  auto flush = [&]() {
+    if (cur >= 0)
+      for (int li = 0; li < nl; ++li) atomicAdd(&hist[li * nbins + cur], acc[li]);
+    acc[0] = acc[1] = acc[2] = 0.0;
+  };
+  for (int line = blockIdx.x * blockDim.x + threadIdx.x; line < m * m; line += gridDim.x * blockDim.x) {
+    const int iy = line % m, ix = line / m;
     const int nx = ix <= m / 2 ? ix : ix - m, ny = iy <= m / 2 ? iy : iy - m;
-    const int n2 = nx * nx + ny * ny + kz * kz;
-    if (n2 == 0) {
-      dbar[box] = (double)Fi[0].x / ((double)m * m * m);
-      continue;
+    const int nxy = nx * nx + ny * ny;
+    const double wxy = wtab[nx < 0 ? -nx : nx] * wtab[ny < 0 ? -ny : ny];
+    const float2* row = Fi + (int64_t)line * h;
+    for (int kz = 0; kz < h; ++kz) {
+      const int n2 = nxy + kz * kz;
+      if (n2 > n2max) break;  // |n|^2 only grows along the line
+      if (n2 == 0) {
+        dbar[box] = (double)row[0].x / ((double)m * m * m);
+        continue;
+      }
+      const int b = bin_of_n2[n2];
+      if (b < 0) continue;
+      if (b != cur) {
+        flush();
+        cur = b;
+      }
+      const float2 v = row[kz];
+      const double wc = wxy * wtab[kz];
+      const double p = ((double)v.x * v.x + (double)v.y * v.y) * wc * wc;
+      const double mult = (kz == 0 || 2 * kz == m) ? 1.0 : 2.0;
+      const double mu = (nx * ex + ny * ey + kz * ez) / sqrt((double)n2);
+      const double mu2 = mu * mu;
+      acc[0] += mult * p;
+      if (nl > 1) acc[1] += mult * 5.0 * 0.5 * (3.0 * mu2 - 1.0) * p;
+      if (nl > 2) acc[2] += mult * 9.0 * (35.0 * mu2 * mu2 - 30.0 * mu2 + 3.0) / 8.0 * p;
     }
-    if (n2 > n2max) continue;
-    const int b = bin_of_n2[n2];
-    if (b < 0) continue;
-    const float2 v = Fi[idx];
-    double p = (double)v.x * v.x + (double)v.y * v.y;
-    if (window >= 0) {
-      // assignment window at the sub-volume frequencies (same cell size)
-      const double pi = 3.14159265358979323846;
-      auto sinc = [&](int a) { return a == 0 ? 1.0 : sin(pi * a / m) / (pi * a / m); };
-      double w = sinc(nx) * sinc(ny) * sinc(kz);
-      if (window == 1) w *= w;
-      p /= w * w;
-    }
-    const double mult = (kz == 0 || 2 * kz == m) ? 1.0 : 2.0;
-    const double mu = (nx * ex + ny * ey + kz * ez) / sqrt((double)n2);
-    const double mu2 = mu * mu;
-    const double L[3] = {1.0, 0.5 * (3.0 * mu2 - 1.0), (35.0 * mu2 * mu2 - 30.0 * mu2 + 3.0) / 8.0};
-    for (int li = 0; li < nl; ++li) atomicAdd(&hist[li * nbins + b], mult * (4 * li + 1) * L[li] * p);
   }
+  flush();
   __syncthreads();
   for (int b = threadIdx.x; b < nl * nbins; b += blockDim.x)
     if (hist[b] != 0.0) unsafeAtomicAdd(&psum[(int64_t)box * nl * nbins + b], hist[b]);
 }
 
-// iB[l][b] = (1/N_s) sum_i P[i][l][b] dbar[i], P = scale psum / N_b (optionally stored).
-__global__ void k_subvolume_finalize(const double* __restrict__ psum, const double* __restrict__ dbar, int ns,
-                                     int nl, int nbins, const int64_t* __restrict__ nb_modes, double scale,
-                                     double* __restrict__ iB, double* __restrict__ P) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= nl * nbins) return;
+// iB[l][b] = (1/N_s) sum_i P[i][l][b] dbar[i], P = scale psum / N_b (optionally
+// stored); one workgroup per (l, b) sums over the sub-volumes.
+__global__ __launch_bounds__(256) void k_subvolume_finalize(const double* __restrict__ psum,
+                                                            const double* __restrict__ dbar, int ns, int nl,
+                                                            int nbins, const int64_t* __restrict__ nb_modes,
+                                                            double scale, double* __restrict__ iB,
+                                                            double* __restrict__ P) {
+  __shared__ double red[256];
+  const int j = blockIdx.x;
   const int64_t nm = nb_modes[j % nbins];
   const double f = nm > 0 ? scale / (double)nm : 0.0;
   double acc = 0.0;
-  for (int i = 0; i < ns; ++i) {
+  for (int i = threadIdx.x; i < ns; i += blockDim.x) {
     const double pv = f * psum[(int64_t)i * nl * nbins + j];
     if (P) P[(int64_t)i * nl * nbins + j] = pv;
     acc += pv * dbar[i];
   }
-  iB[j] = acc / ns;
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) iB[j] = red[0] / ns;
 }
 
 hipError_t launch_gather_subvolumes(const float* grid, const double* wsum, int n, int s, float* out, hipStream_t st) {
@@ -131,20 +162,21 @@ hipError_t launch_subvolume_shells(const float2* F, int m, int s, int plane, con
                                    const int32_t* bin_of_n2, int n2max, int nbins, double* psum, double* dbar,
                                    hipStream_t st) {
   const int ns = s * s * s;
-  if (ns > 65535 || nl < 1 || nl > 3 || (size_t)nl * nbins * sizeof(double) > 64 * 1024) return hipErrorInvalidValue;
-  const int64_t total = (int64_t)m * m * (m / 2 + 1);
-  int64_t bx = (total + 255) / 256;
-  if (bx > 256) bx = 256;
-  hipLaunchKernelGGL(k_subvolume_shells, dim3((unsigned)bx, (unsigned)ns), dim3(256),
-                     (size_t)nl * nbins * sizeof(double), st, F, m, s, plane, obs[0], obs[1], obs[2], window, nl,
-                     bin_of_n2, n2max, nbins, psum, dbar);
+  const size_t lds = ((size_t)nl * nbins + m / 2 + 1) * sizeof(double);
+  if (ns > 65535 || nl < 1 || nl > 3 || lds > 64 * 1024) return hipErrorInvalidValue;
+  // about 16 k_z lines per thread
+  const int64_t lines = (int64_t)m * m;
+  int64_t bx = (lines + 256 * 16 - 1) / (256 * 16);
+  if (bx < 1) bx = 1;
+  hipLaunchKernelGGL(k_subvolume_shells, dim3((unsigned)bx, (unsigned)ns), dim3(256), lds, st, F, m, s, plane,
+                     obs[0], obs[1], obs[2], window, nl, bin_of_n2, n2max, nbins, psum, dbar);
   return hipGetLastError();
 }
 
 hipError_t launch_subvolume_finalize(const double* psum, const double* dbar, int ns, int nl, int nbins,
                                      const int64_t* nb_modes, double scale, double* iB, double* P, hipStream_t st) {
-  hipLaunchKernelGGL(k_subvolume_finalize, dim3((unsigned)((nl * nbins + 63) / 64)), dim3(64), 0, st, psum, dbar, ns,
-                     nl, nbins, nb_modes, scale, iB, P);
+  hipLaunchKernelGGL(k_subvolume_finalize, dim3((unsigned)(nl * nbins)), dim3(256), 0, st, psum, dbar, ns, nl, nbins,
+                     nb_modes, scale, iB, P);
   return hipGetLastError();
 }
 
