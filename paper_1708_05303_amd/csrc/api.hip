@@ -1679,7 +1679,7 @@ bsp_status bsp_bispectrum_multipoles(bsp_plan p, const float* ux, const float* u
     // algorithmic minimum: the catalogue read once, each grid node written once
     StageTimer t(p, 0, (double)np * (w ? 16.0 : 12.0) + (double)p->ngrid * p->N * p->N * p->N * 4.0);
     const size_t tb = assign_tiled_bytes(np, p->N);
-    if (tb && tb <= L.scratch - L.s_grid) {
+    if (tb && tb <= L.scratch - L.s_grid && assign_tiled_preferred(p->N)) {
       HIPCHK(launch_assign_tiled(ux, uy, uz, w, np, p->N, p->g.window, p->g.interlace, 0, grids, wsum, p->d_err,
                                  scr + L.s_grid, L.scratch - L.s_grid, p->stream));
     } else {

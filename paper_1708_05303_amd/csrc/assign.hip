@@ -264,6 +264,14 @@ static int tile_tz(int n) {
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// The tiled path runs one workgroup per tile: with fewer than 512 tiles
+// (grids of 96 nodes a side or less) it cannot fill the GPU and the
+// global-atomic kernel is faster.
+bool assign_tiled_preferred(int n) {
+  const int tz = tile_tz(n);
+  return tz && (int64_t)(n / TXY) * (n / TXY) * (n / tz) >= 512;
+}
+
 size_t assign_tiled_bytes(int64_t np, int n) {
   const int tz = tile_tz(n);
   if (!tz || np <= 0 || np > (int64_t)INT32_MAX) return 0;

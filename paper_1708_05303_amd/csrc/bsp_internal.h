@@ -114,6 +114,7 @@ hipError_t launch_assign(const float* ux, const float* uy, const float* uz, cons
 // overwrites the grids, 1 adds to them. Returns hipErrorInvalidValue when N
 // does not tile or the scratch is too small (nothing is launched then).
 size_t assign_tiled_bytes(int64_t np, int n);
+bool assign_tiled_preferred(int n);
 hipError_t launch_assign_tiled(const float* ux, const float* uy, const float* uz, const float* w, int64_t np, int n,
                                int window, int interlace, int accumulate, float* grids, double* wsum, int32_t* err,
                                void* scratch, size_t scratch_bytes, hipStream_t s);

@@ -535,8 +535,14 @@ hipError_t launch_fwd_z_f64(int n, const double* in, double2* out, const FwdZDes
 
 hipError_t launch_c2c_f32(int n, int sign, const float2* in, float2* out, const PassDesc& p,
                           const FilterDesc* f, const float2* tw, hipStream_t s) {
-#define CASE(NN) \
-  case NN: return c2c_launch<float, NN, 16>(sign, in, out, p, f, tw, s);
+  // lines of at most 128 points: 64-column tiles (512-byte row pieces, 8 threads
+  // per column) when the launch still has at least 2048 of them, else 16
+  const bool wide = n <= 128 && (int64_t)((p.ncols + 63) / 64) * p.nouter >= 2048;
+#define CASE(NN)                                                                                  \
+  case NN:                                                                                        \
+    if constexpr (NN <= 128)                                                                      \
+      if (wide) return c2c_launch<float, NN, 64>(sign, in, out, p, f, tw, s);                     \
+    return c2c_launch<float, NN, 16>(sign, in, out, p, f, tw, s);
   switch (n) { BSP_FOR_SIZES(CASE) }
 #undef CASE
   return hipErrorInvalidValue;
