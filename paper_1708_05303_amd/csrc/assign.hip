@@ -179,11 +179,20 @@ __global__ __launch_bounds__(256) void k_assign_tiles(const float4* __restrict__
   __syncthreads();
   const float fn = (float)n;
   for (int nb = 0; nb < 8; ++nb) {
-    const int ax = txi - ((nb >> 2) & 1), ay = tyi - ((nb >> 1) & 1), az = tzi - (nb & 1);
-    const int k = ((ax < 0 ? ax + ntx : ax) * ntx + (ay < 0 ? ay + ntx : ay)) * ntz + (az < 0 ? az + ntz : az);
+    const int lx = (nb >> 2) & 1, ly = (nb >> 1) & 1, lz = nb & 1;  // neighbour below along x / y / z
+    const int ax = txi - lx, ay = tyi - ly, az = tzi - lz;
+    const int axw = ax < 0 ? ax + ntx : ax, ayw = ay < 0 ? ay + ntx : ay, azw = az < 0 ? az + ntz : az;
+    const int k = (axw * ntx + ayw) * ntz + azw;
+    // A particle of a lower neighbour reaches this tile only from within 1.5
+    // nodes of the shared face: an offset d < size - 1.5 in its tile puts
+    // x + 0.5 below x0 - 1, so neither its CIC nodes floor(v), floor(v) + 1 nor
+    // its NGP node reach x0 on either grid (and a shifted position that wraps
+    // round the box has d >= size - 0.5).
+    const float fx = (float)(axw * TXY), fy = (float)(ayw * TXY), fz = (float)(azw * TZ);
     const int e = offs[k + 1];
     for (int i = offs[k] + threadIdx.x; i < e; i += 256) {
       const float4 pt = sorted[i];
+      if ((lx && pt.x - fx < TXY - 1.5f) || (ly && pt.y - fy < TXY - 1.5f) || (lz && pt.z - fz < TZ - 1.5f)) continue;
       for (int s = 0; s <= interlace; ++s) {
         float vx = pt.x, vy = pt.y, vz = pt.z;
         if (s) {
