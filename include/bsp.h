@@ -154,7 +154,12 @@ bsp_status bsp_geometry(bsp_plan plan, int32_t* tri, int64_t* counts, double* ga
  * positions in grid units in [0, N) (w NULL: unit weights). grids: device
  * [1+interlace][N^3], accumulated into (the caller zeroes them). wsum: device
  * double[1], accumulated sum of weights. Out-of-range or non-finite positions
- * are skipped and latch BSP_ERR_DEVICE. */
+ * are skipped and latch BSP_ERR_DEVICE. When the workspace holds the sorted
+ * catalogue (20 bytes per particle plus the tile offsets) the particles are
+ * sorted by node tile and each tile is summed in LDS; otherwise each
+ * contribution is a global float atomic. Either way the FP32 sums run in an
+ * unspecified order, so grids (and everything made from them) may differ in
+ * the last bit between runs. */
 bsp_status bsp_grid_assign(bsp_plan plan, const float* ux, const float* uy, const float* uz, const float* w,
                            int64_t np, float* grids, double* wsum);
 
@@ -208,8 +213,12 @@ bsp_status bsp_triple_reduce(bsp_plan plan, const float* fields, int32_t nfields
 bsp_status bsp_modal_coeffs(bsp_plan plan, const void* delta_l, bsp_precision prec, double nbar, double* bnum,
                             double* alpha, double* beta);
 
-/* The whole hot path for one catalogue: assignment, LOS moments, shell and
- * modal fields, one triple reduction, FP64 normalisation.
+/* The whole hot path for one catalogue: assignment (the sorted, tiled kernels
+ * on grids of at least 512 node tiles of 8 x 8 x 64 or smaller, the global
+ * atomic kernel below), LOS moments, shell and modal fields, one triple
+ * reduction, FP64 normalisation. Given the same grids every later step is
+ * bit-reproducible; the assignment's summation order is not (see
+ * bsp_grid_assign).
  *   B: device double [nl][ntri], B^l = V^2 T^l / (N^9 N'^3 N_tri) (multipole on b1);
  *   B0sub: device double [ntri] or NULL, B^0 - sum_i Pbar_bi / nbar + 2/nbar^2;
  *   Pbar: device double [nbins] or NULL, shell power V sum |delta0|^2 / (N^6 N_b);
