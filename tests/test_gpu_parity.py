@@ -360,7 +360,8 @@ def test_bispectrum_full_against_oracle(prec, tol):
     multipole. On this 32^3 catalogue B^(400) is 0.3 of the monopole, and its
     FP32 error against its own norm ranges over 4e-6 to 1.2e-5 between runs
     (the assignment's float atomics change the rounding pattern from run to
-    run; given the same grids every later stage is bit-reproducible)."""
+    run; given the same grids the later stages repeat to the last bits of
+    their FP64 sums)."""
     say("bispectrum-full", prec)
     n, box, k0, dk, nb = 32, 200.0, 2.0, 2.0, 4
     obs = np.array([-300.0, -200.0, -250.0])
