@@ -219,7 +219,7 @@ bsp_status bsp_modal_coeffs(bsp_plan plan, const void* delta_l, bsp_precision pr
  * fields, one triple reduction, FP64 normalisation. The assignment's FP32
  * summation order varies between runs (see bsp_grid_assign); later steps add
  * FP64 partial sums in an unspecified order, which changes only their last
- * bits. */
+ * bits.
  *   B: device double [nl][ntri], B^l = V^2 T^l / (N^9 N'^3 N_tri) (multipole on b1);
  *   B0sub: device double [ntri] or NULL, B^0 - sum_i Pbar_bi / nbar + 2/nbar^2;
  *   Pbar: device double [nbins] or NULL, shell power V sum |delta0|^2 / (N^6 N_b);

@@ -66,3 +66,18 @@ def test_modal_basis_validation():
     with pytest.raises(B.BspError) as e:
         B.bsp_plan_create(_geom(), b)
     assert e.value.status == 1
+
+
+@pytest.mark.parametrize("lang,std", [("c", "-std=c99"), ("c++", "-std=c++17")])
+def test_header_compiles_on_its_own(lang, std):
+    """include/bsp.h is a plain C header: it compiles alone as C and as C++ with
+    every warning an error (a stray comment end or a C++-only construct fails)."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no gcc")
+    header = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "bsp.h")
+    r = subprocess.run([gcc, "-x", lang, std, "-fsyntax-only", "-Wall", "-Wextra", "-Werror", header],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
