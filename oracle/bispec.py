@@ -19,9 +19,12 @@ Discrete conventions (the paper states the estimators in the continuum):
 
 Parity pins: every function below is pinned by at least one non-GPU test
 (brute-force closed-triangle sums, exact enumeration of triangle counts,
-direct Legendre-weighted DFT, Gaussian zero mean, the quadratic-field closed
-form, separable-template recovery, CIC invariants, Kaiser multipole ratios,
-Poisson shot noise). The CIC-compensated shot-noise *physics* is parity
+direct Legendre-weighted DFT, x-hat at nodes of both grids worked out by hand,
+the closed-form LOS moments of a point source, the 1-D modal functions against
+written-out Legendre polynomials, basis invariance of the modal reconstruction,
+Gaussian zero mean of the binned and modal estimators, the quadratic-field
+closed forms, separable-template recovery, CIC invariants, Kaiser multipole
+ratios, Poisson shot noise). The CIC-compensated shot-noise *physics* is parity
 unpinned (only its formula is); see ``shot_noise_binned``.
 """
 from __future__ import annotations

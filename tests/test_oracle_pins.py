@@ -764,3 +764,264 @@ def test_batch_covariance_definition():
     d = x - x.mean(0)
     ref = sum(np.outer(d[i], d[i]) for i in range(50)) / 49
     assert np.allclose(c, ref)
+
+
+# ---------------------------------------------------------------- LOS geometry, written out by hand
+
+def test_node_unit_vectors_hand_values():
+    """x-hat at nodes of the plain grid (shift 0) and of the interlaced grid
+    (shift 1/2), off-axis observer: node j of the grid built from u + s stands
+    for the point r = j - s, and x-hat = (r - o) / |r - o| (Sec. 2, the line of
+    sight to each galaxy). Values worked by hand."""
+    n = 8
+    o = np.array([-5.5, 3.25, -9.0])
+    # (node, shift) -> r - o, worked out by hand
+    cases = [((3, 1, 6), 0.0, (8.5, -2.25, 15.0)),
+             ((3, 1, 6), 0.5, (8.0, -2.75, 14.5)),
+             ((0, 7, 0), 0.5, (5.0, 3.25, 8.5)),
+             ((7, 0, 2), 0.0, (12.5, -3.25, 11.0))]
+    for shift in (0.0, 0.5):
+        xh = O.bispec.node_unit_vectors(n, shift, o)
+        for node, s, d in cases:
+            if s != shift:
+                continue
+            d = np.array(d)
+            ref = d / math.sqrt(float(d @ d))
+            got = np.array([xh[a][node] for a in range(3)])
+            assert np.allclose(got, ref, rtol=0, atol=1e-15), (node, shift, got, ref)
+
+
+@pytest.mark.parametrize("shift", [0.0, 0.5])
+def test_point_source_varying_los_closed_form(shift):
+    """A single unit contrast at node x0 of a grid built with the given shift:
+    the LOS moment field of Sec. 2 reduces to
+    delta^(l)(n) = (2l+1) L_l(k-hat . x-hat_p) exp(-2 pi i n . x0 / N),
+    x-hat_p the unit vector from the observer to the point x0 - shift that the
+    node stands for; L_2, L_4 are the textbook Legendre polynomials. Every
+    half-spectrum mode n != 0 is checked."""
+    n = 16
+    x0 = np.array([3, 11, 6])
+    o = np.array([-5.5, 3.25, -9.0])
+    d = np.zeros((n, n, n))
+    d[tuple(x0)] = 1.0
+    spec = O.spectrum_from_field([d], [shift], n, 4, o, None)
+    p = x0 - shift - o
+    xh = p / math.sqrt(float(p @ p))
+    f = np.fft.fftfreq(n, 1.0 / n)
+    fz = np.arange(n // 2 + 1, dtype=np.float64)
+    nx, ny, nz = np.meshgrid(f, f, fz, indexing="ij")
+    kk = np.sqrt(nx ** 2 + ny ** 2 + nz ** 2)
+    kk[0, 0, 0] = 1.0
+    mu = (nx * xh[0] + ny * xh[1] + nz * xh[2]) / kk
+    phase = np.exp(-2j * math.pi * (nx * x0[0] + ny * x0[1] + nz * x0[2]) / n)
+    legendre = [np.ones_like(mu), (3 * mu ** 2 - 1) / 2, (35 * mu ** 4 - 30 * mu ** 2 + 3) / 8]
+    for li in range(3):
+        ref = (4 * li + 1) * legendre[li] * phase
+        ref[0, 0, 0] = 0.0
+        assert np.max(np.abs(spec[li] - ref)) < 1e-12, (shift, li)
+
+
+def test_point_source_interlaced_catalogue():
+    """One particle through the whole catalogue route (CIC on both grids,
+    compensation, interlacing, LOS moments): at low n the result approaches
+    (2l+1) L_l(k-hat . x-hat_p) exp(-2 pi i n . u / N) with x-hat_p taken at the
+    particle itself. The observer is 200 cells away, so the x-hat of the cloud's
+    nodes differ from x-hat_p by under 1e-2; flipping the observer's sign or
+    the interlaced node shift moves the result by more than that."""
+    n = 32
+    u = np.array([[10.3125], [5.75], [21.0625]])
+    o = np.array([-120.0, 90.0, -130.0])
+    spec, _ = O.spectrum_from_catalogue(*u, n, 4, o, window=1, interlace=1)
+    p = u[:, 0] - o
+    xh = p / math.sqrt(float(p @ p))
+    fx, fy, fz = O.bispec.half_freq_vectors(n)
+    kk = np.sqrt(np.maximum(fx ** 2 + fy ** 2 + fz ** 2, 1e-300))
+    mu = (fx * xh[0] + fy * xh[1] + fz * xh[2]) / kk
+    phase = np.exp(-2j * math.pi * (fx * u[0, 0] + fy * u[1, 0] + fz * u[2, 0]) / n)
+    legendre = [np.ones_like(mu), (3 * mu ** 2 - 1) / 2, (35 * mu ** 4 - 30 * mu ** 2 + 3) / 8]
+    low = (np.abs(fx) <= 2) & (np.abs(fy) <= 2) & (fz <= 2) & ((fx != 0) | (fy != 0) | (fz != 0))
+    low = np.broadcast_to(low, spec[0].shape)
+    # the point contributes 1 / nbar_cell = N^3 to the contrast's transform
+    for li in range(3):
+        ref = (4 * li + 1) * legendre[li] * phase * n ** 3
+        err = np.max(np.abs(spec[li] - ref)[low]) / n ** 3
+        assert err < 0.05 * (4 * li + 1), (li, err)
+
+
+# ---------------------------------------------------------------- modal basis, written out by hand
+
+def test_modal_q_explicit_legendre():
+    """q_p(k) = P_p(t) with t = (2k - k_min - k_max) / (k_max - k_min): the map
+    sends the ends of the modal range to -1 and +1. P_0 .. P_7 are written out
+    (textbook coefficients) and evaluated at t = -1, -0.5, 0, 0.3, 1, i.e. at
+    k = 2.5, 40, 77.5, 100, 152.5 for the range [2.5, 152.5)."""
+    kmin, kmax = 2.5, 152.5
+    k = np.array([2.5, 40.0, 77.5, 100.0, 152.5])
+    t = np.array([-1.0, -0.5, 0.0, 0.3, 1.0])
+    P = [lambda x: np.ones_like(x),
+         lambda x: x,
+         lambda x: (3 * x ** 2 - 1) / 2,
+         lambda x: (5 * x ** 3 - 3 * x) / 2,
+         lambda x: (35 * x ** 4 - 30 * x ** 2 + 3) / 8,
+         lambda x: (63 * x ** 5 - 70 * x ** 3 + 15 * x) / 8,
+         lambda x: (231 * x ** 6 - 315 * x ** 4 + 105 * x ** 2 - 5) / 16,
+         lambda x: (429 * x ** 7 - 693 * x ** 5 + 315 * x ** 3 - 35 * x) / 16]
+    for p in range(8):
+        got = O.modal_q(p, k, kmin, kmax)
+        assert np.allclose(got, P[p](t), rtol=0, atol=1e-13), (p, got, P[p](t))
+    # endpoint values P_p(+-1) = (+-1)^p
+    assert np.allclose([O.modal_q(p, 152.5, kmin, kmax) for p in range(8)], 1.0)
+    assert np.allclose([O.modal_q(p, 2.5, kmin, kmax) for p in range(8)], [(-1) ** p for p in range(8)])
+
+
+def _modal_reconstruction(beta, modes, qfun, k1, k2, k3):
+    """sum_n beta_n Q_n(k1, k2, k3), Q_n the symmetrised product q_p q_r q_s."""
+    out = np.zeros_like(k1)
+    for bn, m in zip(beta, modes):
+        Q = sum(qfun(a, k1) * qfun(b, k2) * qfun(c, k3) for a, b, c in itertools.permutations(tuple(m))) / 6.0
+        out = out + bn * Q
+    return out
+
+
+def test_modal_basis_invariance(monkeypatch):
+    """The reconstruction w^-1 sum_n beta_n Q_n of Sec. 3.5 does not depend on
+    the 1-D functions used to build a complete set of modes (the paper notes
+    the form of the one-dimensional modes matters little, eq. Qn; the
+    decomposition of eq. bispDecomp): with P = 3 and all 10 triples, Legendre
+    q_p and monomials (k / k_max)^p span the same space, so b = <<wB|Q>> and
+    gamma must transform together and the two reconstructions agree."""
+    g = _modal_geo(16)
+    n = g["n"]
+    modes = O.modal_modes(3, 10)
+    spec = O.spectrum_from_field([rng(77).standard_normal((n, n, n))], [0.0], n, 2, None, None)
+    args = (3, g["kmin"], g["kmax"], g["kf"])
+    b_leg = O.modal_numerators(spec, n, n, modes, *args, g["pfid"])
+    gam_leg = O.gram_matrix(n, modes, *args, g["box"])
+    _, beta_leg = O.modal_solve(gam_leg, b_leg)
+    kmax = g["kmax"]
+
+    def mono(p, kn, kmin_, kmax_):
+        return (np.asarray(kn, dtype=np.float64) / kmax) ** p
+    monkeypatch.setattr(O.bispec, "modal_q", mono)
+    b_mon = O.modal_numerators(spec, n, n, modes, *args, g["pfid"])
+    gam_mon = O.gram_matrix(n, modes, *args, g["box"])
+    _, beta_mon = O.modal_solve(gam_mon, b_mon)
+    monkeypatch.undo()
+    assert not np.allclose(beta_leg, beta_mon)  # the coefficients differ ...
+    r = rng(78)
+    k1 = r.uniform(g["kmin"], g["kmax"], 50)
+    k2 = r.uniform(g["kmin"], g["kmax"], 50)
+    k3 = r.uniform(g["kmin"], g["kmax"], 50)
+    leg = lambda p, k: O.modal_q(p, k, g["kmin"], g["kmax"])
+    mon = lambda p, k: (k / kmax) ** p
+    for li in range(2):
+        R1 = _modal_reconstruction(beta_leg[li], modes, leg, k1, k2, k3)
+        R2 = _modal_reconstruction(beta_mon[li], modes, mon, k1, k2, k3)
+        # ... the reconstruction does not (the monomial Gram matrix is the worse
+        # conditioned of the two, kappa ~ 1e8, which sets the rounding floor)
+        assert np.max(np.abs(R1 - R2)) < 1e-7 * np.max(np.abs(R1)), li
+    # a set that is not closed downwards (all triples but (0, 0, 1)) spans
+    # different spaces in the two bases, and is not invariant
+    keep = [i for i in range(10) if i != 1]
+    m9 = modes[keep]
+    _, bl = O.modal_solve(O.gram_matrix(n, m9, *args, g["box"]), b_leg[:, keep])
+    monkeypatch.setattr(O.bispec, "modal_q", mono)
+    gm9 = O.gram_matrix(n, m9, *args, g["box"])
+    bm9 = O.modal_numerators(spec, n, n, m9, *args, g["pfid"])
+    monkeypatch.undo()
+    _, bm = O.modal_solve(gm9, bm9)
+    R1 = _modal_reconstruction(bl[0], m9, leg, k1, k2, k3)
+    R2 = _modal_reconstruction(bm[0], m9, mon, k1, k2, k3)
+    assert np.max(np.abs(R1 - R2)) > 1e-4 * np.max(np.abs(R1))
+
+
+def _modal_stat_setup():
+    n, k0, dk, nb, p = _stat_setup()
+    kmin, kmax = k0 - dk / 2, k0 + (nb - 1) * dk + dk / 2
+    box = 300.0
+    kf = 2 * math.pi / box
+    kk = kf * np.sqrt(np.arange(3 * n * n + 1))
+    pfid = 2000.0 / (1.0 + (kk / (4 * kf)) ** 2) + 100.0
+    return n, p, 3, O.modal_modes(3, 10), kmin, kmax, kf, box, pfid
+
+
+def test_modal_numerators_zero_mean_for_gaussian_fields():
+    """Gaussian fields have no three-point function: E[b^l_m] = 0 for every
+    mode and multipole (plane-parallel LOS), from 64 realisations."""
+    n, p, P, modes, kmin, kmax, kf, box, pfid = _modal_stat_setup()
+    out = []
+    for r in range(64):
+        g = _gaussian_lattice_field(n, 3100 + r, p)
+        spec = O.spectrum_from_field([g], [0.0], n, 4, None, None)
+        out.append(O.modal_numerators(spec, n, n, modes, P, kmin, kmax, kf, pfid).ravel())
+    z = _zscores(out, 0.0)
+    nu = z.size
+    assert np.max(np.abs(z)) < 5
+    assert abs(np.sum(z ** 2) / nu - 1) < 5 * math.sqrt(2 / nu)
+
+
+def test_modal_numerators_quadratic_field_expectation():
+    """delta = g + b2 (g^2 - <g^2>) has, to O(b2), the three-point function
+    2 b2 N^3 [p1 p2 + p2 p3 + p3 p1] on closed triangles (E|g(n)|^2 = N^3 p(n)),
+    so E[b^0_m] = <<w B_tree | Q_m>>: the modal numerator of Sec. 3.5 written as
+    N^-9 sum over closed triangles of f_p(n1) f_r(n2) f_s(n3) E[delta delta delta],
+    f_p = q_p / sqrt(k P_fid). Enumerated here over all mode pairs (n1, n2)
+    with n3 = -(n1 + n2) in range; a factor of 2 in either direction is
+    rejected."""
+    n, p, P, modes, kmin, kmax, kf, box, pfid = _modal_stat_setup()
+    b2 = 0.1 / math.sqrt(float(p.sum() * 2) / n ** 3)
+    cm = int(math.ceil(kmax))
+    r_ = np.arange(-cm, cm + 1)
+    vx, vy, vz = np.meshgrid(r_, r_, r_, indexing="ij")
+    v = np.stack([vx.ravel(), vy.ravel(), vz.ravel()], 1)
+    q2 = (v ** 2).sum(1)
+    v = v[O.bispec.in_modal_range(q2, kmin, kmax)]
+    q2 = (v ** 2).sum(1)
+
+    def pk(vec):  # p(n) looked up on the half spectrum (p is even in n)
+        s = np.where(vec[..., 2:3] < 0, -vec, vec)
+        return p[s[..., 0] % n, s[..., 1] % n, s[..., 2]]
+
+    def filt(pp, n2):
+        kn = np.sqrt(n2.astype(np.float64))
+        return O.modal_q(pp, kn, kmin, kmax) / np.sqrt(kf * kn * pfid[n2])
+    n3 = -(v[:, None, :] + v[None, :, :])
+    q3 = (n3 ** 2).sum(-1)
+    ok = O.bispec.in_modal_range(q3, kmin, kmax)
+    i1, i2 = np.nonzero(ok)
+    p1, p2, p3 = pk(v[i1]), pk(v[i2]), pk(n3[i1, i2])
+    w3 = p1 * p2 + p2 * p3 + p3 * p1
+    F = [(filt(a, q2[i1]), filt(a, q2[i2]), filt(a, q3[i1, i2])) for a in range(P)]
+    expect = np.array([2 * b2 * float(n) ** 3 * np.sum(F[a][0] * F[b][1] * F[c][2] * w3) / float(n) ** 9
+                       for a, b, c in modes])
+    out = []
+    for r in range(64):
+        g = _gaussian_lattice_field(n, 3500 + r, p)
+        d = g + b2 * (g * g - np.mean(g * g))
+        spec = O.spectrum_from_field([d], [0.0], n, 0, None, None)
+        out.append(O.modal_numerators(spec, n, n, modes, P, kmin, kmax, kf, pfid)[0])
+    z = _zscores(out, expect)
+    assert np.max(np.abs(z)) < 5, np.max(np.abs(z))
+    assert np.max(np.abs(_zscores(out, 0.0))) > 8
+    assert np.max(np.abs(_zscores(out, 2 * expect))) > 5
+    assert np.max(np.abs(_zscores(out, 0.5 * expect))) > 5
+
+
+def test_batch_covariance_closed_forms_and_sampling():
+    """Two samples: C = (x1 - x2)(x1 - x2)^T / 2. Adding a constant vector to
+    every sample changes nothing. Samples drawn with a known covariance S give
+    C within its sampling error, Var(C_ij) = (S_ii S_jj + S_ij^2) / (M - 1)."""
+    r = rng(44)
+    x = r.standard_normal((2, 5))
+    d = x[0] - x[1]
+    assert np.allclose(O.batch_covariance(x), np.outer(d, d) / 2, rtol=1e-14, atol=1e-15)
+    y = r.standard_normal((30, 5))
+    assert np.allclose(O.batch_covariance(y + np.arange(5.0) * 1e3), O.batch_covariance(y), rtol=1e-9, atol=1e-9)
+    A = r.standard_normal((5, 5))
+    S = A @ A.T + np.eye(5)
+    M = 4000
+    z = r.standard_normal((M, 5)) @ np.linalg.cholesky(S).T + 3.0
+    c = O.batch_covariance(z)
+    se = np.sqrt((np.outer(np.diag(S), np.diag(S)) + S ** 2) / (M - 1))
+    assert np.max(np.abs(c - S) / se) < 5
+    assert np.max(np.abs(2 * c - S) / se) > 5
