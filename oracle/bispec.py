@@ -45,7 +45,7 @@ __all__ = [
     "binned_bispectrum", "shell_power", "power_multipoles", "skew_spectra", "integrated_bispectrum",
     "shot_noise_binned", "modal_modes",
     "modal_q", "modal_filter", "modal_fields", "modal_numerators", "gram_matrix",
-    "modal_solve", "modal_shot_noise", "batch_covariance", "spectrum_from_catalogue",
+    "modal_solve", "modal_pivots", "modal_solve_pivoted", "modal_shot_noise", "batch_covariance", "spectrum_from_catalogue",
     "spectrum_from_field", "estimate", "Geometry", "n2_max_of",
 ]
 
@@ -780,6 +780,66 @@ def modal_solve(gamma: np.ndarray, b: np.ndarray):
     return alpha, beta
 
 
+def modal_pivots(gamma: np.ndarray, tol: float):
+    """Order in which the modes are orthonormalised, and which are kept.
+
+    Gram-Schmidt of the Q_n in the inner product gamma (eq. betaCalc), taking
+    next the mode whose part orthogonal to the modes already taken is largest
+    relative to its own norm: r_j = (gamma_jj - |projection of Q_j on the taken
+    span|^2) / gamma_jj. Stops when the largest r_j falls below tol: the modes
+    left are numerically dependent on the taken ones within the tetrapyd (the
+    near-null directions of a separable polynomial basis there), and their
+    coefficients are set to 0. Ties go to the lower mode index. tol <= 0 keeps
+    every mode in table order (the plain Cholesky factor of gamma).
+
+    r_j is evaluated from its definition, the Schur complement
+    gamma_jj - gamma_jS gamma_SS^-1 gamma_Sj over the taken set S.
+    Returns the list of kept mode indices in the order taken."""
+    nm = gamma.shape[0]
+    if tol <= 0:
+        return list(range(nm))
+    taken: List[int] = []
+    for _ in range(nm):
+        best, best_r = -1, -1.0
+        for j in range(nm):
+            if j in taken:
+                continue
+            if taken:
+                g_sj = gamma[np.ix_(taken, [j])][:, 0]
+                proj = float(g_sj @ np.linalg.solve(gamma[np.ix_(taken, taken)], g_sj))
+            else:
+                proj = 0.0
+            r = (gamma[j, j] - proj) / gamma[j, j]
+            if r > best_r:
+                best, best_r = j, r
+        if best_r < tol:
+            break
+        taken.append(best)
+    return taken
+
+
+def modal_solve_pivoted(gamma: np.ndarray, b: np.ndarray, tol: float):
+    """Coefficients on the orthonormalised modes kept by ``modal_pivots``.
+
+    With S the kept modes in the order taken, gamma_SS = L L^T (Cholesky):
+    alpha = L^-1 b_S are the coefficients of the projection of w B on the
+    orthonormal modes R = L^-1 Q_S (eq. betaCalc and the orthonormal basis of
+    Sec. 3.5); beta_S = L^-T alpha and beta = 0 on the dropped modes, so that
+    w^-1 sum_n beta_n Q_n is that projection. Returns (alpha [nl][nm] with the
+    first |S| entries set in the order taken, beta [nl][nm], S)."""
+    import scipy.linalg as sla
+    S = modal_pivots(gamma, tol)
+    b = np.atleast_2d(b)
+    L = np.linalg.cholesky(gamma[np.ix_(S, S)])
+    a = sla.solve_triangular(L, b[:, S].T, lower=True).T
+    bs = sla.solve_triangular(L.T, a.T, lower=False).T
+    alpha = np.zeros_like(b)
+    beta = np.zeros_like(b)
+    alpha[:, :len(S)] = a
+    beta[:, S] = bs
+    return alpha, beta, S
+
+
 def modal_shot_noise(nr: int, modes: np.ndarray, P: int, kmin, kmax, kf, box: float,
                      pfid_of_n2, nbar: float):
     """Poisson shot-noise part of b^0 (l = 0 only), mirroring the binned reading:
@@ -842,8 +902,11 @@ class Geometry:
 
 
 def estimate(spec_l, geo: Geometry, nbar: Optional[float] = None, counts=None, gamma=None,
-             sn_modal=None):
-    """Binned B_l, counts, shell power, shot-noise-subtracted B_0 and modal beta^l."""
+             sn_modal=None, modal_tol: float = 0.0):
+    """Binned B_l, counts, shell power, shot-noise-subtracted B_0 and modal beta^l.
+
+    modal_tol > 0 orthonormalises with ``modal_solve_pivoted`` (kept modes in
+    out["modal_kept"]); 0 uses the plain Cholesky factor of gamma."""
     n, nr = geo.n, geo.nr
     tris_all = triangle_list(geo.nbins)
     if counts is None:
@@ -872,6 +935,10 @@ def estimate(spec_l, geo: Geometry, nbar: Optional[float] = None, counts=None, g
             b = b.copy()
             b[0] = b[0] - sn_modal
             out["bnum_sub0"] = b[0]
-        alpha, beta = modal_solve(gamma, b)
-        out["alpha"], out["beta"] = alpha, beta
+        if modal_tol > 0:
+            alpha, beta, kept = modal_solve_pivoted(gamma, b, modal_tol)
+        else:
+            alpha, beta = modal_solve(gamma, b)
+            kept = list(range(len(geo.modes)))
+        out["alpha"], out["beta"], out["modal_kept"] = alpha, beta, np.array(kept, np.int64)
     return out

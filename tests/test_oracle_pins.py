@@ -1025,3 +1025,71 @@ def test_batch_covariance_closed_forms_and_sampling():
     se = np.sqrt((np.outer(np.diag(S), np.diag(S)) + S ** 2) / (M - 1))
     assert np.max(np.abs(c - S) / se) < 5
     assert np.max(np.abs(2 * c - S) / se) > 5
+
+
+def _near_dependent_functions(seed, m=400, nm=12):
+    """Columns: values of nm functions at m points (any inner product reduces to
+    a dot product of such columns); two columns are made dependent on others up
+    to 1e-4 and 1e-7 of their norm, and the column norms differ widely."""
+    r = rng(seed)
+    A = r.standard_normal((m, nm)) * r.uniform(0.01, 100.0, nm)
+    A[:, 5] = A[:, 1] - 2.0 * A[:, 3] + 1e-4 * np.linalg.norm(A[:, 1]) * r.standard_normal(m) / math.sqrt(m)
+    A[:, 9] = 0.5 * A[:, 0] + A[:, 7] + 1e-7 * np.linalg.norm(A[:, 0]) * r.standard_normal(m) / math.sqrt(m)
+    y = r.standard_normal(m)
+    return A, y
+
+
+def test_modal_pivots_match_pivoted_qr():
+    """The greedy order of modal_pivots is that of a QR factorisation with
+    column pivoting (LAPACK geqp3 through scipy) of the functions scaled to
+    unit norm, and the modes kept are those whose |R_kk|^2 >= tol. All scaled
+    columns tie at the first step, where the rule takes mode 0; the QR runs on
+    the other columns with mode 0 projected out."""
+    import scipy.linalg as sla
+    for seed in (51, 52, 53):
+        A, _ = _near_dependent_functions(seed)
+        gam = A.T @ A
+        An = A / np.linalg.norm(A, axis=0)
+        u0 = An[:, 0]
+        rest = An[:, 1:] - np.outer(u0, u0 @ An[:, 1:])
+        _, R, perm = sla.qr(rest, mode="economic", pivoting=True)
+        order = [0] + [int(x) + 1 for x in perm]
+        rkk = np.concatenate([[1.0], np.abs(np.diag(R)) ** 2])
+        # fixed tolerances, and ones just above and below a pivot's |R_kk|^2
+        for tol in (1e-2, 1e-6, 1e-12, 1.5 * rkk[4], rkk[4] / 1.5):
+            S = O.modal_pivots(gam, tol)
+            k = int(np.argmax(rkk < tol)) if np.any(rkk < tol) else len(rkk)
+            assert S == order[:k], (seed, tol, S, order[:k])
+        assert 5 not in O.modal_pivots(gam, 1e-6) and 9 not in O.modal_pivots(gam, 1e-6)
+        assert 5 in O.modal_pivots(gam, 1e-12) and 9 not in O.modal_pivots(gam, 1e-12)
+        assert O.modal_pivots(gam, 0.0) == list(range(A.shape[1]))
+
+
+def test_modal_solve_pivoted_is_orthonormal_projection():
+    """For functions A and data y with gamma = A^T A and b = A^T y: alpha are the
+    coefficients of y on the orthonormal vectors U of a thin QR of the kept
+    columns (A_S = U R, diag R > 0), and A_S beta_S is the least-squares
+    projection of y on their span (numpy lstsq); dropped modes get beta = 0."""
+    A, y = _near_dependent_functions(54)
+    gam = A.T @ A
+    b = (A.T @ y)[None, :]
+    alpha, beta, S = O.modal_solve_pivoted(gam, b, 1e-6)
+    U, R = np.linalg.qr(A[:, S])
+    sgn = np.sign(np.diag(R))
+    U = U * sgn
+    a_ref = U.T @ y
+    assert np.allclose(alpha[0, :len(S)], a_ref, rtol=1e-9, atol=1e-9 * np.abs(a_ref).max())
+    assert np.all(alpha[0, len(S):] == 0)
+    bs = np.linalg.lstsq(A[:, S], y, rcond=None)[0]
+    assert np.allclose(beta[0, S], bs, rtol=1e-7, atol=1e-9 * np.abs(bs).max())
+    drop = [j for j in range(A.shape[1]) if j not in S]
+    assert drop and np.all(beta[0, drop] == 0)
+    # tol = 0 on a well-conditioned gamma: the plain solve gamma beta = b
+    B = rng(55).standard_normal((300, 8))
+    g2 = B.T @ B
+    b2 = rng(56).standard_normal((2, 8))
+    al2, be2, S2 = O.modal_solve_pivoted(g2, b2, 0.0)
+    assert S2 == list(range(8))
+    assert np.allclose(be2, np.linalg.solve(g2, b2.T).T, rtol=1e-10, atol=1e-12)
+    al3, be3 = O.modal_solve(g2, b2)
+    assert np.allclose(al2, al3, rtol=1e-12, atol=1e-14) and np.allclose(be2, be3, rtol=1e-12, atol=1e-14)
