@@ -24,6 +24,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM = 8.0e12          # B/s
+MODAL_DROP_TOL = 1e-2      # the orthonormalisation drops modes whose relative residual falls below this
 PEAK_MFMA = {"fp32": 157.3e12, "bf16x3": 2.5e15, "fp16x3": 2.5e15, "bf16x1": 2.5e15}
 
 
@@ -271,7 +272,7 @@ def main():
     pfid[0] = pfid[1]
     plan = B.Plan(n=wl.n, n_reduce=wl.n_reduce, box=wl.box, nbins=wl.nbins, k0=wl.k0, dk=wl.dk, lmax=wl.lmax,
                   window=wl.window, compensate=1, interlace=wl.interlace, los=wl.los, observer=obs, P=wl.P,
-                  nmodes=wl.nmodes, pfid=pfid, device="cuda:0")
+                  nmodes=wl.nmodes, pfid=pfid, drop_tol=MODAL_DROP_TOL, device="cuda:0")
     log(f"workspace {plan.ws.numel() / 2**30:.1f} GiB; precompute ...")
     t0 = time.time()
     plan.precompute()
@@ -338,12 +339,16 @@ def main():
             a, b = a.cpu().numpy(), b.cpu().numpy()
             return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
         err = {f"B{2 * li}": rel(o_mix["B"][li], o32["B"][li]) for li in range(nl)}
-        # modal numerators b_n (the reduction's output); beta = gamma^-1 b inherits the
-        # condition number of the lattice Gram matrix, reported beside it
+        # modal numerators b_n (the reduction's output); alpha, the coefficients on the
+        # orthonormalised kept modes (the stated modal output); beta = L^-T alpha, whose
+        # error can exceed alpha's by up to cond(L), reported beside it
         err.update({f"bnum{2 * li}": rel(o_mix["bn"][li], o32["bn"][li]) for li in range(nl)})
+        err.update({f"alpha{2 * li}": rel(o_mix["al"][li], o32["al"][li]) for li in range(nl)})
         err.update({f"beta{2 * li}": rel(o_mix["be"][li], o32["be"][li]) for li in range(nl)})
         res["err_mixed_vs_fp32"] = err
-        res["gram_condition"] = plan.gram_condition()
+    gc = plan.gram_condition()
+    res["modal"] = {"nmodes": wl.nmodes, "drop_tol": MODAL_DROP_TOL, "kept": gc["rank"],
+                    "cond_gamma": gc["gamma"], "cond_L_kept": gc["L_kept"]}
     # roofline of the dominant kernel, from the event timings of the timed region; the
     # library accumulates each timed launch's algorithmic bytes (flops for the reduction)
     per_stage = {}
@@ -377,9 +382,16 @@ def main():
                  "inv_z": "k_inv_z", "reduce": "k_reduce"}
     traffic = measured_traffic(kernel_of.get(dom, dom).split()[0], wl.name)
     if dom == "reduce":
-        res["roofline"] = {"kernel": kernel_of[dom], "stage": dom, "bound": "mfma", "achieved": d["achieved_TFLOPs"],
-                           "peak": PEAK_MFMA[args.prec] / 1e12, "unit": "TFLOP/s", "frac": d["frac_mfma"],
-                           "traffic": traffic}
+        # the reduction reads every materialised field once: its algorithmic bytes are
+        # F x N'^3 x 4 (the few KB of T written are negligible), so HBM bounds it
+        nf = int(plan.info.nfields_binned + plan.info.nfields_modal)
+        rbytes = nf * float(wl.n_reduce) ** 3 * 4.0
+        d["algorithmic_bytes_per_launch"] = rbytes
+        d["achieved_GBps"] = rbytes / (d["avg_launch_ms"] * 1e-3) / 1e9
+        d["frac_hbm"] = d["achieved_GBps"] * 1e9 / PEAK_HBM
+        res["roofline"] = {"kernel": kernel_of[dom], "stage": dom, "bound": "hbm", "achieved": d["achieved_GBps"],
+                           "peak": PEAK_HBM / 1e9, "unit": "GB/s", "frac": d["frac_hbm"], "traffic": traffic,
+                           "mfma_frac_algorithmic": d["frac_mfma"], "mfma_frac_issued": d["frac_mfma_issued"]}
     else:
         res["roofline"] = {"kernel": kernel_of.get(dom, dom), "stage": dom, "bound": "hbm",
                            "achieved": d["achieved_GBps"], "peak": PEAK_HBM / 1e9, "unit": "GB/s",

@@ -91,13 +91,22 @@ typedef struct {
 
 /* Separable modal basis (Sec. 3.5): q_p(k) = Legendre P_p(t),
  * t = (2k - kmin - kmax)/(kmax - kmin) on kmin <= k < kmax, the union of the
- * shells; weight 1/sqrt(k P_fid(k)). */
+ * shells; weight 1/sqrt(k P_fid(k)).
+ * The modes are orthonormalised through the Gram matrix gamma (eq. betaCalc)
+ * by Gram-Schmidt, i.e. a Cholesky factor. drop_tol = 0: in table order, every
+ * mode kept (gamma must be positive definite). drop_tol in (0, 1): pivoted, the
+ * next mode being the one with the largest residual norm relative to its own
+ * after the modes already taken are projected out; modes whose relative
+ * residual is below drop_tol are dropped as numerically dependent within the
+ * tetrapyd (a separable polynomial basis has near-null directions there, and
+ * the coefficients along them amplify any rounding of the numerators). */
 typedef struct {
   int32_t P;             /* number of 1-D functions q_p, p < P */
-  int32_t nmodes;        /* number of 3-D modes Q_n */
+  int32_t nmodes;        /* number of 3-D modes Q_n (<= 128) */
   const int32_t* modes;  /* host [nmodes][3]: (p, r, s), p <= r <= s < P */
   const double* pfid;    /* host [pfid_len]: P_fid at k = k_f sqrt(m), m = |n|^2, (Mpc/h)^3 */
   int32_t pfid_len;      /* must exceed the largest |n|^2 in the modal range */
+  double drop_tol;       /* relative residual norm^2 below which a mode is dropped; 0 keeps all */
 } bsp_modal_basis;
 
 /* Sizes derived at plan creation. */
@@ -117,6 +126,7 @@ typedef struct {
   int32_t reduce_groups;  /* workgroups per point chunk */
   int32_t reduce_maxr, reduce_maxcw; /* row tiles, column tiles per wave */
   int64_t reduce_needed;  /* (pair, third) entries the estimators use */
+  int32_t modal_rank;     /* modes kept by the orthonormalisation (after bsp_precompute) */
 } bsp_info;
 
 /* ---------------------------------------------------------------- plans */
@@ -143,10 +153,13 @@ bsp_status bsp_sync(bsp_plan plan);
  * (betaCalc, innerProduct), its Cholesky factor, and the Poisson shot-noise
  * integrals of the modal numerators. Needs the workspace. Synchronises. */
 bsp_status bsp_precompute(bsp_plan plan);
-/* Host copies of the precompute results (after bsp_precompute):
- * tri [ntri][3] (b1 >= b2 >= b3, lexicographic), counts [ntri],
- * gamma [nmodes][nmodes] (may be NULL), chol [nmodes][nmodes] lower (may be NULL). */
-bsp_status bsp_geometry(bsp_plan plan, int32_t* tri, int64_t* counts, double* gamma, double* chol);
+/* Host copies of the precompute results (after bsp_precompute); any pointer
+ * may be NULL: tri [ntri][3] (b1 >= b2 >= b3, lexicographic), counts [ntri],
+ * gamma [nmodes][nmodes]; kept [nmodes]: the kept modes in the order they were
+ * orthonormalised, -1 past the rank; chol [nmodes][nmodes]: the lower Cholesky
+ * factor of gamma restricted to the kept modes in that order (rows and
+ * columns past the rank zero). */
+bsp_status bsp_geometry(bsp_plan plan, int32_t* tri, int64_t* counts, double* gamma, double* chol, int32_t* kept);
 
 /* ---------------------------------------------------------------- steps */
 
@@ -207,9 +220,12 @@ bsp_status bsp_triple_reduce(bsp_plan plan, const float* fields, int32_t nfields
  * the multipole modal coefficients with the even compositions of eqs.
  * (Bisp_ell, Bisp_ell2)): b^0 = <M0 M0 M0>, b^2 the three (2,0,0) placements,
  * b^4 the three (4,0,0) and three (0,2,2) placements, <XYZ> = N'^-3 sum_x.
- * nbar > 0 subtracts the Poisson shot noise of b^0. alpha = L^-1 b (orthonormal
- * basis), beta = L^-T alpha. bnum, alpha, beta: device double [nl][nmodes].
- * Requires bsp_precompute and a modal basis. */
+ * nbar > 0 subtracts the Poisson shot noise of b^0. With S the kept modes
+ * in the order orthonormalised (see bsp_modal_basis) and L the Cholesky factor
+ * of gamma_SS: alpha = L^-1 b_S, the coefficients on the orthonormal modes
+ * L^-1 Q_S (entries past the rank are 0); beta_S = L^-T alpha and beta = 0 on
+ * dropped modes (beta = gamma^-1 b when every mode is kept). bnum, alpha,
+ * beta: device double [nl][nmodes]. Requires bsp_precompute and a modal basis. */
 bsp_status bsp_modal_coeffs(bsp_plan plan, const void* delta_l, bsp_precision prec, double nbar, double* bnum,
                             double* alpha, double* beta);
 
@@ -321,22 +337,24 @@ bsp_status bsp_stage_times(bsp_plan plan, double* ms, int64_t* launches, double*
  * estimator). Mock m runs the whole path of bsp_bispectrum_multipoles on
  * plans[mock_plan[m]]: plans of different assignment grids N share one
  * reduction geometry (N', shells, modal basis), so every mock yields outputs
- * of the same shape. Outputs: B_all device [nmocks][nl][ntri]; beta_all device
- * [nmocks][nl*nmodes] (shot-noise-subtracted beta^l, l-major, as in
- * bsp_bispectrum_multipoles); cov device [D][D], D = nl*nmodes, the FP64
- * sample covariance of the beta_all rows. mock_plan, np: host [nmocks];
+ * of the same shape, and keep the same modes in their orthonormalisation.
+ * Outputs: B_all device [nmocks][nl][ntri]; alpha_all device [nmocks][nl*nmodes]
+ * (shot-noise-subtracted alpha^l on the orthonormalised kept modes, l-major, as
+ * in bsp_bispectrum_multipoles); beta_all likewise or NULL; cov device [D][D],
+ * D = nl*nmodes, the FP64 sample covariance of the alpha_all rows (rows and
+ * columns past each l's rank are 0). mock_plan, np: host [nmocks];
  * ux, uy, uz, w (w nullable, entries nullable): host arrays [nmocks] of device
  * pointers to the catalogues. Every plan needs bsp_precompute, a modal basis
  * and its own workspace (plans sharing a workspace must share a stream).
  * Mocks run in order, each on its plan's stream; the call synchronises every
  * plan before enqueueing the covariance on plans[0]'s stream (valid after
- * bsp_sync(plans[0])). Errors: BSP_ERR_ARG if the plans' output shapes
- * differ, nmocks < 2 or an index is out of range; the first failing mock's
+ * bsp_sync(plans[0])). Errors: BSP_ERR_ARG if the plans' output shapes or
+ * kept modes differ, nmocks < 2 or an index is out of range; the first failing mock's
  * status otherwise (its message via bsp_last_error(plans[0])). */
 bsp_status bsp_batch_run(const bsp_plan* plans, int32_t nplans, const int32_t* mock_plan, int32_t nmocks,
                          const float* const* ux, const float* const* uy, const float* const* uz,
                          const float* const* w, const int64_t* np, bsp_precision prec, double* B_all,
-                         double* beta_all, double* cov);
+                         double* alpha_all, double* beta_all, double* cov);
 
 /* Sample covariance of a batch of coefficient vectors (FP64):
  * cov = (1/(M-1)) sum_m (x_m - mean)(x_m - mean)^T. x: device [m][d], cov:

@@ -66,7 +66,7 @@ class Geom(C.Structure):
 
 class ModalBasis(C.Structure):
     _fields_ = [("P", C.c_int32), ("nmodes", C.c_int32), ("modes", C.POINTER(C.c_int32)),
-                ("pfid", C.POINTER(C.c_double)), ("pfid_len", C.c_int32)]
+                ("pfid", C.POINTER(C.c_double)), ("pfid_len", C.c_int32), ("drop_tol", C.c_double)]
 
 
 class Info(C.Structure):
@@ -75,7 +75,7 @@ class Info(C.Structure):
                 ("nfields_binned", C.c_int32), ("nfields_modal", C.c_int32), ("spec_elems", C.c_int64),
                 ("count_residual", C.c_double), ("reduce_pairs", C.c_int32), ("reduce_thirds", C.c_int32),
                 ("reduce_tiles", C.c_int32), ("reduce_groups", C.c_int32), ("reduce_maxr", C.c_int32),
-                ("reduce_maxcw", C.c_int32), ("reduce_needed", C.c_int64)]
+                ("reduce_maxcw", C.c_int32), ("reduce_needed", C.c_int64), ("modal_rank", C.c_int32)]
 
 
 _lib = None
@@ -98,7 +98,7 @@ def lib():
         "bsp_set_workspace": [_vp, _vp, C.c_size_t],
         "bsp_sync": [_vp],
         "bsp_precompute": [_vp],
-        "bsp_geometry": [_vp, _vp, _vp, _vp, _vp],
+        "bsp_geometry": [_vp, _vp, _vp, _vp, _vp, _vp],
         "bsp_grid_assign": [_vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp],
         "bsp_fft_r2c": [_vp, _i32, _i32, _vp, _vp],
         "bsp_fft_c2r": [_vp, _i32, _i32, _vp, _vp],
@@ -109,7 +109,7 @@ def lib():
         "bsp_modal_coeffs": [_vp, _vp, _i32, _d, _vp, _vp, _vp],
         "bsp_bispectrum_multipoles": [_vp, _vp, _vp, _vp, _vp, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp],
         "bsp_bispectrum_field": [_vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp],
-        "bsp_batch_run": [_vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp],
+        "bsp_batch_run": [_vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp],
         "bsp_batch_covariance": [_vp, _i32, _i32, _vp, _vp],
         "bsp_power_multipoles": [_vp, _vp, _vp],
         "bsp_skew_spectra": [_vp, _vp, _vp],
@@ -190,13 +190,17 @@ def bsp_precompute(plan):
 
 
 def bsp_geometry(plan, ntri: int, nmodes: int = 0):
+    """Returns (tri, counts, gamma, chol, kept); kept lists the kept modes in
+    the order orthonormalised, -1 past the rank."""
     tri = np.zeros((ntri, 3), np.int32)
     cnt = np.zeros(ntri, np.int64)
     gam = np.zeros((nmodes, nmodes)) if nmodes else None
     chol = np.zeros((nmodes, nmodes)) if nmodes else None
+    kept = np.zeros(nmodes, np.int32) if nmodes else None
     _check(lib().bsp_geometry(plan, tri.ctypes.data, cnt.ctypes.data,
-                              gam.ctypes.data if nmodes else None, chol.ctypes.data if nmodes else None), plan)
-    return tri, cnt, gam, chol
+                              gam.ctypes.data if nmodes else None, chol.ctypes.data if nmodes else None,
+                              kept.ctypes.data if nmodes else None), plan)
+    return tri, cnt, gam, chol, kept
 
 
 def bsp_grid_assign(plan, ux, uy, uz, w, np_, grids, wsum):
@@ -252,7 +256,7 @@ def bsp_bispectrum_field(plan, delta, prec, B, Pbar=None, bnum=None, alpha=None,
                                       _dptr(beta)), plan)
 
 
-def bsp_batch_run(plans, mock_plan, ux, uy, uz, w, np_, prec, B_all, beta_all, cov):
+def bsp_batch_run(plans, mock_plan, ux, uy, uz, w, np_, prec, B_all, alpha_all, beta_all, cov):
     """plans: list of plan handles; mock_plan, np_: per-mock ints; ux, uy, uz, w:
     per-mock float32 device tensors (w None or a list with None entries)."""
     import torch
@@ -265,7 +269,7 @@ def bsp_batch_run(plans, mock_plan, ux, uy, uz, w, np_, prec, B_all, beta_all, c
         return (C.c_void_p * nm)(*[_dptr(t, torch.float32) for t in ts])
     W = None if w is None else ptrs(w)
     _check(lib().bsp_batch_run(P, npl, mp, nm, ptrs(ux), ptrs(uy), ptrs(uz), W, NP, prec, _dptr(B_all),
-                               _dptr(beta_all), _dptr(cov)), plans[0])
+                               _dptr(alpha_all), _dptr(beta_all), _dptr(cov)), plans[0])
 
 
 def bsp_batch_covariance(x, m, d, cov, stream: int = 0):
@@ -316,7 +320,7 @@ class Plan:
     """Owns a bsp plan, its workspace tensor and the stream it runs on."""
 
     def __init__(self, n, box, nbins, k0, dk, lmax=0, n_reduce=0, window=1, compensate=1, interlace=0, los=0,
-                 observer=(0.0, 0.0, 0.0), P=0, nmodes=0, modes=None, pfid=None, device="cuda:0",
+                 observer=(0.0, 0.0, 0.0), P=0, nmodes=0, modes=None, pfid=None, drop_tol=0.0, device="cuda:0",
                  workspace=True):
         import torch
         self.torch = torch
@@ -338,6 +342,7 @@ class Plan:
             b.modes = self._modes.ctypes.data_as(C.POINTER(C.c_int32))
             b.pfid = self._pfid.ctypes.data_as(C.POINTER(C.c_double))
             b.pfid_len = self._pfid.size
+            b.drop_tol = float(drop_tol)
             self.basis = b
             self.nmodes = nmodes
             self.P = P
@@ -349,22 +354,26 @@ class Plan:
             nbytes = bsp_workspace_size(self.handle)
             self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
             bsp_set_workspace(self.handle, self.ws, nbytes)
-        self.tri = self.counts = self.gamma = self.chol = None
+        self.tri = self.counts = self.gamma = self.chol = self.kept = None
 
     def precompute(self):
         bsp_precompute(self.handle)
         self.info = bsp_plan_info(self.handle)
-        self.tri, self.counts, self.gamma, self.chol = bsp_geometry(self.handle, self.info.ntri, self.nmodes)
+        self.tri, self.counts, self.gamma, self.chol, self.kept = bsp_geometry(self.handle, self.info.ntri,
+                                                                              self.nmodes)
         return self
 
     def gram_condition(self):
-        """2-norm condition number of the lattice Gram matrix gamma (after
-        precompute; None without a modal basis). beta = gamma^-1 b amplifies
-        relative errors of the numerators b by up to this factor."""
+        """2-norm condition numbers (after precompute; None without a modal
+        basis): of the lattice Gram matrix gamma, and of the Cholesky factor L
+        of its kept modes. alpha = L^-1 b amplifies relative errors of the
+        numerators b by up to cond(L), beta by up to cond(L)^2."""
         if self.gamma is None or self.nmodes == 0:
             return None
-        import numpy as np
-        return float(np.linalg.cond(np.asarray(self.gamma)))
+        r = int(self.info.modal_rank)
+        L = np.asarray(self.chol)[:r, :r]
+        return {"gamma": float(np.linalg.cond(np.asarray(self.gamma))), "L_kept": float(np.linalg.cond(L)),
+                "rank": r, "nmodes": int(self.nmodes)}
 
     def sync(self):
         bsp_sync(self.handle)

@@ -309,6 +309,10 @@ struct bsp_plan_s {
   int32_t* d_tri_tidx = nullptr;
   int32_t* d_combo = nullptr;
   double* d_L = nullptr;
+  int32_t* d_piv = nullptr;          // kept modes in the order orthonormalised, then the rank
+  double drop_tol = 0.0;             // relative residual below which a mode is dropped (0: keep all)
+  std::vector<int32_t> piv_h;
+  int modal_rank = 0;
   double* d_sn = nullptr;
   ReducePlan main_rp, cnt_rp, gram_rp, sn_rp;
   ReducePlan full_rp;                // B^(l1 l2 l3): every (l2, l3) pair of shell fields, made on first use
@@ -1193,6 +1197,7 @@ bsp_status bsp_plan_create(bsp_plan* out, const bsp_geom* g, const bsp_modal_bas
     ok = build_gram(p) && upload_rp(p, p->gram_rp) && build_sn(p) && upload_rp(p, p->sn_rp) &&
          (p->d_gidx = upload(p, p->gidx)) && (p->d_sidx = upload(p, p->sidx)) && (p->d_urow = upload(p, urow)) &&
          (p->d_grow = upload(p, grow)) && (p->d_L = dalloc<double>(p, (size_t)p->nmodes * p->nmodes)) &&
+         (p->d_piv = dalloc<int32_t>(p, (size_t)p->nmodes + 1)) &&
          (p->d_sn = dalloc<double>(p, 2 * (size_t)p->nmodes));
   }
   ok = ok && build_main(p, false);  // candidate schedule: bounds the workspace before the counts exist
@@ -1243,6 +1248,7 @@ bsp_status bsp_plan_info(bsp_plan p, bsp_info* info) {
   info->reduce_maxr = m.maxr;
   info->reduce_maxcw = m.maxcw;
   info->reduce_needed = m.needed;
+  info->modal_rank = p->modal_rank;
   return BSP_OK;
 }
 
@@ -1541,11 +1547,15 @@ bsp_status bsp_precompute(bsp_plan p) {
     HIPCHK(hipStreamSynchronize(p->stream));
     p->gamma_h.resize((size_t)nm * nm);
     HIPCHK(hipMemcpy(p->gamma_h.data(), p->d_L, p->gamma_h.size() * sizeof(double), hipMemcpyDeviceToHost));
-    HIPCHK(launch_cholesky(p->d_L, nm, p->d_err, p->stream));
+    if ((size_t)nm * nm * sizeof(double) > scr_bytes) return fail(p, BSP_ERR_WORKSPACE, "workspace too small");
+    HIPCHK(launch_cholesky(p->d_L, reinterpret_cast<double*>(scr), nm, p->drop_tol, p->d_piv, p->d_err, p->stream));
     s = bsp_sync(p);
     if (s != BSP_OK) return s;
     p->chol_h.resize((size_t)nm * nm);
     HIPCHK(hipMemcpy(p->chol_h.data(), p->d_L, p->chol_h.size() * sizeof(double), hipMemcpyDeviceToHost));
+    p->piv_h.resize((size_t)nm + 1);
+    HIPCHK(hipMemcpy(p->piv_h.data(), p->d_piv, p->piv_h.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    p->modal_rank = p->piv_h[nm];
     s = inverse_fields<double>(p, ones, 0, 2 * p->P, p->d_ones_ell, p->d_grow, p->d_tab64, p->d_rng64, f64, scr, L.fb64,
                                std::vector<int>(2 * p->P, p->c));
     if (s != BSP_OK) return s;
@@ -1568,7 +1578,7 @@ bsp_status bsp_precompute(bsp_plan p) {
   return BSP_OK;
 }
 
-bsp_status bsp_geometry(bsp_plan p, int32_t* tri, int64_t* counts, double* gamma, double* chol) {
+bsp_status bsp_geometry(bsp_plan p, int32_t* tri, int64_t* counts, double* gamma, double* chol, int32_t* kept) {
   if (!p) return BSP_ERR_ARG;
   if (!p->pre_done) return fail(p, BSP_ERR_STATE, "bsp_precompute has not run");
   for (size_t i = 0; i < p->tri.size(); ++i) {
@@ -1578,6 +1588,7 @@ bsp_status bsp_geometry(bsp_plan p, int32_t* tri, int64_t* counts, double* gamma
   }
   if (gamma && p->modal) std::memcpy(gamma, p->gamma_h.data(), p->gamma_h.size() * sizeof(double));
   if (chol && p->modal) std::memcpy(chol, p->chol_h.data(), p->chol_h.size() * sizeof(double));
+  if (kept && p->modal) std::memcpy(kept, p->piv_h.data(), (size_t)p->nmodes * sizeof(int32_t));
   return BSP_OK;
 }
 
@@ -1636,7 +1647,7 @@ bsp_status estimate_from_spectrum(bsp_plan p, const float2* dl, bsp_precision pr
     if (nm > 128) return fail(p, BSP_ERR_ARG, "more than 128 modes");
     const double scale_b = 1.0 / ((double)K * std::pow(N, 9));
     HIPCHK(launch_modal_assemble(T, p->d_combo, nm, p->nl, scale_b, p->d_sn, nbar_dev, bo, p->stream));
-    HIPCHK(launch_tri_solve(p->d_L, nm, p->nl, bo, ao, beo, p->stream));
+    HIPCHK(launch_tri_solve(p->d_L, p->d_piv, nm, p->nl, bo, ao, beo, p->stream));
   }
   return BSP_OK;
 }
@@ -1992,8 +2003,8 @@ bsp_status bsp_stage_times(bsp_plan p, double* ms, int64_t* launches, double* am
 bsp_status bsp_batch_run(const bsp_plan* plans, int32_t nplans, const int32_t* mock_plan, int32_t nmocks,
                          const float* const* ux, const float* const* uy, const float* const* uz,
                          const float* const* w, const int64_t* np, bsp_precision prec, double* B_all,
-                         double* beta_all, double* cov) {
-  if (!plans || nplans < 1 || !mock_plan || nmocks < 2 || !ux || !uy || !uz || !np || !B_all || !beta_all || !cov)
+                         double* alpha_all, double* beta_all, double* cov) {
+  if (!plans || nplans < 1 || !mock_plan || nmocks < 2 || !ux || !uy || !uz || !np || !B_all || !alpha_all || !cov)
     return fail(nullptr, BSP_ERR_ARG, "bad argument");
   bsp_plan p0 = plans[0];
   if (!p0) return fail(nullptr, BSP_ERR_ARG, "null plan");
@@ -2004,6 +2015,9 @@ bsp_status bsp_batch_run(const bsp_plan* plans, int32_t nplans, const int32_t* m
     if (!q->pre_done) return fail(p0, BSP_ERR_STATE, "bsp_precompute has not run on every plan");
     if (!q->modal || q->nl != p0->nl || q->nmodes != p0->nmodes || q->tri.size() != p0->tri.size())
       return fail(p0, BSP_ERR_ARG, "plans differ in multipoles, triangles or modes (or have no modal basis)");
+    // alpha is a coefficient vector on the same orthonormal modes only when
+    // every plan kept the same modes in the same order
+    if (q->piv_h != p0->piv_h) return fail(p0, BSP_ERR_ARG, "plans kept different modes in their orthonormalisation");
   }
   for (int m = 0; m < nmocks; ++m)
     if (mock_plan[m] < 0 || mock_plan[m] >= nplans) return fail(p0, BSP_ERR_ARG, "mock plan index out of range");
@@ -2013,7 +2027,8 @@ bsp_status bsp_batch_run(const bsp_plan* plans, int32_t nplans, const int32_t* m
     bsp_plan q = plans[mock_plan[m]];
     const bsp_status s = bsp_bispectrum_multipoles(q, ux[m], uy[m], uz[m], w ? w[m] : nullptr, np[m], prec,
                                                    B_all + (int64_t)m * p0->nl * ntri, nullptr, nullptr, nullptr,
-                                                   nullptr, beta_all + (int64_t)m * D);
+                                                   alpha_all + (int64_t)m * D,
+                                                   beta_all ? beta_all + (int64_t)m * D : nullptr);
     if (s != BSP_OK) {
       if (q != p0) p0->err = q->err;
       return s;
@@ -2028,7 +2043,7 @@ bsp_status bsp_batch_run(const bsp_plan* plans, int32_t nplans, const int32_t* m
     }
   }
   bsp_plan p = p0;
-  HIPCHK(launch_covariance(beta_all, nmocks, (int)D, cov, p0->stream));
+  HIPCHK(launch_covariance(alpha_all, nmocks, (int)D, cov, p0->stream));
   return BSP_OK;
 }
 

@@ -83,46 +83,122 @@ __global__ void k_sn_assemble(const double* __restrict__ T, const int32_t* __res
   sn[nmodes + i] = scale * T[sidx[4 * i + 3]];
 }
 
-// In-place Cholesky of a symmetric positive-definite n x n matrix (row major),
-// lower factor left in place, upper triangle zeroed. One workgroup.
-__global__ __launch_bounds__(256) void k_cholesky(double* __restrict__ A, int n, int32_t* __restrict__ err) {
-  __shared__ double diag;
-  __shared__ int fail;
-  if (threadIdx.x == 0) fail = 0;
+// Cholesky factor of the Gram matrix with optional pivoting and truncation
+// (Gram-Schmidt of the modes in the gamma inner product). tol <= 0: modes in
+// table order, all kept, non-positive pivots latch error bit 8. tol > 0: the
+// next mode is the one whose residual norm relative to its own,
+// resid_j / gamma_jj, is largest (ties to the lower index); stop once it falls
+// below tol (the rest are numerically dependent on the modes taken). One
+// workgroup of 256 threads, n <= 128.
+//   A: in gamma [n][n]; out L [n][n], row i = i-th kept mode, lower triangular,
+//      rows >= rank zero.
+//   W: scratch [n][n] (factor indexed by mode, step).
+//   piv: out [n] kept modes in order taken, -1 past the rank; piv[n] = rank.
+__global__ __launch_bounds__(256) void k_cholesky_pivoted(double* __restrict__ A, double* __restrict__ W, int n,
+                                                          double tol, int32_t* __restrict__ piv,
+                                                          int32_t* __restrict__ err) {
+  __shared__ double resid[128], d0[128];
+  __shared__ int taken[128];
+  __shared__ double rv[256];
+  __shared__ int ri[256];
+  __shared__ int jstar, stop, fail;
+  const int t = threadIdx.x;
+  for (int i = t; i < n * n; i += blockDim.x) W[i] = 0.0;
+  if (t < n) {
+    resid[t] = A[(int64_t)t * n + t];
+    d0[t] = resid[t];
+    taken[t] = 0;
+  }
+  if (t == 0) {
+    stop = 0;
+    fail = 0;
+  }
   __syncthreads();
-  for (int j = 0; j < n; ++j) {
-    if (threadIdx.x == 0) {
-      double d = A[(int64_t)j * n + j];
-      for (int k = 0; k < j; ++k) d -= A[(int64_t)j * n + k] * A[(int64_t)j * n + k];
-      if (!(d > 0.0)) {
-        fail = 1;
-        d = 1.0;
+  int k = 0;
+  for (; k < n; ++k) {
+    if (tol > 0.0) {
+      // argmax of resid / d0 over the modes not taken, lower index on ties
+      double v = -1.0;
+      int vi = n;
+      if (t < n && !taken[t]) {
+        v = resid[t] / d0[t];
+        vi = t;
       }
-      diag = sqrt(d);
-      A[(int64_t)j * n + j] = diag;
+      rv[t] = v;
+      ri[t] = vi;
+      __syncthreads();
+      for (int off = 128; off > 0; off >>= 1) {
+        if (t < off) {
+          const double a = rv[t], b = rv[t + off];
+          const int ia = ri[t], ib = ri[t + off];
+          if (b > a || (b == a && ib < ia)) {
+            rv[t] = b;
+            ri[t] = ib;
+          }
+        }
+        __syncthreads();
+      }
+      if (t == 0) {
+        jstar = ri[0];
+        stop = !(rv[0] >= tol) || ri[0] >= n;
+      }
+    } else if (t == 0) {
+      jstar = k;
+      if (!(resid[k] > 0.0)) {
+        fail = 1;
+        resid[k] = 1.0;
+      }
     }
     __syncthreads();
-    for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) {
-      double s = A[(int64_t)i * n + j];
-      for (int k = 0; k < j; ++k) s -= A[(int64_t)i * n + k] * A[(int64_t)j * n + k];
-      A[(int64_t)i * n + j] = s / diag;
+    if (stop) break;
+    const int j0 = jstar;
+    const double dk = sqrt(resid[j0]);
+    if (t == 0) {
+      piv[k] = j0;
+      taken[j0] = 1;
+      W[(int64_t)j0 * n + k] = dk;
+    }
+    __syncthreads();
+    if (t < n && !taken[t]) {
+      double sum = A[(int64_t)t * n + j0];
+      for (int m = 0; m < k; ++m) sum -= W[(int64_t)t * n + m] * W[(int64_t)j0 * n + m];
+      const double c = sum / dk;
+      W[(int64_t)t * n + k] = c;
+      resid[t] -= c * c;
     }
     __syncthreads();
   }
-  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x)
-    if (idx % n > idx / n) A[idx] = 0.0;
-  if (threadIdx.x == 0 && fail) atomicOr(err, 8);
+  const int rank = k;
+  __syncthreads();
+  for (int idx = t; idx < n * n; idx += blockDim.x) {
+    const int i = idx / n, m = idx % n;
+    A[idx] = (i < rank && m <= i) ? W[(int64_t)piv[i] * n + m] : 0.0;
+  }
+  for (int i = rank + t; i < n; i += blockDim.x) piv[i] = -1;
+  if (t == 0) {
+    piv[n] = rank;
+    if (fail) atomicOr(err, 8);
+  }
 }
 
-// alpha = L^-1 b, beta = L^-T alpha for nrhs right-hand sides (one workgroup each).
-__global__ __launch_bounds__(256) void k_tri_solve(const double* __restrict__ L, int n, const double* __restrict__ b,
-                                                   double* __restrict__ alpha, double* __restrict__ beta) {
+// Coefficients on the kept, orthonormalised modes for nrhs right-hand sides
+// (one workgroup each): alpha_i = (L^-1 b_S)_i for i < rank (0 past it),
+// beta_{piv[i]} = (L^-T alpha)_i on the kept modes and 0 on the others.
+__global__ __launch_bounds__(256) void k_tri_solve(const double* __restrict__ L, const int32_t* __restrict__ piv,
+                                                   int n, const double* __restrict__ b, double* __restrict__ alpha,
+                                                   double* __restrict__ beta) {
   const int r = blockIdx.x;
+  const int rank = piv[n];
   const double* bb = b + (int64_t)r * n;
   double* al = alpha + (int64_t)r * n;
   double* be = beta + (int64_t)r * n;
   __shared__ double red[256];
-  for (int i = 0; i < n; ++i) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    be[i] = 0.0;
+    if (i >= rank) al[i] = 0.0;
+  }
+  __syncthreads();
+  for (int i = 0; i < rank; ++i) {
     double s = 0.0;
     for (int k = threadIdx.x; k < i; k += blockDim.x) s += L[(int64_t)i * n + k] * al[k];
     red[threadIdx.x] = s;
@@ -131,19 +207,19 @@ __global__ __launch_bounds__(256) void k_tri_solve(const double* __restrict__ L,
       if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
       __syncthreads();
     }
-    if (threadIdx.x == 0) al[i] = (bb[i] - red[0]) / L[(int64_t)i * n + i];
+    if (threadIdx.x == 0) al[i] = (bb[piv[i]] - red[0]) / L[(int64_t)i * n + i];
     __syncthreads();
   }
-  for (int i = n - 1; i >= 0; --i) {
+  for (int i = rank - 1; i >= 0; --i) {
     double s = 0.0;
-    for (int k = i + 1 + threadIdx.x; k < n; k += blockDim.x) s += L[(int64_t)k * n + i] * be[k];
+    for (int k = i + 1 + threadIdx.x; k < rank; k += blockDim.x) s += L[(int64_t)k * n + i] * be[piv[k]];
     red[threadIdx.x] = s;
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
       if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
       __syncthreads();
     }
-    if (threadIdx.x == 0) be[i] = (al[i] - red[0]) / L[(int64_t)i * n + i];
+    if (threadIdx.x == 0) be[piv[i]] = (al[i] - red[0]) / L[(int64_t)i * n + i];
     __syncthreads();
   }
 }
@@ -212,15 +288,16 @@ hipError_t launch_sn_assemble(const double* T, const int32_t* sidx, int nmodes, 
   return hipGetLastError();
 }
 
-hipError_t launch_cholesky(double* A, int n, int32_t* err, hipStream_t s) {
-  hipLaunchKernelGGL(k_cholesky, dim3(1), dim3(256), 0, s, A, n, err);
+hipError_t launch_cholesky(double* A, double* W, int n, double tol, int32_t* piv, int32_t* err, hipStream_t s) {
+  if (n < 1 || n > 128) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_cholesky_pivoted, dim3(1), dim3(256), 0, s, A, W, n, tol, piv, err);
   return hipGetLastError();
 }
 
-hipError_t launch_tri_solve(const double* L, int n, int nrhs, const double* b, double* alpha, double* beta,
-                            hipStream_t s) {
+hipError_t launch_tri_solve(const double* L, const int32_t* piv, int n, int nrhs, const double* b, double* alpha,
+                            double* beta, hipStream_t s) {
   if (nrhs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_tri_solve, dim3(nrhs), dim3(256), 0, s, L, n, b, alpha, beta);
+  hipLaunchKernelGGL(k_tri_solve, dim3(nrhs), dim3(256), 0, s, L, piv, n, b, alpha, beta);
   return hipGetLastError();
 }
 

@@ -3,8 +3,9 @@
 Mocks on assignment grids of 128, 192, 256 and 384 points per side share one
 reduction geometry (N' = 128, 20 shells of 2 k_f, l <= 4, 50 modes with P = 6),
 run through bsp_batch_run in bf16 hi+lo, and are checked mock by mock against
-the FP64 oracle; the FP64 covariance of the beta rows is checked against the
-oracle's definition on the same rows.
+the FP64 oracle (B_l, and alpha on the orthonormalised kept modes); the FP64
+covariance of the alpha rows is checked against the oracle's definition on
+the same rows.
 """
 import sys
 
@@ -24,6 +25,7 @@ if not torch.cuda.is_available():  # pragma: no cover - CPU container
 import paper_1708_05303_amd as B  # noqa: E402
 
 DEV = torch.device("cuda:0")
+DROP_TOL = 1e-2  # relative residual below which the orthonormalisation drops a mode
 
 
 def say(*a):
@@ -60,7 +62,7 @@ def uneven_batch():
         wl = C.batch_workload(0, n)
         plans[n] = B.Plan(n=n, n_reduce=wl.n_reduce, box=wl.box, nbins=wl.nbins, k0=wl.k0, dk=wl.dk, lmax=wl.lmax,
                           window=wl.window, interlace=wl.interlace, los=wl.los, observer=C.observer_grid_units(wl),
-                          P=wl.P, nmodes=wl.nmodes, pfid=pf)
+                          P=wl.P, nmodes=wl.nmodes, pfid=pf, drop_tol=DROP_TOL)
         plans[n].precompute()
     cats, refs = [], []
     for m, n in mocks:
@@ -69,7 +71,7 @@ def uneven_batch():
         obs = C.observer_grid_units(wl)
         spec, wsum = O.spectrum_from_catalogue(*u, n, wl.lmax, obs, window=wl.window, interlace=wl.interlace)
         geo = O.Geometry(n, wl.n_reduce, wl.box, wl.lmax, wl.nbins, wl.k0, wl.dk, wl.P, wl.nmodes, pf)
-        refs.append(O.estimate(spec, geo, nbar=wsum / wl.box ** 3))
+        refs.append(O.estimate(spec, geo, nbar=wsum / wl.box ** 3, modal_tol=DROP_TOL))
         cats.append(u)
         say("oracle mock", m, n)
     info = plans[128].info
@@ -77,34 +79,45 @@ def uneven_batch():
     order = [sizes.index(n) for _, n in mocks]
     dv = [[torch.as_tensor(u[a]).to(DEV) for u in cats] for a in range(3)]
     B_all = torch.zeros((len(mocks), nl, info.ntri), dtype=torch.float64, device=DEV)
+    alpha_all = torch.zeros((len(mocks), nl * nm), dtype=torch.float64, device=DEV)
     beta_all = torch.zeros((len(mocks), nl * nm), dtype=torch.float64, device=DEV)
     cov = torch.zeros((nl * nm, nl * nm), dtype=torch.float64, device=DEV)
     B.bsp_batch_run([plans[n].handle for n in sizes], order, dv[0], dv[1], dv[2], None,
-                    [u[0].size for u in cats], B.BSP_BF16X3, B_all, beta_all, cov)
+                    [u[0].size for u in cats], B.BSP_BF16X3, B_all, alpha_all, beta_all, cov)
     plans[128].sync()
     counts = {n: plans[n].counts.copy() for n in sizes}
-    out = (B_all.cpu().numpy(), beta_all.cpu().numpy(), cov.cpu().numpy())
+    kept = {n: plans[n].kept.copy() for n in sizes}
+    out = (B_all.cpu().numpy(), alpha_all.cpu().numpy(), beta_all.cpu().numpy(), cov.cpu().numpy())
     for p in plans.values():
         p.close()
-    return mocks, refs, counts, out, nl, nm
+    return mocks, refs, counts, kept, out, nl, nm
 
 
 def test_uneven_batch_against_oracle(uneven_batch):
-    mocks, refs, counts, (B_all, beta_all, cov), nl, nm = uneven_batch
+    mocks, refs, counts, kept, (B_all, alpha_all, beta_all, cov), nl, nm = uneven_batch
+    ko = refs[0]["modal_kept"]
     for n, c in counts.items():
         assert np.array_equal(c, refs[0]["counts"]), n
+        assert np.array_equal(kept[n][:len(ko)], ko) and np.all(kept[n][len(ko):] == -1), n
+    say("kept modes", len(ko), "of", nm)
     for i, (m, n) in enumerate(mocks):
         ref = refs[i]
         for li in range(nl):
             e = rel_norm(B_all[i, li], ref["B"][li])
             say("mock", m, "n", n, "l", 2 * li, "B err", e)
             assert e < 1e-3, (m, li, e)
-        kL = np.linalg.cond(np.linalg.cholesky(ref["gamma"]))
+        kL = np.linalg.cond(np.linalg.cholesky(ref["gamma"][np.ix_(ko, ko)]))
         for li in range(nl):
-            e = rel_norm(beta_all[i, li * nm:(li + 1) * nm], ref["beta"][li])
-            say("mock", m, "l", 2 * li, "beta err", e, "kappa(L)", kL)
-            assert e < max(1e-4, kL * 1e-4), (m, li, e)
-    assert rel_norm(cov, O.batch_covariance(beta_all)) < 1e-12
+            ea = rel_norm(alpha_all[i, li * nm:(li + 1) * nm], ref["alpha"][li])
+            eb = rel_norm(beta_all[i, li * nm:(li + 1) * nm], ref["beta"][li])
+            say("mock", m, "l", 2 * li, "alpha err", ea, "beta err", eb, "cond(L)", kL)
+            assert ea < 1e-4, (m, li, ea)
+            assert eb < kL * 1e-4, (m, li, eb)
+    assert rel_norm(cov, O.batch_covariance(alpha_all)) < 1e-12
+    ref_alpha = np.stack([r["alpha"].ravel() for r in refs])
+    e = rel_norm(cov, O.batch_covariance(ref_alpha))
+    say("covariance of alpha against the oracle rows", e)
+    assert e < 5e-3
 
 
 def test_batch_run_rejects_mismatched_plans():
@@ -116,9 +129,9 @@ def test_batch_run_rejects_mismatched_plans():
     b.precompute()
     u = [torch.full((10,), 3.0, device=DEV) for _ in range(2)]
     Ball = torch.zeros((2, 3, 64), dtype=torch.float64, device=DEV)
-    beta = torch.zeros((2, 12), dtype=torch.float64, device=DEV)
+    alpha = torch.zeros((2, 12), dtype=torch.float64, device=DEV)
     cov = torch.zeros((12, 12), dtype=torch.float64, device=DEV)
     with pytest.raises(B.BspError):
-        B.bsp_batch_run([a.handle, b.handle], [0, 1], u, u, u, None, [10, 10], B.BSP_FP32, Ball, beta, cov)
+        B.bsp_batch_run([a.handle, b.handle], [0, 1], u, u, u, None, [10, 10], B.BSP_FP32, Ball, alpha, None, cov)
     a.close()
     b.close()
