@@ -167,12 +167,19 @@ bsp_status bsp_geometry(bsp_plan plan, int32_t* tri, int64_t* counts, double* ga
  * positions in grid units in [0, N) (w NULL: unit weights). grids: device
  * [1+interlace][N^3], accumulated into (the caller zeroes them). wsum: device
  * double[1], accumulated sum of weights. Out-of-range or non-finite positions
- * are skipped and latch BSP_ERR_DEVICE. When the workspace holds the sorted
- * catalogue (20 bytes per particle plus the tile offsets) the particles are
- * sorted by node tile and each tile is summed in LDS; otherwise each
- * contribution is a global float atomic. Either way the FP32 sums run in an
- * unspecified order, so grids (and everything made from them) may differ in
- * the last bit between runs. */
+ * are skipped and latch BSP_ERR_DEVICE.
+ * Kernels: when the workspace holds the sorted catalogue (20 bytes per
+ * particle plus the tile offsets and 256 bytes) the particles are sorted by
+ * node tile and each tile is summed in LDS; else, when it holds
+ * (1+interlace) N^3 int64 node sums plus 256 bytes, each contribution is a
+ * global 64-bit atomic; without a workspace, a global FP32 atomic.
+ * Reproducibility: the first two sum node values and weights as 64-bit
+ * integers in units of 2^-S (S = min(36, 62 - e - l), max|w| < 2^e,
+ * np < 2^l), each contribution rounded once, so their result does not depend
+ * on the order of the atomics: the grids are bit-identical between runs, and
+ * for unit weights and positions on multiples of 2^-12 the node sums are exact
+ * (each grid value is the exact sum rounded once to FP32). The FP32-atomic
+ * fallback sums in an unspecified order. */
 bsp_status bsp_grid_assign(bsp_plan plan, const float* ux, const float* uy, const float* uz, const float* w,
                            int64_t np, float* grids, double* wsum);
 
@@ -231,11 +238,12 @@ bsp_status bsp_modal_coeffs(bsp_plan plan, const void* delta_l, bsp_precision pr
 
 /* The whole hot path for one catalogue: assignment (the sorted, tiled kernels
  * when the grid has at least 512 tiles of 8 x 8 x tz nodes, that is 128 nodes a
- * side and up; the global-atomic kernel below), LOS moments, shell and modal
- * fields, one triple reduction, FP64 normalisation. The assignment's FP32
- * summation order varies between runs (see bsp_grid_assign); later steps add
- * FP64 partial sums in an unspecified order, which changes only their last
- * bits.
+ * side and up; the fixed-point global-atomic kernel below), LOS moments, shell
+ * and modal fields, one triple reduction, FP64 normalisation. B, bnum, alpha
+ * and beta are bit-identical between runs on the same inputs (fixed-point
+ * assignment, reduction partials combined in a fixed order); the shell power
+ * (Pbar, and through it B0sub) adds FP64 partial sums in an unspecified order,
+ * which can change its last bits.
  *   B: device double [nl][ntri], B^l = V^2 T^l / (N^9 N'^3 N_tri) (multipole on b1);
  *   B0sub: device double [ntri] or NULL, B^0 - sum_i Pbar_bi / nbar + 2/nbar^2;
  *   Pbar: device double [nbins] or NULL, shell power V sum |delta0|^2 / (N^6 N_b);

@@ -42,6 +42,7 @@ __all__ = [
     "legendre_moments", "legendre_moments_direct", "bin_edges4", "bin_of_n2",
     "n2_grid_half", "shell_field", "triangle_list", "triangle_counts_fft",
     "triangle_counts_brute", "closed_triangle_sum_brute", "binned_triple_sums", "binned_triple_sums_full",
+    "binned_triple_sums_gemm", "triangle_counts_gemm",
     "binned_bispectrum", "shell_power", "power_multipoles", "skew_spectra", "integrated_bispectrum",
     "shot_noise_binned", "modal_modes",
     "modal_q", "modal_filter", "modal_fields", "modal_numerators", "gram_matrix",
@@ -460,6 +461,45 @@ def binned_triple_sums(spec_l: Sequence[np.ndarray], n: int, nr: int, k0: float,
         for li in range(len(specs)):
             T[li, i] = np.dot(D[li][b1], pair)
     return tris, T
+
+
+def binned_triple_sums_gemm(spec_l: Sequence[np.ndarray], n: int, nr: int, k0: float, dk: float,
+                            nb: int, tris=None):
+    """The triple sums of ``binned_triple_sums`` (eq. Standard_ell_Estim, Sec.
+    3.1), T^l(b1,b2,b3) = sum_x D^l_b1 D^0_b2 D^0_b3, with the sum over x of all
+    (b2, b3) for one (l, b1) taken as one matrix product of the field stacks:
+    T^l(b1, ., .) = (D^l_b1 * D0) D0^T, D0 = [D^0_b][x]. Same definition, a
+    library matrix product as the step, for grids where a loop of dot products
+    is slow."""
+    tris = triangle_list(nb) if tris is None else tris
+    bins = bin_of_n2(n2_grid_half(nr), k0, dk, nb)
+    specs = [_crop_spec(s, n, nr) for s in spec_l]
+    D0 = np.stack([shell_field(specs[0], bins == b, nr).ravel() for b in range(nb)])
+    need = sorted({t[0] for t in tris})
+    T = np.empty((len(specs), len(tris)))
+    for li, sp in enumerate(specs):
+        for b1 in need:
+            d1 = D0[b1] if li == 0 else shell_field(sp, bins == b1, nr).ravel()
+            G = (D0 * d1[None, :]) @ D0.T
+            for i, t in enumerate(tris):
+                if t[0] == b1:
+                    T[li, i] = G[t[1], t[2]]
+    return tris, T
+
+
+def triangle_counts_gemm(nr: int, k0: float, dk: float, nb: int):
+    """``triangle_counts_fft`` with the sums over x of all (b2, b3) for one b1
+    taken as one matrix product (I_b1 * I) I^T, I = [I_b][x]."""
+    bins = bin_of_n2(n2_grid_half(nr), k0, dk, nb)
+    I = np.stack([shell_field(np.ones((nr, nr, nr // 2 + 1)), bins == b, nr).ravel() for b in range(nb)])
+    tris = triangle_list(nb)
+    C = np.empty(len(tris))
+    G = {b1: (I * I[b1][None, :]) @ I.T / float(nr) ** 3 for b1 in range(nb)}
+    for i, (b1, b2, b3) in enumerate(tris):
+        C[i] = G[b1][b2, b3]
+    cnt = np.rint(C).astype(np.int64)
+    resid = float(np.max(np.abs(C - cnt))) if len(C) else 0.0
+    return tris, cnt, resid
 
 
 def binned_triple_sums_full(spec_l: Sequence[np.ndarray], n: int, nr: int, k0: float, dk: float,
@@ -902,20 +942,22 @@ class Geometry:
 
 
 def estimate(spec_l, geo: Geometry, nbar: Optional[float] = None, counts=None, gamma=None,
-             sn_modal=None, modal_tol: float = 0.0):
+             sn_modal=None, modal_tol: float = 0.0, gemm: bool = False):
     """Binned B_l, counts, shell power, shot-noise-subtracted B_0 and modal beta^l.
 
     modal_tol > 0 orthonormalises with ``modal_solve_pivoted`` (kept modes in
-    out["modal_kept"]); 0 uses the plain Cholesky factor of gamma."""
+    out["modal_kept"]); 0 uses the plain Cholesky factor of gamma. gemm: the
+    triple sums and counts through ``binned_triple_sums_gemm`` and
+    ``triangle_counts_gemm`` (same sums, for large grids)."""
     n, nr = geo.n, geo.nr
     tris_all = triangle_list(geo.nbins)
     if counts is None:
-        _, counts, resid = triangle_counts_fft(nr, geo.k0, geo.dk, geo.nbins)
+        _, counts, resid = (triangle_counts_gemm if gemm else triangle_counts_fft)(nr, geo.k0, geo.dk, geo.nbins)
         assert resid < 1e-3, resid
     keep = [i for i, c in enumerate(counts) if c > 0]
     tris = [tris_all[i] for i in keep]
     cnt = np.asarray(counts)[keep]
-    _, T = binned_triple_sums(spec_l, n, nr, geo.k0, geo.dk, geo.nbins, tris)
+    _, T = (binned_triple_sums_gemm if gemm else binned_triple_sums)(spec_l, n, nr, geo.k0, geo.dk, geo.nbins, tris)
     B = binned_bispectrum(T, cnt, n, nr, geo.box)
     Pbar, Nb = shell_power(spec_l[0], n, geo.k0, geo.dk, geo.nbins, geo.box)
     out = {"tris": np.array(tris, np.int64), "counts": cnt, "T": T, "B": B,

@@ -476,7 +476,9 @@ Layout layout(const bsp_plan p) {
     for (int prec = 0; prec < 3; ++prec)
       part = std::max(part, partial_bytes(p->main_rp, (int64_t)Nr * Nr * Nr, prec, sizeof(float)));
   const size_t fullc2r = align_up((size_t)N * N * (N / 2 + 1) * sizeof(float2));
-  L.scratch = std::max({fwd, inv_scratch(p, fb, sizeof(float2)), align_up(part) + align_up(1 << 20), fullc2r});
+  // the grids plus the int64 node sums of the fixed-point assignment
+  const size_t fixed = L.s_grid + align_up(assign_fixed_bytes(p->N, p->ngrid - 1));
+  L.scratch = std::max({fwd, inv_scratch(p, fb, sizeof(float2)), align_up(part) + align_up(1 << 20), fullc2r, fixed});
   L.total = L.dl + L.fields + L.T + L.small + L.scratch;
   // FP64 precompute
   const int nfp = std::max({p->nbins, p->modal ? p->nU : 0, p->modal ? 2 * p->P : 0});
@@ -1074,6 +1076,11 @@ bsp_status bsp_plan_create(bsp_plan* out, const bsp_geom* g, const bsp_modal_bas
       }
     }
     p->pfid.assign(m->pfid, m->pfid + m->pfid_len);
+    if (!(m->drop_tol >= 0.0 && m->drop_tol < 1.0)) {
+      delete p;
+      return fail(nullptr, BSP_ERR_ARG, "drop_tol must be in [0, 1)");
+    }
+    p->drop_tol = m->drop_tol;
     for (int n2 = 1; n2 <= p->n2max; ++n2)
       if (p->bin_of_n2[n2] >= 0 && !(p->pfid[n2] > 0)) {
         delete p;
@@ -1288,13 +1295,15 @@ bsp_status bsp_grid_assign(bsp_plan p, const float* ux, const float* uy, const f
                            float* grids, double* wsum) {
   if (!p || (np > 0 && (!ux || !uy || !uz)) || !grids || !wsum || np < 0) return fail(p, BSP_ERR_ARG, "null argument");
   // sorted, tiled accumulation when the grid tiles and the workspace holds the
-  // sorted catalogue; global atomics otherwise
+  // sorted catalogue; otherwise fixed-point global atomics on int64 grids in the
+  // workspace, or, without one, FP32 global atomics
   const size_t tb = assign_tiled_bytes(np, p->N);
   if (tb && p->ws && tb <= p->ws_bytes)
     HIPCHK(launch_assign_tiled(ux, uy, uz, w, np, p->N, p->g.window, p->g.interlace, 1, grids, wsum, p->d_err, p->ws,
                                p->ws_bytes, p->stream));
   else
-    HIPCHK(launch_assign(ux, uy, uz, w, np, p->N, p->g.window, p->g.interlace, grids, wsum, p->d_err, p->stream));
+    HIPCHK(launch_assign(ux, uy, uz, w, np, p->N, p->g.window, p->g.interlace, 1, grids, wsum, p->d_err, p->ws,
+                         p->ws ? p->ws_bytes : 0, p->stream));
   return BSP_OK;
 }
 
@@ -1694,8 +1703,8 @@ bsp_status bsp_bispectrum_multipoles(bsp_plan p, const float* ux, const float* u
       HIPCHK(launch_assign_tiled(ux, uy, uz, w, np, p->N, p->g.window, p->g.interlace, 0, grids, wsum, p->d_err,
                                  scr + L.s_grid, L.scratch - L.s_grid, p->stream));
     } else {
-      HIPCHK(hipMemsetAsync(grids, 0, (size_t)p->ngrid * p->N * p->N * p->N * sizeof(float), p->stream));
-      HIPCHK(launch_assign(ux, uy, uz, w, np, p->N, p->g.window, p->g.interlace, grids, wsum, p->d_err, p->stream));
+      HIPCHK(launch_assign(ux, uy, uz, w, np, p->N, p->g.window, p->g.interlace, 0, grids, wsum, p->d_err,
+                           scr + L.s_grid, L.scratch - L.s_grid, p->stream));
     }
   }
   HIPCHK(launch_scale_scalar(wsum, 1.0 / p->V, nbar, p->stream));

@@ -8,9 +8,137 @@
 //
 // Positions are grid units in [0, N); a position outside that range or not
 // finite sets bit 0 of the error word and is skipped.
+//
+// Reproducible sums: node sums and the weight sum are accumulated as 64-bit
+// integers in units of 2^-S (fixed point), so their value does not depend on
+// the order of the atomic additions. Each contribution w prod(weights) is
+// formed in FP64 and rounded once to a multiple of 2^-S; S = min(36,
+// 62 - e - l) with max|w| < 2^e and np < 2^l keeps every sum below 2^62. For
+// unit weights and positions that are multiples of 2^-12 (as the catalogue
+// generator writes them) every CIC weight product is a multiple of 2^-36, so
+// the sums are exact and each grid value is the exact node sum rounded once
+// to FP32.
 #include "bsp_internal.h"
 
 namespace bsp {
+
+// Fixed-point scale exponent from the largest |w| (as FP32 bits; unit weights
+// give 1.0) and the particle count.
+__device__ __forceinline__ int fixed_shift(unsigned wmax_bits, int64_t np) {
+  const float wmax = __uint_as_float(wmax_bits);
+  int e = 0;
+  if (wmax > 0.0f) (void)frexpf(wmax, &e);
+  const int l = 64 - __clzll((unsigned long long)(np > 0 ? np : 1));
+  const int sh = 62 - e - l;
+  return sh < 36 ? sh : 36;
+}
+
+__device__ __forceinline__ long long to_fixed(double v, int sh) { return __double2ll_rn(ldexp(v, sh)); }
+
+__device__ __forceinline__ void lds_add_fixed(long long* a, long long v) {
+  atomicAdd(reinterpret_cast<unsigned long long*>(a), (unsigned long long)v);
+}
+
+// wmax_bits[0] = max |w| over the finite weights, as FP32 bits (|w| >= 0, so the
+// integer order of the bits is the order of the values).
+__global__ __launch_bounds__(256) void k_weight_max(const float* __restrict__ w, int64_t np,
+                                                    unsigned* __restrict__ wmax_bits) {
+  unsigned m = 0u;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
+    const float a = fabsf(w[i]);
+    if (a == a && a <= 3.4e38f) m = max(m, __float_as_uint(a));
+  }
+  for (int off = 32; off > 0; off >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, off));
+  if ((threadIdx.x & 63) == 0 && m) atomicMax(wmax_bits, m);
+}
+
+// Global fixed-point assignment into int64 grids (zeroed by the caller) and
+// a fixed-point weight sum wsum_fx[0].
+template <int WINDOW>
+__global__ __launch_bounds__(256) void k_assign_fixed(const float* __restrict__ ux, const float* __restrict__ uy,
+                                                      const float* __restrict__ uz, const float* __restrict__ w,
+                                                      int64_t np, int n, int interlace,
+                                                      const unsigned* __restrict__ wmax_bits,
+                                                      unsigned long long* __restrict__ gfx,
+                                                      unsigned long long* __restrict__ wsum_fx,
+                                                      int32_t* __restrict__ err) {
+  const int64_t n3 = (int64_t)n * n * n;
+  const float fn = (float)n;
+  const int sh = fixed_shift(*wmax_bits, np);
+  long long acc = 0;
+  int bad = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
+    const float x = ux[i], y = uy[i], z = uz[i];
+    const float wt = w ? w[i] : 1.0f;
+    if (!(x >= 0.0f && x < fn && y >= 0.0f && y < fn && z >= 0.0f && z < fn && wt == wt)) {
+      bad = 1;
+      continue;
+    }
+    acc += to_fixed((double)wt, sh);
+    for (int s = 0; s <= interlace; ++s) {
+      float vx = x, vy = y, vz = z;
+      if (s) {
+        vx += 0.5f;
+        vy += 0.5f;
+        vz += 0.5f;
+        if (vx >= fn) vx -= fn;
+        if (vy >= fn) vy -= fn;
+        if (vz >= fn) vz -= fn;
+      }
+      unsigned long long* g = gfx + (int64_t)s * n3;
+      if constexpr (WINDOW == 0) {
+        int ix = (int)floorf(vx + 0.5f), iy = (int)floorf(vy + 0.5f), iz = (int)floorf(vz + 0.5f);
+        if (ix >= n) ix -= n;
+        if (iy >= n) iy -= n;
+        if (iz >= n) iz -= n;
+        atomicAdd(g + ((int64_t)ix * n + iy) * n + iz, (unsigned long long)to_fixed((double)wt, sh));
+      } else {
+        const int ix = (int)floorf(vx), iy = (int)floorf(vy), iz = (int)floorf(vz);
+        const float dx = vx - (float)ix, dy = vy - (float)iy, dz = vz - (float)iz;
+        const int jx = (ix + 1 == n) ? 0 : ix + 1;
+        const int jy = (iy + 1 == n) ? 0 : iy + 1;
+        const int jz = (iz + 1 == n) ? 0 : iz + 1;
+        const double wx[2] = {1.0 - (double)dx, (double)dx}, wy[2] = {1.0 - (double)dy, (double)dy},
+                     wz[2] = {1.0 - (double)dz, (double)dz};
+        const int64_t px[2] = {(int64_t)ix * n * n, (int64_t)jx * n * n};
+        const int64_t py[2] = {(int64_t)iy * n, (int64_t)jy * n};
+        const int pz[2] = {iz, jz};
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            const double wab = (double)wt * wx[a] * wy[b];
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+              atomicAdd(g + px[a] + py[b] + pz[c], (unsigned long long)to_fixed(wab * wz[c], sh));
+          }
+      }
+    }
+  }
+  __shared__ long long red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && red[0] != 0) atomicAdd(wsum_fx, (unsigned long long)red[0]);
+  if (bad) atomicOr(err, 1);
+}
+
+// grids[i] (+)= gfx[i] 2^-S rounded to FP32; block 0 also adds the weight sum.
+__global__ __launch_bounds__(256) void k_fixed_to_float(const unsigned long long* __restrict__ gfx, int64_t count,
+                                                        int64_t np, const unsigned* __restrict__ wmax_bits,
+                                                        const unsigned long long* __restrict__ wsum_fx,
+                                                        int accumulate, float* __restrict__ grids,
+                                                        double* __restrict__ wsum) {
+  const int sh = fixed_shift(*wmax_bits, np);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
+    const float v = (float)ldexp((double)(long long)gfx[i], -sh);
+    grids[i] = accumulate ? grids[i] + v : v;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) wsum[0] += ldexp((double)(long long)wsum_fx[0], -sh);
+}
 
 template <int WINDOW>
 __global__ __launch_bounds__(256) void k_assign(const float* __restrict__ ux, const float* __restrict__ uy,
@@ -99,9 +227,12 @@ __global__ __launch_bounds__(256) void k_tile_count(const float* __restrict__ ux
                                                     const float* __restrict__ uz, const float* __restrict__ w,
                                                     int64_t np, int n, int ntx, int ntz, int tz,
                                                     int32_t* __restrict__ count, int32_t* __restrict__ rank,
-                                                    double* __restrict__ wsum, int32_t* __restrict__ err) {
+                                                    const unsigned* __restrict__ wmax_bits,
+                                                    unsigned long long* __restrict__ wsum_fx,
+                                                    int32_t* __restrict__ err) {
   const float fn = (float)n;
-  double acc = 0.0;
+  const int sh = fixed_shift(*wmax_bits, np);
+  long long acc = 0;
   int bad = 0;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
     const float x = ux[i], y = uy[i], z = uz[i];
@@ -110,18 +241,18 @@ __global__ __launch_bounds__(256) void k_tile_count(const float* __restrict__ ux
       bad = 1;
       continue;
     }
-    acc += (double)wt;
+    acc += to_fixed((double)wt, sh);
     const int key = (((int)x / TXY) * ntx + (int)y / TXY) * ntz + (int)z / tz;
     rank[i] = atomicAdd(count + key, 1);
   }
-  __shared__ double red[256];
+  __shared__ long long red[256];
   red[threadIdx.x] = acc;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
     if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x == 0 && red[0] != 0.0) unsafeAtomicAdd(wsum, red[0]);
+  if (threadIdx.x == 0 && red[0] != 0) atomicAdd(wsum_fx, (unsigned long long)red[0]);
   if (bad) atomicOr(err, 1);
 }
 
@@ -169,13 +300,17 @@ __global__ __launch_bounds__(256) void k_tile_scatter(const float* __restrict__ 
 template <int WINDOW, int TZ>
 __global__ __launch_bounds__(256) void k_assign_tiles(const float4* __restrict__ sorted,
                                                       const int32_t* __restrict__ offs, int n, int ntx, int ntz,
-                                                      int interlace, int accumulate, float* __restrict__ grids) {
+                                                      int interlace, int accumulate, int64_t np,
+                                                      const unsigned* __restrict__ wmax_bits,
+                                                      const unsigned long long* __restrict__ wsum_fx,
+                                                      float* __restrict__ grids, double* __restrict__ wsum) {
   constexpr int CELLS = TXY * TXY * TZ;
-  __shared__ float acc[2][CELLS];
+  __shared__ long long acc[2][CELLS];
   const int tile = blockIdx.x;
   const int tzi = tile % ntz, txy = tile / ntz, tyi = txy % ntx, txi = txy / ntx;
   const int x0 = txi * TXY, y0 = tyi * TXY, z0 = tzi * TZ;
-  for (int i = threadIdx.x; i < 2 * CELLS; i += 256) (&acc[0][0])[i] = 0.0f;
+  const int sh = fixed_shift(*wmax_bits, np);
+  for (int i = threadIdx.x; i < 2 * CELLS; i += 256) (&acc[0][0])[i] = 0;
   __syncthreads();
   const float fn = (float)n;
   for (int nb = 0; nb < 8; ++nb) {
@@ -210,11 +345,12 @@ __global__ __launch_bounds__(256) void k_assign_tiles(const float4* __restrict__
           if (iz >= n) iz -= n;
           const int lx = ix - x0, ly = iy - y0, lz = iz - z0;
           if ((unsigned)lx < (unsigned)TXY && (unsigned)ly < (unsigned)TXY && (unsigned)lz < (unsigned)TZ)
-            atomicAdd(&acc[s][(lx * TXY + ly) * TZ + lz], pt.w);
+            lds_add_fixed(&acc[s][(lx * TXY + ly) * TZ + lz], to_fixed((double)pt.w, sh));
         } else {
           const int ix = (int)floorf(vx), iy = (int)floorf(vy), iz = (int)floorf(vz);
           const float dx = vx - (float)ix, dy = vy - (float)iy, dz = vz - (float)iz;
-          const float wx[2] = {1.0f - dx, dx}, wy[2] = {1.0f - dy, dy}, wz[2] = {1.0f - dz, dz};
+          const double wx[2] = {1.0 - (double)dx, (double)dx}, wy[2] = {1.0 - (double)dy, (double)dy},
+                       wz[2] = {1.0 - (double)dz, (double)dz};
 #pragma unroll
           for (int a = 0; a < 2; ++a) {
             int cx = ix + a;
@@ -227,13 +363,14 @@ __global__ __launch_bounds__(256) void k_assign_tiles(const float4* __restrict__
               if (cy == n) cy = 0;
               const int ly = cy - y0;
               if ((unsigned)ly >= (unsigned)TXY) continue;
-              const float wab = pt.w * wx[a] * wy[b];
+              const double wab = (double)pt.w * wx[a] * wy[b];
 #pragma unroll
               for (int c = 0; c < 2; ++c) {
                 int cz = iz + c;
                 if (cz == n) cz = 0;
                 const int lz = cz - z0;
-                if ((unsigned)lz < (unsigned)TZ) atomicAdd(&acc[s][(lx * TXY + ly) * TZ + lz], wab * wz[c]);
+                if ((unsigned)lz < (unsigned)TZ)
+                  lds_add_fixed(&acc[s][(lx * TXY + ly) * TZ + lz], to_fixed(wab * wz[c], sh));
               }
             }
           }
@@ -250,7 +387,8 @@ __global__ __launch_bounds__(256) void k_assign_tiles(const float4* __restrict__
       const int c = v * 4;
       const int lz = c % TZ, ly = (c / TZ) % TXY, lx = c / (TZ * TXY);
       float4* dst = reinterpret_cast<float4*>(g + ((int64_t)(x0 + lx) * n + (y0 + ly)) * n + z0 + lz);
-      float4 val = make_float4(acc[s][c], acc[s][c + 1], acc[s][c + 2], acc[s][c + 3]);
+      float4 val = make_float4((float)ldexp((double)acc[s][c], -sh), (float)ldexp((double)acc[s][c + 1], -sh),
+                               (float)ldexp((double)acc[s][c + 2], -sh), (float)ldexp((double)acc[s][c + 3], -sh));
       if (accumulate) {
         const float4 old = *dst;
         val.x += old.x;
@@ -262,6 +400,8 @@ __global__ __launch_bounds__(256) void k_assign_tiles(const float4* __restrict__
       __builtin_nontemporal_store(F4{val.x, val.y, val.z, val.w}, reinterpret_cast<F4*>(dst));
     }
   }
+  // the count kernel, earlier on the stream, has finished the weight sum
+  if (tile == 0 && threadIdx.x == 0) wsum[0] += ldexp((double)(long long)wsum_fx[0], -sh);
 }
 
 static int tile_tz(int n) {
@@ -281,12 +421,33 @@ bool assign_tiled_preferred(int n) {
   return tz && (int64_t)(n / TXY) * (n / TXY) * (n / tz) >= 512;
 }
 
+// 256 bytes at the head of an assignment scratch: the largest |w| (FP32 bits)
+// and the fixed-point weight sum.
+constexpr size_t kHead = 256;
+
 size_t assign_tiled_bytes(int64_t np, int n) {
   const int tz = tile_tz(n);
   if (!tz || np <= 0 || np > (int64_t)INT32_MAX) return 0;
   const int64_t nt = (int64_t)(n / TXY) * (n / TXY) * (n / tz);
-  return align256((size_t)np * sizeof(float4)) + 2 * align256((size_t)(nt + 1) * sizeof(int32_t)) +
+  return kHead + align256((size_t)np * sizeof(float4)) + 2 * align256((size_t)(nt + 1) * sizeof(int32_t)) +
          align256((size_t)np * sizeof(int32_t));
+}
+
+size_t assign_fixed_bytes(int n, int interlace) { return kHead + (size_t)(1 + interlace) * n * n * n * 8; }
+
+// Head of an assignment scratch: zero the weight sum and set the largest |w|
+// (1.0 for unit weights, else from the weights).
+static hipError_t fixed_head(const float* w, int64_t np, unsigned* head, hipStream_t s) {
+  hipError_t e = hipMemsetAsync(head, 0, kHead, s);
+  if (e != hipSuccess) return e;
+  if (!w) {
+    const unsigned one = 0x3f800000u;
+    return hipMemcpyAsync(head, &one, sizeof(one), hipMemcpyHostToDevice, s);
+  }
+  int64_t blocks = (np + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_weight_max, dim3((unsigned)blocks), dim3(256), 0, s, w, np, head);
+  return hipGetLastError();
 }
 
 hipError_t launch_assign_tiled(const float* ux, const float* uy, const float* uz, const float* w, int64_t np, int n,
@@ -298,32 +459,66 @@ hipError_t launch_assign_tiled(const float* ux, const float* uy, const float* uz
     return hipErrorInvalidValue;
   const int ntx = n / TXY, ntz = n / tz;
   const int nt = ntx * ntx * ntz;
-  char* base = reinterpret_cast<char*>(scratch);
+  unsigned* head = reinterpret_cast<unsigned*>(scratch);
+  unsigned long long* wsum_fx = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(scratch) + 8);
+  char* base = reinterpret_cast<char*>(scratch) + kHead;
   float4* sorted = reinterpret_cast<float4*>(base);
   int32_t* count = reinterpret_cast<int32_t*>(base + align256((size_t)np * sizeof(float4)));
   int32_t* offs = count + align256((size_t)(nt + 1) * sizeof(int32_t)) / sizeof(int32_t);
   int32_t* rank = offs + align256((size_t)(nt + 1) * sizeof(int32_t)) / sizeof(int32_t);
   hipError_t e = hipMemsetAsync(count, 0, (size_t)nt * sizeof(int32_t), s);
   if (e != hipSuccess) return e;
+  e = fixed_head(w, np, head, s);
+  if (e != hipSuccess) return e;
   int64_t blocks = (np + 255) / 256;
   if (blocks > 16384) blocks = 16384;
   hipLaunchKernelGGL(k_tile_count, dim3((unsigned)blocks), dim3(256), 0, s, ux, uy, uz, w, np, n, ntx, ntz, tz, count,
-                     rank, wsum, err);
+                     rank, head, wsum_fx, err);
   hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, count, nt, offs);
   hipLaunchKernelGGL(k_tile_scatter, dim3((unsigned)blocks), dim3(256), 0, s, ux, uy, uz, w, np, n, ntx, ntz, tz,
                      offs, rank, sorted);
-#define TCASE(WIN, TZV)                                                                                         if (window == WIN && tz == TZV) {                                                                               hipLaunchKernelGGL((k_assign_tiles<WIN, TZV>), dim3((unsigned)nt), dim3(256), 0, s, sorted, offs, n, ntx,                        ntz, interlace, accumulate, grids);                                                        return hipGetLastError();                                                                                   }
+#define TCASE(WIN, TZV)                                                                                         if (window == WIN && tz == TZV) {                                                                               hipLaunchKernelGGL((k_assign_tiles<WIN, TZV>), dim3((unsigned)nt), dim3(256), 0, s, sorted, offs, n, ntx,                        ntz, interlace, accumulate, np, head, wsum_fx, grids, wsum);                                                        return hipGetLastError();                                                                                   }
   TCASE(0, 64) TCASE(0, 32) TCASE(0, 16) TCASE(0, 8) TCASE(1, 64) TCASE(1, 32) TCASE(1, 16) TCASE(1, 8)
 #undef TCASE
   return hipErrorInvalidValue;
 }
 
 hipError_t launch_assign(const float* ux, const float* uy, const float* uz, const float* w, int64_t np,
-                         int n, int window, int interlace, float* grids, double* wsum, int32_t* err,
-                         hipStream_t s) {
-  if (np <= 0) return hipSuccess;
+                         int n, int window, int interlace, int accumulate, float* grids, double* wsum, int32_t* err,
+                         void* scratch, size_t scratch_bytes, hipStream_t s) {
+  const int64_t count = (int64_t)(1 + interlace) * n * n * n;
+  if (np <= 0) {
+    if (accumulate) return hipSuccess;
+    return hipMemsetAsync(grids, 0, (size_t)count * sizeof(float), s);
+  }
   int64_t blocks = (np + 255) / 256;
   if (blocks > 65536) blocks = 65536;
+  if (scratch && scratch_bytes >= assign_fixed_bytes(n, interlace)) {
+    // fixed point: int64 node sums, converted (and added) once
+    unsigned* head = reinterpret_cast<unsigned*>(scratch);
+    unsigned long long* wsum_fx = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(scratch) + 8);
+    unsigned long long* gfx = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(scratch) + kHead);
+    hipError_t e = hipMemsetAsync(gfx, 0, (size_t)count * 8, s);
+    if (e != hipSuccess) return e;
+    e = fixed_head(w, np, head, s);
+    if (e != hipSuccess) return e;
+    if (window == 0)
+      hipLaunchKernelGGL((k_assign_fixed<0>), dim3((unsigned)blocks), dim3(256), 0, s, ux, uy, uz, w, np, n, interlace,
+                         head, gfx, wsum_fx, err);
+    else
+      hipLaunchKernelGGL((k_assign_fixed<1>), dim3((unsigned)blocks), dim3(256), 0, s, ux, uy, uz, w, np, n, interlace,
+                         head, gfx, wsum_fx, err);
+    int64_t cb = (count + 255) / 256;
+    if (cb > 16384) cb = 16384;
+    hipLaunchKernelGGL(k_fixed_to_float, dim3((unsigned)cb), dim3(256), 0, s, gfx, count, np, head, wsum_fx,
+                       accumulate, grids, wsum);
+    return hipGetLastError();
+  }
+  // no scratch: FP32 atomics on the grids (summation order varies between runs)
+  if (!accumulate) {
+    hipError_t e = hipMemsetAsync(grids, 0, (size_t)count * sizeof(float), s);
+    if (e != hipSuccess) return e;
+  }
   if (window == 0)
     hipLaunchKernelGGL((k_assign<0>), dim3((unsigned)blocks), dim3(256), 0, s, ux, uy, uz, w, np, n,
                        interlace, grids, wsum, err);

@@ -105,10 +105,15 @@ hipError_t launch_inv_z_f64(int n, const double2* in, double* out, int nfields, 
                             int64_t in_field, int64_t out_field, const double2* tw, hipStream_t s);
 bool fft_size_supported(int n);
 
-// Assignment (assign.hip).
+// Assignment (assign.hip). Node and weight sums are order independent (64-bit
+// fixed point) whenever scratch is given: at least assign_fixed_bytes for the
+// global-atomic kernel, assign_tiled_bytes for the tiled one. Without scratch
+// launch_assign falls back to FP32 atomics. accumulate = 0 overwrites the
+// grids, 1 adds to them; wsum is always added to.
+size_t assign_fixed_bytes(int n, int interlace);
 hipError_t launch_assign(const float* ux, const float* uy, const float* uz, const float* w,
-                         int64_t np, int n, int window, int interlace, float* grids,
-                         double* wsum, int32_t* err, hipStream_t s);
+                         int64_t np, int n, int window, int interlace, int accumulate, float* grids,
+                         double* wsum, int32_t* err, void* scratch, size_t scratch_bytes, hipStream_t s);
 // Tiled assignment (no global atomics on the grids): bytes of scratch it needs
 // for np particles on an N^3 grid, 0 when N does not tile; accumulate = 0
 // overwrites the grids, 1 adds to them. Returns hipErrorInvalidValue when N
@@ -151,7 +156,9 @@ hipError_t launch_reduce(int prec, const float* fields, const ReduceDesc& d, flo
                          hipStream_t s);
 hipError_t launch_reduce_f64(const double* fields, const ReduceDesc& d, double* partials,
                              hipStream_t s);
-hipError_t launch_combine_partials(const void* partials, int is_f64, const ReduceDesc& d,
+// Adds the chunk partials in a fixed order (reproducible T); overwrites part
+// of the partials.
+hipError_t launch_combine_partials(void* partials, int is_f64, const ReduceDesc& d,
                                    int npairs, int nthirds, double* T, double tscale,
                                    hipStream_t s);
 int reduce_waves_per_group();

@@ -164,28 +164,72 @@ __global__ __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
   wt.store(d, partials, chunk, q, r16);
 }
 
-// Sum chunk partials in FP64 and scatter to T[pair][third] (T zeroed before).
+// Sum chunk partials in FP64 and write T[pair][third] (entries outside every
+// tile are left as they are; the caller zeroes T). The sums run in a fixed
+// order, so T does not change between runs: block (tile, y) adds its range of
+// chunks [y cpb, end) in order; with one range per tile it writes T directly,
+// otherwise it parks its 256 FP64 sums in the partial slots of its own first
+// two chunks (which nobody reads again) and k_combine_ranges adds the ranges
+// in order. Every range holds at least cpb >= 2 chunks except when there is
+// a single range.
 template <typename PT>
-__global__ __launch_bounds__(256) void k_combine(const PT* __restrict__ partials, int nchunks, int ntiles,
-                                                 int chunks_per_block, const int32_t* __restrict__ tile_rc,
-                                                 int npairs, int nthirds, const int32_t* __restrict__ pair_a,
-                                                 const int32_t* __restrict__ pair_b,
-                                                 const int32_t* __restrict__ third, const float* __restrict__ scale,
-                                                 double tscale, double* __restrict__ T) {
-  const int tile = blockIdx.x;
-  const int e = threadIdx.x;
-  const int c0 = blockIdx.y * chunks_per_block;
-  int c1 = c0 + chunks_per_block;
-  if (c1 > nchunks) c1 = nchunks;
-  double s = 0.0;
-  for (int c = c0; c < c1; ++c) s += (double)partials[((int64_t)c * ntiles + tile) * 256 + e];
+__device__ __forceinline__ double* park_slot(PT* partials, int c0, int ntiles, int tile, int e) {
+  if constexpr (sizeof(PT) == 8) {
+    return reinterpret_cast<double*>(partials + ((int64_t)c0 * ntiles + tile) * 256) + e;
+  } else {
+    const int c = c0 + (e >> 7);
+    return reinterpret_cast<double*>(partials + ((int64_t)c * ntiles + tile) * 256) + (e & 127);
+  }
+}
+
+template <typename PT>
+__device__ __forceinline__ void write_t(double s, int tile, int e, const int32_t* __restrict__ tile_rc, int npairs,
+                                        int nthirds, const int32_t* __restrict__ pair_a,
+                                        const int32_t* __restrict__ pair_b, const int32_t* __restrict__ third,
+                                        const float* __restrict__ scale, double tscale, double* __restrict__ T) {
   const int pr = tile_rc[2 * tile] * 16 + e / 16;
   const int th = tile_rc[2 * tile + 1] * 16 + e % 16;
   if (pr < npairs && th < nthirds) {
     double f = tscale;
     if (scale) f /= (double)scale[pair_a[pr]] * (double)scale[pair_b[pr]] * (double)scale[third[th]];
-    unsafeAtomicAdd(&T[(int64_t)pr * nthirds + th], s * f);
+    T[(int64_t)pr * nthirds + th] = s * f;
   }
+}
+
+template <typename PT>
+__global__ __launch_bounds__(256) void k_combine(PT* __restrict__ partials, int nchunks, int ntiles, int cpb, int nranges,
+                                                 const int32_t* __restrict__ tile_rc, int npairs, int nthirds,
+                                                 const int32_t* __restrict__ pair_a, const int32_t* __restrict__ pair_b,
+                                                 const int32_t* __restrict__ third, const float* __restrict__ scale,
+                                                 double tscale, double* __restrict__ T) {
+  const int tile = blockIdx.x;
+  const int e = threadIdx.x;
+  const int y = blockIdx.y;
+  const int c0 = y * cpb;
+  const int c1 = (y == nranges - 1) ? nchunks : c0 + cpb;
+  double s = 0.0;
+  for (int c = c0; c < c1; ++c) s += (double)partials[((int64_t)c * ntiles + tile) * 256 + e];
+  if (nranges == 1) {
+    write_t<PT>(s, tile, e, tile_rc, npairs, nthirds, pair_a, pair_b, third, scale, tscale, T);
+    return;
+  }
+  __syncthreads();  // every thread has read its values before the slots are overwritten
+  *park_slot(partials, c0, ntiles, tile, e) = s;
+}
+
+template <typename PT>
+__global__ __launch_bounds__(256) void k_combine_ranges(PT* __restrict__ partials, int ntiles, int cpb, int nranges,
+                                                        const int32_t* __restrict__ tile_rc, int npairs, int nthirds,
+                                                        const int32_t* __restrict__ pair_a,
+                                                        const int32_t* __restrict__ pair_b,
+                                                        const int32_t* __restrict__ third,
+                                                        const float* __restrict__ scale, double tscale,
+                                                        double* __restrict__ T) {
+  const int tile = blockIdx.x;
+  const int e = threadIdx.x;
+  double s = 0.0;
+  for (int y = 0; y < nranges; ++y) s += *park_slot(partials, y * cpb, ntiles, tile, e);
+  write_t<PT>(s, tile, e, tile_rc, npairs, nthirds, pair_a, pair_b, third, scale, tscale, T);
 }
 
 int reduce_waves_per_group() { return WAVES; }
@@ -247,18 +291,26 @@ hipError_t launch_reduce_f64(const double* fields, const ReduceDesc& d, double* 
   return reduce_dispatch<3>(fields, d, partials, s);
 }
 
-hipError_t launch_combine_partials(const void* partials, int is_f64, const ReduceDesc& d, int npairs, int nthirds,
+hipError_t launch_combine_partials(void* partials, int is_f64, const ReduceDesc& d, int npairs, int nthirds,
                                    double* T, double tscale, hipStream_t s) {
   const int cpb = 64;
-  dim3 grid((unsigned)d.ntiles, (unsigned)((d.nchunks + cpb - 1) / cpb));
-  if (is_f64)
-    hipLaunchKernelGGL((k_combine<double>), grid, dim3(256), 0, s, reinterpret_cast<const double*>(partials),
-                       d.nchunks, d.ntiles, cpb, d.tile_rc, npairs, nthirds, d.pair_a, d.pair_b, d.third, d.scale,
-                       tscale, T);
-  else
-    hipLaunchKernelGGL((k_combine<float>), grid, dim3(256), 0, s, reinterpret_cast<const float*>(partials),
-                       d.nchunks, d.ntiles, cpb, d.tile_rc, npairs, nthirds, d.pair_a, d.pair_b, d.third, d.scale,
-                       tscale, T);
+  const int nranges = d.nchunks > cpb ? d.nchunks / cpb : 1;
+  dim3 grid((unsigned)d.ntiles, (unsigned)nranges);
+  if (is_f64) {
+    double* pp = reinterpret_cast<double*>(partials);
+    hipLaunchKernelGGL((k_combine<double>), grid, dim3(256), 0, s, pp, d.nchunks, d.ntiles, cpb, nranges, d.tile_rc,
+                       npairs, nthirds, d.pair_a, d.pair_b, d.third, d.scale, tscale, T);
+    if (nranges > 1)
+      hipLaunchKernelGGL((k_combine_ranges<double>), dim3((unsigned)d.ntiles), dim3(256), 0, s, pp, d.ntiles, cpb,
+                         nranges, d.tile_rc, npairs, nthirds, d.pair_a, d.pair_b, d.third, d.scale, tscale, T);
+  } else {
+    float* pp = reinterpret_cast<float*>(partials);
+    hipLaunchKernelGGL((k_combine<float>), grid, dim3(256), 0, s, pp, d.nchunks, d.ntiles, cpb, nranges, d.tile_rc,
+                       npairs, nthirds, d.pair_a, d.pair_b, d.third, d.scale, tscale, T);
+    if (nranges > 1)
+      hipLaunchKernelGGL((k_combine_ranges<float>), dim3((unsigned)d.ntiles), dim3(256), 0, s, pp, d.ntiles, cpb,
+                         nranges, d.tile_rc, npairs, nthirds, d.pair_a, d.pair_b, d.third, d.scale, tscale, T);
+  }
   return hipGetLastError();
 }
 

@@ -63,32 +63,62 @@ def test_fft_r2c_c2r_against_oracle(n):
 # ---------------------------------------------------------------- assignment
 
 def _tiled_assign_bytes(npart, n):
-    """Scratch the sorted, tiled assignment needs (8 x 8 x tz tiles)."""
+    """Scratch the sorted, tiled assignment needs (8 x 8 x tz tiles, a 256-byte head)."""
     tz = next(t for t in (64, 32, 16, 8) if n % t == 0 and n // t >= 2)
     nt = (n // 8) ** 2 * (n // tz)
     up = lambda b: (b + 255) // 256 * 256
-    return up(npart * 16) + 2 * up((nt + 1) * 4) + up(npart * 4)
+    return 256 + up(npart * 16) + 2 * up((nt + 1) * 4) + up(npart * 4)
 
 
-@pytest.mark.parametrize("n,window,interlace,tiled", [
-    (32, 1, 0, False), (32, 1, 1, False), (32, 0, 1, False),
-    (16, 1, 1, True), (32, 1, 0, True), (32, 1, 1, True), (32, 0, 1, True), (64, 1, 1, True), (96, 1, 1, True),
-    (96, 0, 0, True)])
-def test_grid_assign_against_oracle(n, window, interlace, tiled):
-    """Global-atomic assignment (no workspace) and the sorted, tiled one (with a
-    workspace) against the oracle, adding into grids that already hold 0.25;
-    particles also sit on tile edges and just below N (wrap-around)."""
-    say("assign", n, window, interlace, "tiled" if tiled else "atomic")
-    r = rng(7 + n)
-    npart = 20000 if n >= 32 else 3000
+def _fixed_assign_bytes(n, interlace):
+    """Scratch of the fixed-point global-atomic assignment: int64 grids and a 256-byte head."""
+    return 256 + (1 + interlace) * n ** 3 * 8
+
+
+def _assign_plan(n, window, interlace, mode, npart):
+    """Plan whose workspace selects the assignment kernel: 'atomic' none (FP32
+    global atomics), 'fixed' room for the int64 grids but not for the sorted
+    catalogue (fixed-point global atomics), 'tiled' the full workspace."""
+    plan = B.Plan(n=n, box=100.0, nbins=1, k0=1.0, dk=1.0, window=window, interlace=interlace,
+                  workspace=(mode == "tiled"))
+    if mode == "tiled":
+        assert B.bsp_workspace_size(plan.handle) >= _tiled_assign_bytes(npart, n)
+    if mode == "fixed":
+        nb = _fixed_assign_bytes(n, interlace)
+        assert nb < _tiled_assign_bytes(npart, n)
+        plan.ws = torch.empty(nb, dtype=torch.uint8, device=DEV)
+        B.bsp_set_workspace(plan.handle, plan.ws, nb)
+    return plan
+
+
+def _edge_catalogue(n, npart, seed):
+    r = rng(seed)
     u = [C.quantise_grid_units(r.uniform(0, n, npart), n) for _ in range(3)]
     edges = np.array([0.0, 7.999755859375, 8.0, n - 2.0 ** -12, n - 0.5, 15.999755859375], np.float32)
     for a in range(3):
         u[a][:36] = np.tile(edges, 6)[(np.arange(36) * (a + 1)) % 36]
+    return u, r
+
+
+@pytest.mark.parametrize("n,window,interlace,mode", [
+    (32, 1, 0, "atomic"), (32, 1, 1, "atomic"), (32, 0, 1, "atomic"),
+    (16, 1, 1, "fixed"), (32, 1, 1, "fixed"), (32, 0, 1, "fixed"), (64, 1, 0, "fixed"),
+    (16, 1, 1, "tiled"), (32, 1, 0, "tiled"), (32, 1, 1, "tiled"), (32, 0, 1, "tiled"), (64, 1, 1, "tiled"),
+    (96, 1, 1, "tiled"), (96, 0, 0, "tiled"), (128, 1, 1, "tiled"), (128, 0, 1, "tiled")])
+def test_grid_assign_against_oracle(n, window, interlace, mode):
+    """The three assignment kernels against the oracle, adding into grids that
+    already hold 0.25; particles also sit on tile edges and just below N
+    (wrap-around). 128 points a side runs the 8 x 8 x 64 tiles.
+    Weighted catalogue: FP32 atomics within their summation bound; the
+    fixed-point kernels within 2 ulp (one rounding of the node sum, one of the
+    addition). Unit weights, positions on multiples of 2^-12: the fixed-point
+    node sums are exact, so each node is bit for bit float32(0.25 + float32(rho))
+    of the oracle's rho, and the weight sum is the particle count."""
+    npart = {"atomic": 20000, "tiled": 20000, "fixed": 20 * n ** 3 // 16 + 4000}[mode]
+    say("assign", n, window, interlace, mode, npart)
+    u, r = _edge_catalogue(n, npart, 7 + n)
     w = r.uniform(0.5, 1.5, npart).astype(np.float32)
-    plan = B.Plan(n=n, box=100.0, nbins=1, k0=1.0, dk=1.0, window=window, interlace=interlace, workspace=tiled)
-    if tiled:
-        assert B.bsp_workspace_size(plan.handle) >= _tiled_assign_bytes(npart, n)
+    plan = _assign_plan(n, window, interlace, mode, npart)
     grids = torch.full((1 + interlace, n, n, n), 0.25, dtype=torch.float32, device=DEV)
     wsum = torch.zeros(1, dtype=torch.float64, device=DEV)
     B.bsp_grid_assign(plan.handle, dev(u[0]), dev(u[1]), dev(u[2]), dev(w), u[0].size, grids, wsum)
@@ -96,8 +126,52 @@ def test_grid_assign_against_oracle(n, window, interlace, tiled):
     g = grids.cpu().numpy()
     for s in range(1 + interlace):
         ref = O.assign(*u, n, w.astype(np.float64), window, 0.5 * s) + 0.25
-        assert np.max(np.abs(g[s] - ref)) < 2e-6 * np.max(ref) + 1e-6, s
+        if mode == "atomic":
+            assert np.max(np.abs(g[s] - ref)) < 2e-6 * np.max(ref) + 1e-6, s
+        else:
+            r32 = ref.astype(np.float32)
+            assert np.all(np.abs(g[s] - r32) <= 2 * np.spacing(np.abs(r32))), s
     assert abs(wsum.item() - float(w.astype(np.float64).sum())) < 1e-6 * w.sum()
+    if mode == "atomic":
+        plan.close()
+        return
+    # unit weights: exact
+    for rep in range(2):
+        grids2 = torch.full((1 + interlace, n, n, n), 0.25, dtype=torch.float32, device=DEV)
+        wsum2 = torch.zeros(1, dtype=torch.float64, device=DEV)
+        B.bsp_grid_assign(plan.handle, dev(u[0]), dev(u[1]), dev(u[2]), None, u[0].size, grids2, wsum2)
+        plan.sync()
+        g2 = grids2.cpu().numpy()
+        for s in range(1 + interlace):
+            rho = O.assign(*u, n, None, window, 0.5 * s)
+            expect = np.float32(0.25) + rho.astype(np.float32)
+            assert np.array_equal(g2[s], expect), (rep, s, int(np.sum(g2[s] != expect)))
+        assert wsum2.item() == float(npart)
+    plan.close()
+
+
+@pytest.mark.parametrize("n,mode", [(32, "fixed"), (64, "tiled"), (128, "tiled")])
+def test_grid_assign_reproducible(n, mode):
+    """The fixed-point kernels give bit-identical grids and weight sums on
+    repeated runs of a weighted, clustered catalogue (where FP32 atomics in
+    varying order would differ in the last bits)."""
+    say("assign-repro", n, mode)
+    npart = 20 * n ** 3 // 16 + 4000 if mode == "fixed" else 200000
+    r = rng(300 + n)
+    hot = npart // 2
+    u = [C.quantise_grid_units(np.concatenate([r.uniform(5.0, 9.0, hot), r.uniform(0, n, npart - hot)]), n)
+         for _ in range(3)]
+    w = r.uniform(0.1, 3.0, npart).astype(np.float32)
+    plan = _assign_plan(n, 1, 1, mode, npart)
+    out = []
+    for rep in range(3):
+        grids = torch.zeros((2, n, n, n), dtype=torch.float32, device=DEV)
+        wsum = torch.zeros(1, dtype=torch.float64, device=DEV)
+        B.bsp_grid_assign(plan.handle, dev(u[0]), dev(u[1]), dev(u[2]), dev(w), npart, grids, wsum)
+        plan.sync()
+        out.append((grids.cpu().numpy(), wsum.item()))
+    for g, ws in out[1:]:
+        assert np.array_equal(g, out[0][0]) and ws == out[0][1]
     plan.close()
 
 
@@ -133,11 +207,11 @@ def test_grid_assign_tiled_clustered_with_invalid_particles():
     wv = w[ok].astype(np.float64)
     for s in range(2):
         ref = O.assign(u[0][ok], u[1][ok], u[2][ok], n, wv, 1, 0.5 * s)
-        # FP32 sums of m non-negative terms in any order (the workgroup adds in
-        # atomic order) stay within (m - 1) u of the exact sum, u = 2^-24, and
-        # each term carries 3 product roundings: bound each node by (m + 4) u
-        # times its value, m its number of CIC contributions (tight on sparse
-        # nodes, where a misplaced particle would show)
+        # the tiled kernel rounds each of a node's m CIC contributions once to a
+        # multiple of 2^-36 (fixed point, 2^-37 each at most) and the exact sum
+        # once to FP32: bound each node by (m + 4) u times its value plus
+        # m 2^-37, u = 2^-24 (tight on sparse nodes, where a misplaced particle
+        # would show)
         m = np.zeros(n ** 3)
         fl = [np.floor(a[ok].astype(np.float64) + 0.5 * s).astype(np.int64) for a in u]
         for dx in (0, 1):
@@ -145,7 +219,7 @@ def test_grid_assign_tiled_clustered_with_invalid_particles():
                 for dz in (0, 1):
                     idx = (((fl[0] + dx) % n) * n + (fl[1] + dy) % n) * n + (fl[2] + dz) % n
                     np.add.at(m, idx, 1.0)
-        bound = (m.reshape(n, n, n) + 4.0) * 2.0 ** -24 * ref
+        bound = (m.reshape(n, n, n) + 4.0) * 2.0 ** -24 * ref + m.reshape(n, n, n) * 2.0 ** -37
         assert np.all(np.abs(g[s] - ref) <= bound), (s, np.max(np.abs(g[s] - ref) - bound))
     assert abs(wsum.item() - wv.sum()) < 1e-6 * wv.sum()
     plan.close()
@@ -697,3 +771,26 @@ def test_end_to_end_n96(n96_case, prec):
         assert rel_norm(got["B"][li], ref["B"][li]) < tb, li
     assert rel_norm(got["Pbar"], ref["Pbar"]) < 1e-5
     assert rel_norm(got["B0_sub"], ref["B0_sub"]) < tb
+
+
+@pytest.mark.parametrize("n", [64, 128])
+def test_whole_path_reproducible(n):
+    """Two runs of the whole path on one catalogue give bit-identical B_l,
+    B0sub's monopole part, modal numerators, alpha and beta: the assignment sums
+    in fixed point (global atomics below 512 tiles, the tiled kernel from 128 a
+    side) and the reduction partials are combined in a fixed order."""
+    say("repro", n)
+    box = 500.0
+    wl = C.Workload(f"repro{n}", n, n, box, 150_000, -1.5, 0.6, 0.6, 1, 1, 1, 4, 6, 3.0, 4, 20, 900 + n)
+    obs = C.observer_grid_units(wl)
+    pf = pfid_table(wl, 3 * n * n)
+    plan = B.Plan(n=n, box=box, nbins=wl.nbins, k0=wl.k0, dk=wl.dk, lmax=4, window=1, interlace=1, los=1,
+                  observer=obs, P=wl.P, nmodes=wl.nmodes, pfid=pf, drop_tol=MODAL_DROP_TOL)
+    plan.precompute()
+    u = C.lognormal_catalogue(wl)
+    for prec in (B.BSP_FP32, B.BSP_BF16X3):
+        a = _run_gpu(plan, u, prec, 3, wl.nmodes)
+        b = _run_gpu(plan, u, prec, 3, wl.nmodes)
+        for k in ("B", "bnum", "alpha", "beta"):
+            assert np.array_equal(a[k], b[k]), (prec, k)
+    plan.close()

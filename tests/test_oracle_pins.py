@@ -1093,3 +1093,23 @@ def test_modal_solve_pivoted_is_orthonormal_projection():
     assert np.allclose(be2, np.linalg.solve(g2, b2.T).T, rtol=1e-10, atol=1e-12)
     al3, be3 = O.modal_solve(g2, b2)
     assert np.allclose(al2, al3, rtol=1e-12, atol=1e-14) and np.allclose(be2, be3, rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("n,k0,dk,nb", [(8, 1.0, 1.0, 2), (16, 1.5, 1.0, 4)])
+def test_triple_sums_gemm_brute_force(n, k0, dk, nb):
+    """The matrix-product form of the triple sums and counts against the
+    brute-force closed-triangle sums and the direct count enumeration."""
+    spec = [_random_spec(n, 60 + i) for i in range(3)]
+    lo, hi = O.bin_edges4(k0, dk, nb)
+    tris, T = O.binned_triple_sums_gemm(spec, n, n, k0, dk, nb)
+    scale = np.abs(T).max() / n ** 3
+    for ti, (b1, b2, b3) in enumerate(tris):
+        masks = [lambda q, b=b: (4 * q >= lo[b]) & (4 * q < hi[b]) for b in (b1, b2, b3)]
+        for li in range(3):
+            ref = O.closed_triangle_sum_brute([spec[li], spec[0], spec[0]], n, masks, modular=True)
+            assert abs(T[li, ti] / n ** 3 - ref.real) < 1e-10 * scale, (b1, b2, b3, li)
+    _, T1 = O.binned_triple_sums(spec, n, n, k0, dk, nb)
+    assert np.allclose(T, T1, rtol=1e-12, atol=1e-12 * np.abs(T1).max())
+    t2, cnt, resid = O.triangle_counts_gemm(n, k0, dk, nb)
+    assert resid < 1e-6 and t2 == tris
+    assert np.array_equal(cnt, O.triangle_counts_brute(k0, dk, nb, tris))
