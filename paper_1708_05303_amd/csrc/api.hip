@@ -753,7 +753,7 @@ bsp_status run_reduce(bsp_plan p, const ReducePlan& rp, const T* fields, int64_t
   const ReduceDesc d = make_desc(rp, K, K, prec, scale, kc_min);
   const size_t need = (size_t)d.nchunks * d.ntiles * 256 * sizeof(T);
   if (need > scratch_bytes) return fail(p, BSP_ERR_WORKSPACE, "workspace too small for reduction partials");
-  HIPCHK(hipMemsetAsync(Tout, 0, (size_t)rp.npairs * rp.nthirds * sizeof(double), p->stream));
+  HIPCHK(launch_fill_u32(Tout, 0u, 2 * (int64_t)rp.npairs * rp.nthirds, p->stream));
   if (d.ntiles == 0) return BSP_OK;
   if constexpr (sizeof(T) == 4) {
     {
@@ -792,7 +792,7 @@ __global__ void k_pow2_scale(const unsigned* __restrict__ mx, int n, float* __re
 }
 
 bsp_status field_scales(bsp_plan p, const float* fields, int nf, int64_t K, float* scale, unsigned* tmp) {
-  HIPCHK(hipMemsetAsync(tmp, 0, nf * sizeof(unsigned), p->stream));
+  HIPCHK(launch_fill_u32(tmp, 0u, nf, p->stream));
   hipLaunchKernelGGL(k_absmax, dim3(256, nf), dim3(256), 0, p->stream, fields, K, tmp);
   HIPCHK(hipGetLastError());
   hipLaunchKernelGGL(k_pow2_scale, dim3((nf + 63) / 64), dim3(64), 0, p->stream, tmp, nf, scale);
@@ -1635,7 +1635,7 @@ bsp_status estimate_from_spectrum(bsp_plan p, const float2* dl, bsp_precision pr
   }
   s = run_reduce<float>(p, p->main_rp, fields, K, kprec(prec), sc, T, scr, scr_bytes, 1.0);
   if (s != BSP_OK) return s;
-  HIPCHK(hipMemsetAsync(psum, 0, 64 * sizeof(double), p->stream));
+  HIPCHK(launch_fill_u32(psum, 0u, 2 * 64, p->stream));
   HIPCHK(launch_shell_power(dl, p->c, p->cz, p->d_bin_of_n2, p->n2max, p->nbins, psum, p->stream));
   const double N = p->N;
   if (binned && B) {
@@ -1694,7 +1694,7 @@ bsp_status bsp_bispectrum_multipoles(bsp_plan p, const float* ux, const float* u
   double* nbar = small + 4001;
   float* grids = reinterpret_cast<float*>(scr);
   float2* dl = reinterpret_cast<float2*>(p->ws);
-  HIPCHK(hipMemsetAsync(wsum, 0, sizeof(double), p->stream));
+  HIPCHK(launch_fill_u32(wsum, 0u, 2, p->stream));
   {
     // algorithmic minimum: the catalogue read once, each grid node written once
     StageTimer t(p, 0, (double)np * (w ? 16.0 : 12.0) + (double)p->ngrid * p->N * p->N * p->N * 4.0);
@@ -1882,7 +1882,7 @@ bsp_status bsp_integrated_bispectrum(bsp_plan p, const float* grid, const double
   int64_t* dnb = reinterpret_cast<int64_t*>(p->ws + gbytes + fbytes + pbytes + dbytes + align_up(bin.size() * 4));
   HIPCHK(hipMemcpyAsync(dbin, bin.data(), bin.size() * sizeof(int32_t), hipMemcpyHostToDevice, p->stream));
   HIPCHK(hipMemcpyAsync(dnb, nbm.data(), nbm.size() * sizeof(int64_t), hipMemcpyHostToDevice, p->stream));
-  HIPCHK(hipMemsetAsync(psum, 0, (size_t)ns * nl * nbins * sizeof(double), p->stream));
+  HIPCHK(launch_fill_u32(psum, 0u, 2 * (int64_t)ns * nl * nbins, p->stream));
   // algorithmic bytes: the grid read once, each transform pass's input and
   // output once, the sub-volume spectra read once by the shell sums
   const double R = (double)N * N * N, H = (double)ns * m * m * h * 8.0;

@@ -39,6 +39,20 @@ __device__ __forceinline__ void lds_add_fixed(long long* a, long long v) {
   atomicAdd(reinterpret_cast<unsigned long long*>(a), (unsigned long long)v);
 }
 
+// Fills n 32-bit words with v (used instead of hipMemsetAsync, so that the
+// stream's work is kernels only and can be captured in a graph).
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+hipError_t launch_fill_u32(void* p, uint32_t v, int64_t words, hipStream_t s) {
+  if (words <= 0) return hipSuccess;
+  int64_t blocks = (words + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, s, reinterpret_cast<uint32_t*>(p), v, words);
+  return hipGetLastError();
+}
+
 // wmax_bits[0] = max |w| over the finite weights, as FP32 bits (|w| >= 0, so the
 // integer order of the bits is the order of the values).
 __global__ __launch_bounds__(256) void k_weight_max(const float* __restrict__ w, int64_t np,
@@ -436,14 +450,11 @@ size_t assign_tiled_bytes(int64_t np, int n) {
 size_t assign_fixed_bytes(int n, int interlace) { return kHead + (size_t)(1 + interlace) * n * n * n * 8; }
 
 // Head of an assignment scratch: zero the weight sum and set the largest |w|
-// (1.0 for unit weights, else from the weights).
+// (1.0 for unit weights, else from the weights). Kernels only.
 static hipError_t fixed_head(const float* w, int64_t np, unsigned* head, hipStream_t s) {
-  hipError_t e = hipMemsetAsync(head, 0, kHead, s);
+  hipError_t e = launch_fill_u32(head, 0u, kHead / 4, s);
   if (e != hipSuccess) return e;
-  if (!w) {
-    const unsigned one = 0x3f800000u;
-    return hipMemcpyAsync(head, &one, sizeof(one), hipMemcpyHostToDevice, s);
-  }
+  if (!w) return launch_fill_u32(head, 0x3f800000u, 1, s);
   int64_t blocks = (np + 255) / 256;
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(k_weight_max, dim3((unsigned)blocks), dim3(256), 0, s, w, np, head);
@@ -466,7 +477,7 @@ hipError_t launch_assign_tiled(const float* ux, const float* uy, const float* uz
   int32_t* count = reinterpret_cast<int32_t*>(base + align256((size_t)np * sizeof(float4)));
   int32_t* offs = count + align256((size_t)(nt + 1) * sizeof(int32_t)) / sizeof(int32_t);
   int32_t* rank = offs + align256((size_t)(nt + 1) * sizeof(int32_t)) / sizeof(int32_t);
-  hipError_t e = hipMemsetAsync(count, 0, (size_t)nt * sizeof(int32_t), s);
+  hipError_t e = launch_fill_u32(count, 0u, nt, s);
   if (e != hipSuccess) return e;
   e = fixed_head(w, np, head, s);
   if (e != hipSuccess) return e;
@@ -489,7 +500,7 @@ hipError_t launch_assign(const float* ux, const float* uy, const float* uz, cons
   const int64_t count = (int64_t)(1 + interlace) * n * n * n;
   if (np <= 0) {
     if (accumulate) return hipSuccess;
-    return hipMemsetAsync(grids, 0, (size_t)count * sizeof(float), s);
+    return launch_fill_u32(grids, 0u, count, s);
   }
   int64_t blocks = (np + 255) / 256;
   if (blocks > 65536) blocks = 65536;
@@ -498,7 +509,7 @@ hipError_t launch_assign(const float* ux, const float* uy, const float* uz, cons
     unsigned* head = reinterpret_cast<unsigned*>(scratch);
     unsigned long long* wsum_fx = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(scratch) + 8);
     unsigned long long* gfx = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(scratch) + kHead);
-    hipError_t e = hipMemsetAsync(gfx, 0, (size_t)count * 8, s);
+    hipError_t e = launch_fill_u32(gfx, 0u, 2 * count, s);
     if (e != hipSuccess) return e;
     e = fixed_head(w, np, head, s);
     if (e != hipSuccess) return e;
@@ -516,7 +527,7 @@ hipError_t launch_assign(const float* ux, const float* uy, const float* uz, cons
   }
   // no scratch: FP32 atomics on the grids (summation order varies between runs)
   if (!accumulate) {
-    hipError_t e = hipMemsetAsync(grids, 0, (size_t)count * sizeof(float), s);
+    hipError_t e = launch_fill_u32(grids, 0u, count, s);
     if (e != hipSuccess) return e;
   }
   if (window == 0)

@@ -111,6 +111,8 @@ bool fft_size_supported(int n);
 // launch_assign falls back to FP32 atomics. accumulate = 0 overwrites the
 // grids, 1 adds to them; wsum is always added to.
 size_t assign_fixed_bytes(int n, int interlace);
+// Fills `words` 32-bit words with v by a kernel (capturable, unlike a memset node).
+hipError_t launch_fill_u32(void* p, uint32_t v, int64_t words, hipStream_t s);
 hipError_t launch_assign(const float* ux, const float* uy, const float* uz, const float* w,
                          int64_t np, int n, int window, int interlace, int accumulate, float* grids,
                          double* wsum, int32_t* err, void* scratch, size_t scratch_bytes, hipStream_t s);

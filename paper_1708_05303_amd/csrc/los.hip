@@ -205,7 +205,7 @@ hipError_t launch_shell_cross(const float2* delta_l, int64_t ell_stride, int nl,
                               const int32_t* bin_of_n2, int n2max, int nbins, const int64_t* nb_modes, double scale,
                               double* psum, double* P, hipStream_t s) {
   if (nl < 1 || nbins < 1 || (size_t)nl * nbins * sizeof(double) > 64 * 1024) return hipErrorInvalidValue;
-  hipError_t e = hipMemsetAsync(psum, 0, (size_t)nl * nbins * sizeof(double), s);
+  hipError_t e = launch_fill_u32(psum, 0u, 2 * (int64_t)nl * nbins, s);
   if (e != hipSuccess) return e;
   const int64_t cube = (int64_t)(2 * c + 1) * (2 * c + 1) * cz;
   int64_t blocks = (cube + 255) / 256;
