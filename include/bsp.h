@@ -183,6 +183,22 @@ bsp_status bsp_geometry(bsp_plan plan, int32_t* tri, int64_t* counts, double* ga
 bsp_status bsp_grid_assign(bsp_plan plan, const float* ux, const float* uy, const float* uz, const float* w,
                            int64_t np, float* grids, double* wsum);
 
+/* bsp_grid_assign without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation): the same fixed-point global-atomic assignment, with
+ * the same arguments, results and error behaviour, its int64 node sums held in
+ * a static device array of the library (256 bytes plus 2^22 int64 nodes,
+ * 32 MiB + 256 B, held by each GPU it runs on until the process ends) instead
+ * of the workspace; the plan needs no workspace. (1 + interlace) N^3 above
+ * 2^22 nodes (for example 128^3 interlaced is the largest interlaced grid)
+ * returns BSP_ERR_SIZE before anything is launched. Every call on a GPU shares
+ * that GPU's array, which keeps the last call's contents: each call clears
+ * the sums it uses with a kernel first, and calls that overlap in time on one
+ * GPU (different streams or host threads) race. Calls no hipMalloc or hipFree;
+ * the first call on a device looks up the array's address there. */
+bsp_status bsp_grid_assign_noalloc(bsp_plan plan, const float* ux, const float* uy, const float* uz, const float* w,
+                                   int64_t np, float* grids, double* wsum);
+
 /* Full unnormalised 3-D transforms in the standard layouts (forward e^{-i},
  * inverse e^{+i}), batch of independent grids of size n (any supported size).
  * in/out: device. c2r expects Hermitian input and uses the workspace. */

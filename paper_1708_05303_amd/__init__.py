@@ -19,8 +19,8 @@ __all__ = [
     "BspError", "BspLibraryMissing", "Geom", "ModalBasis", "Info", "lib", "Plan",
     "BSP_FP32", "BSP_BF16X3", "BSP_FP16X3", "BSP_BF16X1", "PRECISIONS", "bsp_plan_create", "bsp_plan_destroy",
     "bsp_plan_info", "bsp_workspace_size", "bsp_set_workspace", "bsp_sync", "bsp_precompute",
-    "bsp_geometry", "bsp_grid_assign", "bsp_fft_r2c", "bsp_fft_c2r", "bsp_los_moments", "bsp_grid_entry",
-    "bsp_filter_fields", "bsp_triple_reduce", "bsp_modal_coeffs", "bsp_bispectrum_multipoles",
+    "bsp_geometry", "bsp_grid_assign", "bsp_grid_assign_noalloc", "bsp_fft_r2c", "bsp_fft_c2r",
+    "bsp_los_moments", "bsp_grid_entry", "bsp_filter_fields", "bsp_triple_reduce", "bsp_modal_coeffs", "bsp_bispectrum_multipoles",
     "bsp_bispectrum_field", "bsp_batch_run", "bsp_batch_covariance", "bsp_power_multipoles", "bsp_skew_spectra",
     "bsp_integrated_bispectrum", "bsp_bispectrum_full", "bsp_set_timing", "bsp_stage_times", "STAGES",
     "EXPORTED",
@@ -37,7 +37,8 @@ STATUS = {0: "BSP_OK", 1: "BSP_ERR_ARG", 2: "BSP_ERR_SIZE", 3: "BSP_ERR_ALIAS", 
 # every symbol include/bsp.h declares
 EXPORTED = [
     "bsp_plan_create", "bsp_plan_destroy", "bsp_plan_info", "bsp_last_error", "bsp_workspace_size",
-    "bsp_set_workspace", "bsp_sync", "bsp_precompute", "bsp_geometry", "bsp_grid_assign", "bsp_fft_r2c",
+    "bsp_set_workspace", "bsp_sync", "bsp_precompute", "bsp_geometry", "bsp_grid_assign",
+    "bsp_grid_assign_noalloc", "bsp_fft_r2c",
     "bsp_fft_c2r", "bsp_los_moments", "bsp_grid_entry", "bsp_filter_fields", "bsp_triple_reduce",
     "bsp_modal_coeffs", "bsp_bispectrum_multipoles", "bsp_bispectrum_field", "bsp_batch_run",
     "bsp_batch_covariance", "bsp_power_multipoles", "bsp_skew_spectra", "bsp_integrated_bispectrum",
@@ -100,6 +101,7 @@ def lib():
         "bsp_precompute": [_vp],
         "bsp_geometry": [_vp, _vp, _vp, _vp, _vp, _vp],
         "bsp_grid_assign": [_vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp],
+        "bsp_grid_assign_noalloc": [_vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp],
         "bsp_fft_r2c": [_vp, _i32, _i32, _vp, _vp],
         "bsp_fft_c2r": [_vp, _i32, _i32, _vp, _vp],
         "bsp_los_moments": [_vp, _vp, _vp, _vp],
@@ -208,6 +210,14 @@ def bsp_grid_assign(plan, ux, uy, uz, w, np_, grids, wsum):
     _check(lib().bsp_grid_assign(plan, _dptr(ux, torch.float32), _dptr(uy, torch.float32),
                                  _dptr(uz, torch.float32), _dptr(w, torch.float32), int(np_),
                                  _dptr(grids, torch.float32), _dptr(wsum, torch.float64)), plan)
+
+
+def bsp_grid_assign_noalloc(plan, ux, uy, uz, w, np_, grids, wsum):
+    """bsp_grid_assign with the library's static device scratch (no workspace)."""
+    import torch
+    _check(lib().bsp_grid_assign_noalloc(plan, _dptr(ux, torch.float32), _dptr(uy, torch.float32),
+                                         _dptr(uz, torch.float32), _dptr(w, torch.float32), int(np_),
+                                         _dptr(grids, torch.float32), _dptr(wsum, torch.float64)), plan)
 
 
 def bsp_fft_r2c(plan, n, batch, inp, out):

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <string>
 #include <map>
+#include <mutex>
 #include <vector>
 
 #include "../../include/bsp.h"
@@ -1304,6 +1305,59 @@ bsp_status bsp_grid_assign(bsp_plan p, const float* ux, const float* uy, const f
   else
     HIPCHK(launch_assign(ux, uy, uz, w, np, p->N, p->g.window, p->g.interlace, 1, grids, wsum, p->d_err, p->ws,
                          p->ws ? p->ws_bytes : 0, p->stream));
+  return BSP_OK;
+}
+
+// ---------------------------------------------------------------- no-allocation assignment
+
+namespace {
+
+// Static device scratch of bsp_grid_assign_noalloc: the int64 node sums of the
+// fixed-point assignment (up to 2^22 nodes over all grids) after a 256-byte
+// head. Every GPU the library runs on holds its own copy until the process
+// ends; host code must use the address returned by hipGetSymbolAddress for
+// the current device, never the array's name.
+constexpr size_t kNoAllocNodes = size_t(1) << 22;
+constexpr size_t kNoAllocBytes = 256 + kNoAllocNodes * sizeof(int64_t);
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of `scratch` on the current device, looked up once per device.
+hipError_t static_scratch(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+}  // namespace
+
+bsp_status bsp_grid_assign_noalloc(bsp_plan p, const float* ux, const float* uy, const float* uz, const float* w,
+                                   int64_t np, float* grids, double* wsum) {
+  if (!p || (np > 0 && (!ux || !uy || !uz)) || !grids || !wsum || np < 0) return fail(p, BSP_ERR_ARG, "null argument");
+  const size_t need = assign_fixed_bytes(p->N, p->g.interlace);
+  if (need > kNoAllocBytes)
+    return fail(p, BSP_ERR_SIZE, "bsp_grid_assign_noalloc: (1 + interlace) N^3 = " +
+                                     std::to_string((need - 256) / sizeof(int64_t)) + " nodes exceed the static scratch of " +
+                                     std::to_string(kNoAllocNodes) + " nodes");
+  void* ptr = nullptr;
+  const hipError_t e = static_scratch(&ptr);
+  if (e != hipSuccess) return fail(p, BSP_ERR_HIP, std::string("static scratch: ") + hipGetErrorString(e));
+  HIPCHK(launch_assign(ux, uy, uz, w, np, p->N, p->g.window, p->g.interlace, 1, grids, wsum, p->d_err, ptr,
+                       kNoAllocBytes, p->stream));
   return BSP_OK;
 }
 
