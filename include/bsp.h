@@ -127,6 +127,9 @@ typedef struct {
   int32_t reduce_maxr, reduce_maxcw; /* row tiles, column tiles per wave */
   int64_t reduce_needed;  /* (pair, third) entries the estimators use */
   int32_t modal_rank;     /* modes kept by the orthonormalisation (after bsp_precompute) */
+  int32_t tune_shape;     /* main reduction register shape chosen by bsp_autotune (-1: the rule) */
+  int32_t tune_tiles;     /* short-line transform tiles (0: the rule, 1: 16, 2: 64 columns) */
+  int64_t tune_kchunk;    /* main reduction chunk length (0: the rule) */
 } bsp_info;
 
 /* ---------------------------------------------------------------- plans */
@@ -160,6 +163,21 @@ bsp_status bsp_precompute(bsp_plan plan);
  * factor of gamma restricted to the kept modes in that order (rows and
  * columns past the rank zero). */
 bsp_status bsp_geometry(bsp_plan plan, int32_t* tri, int64_t* counts, double* gamma, double* chol, int32_t* kept);
+
+/* Autotuning (after bsp_precompute, with the workspace): times, on the plan's
+ * own geometry and unit data, (1) the column tiles of the transform passes
+ * over lines of at most 128 points (16 or 64 columns per workgroup) on the
+ * inverse passes of the whole path, and (2) every register shape of the main
+ * triple reduction that holds its schedule, each with three chunk lengths (a
+ * quarter, half and all of the accuracy cap: 16384 points FP32, 8192 split
+ * precisions), and keeps the fastest for this plan. db_path (may be NULL):
+ * a JSON file, one object per plan key (sizes, shells, multipoles, modes,
+ * precision); an entry found there is applied without timing unless flags has
+ * BSP_TUNE_FORCE; a timed choice is written back (the file is rewritten
+ * whole). Synchronises. Outputs are unchanged up to the rounding of the
+ * chunked FP32 sums. */
+#define BSP_TUNE_FORCE 1
+bsp_status bsp_autotune(bsp_plan plan, bsp_precision prec, const char* db_path, int32_t flags);
 
 /* ---------------------------------------------------------------- steps */
 
@@ -370,15 +388,25 @@ bsp_status bsp_stage_times(bsp_plan plan, double* ms, int64_t* launches, double*
  * ux, uy, uz, w (w nullable, entries nullable): host arrays [nmocks] of device
  * pointers to the catalogues. Every plan needs bsp_precompute, a modal basis
  * and its own workspace (plans sharing a workspace must share a stream).
- * Mocks run in order, each on its plan's stream; the call synchronises every
- * plan before enqueueing the covariance on plans[0]'s stream (valid after
- * bsp_sync(plans[0])). Errors: BSP_ERR_ARG if the plans' output shapes or
+ * flags: BSP_BATCH_GRAPH replays, for each plan, its whole path captured once
+ * in a HIP graph (kernels only) over input and output slots the library
+ * allocates for the plan's largest catalogue and keeps with the plan (3 or 4
+ * floats per particle and the outputs of one mock); each mock is then its
+ * catalogue copied into the slot, its count written on the device, one graph
+ * launch and the outputs copied out, on a stream of the plan's own. The
+ * graph is kept and captured again only when the precision, the presence of
+ * weights or a larger catalogue require it. 0: the mocks call
+ * bsp_bispectrum_multipoles one after another on their plans' streams.
+ * Either way the outputs are bit-identical. The call synchronises every
+ * plan (and its batch stream) before enqueueing the covariance on plans[0]'s
+ * stream (valid after bsp_sync(plans[0])). Errors: BSP_ERR_ARG if the plans' output shapes or
  * kept modes differ, nmocks < 2 or an index is out of range; the first failing mock's
  * status otherwise (its message via bsp_last_error(plans[0])). */
+#define BSP_BATCH_GRAPH 1
 bsp_status bsp_batch_run(const bsp_plan* plans, int32_t nplans, const int32_t* mock_plan, int32_t nmocks,
                          const float* const* ux, const float* const* uy, const float* const* uz,
                          const float* const* w, const int64_t* np, bsp_precision prec, double* B_all,
-                         double* alpha_all, double* beta_all, double* cov);
+                         double* alpha_all, double* beta_all, double* cov, int32_t flags);
 
 /* Sample covariance of a batch of coefficient vectors (FP64):
  * cov = (1/(M-1)) sum_m (x_m - mean)(x_m - mean)^T. x: device [m][d], cov:

@@ -18,10 +18,11 @@ import numpy as np
 __all__ = [
     "BspError", "BspLibraryMissing", "Geom", "ModalBasis", "Info", "lib", "Plan",
     "BSP_FP32", "BSP_BF16X3", "BSP_FP16X3", "BSP_BF16X1", "PRECISIONS", "bsp_plan_create", "bsp_plan_destroy",
-    "bsp_plan_info", "bsp_workspace_size", "bsp_set_workspace", "bsp_sync", "bsp_precompute",
+    "bsp_plan_info", "bsp_workspace_size", "bsp_set_workspace", "bsp_sync", "bsp_precompute", "bsp_autotune",
+    "BSP_TUNE_FORCE",
     "bsp_geometry", "bsp_grid_assign", "bsp_grid_assign_noalloc", "bsp_fft_r2c", "bsp_fft_c2r",
     "bsp_los_moments", "bsp_grid_entry", "bsp_filter_fields", "bsp_triple_reduce", "bsp_modal_coeffs", "bsp_bispectrum_multipoles",
-    "bsp_bispectrum_field", "bsp_batch_run", "bsp_batch_covariance", "bsp_power_multipoles", "bsp_skew_spectra",
+    "bsp_bispectrum_field", "bsp_batch_run", "BSP_BATCH_GRAPH", "bsp_batch_covariance", "bsp_power_multipoles", "bsp_skew_spectra",
     "bsp_integrated_bispectrum", "bsp_bispectrum_full", "bsp_set_timing", "bsp_stage_times", "STAGES",
     "EXPORTED",
 ]
@@ -37,7 +38,7 @@ STATUS = {0: "BSP_OK", 1: "BSP_ERR_ARG", 2: "BSP_ERR_SIZE", 3: "BSP_ERR_ALIAS", 
 # every symbol include/bsp.h declares
 EXPORTED = [
     "bsp_plan_create", "bsp_plan_destroy", "bsp_plan_info", "bsp_last_error", "bsp_workspace_size",
-    "bsp_set_workspace", "bsp_sync", "bsp_precompute", "bsp_geometry", "bsp_grid_assign",
+    "bsp_set_workspace", "bsp_sync", "bsp_precompute", "bsp_autotune", "bsp_geometry", "bsp_grid_assign",
     "bsp_grid_assign_noalloc", "bsp_fft_r2c",
     "bsp_fft_c2r", "bsp_los_moments", "bsp_grid_entry", "bsp_filter_fields", "bsp_triple_reduce",
     "bsp_modal_coeffs", "bsp_bispectrum_multipoles", "bsp_bispectrum_field", "bsp_batch_run",
@@ -76,7 +77,8 @@ class Info(C.Structure):
                 ("nfields_binned", C.c_int32), ("nfields_modal", C.c_int32), ("spec_elems", C.c_int64),
                 ("count_residual", C.c_double), ("reduce_pairs", C.c_int32), ("reduce_thirds", C.c_int32),
                 ("reduce_tiles", C.c_int32), ("reduce_groups", C.c_int32), ("reduce_maxr", C.c_int32),
-                ("reduce_maxcw", C.c_int32), ("reduce_needed", C.c_int64), ("modal_rank", C.c_int32)]
+                ("reduce_maxcw", C.c_int32), ("reduce_needed", C.c_int64), ("modal_rank", C.c_int32),
+                ("tune_shape", C.c_int32), ("tune_tiles", C.c_int32), ("tune_kchunk", C.c_int64)]
 
 
 _lib = None
@@ -99,6 +101,7 @@ def lib():
         "bsp_set_workspace": [_vp, _vp, C.c_size_t],
         "bsp_sync": [_vp],
         "bsp_precompute": [_vp],
+        "bsp_autotune": [_vp, _i32, C.c_char_p, _i32],
         "bsp_geometry": [_vp, _vp, _vp, _vp, _vp, _vp],
         "bsp_grid_assign": [_vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp],
         "bsp_grid_assign_noalloc": [_vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp],
@@ -111,7 +114,7 @@ def lib():
         "bsp_modal_coeffs": [_vp, _vp, _i32, _d, _vp, _vp, _vp],
         "bsp_bispectrum_multipoles": [_vp, _vp, _vp, _vp, _vp, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp],
         "bsp_bispectrum_field": [_vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp],
-        "bsp_batch_run": [_vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp],
+        "bsp_batch_run": [_vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _i32],
         "bsp_batch_covariance": [_vp, _i32, _i32, _vp, _vp],
         "bsp_power_multipoles": [_vp, _vp, _vp],
         "bsp_skew_spectra": [_vp, _vp, _vp],
@@ -191,6 +194,13 @@ def bsp_precompute(plan):
     _check(lib().bsp_precompute(plan), plan)
 
 
+BSP_TUNE_FORCE = 1
+
+
+def bsp_autotune(plan, prec, db_path=None, flags=0):
+    _check(lib().bsp_autotune(plan, int(prec), None if db_path is None else os.fsencode(db_path), int(flags)), plan)
+
+
 def bsp_geometry(plan, ntri: int, nmodes: int = 0):
     """Returns (tri, counts, gamma, chol, kept); kept lists the kept modes in
     the order orthonormalised, -1 past the rank."""
@@ -266,9 +276,13 @@ def bsp_bispectrum_field(plan, delta, prec, B, Pbar=None, bnum=None, alpha=None,
                                       _dptr(beta)), plan)
 
 
-def bsp_batch_run(plans, mock_plan, ux, uy, uz, w, np_, prec, B_all, alpha_all, beta_all, cov):
+BSP_BATCH_GRAPH = 1
+
+
+def bsp_batch_run(plans, mock_plan, ux, uy, uz, w, np_, prec, B_all, alpha_all, beta_all, cov, flags=BSP_BATCH_GRAPH):
     """plans: list of plan handles; mock_plan, np_: per-mock ints; ux, uy, uz, w:
-    per-mock float32 device tensors (w None or a list with None entries)."""
+    per-mock float32 device tensors (w None or a list with None entries);
+    flags: BSP_BATCH_GRAPH replays each plan's captured whole path, 0 calls it."""
     import torch
     nm, npl = len(mock_plan), len(plans)
     P = (C.c_void_p * npl)(*[h.value if isinstance(h, C.c_void_p) else h for h in plans])
@@ -279,7 +293,7 @@ def bsp_batch_run(plans, mock_plan, ux, uy, uz, w, np_, prec, B_all, alpha_all, 
         return (C.c_void_p * nm)(*[_dptr(t, torch.float32) for t in ts])
     W = None if w is None else ptrs(w)
     _check(lib().bsp_batch_run(P, npl, mp, nm, ptrs(ux), ptrs(uy), ptrs(uz), W, NP, prec, _dptr(B_all),
-                               _dptr(alpha_all), _dptr(beta_all), _dptr(cov)), plans[0])
+                               _dptr(alpha_all), _dptr(beta_all), _dptr(cov), int(flags)), plans[0])
 
 
 def bsp_batch_covariance(x, m, d, cov, stream: int = 0):
@@ -371,6 +385,12 @@ class Plan:
         self.info = bsp_plan_info(self.handle)
         self.tri, self.counts, self.gamma, self.chol, self.kept = bsp_geometry(self.handle, self.info.ntri,
                                                                               self.nmodes)
+        return self
+
+    def autotune(self, prec, db_path=None, force=False):
+        """Tile and shape choices for this plan (see bsp_autotune); db_path: JSON database."""
+        bsp_autotune(self.handle, prec, db_path, BSP_TUNE_FORCE if force else 0)
+        self.info = bsp_plan_info(self.handle)
         return self
 
     def gram_condition(self):

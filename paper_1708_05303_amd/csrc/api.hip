@@ -4,7 +4,9 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <map>
 #include <mutex>
@@ -35,6 +37,7 @@ struct ReducePlan {
           *d_tile_index = nullptr, *d_tile_rc = nullptr, *d_wave_rows = nullptr, *d_wave_cols = nullptr;
   int32_t *d_pf_row = nullptr, *d_pair_ra = nullptr, *d_pair_rb = nullptr;
   std::vector<int32_t> packed;
+  int64_t kchunk_force = 0;  // points per workgroup chunk chosen by the autotuner (0: the rule)
 };
 
 // Tiles of 16 pairs x 16 thirds; a tile is needed when any entry is. Row
@@ -86,7 +89,7 @@ bool schedule_rows(ReducePlan& rp, const std::vector<int>& active, int maxr, int
 }
 
 bool build_reduce(ReducePlan& rp, const std::vector<std::array<int, 2>>& pairs, const std::vector<int>& thirds,
-                  const std::vector<uint8_t>& need, int nfields, int prec) {
+                  const std::vector<uint8_t>& need, int nfields, int prec, int force_shape = -1) {
   rp = ReducePlan{};
   rp.npairs = (int)pairs.size();
   rp.nthirds = (int)thirds.size();
@@ -141,6 +144,7 @@ bool build_reduce(ReducePlan& rp, const std::vector<std::array<int, 2>>& pairs, 
   int best_groups = 1 << 30;
   const int ns = reduce_shapes(prec, shapes, 8);
   for (int i = 0; i < ns; ++i) {
+    if (force_shape >= 0 && i != force_shape) continue;
     std::vector<int> wr, wc;
     int ng = 0;
     if (!schedule_rows(rp, active, shapes[i].maxr, shapes[i].maxcw, waves, wr, wc, ng)) continue;
@@ -225,7 +229,7 @@ ReduceDesc make_desc(const ReducePlan& rp, int64_t K, int64_t field_stride, int 
   d.nfields = rp.nfields;
   d.K = K;
   d.field_stride = field_stride;
-  d.kchunk = (int32_t)std::max<int64_t>(kchunk_for(prec, K, rp.ngroups), kc_min);
+  d.kchunk = (int32_t)std::max<int64_t>(rp.kchunk_force > 0 ? rp.kchunk_force : kchunk_for(prec, K, rp.ngroups), kc_min);
   d.nchunks = (int32_t)((K + d.kchunk - 1) / d.kchunk);
   d.ngroups = rp.ngroups;
   d.nct = rp.nct;
@@ -249,7 +253,7 @@ ReduceDesc make_desc(const ReducePlan& rp, int64_t K, int64_t field_stride, int 
 }
 
 size_t partial_bytes(const ReducePlan& rp, int64_t K, int prec, size_t elem) {
-  const int64_t kc = kchunk_for(prec, K, rp.ngroups);
+  const int64_t kc = rp.kchunk_force > 0 ? rp.kchunk_force : kchunk_for(prec, K, rp.ngroups);
   const int64_t nch = (K + kc - 1) / kc;
   return (size_t)nch * rp.ntiles * 256 * elem;
 }
@@ -315,6 +319,12 @@ struct bsp_plan_s {
   std::vector<int32_t> piv_h;
   int modal_rank = 0;
   double* d_sn = nullptr;
+  // autotuned choices (bsp_autotune): register shape of the main reduction
+  // (index into its shape list, -1 the fewest workgroup groups), its chunk
+  // length (0 the rule) and the column tiles of short transform lines (0 the rule)
+  int tune_shape = -1;
+  int64_t tune_kchunk = 0;
+  int tune_tiles = 0;
   ReducePlan main_rp, cnt_rp, gram_rp, sn_rp;
   ReducePlan full_rp;                // B^(l1 l2 l3): every (l2, l3) pair of shell fields, made on first use
   bool full_built = false;
@@ -335,8 +345,33 @@ struct bsp_plan_s {
   // generic triple_reduce staging
   ReducePlan call_rp;
   double host_scalar = 0.0;
+  // batch replay: the whole path captured once in a graph over fixed input
+  // and output slots, on a stream of the library's own
+  struct BatchSlot {
+    hipStream_t stream = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int prec = -1, has_w = 0;
+    int64_t cap = 0;
+    float* in = nullptr;     // [3 or 4][cap]: ux, uy, uz (, w)
+    int64_t* npd = nullptr;  // particle count of the mock being replayed
+    double* out = nullptr;   // B [nl][ntri], alpha [nl][nmodes], beta [nl][nmodes]
+    void release() {
+      if (exec) (void)hipGraphExecDestroy(exec);
+      if (in) (void)hipFree(in);
+      if (npd) (void)hipFree(npd);
+      if (out) (void)hipFree(out);
+      exec = nullptr;
+      in = nullptr;
+      npd = nullptr;
+      out = nullptr;
+      prec = -1;
+      cap = 0;
+    }
+  } bslot;
 
   ~bsp_plan_s() {
+    bslot.release();
+    if (bslot.stream) (void)hipStreamDestroy(bslot.stream);
     for (auto& e : ev_pool) {
       (void)hipEventDestroy(e[0]);
       (void)hipEventDestroy(e[1]);
@@ -543,6 +578,7 @@ bsp_status forward_moments(bsp_plan p, const float* grids, int ngrid, int contra
   }
   const int nb = ngrid * p->nlos;
   PassDesc py{};
+  py.tiles = p->tune_tiles;
   py.nouter = nb * N;
   py.in_outer = (int64_t)N * cz;
   py.out_outer = (int64_t)w * cz;
@@ -559,6 +595,7 @@ bsp_status forward_moments(bsp_plan p, const float* grids, int ngrid, int contra
     HIPCHK(launch_c2c_f32(N, -1, Z, Y, py, nullptr, p->tw32_N, p->stream));
   }
   PassDesc px{};
+  px.tiles = p->tune_tiles;
   px.nouter = nb;
   px.in_outer = (int64_t)N * w * cz;
   px.out_outer = (int64_t)w * w * cz;
@@ -682,6 +719,7 @@ bsp_status inverse_fields(bsp_plan p, const cplx_t<T>* src, int64_t src_ell_stri
     fd.cz = cz;
     fd.field0 = f0;
     PassDesc px{};
+    px.tiles = p->tune_tiles;
     px.nouter = nb;
     px.in_outer = 0;
     px.out_outer = (int64_t)Nr * wb * czb;
@@ -697,6 +735,7 @@ bsp_status inverse_fields(bsp_plan p, const cplx_t<T>* src, int64_t src_ell_stri
     px.out_rows = Nr;
     px.out_off = 0;
     PassDesc py{};
+    py.tiles = p->tune_tiles;
     py.nouter = nb * Nr;
     py.in_outer = (int64_t)wb * czb;
     py.out_outer = (int64_t)Nr * czb;
@@ -971,7 +1010,9 @@ bool build_main(bsp_plan p, bool exact) {
       }
     }
   }
-  return build_reduce(p->main_rp, pr, th, need, p->F, 1);
+  if (!build_reduce(p->main_rp, pr, th, need, p->F, 1, p->tune_shape)) return false;
+  p->main_rp.kchunk_force = p->tune_kchunk;
+  return true;
 }
 
 }  // namespace
@@ -1257,6 +1298,9 @@ bsp_status bsp_plan_info(bsp_plan p, bsp_info* info) {
   info->reduce_maxcw = m.maxcw;
   info->reduce_needed = m.needed;
   info->modal_rank = p->modal_rank;
+  info->tune_shape = p->tune_shape;
+  info->tune_tiles = p->tune_tiles;
+  info->tune_kchunk = p->tune_kchunk;
   return BSP_OK;
 }
 
@@ -1387,6 +1431,7 @@ bsp_status r2c_batch(bsp_plan p, int n, int batch, const float* in, float2* out,
   fz.zs = h;
   HIPCHK(launch_fwd_z_f32(n, in, out, fz, tw, p->stream));
   PassDesc py{};
+  py.tiles = p->tune_tiles;
   py.nouter = batch * n;
   py.in_outer = py.out_outer = (int64_t)n * h;
   py.in_row = py.out_row = h;
@@ -1395,6 +1440,7 @@ bsp_status r2c_batch(bsp_plan p, int n, int batch, const float* in, float2* out,
   set1d(py);
   HIPCHK(launch_c2c_f32(n, -1, out, out, py, nullptr, tw, p->stream));
   PassDesc px{};
+  px.tiles = p->tune_tiles;
   px.nouter = batch;
   px.in_outer = px.out_outer = (int64_t)n * n * h;
   px.in_row = px.out_row = (int64_t)n * h;
@@ -1426,6 +1472,7 @@ bsp_status bsp_fft_c2r(bsp_plan p, int32_t n, int32_t batch, const void* in_c64,
   float2* tmp = reinterpret_cast<float2*>(p->ws);
   for (int b = 0; b < batch; ++b) {
     PassDesc px{};
+    px.tiles = p->tune_tiles;
     px.nouter = 1;
     px.in_outer = px.out_outer = 0;
     px.in_row = px.out_row = (int64_t)n * h;
@@ -1434,6 +1481,7 @@ bsp_status bsp_fft_c2r(bsp_plan p, int32_t n, int32_t batch, const void* in_c64,
     set1d(px);
     HIPCHK(launch_c2c_f32(n, +1, in + (size_t)b * n * n * h, tmp, px, nullptr, tw, p->stream));
     PassDesc py{};
+    py.tiles = p->tune_tiles;
     py.nouter = n;
     py.in_outer = py.out_outer = (int64_t)n * h;
     py.in_row = py.out_row = h;
@@ -1655,6 +1703,191 @@ bsp_status bsp_geometry(bsp_plan p, int32_t* tri, int64_t* counts, double* gamma
   return BSP_OK;
 }
 
+// ---------------------------------------------------------------- autotuning
+
+namespace {
+
+std::string tune_key(const bsp_plan p, bsp_precision prec) {
+  char buf[256];
+  std::snprintf(buf, sizeof buf, "N%d_Nr%d_nb%d_k0%g_dk%g_l%d_w%d_i%d_los%d_P%d_m%d_kept%d_prec%d", p->N, p->Nr,
+                p->nbins, p->g.k0, p->g.dk, p->g.lmax, p->g.window, p->g.interlace, p->g.los, p->modal ? p->P : 0,
+                p->modal ? p->nmodes : 0, p->modal_rank, (int)prec);
+  return buf;
+}
+
+struct TuneEntry {
+  int shape = -1, tiles = 0;
+  long long kchunk = 0;
+  double reduce_ms = 0.0, inverse_ms = 0.0;
+};
+
+// The database is a JSON object with one entry per line:
+//   "<key>": {"shape": 3, "kchunk": 8192, "tiles": 0, "reduce_ms": 26.1, "inverse_ms": 29.5},
+// closed by the sentinel line  "_": {}.
+bool tune_lookup(const std::string& path, const std::string& key, TuneEntry& e) {
+  std::FILE* f = std::fopen(path.c_str(), "r");
+  if (!f) return false;
+  char line[1024];
+  bool found = false;
+  const std::string pre = "\"" + key + "\": {";
+  while (std::fgets(line, sizeof line, f)) {
+    const std::string l(line);
+    const size_t at = l.find(pre);
+    if (at == std::string::npos) continue;
+    found = std::sscanf(l.c_str() + at + pre.size(),
+                        "\"shape\": %d, \"kchunk\": %lld, \"tiles\": %d, \"reduce_ms\": %lf, \"inverse_ms\": %lf",
+                        &e.shape, &e.kchunk, &e.tiles, &e.reduce_ms, &e.inverse_ms) == 5;
+    break;
+  }
+  std::fclose(f);
+  return found;
+}
+
+bool tune_store(const std::string& path, const std::string& key, const TuneEntry& e) {
+  std::vector<std::string> keep;
+  if (std::FILE* f = std::fopen(path.c_str(), "r")) {
+    char line[1024];
+    while (std::fgets(line, sizeof line, f)) {
+      std::string l(line);
+      while (!l.empty() && (l.back() == '\n' || l.back() == '\r')) l.pop_back();
+      if (l.size() > 1 && l[0] == '"' && l.compare(0, 4, "\"_\":") != 0 && l.find("\"" + key + "\":") != 0)
+        keep.push_back(l);
+    }
+    std::fclose(f);
+  }
+  char buf[512];
+  std::snprintf(buf, sizeof buf,
+                "\"%s\": {\"shape\": %d, \"kchunk\": %lld, \"tiles\": %d, \"reduce_ms\": %.4f, \"inverse_ms\": %.4f},",
+                key.c_str(), e.shape, e.kchunk, e.tiles, e.reduce_ms, e.inverse_ms);
+  keep.push_back(buf);
+  const std::string tmp = path + ".tmp";
+  std::FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return false;
+  std::fputs("{\n", f);
+  for (const auto& l : keep) {
+    std::fputs(l.c_str(), f);
+    std::fputs("\n", f);
+  }
+  std::fputs("\"_\": {}\n}\n", f);
+  const bool ok = std::fclose(f) == 0;
+  return ok && std::rename(tmp.c_str(), path.c_str()) == 0;
+}
+
+// Applies a shape / chunk choice to the main reduction schedule.
+bool apply_reduce_choice(bsp_plan p, int shape, int64_t kchunk) {
+  p->tune_shape = shape;
+  p->tune_kchunk = kchunk;
+  return build_main(p, true) && upload_rp(p, p->main_rp);
+}
+
+// Milliseconds of the fastest of `reps` timed runs of f on the plan's stream.
+double time_min(bsp_plan p, int reps, const std::function<bsp_status()>& f, bsp_status& st) {
+  hipEvent_t a, b;
+  st = BSP_OK;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+    st = BSP_ERR_HIP;
+    return 0.0;
+  }
+  double best = 1e300;
+  for (int r = 0; r < reps && st == BSP_OK; ++r) {
+    (void)hipEventRecord(a, p->stream);
+    st = f();
+    (void)hipEventRecord(b, p->stream);
+    if (st == BSP_OK && hipEventSynchronize(b) == hipSuccess) {
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, a, b);
+      best = std::min(best, (double)ms);
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return best;
+}
+
+}  // namespace
+
+bsp_status bsp_autotune(bsp_plan p, bsp_precision prec, const char* db_path, int32_t flags) {
+  if (!p) return BSP_ERR_ARG;
+  if (!p->pre_done) return fail(p, BSP_ERR_STATE, "bsp_precompute has not run");
+  if (prec < BSP_FP32 || prec > BSP_BF16X1) return fail(p, BSP_ERR_ARG, "bad precision");
+  const Layout L = layout(p);
+  bsp_status s = need_ws(p, L.total);
+  if (s != BSP_OK) return s;
+  const std::string key = tune_key(p, prec);
+  TuneEntry e;
+  const std::string path = db_path ? db_path : "";
+  if (!path.empty() && !(flags & BSP_TUNE_FORCE) && tune_lookup(path, key, e)) {
+    p->tune_tiles = e.tiles;
+    if (!apply_reduce_choice(p, e.shape, e.kchunk)) return fail(p, BSP_ERR_ARG, "tuned reduction shape not supported");
+    return BSP_OK;
+  }
+  s = bsp_sync(p);
+  if (s != BSP_OK) return s;
+  const bool timing = p->timing;
+  p->timing = false;
+  const int Nr = p->Nr;
+  const int64_t K = (int64_t)Nr * Nr * Nr;
+  char* ws = p->ws;
+  float2* dl = reinterpret_cast<float2*>(ws);
+  float* fields = reinterpret_cast<float*>(ws + L.dl);
+  double* T = reinterpret_cast<double*>(ws + L.dl + L.fields);
+  char* scr = ws + L.dl + L.fields + L.T + L.small;
+  const size_t scr_bytes = p->ws_bytes - (L.dl + L.fields + L.T + L.small);
+  // defined inputs: a unit spectrum and unit fields (timing does not depend on the values)
+  HIPCHK(launch_fill_u32(dl, 0x3f800000u, 2 * (int64_t)p->nl * p->spec, p->stream));
+  HIPCHK(launch_fill_u32(fields, 0x3f800000u, (int64_t)p->F * K, p->stream));
+  // 1. transform tiles of short lines: the inverse passes of the main pipeline
+  TuneEntry best;
+  best.inverse_ms = 1e300;
+  for (int tiles : {1, 2}) {
+    if (tiles == 2 && Nr > 128) break;  // only lines of <= 128 points have 64-column tiles
+    p->tune_tiles = tiles;
+    bsp_status st;
+    const double ms = time_min(p, 3, [&]() {
+      return inverse_fields<float>(p, dl, p->spec, p->F, p->d_field_ell, p->d_field_tab, p->d_tab32, p->d_rng32,
+                                   fields, scr, L.fb, p->field_c, p->field_row32.data());
+    }, st);
+    if (st != BSP_OK) {
+      p->timing = timing;
+      return st;
+    }
+    if (ms < best.inverse_ms) {
+      best.inverse_ms = ms;
+      best.tiles = tiles;
+    }
+  }
+  p->tune_tiles = best.tiles;
+  HIPCHK(launch_fill_u32(fields, 0x3f800000u, (int64_t)p->F * K, p->stream));
+  // 2. register shape and chunk length of the main reduction
+  ReduceShape shapes[8];
+  const int ns = reduce_shapes(1, shapes, 8);
+  const int64_t cap = (prec == BSP_FP32) ? 16384 : 8192;
+  best.reduce_ms = 1e300;
+  for (int si = 0; si < ns; ++si) {
+    for (int64_t kc : {cap / 4, cap / 2, cap}) {
+      if (kc < 1024 || kc > K) continue;
+      if (!apply_reduce_choice(p, si, kc)) continue;  // shape cannot hold the schedule
+      if (partial_bytes(p->main_rp, K, kprec(prec), sizeof(float)) > scr_bytes) continue;
+      bsp_status st;
+      const double ms = time_min(p, 3, [&]() {
+        return run_reduce<float>(p, p->main_rp, fields, K, kprec(prec), nullptr, T, scr, scr_bytes, 1.0);
+      }, st);
+      if (st != BSP_OK) continue;
+      if (ms < best.reduce_ms) {
+        best.reduce_ms = ms;
+        best.shape = si;
+        best.kchunk = kc;
+      }
+    }
+  }
+  p->timing = timing;
+  if (best.reduce_ms == 1e300) return fail(p, BSP_ERR_ARG, "no reduction shape could be timed");
+  if (!apply_reduce_choice(p, best.shape, best.kchunk)) return fail(p, BSP_ERR_HIP, "reduction schedule upload");
+  if (!path.empty() && !tune_store(path, key, best))
+    return fail(p, BSP_ERR_ARG, "cannot write the tuning database " + path);
+  return bsp_sync(p);
+}
+
 // ---------------------------------------------------------------- estimators
 
 namespace {
@@ -1733,12 +1966,15 @@ bsp_status bsp_modal_coeffs(bsp_plan p, const void* delta_l, bsp_precision prec,
                                 nullptr, nullptr, bnum, alpha, beta, false, true);
 }
 
-bsp_status bsp_bispectrum_multipoles(bsp_plan p, const float* ux, const float* uy, const float* uz, const float* w,
-                                     int64_t np, bsp_precision prec, double* B, double* B0sub, double* Pbar,
-                                     double* bnum, double* alpha, double* beta) {
-  if (!p || !ux || !uy || !uz || !B || np < 1) return fail(p, BSP_ERR_ARG, "bad argument");
-  if (!p->pre_done) return fail(p, BSP_ERR_STATE, "bsp_precompute has not run");
-  if (prec < BSP_FP32 || prec > BSP_BF16X1) return fail(p, BSP_ERR_ARG, "bad precision");
+namespace {
+
+// The whole path on the plan's stream, kernels only (no host synchronisation,
+// no memset or host-copy nodes), so that it can be captured in a graph. npd:
+// optional device-side particle count read by the assignment kernels (np then
+// bounds it).
+bsp_status whole_path(bsp_plan p, const float* ux, const float* uy, const float* uz, const float* w, int64_t np,
+                      const int64_t* npd, bsp_precision prec, double* B, double* B0sub, double* Pbar, double* bnum,
+                      double* alpha, double* beta) {
   const Layout L = layout(p);
   bsp_status s = need_ws(p, L.total);
   if (s != BSP_OK) return s;
@@ -1755,16 +1991,29 @@ bsp_status bsp_bispectrum_multipoles(bsp_plan p, const float* ux, const float* u
     const size_t tb = assign_tiled_bytes(np, p->N);
     if (tb && tb <= L.scratch - L.s_grid && assign_tiled_preferred(p->N)) {
       HIPCHK(launch_assign_tiled(ux, uy, uz, w, np, p->N, p->g.window, p->g.interlace, 0, grids, wsum, p->d_err,
-                                 scr + L.s_grid, L.scratch - L.s_grid, p->stream));
+                                 scr + L.s_grid, L.scratch - L.s_grid, p->stream, npd));
     } else {
       HIPCHK(launch_assign(ux, uy, uz, w, np, p->N, p->g.window, p->g.interlace, 0, grids, wsum, p->d_err,
-                           scr + L.s_grid, L.scratch - L.s_grid, p->stream));
+                           scr + L.s_grid, L.scratch - L.s_grid, p->stream, npd));
     }
   }
   HIPCHK(launch_scale_scalar(wsum, 1.0 / p->V, nbar, p->stream));
   s = forward_moments(p, grids, p->ngrid, 1, wsum, p->g.compensate, dl, scr + L.s_grid);
   if (s != BSP_OK) return s;
   return estimate_from_spectrum(p, dl, prec, nbar, B, B0sub, Pbar, bnum, alpha, beta, true, true);
+}
+
+}  // namespace
+
+bsp_status bsp_bispectrum_multipoles(bsp_plan p, const float* ux, const float* uy, const float* uz, const float* w,
+                                     int64_t np, bsp_precision prec, double* B, double* B0sub, double* Pbar,
+                                     double* bnum, double* alpha, double* beta) {
+  if (!p || !ux || !uy || !uz || !B || np < 1) return fail(p, BSP_ERR_ARG, "bad argument");
+  if (!p->pre_done) return fail(p, BSP_ERR_STATE, "bsp_precompute has not run");
+  if (prec < BSP_FP32 || prec > BSP_BF16X1) return fail(p, BSP_ERR_ARG, "bad precision");
+  const bsp_status s = need_ws(p, layout(p).total);
+  if (s != BSP_OK) return s;
+  return whole_path(p, ux, uy, uz, w, np, nullptr, prec, B, B0sub, Pbar, bnum, alpha, beta);
 }
 
 bsp_status bsp_bispectrum_field(bsp_plan p, const float* delta, bsp_precision prec, double* B, double* Pbar,
@@ -1851,6 +2100,7 @@ bsp_status bsp_skew_spectra(bsp_plan p, const void* delta_l, double* S) {
   fz.zs = cz;
   HIPCHK(launch_fwd_z_f32(Nr, d, Z, fz, p->tw32_Nr, p->stream));
   PassDesc py{};
+  py.tiles = p->tune_tiles;
   py.nouter = Nr;
   py.in_outer = (int64_t)Nr * cz;
   py.out_outer = (int64_t)w * cz;
@@ -1864,6 +2114,7 @@ bsp_status bsp_skew_spectra(bsp_plan p, const void* delta_l, double* S) {
   set1d(py);
   HIPCHK(launch_c2c_f32(Nr, -1, Z, Y, py, nullptr, p->tw32_Nr, p->stream));
   PassDesc px{};
+  px.tiles = p->tune_tiles;
   px.nouter = 1;
   px.in_outer = (int64_t)Nr * w * cz;
   px.out_outer = (int64_t)w * w * cz;
@@ -2063,14 +2314,68 @@ bsp_status bsp_stage_times(bsp_plan p, double* ms, int64_t* launches, double* am
   return BSP_OK;
 }
 
+namespace {
+
+// (Re)captures the whole path of plan q into q's batch graph for catalogues of
+// up to cap particles at precision prec; the graph reads its catalogue from
+// q->bslot.in and its count from q->bslot.npd and writes q->bslot.out.
+bsp_status batch_graph(bsp_plan q, bsp_precision prec, int64_t cap, int has_w) {
+  auto& b = q->bslot;
+  if (b.exec && b.prec == (int)prec && b.cap >= cap && b.has_w == has_w) return BSP_OK;
+  b.release();
+  bsp_plan p = q;  // for HIPCHK
+  if (!b.stream) HIPCHK(hipStreamCreateWithFlags(&b.stream, hipStreamNonBlocking));
+  const size_t nout = (size_t)q->nl * (q->tri.size() + 2 * (size_t)q->nmodes);
+  HIPCHK(hipMalloc(&b.in, (size_t)(3 + has_w) * cap * sizeof(float)));
+  HIPCHK(hipMalloc(&b.npd, sizeof(int64_t)));
+  HIPCHK(hipMalloc(&b.out, nout * sizeof(double)));
+  b.prec = (int)prec;
+  b.cap = cap;
+  b.has_w = has_w;
+  double* oB = b.out;
+  double* oA = oB + (size_t)q->nl * q->tri.size();
+  double* oBe = oA + (size_t)q->nl * q->nmodes;
+  // capture on the batch stream: the path enqueues on q->stream, pointed there
+  // for the capture, with stage timing off
+  const hipStream_t keep = q->stream;
+  const bool timing = q->timing;
+  q->stream = b.stream;
+  q->timing = false;
+  hipGraph_t graph = nullptr;
+  bsp_status s = BSP_OK;
+  hipError_t e = hipStreamBeginCapture(b.stream, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    s = whole_path(q, b.in, b.in + cap, b.in + 2 * cap, has_w ? b.in + 3 * cap : nullptr, cap, b.npd, prec, oB,
+                   nullptr, nullptr, nullptr, oA, oBe);
+    e = hipStreamEndCapture(b.stream, &graph);
+  }
+  q->stream = keep;
+  q->timing = timing;
+  if (s != BSP_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    b.release();
+    return s;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&b.exec, graph, nullptr, nullptr, 0);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    b.release();
+    return fail(q, BSP_ERR_HIP, std::string("graph capture of the whole path: ") + hipGetErrorString(e));
+  }
+  return BSP_OK;
+}
+
+}  // namespace
+
 bsp_status bsp_batch_run(const bsp_plan* plans, int32_t nplans, const int32_t* mock_plan, int32_t nmocks,
                          const float* const* ux, const float* const* uy, const float* const* uz,
                          const float* const* w, const int64_t* np, bsp_precision prec, double* B_all,
-                         double* alpha_all, double* beta_all, double* cov) {
+                         double* alpha_all, double* beta_all, double* cov, int32_t flags) {
   if (!plans || nplans < 1 || !mock_plan || nmocks < 2 || !ux || !uy || !uz || !np || !B_all || !alpha_all || !cov)
     return fail(nullptr, BSP_ERR_ARG, "bad argument");
   bsp_plan p0 = plans[0];
   if (!p0) return fail(nullptr, BSP_ERR_ARG, "null plan");
+  if (prec < BSP_FP32 || prec > BSP_BF16X1) return fail(p0, BSP_ERR_ARG, "bad precision");
   // every plan must produce outputs of the same shape: nl, triangles and modes
   for (int i = 0; i < nplans; ++i) {
     bsp_plan q = plans[i];
@@ -2081,24 +2386,77 @@ bsp_status bsp_batch_run(const bsp_plan* plans, int32_t nplans, const int32_t* m
     // alpha is a coefficient vector on the same orthonormal modes only when
     // every plan kept the same modes in the same order
     if (q->piv_h != p0->piv_h) return fail(p0, BSP_ERR_ARG, "plans kept different modes in their orthonormalisation");
-  }
-  for (int m = 0; m < nmocks; ++m)
-    if (mock_plan[m] < 0 || mock_plan[m] >= nplans) return fail(p0, BSP_ERR_ARG, "mock plan index out of range");
-  const int64_t ntri = (int64_t)p0->tri.size();
-  const int64_t D = (int64_t)p0->nl * p0->nmodes;
-  for (int m = 0; m < nmocks; ++m) {
-    bsp_plan q = plans[mock_plan[m]];
-    const bsp_status s = bsp_bispectrum_multipoles(q, ux[m], uy[m], uz[m], w ? w[m] : nullptr, np[m], prec,
-                                                   B_all + (int64_t)m * p0->nl * ntri, nullptr, nullptr, nullptr,
-                                                   alpha_all + (int64_t)m * D,
-                                                   beta_all ? beta_all + (int64_t)m * D : nullptr);
+    const bsp_status s = need_ws(q, layout(q).total);
     if (s != BSP_OK) {
       if (q != p0) p0->err = q->err;
       return s;
     }
   }
+  for (int m = 0; m < nmocks; ++m) {
+    if (mock_plan[m] < 0 || mock_plan[m] >= nplans) return fail(p0, BSP_ERR_ARG, "mock plan index out of range");
+    if (np[m] < 1 || !ux[m] || !uy[m] || !uz[m]) return fail(p0, BSP_ERR_ARG, "empty or null mock catalogue");
+  }
+  const int64_t ntri = (int64_t)p0->tri.size();
+  const int64_t D = (int64_t)p0->nl * p0->nmodes;
+  const bool graphs = (flags & BSP_BATCH_GRAPH) != 0;
+  if (graphs) {
+    // one graph per plan, sized for the largest catalogue the plan runs
+    std::vector<int64_t> cap(nplans, 0);
+    std::vector<int> hw(nplans, 0);
+    for (int m = 0; m < nmocks; ++m) {
+      cap[mock_plan[m]] = std::max(cap[mock_plan[m]], np[m]);
+      if (w && w[m]) hw[mock_plan[m]] = 1;
+    }
+    for (int i = 0; i < nplans; ++i) {
+      if (cap[i] == 0) continue;
+      // the plan's earlier work (and the caller's) finishes before its batch stream starts
+      bsp_status s = bsp_sync(plans[i]);
+      if (s == BSP_OK) s = batch_graph(plans[i], prec, cap[i], hw[i]);
+      if (s != BSP_OK) {
+        if (plans[i] != p0) p0->err = plans[i]->err;
+        return s;
+      }
+    }
+  }
+  for (int m = 0; m < nmocks; ++m) {
+    bsp_plan q = plans[mock_plan[m]];
+    if (!graphs) {
+      const bsp_status s = bsp_bispectrum_multipoles(q, ux[m], uy[m], uz[m], w ? w[m] : nullptr, np[m], prec,
+                                                     B_all + (int64_t)m * p0->nl * ntri, nullptr, nullptr, nullptr,
+                                                     alpha_all + (int64_t)m * D,
+                                                     beta_all ? beta_all + (int64_t)m * D : nullptr);
+      if (s != BSP_OK) {
+        if (q != p0) p0->err = q->err;
+        return s;
+      }
+      continue;
+    }
+    auto& b = q->bslot;
+    bsp_plan p = q;  // for HIPCHK
+    const size_t nb = (size_t)np[m] * sizeof(float);
+    HIPCHK(hipMemcpyAsync(b.in, ux[m], nb, hipMemcpyDeviceToDevice, b.stream));
+    HIPCHK(hipMemcpyAsync(b.in + b.cap, uy[m], nb, hipMemcpyDeviceToDevice, b.stream));
+    HIPCHK(hipMemcpyAsync(b.in + 2 * b.cap, uz[m], nb, hipMemcpyDeviceToDevice, b.stream));
+    if (b.has_w) {
+      if (w && w[m]) HIPCHK(hipMemcpyAsync(b.in + 3 * b.cap, w[m], nb, hipMemcpyDeviceToDevice, b.stream));
+      else HIPCHK(launch_fill_u32(b.in + 3 * b.cap, 0x3f800000u, np[m], b.stream));
+    }
+    HIPCHK(launch_set_i64(b.npd, np[m], b.stream));
+    HIPCHK(hipGraphLaunch(b.exec, b.stream));
+    const double* oB = b.out;
+    const double* oA = oB + (size_t)q->nl * ntri;
+    HIPCHK(hipMemcpyAsync(B_all + (int64_t)m * p0->nl * ntri, oB, (size_t)q->nl * ntri * sizeof(double),
+                          hipMemcpyDeviceToDevice, b.stream));
+    HIPCHK(hipMemcpyAsync(alpha_all + (int64_t)m * D, oA, (size_t)D * sizeof(double), hipMemcpyDeviceToDevice,
+                          b.stream));
+    if (beta_all)
+      HIPCHK(hipMemcpyAsync(beta_all + (int64_t)m * D, oA + D, (size_t)D * sizeof(double), hipMemcpyDeviceToDevice,
+                            b.stream));
+  }
   // the covariance runs on the first plan's stream once every mock is done
   for (int i = 0; i < nplans; ++i) {
+    bsp_plan p = plans[i];  // for HIPCHK
+    if (graphs && p->bslot.stream) HIPCHK(hipStreamSynchronize(p->bslot.stream));
     const bsp_status s = bsp_sync(plans[i]);
     if (s != BSP_OK) {
       if (plans[i] != p0) p0->err = plans[i]->err;

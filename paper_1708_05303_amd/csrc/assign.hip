@@ -55,8 +55,9 @@ hipError_t launch_fill_u32(void* p, uint32_t v, int64_t words, hipStream_t s) {
 
 // wmax_bits[0] = max |w| over the finite weights, as FP32 bits (|w| >= 0, so the
 // integer order of the bits is the order of the values).
-__global__ __launch_bounds__(256) void k_weight_max(const float* __restrict__ w, int64_t np,
+__global__ __launch_bounds__(256) void k_weight_max(const float* __restrict__ w, const int64_t* __restrict__ npd,
                                                     unsigned* __restrict__ wmax_bits) {
+  const int64_t np = *npd;
   unsigned m = 0u;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
     const float a = fabsf(w[i]);
@@ -71,11 +72,12 @@ __global__ __launch_bounds__(256) void k_weight_max(const float* __restrict__ w,
 template <int WINDOW>
 __global__ __launch_bounds__(256) void k_assign_fixed(const float* __restrict__ ux, const float* __restrict__ uy,
                                                       const float* __restrict__ uz, const float* __restrict__ w,
-                                                      int64_t np, int n, int interlace,
+                                                      const int64_t* __restrict__ npd, int n, int interlace,
                                                       const unsigned* __restrict__ wmax_bits,
                                                       unsigned long long* __restrict__ gfx,
                                                       unsigned long long* __restrict__ wsum_fx,
                                                       int32_t* __restrict__ err) {
+  const int64_t np = *npd;
   const int64_t n3 = (int64_t)n * n * n;
   const float fn = (float)n;
   const int sh = fixed_shift(*wmax_bits, np);
@@ -142,10 +144,12 @@ __global__ __launch_bounds__(256) void k_assign_fixed(const float* __restrict__ 
 
 // grids[i] (+)= gfx[i] 2^-S rounded to FP32; block 0 also adds the weight sum.
 __global__ __launch_bounds__(256) void k_fixed_to_float(const unsigned long long* __restrict__ gfx, int64_t count,
-                                                        int64_t np, const unsigned* __restrict__ wmax_bits,
+                                                        const int64_t* __restrict__ npd,
+                                                        const unsigned* __restrict__ wmax_bits,
                                                         const unsigned long long* __restrict__ wsum_fx,
                                                         int accumulate, float* __restrict__ grids,
                                                         double* __restrict__ wsum) {
+  const int64_t np = *npd;
   const int sh = fixed_shift(*wmax_bits, np);
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x) {
     const float v = (float)ldexp((double)(long long)gfx[i], -sh);
@@ -239,11 +243,12 @@ __device__ __forceinline__ bool valid_particle(float x, float y, float z, float 
 
 __global__ __launch_bounds__(256) void k_tile_count(const float* __restrict__ ux, const float* __restrict__ uy,
                                                     const float* __restrict__ uz, const float* __restrict__ w,
-                                                    int64_t np, int n, int ntx, int ntz, int tz,
+                                                    const int64_t* __restrict__ npd, int n, int ntx, int ntz, int tz,
                                                     int32_t* __restrict__ count, int32_t* __restrict__ rank,
                                                     const unsigned* __restrict__ wmax_bits,
                                                     unsigned long long* __restrict__ wsum_fx,
                                                     int32_t* __restrict__ err) {
+  const int64_t np = *npd;
   const float fn = (float)n;
   const int sh = fixed_shift(*wmax_bits, np);
   long long acc = 0;
@@ -298,9 +303,10 @@ __global__ __launch_bounds__(1024) void k_tile_scan(const int32_t* __restrict__ 
 
 __global__ __launch_bounds__(256) void k_tile_scatter(const float* __restrict__ ux, const float* __restrict__ uy,
                                                       const float* __restrict__ uz, const float* __restrict__ w,
-                                                      int64_t np, int n, int ntx, int ntz, int tz,
+                                                      const int64_t* __restrict__ npd, int n, int ntx, int ntz, int tz,
                                                       const int32_t* __restrict__ offs,
                                                       const int32_t* __restrict__ rank, float4* __restrict__ sorted) {
+  const int64_t np = *npd;
   const float fn = (float)n;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < np; i += (int64_t)gridDim.x * blockDim.x) {
     const float x = ux[i], y = uy[i], z = uz[i];
@@ -314,7 +320,7 @@ __global__ __launch_bounds__(256) void k_tile_scatter(const float* __restrict__ 
 template <int WINDOW, int TZ>
 __global__ __launch_bounds__(256) void k_assign_tiles(const float4* __restrict__ sorted,
                                                       const int32_t* __restrict__ offs, int n, int ntx, int ntz,
-                                                      int interlace, int accumulate, int64_t np,
+                                                      int interlace, int accumulate, const int64_t* __restrict__ npd,
                                                       const unsigned* __restrict__ wmax_bits,
                                                       const unsigned long long* __restrict__ wsum_fx,
                                                       float* __restrict__ grids, double* __restrict__ wsum) {
@@ -323,7 +329,7 @@ __global__ __launch_bounds__(256) void k_assign_tiles(const float4* __restrict__
   const int tile = blockIdx.x;
   const int tzi = tile % ntz, txy = tile / ntz, tyi = txy % ntx, txi = txy / ntx;
   const int x0 = txi * TXY, y0 = tyi * TXY, z0 = tzi * TZ;
-  const int sh = fixed_shift(*wmax_bits, np);
+  const int sh = fixed_shift(*wmax_bits, *npd);
   for (int i = threadIdx.x; i < 2 * CELLS; i += 256) (&acc[0][0])[i] = 0;
   __syncthreads();
   const float fn = (float)n;
@@ -436,8 +442,18 @@ bool assign_tiled_preferred(int n) {
 }
 
 // 256 bytes at the head of an assignment scratch: the largest |w| (FP32 bits)
-// and the fixed-point weight sum.
+// at byte 0, the fixed-point weight sum at byte 8 and the particle count the
+// kernels read at byte 16 (unless the caller points them at its own).
 constexpr size_t kHead = 256;
+
+__global__ void k_set_i64(int64_t* __restrict__ p, int64_t v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) p[0] = v;
+}
+
+hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(64), 0, s, p, v);
+  return hipGetLastError();
+}
 
 size_t assign_tiled_bytes(int64_t np, int n) {
   const int tz = tile_tz(n);
@@ -451,19 +467,29 @@ size_t assign_fixed_bytes(int n, int interlace) { return kHead + (size_t)(1 + in
 
 // Head of an assignment scratch: zero the weight sum and set the largest |w|
 // (1.0 for unit weights, else from the weights). Kernels only.
-static hipError_t fixed_head(const float* w, int64_t np, unsigned* head, hipStream_t s) {
+// npd: the caller's device-side count, or null: np is stored at byte 16 of
+// the head; returns through npd_out the pointer the kernels read.
+static hipError_t fixed_head(const float* w, int64_t np, const int64_t* npd, unsigned* head,
+                             const int64_t** npd_out, hipStream_t s) {
   hipError_t e = launch_fill_u32(head, 0u, kHead / 4, s);
   if (e != hipSuccess) return e;
+  if (!npd) {
+    int64_t* slot = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(head) + 16);
+    e = launch_set_i64(slot, np, s);
+    if (e != hipSuccess) return e;
+    npd = slot;
+  }
+  *npd_out = npd;
   if (!w) return launch_fill_u32(head, 0x3f800000u, 1, s);
   int64_t blocks = (np + 255) / 256;
   if (blocks > 4096) blocks = 4096;
-  hipLaunchKernelGGL(k_weight_max, dim3((unsigned)blocks), dim3(256), 0, s, w, np, head);
+  hipLaunchKernelGGL(k_weight_max, dim3((unsigned)blocks), dim3(256), 0, s, w, npd, head);
   return hipGetLastError();
 }
 
 hipError_t launch_assign_tiled(const float* ux, const float* uy, const float* uz, const float* w, int64_t np, int n,
                                int window, int interlace, int accumulate, float* grids, double* wsum, int32_t* err,
-                               void* scratch, size_t scratch_bytes, hipStream_t s) {
+                               void* scratch, size_t scratch_bytes, hipStream_t s, const int64_t* npd) {
   const int tz = tile_tz(n);
   const size_t need = assign_tiled_bytes(np, n);
   if (!tz || need == 0 || need > scratch_bytes || !scratch || interlace < 0 || interlace > 1)
@@ -479,16 +505,17 @@ hipError_t launch_assign_tiled(const float* ux, const float* uy, const float* uz
   int32_t* rank = offs + align256((size_t)(nt + 1) * sizeof(int32_t)) / sizeof(int32_t);
   hipError_t e = launch_fill_u32(count, 0u, nt, s);
   if (e != hipSuccess) return e;
-  e = fixed_head(w, np, head, s);
+  const int64_t* np_dev = nullptr;
+  e = fixed_head(w, np, npd, head, &np_dev, s);
   if (e != hipSuccess) return e;
   int64_t blocks = (np + 255) / 256;
   if (blocks > 16384) blocks = 16384;
-  hipLaunchKernelGGL(k_tile_count, dim3((unsigned)blocks), dim3(256), 0, s, ux, uy, uz, w, np, n, ntx, ntz, tz, count,
-                     rank, head, wsum_fx, err);
+  hipLaunchKernelGGL(k_tile_count, dim3((unsigned)blocks), dim3(256), 0, s, ux, uy, uz, w, np_dev, n, ntx, ntz, tz,
+                     count, rank, head, wsum_fx, err);
   hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, count, nt, offs);
-  hipLaunchKernelGGL(k_tile_scatter, dim3((unsigned)blocks), dim3(256), 0, s, ux, uy, uz, w, np, n, ntx, ntz, tz,
+  hipLaunchKernelGGL(k_tile_scatter, dim3((unsigned)blocks), dim3(256), 0, s, ux, uy, uz, w, np_dev, n, ntx, ntz, tz,
                      offs, rank, sorted);
-#define TCASE(WIN, TZV)                                                                                         if (window == WIN && tz == TZV) {                                                                               hipLaunchKernelGGL((k_assign_tiles<WIN, TZV>), dim3((unsigned)nt), dim3(256), 0, s, sorted, offs, n, ntx,                        ntz, interlace, accumulate, np, head, wsum_fx, grids, wsum);                                                        return hipGetLastError();                                                                                   }
+#define TCASE(WIN, TZV)                                                                                         if (window == WIN && tz == TZV) {                                                                               hipLaunchKernelGGL((k_assign_tiles<WIN, TZV>), dim3((unsigned)nt), dim3(256), 0, s, sorted, offs, n, ntx,                        ntz, interlace, accumulate, np_dev, head, wsum_fx, grids, wsum);                                                        return hipGetLastError();                                                                                   }
   TCASE(0, 64) TCASE(0, 32) TCASE(0, 16) TCASE(0, 8) TCASE(1, 64) TCASE(1, 32) TCASE(1, 16) TCASE(1, 8)
 #undef TCASE
   return hipErrorInvalidValue;
@@ -496,7 +523,7 @@ hipError_t launch_assign_tiled(const float* ux, const float* uy, const float* uz
 
 hipError_t launch_assign(const float* ux, const float* uy, const float* uz, const float* w, int64_t np,
                          int n, int window, int interlace, int accumulate, float* grids, double* wsum, int32_t* err,
-                         void* scratch, size_t scratch_bytes, hipStream_t s) {
+                         void* scratch, size_t scratch_bytes, hipStream_t s, const int64_t* npd) {
   const int64_t count = (int64_t)(1 + interlace) * n * n * n;
   if (np <= 0) {
     if (accumulate) return hipSuccess;
@@ -511,21 +538,23 @@ hipError_t launch_assign(const float* ux, const float* uy, const float* uz, cons
     unsigned long long* gfx = reinterpret_cast<unsigned long long*>(reinterpret_cast<char*>(scratch) + kHead);
     hipError_t e = launch_fill_u32(gfx, 0u, 2 * count, s);
     if (e != hipSuccess) return e;
-    e = fixed_head(w, np, head, s);
+    const int64_t* np_dev = nullptr;
+    e = fixed_head(w, np, npd, head, &np_dev, s);
     if (e != hipSuccess) return e;
     if (window == 0)
-      hipLaunchKernelGGL((k_assign_fixed<0>), dim3((unsigned)blocks), dim3(256), 0, s, ux, uy, uz, w, np, n, interlace,
-                         head, gfx, wsum_fx, err);
+      hipLaunchKernelGGL((k_assign_fixed<0>), dim3((unsigned)blocks), dim3(256), 0, s, ux, uy, uz, w, np_dev, n,
+                         interlace, head, gfx, wsum_fx, err);
     else
-      hipLaunchKernelGGL((k_assign_fixed<1>), dim3((unsigned)blocks), dim3(256), 0, s, ux, uy, uz, w, np, n, interlace,
-                         head, gfx, wsum_fx, err);
+      hipLaunchKernelGGL((k_assign_fixed<1>), dim3((unsigned)blocks), dim3(256), 0, s, ux, uy, uz, w, np_dev, n,
+                         interlace, head, gfx, wsum_fx, err);
     int64_t cb = (count + 255) / 256;
     if (cb > 16384) cb = 16384;
-    hipLaunchKernelGGL(k_fixed_to_float, dim3((unsigned)cb), dim3(256), 0, s, gfx, count, np, head, wsum_fx,
+    hipLaunchKernelGGL(k_fixed_to_float, dim3((unsigned)cb), dim3(256), 0, s, gfx, count, np_dev, head, wsum_fx,
                        accumulate, grids, wsum);
     return hipGetLastError();
   }
   // no scratch: FP32 atomics on the grids (summation order varies between runs)
+  if (npd) return hipErrorInvalidValue;  // a device-side count needs the fixed-point path
   if (!accumulate) {
     hipError_t e = launch_fill_u32(grids, 0u, count, s);
     if (e != hipSuccess) return e;

@@ -34,6 +34,7 @@ struct PassDesc {
   int32_t in_rows, in_off;       // input row r holds FFT index (r - in_off) mod N
   int32_t out_rows, out_off;     // output row r receives FFT index (r - out_off) mod N
   int32_t nouter;
+  int32_t tiles;                 // FP32 lines of <= 128 points: 0 automatic, 1 16-column, 2 64-column tiles
 };
 
 // Shell / modal filter applied while loading the first inverse pass.
@@ -113,9 +114,14 @@ bool fft_size_supported(int n);
 size_t assign_fixed_bytes(int n, int interlace);
 // Fills `words` 32-bit words with v by a kernel (capturable, unlike a memset node).
 hipError_t launch_fill_u32(void* p, uint32_t v, int64_t words, hipStream_t s);
+// npd (optional): a device-side particle count the kernels read instead of np
+// (then np only bounds the launch grids and the scratch), so that a captured
+// graph can be replayed on catalogues of other sizes.
 hipError_t launch_assign(const float* ux, const float* uy, const float* uz, const float* w,
                          int64_t np, int n, int window, int interlace, int accumulate, float* grids,
-                         double* wsum, int32_t* err, void* scratch, size_t scratch_bytes, hipStream_t s);
+                         double* wsum, int32_t* err, void* scratch, size_t scratch_bytes, hipStream_t s,
+                         const int64_t* npd = nullptr);
+hipError_t launch_set_i64(int64_t* p, int64_t v, hipStream_t s);
 // Tiled assignment (no global atomics on the grids): bytes of scratch it needs
 // for np particles on an N^3 grid, 0 when N does not tile; accumulate = 0
 // overwrites the grids, 1 adds to them. Returns hipErrorInvalidValue when N
@@ -124,7 +130,7 @@ size_t assign_tiled_bytes(int64_t np, int n);
 bool assign_tiled_preferred(int n);
 hipError_t launch_assign_tiled(const float* ux, const float* uy, const float* uz, const float* w, int64_t np, int n,
                                int window, int interlace, int accumulate, float* grids, double* wsum, int32_t* err,
-                               void* scratch, size_t scratch_bytes, hipStream_t s);
+                               void* scratch, size_t scratch_bytes, hipStream_t s, const int64_t* npd = nullptr);
 
 // LOS combination and shell sums (los.hip).
 struct LosDesc {

@@ -537,7 +537,7 @@ hipError_t launch_c2c_f32(int n, int sign, const float2* in, float2* out, const 
                           const FilterDesc* f, const float2* tw, hipStream_t s) {
   // lines of at most 128 points: 64-column tiles (512-byte row pieces, 8 threads
   // per column) when the launch still has at least 2048 of them, else 16
-  const bool wide = n <= 128 && (int64_t)((p.ncols + 63) / 64) * p.nouter >= 2048;
+  const bool wide = n <= 128 && (p.tiles == 2 || (p.tiles == 0 && (int64_t)((p.ncols + 63) / 64) * p.nouter >= 2048));
 #define CASE(NN)                                                                                  \
   case NN:                                                                                        \
     if constexpr (NN <= 128)                                                                      \

@@ -78,23 +78,38 @@ def uneven_batch():
     nl, nm = info.nl, C.batch_workload(0, 128).nmodes
     order = [sizes.index(n) for _, n in mocks]
     dv = [[torch.as_tensor(u[a]).to(DEV) for u in cats] for a in range(3)]
-    B_all = torch.zeros((len(mocks), nl, info.ntri), dtype=torch.float64, device=DEV)
-    alpha_all = torch.zeros((len(mocks), nl * nm), dtype=torch.float64, device=DEV)
-    beta_all = torch.zeros((len(mocks), nl * nm), dtype=torch.float64, device=DEV)
-    cov = torch.zeros((nl * nm, nl * nm), dtype=torch.float64, device=DEV)
-    B.bsp_batch_run([plans[n].handle for n in sizes], order, dv[0], dv[1], dv[2], None,
-                    [u[0].size for u in cats], B.BSP_BF16X3, B_all, alpha_all, beta_all, cov)
-    plans[128].sync()
+    outs = {}
+    # graph replay, graph replay again (the kept graphs), and plain calls
+    for mode, flags in (("graph", B.BSP_BATCH_GRAPH), ("graph2", B.BSP_BATCH_GRAPH), ("plain", 0)):
+        say("batch run", mode)
+        B_all = torch.zeros((len(mocks), nl, info.ntri), dtype=torch.float64, device=DEV)
+        alpha_all = torch.zeros((len(mocks), nl * nm), dtype=torch.float64, device=DEV)
+        beta_all = torch.zeros((len(mocks), nl * nm), dtype=torch.float64, device=DEV)
+        cov = torch.zeros((nl * nm, nl * nm), dtype=torch.float64, device=DEV)
+        B.bsp_batch_run([plans[n].handle for n in sizes], order, dv[0], dv[1], dv[2], None,
+                        [u[0].size for u in cats], B.BSP_BF16X3, B_all, alpha_all, beta_all, cov, flags)
+        plans[128].sync()
+        outs[mode] = (B_all.cpu().numpy(), alpha_all.cpu().numpy(), beta_all.cpu().numpy(), cov.cpu().numpy())
     counts = {n: plans[n].counts.copy() for n in sizes}
     kept = {n: plans[n].kept.copy() for n in sizes}
-    out = (B_all.cpu().numpy(), alpha_all.cpu().numpy(), beta_all.cpu().numpy(), cov.cpu().numpy())
     for p in plans.values():
         p.close()
-    return mocks, refs, counts, kept, out, nl, nm
+    return mocks, refs, counts, kept, outs, nl, nm
+
+
+def test_uneven_batch_graph_replay_is_bit_identical(uneven_batch):
+    """The graph-captured replay and the plain per-mock calls give the same
+    bits (the path is reproducible and the graph replays the same kernels)."""
+    mocks, refs, counts, kept, outs, nl, nm = uneven_batch
+    for a, b in zip(outs["graph"], outs["plain"]):
+        assert np.array_equal(a, b)
+    for a, b in zip(outs["graph"], outs["graph2"]):
+        assert np.array_equal(a, b)
 
 
 def test_uneven_batch_against_oracle(uneven_batch):
-    mocks, refs, counts, kept, (B_all, alpha_all, beta_all, cov), nl, nm = uneven_batch
+    mocks, refs, counts, kept, outs, nl, nm = uneven_batch
+    B_all, alpha_all, beta_all, cov = outs["graph"]
     ko = refs[0]["modal_kept"]
     for n, c in counts.items():
         assert np.array_equal(c, refs[0]["counts"]), n
@@ -133,5 +148,7 @@ def test_batch_run_rejects_mismatched_plans():
     cov = torch.zeros((12, 12), dtype=torch.float64, device=DEV)
     with pytest.raises(B.BspError):
         B.bsp_batch_run([a.handle, b.handle], [0, 1], u, u, u, None, [10, 10], B.BSP_FP32, Ball, alpha, None, cov)
+    with pytest.raises(B.BspError):
+        B.bsp_batch_run([a.handle, b.handle], [0, 1], u, u, u, None, [10, 10], B.BSP_FP32, Ball, alpha, None, cov, 0)
     a.close()
     b.close()
