@@ -314,6 +314,7 @@ struct bsp_plan_s {
   int32_t* d_tri_tidx = nullptr;
   int32_t* d_combo = nullptr;
   double* d_L = nullptr;
+  double* d_Linv = nullptr;          // inverse of the kept modes' Cholesky factor
   int32_t* d_piv = nullptr;          // kept modes in the order orthonormalised, then the rank
   double drop_tol = 0.0;             // relative residual below which a mode is dropped (0: keep all)
   std::vector<int32_t> piv_h;
@@ -1247,6 +1248,7 @@ bsp_status bsp_plan_create(bsp_plan* out, const bsp_geom* g, const bsp_modal_bas
          (p->d_gidx = upload(p, p->gidx)) && (p->d_sidx = upload(p, p->sidx)) && (p->d_urow = upload(p, urow)) &&
          (p->d_grow = upload(p, grow)) && (p->d_L = dalloc<double>(p, (size_t)p->nmodes * p->nmodes)) &&
          (p->d_piv = dalloc<int32_t>(p, (size_t)p->nmodes + 1)) &&
+         (p->d_Linv = dalloc<double>(p, (size_t)p->nmodes * p->nmodes)) &&
          (p->d_sn = dalloc<double>(p, 2 * (size_t)p->nmodes));
   }
   ok = ok && build_main(p, false);  // candidate schedule: bounds the workspace before the counts exist
@@ -1667,6 +1669,7 @@ bsp_status bsp_precompute(bsp_plan p) {
     p->piv_h.resize((size_t)nm + 1);
     HIPCHK(hipMemcpy(p->piv_h.data(), p->d_piv, p->piv_h.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
     p->modal_rank = p->piv_h[nm];
+    HIPCHK(launch_tri_inverse(p->d_L, p->d_piv, nm, p->d_Linv, p->stream));
     s = inverse_fields<double>(p, ones, 0, 2 * p->P, p->d_ones_ell, p->d_grow, p->d_tab64, p->d_rng64, f64, scr, L.fb64,
                                std::vector<int>(2 * p->P, p->c));
     if (s != BSP_OK) return s;
@@ -1943,7 +1946,7 @@ bsp_status estimate_from_spectrum(bsp_plan p, const float2* dl, bsp_precision pr
     if (nm > 128) return fail(p, BSP_ERR_ARG, "more than 128 modes");
     const double scale_b = 1.0 / ((double)K * std::pow(N, 9));
     HIPCHK(launch_modal_assemble(T, p->d_combo, nm, p->nl, scale_b, p->d_sn, nbar_dev, bo, p->stream));
-    HIPCHK(launch_tri_solve(p->d_L, p->d_piv, nm, p->nl, bo, ao, beo, p->stream));
+    HIPCHK(launch_modal_solve(p->d_Linv, p->d_piv, nm, p->nl, bo, ao, beo, p->stream));
   }
   return BSP_OK;
 }

@@ -275,6 +275,65 @@ __global__ __launch_bounds__(256) void k_tile_count(const float* __restrict__ ux
   if (bad) atomicOr(err, 1);
 }
 
+// The same count with the tile histogram of each workgroup in LDS, for grids
+// of at most kPrivTiles tiles: a workgroup takes a contiguous range of `per`
+// particles, ranks them in its LDS histogram, then adds each nonzero bin to
+// the global count with one atomic that returns the bin's base, and a second
+// pass adds that base to the ranks. Few workgroups touch a tile, so the global
+// atomics do not queue on the busy tiles of small clustered catalogues.
+constexpr int kPrivTiles = 16384;
+
+__global__ __launch_bounds__(256) void k_tile_count_lds(const float* __restrict__ ux, const float* __restrict__ uy,
+                                                        const float* __restrict__ uz, const float* __restrict__ w,
+                                                        const int64_t* __restrict__ npd, int64_t per, int n, int ntx,
+                                                        int ntz, int tz, int nt, int32_t* __restrict__ count,
+                                                        int32_t* __restrict__ rank,
+                                                        const unsigned* __restrict__ wmax_bits,
+                                                        unsigned long long* __restrict__ wsum_fx,
+                                                        int32_t* __restrict__ err) {
+  extern __shared__ int32_t hist[];
+  const int64_t np = *npd;
+  const float fn = (float)n;
+  const int sh = fixed_shift(*wmax_bits, np);
+  for (int k = threadIdx.x; k < nt; k += blockDim.x) hist[k] = 0;
+  __syncthreads();
+  const int64_t i0 = (int64_t)blockIdx.x * per;
+  const int64_t i1 = i0 + per < np ? i0 + per : np;
+  long long acc = 0;
+  int bad = 0;
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    const float x = ux[i], y = uy[i], z = uz[i];
+    const float wt = w ? w[i] : 1.0f;
+    if (!valid_particle(x, y, z, wt, fn)) {
+      bad = 1;
+      continue;
+    }
+    acc += to_fixed((double)wt, sh);
+    const int key = (((int)x / TXY) * ntx + (int)y / TXY) * ntz + (int)z / tz;
+    rank[i] = atomicAdd(&hist[key], 1);
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < nt; k += blockDim.x)
+    if (hist[k] > 0) hist[k] = atomicAdd(count + k, hist[k]);
+  __syncthreads();
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += blockDim.x) {
+    const float x = ux[i], y = uy[i], z = uz[i];
+    const float wt = w ? w[i] : 1.0f;
+    if (!valid_particle(x, y, z, wt, fn)) continue;
+    const int key = (((int)x / TXY) * ntx + (int)y / TXY) * ntz + (int)z / tz;
+    rank[i] += hist[key];
+  }
+  __shared__ long long red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && red[0] != 0) atomicAdd(wsum_fx, (unsigned long long)red[0]);
+  if (bad) atomicOr(err, 1);
+}
+
 // Exclusive prefix sum of count[0..nt) into offs[0..nt], one workgroup of 1024
 // threads, each scanning a contiguous run.
 __global__ __launch_bounds__(1024) void k_tile_scan(const int32_t* __restrict__ count, int nt,
@@ -510,8 +569,17 @@ hipError_t launch_assign_tiled(const float* ux, const float* uy, const float* uz
   if (e != hipSuccess) return e;
   int64_t blocks = (np + 255) / 256;
   if (blocks > 16384) blocks = 16384;
-  hipLaunchKernelGGL(k_tile_count, dim3((unsigned)blocks), dim3(256), 0, s, ux, uy, uz, w, np_dev, n, ntx, ntz, tz,
-                     count, rank, head, wsum_fx, err);
+  if (nt <= kPrivTiles) {
+    // about 8 particles per thread, and at most 1024 workgroups touching a tile
+    int64_t per = 2048;
+    while ((np + per - 1) / per > 1024) per *= 2;
+    const int64_t cb = (np + per - 1) / per;
+    hipLaunchKernelGGL(k_tile_count_lds, dim3((unsigned)cb), dim3(256), (size_t)nt * sizeof(int32_t), s, ux, uy, uz,
+                       w, np_dev, per, n, ntx, ntz, tz, nt, count, rank, head, wsum_fx, err);
+  } else {
+    hipLaunchKernelGGL(k_tile_count, dim3((unsigned)blocks), dim3(256), 0, s, ux, uy, uz, w, np_dev, n, ntx, ntz, tz,
+                       count, rank, head, wsum_fx, err);
+  }
   hipLaunchKernelGGL(k_tile_scan, dim3(1), dim3(1024), 0, s, count, nt, offs);
   hipLaunchKernelGGL(k_tile_scatter, dim3((unsigned)blocks), dim3(256), 0, s, ux, uy, uz, w, np_dev, n, ntx, ntz, tz,
                      offs, rank, sorted);

@@ -190,8 +190,9 @@ hipError_t launch_sn_assemble(const double* T, const int32_t* sidx, int nmodes, 
                               double* sn, hipStream_t s);
 hipError_t launch_cholesky(double* A, double* W, int n, double tol, int32_t* piv, int32_t* err,
                            hipStream_t s);
-hipError_t launch_tri_solve(const double* L, const int32_t* piv, int n, int nrhs, const double* b,
-                            double* alpha, double* beta, hipStream_t s);
+hipError_t launch_tri_inverse(const double* L, const int32_t* piv, int n, double* Linv, hipStream_t s);
+hipError_t launch_modal_solve(const double* Linv, const int32_t* piv, int n, int nrhs, const double* b,
+                              double* alpha, double* beta, hipStream_t s);
 hipError_t launch_covariance(const double* x, int m, int d, double* cov, hipStream_t s);
 hipError_t launch_scale_scalar(const double* x, double scale, double* y, hipStream_t s);
 

@@ -181,46 +181,50 @@ __global__ __launch_bounds__(256) void k_cholesky_pivoted(double* __restrict__ A
   }
 }
 
+// Inverse of the lower Cholesky factor of the kept modes (rank = piv[n] rows),
+// once per geometry: thread j solves L x = e_j by forward substitution into
+// column j of Linv. Entries outside the lower rank x rank block are zero.
+__global__ __launch_bounds__(128) void k_tri_inverse(const double* __restrict__ L, const int32_t* __restrict__ piv,
+                                                     int n, double* __restrict__ Linv) {
+  const int rank = piv[n];
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) Linv[idx] = 0.0;
+  __syncthreads();
+  const int j = threadIdx.x;
+  if (j >= rank) return;
+  for (int i = j; i < rank; ++i) {
+    double s = (i == j) ? 1.0 : 0.0;
+    for (int k = j; k < i; ++k) s -= L[(int64_t)i * n + k] * Linv[(int64_t)k * n + j];
+    Linv[(int64_t)i * n + j] = s / L[(int64_t)i * n + i];
+  }
+}
+
 // Coefficients on the kept, orthonormalised modes for nrhs right-hand sides
-// (one workgroup each): alpha_i = (L^-1 b_S)_i for i < rank (0 past it),
-// beta_{piv[i]} = (L^-T alpha)_i on the kept modes and 0 on the others.
-__global__ __launch_bounds__(256) void k_tri_solve(const double* __restrict__ L, const int32_t* __restrict__ piv,
-                                                   int n, const double* __restrict__ b, double* __restrict__ alpha,
-                                                   double* __restrict__ beta) {
+// (one workgroup each), as products with the precomputed inverse factor:
+// alpha_i = sum_k Linv_ik b_piv[k] for i < rank (0 past it), and on the kept
+// modes beta_piv[i] = sum_k Linv_ki alpha_k (beta = L^-T alpha), 0 on the
+// dropped ones. Every sum runs in a fixed order.
+__global__ __launch_bounds__(128) void k_modal_solve(const double* __restrict__ Linv, const int32_t* __restrict__ piv,
+                                                     int n, const double* __restrict__ b, double* __restrict__ alpha,
+                                                     double* __restrict__ beta) {
+  __shared__ double al[128];
   const int r = blockIdx.x;
   const int rank = piv[n];
   const double* bb = b + (int64_t)r * n;
-  double* al = alpha + (int64_t)r * n;
-  double* be = beta + (int64_t)r * n;
-  __shared__ double red[256];
+  double* ao = alpha + (int64_t)r * n;
+  double* bo = beta + (int64_t)r * n;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    be[i] = 0.0;
-    if (i >= rank) al[i] = 0.0;
+    double a = 0.0;
+    if (i < rank)
+      for (int k = 0; k <= i; ++k) a += Linv[(int64_t)i * n + k] * bb[piv[k]];
+    al[i] = a;
+    ao[i] = a;
+    bo[i] = 0.0;
   }
   __syncthreads();
-  for (int i = 0; i < rank; ++i) {
-    double s = 0.0;
-    for (int k = threadIdx.x; k < i; k += blockDim.x) s += L[(int64_t)i * n + k] * al[k];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-      if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) al[i] = (bb[piv[i]] - red[0]) / L[(int64_t)i * n + i];
-    __syncthreads();
-  }
-  for (int i = rank - 1; i >= 0; --i) {
-    double s = 0.0;
-    for (int k = i + 1 + threadIdx.x; k < rank; k += blockDim.x) s += L[(int64_t)k * n + i] * be[piv[k]];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-      if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) be[piv[i]] = (al[i] - red[0]) / L[(int64_t)i * n + i];
-    __syncthreads();
+  for (int i = threadIdx.x; i < rank; i += blockDim.x) {
+    double v = 0.0;
+    for (int k = i; k < rank; ++k) v += Linv[(int64_t)k * n + i] * al[k];
+    bo[piv[i]] = v;
   }
 }
 
@@ -294,10 +298,17 @@ hipError_t launch_cholesky(double* A, double* W, int n, double tol, int32_t* piv
   return hipGetLastError();
 }
 
-hipError_t launch_tri_solve(const double* L, const int32_t* piv, int n, int nrhs, const double* b, double* alpha,
-                            double* beta, hipStream_t s) {
+hipError_t launch_tri_inverse(const double* L, const int32_t* piv, int n, double* Linv, hipStream_t s) {
+  if (n < 1 || n > 128) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_tri_inverse, dim3(1), dim3(128), 0, s, L, piv, n, Linv);
+  return hipGetLastError();
+}
+
+hipError_t launch_modal_solve(const double* Linv, const int32_t* piv, int n, int nrhs, const double* b, double* alpha,
+                              double* beta, hipStream_t s) {
   if (nrhs <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_tri_solve, dim3(nrhs), dim3(256), 0, s, L, piv, n, b, alpha, beta);
+  if (n < 1 || n > 128) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_modal_solve, dim3(nrhs), dim3(128), 0, s, Linv, piv, n, b, alpha, beta);
   return hipGetLastError();
 }
 
