@@ -225,10 +225,12 @@ bsp_status bsp_fft_c2r(bsp_plan plan, int32_t n, int32_t batch, const void* in_c
 
 /* Line-of-sight Legendre moments delta^(l)(n), l = 0, 2, ..., lmax (the LOS
  * moment field defined with the power-spectrum multipoles, Sec. 2, evaluated
- * through x-hat product fields so the line of sight may vary): density
+ * through x-hat-weighted fields so the line of sight may vary): density
  * contrast rho/rho_bar - 1 of each grid (rho_bar = wsum / N^3), weighting by
- * x_hat products at the nodes, forward transforms, window compensation,
- * interlacing, Legendre contraction, delta^(l)(0) = 0.
+ * the real solid harmonics h_m(x_hat) of degree l (polynomials in the
+ * components of x_hat; 1 + 5 + 9 fields for lmax = 4) at the nodes, forward
+ * transforms, window compensation, interlacing, and the addition theorem
+ * delta^(l) = (2l+1) sum_m a_m h_m(k_hat) F_m; delta^(l)(0) = 0.
  * grids: device [1+interlace][N^3] densities from bsp_grid_assign; wsum: device
  * double[1]; delta_l: device compact spectra (see top). Uses the workspace. */
 bsp_status bsp_los_moments(bsp_plan plan, const float* grids, const double* wsum, void* delta_l);

@@ -1046,7 +1046,7 @@ bsp_status bsp_plan_create(bsp_plan* out, const bsp_geom* g, const bsp_modal_bas
   p->nbins = g->nbins;
   p->nl = g->lmax / 2 + 1;
   p->plane = g->los == 0 ? 1 : 0;
-  p->nlos = p->plane ? 1 : (g->lmax == 0 ? 1 : (g->lmax == 2 ? 7 : 22));
+  p->nlos = p->plane ? 1 : (g->lmax == 0 ? 1 : (g->lmax == 2 ? 6 : 15));
   p->ngrid = g->interlace ? 2 : 1;
   p->V = g->box * g->box * g->box;
   p->kf = 2.0 * M_PI / g->box;

@@ -22,6 +22,56 @@ template <typename V> __device__ __forceinline__ V cmul(V a, V b) {
 template <typename V> __device__ __forceinline__ V cconj(V a) { return V{a.x, -a.y}; }
 template <typename V, typename T> __device__ __forceinline__ V cscale(V a, T s) { return V{a.x * s, a.y * s}; }
 
+// ---------------------------------------------------------------- LOS harmonics
+// Weights of the line-of-sight fields: the field F_m = FT[h_m(x_hat) delta]
+// with h_0 = 1, then the five l = 2 and the nine l = 4 real solid harmonics of
+// the unit vector x_hat, as polynomials in its components (|x_hat| = 1 used
+// to write them with lower-degree terms):
+//   l = 2: zx, zy, x^2 - y^2, 2xy, 3z^2 - 1
+//   l = 4: 35z^4 - 30z^2 + 3, (7z^2 - 3)zx, (7z^2 - 3)zy, (7z^2 - 1)(x^2 - y^2),
+//          (7z^2 - 1)2xy, z(x^3 - 3xy^2), z(3x^2y - y^3), x^4 - 6x^2y^2 + y^4,
+//          4x^3y - 4xy^3.
+// The addition theorem L_l(k_hat . x_hat) = sum_m a_m h_m(k_hat) h_m(x_hat)
+// (a_m: los.hip) gives delta^(l)(k) = (2l+1) sum_m a_m h_m(k_hat) F_m(k).
+// Each weight is a sum of at most four terms coef x^ex y^ey z^ez.
+struct LosTerm { int8_t c, ex, ey, ez; };
+constexpr int kLosFields = 15;
+constexpr LosTerm kLosPoly[kLosFields][4] = {
+    {{1, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}},
+    {{1, 1, 0, 1}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}},
+    {{1, 0, 1, 1}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}},
+    {{1, 2, 0, 0}, {-1, 0, 2, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}},
+    {{2, 1, 1, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}},
+    {{3, 0, 0, 2}, {-1, 0, 0, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}},
+    {{35, 0, 0, 4}, {-30, 0, 0, 2}, {3, 0, 0, 0}, {0, 0, 0, 0}},
+    {{7, 1, 0, 3}, {-3, 1, 0, 1}, {0, 0, 0, 0}, {0, 0, 0, 0}},
+    {{7, 0, 1, 3}, {-3, 0, 1, 1}, {0, 0, 0, 0}, {0, 0, 0, 0}},
+    {{7, 2, 0, 2}, {-7, 0, 2, 2}, {-1, 2, 0, 0}, {1, 0, 2, 0}},
+    {{14, 1, 1, 2}, {-2, 1, 1, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}},
+    {{1, 3, 0, 1}, {-3, 1, 2, 1}, {0, 0, 0, 0}, {0, 0, 0, 0}},
+    {{3, 2, 1, 1}, {-1, 0, 3, 1}, {0, 0, 0, 0}, {0, 0, 0, 0}},
+    {{1, 4, 0, 0}, {-6, 2, 2, 0}, {1, 0, 4, 0}, {0, 0, 0, 0}},
+    {{4, 3, 1, 0}, {-4, 1, 3, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}}};
+
+template <int E, typename T> __device__ __forceinline__ T los_pow(T x) {
+  if constexpr (E == 0) return (T)1;
+  else if constexpr (E == 1) return x;
+  else if constexpr (E == 2) return x * x;
+  else if constexpr (E == 3) return x * x * x;
+  else return (x * x) * (x * x);
+}
+
+// h_F(x, y, z), the field index and its terms resolved at compile time.
+template <int F, typename T> __device__ __forceinline__ T los_harmonic(T x, T y, T z) {
+  T v = (T)0;
+  constexpr LosTerm a = kLosPoly[F][0], b = kLosPoly[F][1], c = kLosPoly[F][2], d = kLosPoly[F][3];
+  v += (T)a.c * los_pow<a.ex>(x) * los_pow<a.ey>(y) * los_pow<a.ez>(z);
+  if constexpr (b.c != 0) v += (T)b.c * los_pow<b.ex>(x) * los_pow<b.ey>(y) * los_pow<b.ez>(z);
+  if constexpr (c.c != 0) v += (T)c.c * los_pow<c.ex>(x) * los_pow<c.ey>(y) * los_pow<c.ez>(z);
+  if constexpr (d.c != 0) v += (T)d.c * los_pow<d.ex>(x) * los_pow<d.ey>(y) * los_pow<d.ez>(z);
+  return v;
+}
+
 // ---------------------------------------------------------------- launch params
 
 // Strided column pass of a 3-D transform (see fft.hip).
@@ -55,7 +105,7 @@ struct FilterDesc {
 
 // Forward z pass with line-of-sight weighting.
 struct FwdZDesc {
-  int32_t ngrid, nlos;           // grids (1 or 2), LOS fields per grid (1, 7, 22)
+  int32_t ngrid, nlos;           // grids (1 or 2), LOS fields per grid (1, 6, 15)
   int32_t contrast;              // 1: input is a density, form rho / rho_bar - 1
   const double* wsum;            // sum of weights (device), used when contrast
   double shift[2];               // node offset of each grid (0, 1/2)

@@ -3,10 +3,10 @@
 //
 //   fwd_z : real lines along z -> half-complex, two real lines packed per
 //           complex transform; optionally forms the density contrast and the
-//           line-of-sight weights x_i x_j ..., so that one read of the grid
-//           feeds every weighted field delta(x) prod x_hat (the LOS moment field
-//           of the power-spectrum section of the paper, expanded in x-hat
-//           products).
+//           line-of-sight weights, so that one read of the grid feeds every
+//           weighted field h_m(x_hat) delta(x) (the LOS moment field of the
+//           power-spectrum section of the paper, expanded in the real solid
+//           harmonics h_m of x_hat: 1 + 5 + 9 fields for l <= 4).
 //   c2c   : a strided column pass along y or x; a workgroup owns W consecutive
 //           inner columns (one 128-byte row segment) and all N rows, so every
 //           global access is a coalesced row segment. Input and output rows may
@@ -191,25 +191,10 @@ template <typename V> __device__ __forceinline__ V nt_load(const V* p) {
   return V{v.x, v.y};
 }
 
-// exponents (x, y, z) of the x-hat product of each LOS field: the empty
-// product, the 6 sorted pairs and the 15 sorted quadruples over {x, y, z}.
-constexpr int8_t c_los_exp[22][3] = {
-    {0, 0, 0},
-    {2, 0, 0}, {1, 1, 0}, {1, 0, 1}, {0, 2, 0}, {0, 1, 1}, {0, 0, 2},
-    {4, 0, 0}, {3, 1, 0}, {3, 0, 1}, {2, 2, 0}, {2, 1, 1}, {2, 0, 2}, {1, 3, 0},
-    {1, 2, 1}, {1, 1, 2}, {1, 0, 3}, {0, 4, 0}, {0, 3, 1}, {0, 2, 2}, {0, 1, 3},
-    {0, 0, 4}};
-
-template <int E, typename T> __device__ __forceinline__ T ipow(T x) {
-  if constexpr (E == 0) return (T)1;
-  else if constexpr (E == 1) return x;
-  else if constexpr (E == 2) return x * x;
-  else if constexpr (E == 3) return x * x * x;
-  else return (x * x) * (x * x);
-}
-
+// Weight of LOS field F at a node: the real solid harmonic h_F(x_hat) (see
+// kLosPoly), evaluated in the transform's precision.
 template <int F, typename T> __device__ __forceinline__ T los_weight(T hx, T hy, T hz) {
-  return ipow<c_los_exp[F][0]>(hx) * ipow<c_los_exp[F][1]>(hy) * ipow<c_los_exp[F][2]>(hz);
+  return los_harmonic<F, T>(hx, hy, hz);
 }
 
 // One packed pair (F0, F0+1) of LOS fields for every line of the block, then
@@ -471,8 +456,8 @@ static hipError_t fwd_z_impl(int n, const T* in, cplx_t<T>* out, const FwdZDesc&
     constexpr int L = 256 / NT;                                                         \
     dim3 grid((unsigned)(((int64_t)NN * NN + L * FZ_GROUPS - 1) / (L * FZ_GROUPS)), (unsigned)d.ngrid); \
     if (d.nlos == 1) hipLaunchKernelGGL((k_fwd_z<T, NN, 1>), grid, dim3(L * NT), 0, s, in, out, d, tw);   \
-    else if (d.nlos == 7) hipLaunchKernelGGL((k_fwd_z<T, NN, 7>), grid, dim3(L * NT), 0, s, in, out, d, tw); \
-    else if (d.nlos == 22) hipLaunchKernelGGL((k_fwd_z<T, NN, 22>), grid, dim3(L * NT), 0, s, in, out, d, tw); \
+    else if (d.nlos == 6) hipLaunchKernelGGL((k_fwd_z<T, NN, 6>), grid, dim3(L * NT), 0, s, in, out, d, tw); \
+    else if (d.nlos == 15) hipLaunchKernelGGL((k_fwd_z<T, NN, 15>), grid, dim3(L * NT), 0, s, in, out, d, tw); \
     else return hipErrorInvalidValue;                                                   \
     return hipGetLastError();                                                           \
   }

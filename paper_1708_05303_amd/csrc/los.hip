@@ -2,12 +2,15 @@
 // of the x-hat-weighted fields, and the shell sums of |delta^(0)|^2.
 //
 // The LOS moment field of the paper's power-spectrum section is
-//   delta^(l)(k) = (2l+1) int d^3x e^{-ik.x} delta(x) L_l(k_hat . x_hat);
-// with mu = k_hat . x_hat, L_2 = (3 mu^2 - 1)/2 and L_4 = (35 mu^4 - 30 mu^2 + 3)/8,
-// so with A2 = FT[delta mu^2] = sum_{i<=j} m_ij k_i k_j F_ij and
-// A4 = FT[delta mu^4] = sum_{i<=j<=k<=l} m k_i k_j k_k k_l F_ijkl (m the
-// multinomial multiplicities):
-//   delta^0 = F, delta^2 = 5 (3 A2 - F) / 2, delta^4 = 9 (35 A4 - 30 A2 + 3 F) / 8.
+//   delta^(l)(k) = (2l+1) int d^3x e^{-ik.x} delta(x) L_l(k_hat . x_hat).
+// By the addition theorem L_l(k_hat . x_hat) = sum_m a_m h_m(k_hat) h_m(x_hat)
+// over the 2l+1 real solid harmonics h_m of degree l (their polynomials are
+// listed with kLosPoly), so with F_m = FT[h_m(x_hat) delta]
+//   delta^(l)(k) = (2l+1) sum_m a_m h_m(k_hat) F_m(k):
+// 1 + 5 + 9 weighted transforms for l <= 4, each F_m a single multipole of
+// the line of sight (no cancellation between the l = 0, 2, 4 parts, which the
+// products of x-hat components would carry). Plane parallel: the one field F
+// and delta^(l) = (2l+1) L_l(k_hat_z) F.
 // The mass-assignment window is divided out (CIC: prod sinc^2(pi n_a / N)) and
 // two interlaced grids are averaged after the half-cell phase
 // exp(i pi (nx + ny + nz) / N) is applied to the shifted one.
@@ -15,16 +18,20 @@
 
 namespace bsp {
 
-// Exponents of (x_hat, y_hat, z_hat) and multinomial multiplicities of the 22
-// weighted fields: 1, the 6 of mu^2 (i <= j), the 15 of mu^4 (i <= j <= k <= l).
-// Compile-time tables: the kernel's loops over them unroll and the powers fold.
-constexpr int8_t kMonoExp[22][3] = {
-    {0, 0, 0},
-    {2, 0, 0}, {1, 1, 0}, {1, 0, 1}, {0, 2, 0}, {0, 1, 1}, {0, 0, 2},
-    {4, 0, 0}, {3, 1, 0}, {3, 0, 1}, {2, 2, 0}, {2, 1, 1}, {2, 0, 2}, {1, 3, 0},
-    {1, 2, 1}, {1, 1, 2}, {1, 0, 3}, {0, 4, 0}, {0, 3, 1}, {0, 2, 2}, {0, 1, 3},
-    {0, 0, 4}};
-constexpr double kMonoMult[22] = {1, 1, 2, 2, 1, 2, 1, 1, 4, 4, 6, 12, 6, 4, 12, 12, 4, 1, 4, 6, 4, 1};
+// Addition-theorem coefficients a_m of the harmonics (kLosPoly order): l = 2
+// (fields 1..5) and l = 4 (fields 6..14), from
+// 2 (l-m)!/(l+m)! times the squared prefactors of the associated Legendre
+// functions written as these polynomials.
+constexpr double kLosCoef[kLosFields] = {1.0,
+                                         3.0, 3.0, 0.75, 0.75, 0.25,
+                                         1.0 / 64, 5.0 / 8, 5.0 / 8, 5.0 / 16, 5.0 / 16, 35.0 / 8, 35.0 / 8,
+                                         35.0 / 64, 35.0 / 64};
+
+template <int M> __device__ __forceinline__ void add_harmonic(double2& acc, const double* kh, double2 f) {
+  const double h = kLosCoef[M] * los_harmonic<M, double>(kh[0], kh[1], kh[2]);
+  acc.x += h * f.x;
+  acc.y += h * f.y;
+}
 
 __device__ __forceinline__ double sinc_pi(int n, int N) {
   if (n == 0) return 1.0;
@@ -32,7 +39,7 @@ __device__ __forceinline__ double sinc_pi(int n, int N) {
   return sin(a) / a;
 }
 
-// One mode per thread. NLOS weighted fields per grid (1, 7 or 22) and NG grids
+// One mode per thread. NLOS weighted fields per grid (1, 6 or 15) and NG grids
 // are template parameters so that all NG x NLOS loads of a mode are issued
 // before its arithmetic.
 template <typename T, int NLOS, int NG>
@@ -83,48 +90,39 @@ __global__ __launch_bounds__(256) void k_los_combine(const cplx_t<T>* __restrict
   };
   const double inv = 1.0 / sqrt((double)n2);
   const double kh[3] = {nx * inv, ny * inv, nz * inv};
-  auto mono = [&](int t) -> double {
-    double m = kMonoMult[t];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int e = 0; e < kMonoExp[t][a]; ++e) m *= kh[a];
-    return m;
-  };
   const double2 F0 = F(0);
   dl[idx] = V{(T)F0.x, (T)F0.y};
   if (d.lmax < 2) return;
-  double2 A2{0.0, 0.0};
+  double2 D2{0.0, 0.0}, D4{0.0, 0.0};
   if constexpr (NLOS == 1) {
-    // plane-parallel: mu = k_hat . z_hat for every node
-    const double m = kh[2] * kh[2];
-    A2 = double2{m * F0.x, m * F0.y};
+    // plane parallel: mu = k_hat_z for every node
+    const double m2 = kh[2] * kh[2];
+    const double L2 = 0.5 * (3.0 * m2 - 1.0), L4 = (35.0 * m2 * m2 - 30.0 * m2 + 3.0) / 8.0;
+    D2 = double2{5.0 * L2 * F0.x, 5.0 * L2 * F0.y};
+    D4 = double2{9.0 * L4 * F0.x, 9.0 * L4 * F0.y};
   } else {
-#pragma unroll
-    for (int t = 1; t <= 6; ++t) {
-      const double m = mono(t);
-      const double2 f = F(t);
-      A2.x += m * f.x;
-      A2.y += m * f.y;
+    add_harmonic<1>(D2, kh, F(1));
+    add_harmonic<2>(D2, kh, F(2));
+    add_harmonic<3>(D2, kh, F(3));
+    add_harmonic<4>(D2, kh, F(4));
+    add_harmonic<5>(D2, kh, F(5));
+    D2 = double2{5.0 * D2.x, 5.0 * D2.y};
+    if constexpr (NLOS == 15) {
+      add_harmonic<6>(D4, kh, F(6));
+      add_harmonic<7>(D4, kh, F(7));
+      add_harmonic<8>(D4, kh, F(8));
+      add_harmonic<9>(D4, kh, F(9));
+      add_harmonic<10>(D4, kh, F(10));
+      add_harmonic<11>(D4, kh, F(11));
+      add_harmonic<12>(D4, kh, F(12));
+      add_harmonic<13>(D4, kh, F(13));
+      add_harmonic<14>(D4, kh, F(14));
+      D4 = double2{9.0 * D4.x, 9.0 * D4.y};
     }
   }
-  dl[cube + idx] = V{(T)(2.5 * (3.0 * A2.x - F0.x)), (T)(2.5 * (3.0 * A2.y - F0.y))};
+  dl[cube + idx] = V{(T)D2.x, (T)D2.y};
   if (d.lmax < 4) return;
-  double2 A4{0.0, 0.0};
-  if constexpr (NLOS == 1) {
-    const double m = kh[2] * kh[2] * kh[2] * kh[2];
-    A4 = double2{m * F0.x, m * F0.y};
-  } else if constexpr (NLOS == 22) {
-#pragma unroll
-    for (int t = 7; t <= 21; ++t) {
-      const double m = mono(t);
-      const double2 f = F(t);
-      A4.x += m * f.x;
-      A4.y += m * f.y;
-    }
-  }
-  dl[2 * cube + idx] = V{(T)(1.125 * (35.0 * A4.x - 30.0 * A2.x + 3.0 * F0.x)),
-                         (T)(1.125 * (35.0 * A4.y - 30.0 * A2.y + 3.0 * F0.y))};
+  dl[2 * cube + idx] = V{(T)D4.x, (T)D4.y};
 }
 
 // psum[b] += sum over the compact half cube of mult * |delta0|^2, mult = 2 for kz > 0
@@ -239,11 +237,11 @@ hipError_t launch_square(float* x, int64_t n, hipStream_t s) {
 }
 
 // The field count must match the moments asked for: one field (lmax 0, or a
-// plane-parallel line of sight), 7 (lmax 2) or 22 (lmax 4).
+// plane-parallel line of sight), 6 (lmax 2) or 15 (lmax 4).
 template <typename T>
 static hipError_t los_combine_impl(const cplx_t<T>* X, cplx_t<T>* delta_l, const LosDesc& d, hipStream_t s) {
   if (d.ngrid < 1 || d.ngrid > 2 || d.lmax < 0 || d.lmax > 4) return hipErrorInvalidValue;
-  const bool ok = d.nlos == 1 ? (d.plane || d.lmax == 0) : (d.nlos == 7 ? d.lmax <= 2 : d.nlos == 22);
+  const bool ok = d.nlos == 1 ? (d.plane || d.lmax == 0) : (d.nlos == 6 ? d.lmax <= 2 : d.nlos == 15);
   if (!ok) return hipErrorInvalidValue;
   const int64_t cube = (int64_t)(2 * d.c + 1) * (2 * d.c + 1) * d.cz;
   const dim3 grid((unsigned)((cube + 255) / 256));
@@ -252,7 +250,7 @@ static hipError_t los_combine_impl(const cplx_t<T>* X, cplx_t<T>* delta_l, const
     hipLaunchKernelGGL((k_los_combine<T, NL, G>), grid, dim3(256), 0, s, X, delta_l, d);              \
     return hipGetLastError();                                                                          \
   }
-  LCASE(1, 1) LCASE(1, 2) LCASE(7, 1) LCASE(7, 2) LCASE(22, 1) LCASE(22, 2)
+  LCASE(1, 1) LCASE(1, 2) LCASE(6, 1) LCASE(6, 2) LCASE(15, 1) LCASE(15, 2)
 #undef LCASE
   return hipErrorInvalidValue;
 }

@@ -302,7 +302,8 @@ def test_los_moments_against_oracle(los, interlace, lmax):
         ref = spec[li][idx]
         ref = np.where((idx[0] == 0) & (idx[1] == 0) & (idx[2] == 0), 0, ref)
         e = rel_norm(np.stack([vals.real, vals.imag]), np.stack([ref.real, ref.imag]))
-        assert e < 2e-5, (li, e)
+        say("  l", 2 * li, "err", e)
+        assert e < 1e-5, (li, e)
 
 
 @pytest.mark.parametrize("los,interlace,lmax", [(0, 0, 4), (1, 1, 4), (1, 0, 2)])
@@ -330,7 +331,7 @@ def test_power_multipoles_against_oracle(los, interlace, lmax):
     for li in range(info.nl):
         e = np.linalg.norm(got[li] - ref[li]) / max(np.linalg.norm(ref[li]), 0.01 * s0)
         say("  l", 2 * li, "err", e)
-        assert e < 2e-5, (li, e)
+        assert e < 1e-5, (li, e)
     plan.close()
 
 
@@ -366,9 +367,9 @@ def test_skew_spectra_against_oracle(n, nr, los, interlace, nb):
     ref, _ = O.skew_spectra(spec, n, nr, k0, dk, nb, box)
     s0 = np.linalg.norm(ref[0])
     for li in range(info.nl):
-        e = np.linalg.norm(got[li] - ref[li]) / max(np.linalg.norm(ref[li]), 0.05 * s0)
+        e = np.linalg.norm(got[li] - ref[li]) / max(np.linalg.norm(ref[li]), 0.01 * s0)
         say("  l", 2 * li, "err", e)
-        assert e < 1e-4, (li, e)
+        assert e < 1e-5, (li, e)
     plan.close()
 
 
@@ -410,7 +411,7 @@ def test_integrated_bispectrum_against_oracle(n, s, los, window, nb):
         scale = np.linalg.norm(np.abs(rP[:, li]).T @ np.abs(rdb)) / ns
         ei = np.linalg.norm(giB[li] - riB[li]) / scale
         say("  l", 2 * li, "P err", e, "iB err / term scale", ei)
-        assert e < 2e-5 and ei < 2e-5, (li, e, ei)
+        assert e < 1e-5 and ei < 1e-5, (li, e, ei)
     plan.close()
 
 
@@ -427,16 +428,9 @@ def test_integrated_bispectrum_rejects_bad_geometry():
 @pytest.mark.parametrize("prec,tol", [(B.BSP_FP32, 1e-5), (B.BSP_BF16X3, 1e-3)])
 def test_bispectrum_full_against_oracle(prec, tol):
     """B^(l1 l2 l3) for every combination (one LOS moment per side) against the
-    FP64 oracle; B^(l00) also against the whole path's B^l.
-
-    Errors are measured against max(||B^(l1 l2 l3)||, ||B^(000)||): the
-    rounding of the x_hat-weighted transforms every combination is built from
-    scales with |delta|, that is with the monopole, not with the size of each
-    multipole. On this 32^3 catalogue B^(400) is 0.3 of the monopole, and its
-    FP32 error against its own norm ranges over 4e-6 to 1.2e-5 between runs
-    (the assignment's float atomics change the rounding pattern from run to
-    run; given the same grids the later stages repeat to the last bits of
-    their FP64 sums)."""
+    FP64 oracle, each against its own norm (floored at 1% of the monopole's);
+    B^(l00) also against the whole path's B^l. The path is reproducible, so
+    the errors are the same on every run."""
     say("bispectrum-full", prec)
     n, box, k0, dk, nb = 32, 200.0, 2.0, 2.0, 4
     obs = np.array([-300.0, -200.0, -250.0])
@@ -465,13 +459,14 @@ def test_bispectrum_full_against_oracle(prec, tol):
     s0 = np.linalg.norm(ref[0])
     worst = 0.0
     for ci in range(nl ** 3):
-        e = np.linalg.norm(got[ci] - ref[ci]) / max(np.linalg.norm(ref[ci]), s0)
+        e = np.linalg.norm(got[ci] - ref[ci]) / max(np.linalg.norm(ref[ci]), 0.01 * s0)
+        say("  combination", combos[ci], "err", e)
         worst = max(worst, e)
         assert e < tol, (combos[ci], e)
     # two GPU results, each within tol of the oracle: their difference is bounded by 2 tol
     for li in range(nl):
         ci = combos.index((li, 0, 0))
-        assert np.linalg.norm(got[ci] - path[li]) <= 2 * tol * max(np.linalg.norm(path[li]), s0), li
+        assert np.linalg.norm(got[ci] - path[li]) <= 2 * tol * max(np.linalg.norm(path[li]), 0.01 * s0), li
     say("  worst combination error", worst)
     plan.close()
 
