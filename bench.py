@@ -2,8 +2,9 @@
 """Throughput of the bispectrum-multipole + modal estimator on one MI355X.
 
 One step = the whole hot path for one synthetic catalogue resident in HBM:
-CIC assignment to two interlaced 512^3 grids, 2 x 22 forward transforms with
-x-hat line-of-sight weights, Legendre moments l = 0, 2, 4, 90 shell fields and
+CIC assignment to two interlaced 512^3 grids, 2 x 15 forward transforms with
+line-of-sight weights (real solid harmonics of x-hat), Legendre moments
+l = 0, 2, 4, 90 shell fields and
 24 modal fields (inverse transforms), one triple reduction (binned B_0,2,4 on
 every closed triangle and 100 modal numerators per l), FP64 normalisation,
 shot noise and the Cholesky solves for beta. Geometry (triangle counts, Gram
@@ -24,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM = 8.0e12          # B/s
+TUNE_DB = os.path.join(ROOT, "paper_1708_05303_amd", "autotune_mi355x.json")
 MODAL_DROP_TOL = 1e-2      # the orthonormalisation drops modes whose relative residual falls below this
 PEAK_MFMA = {"fp32": 157.3e12, "bf16x3": 2.5e15, "fp16x3": 2.5e15, "bf16x1": 2.5e15}
 
@@ -207,7 +209,7 @@ def spectra_legs(B, torch, plan, wl, ux, uy, uz, npart, pbar_path, b_path, prec,
     return pm, sk, ib, full
 
 
-def batch_leg(B, torch, log_fn, nmocks=256, ncat_per_size=2, seed=4242):
+def batch_leg(B, torch, log_fn, nmocks=256, ncat_per_size=2, seed=4242, tune_db=None):
     """The uneven batch for covariances (Sec. 3.5, closing remark): nmocks
     mocks on assignment grids drawn uniformly from {128, 192, 256, 384}^3,
     one reduction geometry (N' = 128, 20 shells of 2 k_f, l <= 4, 50 modes,
@@ -234,6 +236,8 @@ def batch_leg(B, torch, log_fn, nmocks=256, ncat_per_size=2, seed=4242):
                     window=wl.window, interlace=wl.interlace, los=wl.los, observer=C.observer_grid_units(wl),
                     P=wl.P, nmodes=wl.nmodes, pfid=pfid, drop_tol=MODAL_DROP_TOL, device="cuda:0")
         pl.precompute()
+        if tune_db:
+            pl.autotune(B.BSP_BF16X3, tune_db)
         plans.append(pl)
     log_fn(f"batch: 4 plans in {time.time() - t0:.1f} s")
     t0 = time.time()
@@ -338,6 +342,8 @@ def main():
     ap.add_argument("--no-legs", action="store_true",
                     help="skip the power-spectrum, skew-spectrum, integrated and full multipole legs")
     ap.add_argument("--no-batch", action="store_true", help="skip the uneven-batch leg")
+    ap.add_argument("--tune-db", default=TUNE_DB,
+                    help="autotuning database (JSON); plans missing from it are timed and added; '' disables tuning")
     ap.add_argument("--batch-only", action="store_true",
                     help="only the uneven-batch leg (prints its JSON object; for profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -357,7 +363,7 @@ def main():
     from synth import catalog as C
 
     if args.batch_only:
-        print(json.dumps(batch_leg(B, torch, log)), flush=True)
+        print(json.dumps(batch_leg(B, torch, log, tune_db=args.tune_db or None)), flush=True)
         return
     wl = C.workload(args.workload)
     dev = torch.device("cuda:0")
@@ -419,6 +425,16 @@ def main():
         return dt / steps, o, stages
 
     prec = B.PRECISIONS[args.prec]
+
+    def tune(p):
+        if args.tune_db:
+            t0 = time.time()
+            plan.autotune(p, args.tune_db)
+            log(f"  tuned ({p}): shape {plan.info.tune_shape}, chunk {plan.info.tune_kchunk}, "
+                f"tiles {plan.info.tune_tiles} ({time.time() - t0:.2f} s)")
+        return {"reduce_shape": int(plan.info.tune_shape), "reduce_chunk": int(plan.info.tune_kchunk),
+                "short_line_tiles": int(plan.info.tune_tiles)}
+    tuned = {args.prec: tune(prec)}
     t_mix, o_mix, stages = timed(prec, args.steps, args.warmup, True)
     res = {"metric": "mocks/sec for B_0,2,4 + 100 modal coeffs at 512^3, mixed vs FP32 at stated err",
            "value": 1.0 / t_mix, "unit": "mocks/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -432,6 +448,7 @@ def main():
                       "reduce_schedule": {k: int(getattr(plan.info, "reduce_" + k)) for k in
                                           ("pairs", "thirds", "tiles", "groups", "maxr", "maxcw", "needed")}}}
     if not args.no_fp32 and args.prec != "fp32":
+        tuned["fp32"] = tune(B.BSP_FP32)
         t32, o32, _ = timed(B.BSP_FP32, args.steps, 1, False)
         res["fp32_mocks_per_sec"] = 1.0 / t32
         res["fp32_ms_per_step"] = t32 * 1e3
@@ -448,6 +465,7 @@ def main():
         err.update({f"alpha{2 * li}": rel(o_mix["al"][li], o32["al"][li]) for li in range(nl)})
         err.update({f"beta{2 * li}": rel(o_mix["be"][li], o32["be"][li]) for li in range(nl)})
         res["err_mixed_vs_fp32"] = err
+    res["autotune"] = tuned
     gc = plan.gram_condition()
     res["modal"] = {"nmodes": wl.nmodes, "drop_tol": MODAL_DROP_TOL, "kept": gc["rank"],
                     "cond_gamma": gc["gamma"], "cond_L_kept": gc["L_kept"]}
@@ -505,7 +523,7 @@ def main():
         plan.close()
         del ux, uy, uz
         torch.cuda.empty_cache()
-        res["batch"] = batch_leg(B, torch, log)
+        res["batch"] = batch_leg(B, torch, log, tune_db=args.tune_db or None)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a bounded sample ...")
         res["cpu_baseline"] = cpu_baseline(wl, u, int(ntri), log)
