@@ -130,6 +130,8 @@ typedef struct {
   int32_t tune_shape;     /* main reduction register shape chosen by bsp_autotune (-1: the rule) */
   int32_t tune_tiles;     /* short-line transform tiles (0: the rule, 1: 16, 2: 64 columns) */
   int64_t tune_kchunk;    /* main reduction chunk length (0: the rule) */
+  int32_t reduce_row_tiles; /* row tiles of 16 pair slots (pairs that meet a needed third) */
+  int32_t reserved0;
 } bsp_info;
 
 /* ---------------------------------------------------------------- plans */

@@ -78,7 +78,8 @@ class Info(C.Structure):
                 ("count_residual", C.c_double), ("reduce_pairs", C.c_int32), ("reduce_thirds", C.c_int32),
                 ("reduce_tiles", C.c_int32), ("reduce_groups", C.c_int32), ("reduce_maxr", C.c_int32),
                 ("reduce_maxcw", C.c_int32), ("reduce_needed", C.c_int64), ("modal_rank", C.c_int32),
-                ("tune_shape", C.c_int32), ("tune_tiles", C.c_int32), ("tune_kchunk", C.c_int64)]
+                ("tune_shape", C.c_int32), ("tune_tiles", C.c_int32), ("tune_kchunk", C.c_int64),
+                ("reduce_row_tiles", C.c_int32), ("reserved0", C.c_int32)]
 
 
 _lib = None

@@ -36,48 +36,49 @@ struct ReducePlan {
   int32_t *d_pair_a = nullptr, *d_pair_b = nullptr, *d_third = nullptr, *d_row_mask = nullptr,
           *d_tile_index = nullptr, *d_tile_rc = nullptr, *d_wave_rows = nullptr, *d_wave_cols = nullptr;
   int32_t *d_pf_row = nullptr, *d_pair_ra = nullptr, *d_pair_rb = nullptr;
+  std::vector<int32_t> slot_pair;            // pair of each row slot (-1 pad)
+  int32_t* d_slot_pair = nullptr;
   std::vector<int32_t> packed;
   int64_t kchunk_force = 0;  // points per workgroup chunk chosen by the autotuner (0: the rule)
 };
 
-// Tiles of 16 pairs x 16 thirds; a tile is needed when any entry is. Row
-// tiles are given to (group, wave) slots, heaviest first, each wave holding at
-// most maxr row tiles whose needed column tiles number at most maxcw; the
-// register shape is the one that needs the fewest groups (each group reads
-// every field once).
+// Greedy placement of one kind of row tiles on nw waves: each row goes to the
+// least loaded wave that can still hold it. wrows / cm: per wave.
+bool place_rows(const ReducePlan& rp, const std::vector<int>& rows, int maxr, int maxcw, int nw,
+                std::vector<int>& wrows, std::vector<int>& cm) {
+  std::vector<int> load(nw, 0), cnt(nw, 0);
+  wrows.assign((size_t)nw * maxr, -1);
+  cm.assign(nw, 0);
+  for (int r : rows) {
+    const int m = rp.row_mask[r];
+    int best = -1, best_grow = 0;
+    for (int w = 0; w < nw; ++w) {
+      if (cnt[w] >= maxr || __builtin_popcount(cm[w] | m) > maxcw) continue;
+      const int grow = __builtin_popcount((cm[w] | m) & ~cm[w]);
+      if (best < 0 || load[w] < load[best] || (load[w] == load[best] && grow < best_grow)) {
+        best = w;
+        best_grow = grow;
+      }
+    }
+    if (best < 0) return false;
+    wrows[(size_t)best * maxr + cnt[best]++] = r;
+    load[best] += __builtin_popcount(m);
+    cm[best] |= m;
+  }
+  return true;
+}
+
+// Row tiles go to (group, wave) slots, heaviest first, each wave holding at
+// most maxr row tiles whose needed column tiles number at most maxcw.
 bool schedule_rows(ReducePlan& rp, const std::vector<int>& active, int maxr, int maxcw, int waves,
                    std::vector<int>& wrows, std::vector<int>& wcols, int& ngroups) {
   for (int r : active)
     if (__builtin_popcount(rp.row_mask[r]) > maxcw) return false;
-  ngroups = std::max(1, (int)((active.size() + (size_t)waves * maxr - 1) / ((size_t)waves * maxr)));
-  for (;; ++ngroups) {
+  for (ngroups = std::max(1, (int)((active.size() + (size_t)waves * maxr - 1) / ((size_t)waves * maxr)));
+       ngroups <= (int)active.size(); ++ngroups) {
     const int nw = ngroups * waves;
-    std::vector<int> load(nw, 0), cnt(nw, 0), cm(nw, 0);
-    wrows.assign((size_t)nw * maxr, -1);
-    bool ok = true;
-    for (int r : active) {
-      const int m = rp.row_mask[r];
-      int best = -1, best_grow = 0;
-      for (int w = 0; w < nw; ++w) {
-        if (cnt[w] >= maxr || __builtin_popcount(cm[w] | m) > maxcw) continue;
-        const int grow = __builtin_popcount((cm[w] | m) & ~cm[w]);
-        if (best < 0 || load[w] < load[best] || (load[w] == load[best] && grow < best_grow)) {
-          best = w;
-          best_grow = grow;
-        }
-      }
-      if (best < 0) {
-        ok = false;
-        break;
-      }
-      wrows[(size_t)best * maxr + cnt[best]++] = r;
-      load[best] += __builtin_popcount(m);
-      cm[best] |= m;
-    }
-    if (!ok) {
-      if (ngroups > (int)active.size()) return false;
-      continue;
-    }
+    std::vector<int> cm;
+    if (!place_rows(rp, active, maxr, maxcw, nw, wrows, cm)) continue;
     wcols.assign((size_t)nw * maxcw, -1);
     for (int w = 0; w < nw; ++w) {
       int k = 0;
@@ -86,45 +87,77 @@ bool schedule_rows(ReducePlan& rp, const std::vector<int>& active, int maxr, int
     }
     return true;
   }
+  return false;
 }
 
+// Row tiles of 16 pair slots: the pairs that meet a needed third, in their
+// given order (a pair that meets none gets no slot; its row of T stays as the
+// caller set it).
+void tile_rows(const std::vector<std::array<int, 2>>& pairs, const std::vector<int>& pmask,
+               std::vector<int32_t>& slot_pair, std::vector<int32_t>& pa, std::vector<int32_t>& pb) {
+  slot_pair.clear();
+  pa.clear();
+  pb.clear();
+  for (int i = 0; i < (int)pairs.size(); ++i) {
+    if (!pmask[i]) continue;
+    slot_pair.push_back(i);
+    pa.push_back(pairs[i][0]);
+    pb.push_back(pairs[i][1]);
+  }
+  while (slot_pair.size() % 16) {
+    slot_pair.push_back(-1);
+    pa.push_back(-1);
+    pb.push_back(-1);
+  }
+}
+
+// Tiles of 16 pair slots x 16 thirds; a tile is needed when any entry is. The
+// register shape is the one that needs the fewest groups (each group reads
+// every field once).
 bool build_reduce(ReducePlan& rp, const std::vector<std::array<int, 2>>& pairs, const std::vector<int>& thirds,
                   const std::vector<uint8_t>& need, int nfields, int prec, int force_shape = -1) {
   rp = ReducePlan{};
   rp.npairs = (int)pairs.size();
   rp.nthirds = (int)thirds.size();
   rp.nfields = nfields;
-  rp.nrt = (rp.npairs + 15) / 16;
   rp.nct = (rp.nthirds + 15) / 16;
-  if (rp.nct > 8 || rp.nct == 0 || rp.nrt == 0) return false;
-  rp.pair_a.assign(rp.nrt * 16, -1);
-  rp.pair_b.assign(rp.nrt * 16, -1);
+  if (rp.nct > 8 || rp.nct == 0 || rp.npairs == 0) return false;
+  for (int i = 0; i < rp.npairs; ++i)
+    for (int k = 0; k < 2; ++k)
+      if (pairs[i][k] < 0 || pairs[i][k] >= nfields) return false;
+  // column tiles each pair needs (0: the pair meets no needed third and gets no slot)
+  std::vector<int> pmask(rp.npairs, 0);
+  for (int p = 0; p < rp.npairs; ++p)
+    for (int t = 0; t < rp.nthirds; ++t)
+      if (need.empty() || need[(size_t)p * rp.nthirds + t]) pmask[p] |= 1 << (t / 16);
+  tile_rows(pairs, pmask, rp.slot_pair, rp.pair_a, rp.pair_b);
+  rp.nrt = (int)rp.slot_pair.size() / 16;
+  if (rp.nrt == 0) return false;
   rp.third.assign(rp.nct * 16, -1);
-  for (int i = 0; i < rp.npairs; ++i) {
-    rp.pair_a[i] = pairs[i][0];
-    rp.pair_b[i] = pairs[i][1];
-  }
   for (int i = 0; i < rp.nthirds; ++i) rp.third[i] = thirds[i];
   // rows of the pair factors, in order of first use
   rp.pf_row.assign(std::max(nfields, 1), -1);
   rp.pair_ra.assign(rp.nrt * 16, -1);
   rp.pair_rb.assign(rp.nrt * 16, -1);
   rp.npf = 0;
-  for (int i = 0; i < rp.npairs; ++i)
+  for (int i = 0; i < rp.nrt * 16; ++i)
     for (int k = 0; k < 2; ++k) {
-      const int f = pairs[i][k];
-      if (f < 0 || f >= nfields) return false;
+      const int f = k ? rp.pair_b[i] : rp.pair_a[i];
+      if (f < 0) continue;
       if (rp.pf_row[f] < 0) rp.pf_row[f] = rp.npf++;
       (k ? rp.pair_rb : rp.pair_ra)[i] = rp.pf_row[f];
     }
   rp.row_mask.assign(rp.nrt, 0);
   rp.tile_index.assign(rp.nrt * 8, -1);
-  for (int p = 0; p < rp.npairs; ++p)
+  for (int sl = 0; sl < rp.nrt * 16; ++sl) {
+    const int p = rp.slot_pair[sl];
+    if (p < 0) continue;
     for (int t = 0; t < rp.nthirds; ++t)
       if (need.empty() || need[(size_t)p * rp.nthirds + t]) {
-        rp.row_mask[p / 16] |= 1 << (t / 16);
+        rp.row_mask[sl / 16] |= 1 << (t / 16);
         rp.needed++;
       }
+  }
   std::vector<int> active;
   for (int r = 0; r < rp.nrt; ++r)
     if (rp.row_mask[r]) {
@@ -175,6 +208,7 @@ bool build_reduce(ReducePlan& rp, const std::vector<std::array<int, 2>>& pairs, 
   put(rp.pf_row);
   put(rp.pair_ra);
   put(rp.pair_rb);
+  put(rp.slot_pair);
   rp.words = rp.packed.size();
   return true;
 }
@@ -199,6 +233,7 @@ void bind_reduce(ReducePlan& rp, int32_t* dev) {
   rp.d_pf_row = take(rp.pf_row.size());
   rp.d_pair_ra = take(rp.pair_ra.size());
   rp.d_pair_rb = take(rp.pair_rb.size());
+  rp.d_slot_pair = take(rp.slot_pair.size());
 }
 
 // Points per workgroup chunk: about 2048 chunks, at least 1024 points, at most
@@ -231,6 +266,8 @@ ReduceDesc make_desc(const ReducePlan& rp, int64_t K, int64_t field_stride, int 
   d.field_stride = field_stride;
   d.kchunk = (int32_t)std::max<int64_t>(rp.kchunk_force > 0 ? rp.kchunk_force : kchunk_for(prec, K, rp.ngroups), kc_min);
   d.nchunks = (int32_t)((K + d.kchunk - 1) / d.kchunk);
+  d.chunks_per_set = d.nchunks;
+  d.set_stride = 0;
   d.ngroups = rp.ngroups;
   d.nct = rp.nct;
   d.maxr = rp.maxr;
@@ -249,6 +286,7 @@ ReduceDesc make_desc(const ReducePlan& rp, int64_t K, int64_t field_stride, int 
   d.pf_row = rp.d_pf_row;
   d.pair_ra = rp.d_pair_ra;
   d.pair_rb = rp.d_pair_rb;
+  d.slot_pair = rp.d_slot_pair;
   return d;
 }
 
@@ -1303,6 +1341,8 @@ bsp_status bsp_plan_info(bsp_plan p, bsp_info* info) {
   info->tune_shape = p->tune_shape;
   info->tune_tiles = p->tune_tiles;
   info->tune_kchunk = p->tune_kchunk;
+  info->reduce_row_tiles = m.nrt;
+  info->reserved0 = 0;
   return BSP_OK;
 }
 
@@ -1821,7 +1861,8 @@ bsp_status bsp_autotune(bsp_plan p, bsp_precision prec, const char* db_path, int
   const std::string path = db_path ? db_path : "";
   if (!path.empty() && !(flags & BSP_TUNE_FORCE) && tune_lookup(path, key, e)) {
     p->tune_tiles = e.tiles;
-    if (!apply_reduce_choice(p, e.shape, e.kchunk)) return fail(p, BSP_ERR_ARG, "tuned reduction shape not supported");
+    if (!apply_reduce_choice(p, e.shape, e.kchunk))
+      return fail(p, BSP_ERR_ARG, "tuned reduction shape not supported");
     return BSP_OK;
   }
   s = bsp_sync(p);

@@ -138,6 +138,13 @@ struct ReduceDesc {
   const int32_t* pf_row;         // [nfields] full-precision row of each field, -1 if none
   const int32_t* pair_ra;        // [nrt*16] row of pair_a (-1 pad)
   const int32_t* pair_rb;        // [nrt*16] row of pair_b (-1 pad)
+  // row slots: slot_pair[s] is the pair (row of T) that slot s computes, -1 pad
+  const int32_t* slot_pair;      // [nrt*16]
+  // several field stacks reduced by one launch (the same schedule on each):
+  // chunk c works on stack c / chunks_per_set, elements set_stride apart;
+  // chunks_per_set = nchunks for one stack
+  int32_t chunks_per_set;
+  int64_t set_stride;
 };
 
 // ---------------------------------------------------------------- launchers

@@ -2,9 +2,9 @@
 // over the spatial points x (the K dimension): rows are pair products
 // (F_a F_b)(x), columns are third fields F_s(x).
 //
-// This is the "three dimensional integral over products of FFTs" of the
-// standard estimator (its FFT form and the multipole form with D^(l)_k) and the
-// integral of M M M of the modal estimator, both in Sec. 3 of the paper.
+// This is the FFT form of the standard estimator (Sec. 3.1, also its
+// multipole form with D^(l)_k) and the real-space sum of M M M of the modal
+// estimator (Sec. 3.5, eq. (betaEst)).
 //
 // Structure: a workgroup (12 waves, three per SIMD) owns a chunk of K points and a group of
 // row tiles; each wave owns up to MAXR row tiles of 16 pairs and every needed
@@ -33,68 +33,79 @@ constexpr int NTHR = WAVES * 64;
 template <int PREC, int KS>
 size_t reduce_lds_bytes(const ReduceDesc& d) {
   constexpr bool SPLIT = (PREC == 1 || PREC == 2 || PREC == 4);
-  const size_t elem = PREC == 3 ? 8 : 4;
+  using L = LdsRows<typename RT<PREC>::T, KS>;
   const size_t nfull = (SPLIT ? d.npf : d.nfields) + 1;
-  size_t b = 2 * nfull * (KS + 16 / elem) * elem;
-  if (SPLIT) b += (size_t)4 * (d.nfields + 1) * (KS + 8) * 2;
+  size_t b = nfull * L::RS;
+  if (SPLIT) b += (size_t)(d.nfields + 1) * L::HS;
   return b;
 }
 
 template <int PREC, int MAXR, int MAXC, int KS>
 __global__ __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(3, 3))) void k_reduce(
     const typename RT<PREC>::T* __restrict__ fields, ReduceDesc d, typename RT<PREC>::T* __restrict__ partials) {
-  using WT = WaveTiles<PREC, MAXR, MAXC, WAVES>;
+  using WT = WaveTiles<PREC, MAXR, MAXC, WAVES, KS>;
   using T = typename WT::T;
-  using H = typename WT::H;
+  using L = typename WT::L;
   constexpr bool SPLIT = WT::SPLIT;
-  constexpr int LDW = KS + (16 / (int)sizeof(T));  // padded full-precision LDS row
-  constexpr int LDH = KS + 8;                      // padded row of 16-bit halves
   constexpr int EPV = 16 / (int)sizeof(T);         // elements per 16-byte vector
   using VEC = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
   constexpr int MAXV = (128 * KS / EPV + NTHR - 1) / NTHR;  // vectors per thread per stage (<= 128 fields)
 
   extern __shared__ __align__(16) unsigned char smem_raw[];
   // full-precision rows: the pair factors (split precisions: thirds come from the
-  // hi / lo rows) or every field; the last row stays zero
+  // split rows) or every field; the last row stays zero
   const int nfull = SPLIT ? d.npf : d.nfields;
-  const int nrow_lds = nfull + 1;
-  const int nrow_h = d.nfields + 1;
-  T* lds = reinterpret_cast<T*>(smem_raw);
-  // split copies: [buffer][hi | lo][field][LDH], written once per stage by the whole workgroup
-  H* ldh = reinterpret_cast<H*>(smem_raw + (size_t)2 * nrow_lds * LDW * sizeof(T));
+  unsigned char* lf = smem_raw;
+  unsigned char* lh = smem_raw + (size_t)(nfull + 1) * L::RS;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int q = lane >> 4, r16 = lane & 15;
   const int chunk = blockIdx.x, group = blockIdx.y;
-  const int64_t k0 = (int64_t)chunk * d.kchunk;
+  const int set = chunk / d.chunks_per_set;
+  fields += (int64_t)set * d.set_stride;
+  const int64_t k0 = (int64_t)(chunk - set * d.chunks_per_set) * d.kchunk;
   int64_t k1 = k0 + d.kchunk;
   if (k1 > d.K) k1 = d.K;
   const int nst = (int)((k1 - k0 + KS - 1) / KS);
 
   WT wt;
-  wt.init(d, group, wave, r16);
+  wt.init(d, group, wave, q, r16);
 
-  // zero rows of both buffers
-  for (int i = threadIdx.x; i < LDW; i += blockDim.x) {
-    lds[(int64_t)nfull * LDW + i] = (T)0;
-    lds[(int64_t)(nrow_lds + nfull) * LDW + i] = (T)0;
-  }
+  // zero rows (both buffers)
+  for (int i = threadIdx.x; i < L::RS / 4; i += NTHR)
+    reinterpret_cast<uint32_t*>(lf + (size_t)nfull * L::RS)[i] = 0u;
   if constexpr (SPLIT) {
-    for (int i = threadIdx.x; i < LDH; i += blockDim.x)
-      for (int b = 0; b < 4; ++b) ldh[((int64_t)b * nrow_h + d.nfields) * LDH + i] = (H)0.0f;
+    for (int i = threadIdx.x; i < L::HS / 4; i += NTHR)
+      reinterpret_cast<uint32_t*>(lh + (size_t)d.nfields * L::HS)[i] = 0u;
   }
 
-  const int nvec = d.nfields * (KS / EPV);
+  // Each thread stages the same MAXV vectors (field f, point offset e) of every
+  // stage; f and e follow from the thread index. Split precisions keep the
+  // full-precision row of f packed (8 bits per vector, row + 1, 0: none);
+  // otherwise the row is f itself.
+  constexpr int VPR = KS / EPV;  // vectors per field row and stage
+  static_assert(!SPLIT || MAXV <= 4, "packed rows: at most four vectors per thread");
+  const int nvec = d.nfields * VPR;
+  uint32_t frow_packed = 0;
+  if constexpr (SPLIT) {
+#pragma unroll
+    for (int v = 0; v < MAXV; ++v) {
+      const int vi = threadIdx.x + v * NTHR;
+      const int fr = vi < nvec ? d.pf_row[vi / VPR] : -1;
+      frow_packed |= (uint32_t)(fr + 1) << (8 * v);
+    }
+  }
+  // 16-byte loads only when every field row stays 16-byte aligned
+  const bool aligned = (d.field_stride % EPV == 0) && (d.set_stride % EPV == 0);
   VEC stage_regs[MAXV];
   auto gload = [&](int st) {
     const int64_t kb = k0 + (int64_t)st * KS;
-    // 16-byte vector loads only when every field row stays 16-byte aligned
-    const bool full = (kb + KS <= k1) && (d.field_stride % EPV == 0);
+    const bool full = aligned && (kb + KS <= k1);
 #pragma unroll
     for (int v = 0; v < MAXV; ++v) {
       const int vi = threadIdx.x + v * NTHR;
       VEC val{};
       if (vi < nvec) {
-        const int f = vi / (KS / EPV), e = (vi % (KS / EPV)) * EPV;
+        const int f = vi / VPR, e = (vi % VPR) * EPV;
         const T* src = fields + (int64_t)f * d.field_stride + kb + e;
         if (full) {
           typedef T TV __attribute__((ext_vector_type(EPV)));
@@ -111,54 +122,56 @@ __global__ __launch_bounds__(768) __attribute__((amdgpu_waves_per_eu(3, 3))) voi
       stage_regs[v] = val;
     }
   };
-  // full-precision row of each staged vector's field (constant per thread)
-  int frow[MAXV];
-#pragma unroll
-  for (int v = 0; v < MAXV; ++v) {
-    const int vi = threadIdx.x + v * NTHR;
-    const int f = vi < nvec ? vi / (KS / EPV) : 0;
-    frow[v] = SPLIT ? d.pf_row[f] : f;
-  }
-  auto sstore = [&](int buf) {
-    T* base = lds + (int64_t)buf * nrow_lds * LDW;
+  auto sstore = [&](auto bufc) {
+    constexpr int BUF = decltype(bufc)::value;
 #pragma unroll
     for (int v = 0; v < MAXV; ++v) {
       const int vi = threadIdx.x + v * NTHR;
-      if (vi < nvec) {
-        const int f = vi / (KS / EPV), e = (vi % (KS / EPV)) * EPV;
-        if (frow[v] >= 0) *reinterpret_cast<VEC*>(base + (int64_t)frow[v] * LDW + e) = stage_regs[v];
-        if constexpr (SPLIT) {
-          // round-to-nearest-even split x = hi + lo of the (scaled) value, once per workgroup
-          const float sc = (PREC == 2 && d.scale) ? d.scale[f] : 1.0f;
-          const float x[4] = {stage_regs[v].x * sc, stage_regs[v].y * sc, stage_regs[v].z * sc,
-                              stage_regs[v].w * sc};
-          int2 hi, lo;
-          split4<typename WT::H2>(x, hi, lo);
-          H* hb = ldh + ((int64_t)(2 * buf) * nrow_h + f) * LDH + e;
-          H* lb = ldh + ((int64_t)(2 * buf + 1) * nrow_h + f) * LDH + e;
-          *reinterpret_cast<int2*>(hb) = hi;
-          *reinterpret_cast<int2*>(lb) = lo;
-        }
+      if (vi >= nvec) continue;
+      const int f = vi / VPR, e = (vi % VPR) * EPV;
+      VEC val = stage_regs[v];
+      if constexpr (PREC == 2) {
+        // FP16 split: every staged value carries its field's power-of-two scale
+        const float sc = d.scale ? d.scale[f] : 1.0f;
+        val.x *= sc; val.y *= sc; val.z *= sc; val.w *= sc;
+      }
+      const int fr = SPLIT ? (int)((frow_packed >> (8 * v)) & 0xffu) - 1 : f;
+      if (fr >= 0) *reinterpret_cast<VEC*>(lf + fr * L::RS + e * (int)sizeof(T) + L::full(BUF)) = val;
+      if constexpr (SPLIT) {
+        // round-to-nearest-even split x = hi + lo, once per workgroup
+        const float x[4] = {val.x, val.y, val.z, val.w};
+        int2 hi, lo;
+        split4<typename WT::H2>(x, hi, lo);
+        unsigned char* hrow = lh + f * L::HS + e * 2;
+        *reinterpret_cast<int2*>(hrow + L::half(BUF, 0)) = hi;
+        *reinterpret_cast<int2*>(hrow + L::half(BUF, 1)) = lo;
       }
     }
   };
+  auto ksteps = [&](auto bufc) {
+    constexpr int BUF = decltype(bufc)::value;
+    if (!wt.colmask_any) return;
+#pragma unroll 1
+    for (int ks = 0; ks < WT::NKS; ++ks) wt.template kstep<BUF>(lf, lh, ks);
+  };
+  using B0 = std::integral_constant<int, 0>;
+  using B1 = std::integral_constant<int, 1>;
 
   if (nst > 0) {
     gload(0);
-    sstore(0);
+    sstore(B0{});
   }
   __syncthreads();
-  for (int st = 0; st < nst; ++st) {
-    const int cur = st & 1;
+  // stages alternate between the two buffers; the loop body covers two
+  for (int st = 0; st < nst; st += 2) {
     if (st + 1 < nst) gload(st + 1);
-    const T* base = lds + (int64_t)cur * nrow_lds * LDW;
-    const H* hib = ldh + (int64_t)(2 * cur) * nrow_h * LDH;
-    const H* lob = ldh + (int64_t)(2 * cur + 1) * nrow_h * LDH;
-    if (wt.colmask_any) {
-#pragma unroll 1
-      for (int ks = 0; ks < KS / WT::KSTEP; ++ks) wt.kstep(base, hib, lob, LDW, LDH, ks * WT::KSTEP + q * WT::KK);
-    }
-    if (st + 1 < nst) sstore(cur ^ 1);
+    ksteps(B0{});
+    if (st + 1 < nst) sstore(B1{});
+    __syncthreads();
+    if (st + 1 >= nst) break;
+    if (st + 2 < nst) gload(st + 2);
+    ksteps(B1{});
+    if (st + 2 < nst) sstore(B0{});
     __syncthreads();
   }
   wt.store(d, partials, chunk, q, r16);
@@ -183,22 +196,25 @@ __device__ __forceinline__ double* park_slot(PT* partials, int c0, int ntiles, i
 }
 
 template <typename PT>
-__device__ __forceinline__ void write_t(double s, int tile, int e, const int32_t* __restrict__ tile_rc, int npairs,
+__device__ __forceinline__ void write_t(double s, int tile, int e, const int32_t* __restrict__ tile_rc,
+                                        const int32_t* __restrict__ slot_pair, int npairs,
                                         int nthirds, const int32_t* __restrict__ pair_a,
                                         const int32_t* __restrict__ pair_b, const int32_t* __restrict__ third,
                                         const float* __restrict__ scale, double tscale, double* __restrict__ T) {
-  const int pr = tile_rc[2 * tile] * 16 + e / 16;
+  const int slot = tile_rc[2 * tile] * 16 + e / 16;
   const int th = tile_rc[2 * tile + 1] * 16 + e % 16;
-  if (pr < npairs && th < nthirds) {
+  const int pr = slot_pair[slot];
+  if (pr >= 0 && pr < npairs && th < nthirds) {
     double f = tscale;
-    if (scale) f /= (double)scale[pair_a[pr]] * (double)scale[pair_b[pr]] * (double)scale[third[th]];
+    if (scale) f /= (double)scale[pair_a[slot]] * (double)scale[pair_b[slot]] * (double)scale[third[th]];
     T[(int64_t)pr * nthirds + th] = s * f;
   }
 }
 
 template <typename PT>
 __global__ __launch_bounds__(256) void k_combine(PT* __restrict__ partials, int nchunks, int ntiles, int cpb, int nranges,
-                                                 const int32_t* __restrict__ tile_rc, int npairs, int nthirds,
+                                                 const int32_t* __restrict__ tile_rc,
+                                                 const int32_t* __restrict__ slot_pair, int npairs, int nthirds,
                                                  const int32_t* __restrict__ pair_a, const int32_t* __restrict__ pair_b,
                                                  const int32_t* __restrict__ third, const float* __restrict__ scale,
                                                  double tscale, double* __restrict__ T) {
@@ -210,7 +226,7 @@ __global__ __launch_bounds__(256) void k_combine(PT* __restrict__ partials, int 
   double s = 0.0;
   for (int c = c0; c < c1; ++c) s += (double)partials[((int64_t)c * ntiles + tile) * 256 + e];
   if (nranges == 1) {
-    write_t<PT>(s, tile, e, tile_rc, npairs, nthirds, pair_a, pair_b, third, scale, tscale, T);
+    write_t<PT>(s, tile, e, tile_rc, slot_pair, npairs, nthirds, pair_a, pair_b, third, scale, tscale, T);
     return;
   }
   __syncthreads();  // every thread has read its values before the slots are overwritten
@@ -219,7 +235,8 @@ __global__ __launch_bounds__(256) void k_combine(PT* __restrict__ partials, int 
 
 template <typename PT>
 __global__ __launch_bounds__(256) void k_combine_ranges(PT* __restrict__ partials, int ntiles, int cpb, int nranges,
-                                                        const int32_t* __restrict__ tile_rc, int npairs, int nthirds,
+                                                        const int32_t* __restrict__ tile_rc,
+                                                 const int32_t* __restrict__ slot_pair, int npairs, int nthirds,
                                                         const int32_t* __restrict__ pair_a,
                                                         const int32_t* __restrict__ pair_b,
                                                         const int32_t* __restrict__ third,
@@ -229,7 +246,7 @@ __global__ __launch_bounds__(256) void k_combine_ranges(PT* __restrict__ partial
   const int e = threadIdx.x;
   double s = 0.0;
   for (int y = 0; y < nranges; ++y) s += *park_slot(partials, y * cpb, ntiles, tile, e);
-  write_t<PT>(s, tile, e, tile_rc, npairs, nthirds, pair_a, pair_b, third, scale, tscale, T);
+  write_t<PT>(s, tile, e, tile_rc, slot_pair, npairs, nthirds, pair_a, pair_b, third, scale, tscale, T);
 }
 
 int reduce_waves_per_group() { return WAVES; }
@@ -298,18 +315,18 @@ hipError_t launch_combine_partials(void* partials, int is_f64, const ReduceDesc&
   dim3 grid((unsigned)d.ntiles, (unsigned)nranges);
   if (is_f64) {
     double* pp = reinterpret_cast<double*>(partials);
-    hipLaunchKernelGGL((k_combine<double>), grid, dim3(256), 0, s, pp, d.nchunks, d.ntiles, cpb, nranges, d.tile_rc,
+    hipLaunchKernelGGL((k_combine<double>), grid, dim3(256), 0, s, pp, d.nchunks, d.ntiles, cpb, nranges, d.tile_rc, d.slot_pair,
                        npairs, nthirds, d.pair_a, d.pair_b, d.third, d.scale, tscale, T);
     if (nranges > 1)
       hipLaunchKernelGGL((k_combine_ranges<double>), dim3((unsigned)d.ntiles), dim3(256), 0, s, pp, d.ntiles, cpb,
-                         nranges, d.tile_rc, npairs, nthirds, d.pair_a, d.pair_b, d.third, d.scale, tscale, T);
+                         nranges, d.tile_rc, d.slot_pair, npairs, nthirds, d.pair_a, d.pair_b, d.third, d.scale, tscale, T);
   } else {
     float* pp = reinterpret_cast<float*>(partials);
-    hipLaunchKernelGGL((k_combine<float>), grid, dim3(256), 0, s, pp, d.nchunks, d.ntiles, cpb, nranges, d.tile_rc,
+    hipLaunchKernelGGL((k_combine<float>), grid, dim3(256), 0, s, pp, d.nchunks, d.ntiles, cpb, nranges, d.tile_rc, d.slot_pair,
                        npairs, nthirds, d.pair_a, d.pair_b, d.third, d.scale, tscale, T);
     if (nranges > 1)
       hipLaunchKernelGGL((k_combine_ranges<float>), dim3((unsigned)d.ntiles), dim3(256), 0, s, pp, d.ntiles, cpb,
-                         nranges, d.tile_rc, npairs, nthirds, d.pair_a, d.pair_b, d.third, d.scale, tscale, T);
+                         nranges, d.tile_rc, d.slot_pair, npairs, nthirds, d.pair_a, d.pair_b, d.third, d.scale, tscale, T);
   }
   return hipGetLastError();
 }

@@ -1,6 +1,7 @@
 // Register-resident 16x16 output tiles of the triple-reduction GEMM and the
 // MFMA k-step over one LDS stage of the reduction over materialised fields
 // (reduce.hip).
+
 //
 // A wave owns up to MAXR row tiles (16 pair products each) and up to MAXC
 // column tiles (16 third fields each) of its own; a row's needed columns are
@@ -61,25 +62,45 @@ __device__ __forceinline__ void split4(const float* x, int2& hi, int2& lo) {
   lo = int2{l[0], l[1]};
 }
 
-template <int PREC, int MAXR, int MAXC, int WAVES> struct WaveTiles {
+template <typename V>
+__device__ __forceinline__ V lds_ld(const unsigned char* p) {
+  return *reinterpret_cast<const V*>(p);
+}
+
+// LDS layout of one stage pair (both double buffers interleaved in each row, so
+// that every k-step reads at compile-time offsets from per-lane row addresses):
+//   full-precision row  [buffer 0: KS values][buffer 1: KS values][16 bytes pad]
+//   split row (16-bit)  [hi 0][lo 0][hi 1][lo 1] (KS halves each) [16 bytes pad]
+// The 16-byte pad puts 16 consecutive rows on distinct 4-bank groups.
+template <typename T, int KS> struct LdsRows {
+  static constexpr int RS = 2 * KS * (int)sizeof(T) + 16;
+  static constexpr int HS = 8 * KS + 16;
+  static constexpr int full(int buf) { return buf * KS * (int)sizeof(T); }
+  static constexpr int half(int buf, int lo) { return (2 * buf + lo) * KS * 2; }
+};
+
+template <int PREC, int MAXR, int MAXC, int WAVES, int KS> struct WaveTiles {
   using T = typename RT<PREC>::T;
   using ACC = typename RT<PREC>::acc;
   static constexpr bool SPLIT = (PREC == 1 || PREC == 2 || PREC == 4);
   using H = typename std::conditional<PREC == 2, _Float16, __bf16>::type;
   using H8 = typename std::conditional<PREC == 2, f16x8, bf16x8>::type;
   using H2 = typename std::conditional<PREC == 2, f16x2, bf16x2>::type;
+  using L = LdsRows<T, KS>;
   static constexpr int KK = RT<PREC>::KK;
   static constexpr int KSTEP = 4 * KK;
+  static constexpr int NKS = KS / KSTEP;
 
   int rows[MAXR], masks[MAXR], cols[MAXC];
-  int pa[MAXR], pb[MAXR], th[MAXC];
-  float sab[MAXR];
+  // per-lane byte offsets into the LDS rows: first and second pair factor of
+  // each row slot, third of each column slot
+  int oa[MAXR], ob[MAXR], oc[MAXC];
   int colmask_any;
   ACC acc[MAXR][MAXC];
 
   // The tile lists are wave-uniform: reading them through a uniform wave index
   // keeps them in scalar registers and the block-sparse skips scalar branches.
-  __device__ __forceinline__ void init(const ReduceDesc& d, int group, int wave_in, int r16) {
+  __device__ __forceinline__ void init(const ReduceDesc& d, int group, int wave_in, int q, int r16) {
     const int wave = __builtin_amdgcn_readfirstlane(wave_in);
 #pragma unroll
     for (int c = 0; c < MAXC; ++c) cols[c] = d.wave_cols[(group * WAVES + wave) * MAXC + c];
@@ -98,20 +119,20 @@ template <int PREC, int MAXR, int MAXC, int WAVES> struct WaveTiles {
     const int32_t* ra = SPLIT ? d.pair_ra : d.pair_a;
     const int32_t* rb = SPLIT ? d.pair_rb : d.pair_b;
     const int zrow = SPLIT ? d.npf : d.nfields;
+    const int lane_k = q * KK * (int)sizeof(T);
 #pragma unroll
     for (int r = 0; r < MAXR; ++r) {
       const int pr = rows[r] * 16 + r16;
       const int a = rows[r] >= 0 ? ra[pr] : -1;
       const int b = rows[r] >= 0 ? rb[pr] : -1;
-      pa[r] = a >= 0 ? a : zrow;
-      pb[r] = b >= 0 ? b : zrow;
-      const int fa = rows[r] >= 0 ? d.pair_a[pr] : -1, fb = rows[r] >= 0 ? d.pair_b[pr] : -1;
-      sab[r] = (d.scale && fa >= 0 && fb >= 0) ? d.scale[fa] * d.scale[fb] : 1.0f;
+      oa[r] = (a >= 0 ? a : zrow) * L::RS + lane_k;
+      ob[r] = (b >= 0 ? b : zrow) * L::RS + lane_k;
     }
 #pragma unroll
     for (int c = 0; c < MAXC; ++c) {
       const int s = cols[c] >= 0 ? d.third[cols[c] * 16 + r16] : -1;
-      th[c] = s >= 0 ? s : d.nfields;
+      const int srow = s >= 0 ? s : d.nfields;
+      oc[c] = SPLIT ? srow * L::HS + q * KK * 2 : srow * L::RS + lane_k;
     }
     colmask_any = 0;
 #pragma unroll
@@ -124,67 +145,95 @@ template <int PREC, int MAXR, int MAXC, int WAVES> struct WaveTiles {
         for (int i = 0; i < 4; ++i) acc[r][c][i] = (T)0;
   }
 
-  // One k-step of KSTEP points at point offset `off` (= k-step base + q * KK):
-  // base holds the fields at full precision ([row][LDW]); hib / lob their
-  // bf16 or fp16 splits ([row][LDH]) when SPLIT.
-  __device__ __forceinline__ void kstep(const T* __restrict__ base, const H* __restrict__ hib,
-                                        const H* __restrict__ lob, int LDW, int LDH, int off) {
+  // Pair products of row slot r at the KK points of this lane (byte offset
+  // `ko` of the k-step inside the rows).
+  __device__ __forceinline__ void products(const unsigned char* __restrict__ lf, int r, int ko, T* x) const {
+    if constexpr (PREC == 3) {
+      const double2 a0 = lds_ld<double2>(lf + oa[r] + ko);
+      const double2 b0 = lds_ld<double2>(lf + ob[r] + ko);
+      x[0] = a0.x * b0.x;
+      x[1] = a0.y * b0.y;
+    } else {
+      const float4 a0 = lds_ld<float4>(lf + oa[r] + ko), a1 = lds_ld<float4>(lf + oa[r] + ko + 16);
+      const float4 b0 = lds_ld<float4>(lf + ob[r] + ko), b1 = lds_ld<float4>(lf + ob[r] + ko + 16);
+      x[0] = a0.x * b0.x;
+      x[1] = a0.y * b0.y;
+      x[2] = a0.z * b0.z;
+      x[3] = a0.w * b0.w;
+      x[4] = a1.x * b1.x;
+      x[5] = a1.y * b1.y;
+      x[6] = a1.z * b1.z;
+      x[7] = a1.w * b1.w;
+    }
+  }
+
+  // One k-step (KSTEP points) of stage buffer BUF: lf holds the full-precision
+  // rows, lh the split rows (SPLIT only).
+  template <int BUF>
+  __device__ __forceinline__ void kstep(const unsigned char* __restrict__ lf, const unsigned char* __restrict__ lh,
+                                        int ks) {
+    const int ko = L::full(BUF) + ks * KSTEP * (int)sizeof(T);
     if constexpr (!SPLIT) {
       T av[MAXR][KK];
 #pragma unroll
-      for (int r = 0; r < MAXR; ++r)
-#pragma unroll
-        for (int j = 0; j < KK; ++j) av[r][j] = base[pa[r] * LDW + off + j] * base[pb[r] * LDW + off + j];
+      for (int r = 0; r < MAXR; ++r) products(lf, r, ko, av[r]);
+      auto load_col = [&](int c, T* dst) {
+        if constexpr (PREC == 3) {
+          const double2 b0 = lds_ld<double2>(lf + oc[c] + ko);
+          dst[0] = b0.x;
+          dst[1] = b0.y;
+        } else {
+          const float4 b0 = lds_ld<float4>(lf + oc[c] + ko), b1 = lds_ld<float4>(lf + oc[c] + ko + 16);
+          dst[0] = b0.x; dst[1] = b0.y; dst[2] = b0.z; dst[3] = b0.w;
+          dst[4] = b1.x; dst[5] = b1.y; dst[6] = b1.z; dst[7] = b1.w;
+        }
+      };
 #pragma unroll
       for (int c = 0; c < MAXC; ++c) {
         if (!((colmask_any >> c) & 1)) continue;
-        T bv[KK];
-#pragma unroll
-        for (int j = 0; j < KK; ++j) bv[j] = base[th[c] * LDW + off + j];
+        T b[KK];
+        load_col(c, b);
 #pragma unroll
         for (int r = 0; r < MAXR; ++r) {
           if (!((masks[r] >> c) & 1)) continue;
 #pragma unroll
           for (int j = 0; j < KK; ++j) {
             if constexpr (PREC == 0)
-              acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[r][j], bv[j], acc[r][c], 0, 0, 0);
+              acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[r][j], b[j], acc[r][c], 0, 0, 0);
             else
-              acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[r][j], bv[j], acc[r][c], 0, 0, 0);
+              acc[r][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[r][j], b[j], acc[r][c], 0, 0, 0);
           }
         }
       }
     } else {
+      const int ho = L::half(BUF, 0) + ks * KSTEP * 2, lo_o = L::half(BUF, 1) + ks * KSTEP * 2;
       i32x4 ah[MAXR], al[MAXR];
 #pragma unroll
       for (int r = 0; r < MAXR; ++r) {
         // empty rows read the zero row: no branch, no value carried across steps
         float x[KK];
-#pragma unroll
-        for (int j = 0; j < KK; ++j) {
-          x[j] = base[pa[r] * LDW + off + j] * base[pb[r] * LDW + off + j];
-          if constexpr (PREC == 2) x[j] *= sab[r];
-        }
+        products(lf, r, ko, x);
         split8<H2>(x, ah[r], al[r]);
       }
 #pragma unroll
       for (int c = 0; c < MAXC; ++c) {
         if (!((colmask_any >> c) & 1)) continue;
-        const H8 bh = *reinterpret_cast<const H8*>(hib + th[c] * LDH + off);
-        const H8 bl = *reinterpret_cast<const H8*>(lob + th[c] * LDH + off);
+        const H8 h = lds_ld<H8>(lh + oc[c] + ho);
+        const H8 l = lds_ld<H8>(lh + oc[c] + lo_o);
 #pragma unroll
         for (int r = 0; r < MAXR; ++r) {
           if (!((masks[r] >> c) & 1)) continue;
           const H8 a_h = __builtin_bit_cast(H8, ah[r]), a_l = __builtin_bit_cast(H8, al[r]);
           if constexpr (PREC == 1) {
-            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, bh, acc[r][c], 0, 0, 0);
-            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, bl, acc[r][c], 0, 0, 0);
-            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_l, bh, acc[r][c], 0, 0, 0);
+            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, h, acc[r][c], 0, 0, 0);
+            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, l, acc[r][c], 0, 0, 0);
+            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_l, h, acc[r][c], 0, 0, 0);
           } else if constexpr (PREC == 4) {
-            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, bh, acc[r][c], 0, 0, 0);
+            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_h, h, acc[r][c], 0, 0, 0);
           } else {
-            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_h, bh, acc[r][c], 0, 0, 0);
-            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_h, bl, acc[r][c], 0, 0, 0);
-            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_l, bh, acc[r][c], 0, 0, 0);
+            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_h, h, acc[r][c], 0, 0, 0);
+            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_h, l, acc[r][c], 0, 0, 0);
+            acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_l, h, acc[r][c], 0, 0, 0);
           }
         }
       }

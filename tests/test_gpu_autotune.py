@@ -95,3 +95,4 @@ def test_autotune_database_and_outputs(tmp_path):
         assert eB < 1e-5, (li, eB)
     a.close()
     b.close()
+

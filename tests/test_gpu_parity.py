@@ -543,17 +543,13 @@ def test_triple_reduce_definition(prec, tol, K):
     got = T.cpu().numpy()
     F64 = F.astype(np.float64)
     ref = np.array([[np.dot(F64[a] * F64[b], F64[t]) for t in thirds] for a, b in pairs])
-    # the reduction works in 16 x 16 tiles: unneeded entries are 0 or computed
-    tile_need = np.zeros_like(need)
-    for i in range(0, need.shape[0], 16):
-        for j in range(0, need.shape[1], 16):
-            tile_need[i:i + 16, j:j + 16] = need[i:i + 16, j:j + 16].any()
-    assert np.all(got[tile_need == 0] == 0)
-    need = tile_need
     # the sums are noise dominated: compare with the scale of the summed terms
     scale = np.sqrt(np.array([[np.dot((F64[a] * F64[b]) ** 2, F64[t] ** 2) for t in thirds] for a, b in pairs]))
-    err = np.abs(got - ref)[need == 1] / scale[need == 1]
-    assert np.sqrt(np.mean(err ** 2)) < tol, np.sqrt(np.mean(err ** 2))
+    err = np.abs(got - ref) / scale
+    assert np.sqrt(np.mean(err[need == 1] ** 2)) < tol, np.sqrt(np.mean(err[need == 1] ** 2))
+    # the reduction works in 16 x 16 tiles of its own pair order: an unneeded
+    # entry is 0 (outside every computed tile) or computed like a needed one
+    assert np.all((got[need == 0] == 0) | (err[need == 0] < 50 * tol))
 
 
 def test_triple_reduce_bf16x1_error_study():
@@ -609,13 +605,11 @@ def test_triple_reduce_many_row_tiles(prec, tol):
     P2 = F64[pairs[:, 0]] * F64[pairs[:, 1]]
     ref = P2 @ F64[thirds].T
     scale = np.sqrt((P2 ** 2) @ (F64[thirds] ** 2).T)
-    tile_need = np.zeros_like(need)
-    for i in range(0, need.shape[0], 16):
-        for j in range(0, need.shape[1], 16):
-            tile_need[i:i + 16, j:j + 16] = need[i:i + 16, j:j + 16].any()
-    assert np.all(got[tile_need == 0] == 0)
-    err = np.abs(got - ref)[tile_need == 1] / scale[tile_need == 1]
+    err_all = np.abs(got - ref) / scale
+    err = err_all[need == 1]
     assert np.sqrt(np.mean(err ** 2)) < tol and err.max() < 50 * tol, (np.sqrt(np.mean(err ** 2)), err.max())
+    # unneeded entries: 0, or computed in a tile some needed entry shares
+    assert np.all((got[need == 0] == 0) | (err_all[need == 0] < 50 * tol))
 
 
 # ---------------------------------------------------------------- geometry precompute
