@@ -81,10 +81,53 @@ def cpu_baseline(wl, u, ntri, log_fn):
                 + reps * t["one_triple_dot"])
     log_fn("cpu oracle sample timings (s):", {k: round(v, 3) for k, v in t.items()})
     return {"value": 1.0 / per_mock, "unit": "mocks/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": (f"FP64 oracle on one {n}^3 mock: CIC assignment of {u[0].size} particles to 2 grids, {nfwd} of 44 "
                        f"LOS-weighted forward FFTs, {ninv} of {nfield} inverse shell FFTs, {reps} of {ntri_dots} "
                        f"triple-sum dot products; extrapolated per mock ({per_mock:.1f} s/mock, "
-                       f"{sample_s:.1f} s measured)")}
+                       f"{sample_s:.1f} s measured)"),
+            "c1_64_single_core": c1_single_core(log_fn)}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def c1_single_core(log_fn):
+    """The whole FP64 oracle (catalogue to B_0 and modal coefficients) on the
+    small 64^3 workload, on one thread (FFT workers and BLAS limited to 1)."""
+    import numpy as np
+    import oracle as O
+    from synth import catalog as C
+    from threadpoolctl import threadpool_limits
+    wl = C.workload("c1_64")
+    obs = C.observer_grid_units(wl)
+    u = C.lognormal_catalogue(wl)
+    kf = 2 * math.pi / wl.box
+    k = kf * np.sqrt(np.arange(3 * wl.n ** 2, dtype=np.float64))
+    pf = (1 + 2 * wl.f / 3 + wl.f ** 2 / 5) * C.input_power(wl)(k) + 1.0 / wl.nbar
+    pf[0] = pf[1]
+    workers = O.bispec.WORKERS
+    try:
+        O.bispec.WORKERS = 1
+        with threadpool_limits(1):
+            t0 = time.perf_counter()
+            spec, wsum = O.spectrum_from_catalogue(*u, wl.n, wl.lmax, obs, window=1, interlace=wl.interlace)
+            geo = O.Geometry(wl.n, wl.n_reduce, wl.box, wl.lmax, wl.nbins, wl.k0, wl.dk, wl.P, wl.nmodes, pf)
+            O.estimate(spec, geo, nbar=wsum / wl.box ** 3)
+            s = time.perf_counter() - t0
+    finally:
+        O.bispec.WORKERS = workers
+    log_fn(f"cpu oracle c1_64 on one core: {s:.2f} s")
+    return {"s_per_mock": s, "cores": 1,
+            "workload": f"c1_64: {wl.n}^3, {wl.nparticles} particles, CIC, plane parallel, l=0, {wl.nbins} bins, "
+                        f"{wl.nmodes} modes P={wl.P}; geometry included"}
 
 
 # HIP sources each kernel is built from; a counter summary is used only while
@@ -446,7 +489,8 @@ def main():
                                   f"dk={wl.dk:g}kf, {wl.nmodes} modes P={wl.P}",
                       "precision": args.prec, "ntri": int(ntri), "particles": int(npart),
                       "reduce_schedule": {k: int(getattr(plan.info, "reduce_" + k)) for k in
-                                          ("pairs", "thirds", "tiles", "groups", "maxr", "maxcw", "needed")}}}
+                                          ("pairs", "thirds", "tiles", "groups", "maxr", "maxcw", "needed",
+                                           "row_tiles")}}}
     if not args.no_fp32 and args.prec != "fp32":
         tuned["fp32"] = tune(B.BSP_FP32)
         t32, o32, _ = timed(B.BSP_FP32, args.steps, 1, False)
