@@ -44,7 +44,8 @@ __all__ = [
     "triangle_counts_brute", "closed_triangle_sum_brute", "binned_triple_sums", "binned_triple_sums_full",
     "binned_triple_sums_gemm", "triangle_counts_gemm",
     "binned_bispectrum", "shell_power", "power_multipoles", "skew_spectra", "integrated_bispectrum",
-    "shot_noise_binned", "modal_modes",
+    "shot_noise_binned", "legendre_integral", "ring_factor", "shot_noise_multipoles",
+    "shot_noise_coincidence", "modal_modes",
     "modal_q", "modal_filter", "modal_fields", "modal_numerators", "gram_matrix",
     "modal_solve", "modal_pivots", "modal_solve_pivoted", "modal_shot_noise", "batch_covariance", "spectrum_from_catalogue",
     "spectrum_from_field", "estimate", "Geometry", "n2_max_of",
@@ -685,6 +686,156 @@ def shot_noise_binned(B0: np.ndarray, Pbar: np.ndarray, tris, nbar: float) -> np
     """
     s = np.array([Pbar[a] + Pbar[b] + Pbar[c] for a, b, c in tris])
     return B0 - s / nbar + 2.0 / nbar ** 2
+
+
+# --------------------------------------------------------------------------
+# Poisson shot noise of the multipoles B_l, l > 0 (the paper gives none; a
+# reading derived for the LOS-on-the-first-leg estimator of Sec. 3.1 / eq.
+# (Standard_ell_Estim); see shot_noise_multipoles)
+# --------------------------------------------------------------------------
+
+def legendre_integral(ell: int, mu):
+    """int_0^mu L_l(t) dt for l = 0, 2, 4 (L_2 = (3t^2 - 1)/2, L_4 = (35t^4 - 30t^2 + 3)/8)."""
+    mu = np.asarray(mu, dtype=np.float64)
+    if ell == 0:
+        return mu
+    if ell == 2:
+        return 0.5 * (mu ** 3 - mu)
+    if ell == 4:
+        return (7.0 * mu ** 5 - 10.0 * mu ** 3 + 3.0 * mu) / 8.0
+    raise ValueError("l must be 0, 2 or 4")
+
+
+def ring_factor(ell: int, c1: float, c2: float, c3: float, dk: float, nq: int = 32) -> float:
+    """W_l(b1, b2 | b3): the mean of L_l(k1_hat . k2_hat) over the closed
+    triangles k1 + k2 + k3 = 0 with |k_i| in the shell [c_i - dk/2, c_i + dk/2)
+    (units of k_f), in the continuum: closed triangles with side lengths
+    (k1, k2, k3) have density k1 k2 k3 dk1 dk2 dk3, and k1_hat . k2_hat =
+    (k3^2 - k1^2 - k2^2) / (2 k1 k2) =: mu. The k3 integral is exact
+    (k3 dk3 = k1 k2 dmu, over the k3 shell intersected with |k1 - k2| <= k3 <=
+    k1 + k2), the k1 and k2 integrals nq-point Gauss-Legendre rules over their
+    shells. l = 0 gives 1."""
+    x, w = np.polynomial.legendre.leggauss(nq)
+    k1 = c1 + 0.5 * dk * x
+    k2 = c2 + 0.5 * dk * x
+    K1, K2 = np.meshgrid(k1, k2, indexing="ij")
+    Wq = np.outer(w, w)
+    lo, hi = c3 - 0.5 * dk, c3 + 0.5 * dk
+    m_lo = (np.maximum(lo, np.abs(K1 - K2)) ** 2 - K1 ** 2 - K2 ** 2) / (2.0 * K1 * K2)
+    m_hi = (np.minimum(hi, K1 + K2) ** 2 - K1 ** 2 - K2 ** 2) / (2.0 * K1 * K2)
+    m_lo = np.clip(m_lo, -1.0, 1.0)
+    m_hi = np.clip(np.maximum(m_hi, m_lo), -1.0, 1.0)
+    wt = Wq * (K1 * K2) ** 2
+    den = float(np.sum(wt * (m_hi - m_lo)))
+    if den <= 0.0:
+        return 0.0
+    num = float(np.sum(wt * (legendre_integral(ell, m_hi) - legendre_integral(ell, m_lo))))
+    return num / den
+
+
+def shot_noise_multipoles(P_l: np.ndarray, tris, k0: float, dk: float, nbar: float) -> np.ndarray:
+    """Poisson shot-noise model SN_l(b1, b2, b3) of the raw B_l, [nl][ntri].
+
+    B_l sums delta^(l)(k1) delta(k2) delta(k3) over closed triangles, the
+    Legendre weight on the first leg. For Poisson points the sum over
+    particle triples (i, j, k) holds, beside the distinct triples, the terms
+    with j = k, i = k, i = j (counted with i = j = k) and i = j = k; the
+    distinct part is the sum minus the three pair terms plus twice the triple
+    term. Averaged over a bin: j = k gives P_l(b1)/nbar; i = k gives the
+    power at k2 with the Legendre weight of k1, which, averaging k1 over its
+    ring of directions around k2 at the triangle's opening angle,
+    L_l(k1_hat . x_hat) -> L_l(k1_hat . k2_hat) L_l(k2_hat . x_hat), is
+    W_l(b1, b2 | b3) P_l(b2)/nbar; i = j likewise with b3; i = j = k gives
+    (2l + 1) <L_l(k1_hat . x_hat)>/nbar^2, which is 1/nbar^2 for l = 0 and is
+    dropped for l > 0 (zero for l = 2 over the cubic-symmetric set of closed
+    triangles, a lattice-anisotropy term for l = 4). So
+      SN_0 = (P_0(b1) + P_0(b2) + P_0(b3)) / nbar - 2 / nbar^2   (= shot_noise_binned)
+      SN_l = (P_l(b1) + W_l(b1,b2|b3) P_l(b2) + W_l(b1,b3|b2) P_l(b3)) / nbar.
+    P_l: raw shell power multipoles [nl][nb] (power_multipoles; P_0 = Pbar).
+    The model's accuracy against the exact coincidence terms
+    (shot_noise_coincidence) is pinned in the tests; it is a reading, not in
+    the paper."""
+    P_l = np.asarray(P_l, dtype=np.float64)
+    nl = P_l.shape[0]
+    out = np.zeros((nl, len(tris)))
+    for i, (b1, b2, b3) in enumerate(tris):
+        c1, c2, c3 = k0 + b1 * dk, k0 + b2 * dk, k0 + b3 * dk
+        for li in range(nl):
+            ell = 2 * li
+            if ell == 0:
+                out[li, i] = (P_l[0][b1] + P_l[0][b2] + P_l[0][b3]) / nbar - 2.0 / nbar ** 2
+            else:
+                w12 = ring_factor(ell, c1, c2, c3, dk)
+                w13 = ring_factor(ell, c1, c3, c2, dk)
+                out[li, i] = (P_l[li][b1] + w12 * P_l[li][b2] + w13 * P_l[li][b3]) / nbar
+    return out
+
+
+def shot_noise_coincidence(cnt: np.ndarray, lmax: int, observer, k0: float, dk: float, nb: int,
+                           tris, box: float, nbar_cell: float) -> np.ndarray:
+    """Exact Poisson coincidence terms of the raw B_l for unit-weight particles
+    sitting on the nodes (NGP, no compensation, no interlacing): cnt[N][N][N]
+    particle counts, delta = cnt / nbar_cell - 1. Returns [4][nl][ntri], the
+    sums over particle triples with j = k, i = k, i = j and i = j = k, each in
+    the normalisation of B_l (binned_bispectrum with N' = N); the shot-noise
+    part of B_l is the first three minus twice the last (inclusion-exclusion).
+
+    With F(k) = sum_i exp(-i k.x_i) and the x_hat-product transforms
+    T_t(k) = sum_i x_hat_t(x_i) exp(-i k.x_i), delta^(l)(k) = sum_t c_t(k) T_t(k)
+    (legendre_moments gives c_t(k) as the moment of a unit T_t), and:
+      j = k:      sum_closed delta^(l)(k1) conj F(k1)
+      i = k:      sum_t sum_closed c_t(k1) conj T_t(k2) F(k2)
+      i = j:      sum_t sum_closed c_t(k1) conj T_t(k3) F(k3)
+      i = j = k:  sum_t sum_closed c_t(k1) * T_t(0)
+    (all divided by nbar_cell^3, as delta(k) = F(k) / nbar_cell for k != 0)."""
+    n = cnt.shape[0]
+    plane = observer is None
+    cnt = np.asarray(cnt, dtype=np.float64)
+    tens = [()]
+    xh = None
+    if not plane:
+        xh = node_unit_vectors(n, 0.0, observer)
+        for m in (2, 4):
+            if lmax >= m:
+                tens += los_tensor_indices(m)
+    T = {t: sfft.rfftn(los_weighted_field(cnt, t, xh) if t else cnt, workers=WORKERS) for t in tens}
+    F = T[()]
+    Dl = legendre_moments(T, n, lmax, plane)
+    coef = {}
+    for t in tens:
+        unit = {s2: np.zeros_like(F) for s2 in tens}
+        unit[t] = np.ones_like(F)
+        coef[t] = legendre_moments(unit, n, lmax, plane)
+    tau = {t: float(np.real(T[t][0, 0, 0])) for t in tens}
+    bins = bin_of_n2(n2_grid_half(n), k0, dk, nb)
+
+    def inv(h):
+        return sfft.irfftn(h, s=(n, n, n), workers=WORKERS) * float(n) ** 3
+
+    ind = [inv((bins == b).astype(np.complex128)) for b in range(nb)]
+
+    def closed(h1, b1, h2, b2, h3, b3):
+        # sum over k1 + k2 + k3 = 0 with k_i in shell b_i of h1 h2 h3
+        f = [ind[b] if h is None else inv(np.where(bins == b, h, 0)) for h, b in ((h1, b1), (h2, b2), (h3, b3))]
+        return float(np.sum(f[0] * f[1] * f[2])) / float(n) ** 3
+
+    nl = lmax // 2 + 1
+    out = np.zeros((4, nl, len(tris)))
+    V = box ** 3
+    counts = [closed(None, a, None, b, None, c) for a, b, c in tris]
+    for i, (b1, b2, b3) in enumerate(tris):
+        norm = V ** 2 * float(n) ** 3 / (float(n) ** 12 * counts[i] * nbar_cell ** 3)
+        for li in range(nl):
+            A = closed(Dl[li] * np.conj(F), b1, None, b2, None, b3)
+            B = C = D = 0.0
+            for t in tens:
+                c = coef[t][li]
+                g = np.conj(T[t]) * F
+                B += closed(c, b1, g, b2, None, b3)
+                C += closed(c, b1, None, b2, g, b3)
+                D += closed(c, b1, None, b2, None, b3) * tau[t]
+            out[:, li, i] = np.array([A, B, C, D]) * norm
+    return out
 
 
 # --------------------------------------------------------------------------
