@@ -22,7 +22,8 @@ __all__ = [
     "BSP_TUNE_FORCE",
     "bsp_geometry", "bsp_grid_assign", "bsp_grid_assign_noalloc", "bsp_fft_r2c", "bsp_fft_c2r",
     "bsp_los_moments", "bsp_grid_entry", "bsp_filter_fields", "bsp_triple_reduce", "bsp_modal_coeffs", "bsp_bispectrum_multipoles",
-    "bsp_bispectrum_field", "bsp_batch_run", "BSP_BATCH_GRAPH", "bsp_batch_covariance", "bsp_power_multipoles", "bsp_skew_spectra",
+    "bsp_bispectrum_field", "bsp_batch_run", "BSP_BATCH_GRAPH", "bsp_batch_covariance", "bsp_power_multipoles",
+    "bsp_shot_noise_multipoles", "bsp_skew_spectra",
     "bsp_integrated_bispectrum", "bsp_bispectrum_full", "bsp_set_timing", "bsp_stage_times", "STAGES",
     "EXPORTED",
 ]
@@ -42,8 +43,8 @@ EXPORTED = [
     "bsp_grid_assign_noalloc", "bsp_fft_r2c",
     "bsp_fft_c2r", "bsp_los_moments", "bsp_grid_entry", "bsp_filter_fields", "bsp_triple_reduce",
     "bsp_modal_coeffs", "bsp_bispectrum_multipoles", "bsp_bispectrum_field", "bsp_batch_run",
-    "bsp_batch_covariance", "bsp_power_multipoles", "bsp_skew_spectra", "bsp_integrated_bispectrum",
-    "bsp_bispectrum_full", "bsp_set_timing", "bsp_stage_times",
+    "bsp_batch_covariance", "bsp_power_multipoles", "bsp_shot_noise_multipoles", "bsp_skew_spectra",
+    "bsp_integrated_bispectrum", "bsp_bispectrum_full", "bsp_set_timing", "bsp_stage_times",
 ]
 STAGES = ["assign", "fwd_z", "fwd_y", "fwd_x", "los_combine", "inv_x_filter", "inv_y", "inv_z", "reduce",
           "reduce_combine", "power_multipoles", "skew_spectra", "integrated_bispectrum"]
@@ -118,6 +119,7 @@ def lib():
         "bsp_batch_run": [_vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _i32],
         "bsp_batch_covariance": [_vp, _i32, _i32, _vp, _vp],
         "bsp_power_multipoles": [_vp, _vp, _vp],
+        "bsp_shot_noise_multipoles": [_vp, _vp, _d, _vp],
         "bsp_skew_spectra": [_vp, _vp, _vp],
         "bsp_integrated_bispectrum": [_vp, _vp, _vp, _i32, _d, _d, _i32, _vp, _vp, _vp],
         "bsp_bispectrum_full": [_vp, _vp, _i32, _vp],
@@ -303,6 +305,10 @@ def bsp_batch_covariance(x, m, d, cov, stream: int = 0):
 
 def bsp_power_multipoles(plan, delta_l, P):
     _check(lib().bsp_power_multipoles(plan, _dptr(delta_l), _dptr(P)), plan)
+
+
+def bsp_shot_noise_multipoles(plan, P, nbar, SN):
+    _check(lib().bsp_shot_noise_multipoles(plan, _dptr(P), float(nbar), _dptr(SN)), plan)
 
 
 def bsp_skew_spectra(plan, delta_l, S):

@@ -349,6 +349,7 @@ struct bsp_plan_s {
   double count_residual = -1.0;
   int64_t* d_counts = nullptr;
   int32_t* d_tri_bins = nullptr;
+  double* d_ring = nullptr;  // ring factors of the l > 0 shot noise [nl][ntri][2]
   int32_t* d_tri_tidx = nullptr;
   int32_t* d_combo = nullptr;
   double* d_L = nullptr;
@@ -369,6 +370,7 @@ struct bsp_plan_s {
   bool full_built = false;
   int32_t* d_full_tidx = nullptr;    // [nl^3][ntri] index of each output in T
   std::vector<int32_t> cnt_tidx, gidx, sidx, tri_tidx, tri_bins, combo;
+  std::vector<double> ring_h;
   int32_t *d_cnt_tidx = nullptr, *d_gidx = nullptr, *d_sidx = nullptr, *d_urow = nullptr, *d_grow = nullptr;
   // workspace
   char* ws = nullptr;
@@ -969,6 +971,83 @@ bool build_sn(bsp_plan p) {
   }
   return build_reduce(p->sn_rp, pr, th, need, 2 * P, 3);
 }
+
+// Gauss-Legendre rule of n points on [-1, 1]: Newton's iteration on the
+// Legendre polynomial P_n (three-term recurrence) from the first guesses
+// cos(pi (i + 3/4) / (n + 1/2)).
+void gauss_legendre(int n, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(n, 0.0);
+  w.assign(n, 0.0);
+  const double pi = 3.14159265358979323846;
+  for (int i = 0; i < (n + 1) / 2; ++i) {
+    double z = std::cos(pi * (i + 0.75) / (n + 0.5)), dp = 0.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = 0.0;
+      for (int k = 1; k <= n; ++k) {
+        const double p2 = p1;
+        p1 = p0;
+        p0 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p2) / k;
+      }
+      dp = n * (z * p0 - p1) / (z * z - 1.0);
+      const double dz = p0 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    x[i] = -z;
+    x[n - 1 - i] = z;
+    w[i] = w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+// int_0^mu L_l(t) dt, l = 0, 2, 4.
+double legendre_antiderivative(int l, double mu) {
+  if (l == 2) return 0.5 * (mu * mu * mu - mu);
+  if (l == 4) return (7.0 * std::pow(mu, 5) - 10.0 * mu * mu * mu + 3.0 * mu) / 8.0;
+  return mu;
+}
+
+// Ring factor W_l(b1, b2 | b3) of the l > 0 shot noise: the mean of
+// L_l(k1_hat . k2_hat) over the closed triangles with sides in the shells
+// [c_i - dk/2, c_i + dk/2) (units of k_f), continuum density k1 k2 k3 dk1 dk2
+// dk3 with k1_hat . k2_hat = (k3^2 - k1^2 - k2^2) / (2 k1 k2); the k3 integral
+// in closed form (k3 dk3 = k1 k2 dmu), k1 and k2 by the 32-point rule.
+double ring_factor(int l, double c1, double c2, double c3, double dk, const std::vector<double>& gx,
+                   const std::vector<double>& gw) {
+  const double lo = c3 - 0.5 * dk, hi = c3 + 0.5 * dk;
+  double num = 0.0, den = 0.0;
+  for (size_t a = 0; a < gx.size(); ++a) {
+    const double k1 = c1 + 0.5 * dk * gx[a];
+    for (size_t b = 0; b < gx.size(); ++b) {
+      const double k2 = c2 + 0.5 * dk * gx[b];
+      const double s = 2.0 * k1 * k2, q = k1 * k1 + k2 * k2;
+      const double r_lo = std::max(lo, std::fabs(k1 - k2)), r_hi = std::min(hi, k1 + k2);
+      const double m_lo = std::clamp((r_lo * r_lo - q) / s, -1.0, 1.0);
+      const double m_hi = std::clamp(std::max((r_hi * r_hi - q) / s, m_lo), -1.0, 1.0);
+      const double wt = gw[a] * gw[b] * (k1 * k2) * (k1 * k2);
+      den += wt * (m_hi - m_lo);
+      num += wt * (legendre_antiderivative(l, m_hi) - legendre_antiderivative(l, m_lo));
+    }
+  }
+  return den > 0.0 ? num / den : 0.0;
+}
+
+// Ring factors of every triangle of the plan: [nl][ntri][2] = W_l(b1,b2|b3),
+// W_l(b1,b3|b2) (row l = 0 unused, 1).
+void build_ring(bsp_plan p) {
+  const int ntri = (int)p->tri.size(), nl = p->nl;
+  std::vector<double> gx, gw;
+  gauss_legendre(32, gx, gw);
+  p->ring_h.assign((size_t)nl * ntri * 2, 1.0);
+  for (int li = 1; li < nl; ++li)
+    for (int i = 0; i < ntri; ++i) {
+      const double c1 = p->g.k0 + p->tri[i][0] * p->g.dk, c2 = p->g.k0 + p->tri[i][1] * p->g.dk,
+                   c3 = p->g.k0 + p->tri[i][2] * p->g.dk;
+      double* w = &p->ring_h[((size_t)li * ntri + i) * 2];
+      w[0] = ring_factor(2 * li, c1, c2, c3, p->g.dk, gx, gw);
+      w[1] = ring_factor(2 * li, c1, c3, c2, p->g.dk, gx, gw);
+    }
+}
+
 
 // Main schedule: pairs (D0_b2 D0_b3, b2 >= b3), (M0_a M0_b), (M2_a M2_b);
 // thirds D^l_b1 interleaved (b1, l), then M^l_s interleaved (s, l).
@@ -1726,7 +1805,10 @@ bsp_status bsp_precompute(bsp_plan p) {
   p->d_tri_tidx = upload(p, p->tri_tidx);
   p->d_tri_bins = upload(p, p->tri_bins);
   if (p->modal) p->d_combo = upload(p, p->combo);
-  if (!p->d_counts || !p->d_tri_tidx || !p->d_tri_bins || (p->modal && !p->d_combo))
+  build_ring(p);
+  if (!p->ring_h.empty()) p->d_ring = upload(p, p->ring_h);
+  if (!p->d_counts || !p->d_tri_tidx || !p->d_tri_bins || (p->modal && !p->d_combo) ||
+      (!p->ring_h.empty() && !p->d_ring))
     return fail(p, BSP_ERR_HIP, "allocation failed");
   p->pre_done = true;
   return BSP_OK;
@@ -2100,6 +2182,13 @@ bsp_status bsp_power_multipoles(bsp_plan p, const void* delta_l, double* P) {
   const float2* dl = reinterpret_cast<const float2*>(delta_l);
   HIPCHK(launch_shell_cross(dl, p->spec, p->nl, dl, p->c, p->cz, p->d_bin_of_n2, p->n2max, p->nbins, p->d_nb_modes,
                             p->V / std::pow((double)p->N, 6), psum, P, p->stream));
+  return BSP_OK;
+}
+
+bsp_status bsp_shot_noise_multipoles(bsp_plan p, const double* Pl, double nbar, double* SN) {
+  if (!p || !Pl || !SN || !(nbar > 0.0)) return fail(p, BSP_ERR_ARG, "null argument or nbar <= 0");
+  if (!p->pre_done) return fail(p, BSP_ERR_STATE, "bsp_precompute has not run");
+  HIPCHK(launch_shot_noise(Pl, p->nbins, p->d_tri_bins, (int)p->tri.size(), p->nl, p->d_ring, nbar, SN, p->stream));
   return BSP_OK;
 }
 

@@ -236,6 +236,8 @@ hipError_t launch_binned_finalize(const double* T, const int32_t* tri_tidx, int 
                                   const int64_t* counts, const double* psum, const int64_t* nb_modes,
                                   int nbins, const int32_t* tri_bins, double norm_b, double pnorm,
                                   const double* nbar, double* B, double* B0sub, double* Pbar, hipStream_t s);
+hipError_t launch_shot_noise(const double* Pl, int nbins, const int32_t* tri_bins, int ntri, int nl,
+                             const double* ring, double nbar, double* SN, hipStream_t s);
 hipError_t launch_counts_finalize(const double* T, const int32_t* tidx, int ntri, double inv_k,
                                   int64_t* counts, double* raw, int32_t* err, hipStream_t s);
 hipError_t launch_modal_assemble(const double* T, const int32_t* combo, int nmodes, int nl,

@@ -32,6 +32,24 @@ __global__ void k_binned_finalize(const double* __restrict__ T, const int32_t* _
   }
 }
 
+// Poisson shot noise of B_l (the reading of the multipole estimator's
+// coincidence terms): per triangle i and multipole l,
+//   SN_0 = (P_0(b1) + P_0(b2) + P_0(b3)) / nbar - 2 / nbar^2,
+//   SN_l = (P_l(b1) + W[l][i][0] P_l(b2) + W[l][i][1] P_l(b3)) / nbar  (l > 0),
+// W the ring factors of the plan ([nl][ntri][2], row 0 unused).
+__global__ void k_shot_noise(const double* __restrict__ Pl, int nbins, const int32_t* __restrict__ tri_bins, int ntri,
+                             int nl, const double* __restrict__ ring, double nbar, double* __restrict__ SN) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= ntri) return;
+  const int b1 = tri_bins[3 * i], b2 = tri_bins[3 * i + 1], b3 = tri_bins[3 * i + 2];
+  SN[i] = (Pl[b1] + Pl[b2] + Pl[b3]) / nbar - 2.0 / (nbar * nbar);
+  for (int l = 1; l < nl; ++l) {
+    const double* P = Pl + (int64_t)l * nbins;
+    const double* w = ring + ((int64_t)l * ntri + i) * 2;
+    SN[(int64_t)l * ntri + i] = (P[b1] + w[0] * P[b2] + w[1] * P[b3]) / nbar;
+  }
+}
+
 // counts_i = round(T_i / N'^3); bit 2 of err if any |T/N'^3 - round| >= 0.05
 // (rounding is unambiguous below 0.5; FP64 sums of 1e8 terms of this dynamic
 // range leave ~1e-3 on counts of 1e10).
@@ -260,6 +278,14 @@ hipError_t launch_binned_finalize(const double* T, const int32_t* tri_tidx, int 
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_binned_finalize, dim3(nblk(n, 256)), dim3(256), 0, s, T, tri_tidx, ntri, nl, counts, psum,
                      nb_modes, nbins, tri_bins, norm_b, pnorm, nbar, B, B0sub, Pbar);
+  return hipGetLastError();
+}
+
+hipError_t launch_shot_noise(const double* Pl, int nbins, const int32_t* tri_bins, int ntri, int nl,
+                             const double* ring, double nbar, double* SN, hipStream_t s) {
+  if (ntri <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_shot_noise, dim3((unsigned)((ntri + 255) / 256)), dim3(256), 0, s, Pl, nbins, tri_bins, ntri,
+                     nl, ring, nbar, SN);
   return hipGetLastError();
 }
 
