@@ -205,6 +205,22 @@ def spectra_legs(B, torch, plan, wl, ux, uy, uz, npart, pbar_path, b_path, prec,
     pm = {"ms": avg_s * 1e3, "launches": n, "algorithmic_bytes": amt / n, "achieved_GBps": amt / n / avg_s / 1e9,
           "frac_hbm": amt / n / avg_s / PEAK_HBM, "P0_vs_path_Pbar": float(np.linalg.norm(p0 - pb) / np.linalg.norm(pb)),
           "P_l_first_bins": [[float(x) for x in Pl[li, :3].cpu().numpy()] for li in range(nl)]}
+    # Poisson shot-noise model of every B_l from these shell powers (unit weights: nbar = N / V)
+    ntri = plan.info.ntri
+    SN = torch.zeros((nl, ntri), dtype=torch.float64, device=dev)
+    nbar = npart / wl.box ** 3
+    B.bsp_shot_noise_multipoles(plan.handle, Pl, nbar, SN)
+    plan.sync()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        B.bsp_shot_noise_multipoles(plan.handle, Pl, nbar, SN)
+    plan.sync()
+    sn_ms = (time.perf_counter() - t0) / reps * 1e3
+    bl = b_path.cpu().numpy()
+    sn = SN.cpu().numpy()
+    pm["shot_noise"] = {"ms_per_call_host_timed": sn_ms, "nbar": nbar,
+                        "SN_norm_over_B_norm": [float(np.linalg.norm(sn[li]) / np.linalg.norm(bl[li])) for li in range(nl)]}
+    log_fn(f"shot noise model: {sn_ms:.3f} ms per call, |SN_l|/|B_l| = {pm['shot_noise']['SN_norm_over_B_norm']}")
     Sl = torch.zeros((nl, wl.nbins), dtype=torch.float64, device=dev)
     B.bsp_skew_spectra(plan.handle, dl, Sl)
     plan.sync()
