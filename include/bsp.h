@@ -64,7 +64,8 @@ typedef enum {
   BSP_ERR_HIP = 5,       /* HIP runtime error (message in bsp_last_error) */
   BSP_ERR_DEVICE = 6,    /* latched by a kernel: particle outside [0,N) or not finite */
   BSP_ERR_NUMERIC = 7,   /* latched: triangle count residual >= 0.05, or Cholesky failure */
-  BSP_ERR_STATE = 8      /* call out of order */
+  BSP_ERR_STATE = 8,     /* call out of order */
+  BSP_ERR_IO = 9         /* batch journal could not be opened, read, locked or written */
 } bsp_status;
 
 typedef enum {
@@ -433,6 +434,62 @@ bsp_status bsp_batch_run(const bsp_plan* plans, int32_t nplans, const int32_t* m
                          const float* const* ux, const float* const* uy, const float* const* uz,
                          const float* const* w, const int64_t* np, bsp_precision prec, double* B_all,
                          double* alpha_all, double* beta_all, double* cov, int32_t flags);
+
+/* Checkpoint and resume of a batch (the covariance runs of Sec. 3.5 are
+ * hundreds of independent mocks; a stopped batch should not redo the finished
+ * ones). As bsp_batch_run, with a journal file of one record per finished
+ * mock: the caller's key of the mock (mock_key host [nmocks], e.g. the seed
+ * of its catalogue), the configuration hash of its plan (bsp_config_hash),
+ * its particle count and its B, alpha and (when beta_all is given) beta,
+ * closed by a 64-bit FNV-1a checksum. A mock whose (key, hash) is recorded
+ * with the same particle count is not run: its outputs are copied from the
+ * record into B_all, alpha_all and beta_all. Every other mock runs and is
+ * appended to the journal as soon as its outputs are on the host (the host
+ * writes mock k while mock k+1 runs), unless a kernel error is latched on its
+ * plan, which ends the call with that error. A process killed at any point
+ * leaves a journal whose valid prefix holds whole records only: a torn last
+ * record fails its length or checksum test and is cut off by the next call.
+ * The file is created if absent and locked exclusively (flock) for the call.
+ * Outputs are bit-identical to one uninterrupted bsp_batch_run: the records
+ * hold the FP64 outputs exactly, and the covariance is computed over all
+ * mocks at the end. nresumed (host, nullable): mocks taken from the journal.
+ * flags: BSP_BATCH_GRAPH as bsp_batch_run; BSP_BATCH_FSYNC also makes each
+ * record durable (fdatasync) before the next is written. Errors: those of
+ * bsp_batch_run; BSP_ERR_ARG if mock_key is NULL, two mocks share a key on the
+ * same configuration, or a record of the same key and configuration has
+ * another particle count; BSP_ERR_IO if the journal cannot be opened, is not
+ * a journal, is locked by another process, or cannot be read or written. */
+#define BSP_BATCH_FSYNC 2
+bsp_status bsp_batch_run_journal(const bsp_plan* plans, int32_t nplans, const int32_t* mock_plan, int32_t nmocks,
+                                 const uint64_t* mock_key, const float* const* ux, const float* const* uy,
+                                 const float* const* uz, const float* const* w, const int64_t* np,
+                                 bsp_precision prec, double* B_all, double* alpha_all, double* beta_all,
+                                 double* cov, int32_t flags, const char* journal, int32_t* nresumed);
+
+/* Configuration hash under which the journal records a mock of this plan at
+ * precision prec: a 64-bit FNV-1a hash of the geometry, the modal basis
+ * (functions, modes, P_fid, drop tolerance), the kept modes, the triangles,
+ * the precision and the journal format. Host output. Needs bsp_precompute
+ * (BSP_ERR_STATE). Plans of different N hash differently. */
+bsp_status bsp_config_hash(bsp_plan plan, bsp_precision prec, uint64_t* hash /*host*/);
+
+/* Host-only journal access (no GPU call; errors via bsp_last_error(NULL)).
+ * scan: opens read-only and counts the whole, checksummed records of the valid
+ * prefix (valid_bytes) of a file of file_bytes (a torn tail is the
+ * difference); the file is not changed. append: appends one record (host
+ * arrays B [nl][ntri], alpha [d], beta [d] or NULL), cutting a torn tail off
+ * first; BSP_ERR_ARG if the key is already recorded for config_hash. lookup:
+ * found = 1 and the record copied to B, alpha, beta (beta nullable) if a
+ * record of (key, config_hash) with these sizes exists and holds beta when
+ * asked for; found = 0 otherwise; BSP_ERR_ARG if it exists with other sizes.
+ * All three return BSP_ERR_IO for a file that cannot be opened or locked or
+ * is not a journal of this format. */
+bsp_status bsp_journal_scan(const char* journal, int64_t* nrecords /*host*/, int64_t* valid_bytes /*host*/,
+                            int64_t* file_bytes /*host*/);
+bsp_status bsp_journal_append(const char* journal, uint64_t key, uint64_t config_hash, int64_t np, int32_t nl,
+                              int32_t ntri, int32_t d, const double* B, const double* alpha, const double* beta);
+bsp_status bsp_journal_lookup(const char* journal, uint64_t key, uint64_t config_hash, int64_t np, int32_t nl,
+                              int32_t ntri, int32_t d, double* B, double* alpha, double* beta, int32_t* found);
 
 /* Sample covariance of a batch of coefficient vectors (FP64):
  * cov = (1/(M-1)) sum_m (x_m - mean)(x_m - mean)^T. x: device [m][d], cov:

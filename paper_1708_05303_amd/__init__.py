@@ -22,7 +22,9 @@ __all__ = [
     "BSP_TUNE_FORCE",
     "bsp_geometry", "bsp_grid_assign", "bsp_grid_assign_noalloc", "bsp_fft_r2c", "bsp_fft_c2r",
     "bsp_los_moments", "bsp_grid_entry", "bsp_filter_fields", "bsp_triple_reduce", "bsp_modal_coeffs", "bsp_bispectrum_multipoles",
-    "bsp_bispectrum_field", "bsp_batch_run", "BSP_BATCH_GRAPH", "bsp_batch_covariance", "bsp_power_multipoles",
+    "bsp_bispectrum_field", "bsp_batch_run", "BSP_BATCH_GRAPH", "BSP_BATCH_FSYNC", "bsp_batch_run_journal",
+    "bsp_config_hash", "bsp_journal_scan", "bsp_journal_append", "bsp_journal_lookup",
+    "bsp_batch_covariance", "bsp_power_multipoles",
     "bsp_shot_noise_multipoles", "bsp_skew_spectra",
     "bsp_integrated_bispectrum", "bsp_bispectrum_full", "bsp_set_timing", "bsp_stage_times", "STAGES",
     "EXPORTED",
@@ -34,7 +36,7 @@ LIB_PATH = os.path.join(HERE, "libbsp.so")
 BSP_FP32, BSP_BF16X3, BSP_FP16X3, BSP_BF16X1 = 0, 1, 2, 3
 PRECISIONS = {"fp32": BSP_FP32, "bf16x3": BSP_BF16X3, "fp16x3": BSP_FP16X3, "bf16x1": BSP_BF16X1}
 STATUS = {0: "BSP_OK", 1: "BSP_ERR_ARG", 2: "BSP_ERR_SIZE", 3: "BSP_ERR_ALIAS", 4: "BSP_ERR_WORKSPACE",
-          5: "BSP_ERR_HIP", 6: "BSP_ERR_DEVICE", 7: "BSP_ERR_NUMERIC", 8: "BSP_ERR_STATE"}
+          5: "BSP_ERR_HIP", 6: "BSP_ERR_DEVICE", 7: "BSP_ERR_NUMERIC", 8: "BSP_ERR_STATE", 9: "BSP_ERR_IO"}
 
 # every symbol include/bsp.h declares
 EXPORTED = [
@@ -43,6 +45,7 @@ EXPORTED = [
     "bsp_grid_assign_noalloc", "bsp_fft_r2c",
     "bsp_fft_c2r", "bsp_los_moments", "bsp_grid_entry", "bsp_filter_fields", "bsp_triple_reduce",
     "bsp_modal_coeffs", "bsp_bispectrum_multipoles", "bsp_bispectrum_field", "bsp_batch_run",
+    "bsp_batch_run_journal", "bsp_config_hash", "bsp_journal_scan", "bsp_journal_append", "bsp_journal_lookup",
     "bsp_batch_covariance", "bsp_power_multipoles", "bsp_shot_noise_multipoles", "bsp_skew_spectra",
     "bsp_integrated_bispectrum", "bsp_bispectrum_full", "bsp_set_timing", "bsp_stage_times",
 ]
@@ -117,6 +120,12 @@ def lib():
         "bsp_bispectrum_multipoles": [_vp, _vp, _vp, _vp, _vp, _i64, _i32, _vp, _vp, _vp, _vp, _vp, _vp],
         "bsp_bispectrum_field": [_vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp],
         "bsp_batch_run": [_vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _i32],
+        "bsp_batch_run_journal": [_vp, _i32, _vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp, _vp, _vp,
+                                  _i32, C.c_char_p, _vp],
+        "bsp_config_hash": [_vp, _i32, _vp],
+        "bsp_journal_scan": [C.c_char_p, _vp, _vp, _vp],
+        "bsp_journal_append": [C.c_char_p, C.c_uint64, C.c_uint64, _i64, _i32, _i32, _i32, _vp, _vp, _vp],
+        "bsp_journal_lookup": [C.c_char_p, C.c_uint64, C.c_uint64, _i64, _i32, _i32, _i32, _vp, _vp, _vp, _vp],
         "bsp_batch_covariance": [_vp, _i32, _i32, _vp, _vp],
         "bsp_power_multipoles": [_vp, _vp, _vp],
         "bsp_shot_noise_multipoles": [_vp, _vp, _d, _vp],
@@ -280,12 +289,10 @@ def bsp_bispectrum_field(plan, delta, prec, B, Pbar=None, bnum=None, alpha=None,
 
 
 BSP_BATCH_GRAPH = 1
+BSP_BATCH_FSYNC = 2
 
 
-def bsp_batch_run(plans, mock_plan, ux, uy, uz, w, np_, prec, B_all, alpha_all, beta_all, cov, flags=BSP_BATCH_GRAPH):
-    """plans: list of plan handles; mock_plan, np_: per-mock ints; ux, uy, uz, w:
-    per-mock float32 device tensors (w None or a list with None entries);
-    flags: BSP_BATCH_GRAPH replays each plan's captured whole path, 0 calls it."""
+def _batch_args(plans, mock_plan, ux, uy, uz, w, np_):
     import torch
     nm, npl = len(mock_plan), len(plans)
     P = (C.c_void_p * npl)(*[h.value if isinstance(h, C.c_void_p) else h for h in plans])
@@ -295,8 +302,66 @@ def bsp_batch_run(plans, mock_plan, ux, uy, uz, w, np_, prec, B_all, alpha_all, 
     def ptrs(ts):
         return (C.c_void_p * nm)(*[_dptr(t, torch.float32) for t in ts])
     W = None if w is None else ptrs(w)
-    _check(lib().bsp_batch_run(P, npl, mp, nm, ptrs(ux), ptrs(uy), ptrs(uz), W, NP, prec, _dptr(B_all),
-                               _dptr(alpha_all), _dptr(beta_all), _dptr(cov), int(flags)), plans[0])
+    return P, npl, mp, nm, ptrs(ux), ptrs(uy), ptrs(uz), W, NP
+
+
+def bsp_batch_run(plans, mock_plan, ux, uy, uz, w, np_, prec, B_all, alpha_all, beta_all, cov, flags=BSP_BATCH_GRAPH):
+    """plans: list of plan handles; mock_plan, np_: per-mock ints; ux, uy, uz, w:
+    per-mock float32 device tensors (w None or a list with None entries);
+    flags: BSP_BATCH_GRAPH replays each plan's captured whole path, 0 calls it."""
+    P, npl, mp, nm, X, Y, Z, W, NP = _batch_args(plans, mock_plan, ux, uy, uz, w, np_)
+    _check(lib().bsp_batch_run(P, npl, mp, nm, X, Y, Z, W, NP, prec, _dptr(B_all), _dptr(alpha_all),
+                               _dptr(beta_all), _dptr(cov), int(flags)), plans[0])
+
+
+def bsp_batch_run_journal(plans, mock_plan, mock_key, ux, uy, uz, w, np_, prec, B_all, alpha_all, beta_all, cov,
+                          journal, flags=BSP_BATCH_GRAPH):
+    """bsp_batch_run with a checkpoint journal (path); mock_key: per-mock
+    unsigned 64-bit keys. Returns the number of mocks taken from the journal."""
+    P, npl, mp, nm, X, Y, Z, W, NP = _batch_args(plans, mock_plan, ux, uy, uz, w, np_)
+    keys = (C.c_uint64 * nm)(*[int(k) for k in mock_key])
+    nres = C.c_int32(0)
+    _check(lib().bsp_batch_run_journal(P, npl, mp, nm, keys, X, Y, Z, W, NP, prec, _dptr(B_all), _dptr(alpha_all),
+                                       _dptr(beta_all), _dptr(cov), int(flags), os.fsencode(journal),
+                                       C.byref(nres)), plans[0])
+    return nres.value
+
+
+def bsp_config_hash(plan, prec) -> int:
+    h = C.c_uint64(0)
+    _check(lib().bsp_config_hash(plan, prec, C.byref(h)), plan)
+    return h.value
+
+
+def bsp_journal_scan(journal):
+    """(records, valid_bytes, file_bytes) of a journal file; host only."""
+    n, v, f = C.c_int64(0), C.c_int64(0), C.c_int64(0)
+    _check(lib().bsp_journal_scan(os.fsencode(journal), C.byref(n), C.byref(v), C.byref(f)))
+    return n.value, v.value, f.value
+
+
+def bsp_journal_append(journal, key, config_hash, np_, B, alpha, beta=None):
+    """Appends one record; B: host float64 [nl][ntri], alpha, beta: host float64 [d]."""
+    B = np.ascontiguousarray(B, dtype=np.float64)
+    alpha = np.ascontiguousarray(alpha, dtype=np.float64)
+    beta = None if beta is None else np.ascontiguousarray(beta, dtype=np.float64)
+    if B.ndim != 2 or alpha.ndim != 1 or (beta is not None and beta.shape != alpha.shape):
+        raise ValueError("B must be [nl][ntri], alpha and beta [d]")
+    _check(lib().bsp_journal_append(os.fsencode(journal), int(key), int(config_hash), int(np_), B.shape[0],
+                                    B.shape[1], alpha.shape[0], B.ctypes.data, alpha.ctypes.data,
+                                    None if beta is None else beta.ctypes.data))
+
+
+def bsp_journal_lookup(journal, key, config_hash, np_, nl, ntri, d, with_beta=True):
+    """(B, alpha, beta) of a record, or None if there is none."""
+    B = np.zeros((nl, ntri))
+    alpha = np.zeros(d)
+    beta = np.zeros(d) if with_beta else None
+    found = C.c_int32(0)
+    _check(lib().bsp_journal_lookup(os.fsencode(journal), int(key), int(config_hash), int(np_), nl, ntri, d,
+                                    B.ctypes.data, alpha.ctypes.data, None if beta is None else beta.ctypes.data,
+                                    C.byref(found)))
+    return (B, alpha, beta) if found.value else None
 
 
 def bsp_batch_covariance(x, m, d, cov, stream: int = 0):

@@ -1475,6 +1475,7 @@ bsp_status bsp_grid_assign(bsp_plan p, const float* ux, const float* uy, const f
 
 // ---------------------------------------------------------------- no-allocation assignment
 
+extern "C++" {  // helpers keep C++ (internal) linkage inside the C block
 namespace {
 
 // Static device scratch of bsp_grid_assign_noalloc: the int64 node sums of the
@@ -1509,6 +1510,7 @@ hipError_t static_scratch(void** out) {
 }
 
 }  // namespace
+}  // extern "C++"
 
 bsp_status bsp_grid_assign_noalloc(bsp_plan p, const float* ux, const float* uy, const float* uz, const float* w,
                                    int64_t np, float* grids, double* wsum) {
@@ -1528,7 +1530,7 @@ bsp_status bsp_grid_assign_noalloc(bsp_plan p, const float* ux, const float* uy,
 
 // FP32 twiddles of a supported transform size (the plan's N and N' are built
 // with the plan, other sizes on first use and kept with it).
-const float2* tw32_for(bsp_plan p, int n) {
+static const float2* tw32_for(bsp_plan p, int n) {
   if (n == p->N) return p->tw32_N;
   if (n == p->Nr) return p->tw32_Nr;
   auto it = p->tw32_other.find(n);
@@ -1541,7 +1543,7 @@ const float2* tw32_for(bsp_plan p, int n) {
 }
 
 // Unnormalised r2c of `batch` contiguous n^3 grids into [batch][n][n][n/2+1].
-bsp_status r2c_batch(bsp_plan p, int n, int batch, const float* in, float2* out, const float2* tw) {
+static bsp_status r2c_batch(bsp_plan p, int n, int batch, const float* in, float2* out, const float2* tw) {
   const int h = n / 2 + 1;
   FwdZDesc fz{};
   fz.ngrid = batch;
@@ -1830,6 +1832,7 @@ bsp_status bsp_geometry(bsp_plan p, int32_t* tri, int64_t* counts, double* gamma
 
 // ---------------------------------------------------------------- autotuning
 
+extern "C++" {  // helpers keep C++ (internal) linkage inside the C block
 namespace {
 
 std::string tune_key(const bsp_plan p, bsp_precision prec) {
@@ -1930,6 +1933,7 @@ double time_min(bsp_plan p, int reps, const std::function<bsp_status()>& f, bsp_
 }
 
 }  // namespace
+}  // extern "C++"
 
 bsp_status bsp_autotune(bsp_plan p, bsp_precision prec, const char* db_path, int32_t flags) {
   if (!p) return BSP_ERR_ARG;
@@ -2016,6 +2020,7 @@ bsp_status bsp_autotune(bsp_plan p, bsp_precision prec, const char* db_path, int
 
 // ---------------------------------------------------------------- estimators
 
+extern "C++" {  // helpers keep C++ (internal) linkage inside the C block
 namespace {
 
 // fields -> T -> B, Pbar, modal numerators and coefficients (everything after delta_l)
@@ -2075,6 +2080,7 @@ bsp_status estimate_from_spectrum(bsp_plan p, const float2* dl, bsp_precision pr
 }
 
 }  // namespace
+}  // extern "C++"
 
 bsp_status bsp_modal_coeffs(bsp_plan p, const void* delta_l, bsp_precision prec, double nbar, double* bnum,
                             double* alpha, double* beta) {
@@ -2092,6 +2098,7 @@ bsp_status bsp_modal_coeffs(bsp_plan p, const void* delta_l, bsp_precision prec,
                                 nullptr, nullptr, bnum, alpha, beta, false, true);
 }
 
+extern "C++" {  // helpers keep C++ (internal) linkage inside the C block
 namespace {
 
 // The whole path on the plan's stream, kernels only (no host synchronisation,
@@ -2130,6 +2137,7 @@ bsp_status whole_path(bsp_plan p, const float* ux, const float* uy, const float*
 }
 
 }  // namespace
+}  // extern "C++"
 
 bsp_status bsp_bispectrum_multipoles(bsp_plan p, const float* ux, const float* uy, const float* uz, const float* w,
                                      int64_t np, bsp_precision prec, double* B, double* B0sub, double* Pbar,
@@ -2343,7 +2351,7 @@ bsp_status bsp_integrated_bispectrum(bsp_plan p, const float* grid, const double
 // pairs (D^l2_b2 D^l3_b3, b2 >= b3; for b2 = b3 only l2 <= l3, the other order
 // is the same product) in b2-major order, thirds D^l1_b1, every combination of
 // each triangle with a nonzero count.
-bool build_full(bsp_plan p) {
+static bool build_full(bsp_plan p) {
   const int nb = p->nbins, nl = p->nl, nsh = nb * nl;
   std::vector<std::array<int, 2>> pr;
   std::vector<int> pidx((size_t)nsh * nsh, -1);
@@ -2447,6 +2455,7 @@ bsp_status bsp_stage_times(bsp_plan p, double* ms, int64_t* launches, double* am
   return BSP_OK;
 }
 
+extern "C++" {  // helpers keep C++ (internal) linkage inside the C block
 namespace {
 
 // (Re)captures the whole path of plan q into q's batch graph for catalogues of
@@ -2499,16 +2508,73 @@ bsp_status batch_graph(bsp_plan q, bsp_precision prec, int64_t cap, int has_w) {
 }
 
 }  // namespace
+}  // extern "C++"
 
-bsp_status bsp_batch_run(const bsp_plan* plans, int32_t nplans, const int32_t* mock_plan, int32_t nmocks,
-                         const float* const* ux, const float* const* uy, const float* const* uz,
-                         const float* const* w, const int64_t* np, bsp_precision prec, double* B_all,
-                         double* alpha_all, double* beta_all, double* cov, int32_t flags) {
+extern "C++" {  // helpers keep C++ (internal) linkage inside the C block
+namespace {
+
+// Content hash of everything that fixes a mock's outputs apart from its
+// catalogue: the geometry, the modal basis and the modes the
+// orthonormalisation kept, the triangles, the precision and the journal
+// format. Journal records are matched on (mock key, this hash).
+uint64_t config_hash(const bsp_plan p, bsp_precision prec) {
+  uint64_t h = fnv1a64("libbsp batch journal v1", 23);
+  auto mix = [&h](const void* d, size_t n) { h = fnv1a64(d, n, h); };
+  auto mixi = [&mix](int64_t v) { mix(&v, sizeof v); };
+  auto mixd = [&mix](double v) { mix(&v, sizeof v); };
+  mixi(p->N);
+  mixi(p->Nr);
+  mixd(p->g.box);
+  mixi(p->g.window);
+  mixi(p->g.compensate);
+  mixi(p->g.interlace);
+  mixi(p->g.los);
+  for (double o : p->g.observer) mixd(p->g.los ? o : 0.0);
+  mixi(p->g.lmax);
+  mixi(p->g.nbins);
+  mixd(p->g.k0);
+  mixd(p->g.dk);
+  mixi(p->modal ? 1 : 0);
+  mixi(p->P);
+  mixi(p->nmodes);
+  mix(p->modes.data(), p->modes.size() * sizeof(int32_t));
+  mix(p->pfid.data(), p->pfid.size() * sizeof(double));
+  mixd(p->drop_tol);
+  mix(p->piv_h.data(), p->piv_h.size() * sizeof(int32_t));
+  for (const auto& t : p->tri) mix(t.data(), 3 * sizeof(int));
+  mixi((int)prec);
+  return h;
+}
+
+// Pinned staging of finished mocks' outputs on their way to the journal: two
+// slots, each [B | alpha | beta | error word]; the host writes mock k's record
+// while mock k+1 runs. Released only after every stream that copies into it
+// has drained.
+struct JournalStage {
+  double* h = nullptr;
+  int64_t slot = 0;  // doubles per slot
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  std::vector<hipStream_t> streams;
+  ~JournalStage() {
+    for (hipStream_t s : streams) (void)hipStreamSynchronize(s);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (h) (void)hipHostFree(h);
+  }
+};
+
+bsp_status batch_impl(const bsp_plan* plans, int32_t nplans, const int32_t* mock_plan, int32_t nmocks,
+                      const uint64_t* mock_key, const float* const* ux, const float* const* uy,
+                      const float* const* uz, const float* const* w, const int64_t* np, bsp_precision prec,
+                      double* B_all, double* alpha_all, double* beta_all, double* cov, int32_t flags,
+                      const char* journal_path, int32_t* nresumed) {
   if (!plans || nplans < 1 || !mock_plan || nmocks < 2 || !ux || !uy || !uz || !np || !B_all || !alpha_all || !cov)
     return fail(nullptr, BSP_ERR_ARG, "bad argument");
   bsp_plan p0 = plans[0];
   if (!p0) return fail(nullptr, BSP_ERR_ARG, "null plan");
   if (prec < BSP_FP32 || prec > BSP_BF16X1) return fail(p0, BSP_ERR_ARG, "bad precision");
+  const bool journaled = journal_path != nullptr;
+  if (journaled && (!mock_key || !*journal_path)) return fail(p0, BSP_ERR_ARG, "journal without mock keys or path");
   // every plan must produce outputs of the same shape: nl, triangles and modes
   for (int i = 0; i < nplans; ++i) {
     bsp_plan q = plans[i];
@@ -2530,13 +2596,44 @@ bsp_status bsp_batch_run(const bsp_plan* plans, int32_t nplans, const int32_t* m
     if (np[m] < 1 || !ux[m] || !uy[m] || !uz[m]) return fail(p0, BSP_ERR_ARG, "empty or null mock catalogue");
   }
   const int64_t ntri = (int64_t)p0->tri.size();
+  const int64_t nB = (int64_t)p0->nl * ntri;
   const int64_t D = (int64_t)p0->nl * p0->nmodes;
   const bool graphs = (flags & BSP_BATCH_GRAPH) != 0;
+  if (nresumed) *nresumed = 0;
+
+  // journal: which mocks are already recorded under their plan's configuration
+  Journal jn;
+  std::vector<uint64_t> hashes(nplans, 0);
+  std::vector<const JournalRecord*> rec(nmocks, nullptr);
+  int64_t nres = 0;
+  if (journaled) {
+    std::string err;
+    if (!jn.open(journal_path, true, err)) return fail(p0, BSP_ERR_IO, err);
+    for (int i = 0; i < nplans; ++i) hashes[i] = config_hash(plans[i], prec);
+    std::vector<std::pair<uint64_t, uint64_t>> seen;
+    for (int m = 0; m < nmocks; ++m) {
+      const uint64_t hm = hashes[mock_plan[m]];
+      seen.emplace_back(mock_key[m], hm);
+      const JournalRecord* r = jn.find(mock_key[m], hm);
+      if (!r) continue;
+      if (r->np != np[m] || r->nl != p0->nl || r->ntri != ntri || r->d != D)
+        return fail(p0, BSP_ERR_ARG, "journal record of mock key " + std::to_string(mock_key[m]) +
+                                         " has another particle count or output shape");
+      if (beta_all && !r->has_beta) continue;  // recorded without beta: run it again
+      rec[m] = r;
+      ++nres;
+    }
+    std::sort(seen.begin(), seen.end());
+    if (std::adjacent_find(seen.begin(), seen.end()) != seen.end())
+      return fail(p0, BSP_ERR_ARG, "two mocks share a key on the same configuration");
+  }
+
   if (graphs) {
     // one graph per plan, sized for the largest catalogue the plan runs
     std::vector<int64_t> cap(nplans, 0);
     std::vector<int> hw(nplans, 0);
     for (int m = 0; m < nmocks; ++m) {
+      if (rec[m]) continue;
       cap[mock_plan[m]] = std::max(cap[mock_plan[m]], np[m]);
       if (w && w[m]) hw[mock_plan[m]] = 1;
     }
@@ -2551,41 +2648,113 @@ bsp_status bsp_batch_run(const bsp_plan* plans, int32_t nplans, const int32_t* m
       }
     }
   }
+
+  JournalStage st;
+  if (journaled) {
+    bsp_plan p = p0;  // for HIPCHK
+    st.slot = nB + 2 * D + 1;
+    for (int i = 0; i < nplans; ++i) {
+      st.streams.push_back(plans[i]->stream);
+      if (graphs && plans[i]->bslot.stream) st.streams.push_back(plans[i]->bslot.stream);
+    }
+    HIPCHK(hipHostMalloc((void**)&st.h, (size_t)(2 + nres) * st.slot * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipEventCreateWithFlags(&st.ev[0], hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&st.ev[1], hipEventDisableTiming));
+    // recorded mocks: their outputs go back to the device from the journal
+    int64_t k = 0;
+    for (int m = 0; m < nmocks; ++m) {
+      if (!rec[m]) continue;
+      double* hb = st.h + (2 + k++) * st.slot;
+      std::string err;
+      if (!jn.read(*rec[m], hb, hb + nB, hb + nB + D, err)) return fail(p0, BSP_ERR_IO, err);
+      HIPCHK(hipMemcpyAsync(B_all + m * nB, hb, nB * sizeof(double), hipMemcpyHostToDevice, p0->stream));
+      HIPCHK(hipMemcpyAsync(alpha_all + m * D, hb + nB, D * sizeof(double), hipMemcpyHostToDevice, p0->stream));
+      if (beta_all)
+        HIPCHK(hipMemcpyAsync(beta_all + m * D, hb + nB + D, D * sizeof(double), hipMemcpyHostToDevice,
+                              p0->stream));
+    }
+  }
+
+  // record of the k-th mock run in this call, once its copies have landed;
+  // a kernel error latched on its plan stops the journal there
+  std::vector<int> run_mock;
+  auto flush = [&](int64_t k) -> bsp_status {
+    const int m = run_mock[k];
+    bsp_plan p = p0;  // for HIPCHK
+    HIPCHK(hipEventSynchronize(st.ev[k & 1]));
+    const double* hb = st.h + (k & 1) * st.slot;
+    int32_t e = 0;
+    std::memcpy(&e, hb + nB + 2 * D, sizeof e);
+    if (e) {
+      // drain every stream, then report (and clear) the latched error
+      for (hipStream_t s : st.streams) (void)hipStreamSynchronize(s);
+      bsp_plan q = plans[mock_plan[m]];
+      const bsp_status s = bsp_sync(q);
+      if (q != p0) p0->err = q->err;
+      return s != BSP_OK ? s : fail(p0, BSP_ERR_DEVICE, "device error");
+    }
+    std::string err;
+    if (!jn.append(mock_key[m], hashes[mock_plan[m]], np[m], (int)p0->nl, (int)ntri, (int)D, hb, hb + nB,
+                   beta_all ? hb + nB + D : nullptr, (flags & BSP_BATCH_FSYNC) != 0, err))
+      return fail(p0, BSP_ERR_IO, err);
+    return BSP_OK;
+  };
+
   for (int m = 0; m < nmocks; ++m) {
+    if (rec[m]) continue;
     bsp_plan q = plans[mock_plan[m]];
+    bsp_plan p = p0;  // for HIPCHK: errors are reported on the first plan
+    hipStream_t ms = q->stream;
     if (!graphs) {
       const bsp_status s = bsp_bispectrum_multipoles(q, ux[m], uy[m], uz[m], w ? w[m] : nullptr, np[m], prec,
-                                                     B_all + (int64_t)m * p0->nl * ntri, nullptr, nullptr, nullptr,
-                                                     alpha_all + (int64_t)m * D,
-                                                     beta_all ? beta_all + (int64_t)m * D : nullptr);
+                                                     B_all + m * nB, nullptr, nullptr, nullptr, alpha_all + m * D,
+                                                     beta_all ? beta_all + m * D : nullptr);
       if (s != BSP_OK) {
         if (q != p0) p0->err = q->err;
         return s;
       }
-      continue;
+    } else {
+      auto& b = q->bslot;
+      ms = b.stream;
+      const size_t nb = (size_t)np[m] * sizeof(float);
+      HIPCHK(hipMemcpyAsync(b.in, ux[m], nb, hipMemcpyDeviceToDevice, b.stream));
+      HIPCHK(hipMemcpyAsync(b.in + b.cap, uy[m], nb, hipMemcpyDeviceToDevice, b.stream));
+      HIPCHK(hipMemcpyAsync(b.in + 2 * b.cap, uz[m], nb, hipMemcpyDeviceToDevice, b.stream));
+      if (b.has_w) {
+        if (w && w[m]) HIPCHK(hipMemcpyAsync(b.in + 3 * b.cap, w[m], nb, hipMemcpyDeviceToDevice, b.stream));
+        else HIPCHK(launch_fill_u32(b.in + 3 * b.cap, 0x3f800000u, np[m], b.stream));
+      }
+      HIPCHK(launch_set_i64(b.npd, np[m], b.stream));
+      HIPCHK(hipGraphLaunch(b.exec, b.stream));
+      const double* oB = b.out;
+      const double* oA = oB + nB;
+      HIPCHK(hipMemcpyAsync(B_all + m * nB, oB, nB * sizeof(double), hipMemcpyDeviceToDevice, b.stream));
+      HIPCHK(hipMemcpyAsync(alpha_all + m * D, oA, D * sizeof(double), hipMemcpyDeviceToDevice, b.stream));
+      if (beta_all)
+        HIPCHK(hipMemcpyAsync(beta_all + m * D, oA + D, D * sizeof(double), hipMemcpyDeviceToDevice, b.stream));
     }
-    auto& b = q->bslot;
-    bsp_plan p = q;  // for HIPCHK
-    const size_t nb = (size_t)np[m] * sizeof(float);
-    HIPCHK(hipMemcpyAsync(b.in, ux[m], nb, hipMemcpyDeviceToDevice, b.stream));
-    HIPCHK(hipMemcpyAsync(b.in + b.cap, uy[m], nb, hipMemcpyDeviceToDevice, b.stream));
-    HIPCHK(hipMemcpyAsync(b.in + 2 * b.cap, uz[m], nb, hipMemcpyDeviceToDevice, b.stream));
-    if (b.has_w) {
-      if (w && w[m]) HIPCHK(hipMemcpyAsync(b.in + 3 * b.cap, w[m], nb, hipMemcpyDeviceToDevice, b.stream));
-      else HIPCHK(launch_fill_u32(b.in + 3 * b.cap, 0x3f800000u, np[m], b.stream));
+    if (!journaled) continue;
+    // stage this mock's outputs and its plan's error word for the journal
+    const int64_t k = (int64_t)run_mock.size();
+    run_mock.push_back(m);
+    double* hb = st.h + (k & 1) * st.slot;
+    hb[nB + 2 * D] = 0.0;
+    HIPCHK(hipMemcpyAsync(hb, B_all + m * nB, nB * sizeof(double), hipMemcpyDeviceToHost, ms));
+    HIPCHK(hipMemcpyAsync(hb + nB, alpha_all + m * D, D * sizeof(double), hipMemcpyDeviceToHost, ms));
+    if (beta_all) HIPCHK(hipMemcpyAsync(hb + nB + D, beta_all + m * D, D * sizeof(double), hipMemcpyDeviceToHost, ms));
+    HIPCHK(hipMemcpyAsync(hb + nB + 2 * D, q->d_err, sizeof(int32_t), hipMemcpyDeviceToHost, ms));
+    HIPCHK(hipEventRecord(st.ev[k & 1], ms));
+    if (k > 0) {
+      const bsp_status s = flush(k - 1);
+      if (s != BSP_OK) return s;
     }
-    HIPCHK(launch_set_i64(b.npd, np[m], b.stream));
-    HIPCHK(hipGraphLaunch(b.exec, b.stream));
-    const double* oB = b.out;
-    const double* oA = oB + (size_t)q->nl * ntri;
-    HIPCHK(hipMemcpyAsync(B_all + (int64_t)m * p0->nl * ntri, oB, (size_t)q->nl * ntri * sizeof(double),
-                          hipMemcpyDeviceToDevice, b.stream));
-    HIPCHK(hipMemcpyAsync(alpha_all + (int64_t)m * D, oA, (size_t)D * sizeof(double), hipMemcpyDeviceToDevice,
-                          b.stream));
-    if (beta_all)
-      HIPCHK(hipMemcpyAsync(beta_all + (int64_t)m * D, oA + D, (size_t)D * sizeof(double), hipMemcpyDeviceToDevice,
-                            b.stream));
   }
+  if (!run_mock.empty()) {
+    const bsp_status s = flush((int64_t)run_mock.size() - 1);
+    if (s != BSP_OK) return s;
+  }
+  if (nresumed) *nresumed = (int32_t)nres;
+
   // the covariance runs on the first plan's stream once every mock is done
   for (int i = 0; i < nplans; ++i) {
     bsp_plan p = plans[i];  // for HIPCHK
@@ -2596,8 +2765,78 @@ bsp_status bsp_batch_run(const bsp_plan* plans, int32_t nplans, const int32_t* m
       return s;
     }
   }
+  st.streams.clear();  // drained above
   bsp_plan p = p0;
   HIPCHK(launch_covariance(alpha_all, nmocks, (int)D, cov, p0->stream));
+  return BSP_OK;
+}
+
+}  // namespace
+}  // extern "C++"
+
+bsp_status bsp_batch_run(const bsp_plan* plans, int32_t nplans, const int32_t* mock_plan, int32_t nmocks,
+                         const float* const* ux, const float* const* uy, const float* const* uz,
+                         const float* const* w, const int64_t* np, bsp_precision prec, double* B_all,
+                         double* alpha_all, double* beta_all, double* cov, int32_t flags) {
+  return batch_impl(plans, nplans, mock_plan, nmocks, nullptr, ux, uy, uz, w, np, prec, B_all, alpha_all, beta_all,
+                    cov, flags, nullptr, nullptr);
+}
+
+bsp_status bsp_batch_run_journal(const bsp_plan* plans, int32_t nplans, const int32_t* mock_plan, int32_t nmocks,
+                                 const uint64_t* mock_key, const float* const* ux, const float* const* uy,
+                                 const float* const* uz, const float* const* w, const int64_t* np,
+                                 bsp_precision prec, double* B_all, double* alpha_all, double* beta_all,
+                                 double* cov, int32_t flags, const char* journal, int32_t* nresumed) {
+  if (!journal) return fail(plans ? plans[0] : nullptr, BSP_ERR_ARG, "null journal path");
+  return batch_impl(plans, nplans, mock_plan, nmocks, mock_key, ux, uy, uz, w, np, prec, B_all, alpha_all, beta_all,
+                    cov, flags, journal, nresumed);
+}
+
+bsp_status bsp_config_hash(bsp_plan p, bsp_precision prec, uint64_t* hash) {
+  if (!p || !hash) return fail(p, BSP_ERR_ARG, "null argument");
+  if (!p->pre_done) return fail(p, BSP_ERR_STATE, "bsp_precompute has not run");
+  if (prec < BSP_FP32 || prec > BSP_BF16X1) return fail(p, BSP_ERR_ARG, "bad precision");
+  *hash = config_hash(p, prec);
+  return BSP_OK;
+}
+
+bsp_status bsp_journal_scan(const char* journal, int64_t* nrecords, int64_t* valid_bytes, int64_t* file_bytes) {
+  if (!journal || !nrecords) return fail(nullptr, BSP_ERR_ARG, "null argument");
+  Journal jn;
+  std::string err;
+  if (!jn.open(journal, false, err)) return fail(nullptr, BSP_ERR_IO, err);
+  *nrecords = jn.records();
+  if (valid_bytes) *valid_bytes = jn.valid_bytes();
+  if (file_bytes) *file_bytes = jn.file_bytes();
+  return BSP_OK;
+}
+
+bsp_status bsp_journal_append(const char* journal, uint64_t key, uint64_t config_hash, int64_t np, int32_t nl,
+                              int32_t ntri, int32_t d, const double* B, const double* alpha, const double* beta) {
+  if (!journal || !B || !alpha || np < 1 || nl < 1 || nl > 3 || ntri < 0 || d < 0 || d > 3 * 128)
+    return fail(nullptr, BSP_ERR_ARG, "bad argument");
+  Journal jn;
+  std::string err;
+  if (!jn.open(journal, true, err)) return fail(nullptr, BSP_ERR_IO, err);
+  if (jn.find(key, config_hash)) return fail(nullptr, BSP_ERR_ARG, "key already recorded for this configuration");
+  if (!jn.append(key, config_hash, np, nl, ntri, d, B, alpha, beta, false, err)) return fail(nullptr, BSP_ERR_IO, err);
+  return BSP_OK;
+}
+
+bsp_status bsp_journal_lookup(const char* journal, uint64_t key, uint64_t config_hash, int64_t np, int32_t nl,
+                              int32_t ntri, int32_t d, double* B, double* alpha, double* beta, int32_t* found) {
+  if (!journal || !B || !alpha || !found) return fail(nullptr, BSP_ERR_ARG, "null argument");
+  *found = 0;
+  Journal jn;
+  std::string err;
+  if (!jn.open(journal, false, err)) return fail(nullptr, BSP_ERR_IO, err);
+  const JournalRecord* r = jn.find(key, config_hash);
+  if (!r) return BSP_OK;
+  if (r->np != np || r->nl != nl || r->ntri != ntri || r->d != d)
+    return fail(nullptr, BSP_ERR_ARG, "record has another particle count or output shape");
+  if (beta && !r->has_beta) return BSP_OK;
+  if (!jn.read(*r, B, alpha, beta, err)) return fail(nullptr, BSP_ERR_IO, err);
+  *found = 1;
   return BSP_OK;
 }
 

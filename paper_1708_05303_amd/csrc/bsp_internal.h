@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 #include <cstddef>
+#include <string>
+#include <vector>
 
 namespace bsp {
 
@@ -254,5 +256,39 @@ hipError_t launch_modal_solve(const double* Linv, const int32_t* piv, int n, int
                               double* alpha, double* beta, hipStream_t s);
 hipError_t launch_covariance(const double* x, int m, int d, double* cov, hipStream_t s);
 hipError_t launch_scale_scalar(const double* x, double scale, double* y, hipStream_t s);
+
+// Batch journal (journal.hip): checksummed per-mock records, resumable.
+uint64_t fnv1a64(const void* data, size_t n, uint64_t h = 0xcbf29ce484222325ull);
+int64_t journal_payload_doubles(int nl, int ntri, int d, int has_beta);
+
+struct JournalRecord {
+  uint64_t key, hash;
+  int64_t np;
+  int nl, ntri, d, has_beta;
+  int64_t offset;
+};
+
+class Journal {
+ public:
+  ~Journal();
+  // Opens the file (create: read-write, created if absent, exclusive lock;
+  // else read-only, shared lock) and indexes its valid records; with create a
+  // torn or corrupt tail is truncated away.
+  bool open(const std::string& path, bool create, std::string& err);
+  void close();
+  const JournalRecord* find(uint64_t key, uint64_t hash) const;
+  bool read(const JournalRecord& r, double* B, double* alpha, double* beta, std::string& err) const;
+  bool append(uint64_t key, uint64_t hash, int64_t np, int nl, int ntri, int d, const double* B,
+              const double* alpha, const double* beta, bool sync, std::string& err);
+  int64_t records() const { return (int64_t)recs_.size(); }
+  int64_t valid_bytes() const { return valid_bytes_; }
+  int64_t file_bytes() const { return file_bytes_; }
+
+ private:
+  int fd_ = -1;
+  std::string path_;
+  std::vector<JournalRecord> recs_;
+  int64_t valid_bytes_ = 0, file_bytes_ = 0;
+};
 
 }  // namespace bsp

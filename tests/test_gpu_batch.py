@@ -52,7 +52,7 @@ def test_batch_covariance_rejects_single_mock():
 
 
 @pytest.fixture(scope="module")
-def uneven_batch():
+def uneven_batch(tmp_path_factory):
     sizes = [128, 192, 256, 384]
     mocks = [(0, 128), (1, 192), (2, 256), (3, 384), (4, 128)]  # (seed offset, grid)
     ref_wl = C.batch_workload(0, 256)
@@ -90,6 +90,44 @@ def uneven_batch():
                         [u[0].size for u in cats], B.BSP_BF16X3, B_all, alpha_all, beta_all, cov, flags)
         plans[128].sync()
         outs[mode] = (B_all.cpu().numpy(), alpha_all.cpu().numpy(), beta_all.cpu().numpy(), cov.cpu().numpy())
+    # checkpoint / resume: the first three mocks are journaled, a torn record
+    # (what a writer killed mid-append leaves) is added by hand, and the whole
+    # batch is run again on the same journal, then once more without graphs
+    jdir = tmp_path_factory.mktemp("journal")
+    keys = [1000 + m for m, _ in mocks]
+    hpl = [plans[n].handle for n in sizes]
+    npart = [u[0].size for u in cats]
+
+    def jrun(path, idx, flags):
+        sub = [[dv[a][i] for i in idx] for a in range(3)]
+        B_all = torch.zeros((len(idx), nl, info.ntri), dtype=torch.float64, device=DEV)
+        alpha_all = torch.zeros((len(idx), nl * nm), dtype=torch.float64, device=DEV)
+        beta_all = torch.zeros((len(idx), nl * nm), dtype=torch.float64, device=DEV)
+        cov = torch.zeros((nl * nm, nl * nm), dtype=torch.float64, device=DEV)
+        nres = B.bsp_batch_run_journal(hpl, [order[i] for i in idx], [keys[i] for i in idx], sub[0], sub[1], sub[2],
+                                       None, [npart[i] for i in idx], B.BSP_BF16X3, B_all, alpha_all, beta_all, cov,
+                                       str(path), flags)
+        plans[128].sync()
+        return nres, (B_all.cpu().numpy(), alpha_all.cpu().numpy(), beta_all.cpu().numpy(), cov.cpu().numpy())
+
+    say("journal: fresh run of all mocks")
+    full = jdir / "full.bspj"
+    outs["journal_fresh"] = jrun(full, range(len(mocks)), B.BSP_BATCH_GRAPH)
+    outs["journal_fresh_scan"] = B.bsp_journal_scan(str(full))
+    say("journal: first three mocks, then a torn record, then the whole batch")
+    part = jdir / "part.bspj"
+    outs["journal_part"] = jrun(part, [0, 1, 2], B.BSP_BATCH_GRAPH)
+    n3, v3, f3 = B.bsp_journal_scan(str(part))
+    raw = part.read_bytes()
+    with open(part, "ab") as fh:
+        fh.write(raw[v3 - (v3 - 16) // 3: v3 - (v3 - 16) // 3 + 200])  # head of the last record, cut short
+    outs["journal_torn_scan"] = (n3, v3, f3, B.bsp_journal_scan(str(part)))
+    outs["journal_resume"] = jrun(part, range(len(mocks)), B.BSP_BATCH_GRAPH)
+    outs["journal_resume_scan"] = B.bsp_journal_scan(str(part))
+    say("journal: every mock recorded, plain calls")
+    outs["journal_all_recorded"] = jrun(part, range(len(mocks)), 0)
+    outs["config_hash"] = {n: B.bsp_config_hash(plans[n].handle, B.BSP_BF16X3) for n in sizes}
+    outs["config_hash_fp32"] = B.bsp_config_hash(plans[128].handle, B.BSP_FP32)
     counts = {n: plans[n].counts.copy() for n in sizes}
     kept = {n: plans[n].kept.copy() for n in sizes}
     for p in plans.values():
@@ -105,6 +143,42 @@ def test_uneven_batch_graph_replay_is_bit_identical(uneven_batch):
         assert np.array_equal(a, b)
     for a, b in zip(outs["graph"], outs["graph2"]):
         assert np.array_equal(a, b)
+
+
+def test_batch_journal_resume_is_bit_identical(uneven_batch):
+    """Checkpoint / resume: a journaled batch gives the bits of the plain
+    batch; after three mocks and a torn fourth record, the resumed batch takes
+    the three from the journal, cuts the torn tail off, runs the other two and
+    again gives the same bits (B, alpha, beta and the covariance over all
+    mocks); a batch whose mocks are all recorded runs none."""
+    mocks, refs, counts, kept, outs, nl, nm = uneven_batch
+    ref = outs["graph"]
+    nres, got = outs["journal_fresh"]
+    assert nres == 0
+    for a, b in zip(got, ref):
+        assert np.array_equal(a, b)
+    nrec, valid, size = outs["journal_fresh_scan"]
+    assert nrec == len(mocks) and valid == size
+    nres, got = outs["journal_part"]
+    assert nres == 0
+    for a, b in zip(got[:3], ref[:3]):
+        assert np.array_equal(a, b[:3])
+    n3, v3, f3, torn = outs["journal_torn_scan"]
+    assert n3 == 3 and v3 == f3
+    assert torn == (3, v3, v3 + 200)
+    nres, got = outs["journal_resume"]
+    assert nres == 3
+    for a, b in zip(got, ref):
+        assert np.array_equal(a, b)
+    nrec, valid, size = outs["journal_resume_scan"]
+    assert nrec == len(mocks) and valid == size
+    nres, got = outs["journal_all_recorded"]
+    assert nres == len(mocks)
+    for a, b in zip(got, ref):
+        assert np.array_equal(a, b)
+    hashes = outs["config_hash"]
+    assert len(set(hashes.values())) == len(hashes)  # plans of different N hash differently
+    assert outs["config_hash_fp32"] != hashes[128]
 
 
 def test_uneven_batch_against_oracle(uneven_batch):
