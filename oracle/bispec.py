@@ -44,6 +44,7 @@ __all__ = [
     "triangle_counts_brute", "closed_triangle_sum_brute", "binned_triple_sums", "binned_triple_sums_full",
     "binned_triple_sums_gemm", "triangle_counts_gemm",
     "binned_bispectrum", "shell_power", "power_multipoles", "skew_spectra", "integrated_bispectrum",
+    "subvolume_unit_vectors", "integrated_bispectrum_local_los",
     "shot_noise_binned", "legendre_integral", "ring_factor", "shot_noise_multipoles",
     "shot_noise_coincidence", "modal_modes",
     "modal_q", "modal_filter", "modal_fields", "modal_numerators", "gram_matrix",
@@ -673,6 +674,76 @@ def integrated_bispectrum(delta: np.ndarray, s: int, lmax: int, observer, window
             for b in range(nb):
                 sel = bins == b
                 P[i, li, b] = Vs * float(wl[sel].sum()) / (float(m) ** 6 * Nb[b]) if Nb[b] else 0.0
+    iB = np.einsum("ilb,i->lb", P, dbar) / s ** 3
+    return iB, P, dbar, Nb
+
+
+def subvolume_unit_vectors(m: int, origin, observer):
+    """x_hat at the nodes of the sub-volume whose node (0, 0, 0) is grid node
+    origin: node origin + j represents the point r = origin + j (grid units),
+    x_hat = (r - o) / |r - o|."""
+    j = np.arange(m, dtype=np.float64)
+    o = np.asarray(observer, dtype=np.float64)
+    rx = (origin[0] + j - o[0])[:, None, None]
+    ry = (origin[1] + j - o[1])[None, :, None]
+    rz = (origin[2] + j - o[2])[None, None, :]
+    norm = np.sqrt(rx ** 2 + ry ** 2 + rz ** 2)
+    return rx / norm, ry / norm, rz / norm
+
+
+def integrated_bispectrum_local_los(delta: np.ndarray, s: int, lmax: int, observer, window, box: float,
+                                    k0: float, dk: float, nb: int):
+    """Integrated bispectrum multipoles of Sec. 3.4 with the power-spectrum
+    multipoles of each sub-volume taken as in Sec. 2 (eq. PowSpecMultipole):
+    the line of sight x_hat varies over the nodes of the sub-volume.
+
+    For sub-volume i (nodes origin_i + [0, M)^3, M = N / s):
+      delta^(l)_i(n) = (2l+1) sum_x e^{-2 pi i n.x / M} delta(origin_i + x) L_l(n_hat . x_hat),
+            x_hat from the observer to the node, formed from the transforms of
+            the x_hat-product fields (legendre_moments), each divided by the
+            assignment window at the sub-volume frequencies (window None: none);
+      dbar_i = (DFT_M of delta)(0) / M^3;
+      P^(l)_i(k_b) = V_s sum_{n in b} Re[delta^(l)_i(n) conj delta^(0)_i(n)] / (M^6 N_b)
+            over the full lattice (Hermitian halves counted twice).
+    iB^(l) = (1/N_s) sum_i P^(l)_i dbar_i. Bins as integrated_bispectrum.
+    Returns (iB [nl][nb], P [N_s][nl][nb], dbar [N_s], N_b)."""
+    n = delta.shape[0]
+    assert n % s == 0 and observer is not None
+    m = n // s
+    nl = lmax // 2 + 1
+    n2 = n2_grid_half(m)
+    bins = bin_of_n2(n2, k0, dk, nb)
+    mult = np.full(m // 2 + 1, 2.0)
+    mult[0] = 1.0
+    if m % 2 == 0:
+        mult[-1] = 1.0
+    mm = np.broadcast_to(mult[None, None, :], n2.shape)
+    Nb = np.array([int(round(mm[bins == b].sum())) for b in range(nb)], np.int64)
+    Vs = (box / s) ** 3
+    W = window_half(m, window) if window is not None else None
+    tensors = [()]
+    if lmax >= 2:
+        tensors += los_tensor_indices(2)
+    if lmax >= 4:
+        tensors += los_tensor_indices(4)
+    P = np.zeros((s ** 3, nl, nb))
+    dbar = np.zeros(s ** 3)
+    for i in range(s ** 3):
+        org = ((i // (s * s)) * m, ((i // s) % s) * m, (i % s) * m)
+        sub = delta[org[0]:org[0] + m, org[1]:org[1] + m, org[2]:org[2] + m]
+        xh = subvolume_unit_vectors(m, org, observer)
+        T = {}
+        for t in tensors:
+            F = forward(los_weighted_field(sub, t, xh))
+            if t == ():
+                dbar[i] = float(np.real(F[0, 0, 0])) / float(m) ** 3
+            T[t] = F / W if W is not None else F
+        dl = legendre_moments(T, m, lmax, False)
+        for li in range(nl):
+            cr = np.real(dl[li] * np.conj(dl[0])) * mm
+            for b in range(nb):
+                sel = bins == b
+                P[i, li, b] = Vs * float(cr[sel].sum()) / (float(m) ** 6 * Nb[b]) if Nb[b] else 0.0
     iB = np.einsum("ilb,i->lb", P, dbar) / s ** 3
     return iB, P, dbar, Nb
 

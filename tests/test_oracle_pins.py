@@ -353,6 +353,67 @@ def test_integrated_bispectrum_brute_subvolume():
     assert abs(dbar[i] - blk.mean()) < 1e-14
 
 
+def test_integrated_bispectrum_local_los_brute_subvolume():
+    """Line of sight varying inside the sub-volumes: one sub-volume against a
+    direct sum of the LOS moment definition over its nodes, with x_hat written
+    out here from the nodes' grid coordinates and the observer, and P^(l) from
+    Re[delta^(l) conj delta^(0)] summed over the full lattice of each shell."""
+    n, s, box, k0, dk, nb = 16, 2, 100.0, 1.0, 1.0, 3
+    m = n // s
+    d = rng(45).standard_normal((n, n, n))
+    obs = np.array([-20.0, -35.0, -10.0])
+    iB, P, dbar, Nb = O.integrated_bispectrum_local_los(d, s, 4, obs, 1, box, k0, dk, nb)
+    Vs = (box / s) ** 3
+    for i in (0, 6):
+        org = np.array([(i // 4) * m, ((i // 2) % 2) * m, (i % 2) * m], np.float64)
+        blk = d[int(org[0]):int(org[0]) + m, int(org[1]):int(org[1]) + m, int(org[2]):int(org[2]) + m]
+        j = np.arange(m)
+        gx, gy, gz = np.meshgrid(j, j, j, indexing="ij")
+        r = np.stack([gx + org[0] - obs[0], gy + org[1] - obs[1], gz + org[2] - obs[2]])
+        xh = r / np.sqrt((r ** 2).sum(axis=0))
+        fr = np.fft.fftfreq(m, 1.0 / m)
+        acc = np.zeros((3, nb))
+        cnt = np.zeros(nb)
+        for a in fr:
+            for b in fr:
+                for c in fr:
+                    q2 = int(a * a + b * b + c * c)
+                    bb = O.bin_of_n2(np.array([q2]), k0, dk, nb)[0]
+                    if bb < 0:
+                        continue
+                    ph = np.exp(-2j * np.pi * (a * gx + b * gy + c * gz) / m)
+                    win = (np.sinc(a / m) * np.sinc(b / m) * np.sinc(c / m)) ** 2
+                    mu = (a * xh[0] + b * xh[1] + c * xh[2]) / math.sqrt(q2)
+                    leg = [np.ones_like(mu), 0.5 * (3 * mu * mu - 1), (35 * mu ** 4 - 30 * mu * mu + 3) / 8]
+                    dl = [(4 * li + 1) * np.sum(blk * leg[li] * ph) / win for li in range(3)]
+                    for li in range(3):
+                        acc[li, bb] += (dl[li] * np.conj(dl[0])).real
+                    cnt[bb] += 1
+        assert np.array_equal(cnt.astype(np.int64), Nb)
+        ref = Vs * acc / (float(m) ** 6 * cnt[None, :])
+        assert np.allclose(P[i], ref, rtol=1e-10, atol=1e-10 * np.abs(ref).max()), i
+        assert abs(dbar[i] - blk.mean()) < 1e-14
+    assert np.allclose(iB, np.einsum("ilb,i->lb", P, dbar) / s ** 3, rtol=1e-13)
+
+
+def test_integrated_bispectrum_local_los_far_observer_limit():
+    """An observer far away makes x_hat the same over a sub-volume, and the
+    local line of sight reduces to the one line of sight per sub-volume."""
+    n, s, box, k0, dk, nb = 16, 2, 100.0, 1.0, 1.0, 3
+    d = rng(46).standard_normal((n, n, n))
+    obs = np.array([-3.0e6, 1.0e6, -2.0e6])
+    iB, P, dbar, _ = O.integrated_bispectrum_local_los(d, s, 4, obs, 1, box, k0, dk, nb)
+    iB1, P1, dbar1, _ = O.integrated_bispectrum(d, s, 4, obs, 1, box, k0, dk, nb)
+    assert np.array_equal(dbar, dbar1)
+    for li in range(3):
+        assert np.linalg.norm(P[:, li] - P1[:, li]) < 1e-4 * np.linalg.norm(P1[:, 0]), li
+    # a near observer makes the two readings differ at l > 0 only
+    iB2, P2, _, _ = O.integrated_bispectrum_local_los(d, s, 4, np.array([-4.0, 3.0, -5.0]), 1, box, k0, dk, nb)
+    iB3, P3, _, _ = O.integrated_bispectrum(d, s, 4, np.array([-4.0, 3.0, -5.0]), 1, box, k0, dk, nb)
+    assert np.allclose(P2[:, 0], P3[:, 0], rtol=1e-12)
+    assert np.linalg.norm(P2[:, 1] - P3[:, 1]) > 1e-2 * np.linalg.norm(P3[:, 1])
+
+
 # ---------------------------------------------------------------- shells
 
 def test_bins_integer_edges_and_isotropy():
