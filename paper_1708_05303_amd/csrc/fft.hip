@@ -136,9 +136,9 @@ template <int R, int SIGN, typename V> __device__ __forceinline__ void butterfly
 // thread index t. All threads of the block must call this (it synchronises).
 // Stage s with sub-length NS: butterfly b reads b + r N/R, twiddles by
 // W_{NS R}^{r (b mod NS)}, and writes (b/NS) NS R + (b mod NS) + r NS.
-template <typename V, int N, int SIGN, int NT, int S, int NS, int SWZ, int WAVE>
+template <typename V, int N, int SIGN, int NT, int S, int NS, int SWZ, int WAVE, int SEND = nstages(N)>
 __device__ __forceinline__ void fft_stages(V* __restrict__ buf, const V* __restrict__ tw, int t) {
-  if constexpr (S < nstages(N)) {
+  if constexpr (S < SEND) {
     constexpr int R = radix_at(N, S);
     constexpr int NB = N / R;
     constexpr int PER = (NB + NT - 1) / NT;
@@ -173,7 +173,65 @@ __device__ __forceinline__ void fft_stages(V* __restrict__ buf, const V* __restr
       }
     }
     lds_sync<WAVE>();
-    fft_stages<V, N, SIGN, NT, S + 1, NS * R, SWZ, WAVE>(buf, tw, t);
+    fft_stages<V, N, SIGN, NT, S + 1, NS * R, SWZ, WAVE, SEND>(buf, tw, t);
+  }
+}
+
+// Register-held ends of a transform. Thread t holds elements t + NT e
+// (e < N / NT). When N / R0 (R0 the first radix) is a multiple of NT, the
+// first pass's butterflies read exactly those elements, so the pass takes its
+// input from registers instead of an LDS round trip; when N / RL (RL the last
+// radix) is a multiple of NT, the last pass's butterflies write exactly those
+// elements, so its output stays in registers.
+constexpr bool reg_in(int n, int nt) { return n % nt == 0 && nstages(n) >= 2 && (n / radix_at(n, 0)) % nt == 0; }
+constexpr bool reg_out(int n, int nt) {
+  return reg_in(n, nt) && (n / radix_at(n, nstages(n) - 1)) % nt == 0;
+}
+
+// Length-N transform of x (layout above) with buf as the exchange buffer
+// between passes. OUT_REG: the result is left in x; otherwise in buf (natural
+// order), as fft_stages leaves it. The caller synchronises before buf is
+// written again.
+template <typename V, int N, int SIGN, int NT, int SWZ, int WAVE, bool OUT_REG>
+__device__ __forceinline__ void fft_reg(V* __restrict__ buf, const V* __restrict__ tw, int t, V* x) {
+  static_assert(reg_in(N, NT) && (!OUT_REG || reg_out(N, NT)), "pass layout does not match the thread layout");
+  constexpr int NSTG = nstages(N);
+  constexpr int R0 = radix_at(N, 0);
+  {
+    constexpr int PER = N / R0 / NT;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      V v[R0];
+#pragma unroll
+      for (int r = 0; r < R0; ++r) v[r] = x[i + r * PER];
+      butterfly<R0, SIGN>(v);
+      const int b = t + i * NT;
+#pragma unroll
+      for (int r = 0; r < R0; ++r) buf[swz<SWZ>(b * R0 + r)] = v[r];
+    }
+  }
+  lds_sync<WAVE>();
+  if constexpr (!OUT_REG) {
+    fft_stages<V, N, SIGN, NT, 1, R0, SWZ, WAVE>(buf, tw, t);
+  } else {
+    fft_stages<V, N, SIGN, NT, 1, R0, SWZ, WAVE, NSTG - 1>(buf, tw, t);
+    constexpr int R = radix_at(N, NSTG - 1), NS = N / R, PER = NS / NT;
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int b = t + i * NT;  // b < NS: the butterfly's twiddle index and output base
+      V v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = buf[swz<SWZ>(b + r * NS)];
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        V w = tw[(NS - 1) + (r - 1) * NS + b];
+        if constexpr (SIGN > 0) w.y = -w.y;
+        v[r] = cmul(v[r], w);
+      }
+      butterfly<R, SIGN>(v);
+#pragma unroll
+      for (int r = 0; r < R; ++r) x[i + r * PER] = v[r];
+    }
   }
 }
 
@@ -191,6 +249,19 @@ template <typename V> __device__ __forceinline__ V nt_load(const V* p) {
   return V{v.x, v.y};
 }
 
+// Value of v in the lane whose byte address (4 x lane) is addr, within the
+// wave (ds_bpermute per 32-bit word; every lane of the wave must execute it).
+template <typename T> __device__ __forceinline__ T lane_read(int addr, T v) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_ds_bpermute(addr, __builtin_bit_cast(int, v)));
+  } else {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_ds_bpermute(addr, (int)(unsigned)u);
+    const unsigned hi = (unsigned)__builtin_amdgcn_ds_bpermute(addr, (int)(unsigned)(u >> 32));
+    return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
+  }
+}
+
 // Weight of LOS field F at a node: the real solid harmonic h_F(x_hat) (see
 // kLosPoly), evaluated in the transform's precision.
 template <int F, typename T> __device__ __forceinline__ T los_weight(T hx, T hy, T hz) {
@@ -205,6 +276,8 @@ __device__ __forceinline__ void fwd_z_pairs(V* b, const V* tw, int t, const T* r
                                             int64_t line, int cout, int zs) {
   if constexpr (F0 < NLOS) {
     constexpr bool HAS1 = F0 + 1 < NLOS;
+    constexpr int WS = FZ_WAVE_SYNC && line_in_wave(N);
+    V x[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       T w0 = (T)1, w1 = (T)0;
@@ -214,31 +287,59 @@ __device__ __forceinline__ void fwd_z_pairs(V* b, const V* tw, int t, const T* r
         w0 = los_weight<F0>(hx, hy, hz);
         if constexpr (HAS1) w1 = los_weight<(HAS1 ? F0 + 1 : 0)>(hx, hy, hz);
       }
-      b[swz<1>(t + e * NT)] = V{w0 * rv[e], w1 * rv[e]};
+      x[e] = V{w0 * rv[e], w1 * rv[e]};
     }
-    lds_sync<FZ_WAVE_SYNC && line_in_wave(N)>();
-    fft_stages<V, N, -1, NT, 0, 1, 1, FZ_WAVE_SYNC && line_in_wave(N)>(b, tw, t);
-    if (valid) {
-      V* o0 = out_g + ((int64_t)F0 * nlines + line) * zs;
-      V* o1 = out_g + ((int64_t)(F0 + 1) * nlines + line) * zs;
-      for (int k = t; k < cout; k += NT) {
-        const V zk = b[swz<1>(k)], zm = b[swz<1>((N - k) % N)];
-        nt_store(o0 + k, V{(zk.x + zm.x) * (T)0.5, (zk.y - zm.y) * (T)0.5});
-        if constexpr (HAS1) nt_store(o1 + k, V{(zk.y + zm.y) * (T)0.5, (zm.x - zk.x) * (T)0.5});
+    V* o0 = out_g + ((int64_t)F0 * nlines + line) * zs;
+    V* o1 = out_g + ((int64_t)(F0 + 1) * nlines + line) * zs;
+    // the two real fields packed as z = a + i b separate as
+    // a_k = (z_k + conj z_{N-k}) / 2, b_k = (z_k - conj z_{N-k}) / (2i)
+    auto split = [&](int k, const V& zk, const V& zm) {
+      nt_store(o0 + k, V{(zk.x + zm.x) * (T)0.5, (zk.y - zm.y) * (T)0.5});
+      if constexpr (HAS1) nt_store(o1 + k, V{(zk.y + zm.y) * (T)0.5, (zm.x - zk.x) * (T)0.5});
+    };
+    if constexpr (reg_out(N, NT) && line_in_wave(N) && E == 8) {
+      // both ends in registers. Lane t holds z at t + NT e; the partner of
+      // k = t + NT j is N - k = (NT - t) + NT (7 - j) for t > 0 (lane NT - t of
+      // the same line, same wave) and NT (8 - j) mod N for t = 0 (own lane)
+      fft_reg<V, N, -1, NT, 1, WS, true>(b, tw, t, x);
+      const int lane = (int)(threadIdx.x & 63);
+      const int src = (lane - t + ((NT - t) & (NT - 1))) * 4;
+#pragma unroll
+      for (int j = 0; j < 5; ++j) {
+        if (NT * j >= cout) break;  // uniform: cout <= N/2 + 1
+        const V zr = V{lane_read(src, x[7 - j].x), lane_read(src, x[7 - j].y)};
+        const V zm = t == 0 ? x[(8 - j) & 7] : zr;
+        if (valid && t + NT * j < cout) split(t + NT * j, x[j], zm);
       }
+    } else {
+      if constexpr (reg_in(N, NT)) {
+        // the first pass takes the weighted line from registers
+        fft_reg<V, N, -1, NT, 1, WS, false>(b, tw, t, x);
+      } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) b[swz<1>(t + e * NT)] = x[e];
+        lds_sync<WS>();
+        fft_stages<V, N, -1, NT, 0, 1, 1, WS>(b, tw, t);
+      }
+      if (valid)
+        for (int k = t; k < cout; k += NT) split(k, b[swz<1>(k)], b[swz<1>((N - k) % N)]);
     }
-    lds_sync<FZ_WAVE_SYNC && line_in_wave(N)>();
+    lds_sync<WS>();
     fwd_z_pairs<F0 + 2, NLOS, T, V, N, NT, E, PAD>(b, tw, t, rv, rx, ry, sh, oz, inv, plane, valid, out_g, nlines,
                                                    line, cout, zs);
   }
 }
 
+// Waves per SIMD the forward z pass is compiled for: FP32 power-of-two sizes
+// keep both transform ends in registers and fit 128 registers (four waves);
+// the others keep the compiler's choice.
+constexpr int fz_waves(size_t tsize, int n) { return tsize == 4 && (n & (n - 1)) == 0 ? 4 : 1; }
+
 // ---------------------------------------------------------------- fwd_z
 // grid: blockIdx.x -> LZ_GROUPS consecutive groups of L lines (line = x*N + y), blockIdx.y -> input grid.
-// FP32 power-of-two sizes are held to 96 registers (five waves per SIMD); the
-// radix-3 sizes and FP64 would spill there.
+// FP32 power-of-two sizes are held to 128 registers (fz_waves).
 template <typename T, int N, int NLOS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 && (N & (N - 1)) == 0 ? 5 : 1)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(fz_waves(sizeof(T), N))))
 void k_fwd_z(const T* __restrict__ in, cplx_t<T>* __restrict__ out, FwdZDesc d, const cplx_t<T>* __restrict__ twg) {
   using V = cplx_t<T>;
   constexpr int NT = (N >= 8) ? N / 8 : 1;
@@ -361,18 +462,32 @@ __global__ __launch_bounds__(BT) void k_c2c(const cplx_t<T>* __restrict__ in, cp
       }
     }
   }
+  if constexpr (reg_out(N, NT)) {
+    // both ends of the transform in registers; element pos of the output
+    // goes to row (pos + out_off) mod N when that row is kept (the first
+    // barrier inside covers the twiddle staging)
+    fft_reg<V, N, SIGN, NT, 0, 0, true>(buf + c * PAD, tw, j0, v);
+    if (cv) {
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int pos = j0 + e * NT;
-    if (N % NT == 0 || pos < N) buf[c * PAD + pos] = v[e];
-  }
-  __syncthreads();
-  fft_stages<V, N, SIGN, NT, 0, 1, 0, 0>(buf + c * PAD, tw, j0);
-  if (cv) {
+      for (int e = 0; e < E; ++e) {
+        const int r = (j0 + e * NT + p.out_off) % N;
+        if (r < p.out_rows) nt_store(dst + (int64_t)r * p.out_row + ocol, v[e]);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int pos = j0 + e * NT;
+      if (N % NT == 0 || pos < N) buf[c * PAD + pos] = v[e];
+    }
+    __syncthreads();
+    fft_stages<V, N, SIGN, NT, 0, 1, 0, 0>(buf + c * PAD, tw, j0);
+    if (cv) {
 #pragma unroll 4
-    for (int r = j0; r < p.out_rows; r += NT) {
-      const int pos = (r - p.out_off + N) % N;
-      nt_store(dst + (int64_t)r * p.out_row + ocol, buf[c * PAD + pos]);
+      for (int r = j0; r < p.out_rows; r += NT) {
+        const int pos = (r - p.out_off + N) % N;
+        nt_store(dst + (int64_t)r * p.out_row + ocol, buf[c * PAD + pos]);
+      }
     }
   }
 }
@@ -402,7 +517,8 @@ __global__ __launch_bounds__(256) void k_inv_z(const cplx_t<T>* __restrict__ in,
     const bool valid = line < nlines;
     const V* a = in + (int64_t)f0 * in_field + (valid ? line : 0) * zs;
     const V* bb = in + (int64_t)f1 * in_field + (valid ? line : 0) * zs;
-    for (int pos = t; pos < N; pos += NT) {
+    // two fields packed as A + iB, each completed from its half spectrum
+    auto packed = [&](int pos) {
       V z = V{(T)0, (T)0};
       if (valid) {
         if (pos < cin) {
@@ -417,17 +533,34 @@ __global__ __launch_bounds__(256) void k_inv_z(const cplx_t<T>* __restrict__ in,
           z = V{A.x + B.y, B.x - A.y};
         }
       }
-      b[swz<SW>(pos)] = z;
-    }
-    lds_sync<line_in_wave(N)>();
-    fft_stages<V, N, +1, NT, 0, 1, SW, line_in_wave(N)>(b, tw, t);
-    if (valid) {
-      T* o0 = out + (int64_t)f0 * out_field + line * N;
-      T* o1 = out + (int64_t)f1 * out_field + line * N;
-      for (int pos = t; pos < N; pos += NT) {
-        const V v = b[swz<SW>(pos)];
-        __builtin_nontemporal_store(v.x, o0 + pos);
-        if (has1) __builtin_nontemporal_store(v.y, o1 + pos);
+      return z;
+    };
+    T* o0 = out + (int64_t)f0 * out_field + line * N;
+    T* o1 = out + (int64_t)f1 * out_field + line * N;
+    if constexpr (reg_out(N, NT)) {
+      // both ends of the transform in registers: the line passes through LDS
+      // only between passes
+      V x[N / NT];
+#pragma unroll
+      for (int e = 0; e < N / NT; ++e) x[e] = packed(t + e * NT);
+      fft_reg<V, N, +1, NT, SW, line_in_wave(N), true>(b, tw, t, x);
+      if (valid) {
+#pragma unroll
+        for (int e = 0; e < N / NT; ++e) {
+          __builtin_nontemporal_store(x[e].x, o0 + t + e * NT);
+          if (has1) __builtin_nontemporal_store(x[e].y, o1 + t + e * NT);
+        }
+      }
+    } else {
+      for (int pos = t; pos < N; pos += NT) b[swz<SW>(pos)] = packed(pos);
+      lds_sync<line_in_wave(N)>();
+      fft_stages<V, N, +1, NT, 0, 1, SW, line_in_wave(N)>(b, tw, t);
+      if (valid) {
+        for (int pos = t; pos < N; pos += NT) {
+          const V v = b[swz<SW>(pos)];
+          __builtin_nontemporal_store(v.x, o0 + pos);
+          if (has1) __builtin_nontemporal_store(v.y, o1 + pos);
+        }
       }
     }
     lds_sync<line_in_wave(N)>();  // the next line reuses the buffer
