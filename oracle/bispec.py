@@ -584,7 +584,8 @@ def power_multipoles(spec_l: Sequence[np.ndarray], n: int, k0: float, dk: float,
     return P, Nb
 
 
-def skew_spectra(spec_l: Sequence[np.ndarray], n: int, nr: int, k0: float, dk: float, nb: int, box: float):
+def skew_spectra(spec_l: Sequence[np.ndarray], n: int, nr: int, k0: float, dk: float, nb: int, box: float,
+                 square_range: str = "shells"):
     """Skew-spectrum multipoles S_{*,l} of Sec. 3.2 (the estimator after
     eq. skewspecQ, with Q the convolution delta^(0) * delta^(0)): the shell
     average over directions of [delta^(0) * delta^(0)](-k) delta^(l)(k) / V.
@@ -595,11 +596,22 @@ def skew_spectra(spec_l: Sequence[np.ndarray], n: int, nr: int, k0: float, dk: f
       S^l_b = V sum_{n in b} Re[conj(Q(n)) delta^(l)(n)] / (N^9 N'^3 N_b)
     over the full lattice (the 1/V and the band are readings; with them
     S^l_b N_b = V / (N^9 N'^3) sum_{b2, b3} T^l(b, b2, b3), the discrete form of
-    S = int d^3q / (2 pi)^3 B(k, q, |k + q|)). Returns (S [nl][nb], N_b)."""
+    S = int d^3q / (2 pi)^3 B(k, q, |k + q|)). Returns (S [nl][nb], N_b).
+
+    square_range "ball": the squared field keeps delta^(0) on every mode
+    0 < |n|^2 <= n2max of the bins' band (the modes below the first shell
+    too), the closest the no-wrap condition allows to squaring the full
+    field; the sum rule then no longer holds."""
     n2 = n2_grid_half(nr)
     bins = bin_of_n2(n2, k0, dk, nb)
     specs = [_crop_spec(s, n, nr) for s in spec_l]
-    d = shell_field(specs[0], bins >= 0, nr)
+    if square_range == "shells":
+        keep = bins >= 0
+    elif square_range == "ball":
+        keep = (n2 > 0) & (n2 <= n2_max_of(k0, dk, nb))
+    else:
+        raise ValueError("square_range must be 'shells' or 'ball'")
+    d = shell_field(specs[0], keep, nr)
     Q = forward(d * d)
     mult = np.full(nr // 2 + 1, 2.0)
     mult[0] = 1.0

@@ -232,13 +232,16 @@ def test_skew_spectra_sum_rule():
             assert abs(S[li, b] * Nb[b] - rhs) <= 1e-10 * scale, (li, b)
 
 
-def test_skew_spectra_brute_convolution():
+@pytest.mark.parametrize("square_range", ["shells", "ball"])
+def test_skew_spectra_brute_convolution(square_range):
     """Q(n) = N'^3 sum_q delta^0(q) delta^0(n - q) over q and n - q in the bins'
-    union, summed directly over the full lattice (plane-parallel LOS)."""
-    n, box, k0, dk, nb = 16, 100.0, 2.0, 2.0, 2
+    union (or in the ball 0 < |q|^2 <= n2max of the band), summed directly over
+    the full lattice (plane-parallel LOS)."""
+    n, box, dk, nb = 16, 100.0, 2.0, 2
+    k0 = 2.0 if square_range == "shells" else 3.0  # the ball: a gap 1 <= |n|^2 < 4 below the first shell
     d = rng(32).standard_normal((n, n, n))
     spec = O.spectrum_from_field([d], [0.0], n, 2, None, None)
-    S, Nb = O.skew_spectra(spec, n, n, k0, dk, nb, box)
+    S, Nb = O.skew_spectra(spec, n, n, k0, dk, nb, box, square_range)
     fr = np.fft.fftfreq(n, 1.0 / n).astype(int)
     F0 = np.fft.fftn(d)
     # delta^(2) on the full lattice: (5) L_2(n_z / |n|) delta(n) for a LOS along z
@@ -247,7 +250,11 @@ def test_skew_spectra_brute_convolution():
     mu2 = nz ** 2 / np.maximum(n2, 1)
     F2 = 5 * 0.5 * (3 * mu2 - 1) * F0
     bins = O.bin_of_n2(n2, k0, dk, nb)
-    band = np.argwhere(bins >= 0)
+    # the ball written out: 0 < 4 |n|^2 < (2 (k0 + (nb - 1) dk) + dk)^2 = 144
+    inband = (bins >= 0) if square_range == "shells" else ((n2 > 0) & (4 * n2 < 144))
+    if square_range == "ball":
+        assert (inband & (bins < 0)).any()  # the ball holds modes below the first shell
+    band = np.argwhere(inband)
     V = box ** 3
     for b in range(nb):
         acc = [0.0, 0.0]
@@ -255,7 +262,7 @@ def test_skew_spectra_brute_convolution():
             q = 0.0j
             for (a, bb, cc) in band:
                 i2, j2, k2 = (i - a) % n, (j - bb) % n, (k - cc) % n
-                if bins[i2, j2, k2] >= 0:
+                if inband[i2, j2, k2]:
                     q += F0[a, bb, cc] * F0[i2, j2, k2]
             Q = float(n) ** 3 * q
             acc[0] += float(np.real(np.conj(Q) * F0[i, j, k]))
@@ -263,6 +270,22 @@ def test_skew_spectra_brute_convolution():
         for li in range(2):
             ref = V * acc[li] / (float(n) ** 12 * Nb[b])
             assert abs(S[li, b] - ref) <= 1e-9 * abs(V * acc[0] / (float(n) ** 12 * Nb[b])), (b, li, S[li, b], ref)
+
+
+def test_skew_spectra_ball_equals_shells_when_the_shells_fill_it():
+    """With the first shell reaching down to |n| = 0 the union of the shells is
+    the whole ball and both squared fields are the same; with a gap below the
+    first shell they differ."""
+    n, box, nb = 32, 200.0, 4
+    d = rng(33).standard_normal((n, n, n))
+    obs = np.array([-40.0, -30.0, -55.0])
+    spec = O.spectrum_from_field([d], [0.0], n, 4, obs, None)
+    Sa, _ = O.skew_spectra(spec, n, n, 1.0, 2.0, nb, box, "shells")
+    Sb, _ = O.skew_spectra(spec, n, n, 1.0, 2.0, nb, box, "ball")
+    assert np.allclose(Sa, Sb, rtol=1e-12, atol=1e-12 * np.abs(Sa).max())
+    Sc, _ = O.skew_spectra(spec, n, n, 3.0, 2.0, nb, box, "shells")
+    Sd, _ = O.skew_spectra(spec, n, n, 3.0, 2.0, nb, box, "ball")
+    assert np.linalg.norm(Sc - Sd) > 1e-3 * np.linalg.norm(Sc)
 
 
 def test_skew_spectra_vanish_without_closed_triangles():
