@@ -344,8 +344,13 @@ bsp_status bsp_shot_noise_multipoles(bsp_plan plan, const double* P, double nbar
  * and in the power-spectrum estimator) and the band are readings; with them
  * S[l][b] N_b = V / (N^9 N'^3) sum over all (b2, b3) of the triple sums
  * sum_x D^l_b D^0_b2 D^0_b3. delta_l: device, the compact spectrum [nl][spec]
- * of bsp_los_moments. S: device double [nl][nbins]. Uses the workspace. */
-bsp_status bsp_skew_spectra(bsp_plan plan, const void* delta_l, double* S);
+ * of bsp_los_moments. S: device double [nl][nbins]. Uses the workspace.
+ * flags: 0, or BSP_SKEW_BALL: d keeps delta^(0) on every mode
+ * 0 < |n|^2 <= n2max (the modes below the first shell too), the widest range
+ * that stays free of wrap-around, closer to squaring the whole density field
+ * (the sum rule above then does not hold). Other bits: BSP_ERR_ARG. */
+#define BSP_SKEW_BALL 1
+bsp_status bsp_skew_spectra(bsp_plan plan, const void* delta_l, double* S, int32_t flags);
 
 /* Integrated bispectrum multipoles (Sec. 3.4, eq. integBisp and the RSD
  * estimator after it): the N^3 grid is cut into s^3 cubic sub-volumes of side
@@ -366,9 +371,21 @@ bsp_status bsp_skew_spectra(bsp_plan plan, const void* delta_l, double* S);
  * iB: device double [nl][nbins]; Psub: device double [s^3][nl][nbins] or NULL;
  * dbar: device double [s^3] or NULL. Sub-volume i has origin
  * M (i / s^2, (i / s) mod s, i mod s). Uses the workspace (about 3 N^3 floats);
- * synchronises. */
+ * synchronises.
+ * flags: 0, or BSP_IB_LOCAL_LOS: the line of sight varies over the nodes of
+ * each sub-volume as in eq. (PowSpecMultipole) (x_hat from the observer to the
+ * node; the grid's first node set, no shift):
+ *   P[i][l][b] = V_s sum_{n in b} Re[delta^(l)_i(n) conj delta^(0)_i(n)] / (M^6 N_b),
+ *   delta^(l)_i(n) = (2l+1) sum_x e^{-2 pi i n.x / M} delta(x) L_l(nhat . xhat) / W(n)
+ * over the sub-volume's nodes, computed per real solid harmonic of x_hat
+ * (1, 6 or 15 batched transforms of all sub-volumes, one after another) by
+ * the addition theorem; about one more N^3 floats of workspace. For
+ * plane-parallel plans both readings are the same and the flag is ignored.
+ * Any other flag bit: BSP_ERR_ARG. */
+#define BSP_IB_LOCAL_LOS 1
 bsp_status bsp_integrated_bispectrum(bsp_plan plan, const float* grid, const double* wsum, int32_t s, double k0,
-                                     double dk, int32_t nbins, double* iB, double* Psub, double* dbar);
+                                     double dk, int32_t nbins, double* iB, double* Psub, double* dbar,
+                                     int32_t flags);
 
 /* Full bispectrum multipoles B^(l1 l2 l3) (Sec. 3, the general Legendre
  * decomposition with one multipole per side) in the FFT form of eq.

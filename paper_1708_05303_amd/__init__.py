@@ -25,8 +25,8 @@ __all__ = [
     "bsp_bispectrum_field", "bsp_batch_run", "BSP_BATCH_GRAPH", "BSP_BATCH_FSYNC", "bsp_batch_run_journal",
     "bsp_config_hash", "bsp_journal_scan", "bsp_journal_append", "bsp_journal_lookup",
     "bsp_batch_covariance", "bsp_power_multipoles",
-    "bsp_shot_noise_multipoles", "bsp_skew_spectra",
-    "bsp_integrated_bispectrum", "bsp_bispectrum_full", "bsp_set_timing", "bsp_stage_times", "STAGES",
+    "bsp_shot_noise_multipoles", "bsp_skew_spectra", "BSP_SKEW_BALL",
+    "bsp_integrated_bispectrum", "BSP_IB_LOCAL_LOS", "bsp_bispectrum_full", "bsp_set_timing", "bsp_stage_times", "STAGES",
     "EXPORTED",
 ]
 
@@ -129,8 +129,8 @@ def lib():
         "bsp_batch_covariance": [_vp, _i32, _i32, _vp, _vp],
         "bsp_power_multipoles": [_vp, _vp, _vp],
         "bsp_shot_noise_multipoles": [_vp, _vp, _d, _vp],
-        "bsp_skew_spectra": [_vp, _vp, _vp],
-        "bsp_integrated_bispectrum": [_vp, _vp, _vp, _i32, _d, _d, _i32, _vp, _vp, _vp],
+        "bsp_skew_spectra": [_vp, _vp, _vp, _i32],
+        "bsp_integrated_bispectrum": [_vp, _vp, _vp, _i32, _d, _d, _i32, _vp, _vp, _vp, _i32],
         "bsp_bispectrum_full": [_vp, _vp, _i32, _vp],
         "bsp_set_timing": [_vp, _i32],
         "bsp_stage_times": [_vp, _vp, _vp, _vp],
@@ -376,13 +376,21 @@ def bsp_shot_noise_multipoles(plan, P, nbar, SN):
     _check(lib().bsp_shot_noise_multipoles(plan, _dptr(P), float(nbar), _dptr(SN)), plan)
 
 
-def bsp_skew_spectra(plan, delta_l, S):
-    _check(lib().bsp_skew_spectra(plan, _dptr(delta_l), _dptr(S)), plan)
+BSP_SKEW_BALL = 1
 
 
-def bsp_integrated_bispectrum(plan, grid, wsum, s, k0, dk, nbins, iB, Psub=None, dbar=None):
+def bsp_skew_spectra(plan, delta_l, S, flags=0):
+    """flags: 0 (monopole squared on the union of the shells) or BSP_SKEW_BALL (on the ball |n|^2 <= n2max)."""
+    _check(lib().bsp_skew_spectra(plan, _dptr(delta_l), _dptr(S), int(flags)), plan)
+
+
+BSP_IB_LOCAL_LOS = 1
+
+
+def bsp_integrated_bispectrum(plan, grid, wsum, s, k0, dk, nbins, iB, Psub=None, dbar=None, flags=0):
+    """flags: 0 (one line of sight per sub-volume) or BSP_IB_LOCAL_LOS (x_hat per node)."""
     _check(lib().bsp_integrated_bispectrum(plan, _dptr(grid), _dptr(wsum), int(s), float(k0), float(dk), int(nbins),
-                                           _dptr(iB), _dptr(Psub), _dptr(dbar)), plan)
+                                           _dptr(iB), _dptr(Psub), _dptr(dbar), int(flags)), plan)
 
 
 def bsp_bispectrum_full(plan, delta_l, prec, B):

@@ -337,7 +337,8 @@ struct bsp_plan_s {
   std::vector<int32_t> field_row32;  // tab32 row of each main pipeline field
   int32_t band_row32 = 0;            // tab32 row of the union of the shells
   std::map<int, float2*> tw32_other;  // FP32 twiddles of other transform sizes, made on first use
-  int32_t* d_band_meta = nullptr;    // {0, band_row32}: l slot and table row of the band-limited monopole
+  int32_t* d_band_meta = nullptr;    // {0, band_row32, 0, band_row32 + 1}: l slot and table row of the
+                                     // monopole on the union of the shells, then on the ball
   std::vector<int> field_c;   // per main-pipeline field
   int32_t *d_field_ell = nullptr, *d_field_tab = nullptr;
   int32_t *d_ones_ell = nullptr, *d_pre_tab = nullptr;  // precompute: all ell 0, table row = index
@@ -454,9 +455,12 @@ struct StageTimer {
     p->ev_stage[slot] = st;
     (void)hipEventRecord(p->ev_pool[slot][0], p->stream);
   }
-  ~StageTimer() {
+  // records the end event now (once) instead of at scope exit
+  void stop() {
     if (slot != (size_t)-1) (void)hipEventRecord(p->ev_pool[slot][1], p->stream);
+    slot = (size_t)-1;
   }
+  ~StageTimer() { stop(); }
 };
 
 template <typename T>
@@ -1265,8 +1269,10 @@ bsp_status bsp_plan_create(bsp_plan* out, const bsp_geom* g, const bsp_modal_bas
   p->d_bin_of_n2 = upload(p, p->bin_of_n2);
   p->d_nb_modes = upload(p, p->nb_modes);
   const int tl = p->n2max + 1;
-  // tab32 rows: nbins shells, P modal weights, then the union of the shells
-  std::vector<float> tab32((size_t)(p->nbins + p->P + 1) * tl, 0.f);
+  // tab32 rows: nbins shells, P modal weights, the union of the shells, then
+  // the ball 0 < |n|^2 <= n2max
+  std::vector<float> tab32((size_t)(p->nbins + p->P + 2) * tl, 0.f);
+  for (int n2 = 1; n2 < tl; ++n2) tab32[(size_t)(p->nbins + p->P + 1) * tl + n2] = 1.f;
   const int nrow64 = p->nbins + (p->modal ? p->nU + 2 * p->P : 0);
   std::vector<double> tab64((size_t)nrow64 * tl, 0.0);
   for (int n2 = 0; n2 < tl; ++n2) {
@@ -1350,7 +1356,7 @@ bsp_status bsp_plan_create(bsp_plan* out, const bsp_geom* g, const bsp_modal_bas
   p->d_field_tab = upload(p, ft);
   p->field_row32 = ft;
   p->band_row32 = p->nbins + p->P;
-  p->d_band_meta = upload(p, std::vector<int32_t>{0, p->band_row32});
+  p->d_band_meta = upload(p, std::vector<int32_t>{0, p->band_row32, 0, p->band_row32 + 1});
   std::vector<int32_t> zeros(std::max(nrow64, 1), 0), iota(std::max(nrow64, 1));
   for (int i = 0; i < (int)iota.size(); ++i) iota[i] = i;
   p->d_ones_ell = upload(p, zeros);
@@ -2200,8 +2206,10 @@ bsp_status bsp_shot_noise_multipoles(bsp_plan p, const double* Pl, double nbar, 
   return BSP_OK;
 }
 
-bsp_status bsp_skew_spectra(bsp_plan p, const void* delta_l, double* S) {
-  if (!p || !delta_l || !S) return fail(p, BSP_ERR_ARG, "null argument");
+bsp_status bsp_skew_spectra(bsp_plan p, const void* delta_l, double* S, int32_t flags) {
+  if (!p || !delta_l || !S || (flags & ~BSP_SKEW_BALL)) return fail(p, BSP_ERR_ARG, "null argument or bad flags");
+  const int brow = p->band_row32 + ((flags & BSP_SKEW_BALL) ? 1 : 0);  // table row of the squared monopole's range
+  const int32_t* meta = p->d_band_meta + ((flags & BSP_SKEW_BALL) ? 2 : 0);
   const int Nr = p->Nr, c = p->c, cz = p->cz, w = 2 * c + 1;
   const size_t dbytes = align_up((size_t)Nr * Nr * Nr * sizeof(float));
   const size_t zb = align_up((size_t)Nr * Nr * cz * sizeof(float2)), yb = align_up((size_t)Nr * w * cz * sizeof(float2));
@@ -2217,16 +2225,15 @@ bsp_status bsp_skew_spectra(bsp_plan p, const void* delta_l, double* S) {
   // transform (its modes read, nonzero columns, y output, real field written),
   // the square (read + write), the pruned forward transform of the square to
   // the compact cube, and the shell sums (nl moments and the partner spectrum)
-  const double C1 = c + 1.0, W1 = w, R = Nr, sup = (double)p->row_support32[p->band_row32],
-               cols = (double)p->row_cols32[p->band_row32];
+  const double C1 = c + 1.0, W1 = w, R = Nr, sup = (double)p->row_support32[brow],
+               cols = (double)p->row_cols32[brow];
   const double amount = (sup + 2.0 * R * cols + 2.0 * R * R * C1) * 8.0 + R * R * R * 4.0 + R * R * R * 8.0 +
                         R * R * R * 4.0 + R * R * C1 * 8.0 + R * C1 * 8.0 * (R + W1) + W1 * C1 * 8.0 * (R + W1) +
                         (p->nl + 1.0) * sup * 8.0;
   StageTimer t(p, 11, amount);
-  // d(x): unnormalised inverse DFT at N' of delta^(0) kept on the union of the shells
+  // d(x): unnormalised inverse DFT at N' of delta^(0) kept on the union of the shells (or the ball)
   const std::vector<int> cf{c};
-  s = inverse_fields<float>(p, dl, p->spec, 1, p->d_band_meta, p->d_band_meta + 1, p->d_tab32, p->d_rng32, d, sc, 2,
-                            cf, &p->band_row32);
+  s = inverse_fields<float>(p, dl, p->spec, 1, meta, meta + 1, p->d_tab32, p->d_rng32, d, sc, 2, cf, &brow);
   if (s != BSP_OK) return s;
   HIPCHK(launch_square(d, (int64_t)Nr * Nr * Nr, p->stream));
   // Q = DFT[d^2] at N', pruned to the compact cube |n_a| <= c
@@ -2276,9 +2283,11 @@ bsp_status bsp_skew_spectra(bsp_plan p, const void* delta_l, double* S) {
 }
 
 bsp_status bsp_integrated_bispectrum(bsp_plan p, const float* grid, const double* wsum, int32_t s, double k0,
-                                     double dk, int32_t nbins, double* iB, double* Psub, double* dbar) {
-  if (!p || !grid || !iB || s < 1 || nbins < 1 || !(dk > 0.0) || !(k0 > 0.0))
+                                     double dk, int32_t nbins, double* iB, double* Psub, double* dbar, int32_t flags) {
+  if (!p || !grid || !iB || s < 1 || nbins < 1 || !(dk > 0.0) || !(k0 > 0.0) || (flags & ~BSP_IB_LOCAL_LOS))
     return fail(p, BSP_ERR_ARG, "bad argument");
+  // the local line of sight differs from the one per sub-volume only when it varies
+  const bool local = (flags & BSP_IB_LOCAL_LOS) && !p->plane;
   const int N = p->N;
   if (N % s != 0) return fail(p, BSP_ERR_SIZE, "s must divide N");
   const int m = N / s, ns = s * s * s;
@@ -2316,7 +2325,8 @@ bsp_status bsp_integrated_bispectrum(bsp_plan p, const float* grid, const double
   const size_t pbytes = align_up((size_t)ns * nl * nbins * sizeof(double));
   const size_t dbytes = align_up((size_t)ns * sizeof(double));
   const size_t tbytes = align_up(bin.size() * sizeof(int32_t)) + align_up(nbm.size() * sizeof(int64_t));
-  bsp_status st = need_ws(p, gbytes + fbytes + pbytes + dbytes + tbytes);
+  const size_t f2bytes = local ? fbytes : 0;  // the kept F_i0 beside each harmonic's spectra
+  bsp_status st = need_ws(p, gbytes + fbytes + pbytes + dbytes + tbytes + f2bytes);
   if (st != BSP_OK) return st;
   const float2* tw = tw32_for(p, m);
   if (!tw) return fail(p, BSP_ERR_HIP, "twiddle table allocation failed");
@@ -2332,17 +2342,32 @@ bsp_status bsp_integrated_bispectrum(bsp_plan p, const float* grid, const double
   // algorithmic bytes: the grid read once, each transform pass's input and
   // output once, the sub-volume spectra read once by the shell sums
   const double R = (double)N * N * N, H = (double)ns * m * m * h * 8.0;
-  {
-    StageTimer t(p, 12, R * 4.0 + R * 4.0 * 2.0 + H * 6.0 + H);
+  const int window = p->g.compensate ? p->g.window : -1;
+  // with the local line of sight, one pass per harmonic h_m of degree <= lmax
+  const int nh = local ? (nl == 1 ? 1 : (nl == 2 ? 6 : 15)) : 1;
+  StageTimer t(p, 12, local ? nh * (R * 4.0 + R * 4.0 * 2.0 + H * 6.0 + 2.0 * H) : R * 4.0 + R * 4.0 * 2.0 + H * 7.0);
+  if (local) {
+    // each harmonic's spectra are summed against the kept F_i0
+    float2* Fm = reinterpret_cast<float2*>(p->ws + gbytes + fbytes + pbytes + dbytes + tbytes);
+    for (int hm = 0; hm < nh; ++hm) {
+      float2* dst = hm == 0 ? F : Fm;
+      HIPCHK(launch_gather_subvolumes_los(grid, wsum, N, s, hm, p->g.observer, sub, p->stream));
+      st = r2c_batch(p, m, ns, sub, dst, tw);
+      if (st != BSP_OK) return st;
+      const int l = kLosDegree[hm];
+      HIPCHK(launch_subvolume_cross(F, dst, m, s, hm, l / 2, (2.0 * l + 1.0) * kLosCoef[hm], window, nl, dbin, n2max,
+                                    nbins, psum, db, p->stream));
+    }
+  } else {
     HIPCHK(launch_gather_subvolumes(grid, wsum, N, s, sub, p->stream));
     st = r2c_batch(p, m, ns, sub, F, tw);
     if (st != BSP_OK) return st;
-    HIPCHK(launch_subvolume_shells(F, m, s, p->plane, p->g.observer, p->g.compensate ? p->g.window : -1, nl, dbin,
-                                   n2max, nbins, psum, db, p->stream));
-    const double Vs = p->V / ((double)s * s * s);
-    HIPCHK(launch_subvolume_finalize(psum, db, ns, nl, nbins, dnb, Vs / std::pow((double)m, 6), iB, Psub,
-                                     p->stream));
+    HIPCHK(launch_subvolume_shells(F, m, s, p->plane, p->g.observer, window, nl, dbin, n2max, nbins, psum, db,
+                                   p->stream));
   }
+  const double Vs = p->V / ((double)s * s * s);
+  HIPCHK(launch_subvolume_finalize(psum, db, ns, nl, nbins, dnb, Vs / std::pow((double)m, 6), iB, Psub, p->stream));
+  t.stop();
   HIPCHK(hipStreamSynchronize(p->stream));  // the host tables above are read by the copies
   return BSP_OK;
 }

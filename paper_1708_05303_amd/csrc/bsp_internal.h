@@ -55,6 +55,17 @@ constexpr LosTerm kLosPoly[kLosFields][4] = {
     {{1, 4, 0, 0}, {-6, 2, 2, 0}, {1, 0, 4, 0}, {0, 0, 0, 0}},
     {{4, 3, 1, 0}, {-4, 1, 3, 0}, {0, 0, 0, 0}, {0, 0, 0, 0}}};
 
+// Addition-theorem coefficients a_m of the harmonics (kLosPoly order): l = 2
+// (fields 1..5) and l = 4 (fields 6..14), from
+// 2 (l-m)!/(l+m)! times the squared prefactors of the associated Legendre
+// functions written as these polynomials.
+constexpr double kLosCoef[kLosFields] = {1.0,
+                                         3.0, 3.0, 0.75, 0.75, 0.25,
+                                         1.0 / 64, 5.0 / 8, 5.0 / 8, 5.0 / 16, 5.0 / 16, 35.0 / 8, 35.0 / 8,
+                                         35.0 / 64, 35.0 / 64};
+// Degree l of each harmonic.
+constexpr int kLosDegree[kLosFields] = {0, 2, 2, 2, 2, 2, 4, 4, 4, 4, 4, 4, 4, 4, 4};
+
 template <int E, typename T> __device__ __forceinline__ T los_pow(T x) {
   if constexpr (E == 0) return (T)1;
   else if constexpr (E == 1) return x;
@@ -215,6 +226,14 @@ hipError_t launch_gather_subvolumes(const float* grid, const double* wsum, int n
 hipError_t launch_subvolume_shells(const float2* F, int m, int s, int plane, const double* obs, int window, int nl,
                                    const int32_t* bin_of_n2, int n2max, int nbins, double* psum, double* dbar,
                                    hipStream_t st);
+// Local line of sight: the sub-volumes times the harmonic h_harm(x_hat), x_hat
+// from the observer obs (grid units) to each node; the cross sums
+// psum[i][ell_slot][b] += coef sum_{n in b} mult h_harm(n_hat) Re[Fm conj F0] / W^2.
+hipError_t launch_gather_subvolumes_los(const float* grid, const double* wsum, int n, int s, int harm,
+                                       const double* obs, float* out, hipStream_t st);
+hipError_t launch_subvolume_cross(const float2* F0, const float2* Fm, int m, int s, int harm, int ell_slot,
+                                  double coef, int window, int nl, const int32_t* bin_of_n2, int n2max, int nbins,
+                                  double* psum, double* dbar, hipStream_t st);
 hipError_t launch_subvolume_finalize(const double* psum, const double* dbar, int ns, int nl, int nbins,
                                      const int64_t* nb_modes, double scale, double* iB, double* P, hipStream_t st);
 

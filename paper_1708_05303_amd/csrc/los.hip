@@ -18,15 +18,6 @@
 
 namespace bsp {
 
-// Addition-theorem coefficients a_m of the harmonics (kLosPoly order): l = 2
-// (fields 1..5) and l = 4 (fields 6..14), from
-// 2 (l-m)!/(l+m)! times the squared prefactors of the associated Legendre
-// functions written as these polynomials.
-constexpr double kLosCoef[kLosFields] = {1.0,
-                                         3.0, 3.0, 0.75, 0.75, 0.25,
-                                         1.0 / 64, 5.0 / 8, 5.0 / 8, 5.0 / 16, 5.0 / 16, 35.0 / 8, 35.0 / 8,
-                                         35.0 / 64, 35.0 / 64};
-
 template <int M> __device__ __forceinline__ void add_harmonic(double2& acc, const double* kh, double2 f) {
   const double h = kLosCoef[M] * los_harmonic<M, double>(kh[0], kh[1], kh[2]);
   acc.x += h * f.x;

@@ -343,12 +343,17 @@ def test_power_multipoles_rejects_null():
     plan.close()
 
 
-@pytest.mark.parametrize("n,nr,los,interlace,nb", [(32, 32, 1, 1, 5), (32, 16, 0, 0, 2)])
-def test_skew_spectra_against_oracle(n, nr, los, interlace, nb):
+@pytest.mark.parametrize("n,nr,los,interlace,nb,square,k0", [(32, 32, 1, 1, 5, "shells", 2.0),
+                                                               (32, 16, 0, 0, 2, "shells", 2.0),
+                                                               (32, 32, 1, 1, 4, "ball", 3.0),
+                                                               (32, 16, 0, 0, 2, "ball", 3.0)])
+def test_skew_spectra_against_oracle(n, nr, los, interlace, nb, square, k0):
     """Skew-spectrum multipoles (Sec. 3.2) from the LOS moment spectra of a
-    clustered redshift-space catalogue, against the FP64 oracle."""
-    say("skew-spectra", n, nr, los, interlace, nb)
-    box, k0, dk = 200.0, 2.0, 2.0
+    clustered redshift-space catalogue, against the FP64 oracle; the squared
+    monopole on the union of the shells, or on the whole ball of the band
+    (k0 = 3 leaves a gap below the first shell, so the two differ)."""
+    say("skew-spectra", n, nr, los, interlace, nb, square)
+    box, dk = 200.0, 2.0
     obs = np.array([-300.0, -200.0, -250.0])
     u = _catalogue(n, 30000, 17)
     plan = B.Plan(n=n, n_reduce=nr, box=box, nbins=nb, k0=k0, dk=dk, lmax=4, interlace=interlace, los=los,
@@ -360,11 +365,14 @@ def test_skew_spectra_against_oracle(n, nr, los, interlace, nb):
     dl = plan.spectrum_buffer()
     B.bsp_los_moments(plan.handle, grids, wsum, dl)
     S = torch.zeros((info.nl, nb), dtype=torch.float64, device=DEV)
-    B.bsp_skew_spectra(plan.handle, dl, S)
+    B.bsp_skew_spectra(plan.handle, dl, S, B.BSP_SKEW_BALL if square == "ball" else 0)
     plan.sync()
     got = S.cpu().numpy()
     spec, _ = O.spectrum_from_catalogue(*u, n, 4, obs if los else None, window=1, interlace=interlace)
-    ref, _ = O.skew_spectra(spec, n, nr, k0, dk, nb, box)
+    ref, _ = O.skew_spectra(spec, n, nr, k0, dk, nb, box, square)
+    if square == "ball":
+        other, _ = O.skew_spectra(spec, n, nr, k0, dk, nb, box, "shells")
+        assert np.linalg.norm(other - ref) > 1e-3 * np.linalg.norm(ref)
     s0 = np.linalg.norm(ref[0])
     for li in range(info.nl):
         e = np.linalg.norm(got[li] - ref[li]) / max(np.linalg.norm(ref[li]), 0.01 * s0)
@@ -378,6 +386,9 @@ def test_skew_spectra_rejects_null():
     S = torch.zeros((1, 2), dtype=torch.float64, device=DEV)
     with pytest.raises(B.BspError):
         B.bsp_skew_spectra(plan.handle, None, S)
+    dl = plan.spectrum_buffer()
+    with pytest.raises(B.BspError):
+        B.bsp_skew_spectra(plan.handle, dl, S, 2)
     plan.close()
 
 
@@ -412,6 +423,69 @@ def test_integrated_bispectrum_against_oracle(n, s, los, window, nb):
         ei = np.linalg.norm(giB[li] - riB[li]) / scale
         say("  l", 2 * li, "P err", e, "iB err / term scale", ei)
         assert e < 1e-5 and ei < 1e-5, (li, e, ei)
+    plan.close()
+
+
+@pytest.mark.parametrize("n,s,window,lmax", [(32, 2, 1, 4), (64, 2, 1, 4), (64, 4, 0, 2)])
+def test_integrated_bispectrum_local_los_against_oracle(n, s, window, lmax):
+    """The integrated bispectrum with the line of sight varying inside each
+    sub-volume (eq. PowSpecMultipole per sub-volume) against the FP64 oracle;
+    the l = 0 parts equal those of the one-LOS reading."""
+    say("integrated-bispectrum local LOS", n, s, window, lmax)
+    box, k0, dk, nb = 200.0, 1.0, 1.0, 5
+    obs = np.array([-30.0, -20.0, -25.0]) * n / 32  # near: x_hat turns by tens of degrees over a sub-volume
+    u = _catalogue(n, 40000, 23)
+    plan = B.Plan(n=n, box=box, nbins=2, k0=2.0, dk=2.0, lmax=lmax, window=window, los=1, observer=obs)
+    info = plan.info
+    grids = torch.zeros((1, n, n, n), dtype=torch.float32, device=DEV)
+    wsum = torch.zeros(1, dtype=torch.float64, device=DEV)
+    B.bsp_grid_assign(plan.handle, dev(u[0]), dev(u[1]), dev(u[2]), None, u[0].size, grids, wsum)
+    ns = s ** 3
+    out = {}
+    for flags in (0, B.BSP_IB_LOCAL_LOS):
+        iB = torch.zeros((info.nl, nb), dtype=torch.float64, device=DEV)
+        Ps = torch.zeros((ns, info.nl, nb), dtype=torch.float64, device=DEV)
+        db = torch.zeros(ns, dtype=torch.float64, device=DEV)
+        B.bsp_integrated_bispectrum(plan.handle, grids, wsum, s, k0, dk, nb, iB, Ps, db, flags)
+        plan.sync()
+        out[flags] = (iB.cpu().numpy(), Ps.cpu().numpy(), db.cpu().numpy())
+    rho = O.assign(*u, n, None, window, 0.0)
+    delta = O.density_contrast(rho, float(wsum.item()))
+    riB, rP, rdb, _ = O.integrated_bispectrum_local_los(delta, s, lmax, obs, window, box, k0, dk, nb)
+    giB, gP, gdb = out[B.BSP_IB_LOCAL_LOS]
+    assert np.max(np.abs(gdb - rdb)) < 1e-5 * np.sqrt(np.mean(rdb ** 2)) + 1e-7
+    for li in range(info.nl):
+        e = np.linalg.norm(gP[:, li] - rP[:, li]) / max(np.linalg.norm(rP[:, li]), 0.01 * np.linalg.norm(rP[:, 0]))
+        scale = np.linalg.norm(np.abs(rP[:, li]).T @ np.abs(rdb)) / ns
+        ei = np.linalg.norm(giB[li] - riB[li]) / scale
+        say("  l", 2 * li, "P err", e, "iB err / term scale", ei)
+        assert e < 1e-5 and ei < 1e-5, (li, e, ei)
+    # the monopole does not depend on the line of sight; the l > 0 parts do
+    p1 = out[0][1]
+    assert np.linalg.norm(gP[:, 0] - p1[:, 0]) < 1e-5 * np.linalg.norm(p1[:, 0])
+    assert np.linalg.norm(gP[:, 1] - p1[:, 1]) > 1e-3 * np.linalg.norm(p1[:, 1])
+    plan.close()
+
+
+def test_integrated_bispectrum_local_los_plane_parallel_and_flags():
+    """Plane-parallel plans have one line of sight: both readings give the same
+    values (up to the order of the FP64 atomic shell sums). An unknown flag bit
+    is rejected."""
+    n, s, nb = 32, 2, 4
+    u = _catalogue(n, 20000, 29)
+    plan = B.Plan(n=n, box=150.0, nbins=2, k0=2.0, dk=2.0, lmax=4, los=0)
+    grids = torch.zeros((1, n, n, n), dtype=torch.float32, device=DEV)
+    wsum = torch.zeros(1, dtype=torch.float64, device=DEV)
+    B.bsp_grid_assign(plan.handle, dev(u[0]), dev(u[1]), dev(u[2]), None, u[0].size, grids, wsum)
+    res = []
+    for flags in (0, B.BSP_IB_LOCAL_LOS):
+        iB = torch.zeros((3, nb), dtype=torch.float64, device=DEV)
+        B.bsp_integrated_bispectrum(plan.handle, grids, wsum, s, 1.0, 1.0, nb, iB, None, None, flags)
+        plan.sync()
+        res.append(iB.cpu().numpy())
+    assert np.allclose(res[0], res[1], rtol=1e-12, atol=1e-12 * np.abs(res[0]).max())
+    with pytest.raises(B.BspError):
+        B.bsp_integrated_bispectrum(plan.handle, grids, wsum, s, 1.0, 1.0, nb, iB, None, None, 2)
     plan.close()
 
 
