@@ -234,6 +234,18 @@ def spectra_legs(B, torch, plan, wl, ux, uy, uz, npart, pbar_path, b_path, prec,
     sk = {"ms": avg_s * 1e3, "launches": n, "algorithmic_bytes": amt / n, "achieved_GBps": amt / n / avg_s / 1e9,
           "frac_hbm": amt / n / avg_s / PEAK_HBM,
           "S_l_first_bins": [[float(x) for x in Sl[li, :3].cpu().numpy()] for li in range(nl)]}
+    # the squared monopole on the whole ball of the band instead of the shells
+    Sb = torch.zeros_like(Sl)
+    B.bsp_skew_spectra(plan.handle, dl, Sb, B.BSP_SKEW_BALL)
+    plan.sync()
+    B.bsp_set_timing(plan.handle, True)
+    for _ in range(skew_reps):
+        B.bsp_skew_spectra(plan.handle, dl, Sb, B.BSP_SKEW_BALL)
+    ms, n, _ = B.bsp_stage_times(plan.handle)["skew_spectra"]
+    B.bsp_set_timing(plan.handle, False)
+    sk["ball"] = {"ms": ms / n, "rel_diff_from_shells": [float(np.linalg.norm((Sb[li] - Sl[li]).cpu().numpy()) /
+                                                               np.linalg.norm(Sl[li].cpu().numpy())) for li in range(nl)]}
+    log_fn(f"skew spectra (ball): {ms / n:.3f} ms per call")
     ntri = plan.info.ntri
     Bf = torch.zeros((nl ** 3, ntri), dtype=torch.float64, device=dev)
     B.bsp_bispectrum_full(plan.handle, dl, prec, Bf)  # builds the schedule
@@ -264,6 +276,20 @@ def spectra_legs(B, torch, plan, wl, ux, uy, uz, npart, pbar_path, b_path, prec,
     ib = {"ms": avg_s * 1e3, "launches": n, "subvolumes": ib_s ** 3, "subvolume_side": wl.n // ib_s,
           "algorithmic_bytes": amt / n, "achieved_GBps": amt / n / avg_s / 1e9, "frac_hbm": amt / n / avg_s / PEAK_HBM,
           "iB_l_first_bins": [[float(x) for x in iB[li, :3].cpu().numpy()] for li in range(nl)]}
+    # the line of sight varying over the nodes of each sub-volume
+    iBl = torch.zeros_like(iB)
+    B.bsp_integrated_bispectrum(plan.handle, grids[0], wsum, ib_s, 1.0, 1.0, ib_nbins, iBl, None, None,
+                                B.BSP_IB_LOCAL_LOS)
+    B.bsp_set_timing(plan.handle, True)
+    for _ in range(ib_reps):
+        B.bsp_integrated_bispectrum(plan.handle, grids[0], wsum, ib_s, 1.0, 1.0, ib_nbins, iBl, None, None,
+                                    B.BSP_IB_LOCAL_LOS)
+    ms, n, amt = B.bsp_stage_times(plan.handle)["integrated_bispectrum"]
+    B.bsp_set_timing(plan.handle, False)
+    ib["local_los"] = {"ms": ms / n, "achieved_GBps": amt / n / (ms / n * 1e-3) / 1e9,
+                       "rel_diff_from_one_los": [float(np.linalg.norm((iBl[li] - iB[li]).cpu().numpy()) /
+                                                       np.linalg.norm(iB[li].cpu().numpy())) for li in range(nl)]}
+    log_fn(f"integrated bispectrum (local LOS): {ms / n:.3f} ms per call")
     del grids
     return pm, sk, ib, full
 

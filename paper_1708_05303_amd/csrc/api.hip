@@ -1551,6 +1551,9 @@ static const float2* tw32_for(bsp_plan p, int n) {
 // Unnormalised r2c of `batch` contiguous n^3 grids into [batch][n][n][n/2+1].
 static bsp_status r2c_batch(bsp_plan p, int n, int batch, const float* in, float2* out, const float2* tw) {
   const int h = n / 2 + 1;
+  // the tuned tile choice belongs to the plan's own grid sizes; other lengths
+  // (the integrated bispectrum's sub-volumes) take the rule
+  const int tiles = (n == p->N || n == p->Nr) ? p->tune_tiles : 0;
   FwdZDesc fz{};
   fz.ngrid = batch;
   fz.nlos = 1;
@@ -1560,7 +1563,7 @@ static bsp_status r2c_batch(bsp_plan p, int n, int batch, const float* in, float
   fz.zs = h;
   HIPCHK(launch_fwd_z_f32(n, in, out, fz, tw, p->stream));
   PassDesc py{};
-  py.tiles = p->tune_tiles;
+  py.tiles = tiles;
   py.nouter = batch * n;
   py.in_outer = py.out_outer = (int64_t)n * h;
   py.in_row = py.out_row = h;
@@ -1569,7 +1572,7 @@ static bsp_status r2c_batch(bsp_plan p, int n, int batch, const float* in, float
   set1d(py);
   HIPCHK(launch_c2c_f32(n, -1, out, out, py, nullptr, tw, p->stream));
   PassDesc px{};
-  px.tiles = p->tune_tiles;
+  px.tiles = tiles;
   px.nouter = batch;
   px.in_outer = px.out_outer = (int64_t)n * n * h;
   px.in_row = px.out_row = (int64_t)n * h;
