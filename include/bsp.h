@@ -460,7 +460,10 @@ bsp_status bsp_batch_run(const bsp_plan* plans, int32_t nplans, const int32_t* m
  * its particle count and its B, alpha and (when beta_all is given) beta,
  * closed by a 64-bit FNV-1a checksum. A mock whose (key, hash) is recorded
  * with the same particle count is not run: its outputs are copied from the
- * record into B_all, alpha_all and beta_all. Every other mock runs and is
+ * record into B_all, alpha_all and beta_all (a record without beta serves
+ * only calls without beta_all; otherwise the mock runs again and its new
+ * record, appended later, supersedes the old one: the last record of a key
+ * and configuration wins). Every other mock runs and is
  * appended to the journal as soon as its outputs are on the host (the host
  * writes mock k while mock k+1 runs), unless a kernel error is latched on its
  * plan, which ends the call with that error. A process killed at any point

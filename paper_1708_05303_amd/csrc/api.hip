@@ -2632,7 +2632,9 @@ bsp_status batch_impl(const bsp_plan* plans, int32_t nplans, const int32_t* mock
   // journal: which mocks are already recorded under their plan's configuration
   Journal jn;
   std::vector<uint64_t> hashes(nplans, 0);
-  std::vector<const JournalRecord*> rec(nmocks, nullptr);
+  // records of the mocks taken from the journal (copies: appends may move the index)
+  std::vector<JournalRecord> recv(nmocks);
+  std::vector<char> rec(nmocks, 0);
   int64_t nres = 0;
   if (journaled) {
     std::string err;
@@ -2648,7 +2650,8 @@ bsp_status batch_impl(const bsp_plan* plans, int32_t nplans, const int32_t* mock
         return fail(p0, BSP_ERR_ARG, "journal record of mock key " + std::to_string(mock_key[m]) +
                                          " has another particle count or output shape");
       if (beta_all && !r->has_beta) continue;  // recorded without beta: run it again
-      rec[m] = r;
+      recv[m] = *r;
+      rec[m] = 1;
       ++nres;
     }
     std::sort(seen.begin(), seen.end());
@@ -2694,7 +2697,7 @@ bsp_status batch_impl(const bsp_plan* plans, int32_t nplans, const int32_t* mock
       if (!rec[m]) continue;
       double* hb = st.h + (2 + k++) * st.slot;
       std::string err;
-      if (!jn.read(*rec[m], hb, hb + nB, hb + nB + D, err)) return fail(p0, BSP_ERR_IO, err);
+      if (!jn.read(recv[m], hb, hb + nB, hb + nB + D, err)) return fail(p0, BSP_ERR_IO, err);
       HIPCHK(hipMemcpyAsync(B_all + m * nB, hb, nB * sizeof(double), hipMemcpyHostToDevice, p0->stream));
       HIPCHK(hipMemcpyAsync(alpha_all + m * D, hb + nB, D * sizeof(double), hipMemcpyHostToDevice, p0->stream));
       if (beta_all)

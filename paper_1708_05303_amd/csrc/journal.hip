@@ -176,9 +176,11 @@ bool Journal::open(const std::string& path, bool create, std::string& err) {
   return true;
 }
 
+// The last record of (key, hash) wins: a mock recorded without beta and run
+// again for a caller that asks for beta is appended once more, with beta.
 const JournalRecord* Journal::find(uint64_t key, uint64_t hash) const {
-  for (const auto& r : recs_)
-    if (r.key == key && r.hash == hash) return &r;
+  for (auto it = recs_.rbegin(); it != recs_.rend(); ++it)
+    if (it->key == key && it->hash == hash) return &*it;
   return nullptr;
 }
 

@@ -98,17 +98,18 @@ def uneven_batch(tmp_path_factory):
     hpl = [plans[n].handle for n in sizes]
     npart = [u[0].size for u in cats]
 
-    def jrun(path, idx, flags):
+    def jrun(path, idx, flags, with_beta=True):
         sub = [[dv[a][i] for i in idx] for a in range(3)]
         B_all = torch.zeros((len(idx), nl, info.ntri), dtype=torch.float64, device=DEV)
         alpha_all = torch.zeros((len(idx), nl * nm), dtype=torch.float64, device=DEV)
-        beta_all = torch.zeros((len(idx), nl * nm), dtype=torch.float64, device=DEV)
+        beta_all = torch.zeros((len(idx), nl * nm), dtype=torch.float64, device=DEV) if with_beta else None
         cov = torch.zeros((nl * nm, nl * nm), dtype=torch.float64, device=DEV)
         nres = B.bsp_batch_run_journal(hpl, [order[i] for i in idx], [keys[i] for i in idx], sub[0], sub[1], sub[2],
                                        None, [npart[i] for i in idx], B.BSP_BF16X3, B_all, alpha_all, beta_all, cov,
                                        str(path), flags)
         plans[128].sync()
-        return nres, (B_all.cpu().numpy(), alpha_all.cpu().numpy(), beta_all.cpu().numpy(), cov.cpu().numpy())
+        return nres, (B_all.cpu().numpy(), alpha_all.cpu().numpy(),
+                      beta_all.cpu().numpy() if with_beta else None, cov.cpu().numpy())
 
     say("journal: fresh run of all mocks")
     full = jdir / "full.bspj"
@@ -126,6 +127,11 @@ def uneven_batch(tmp_path_factory):
     outs["journal_resume_scan"] = B.bsp_journal_scan(str(part))
     say("journal: every mock recorded, plain calls")
     outs["journal_all_recorded"] = jrun(part, range(len(mocks)), 0)
+    say("journal: records without beta serve only calls without beta")
+    nob = jdir / "nobeta.bspj"
+    outs["journal_nobeta"] = jrun(nob, [0, 1], B.BSP_BATCH_GRAPH, with_beta=False)
+    outs["journal_nobeta_again"] = jrun(nob, [0, 1], B.BSP_BATCH_GRAPH, with_beta=False)
+    outs["journal_beta_after_nobeta"] = jrun(nob, [0, 1], B.BSP_BATCH_GRAPH)
     outs["config_hash"] = {n: B.bsp_config_hash(plans[n].handle, B.BSP_BF16X3) for n in sizes}
     outs["config_hash_fp32"] = B.bsp_config_hash(plans[128].handle, B.BSP_FP32)
     counts = {n: plans[n].counts.copy() for n in sizes}
@@ -176,6 +182,12 @@ def test_batch_journal_resume_is_bit_identical(uneven_batch):
     assert nres == len(mocks)
     for a, b in zip(got, ref):
         assert np.array_equal(a, b)
+    for key, want in (("journal_nobeta", 0), ("journal_nobeta_again", 2), ("journal_beta_after_nobeta", 0)):
+        nres, got = outs[key]
+        assert nres == want, key
+        assert np.array_equal(got[0], ref[0][:2]) and np.array_equal(got[1], ref[1][:2]), key
+        if got[2] is not None:
+            assert np.array_equal(got[2], ref[2][:2]), key
     hashes = outs["config_hash"]
     assert len(set(hashes.values())) == len(hashes)  # plans of different N hash differently
     assert outs["config_hash_fp32"] != hashes[128]

@@ -93,6 +93,20 @@ def test_matching_rules(tmp_path):
     assert B.bsp_journal_scan(path)[0] == 2
 
 
+def test_last_record_of_a_key_wins(tmp_path):
+    """A record written without beta, then the same mock recorded again with
+    beta (what a batch that needs beta appends): lookups see the later one."""
+    path = tmp_path / "w.bspj"
+    Bm, al, be = sample(8)
+    B.bsp_journal_append(str(path), 3, 50, 700, Bm, al, None)
+    with open(path, "ab") as fh:
+        fh.write(record_bytes(3, 50, 700, Bm + 1, al + 1, be))
+    got = B.bsp_journal_lookup(str(path), 3, 50, 700, 3, 7, 12)
+    assert got is not None
+    assert np.array_equal(got[0], Bm + 1) and np.array_equal(got[1], al + 1) and np.array_equal(got[2], be)
+    assert B.bsp_journal_scan(str(path))[0] == 2
+
+
 def test_torn_tail_is_ignored_then_cut(tmp_path):
     path = tmp_path / "t.bspj"
     for k in range(4):
