@@ -483,9 +483,12 @@ __global__ __launch_bounds__(256) void k_assign_tiles(const float4* __restrict__
   if (tile == 0 && threadIdx.x == 0) wsum[0] += ldexp((double)(long long)wsum_fx[0], -sh);
 }
 
+// Tile depth along z: 32 nodes keeps the two grids' int64 node sums of an
+// 8 x 8 x 32 tile at 32 KB, so four workgroups share a CU (64-deep tiles left
+// under two waves per SIMD to hide the gather's memory latency).
 static int tile_tz(int n) {
   if (n % TXY != 0 || n / TXY < 2) return 0;
-  for (int tz = 64; tz >= 8; tz >>= 1)
+  for (int tz = 32; tz >= 8; tz >>= 1)
     if (n % tz == 0 && n / tz >= 2) return tz;
   return 0;
 }
@@ -584,7 +587,7 @@ hipError_t launch_assign_tiled(const float* ux, const float* uy, const float* uz
   hipLaunchKernelGGL(k_tile_scatter, dim3((unsigned)blocks), dim3(256), 0, s, ux, uy, uz, w, np_dev, n, ntx, ntz, tz,
                      offs, rank, sorted);
 #define TCASE(WIN, TZV)                                                                                         if (window == WIN && tz == TZV) {                                                                               hipLaunchKernelGGL((k_assign_tiles<WIN, TZV>), dim3((unsigned)nt), dim3(256), 0, s, sorted, offs, n, ntx,                        ntz, interlace, accumulate, np_dev, head, wsum_fx, grids, wsum);                                                        return hipGetLastError();                                                                                   }
-  TCASE(0, 64) TCASE(0, 32) TCASE(0, 16) TCASE(0, 8) TCASE(1, 64) TCASE(1, 32) TCASE(1, 16) TCASE(1, 8)
+  TCASE(0, 32) TCASE(0, 16) TCASE(0, 8) TCASE(1, 32) TCASE(1, 16) TCASE(1, 8)
 #undef TCASE
   return hipErrorInvalidValue;
 }

@@ -198,7 +198,7 @@ def test_full_size_integrated_bispectrum(spectra_case):
 @pytest.fixture(scope="module")
 def catalogue_case():
     """The bench catalogue itself (1e7 lognormal particles with Kaiser
-    displacements, CIC on two interlaced grids, 8 x 8 x 64 tiles) through
+    displacements, CIC on two interlaced grids, 8 x 8 x 32 tiles) through
     bsp_bispectrum_multipoles in FP32 and bf16 hi+lo, and its LOS moment
     spectra through bsp_los_moments for the raw modal numerators
     (bsp_modal_coeffs without shot noise); the oracle runs the same catalogue

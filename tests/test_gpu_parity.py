@@ -108,7 +108,7 @@ def _edge_catalogue(n, npart, seed):
 def test_grid_assign_against_oracle(n, window, interlace, mode):
     """The three assignment kernels against the oracle, adding into grids that
     already hold 0.25; particles also sit on tile edges and just below N
-    (wrap-around). 128 points a side runs the 8 x 8 x 64 tiles.
+    (wrap-around). 128 points a side runs the 8 x 8 x 32 tiles.
     Weighted catalogue: FP32 atomics within their summation bound; the
     fixed-point kernels within 2 ulp (one rounding of the node sum, one of the
     addition). Unit weights, positions on multiples of 2^-12: the fixed-point
