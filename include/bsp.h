@@ -465,8 +465,10 @@ bsp_status bsp_batch_run(const bsp_plan* plans, int32_t nplans, const int32_t* m
  * record, appended later, supersedes the old one: the last record of a key
  * and configuration wins). Every other mock runs and is
  * appended to the journal as soon as its outputs are on the host (the host
- * writes mock k while mock k+1 runs), unless a kernel error is latched on its
- * plan, which ends the call with that error. A process killed at any point
+ * writes mock k while mock k+1 runs, through pinned host staging that the call
+ * allocates for two mocks' outputs plus those of the recorded mocks and frees
+ * before it returns), unless a kernel error is latched on its plan, which
+ * ends the call with that error. A process killed at any point
  * leaves a journal whose valid prefix holds whole records only: a torn last
  * record fails its length or checksum test and is cut off by the next call.
  * The file is created if absent and locked exclusively (flock) for the call.
