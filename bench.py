@@ -367,6 +367,23 @@ def batch_leg(B, torch, log_fn, nmocks=256, ncat_per_size=2, seed=4242, tune_db=
         dt = time.perf_counter() - t0
         out[name] = nmocks / dt
         log_fn(f"batch ({name}): {nmocks} mocks in {dt:.3f} s, {nmocks / dt:.1f} mocks/s")
+    # the same batch with the checkpoint journal: a fresh journal (every mock
+    # run and recorded), then the same call again (every mock resumed from it)
+    import tempfile
+    with tempfile.TemporaryDirectory() as td:
+        jpath = os.path.join(td, "batch.bspj")
+        keys = list(range(nmocks))
+        jt = {}
+        for name in ("journal_fresh", "journal_resumed"):
+            t0 = time.perf_counter()
+            nres = B.bsp_batch_run_journal(handles, [int(i) for i in order], keys, ux, uy, uz, None, npl,
+                                           B.BSP_BF16X3, B_all, al, be, cov, jpath, B.BSP_BATCH_GRAPH)
+            plans[0].sync()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            jt[name] = {"mocks_per_s": nmocks / dt, "resumed": nres}
+            log_fn(f"batch ({name}): {nmocks} mocks in {dt:.3f} s, {nmocks / dt:.1f} mocks/s, {nres} resumed")
+        jt["journal_bytes"] = os.path.getsize(jpath)
     # per grid size: 32 mocks of one size through the graph replay
     per_size = {}
     for si, n in enumerate(sizes):
@@ -384,7 +401,7 @@ def batch_leg(B, torch, log_fn, nmocks=256, ncat_per_size=2, seed=4242, tune_db=
     res = {"workload": f"{nmocks} mocks on grids drawn uniformly from {{128,192,256,384}}^3, N'=128, 20 bins dk=2kf, "
                        f"l<=4, 50 modes P=6 (drop tol {MODAL_DROP_TOL}), 3e5 particles each, bf16x3",
            "mocks": nmocks, "mocks_per_s": out["graph"], "mocks_per_s_plain_calls": out["plain"],
-           "graph_over_plain": out["graph"] / out["plain"], "ms_per_mock_by_grid": per_size,
+           "graph_over_plain": out["graph"] / out["plain"], "journal": jt, "ms_per_mock_by_grid": per_size,
            "grids_drawn": {str(sizes[i]): int((order == i).sum()) for i in range(len(sizes))},
            "distinct_catalogues": len(sizes) * ncat_per_size, "kept_modes": int(plans[0].info.modal_rank)}
     for pl in plans:
