@@ -704,7 +704,7 @@ def subvolume_unit_vectors(m: int, origin, observer):
 
 
 def integrated_bispectrum_local_los(delta: np.ndarray, s: int, lmax: int, observer, window, box: float,
-                                    k0: float, dk: float, nb: int):
+                                    k0: float, dk: float, nb: int, subvolumes=None):
     """Integrated bispectrum multipoles of Sec. 3.4 with the power-spectrum
     multipoles of each sub-volume taken as in Sec. 2 (eq. PowSpecMultipole):
     the line of sight x_hat varies over the nodes of the sub-volume.
@@ -718,6 +718,8 @@ def integrated_bispectrum_local_los(delta: np.ndarray, s: int, lmax: int, observ
       P^(l)_i(k_b) = V_s sum_{n in b} Re[delta^(l)_i(n) conj delta^(0)_i(n)] / (M^6 N_b)
             over the full lattice (Hermitian halves counted twice).
     iB^(l) = (1/N_s) sum_i P^(l)_i dbar_i. Bins as integrated_bispectrum.
+    subvolumes: optional list of sub-volume indices to evaluate (the others
+    stay zero in P and dbar, and iB is then not meaningful).
     Returns (iB [nl][nb], P [N_s][nl][nb], dbar [N_s], N_b)."""
     n = delta.shape[0]
     assert n % s == 0 and observer is not None
@@ -740,7 +742,7 @@ def integrated_bispectrum_local_los(delta: np.ndarray, s: int, lmax: int, observ
         tensors += los_tensor_indices(4)
     P = np.zeros((s ** 3, nl, nb))
     dbar = np.zeros(s ** 3)
-    for i in range(s ** 3):
+    for i in (range(s ** 3) if subvolumes is None else subvolumes):
         org = ((i // (s * s)) * m, ((i // s) % s) * m, (i % s) * m)
         sub = delta[org[0]:org[0] + m, org[1]:org[1] + m, org[2]:org[2] + m]
         xh = subvolume_unit_vectors(m, org, observer)

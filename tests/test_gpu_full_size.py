@@ -134,9 +134,11 @@ def test_full_size_modal_numerators(full_case):
 @pytest.fixture(scope="module")
 def spectra_case():
     """The bench plan's LOS moments of a seeded white-noise contrast field
-    (bsp_grid_entry), then the power-spectrum multipoles, skew spectra and
-    integrated bispectrum (8^3 sub-volumes of 64^3, 20 shells of one
-    sub-volume fundamental) on the GPU, and the same from the FP64 oracle."""
+    (bsp_grid_entry), then the power-spectrum multipoles, skew spectra (also
+    with the squared monopole on the ball of the band) and integrated
+    bispectrum (8^3 sub-volumes of 64^3, 20 shells of one sub-volume
+    fundamental; one line of sight per sub-volume and varying inside each) on
+    the GPU, and the same from the FP64 oracle."""
     t0 = time.time()
     wl = C.workload("c3_512")
     n = wl.n
@@ -153,11 +155,17 @@ def spectra_case():
     s, ibn = 8, 20
     iB = torch.zeros((info.nl, ibn), dtype=torch.float64, device=DEV)
     Ps = torch.zeros((s ** 3, info.nl, ibn), dtype=torch.float64, device=DEV)
+    Sb = torch.zeros_like(S)
+    iBl = torch.zeros_like(iB)
+    Psl = torch.zeros_like(Ps)
     B.bsp_power_multipoles(plan.handle, dl, P)
     B.bsp_skew_spectra(plan.handle, dl, S)
+    B.bsp_skew_spectra(plan.handle, dl, Sb, B.BSP_SKEW_BALL)
     B.bsp_integrated_bispectrum(plan.handle, dd, None, s, 1.0, 1.0, ibn, iB, Ps, None)
+    B.bsp_integrated_bispectrum(plan.handle, dd, None, s, 1.0, 1.0, ibn, iBl, Psl, None, B.BSP_IB_LOCAL_LOS)
     plan.sync()
-    got = (P.cpu().numpy(), S.cpu().numpy(), iB.cpu().numpy(), Ps.cpu().numpy())
+    got = (P.cpu().numpy(), S.cpu().numpy(), iB.cpu().numpy(), Ps.cpu().numpy(), Sb.cpu().numpy(),
+           iBl.cpu().numpy(), Psl.cpu().numpy())
     del dd, dl
     plan.close()
     torch.cuda.empty_cache()
@@ -167,15 +175,21 @@ def spectra_case():
     spec = O.spectrum_from_field([d64], [0.0], n, 4, obs, None)
     Pref, _ = O.power_multipoles(spec, n, wl.k0, wl.dk, wl.nbins, wl.box)
     Sref, _ = O.skew_spectra(spec, n, n, wl.k0, wl.dk, wl.nbins, wl.box)
+    Sbref, _ = O.skew_spectra(spec, n, n, wl.k0, wl.dk, wl.nbins, wl.box, "ball")
     del spec
     iBref, Psref, dbar, _ = O.integrated_bispectrum(d64, s, 4, obs, 1, wl.box, 1.0, 1.0, ibn)
-    say("spectra oracle", time.time() - t0)
-    return got, (Pref, Sref, iBref, Psref, dbar)
+    say("spectra oracle, one LOS per sub-volume", time.time() - t0)
+    # the local line of sight on 24 sampled sub-volumes (corners, centre, seeded picks)
+    picks = sorted({0, s ** 3 - 1, s ** 3 // 2, s * s - 1, s ** 3 - s * s} |
+                   set(np.random.Generator(np.random.PCG64(77)).choice(s ** 3, 19, replace=False).tolist()))
+    _, Pslref, _, _ = O.integrated_bispectrum_local_los(d64, s, 4, obs, 1, wl.box, 1.0, 1.0, ibn, picks)
+    say("spectra oracle, local LOS on", len(picks), "sub-volumes", time.time() - t0)
+    return got, (Pref, Sref, iBref, Psref, dbar, Sbref, picks, Pslref)
 
 
 def test_full_size_power_and_skew_spectra(spectra_case):
-    (P, S, _, _), (Pref, Sref, _, _, _) = spectra_case
-    for name, g, r, tol in (("P", P, Pref, 1e-5), ("S", S, Sref, 1e-5)):
+    (P, S, _, _, Sb, _, _), (Pref, Sref, _, _, _, Sbref, _, _) = spectra_case
+    for name, g, r, tol in (("P", P, Pref, 1e-5), ("S", S, Sref, 1e-5), ("S ball", Sb, Sbref, 1e-5)):
         s0 = np.linalg.norm(r[0])
         for li in range(r.shape[0]):
             e = np.linalg.norm(g[li] - r[li]) / max(np.linalg.norm(r[li]), 0.01 * s0)
@@ -184,7 +198,7 @@ def test_full_size_power_and_skew_spectra(spectra_case):
 
 
 def test_full_size_integrated_bispectrum(spectra_case):
-    (_, _, iB, Ps), (_, _, iBref, Psref, dbar) = spectra_case
+    (_, _, iB, Ps, _, _, _), (_, _, iBref, Psref, dbar, _, _, _) = spectra_case
     ns = Ps.shape[0]
     for li in range(iB.shape[0]):
         e = np.linalg.norm(Ps[:, li] - Psref[:, li]) / max(np.linalg.norm(Psref[:, li]),
@@ -193,6 +207,24 @@ def test_full_size_integrated_bispectrum(spectra_case):
         ei = np.linalg.norm(iB[li] - iBref[li]) / scale
         say("iB l", 2 * li, "P err", e, "iB err / term scale", ei)
         assert e < 1e-5 and ei < 1e-5, (li, e, ei)
+
+
+def test_full_size_integrated_bispectrum_local_los(spectra_case):
+    """Sub-volume multipoles with the line of sight varying inside each, on
+    sampled sub-volumes (the oracle evaluates them one by one); the average
+    iB uses every sub-volume and is checked against the GPU's P with the
+    oracle's mean overdensities."""
+    (_, _, _, _, _, iBl, Psl), (_, _, _, _, dbar, _, picks, Pslref) = spectra_case
+    for li in range(Psl.shape[1]):
+        g, r = Psl[picks, li], Pslref[picks, li]
+        e = np.linalg.norm(g - r) / max(np.linalg.norm(r), 0.01 * np.linalg.norm(Pslref[picks, 0]))
+        say("local LOS P l", 2 * li, "err on", len(picks), "sub-volumes", e)
+        assert e < 1e-5, (li, e)
+    ns = Psl.shape[0]
+    for li in range(Psl.shape[1]):
+        avg = Psl[:, li].T @ dbar / ns
+        scale = np.linalg.norm(np.abs(Psl[:, li]).T @ np.abs(dbar)) / ns
+        assert np.linalg.norm(iBl[li] - avg) < 1e-5 * scale, li
 
 
 @pytest.fixture(scope="module")

@@ -560,7 +560,9 @@ def test_grid_entry_against_oracle():
     for li in range(3):
         idx, vals, _ = compact_to_half(got[li], n, info.c, info.cz, info.n2max)
         ref = np.where((idx[0] == 0) & (idx[1] == 0) & (idx[2] == 0), 0, spec[li][idx])
-        assert rel_norm(np.stack([vals.real, vals.imag]), np.stack([ref.real, ref.imag])) < 2e-5
+        e = rel_norm(np.stack([vals.real, vals.imag]), np.stack([ref.real, ref.imag]))
+        say("  l", 2 * li, "err", e)
+        assert e < 2e-5, (li, e)
 
 
 # ---------------------------------------------------------------- filtered fields
