@@ -53,6 +53,27 @@ hipError_t launch_fill_u32(void* p, uint32_t v, int64_t words, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Fills n floats with values uniform in [-1, 1) from a counter hash of the
+// index (the autotuner times the reduction on such fields: matrix units draw
+// more power, and run at lower clocks, on varying operands than on constants).
+__global__ __launch_bounds__(256) void k_fill_noise(float* __restrict__ p, int64_t n, uint32_t seed) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t h = (uint64_t)i * 0x9e3779b97f4a7c15ull + seed;
+    h ^= h >> 31;
+    h *= 0xbf58476d1ce4e5b9ull;
+    h ^= h >> 29;
+    p[i] = (float)(int32_t)(uint32_t)(h >> 32) * 4.656612873077393e-10f;
+  }
+}
+
+hipError_t launch_fill_noise(float* p, int64_t n, uint32_t seed, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(k_fill_noise, dim3((unsigned)blocks), dim3(256), 0, s, p, n, seed);
+  return hipGetLastError();
+}
+
 // wmax_bits[0] = max |w| over the finite weights, as FP32 bits (|w| >= 0, so the
 // integer order of the bits is the order of the values).
 __global__ __launch_bounds__(256) void k_weight_max(const float* __restrict__ w, const int64_t* __restrict__ npd,

@@ -184,6 +184,7 @@ bool fft_size_supported(int n);
 size_t assign_fixed_bytes(int n, int interlace);
 // Fills `words` 32-bit words with v by a kernel (capturable, unlike a memset node).
 hipError_t launch_fill_u32(void* p, uint32_t v, int64_t words, hipStream_t s);
+hipError_t launch_fill_noise(float* p, int64_t n, uint32_t seed, hipStream_t s);
 // npd (optional): a device-side particle count the kernels read instead of np
 // (then np only bounds the launch grids and the scratch), so that a captured
 // graph can be replayed on catalogues of other sizes.
