@@ -139,7 +139,10 @@ typedef struct {
 
 /* Validates the geometry (BSP_ERR_ARG, BSP_ERR_SIZE, BSP_ERR_ALIAS) and builds
  * the constant tables. basis may be NULL (no modal output). stream is a
- * hipStream_t (NULL: default stream). */
+ * hipStream_t (NULL: default stream). With los = 1 the observer must be finite
+ * and must not sit on a node of either grid (node j of the grid at shift s is
+ * the point j - s), where x_hat is undefined: BSP_ERR_ARG, before any device
+ * work. */
 bsp_status bsp_plan_create(bsp_plan* plan, const bsp_geom* geom, const bsp_modal_basis* basis, void* stream);
 bsp_status bsp_plan_destroy(bsp_plan plan);
 bsp_status bsp_plan_info(bsp_plan plan, bsp_info* info /*host*/);
@@ -381,7 +384,8 @@ bsp_status bsp_skew_spectra(bsp_plan plan, const void* delta_l, double* S, int32
  * (1, 6 or 15 batched transforms of all sub-volumes, one after another) by
  * the addition theorem; about one more N^3 floats of workspace. For
  * plane-parallel plans both readings are the same and the flag is ignored.
- * Any other flag bit: BSP_ERR_ARG. */
+ * Any other flag bit: BSP_ERR_ARG; so is an observer at the centre of a
+ * sub-volume with the one-LOS reading (its direction is undefined). */
 #define BSP_IB_LOCAL_LOS 1
 bsp_status bsp_integrated_bispectrum(bsp_plan plan, const float* grid, const double* wsum, int32_t s, double k0,
                                      double dk, int32_t nbins, double* iB, double* Psub, double* dbar,

@@ -1156,6 +1156,21 @@ bsp_status bsp_plan_create(bsp_plan* out, const bsp_geom* g, const bsp_modal_bas
   if (g->nbins < 1 || g->nbins > 64) return fail(p, BSP_ERR_ARG, "nbins must be in [1, 64]");
   if (!(g->box > 0) || !(g->dk > 0)) return fail(p, BSP_ERR_ARG, "box and dk must be positive");
   if (g->window != 0 && g->window != 1) return fail(p, BSP_ERR_ARG, "window must be 0 or 1");
+  if (g->los != 0 && g->los != 1) return fail(p, BSP_ERR_ARG, "los must be 0 or 1");
+  if (g->los == 1) {
+    // x_hat is undefined at the observer: it must not sit on a node of either grid
+    // (node j of the grid built at shift s represents the point j - s)
+    for (int a = 0; a < 3; ++a)
+      if (!std::isfinite(g->observer[a])) return fail(p, BSP_ERR_ARG, "observer must be finite");
+    for (int gi = 0; gi <= (g->interlace ? 1 : 0); ++gi) {
+      bool on_node = true;
+      for (int a = 0; a < 3; ++a) {
+        const double j = g->observer[a] + 0.5 * gi;
+        on_node = on_node && std::fabs(j - std::rint(j)) < 1e-9 && std::rint(j) >= 0 && std::rint(j) < g->n;
+      }
+      if (on_node) return fail(p, BSP_ERR_ARG, "observer on a grid node (its line of sight is undefined)");
+    }
+  }
   const double e0 = 2.0 * g->k0 - g->dk;
   if (std::fabs(2.0 * g->k0 - std::rint(2.0 * g->k0)) > 1e-9 || std::fabs(g->dk - std::rint(g->dk)) > 1e-9 || e0 <= 0)
     return fail(p, BSP_ERR_ARG, "2 k0 and dk must be integers with k0 > dk/2");
@@ -2295,6 +2310,15 @@ bsp_status bsp_integrated_bispectrum(bsp_plan p, const float* grid, const double
   if (N % s != 0) return fail(p, BSP_ERR_SIZE, "s must divide N");
   const int m = N / s, ns = s * s * s;
   if (!fft_size_supported(m) || m % 4 != 0) return fail(p, BSP_ERR_SIZE, "unsupported sub-volume size N / s");
+  if (!p->plane && !(flags & BSP_IB_LOCAL_LOS)) {
+    // the one line of sight of a sub-volume points at its centre, origin + (M - 1)/2
+    bool at_centre = true;
+    for (int a = 0; a < 3; ++a) {
+      const double u = (p->g.observer[a] - 0.5 * (m - 1)) / m;
+      at_centre = at_centre && std::fabs(u - std::rint(u)) < 1e-12 && std::rint(u) >= 0 && std::rint(u) < s;
+    }
+    if (at_centre) return fail(p, BSP_ERR_ARG, "observer at a sub-volume centre (its line of sight is undefined)");
+  }
   if (ns > 65535) return fail(p, BSP_ERR_SIZE, "too many sub-volumes");
   // sub-volume shells (units of 2 pi s / L): (2 c_b - dk)^2 <= 4 n^2 < (2 c_b + dk)^2, 2 k0 and dk integers
   std::vector<int64_t> lo(nbins), hi(nbins);

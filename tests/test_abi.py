@@ -34,6 +34,8 @@ def _geom(**kw):
              k0=2.0, dk=2.0)
     d.update(kw)
     for k, v in d.items():
+        if k == "observer":
+            v = (ctypes.c_double * 3)(*v)
         setattr(g, k, v)
     return g
 
@@ -47,12 +49,30 @@ def _geom(**kw):
     (dict(box=-1.0), 1),
     (dict(n=64, n_reduce=48), 2),        # 48 is not a supported size
     (dict(n=128, n_reduce=32, nbins=6), 3),  # c = 13: 3c >= 32
+    (dict(los=2), 1),                    # los must be 0 or 1
+    (dict(los=1, observer=(32.0, 32.0, 32.0)), 1),            # observer on a node: x_hat undefined
+    (dict(los=1, interlace=1, observer=(31.5, 7.5, 0.5)), 1),  # on a node of the shifted grid
+    (dict(los=1, observer=(float("nan"), 0.0, -100.0)), 1),
 ])
 def test_plan_create_rejects_invalid_geometry(kw, status):
     with pytest.raises(B.BspError) as e:
         B.bsp_plan_create(_geom(**kw))
     assert e.value.status == status
     assert B.lib().bsp_last_error(None)
+
+
+def test_plan_create_accepts_observer_off_the_nodes():
+    """The same positions are fine where no node sits: half-integers without
+    interlacing, outside the grid, or off the lattice in one coordinate (the
+    check runs before any device work, so only its verdict is looked at)."""
+    for kw in (dict(los=1, observer=(31.5, 7.5, 0.5)), dict(los=1, observer=(-32.0, 32.0, 32.0)),
+               dict(los=1, interlace=1, observer=(32.0, 32.0, 32.25))):
+        try:
+            B.bsp_plan_destroy(B.bsp_plan_create(_geom(**kw)))
+        except B.BspError as e:
+            assert "observer" not in str(e), (kw, str(e))
+        except Exception:  # no GPU here: plan creation stops at its first device call
+            pass
 
 
 def test_modal_basis_validation():

@@ -489,6 +489,21 @@ def test_integrated_bispectrum_local_los_plane_parallel_and_flags():
     plan.close()
 
 
+def test_integrated_bispectrum_rejects_observer_at_a_subvolume_centre():
+    """The one line of sight of a sub-volume points at its centre: an observer
+    there has none (BSP_ERR_ARG); the local reading needs only the nodes."""
+    n, s, nb = 32, 2, 4
+    plan = B.Plan(n=n, box=150.0, nbins=2, k0=2.0, dk=2.0, lmax=2, los=1, observer=np.array([7.5, 7.5, 7.5]))
+    g = torch.zeros((1, n, n, n), dtype=torch.float32, device=DEV)
+    iB = torch.zeros((2, nb), dtype=torch.float64, device=DEV)
+    with pytest.raises(B.BspError) as e:
+        B.bsp_integrated_bispectrum(plan.handle, g, None, s, 1.0, 1.0, nb, iB)
+    assert e.value.status == 1
+    B.bsp_integrated_bispectrum(plan.handle, g, None, s, 1.0, 1.0, nb, iB, None, None, B.BSP_IB_LOCAL_LOS)
+    plan.sync()
+    plan.close()
+
+
 def test_integrated_bispectrum_rejects_bad_geometry():
     plan = B.Plan(n=32, box=100.0, nbins=2, k0=2.0, dk=2.0)
     g = torch.zeros((1, 32, 32, 32), dtype=torch.float32, device=DEV)
