@@ -64,7 +64,7 @@ def test_plan_create_rejects_invalid_geometry(kw, status):
 def test_plan_create_accepts_observer_off_the_nodes():
     """The same positions are fine where no node sits: half-integers without
     interlacing, outside the grid, or off the lattice in one coordinate (the
-    check runs before any device work, so only its verdict is looked at)."""
+    check runs before any device work, so only its outcome is looked at)."""
     for kw in (dict(los=1, observer=(31.5, 7.5, 0.5)), dict(los=1, observer=(-32.0, 32.0, 32.0)),
                dict(los=1, interlace=1, observer=(32.0, 32.0, 32.25))):
         try:
