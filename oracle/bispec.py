@@ -38,7 +38,7 @@ import scipy.fft as sfft
 
 __all__ = [
     "signed_freq", "assign", "density_contrast", "los_tensor_indices",
-    "los_weighted_field", "forward", "compensate", "interlace_combine",
+    "los_weighted_field", "forward", "dft_modes", "compensate", "interlace_combine",
     "legendre_moments", "legendre_moments_direct", "bin_edges4", "bin_of_n2",
     "n2_grid_half", "shell_field", "triangle_list", "triangle_counts_fft",
     "triangle_counts_brute", "closed_triangle_sum_brute", "binned_triple_sums", "binned_triple_sums_full",
@@ -158,6 +158,23 @@ def los_weighted_field(delta: np.ndarray, t: Tuple[int, ...], xhat) -> np.ndarra
 def forward(field: np.ndarray) -> np.ndarray:
     """Unnormalised forward real-to-half-complex DFT, exp(-2 pi i n.j / N)."""
     return sfft.rfftn(field, workers=WORKERS)
+
+
+def dft_modes(field: np.ndarray, modes) -> np.ndarray:
+    """The forward DFT of the definition, F(m) = sum_j f(j) exp(-2 pi i m.j / N),
+    at a few integer wavevectors m [M, 3] (any sign), in FP64: the sum over z
+    for all M at once (x-blocks of the cube), then over y and x per mode. For
+    grids too large for a whole transform (sampled parity)."""
+    n = field.shape[0]
+    m = np.asarray(modes, np.int64).reshape(-1, 3)
+    j = np.arange(n, dtype=np.int64)
+    ph = lambda a: np.exp(-2j * np.pi * (np.outer(j, m[:, a]) % n) / n)  # [n, M]
+    ez, ey, ex = ph(2), ph(1), ph(0)
+    G = np.empty((n, n, len(m)), np.complex128)
+    for x0 in range(0, n, 32):
+        blk = np.asarray(field[x0:x0 + 32], np.float64)
+        G[x0:x0 + 32] = blk @ ez.real + 1j * (blk @ ez.imag)
+    return np.array([ex[:, i] @ G[:, :, i] @ ey[:, i] for i in range(len(m))])
 
 
 def window_half(n: int, window: int) -> np.ndarray:
