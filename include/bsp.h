@@ -58,12 +58,12 @@ typedef struct bsp_plan_s* bsp_plan;
 typedef enum {
   BSP_OK = 0,
   BSP_ERR_ARG = 1,       /* null or inconsistent argument */
-  BSP_ERR_SIZE = 2,      /* grid size without a transform kernel (supported: 16,32,64,96,128,192,256,384,512) */
+  BSP_ERR_SIZE = 2,      /* grid size without a transform kernel (supported: 16,32,64,96,128,192,256,384,512,1024) */
   BSP_ERR_ALIAS = 3,     /* 3 c >= N': closed triangles would wrap on the N' grid */
   BSP_ERR_WORKSPACE = 4, /* no workspace, or smaller than bsp_workspace_size */
   BSP_ERR_HIP = 5,       /* HIP runtime error (message in bsp_last_error) */
   BSP_ERR_DEVICE = 6,    /* latched by a kernel: particle outside [0,N) or not finite */
-  BSP_ERR_NUMERIC = 7,   /* latched: triangle count residual >= 0.05, or Cholesky failure */
+  BSP_ERR_NUMERIC = 7,   /* latched: triangle count residual above its bound (see bsp_precompute), or Cholesky failure */
   BSP_ERR_STATE = 8,     /* call out of order */
   BSP_ERR_IO = 9         /* batch journal could not be opened, read, locked or written */
 } bsp_status;
@@ -132,7 +132,7 @@ typedef struct {
   int32_t tune_tiles;     /* short-line transform tiles (0: the rule, 1: 16, 2: 64 columns) */
   int64_t tune_kchunk;    /* main reduction chunk length (0: the rule) */
   int32_t reduce_row_tiles; /* row tiles of 16 pair slots (pairs that meet a needed third) */
-  int32_t reserved0;
+  int32_t slab_planes;    /* x planes of N' per slab of the field stacks (N': whole cubes; bsp_set_slab) */
 } bsp_info;
 
 /* ---------------------------------------------------------------- plans */
@@ -152,12 +152,28 @@ const char* bsp_last_error(bsp_plan plan);
 bsp_status bsp_workspace_size(bsp_plan plan, size_t* bytes /*host*/);
 /* Workspace: device pointer, 256-byte aligned, at least bsp_workspace_size bytes. */
 bsp_status bsp_set_workspace(bsp_plan plan, void* dev, size_t bytes);
+/* Field stacks in x-slabs. The triple sum over x is additive, so the
+ * estimators (and bsp_precompute) make the filtered real fields of one slab of
+ * `planes` x planes at a time, reduce it, and add its sums to T in slab order:
+ * the stacks need planes / N' of the whole fields' memory (at 1024^3 the 114
+ * FP32 fields of three multipoles, 30 shells and 8 modal functions take 490 GB
+ * whole, 122 GB in slabs of 256 planes). The first inverse pass runs once per
+ * slab (it transforms along x), so fewer, thicker slabs are faster. planes must
+ * divide N'; 0 restores the plan's default, chosen at bsp_plan_create: N' when
+ * the FP32 main stack and the FP64 precompute stack each fit in 128 GiB, else
+ * the largest power-of-two fraction of N' for which both do. The results agree with whole cubes to the
+ * rounding of the FP64 sums of T (the slabs add in another order). Changes
+ * bsp_workspace_size; call it between runs (it waits for the plan's streams
+ * and drops a captured batch graph). */
+bsp_status bsp_set_slab(bsp_plan plan, int32_t planes);
 /* Waits for the plan's stream; returns the first latched device error. */
 bsp_status bsp_sync(bsp_plan plan);
 
 /* Geometry-only FP64 precompute on the GPU (once per plan): triangle counts
  * V_B(k1,k2,k3) of the standard estimator as round(sum_x I I I / N'^3) with
- * I_b the inverse DFT of the shell indicator (residual < 0.05 checked), and, with a
+ * I_b the inverse DFT of the shell indicator (the residual from an integer must
+ * stay below 0.05 + 32 eps log2(N'^3) |count|, eps = 2^-53, the FP64 transforms'
+ * rounding, and that bound below 0.5; else BSP_ERR_NUMERIC), and, with a
  * modal basis, the lattice Gram matrix gamma_nm = <<Q_n|Q_m>> of eqs.
  * (betaCalc, innerProduct), its Cholesky factor, and the Poisson shot-noise
  * integrals of the modal numerators. Needs the workspace. Synchronises. */
@@ -495,7 +511,8 @@ bsp_status bsp_batch_run_journal(const bsp_plan* plans, int32_t nplans, const in
 /* Configuration hash under which the journal records a mock of this plan at
  * precision prec: a 64-bit FNV-1a hash of the geometry, the modal basis
  * (functions, modes, P_fid, drop tolerance), the kept modes, the triangles,
- * the precision and the journal format. Host output. Needs bsp_precompute
+ * the precision, the slab planes when they are not all of N' (bsp_set_slab)
+ * and the journal format. Host output. Needs bsp_precompute
  * (BSP_ERR_STATE). Plans of different N hash differently. */
 bsp_status bsp_config_hash(bsp_plan plan, bsp_precision prec, uint64_t* hash /*host*/);
 

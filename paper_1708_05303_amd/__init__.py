@@ -18,7 +18,7 @@ import numpy as np
 __all__ = [
     "BspError", "BspLibraryMissing", "Geom", "ModalBasis", "Info", "lib", "Plan",
     "BSP_FP32", "BSP_BF16X3", "BSP_FP16X3", "BSP_BF16X1", "PRECISIONS", "bsp_plan_create", "bsp_plan_destroy",
-    "bsp_plan_info", "bsp_workspace_size", "bsp_set_workspace", "bsp_sync", "bsp_precompute", "bsp_autotune",
+    "bsp_plan_info", "bsp_workspace_size", "bsp_set_workspace", "bsp_set_slab", "bsp_sync", "bsp_precompute", "bsp_autotune",
     "BSP_TUNE_FORCE",
     "bsp_geometry", "bsp_grid_assign", "bsp_grid_assign_noalloc", "bsp_fft_r2c", "bsp_fft_c2r",
     "bsp_los_moments", "bsp_grid_entry", "bsp_filter_fields", "bsp_triple_reduce", "bsp_modal_coeffs", "bsp_bispectrum_multipoles",
@@ -41,7 +41,7 @@ STATUS = {0: "BSP_OK", 1: "BSP_ERR_ARG", 2: "BSP_ERR_SIZE", 3: "BSP_ERR_ALIAS", 
 # every symbol include/bsp.h declares
 EXPORTED = [
     "bsp_plan_create", "bsp_plan_destroy", "bsp_plan_info", "bsp_last_error", "bsp_workspace_size",
-    "bsp_set_workspace", "bsp_sync", "bsp_precompute", "bsp_autotune", "bsp_geometry", "bsp_grid_assign",
+    "bsp_set_workspace", "bsp_set_slab", "bsp_sync", "bsp_precompute", "bsp_autotune", "bsp_geometry", "bsp_grid_assign",
     "bsp_grid_assign_noalloc", "bsp_fft_r2c",
     "bsp_fft_c2r", "bsp_los_moments", "bsp_grid_entry", "bsp_filter_fields", "bsp_triple_reduce",
     "bsp_modal_coeffs", "bsp_bispectrum_multipoles", "bsp_bispectrum_field", "bsp_batch_run",
@@ -83,7 +83,7 @@ class Info(C.Structure):
                 ("reduce_tiles", C.c_int32), ("reduce_groups", C.c_int32), ("reduce_maxr", C.c_int32),
                 ("reduce_maxcw", C.c_int32), ("reduce_needed", C.c_int64), ("modal_rank", C.c_int32),
                 ("tune_shape", C.c_int32), ("tune_tiles", C.c_int32), ("tune_kchunk", C.c_int64),
-                ("reduce_row_tiles", C.c_int32), ("reserved0", C.c_int32)]
+                ("reduce_row_tiles", C.c_int32), ("slab_planes", C.c_int32)]
 
 
 _lib = None
@@ -104,6 +104,7 @@ def lib():
         "bsp_plan_info": [_vp, C.POINTER(Info)],
         "bsp_workspace_size": [_vp, C.POINTER(C.c_size_t)],
         "bsp_set_workspace": [_vp, _vp, C.c_size_t],
+        "bsp_set_slab": [_vp, C.c_int32],
         "bsp_sync": [_vp],
         "bsp_precompute": [_vp],
         "bsp_autotune": [_vp, _i32, C.c_char_p, _i32],
@@ -196,6 +197,11 @@ def bsp_workspace_size(plan) -> int:
 
 def bsp_set_workspace(plan, ws, nbytes: int):
     _check(lib().bsp_set_workspace(plan, _dptr(ws), nbytes), plan)
+
+
+def bsp_set_slab(plan, planes: int):
+    """x planes per slab of the field stacks (0: the plan's default)."""
+    _check(lib().bsp_set_slab(plan, int(planes)), plan)
 
 
 def bsp_sync(plan):
@@ -425,7 +431,7 @@ class Plan:
 
     def __init__(self, n, box, nbins, k0, dk, lmax=0, n_reduce=0, window=1, compensate=1, interlace=0, los=0,
                  observer=(0.0, 0.0, 0.0), P=0, nmodes=0, modes=None, pfid=None, drop_tol=0.0, device="cuda:0",
-                 workspace=True):
+                 workspace=True, slab=0):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -452,6 +458,8 @@ class Plan:
             self.P = P
         self.stream = torch.cuda.current_stream(self.device)
         self.handle = bsp_plan_create(g, self.basis, self.stream.cuda_stream)
+        if slab:
+            bsp_set_slab(self.handle, slab)
         self.info = bsp_plan_info(self.handle)
         self.ws = None
         if workspace:

@@ -330,6 +330,7 @@ struct bsp_plan_s {
   int32_t* d_err = nullptr;
   int32_t* d_ints = nullptr;  // field_ell / field_tab for the main and precompute passes
   int F = 0;                  // fields of the main pipeline
+  int slab = 0;               // x planes of N' per slab of the field stacks (N': whole cubes)
   std::vector<int> row_c;     // largest |n_a| kept by each filter table row (tab64 row numbering)
   // per tab32 row: modes of the compact half cube the filter keeps, and the
   // (n_y, n_z) columns it leaves nonzero (algorithmic bytes of the inverse passes)
@@ -531,9 +532,32 @@ struct Layout {
   int fb64;
 };
 
-size_t inv_scratch(const bsp_plan p, int fb, size_t celem) {
+// x planes per slab of the field stacks: all of N' when the FP32 main stack
+// and the FP64 precompute stack each stay within kSlabCap bytes, else the
+// largest power-of-two fraction of N' for which both do.
+constexpr size_t kSlabCap = 128ull << 30;
+int default_slab(const bsp_plan p) {
+  const size_t plane = (size_t)p->Nr * p->Nr;
+  const size_t nfp = std::max({p->nbins, p->modal ? p->nU : 0, p->modal ? 2 * p->P : 0});
+  int S = p->Nr;
+  while (S % 2 == 0 && S > 8 && ((size_t)p->F * S * plane * 4 > kSlabCap || nfp * S * plane * 8 > kSlabCap)) S /= 2;
+  return S;
+}
+
+// Relative part of the triangle counts' residual bound. The counts are
+// sum_x I_b1 I_b2 I_b3 / N'^3 with FP64 shell fields whose values near x = 0 are
+// the coherent sums N_b; the product there is of the order of the count times
+// N'^3, so the rounding of the FP64 transforms (about eps log2(N'^3) relative
+// each) leaves an error proportional to the count. Measured: 0.11 on 2.9e12 at
+// 1024^3 and about 1e-3 on 3e10 at 512^3, 10-11 eps log2(N'^3) |count|; the
+// bound takes 32.
+double count_rel_tol(int64_t K) { return 32.0 * std::ldexp(1.0, -53) * std::log2((double)K); }
+
+// Scratch of the inverse passes of fb fields over an x-slab of S planes: the
+// x pass output [fb][S][2c+1][cz] and the y pass output [fb][S][N'][cz].
+size_t inv_scratch(const bsp_plan p, int fb, int S, size_t celem) {
   const size_t w = 2 * (size_t)p->c + 1;
-  return align_up((size_t)fb * p->Nr * w * p->cz * celem) + align_up((size_t)fb * p->Nr * p->Nr * p->cz * celem);
+  return align_up((size_t)fb * S * w * p->cz * celem) + align_up((size_t)fb * S * p->Nr * p->cz * celem);
 }
 
 Layout layout(const bsp_plan p) {
@@ -541,7 +565,8 @@ Layout layout(const bsp_plan p) {
   const size_t w = 2 * (size_t)p->c + 1;
   const size_t N = p->N, Nr = p->Nr;
   L.dl = align_up((size_t)p->nl * p->spec * sizeof(float2));
-  L.fields = align_up((size_t)p->F * Nr * Nr * Nr * sizeof(float));
+  const size_t S = p->slab;
+  L.fields = align_up((size_t)p->F * S * Nr * Nr * sizeof(float));
   L.T = align_up(std::max<size_t>((size_t)p->main_rp.npairs * p->main_rp.nthirds, 1) * sizeof(double));
   L.small = align_up(4096 * sizeof(double) + (size_t)(p->F + 64) * sizeof(float));
   L.s_grid = align_up((size_t)p->ngrid * N * N * N * sizeof(float));
@@ -549,34 +574,36 @@ Layout layout(const bsp_plan p) {
   L.s_Y = align_up((size_t)p->ngrid * p->nlos * N * w * p->cz * sizeof(float2));
   const size_t fwd = L.s_grid + L.s_Z + L.s_Y;
   int fb = 2;
-  while (fb + 2 <= std::max(p->F, 2) && inv_scratch(p, fb + 2, sizeof(float2)) <= std::max<size_t>(fwd, 1ull << 31))
+  while (fb + 2 <= std::max(p->F, 2) && inv_scratch(p, fb + 2, p->slab, sizeof(float2)) <= std::max<size_t>(fwd, 1ull << 31))
     fb += 2;
   L.fb = fb;
   size_t part = 0;
   if (p->main_rp.ntiles)
     for (int prec = 0; prec < 3; ++prec)
-      part = std::max(part, partial_bytes(p->main_rp, (int64_t)Nr * Nr * Nr, prec, sizeof(float)));
+      part = std::max(part, partial_bytes(p->main_rp, (int64_t)S * Nr * Nr, prec, sizeof(float)));
   const size_t fullc2r = align_up((size_t)N * N * (N / 2 + 1) * sizeof(float2));
   // the grids plus the int64 node sums of the fixed-point assignment
   const size_t fixed = L.s_grid + align_up(assign_fixed_bytes(p->N, p->ngrid - 1));
-  L.scratch = std::max({fwd, inv_scratch(p, fb, sizeof(float2)), align_up(part) + align_up(1 << 20), fullc2r, fixed});
+  // (two whole-cube fields: the single-field inverse of the skew spectra)
+  L.scratch = std::max({fwd, inv_scratch(p, fb, p->slab, sizeof(float2)), inv_scratch(p, 2, p->Nr, sizeof(float2)),
+                        align_up(part) + align_up(1 << 20), fullc2r, fixed});
   L.total = L.dl + L.fields + L.T + L.small + L.scratch;
   // FP64 precompute
   const int nfp = std::max({p->nbins, p->modal ? p->nU : 0, p->modal ? 2 * p->P : 0});
   L.pre_ones = align_up((size_t)p->spec * sizeof(double2));
-  L.pre_fields = align_up((size_t)nfp * Nr * Nr * Nr * sizeof(double));
+  L.pre_fields = align_up((size_t)nfp * S * Nr * Nr * sizeof(double));
   L.pre_T = align_up((size_t)4096 * 128 * sizeof(double));
   int fb64 = 2;
-  while (fb64 + 2 <= std::max(nfp, 2) && inv_scratch(p, fb64 + 2, sizeof(double2)) <= std::max<size_t>(fwd, 1ull << 31))
+  while (fb64 + 2 <= std::max(nfp, 2) && inv_scratch(p, fb64 + 2, p->slab, sizeof(double2)) <= std::max<size_t>(fwd, 1ull << 31))
     fb64 += 2;
   L.fb64 = fb64;
-  const int64_t K = (int64_t)Nr * Nr * Nr;
+  const int64_t K = (int64_t)S * Nr * Nr;
   size_t part64 = partial_bytes(p->cnt_rp, K, 3, sizeof(double));
   if (p->modal)
     part64 = std::max({part64, partial_bytes(p->gram_rp, K, 3, sizeof(double)),
                        partial_bytes(p->sn_rp, K, 3, sizeof(double))});
   part64 = align_up(std::max<size_t>(part64, p->cand.size() * 2 * sizeof(int64_t) + ALIGN));
-  L.pre_scratch = std::max(inv_scratch(p, fb64, sizeof(double2)), part64 + align_up(1 << 20));
+  L.pre_scratch = std::max(inv_scratch(p, fb64, p->slab, sizeof(double2)), part64 + align_up(1 << 20));
   L.pre_total = L.pre_ones + L.pre_fields + L.pre_T + L.pre_scratch;
   return L;
 }
@@ -737,15 +764,20 @@ std::vector<int32_t> row_ranges(const std::vector<T>& tab, int tl) {
 // field_ell / field_tab index the filter of each output field; cf[f] is the
 // largest |n_a| the filter of field f keeps. A batch of fields is transformed
 // on the band |n_a| <= c_b of its widest filter, so narrow shells move little data.
+// Only the x-slab x0 <= x < x0 + S of each field is made (S = N': the whole
+// cube): the x pass keeps the S output rows of the slab, the y and z passes
+// run on those rows alone, and out holds [nf][S][N'][N'].
 template <typename T>
 bsp_status inverse_fields(bsp_plan p, const cplx_t<T>* src, int64_t src_ell_stride, int nf,
                           const int32_t* d_field_ell, const int32_t* d_field_tab, const T* tables,
                           const int32_t* row_range, T* out, char* scratch, int fb, const std::vector<int>& cf,
-                          const int32_t* frow32 = nullptr) {
+                          const int32_t* frow32 = nullptr, int x0 = 0, int S = 0) {
   const int Nr = p->Nr, c = p->c, cz = p->cz, w = 2 * c + 1;
+  if (S == 0) S = Nr;
+  if (S < 1 || x0 < 0 || x0 + S > Nr) return fail(p, BSP_ERR_ARG, "x-slab outside the grid");
   using V = cplx_t<T>;
   V* Xb = reinterpret_cast<V*>(scratch);
-  V* Yb = reinterpret_cast<V*>(scratch + align_up((size_t)fb * Nr * w * cz * sizeof(V)));
+  V* Yb = reinterpret_cast<V*>(scratch + align_up((size_t)fb * S * w * cz * sizeof(V)));
   for (const auto& bt : inverse_batches(nf, fb, Nr, cf)) {
     const int f0 = bt[0], nb = bt[1] - bt[0];
     int cb = 0;
@@ -767,7 +799,7 @@ bsp_status inverse_fields(bsp_plan p, const cplx_t<T>* src, int64_t src_ell_stri
     px.tiles = p->tune_tiles;
     px.nouter = nb;
     px.in_outer = 0;
-    px.out_outer = (int64_t)Nr * wb * czb;
+    px.out_outer = (int64_t)S * wb * czb;
     px.in_row = (int64_t)w * cz;
     px.out_row = (int64_t)wb * czb;
     px.ncols = wb * czb;
@@ -777,11 +809,11 @@ bsp_status inverse_fields(bsp_plan p, const cplx_t<T>* src, int64_t src_ell_stri
     px.out_js = czb;
     px.in_rows = wb;
     px.in_off = cb;
-    px.out_rows = Nr;
-    px.out_off = 0;
+    px.out_rows = S;              // output row r holds x = x0 + r
+    px.out_off = (Nr - x0) % Nr;
     PassDesc py{};
     py.tiles = p->tune_tiles;
-    py.nouter = nb * Nr;
+    py.nouter = nb * S;
     py.in_outer = (int64_t)wb * czb;
     py.out_outer = (int64_t)Nr * czb;
     py.in_row = czb;
@@ -800,6 +832,7 @@ bsp_status inverse_fields(bsp_plan p, const cplx_t<T>* src, int64_t src_ell_stri
       // z pass, and the real field written once (batching on the widest band of
       // a batch is the kernels' overhead, not part of the minimum)
       double a5 = 0.0, a6 = 0.0, a7 = 0.0;
+      // (per slab: the modes read once per slab, the rest in proportion to S)
       for (int f = f0; f < f0 + nb; ++f) {
         const double c1 = cf[f] + 1.0, w1 = 2.0 * cf[f] + 1.0;
         double sup = w1 * w1 * c1, cols = w1 * c1;
@@ -807,9 +840,9 @@ bsp_status inverse_fields(bsp_plan p, const cplx_t<T>* src, int64_t src_ell_stri
           sup = (double)p->row_support32[frow32[f]];
           cols = (double)p->row_cols32[frow32[f]];
         }
-        a5 += (sup + (double)Nr * cols) * 8.0;
-        a6 += ((double)Nr * cols + (double)Nr * Nr * c1) * 8.0;
-        a7 += (double)Nr * Nr * c1 * 8.0 + (double)Nr * Nr * Nr * 4.0;
+        a5 += (sup + (double)S * cols) * 8.0;
+        a6 += ((double)S * cols + (double)S * Nr * c1) * 8.0;
+        a7 += (double)S * Nr * c1 * 8.0 + (double)S * Nr * Nr * 4.0;
       }
       {
         StageTimer t(p, 5, a5);
@@ -820,25 +853,28 @@ bsp_status inverse_fields(bsp_plan p, const cplx_t<T>* src, int64_t src_ell_stri
         HIPCHK(launch_c2c_f32(Nr, +1, Xb, Yb, py, nullptr, p->tw32_Nr, p->stream));
       }
       StageTimer t(p, 7, a7);
-      HIPCHK(launch_inv_z_f32(Nr, Yb, out + (int64_t)f0 * Nr * Nr * Nr, nb, cb + 1, czb, (int64_t)Nr * Nr * czb,
-                              (int64_t)Nr * Nr * Nr, p->tw32_Nr, p->stream));
+      HIPCHK(launch_inv_z_f32(Nr, Yb, out + (int64_t)f0 * S * Nr * Nr, nb, (int64_t)S * Nr, cb + 1, czb,
+                              (int64_t)S * Nr * czb, (int64_t)S * Nr * Nr, p->tw32_Nr, p->stream));
     } else {
       HIPCHK(launch_c2c_f64(Nr, +1, nullptr, Xb, px, &fd, p->tw64_Nr, p->stream));
       HIPCHK(launch_c2c_f64(Nr, +1, Xb, Yb, py, nullptr, p->tw64_Nr, p->stream));
-      HIPCHK(launch_inv_z_f64(Nr, Yb, out + (int64_t)f0 * Nr * Nr * Nr, nb, cb + 1, czb, (int64_t)Nr * Nr * czb,
-                              (int64_t)Nr * Nr * Nr, p->tw64_Nr, p->stream));
+      HIPCHK(launch_inv_z_f64(Nr, Yb, out + (int64_t)f0 * S * Nr * Nr, nb, (int64_t)S * Nr, cb + 1, czb,
+                              (int64_t)S * Nr * czb, (int64_t)S * Nr * Nr, p->tw64_Nr, p->stream));
     }
   }
   return BSP_OK;
 }
 
+// accumulate: add this reduction's T to Tout (the next x-slab of a field
+// stack) instead of overwriting it.
 template <typename T>
 bsp_status run_reduce(bsp_plan p, const ReducePlan& rp, const T* fields, int64_t K, int prec, const float* scale,
-                      double* Tout, char* scratch, size_t scratch_bytes, double tscale, int64_t kc_min = 0) {
+                      double* Tout, char* scratch, size_t scratch_bytes, double tscale, int64_t kc_min = 0,
+                      bool accumulate = false) {
   const ReduceDesc d = make_desc(rp, K, K, prec, scale, kc_min);
   const size_t need = (size_t)d.nchunks * d.ntiles * 256 * sizeof(T);
   if (need > scratch_bytes) return fail(p, BSP_ERR_WORKSPACE, "workspace too small for reduction partials");
-  HIPCHK(launch_fill_u32(Tout, 0u, 2 * (int64_t)rp.npairs * rp.nthirds, p->stream));
+  if (!accumulate) HIPCHK(launch_fill_u32(Tout, 0u, 2 * (int64_t)rp.npairs * rp.nthirds, p->stream));
   if (d.ntiles == 0) return BSP_OK;
   if constexpr (sizeof(T) == 4) {
     {
@@ -847,10 +883,10 @@ bsp_status run_reduce(bsp_plan p, const ReducePlan& rp, const T* fields, int64_t
       HIPCHK(launch_reduce(prec, fields, d, reinterpret_cast<float*>(scratch), p->stream));
     }
     StageTimer t(p, 9);
-    HIPCHK(launch_combine_partials(scratch, 0, d, rp.npairs, rp.nthirds, Tout, tscale, p->stream));
+    HIPCHK(launch_combine_partials(scratch, 0, d, rp.npairs, rp.nthirds, Tout, tscale, accumulate, p->stream));
   } else {
     HIPCHK(launch_reduce_f64(fields, d, reinterpret_cast<double*>(scratch), p->stream));
-    HIPCHK(launch_combine_partials(scratch, 1, d, rp.npairs, rp.nthirds, Tout, tscale, p->stream));
+    HIPCHK(launch_combine_partials(scratch, 1, d, rp.npairs, rp.nthirds, Tout, tscale, accumulate, p->stream));
   }
   return BSP_OK;
 }
@@ -882,6 +918,36 @@ bsp_status field_scales(bsp_plan p, const float* fields, int nf, int64_t K, floa
   HIPCHK(hipGetLastError());
   hipLaunchKernelGGL(k_pow2_scale, dim3((nf + 63) / 64), dim3(64), 0, p->stream, tmp, nf, scale);
   HIPCHK(hipGetLastError());
+  return BSP_OK;
+}
+
+// The filtered inverse transforms of nf fields and their triple reduction into
+// T, one x-slab of p->slab planes at a time. The sum over x is additive, so
+// each slab is made in the field stack, reduced, and added to T in slab order
+// (a fixed order: T does not depend on timing); the stack holds slab / N' of
+// the whole fields. With FP16 splits (scale given) the power-of-two scales are
+// taken per slab and undone per slab in the combine.
+template <typename T>
+bsp_status slab_reduce(bsp_plan p, const ReducePlan& rp, const cplx_t<T>* src, int64_t src_ell_stride, int nf,
+                       const int32_t* d_field_ell, const int32_t* d_field_tab, const T* tables,
+                       const int32_t* row_range, const std::vector<int>& cf, const int32_t* frow32, int fb,
+                       T* fields, int prec, float* scale, unsigned* tmpu, double* Tout, char* inv_scr,
+                       char* red_scr, size_t red_bytes, int64_t kc_min = 0) {
+  const int Nr = p->Nr, S = p->slab;
+  const int64_t K = (int64_t)S * Nr * Nr;
+  for (int x0 = 0; x0 < Nr; x0 += S) {
+    bsp_status s = inverse_fields<T>(p, src, src_ell_stride, nf, d_field_ell, d_field_tab, tables, row_range, fields,
+                                     inv_scr, fb, cf, frow32, x0, S);
+    if (s != BSP_OK) return s;
+    if constexpr (sizeof(T) == 4) {
+      if (scale) {
+        s = field_scales(p, fields, nf, K, scale, tmpu);
+        if (s != BSP_OK) return s;
+      }
+    }
+    s = run_reduce<T>(p, rp, fields, K, prec, scale, Tout, red_scr, red_bytes, 1.0, kc_min, x0 > 0);
+    if (s != BSP_OK) return s;
+  }
   return BSP_OK;
 }
 
@@ -1271,6 +1337,7 @@ bsp_status bsp_plan_create(bsp_plan* out, const bsp_geom* g, const bsp_modal_bas
     delete p;
     return fail(nullptr, BSP_ERR_ARG, "more than 128 shell and modal fields");
   }
+  p->slab = default_slab(p);
   // ---- device tables
   auto tw = [&](int n, bool dbl) -> void* {
     std::vector<double> t = twiddles(n);
@@ -1442,7 +1509,7 @@ bsp_status bsp_plan_info(bsp_plan p, bsp_info* info) {
   info->tune_tiles = p->tune_tiles;
   info->tune_kchunk = p->tune_kchunk;
   info->reduce_row_tiles = m.nrt;
-  info->reserved0 = 0;
+  info->slab_planes = p->slab;
   return BSP_OK;
 }
 
@@ -1452,6 +1519,20 @@ bsp_status bsp_workspace_size(bsp_plan p, size_t* bytes) {
   // a superset of the final one, so this bound stays valid afterwards
   const Layout L = layout(p);
   *bytes = std::max(L.total, L.pre_total);
+  return BSP_OK;
+}
+
+bsp_status bsp_set_slab(bsp_plan p, int32_t planes) {
+  if (!p) return BSP_ERR_ARG;
+  if (planes == 0) planes = default_slab(p);
+  if (planes < 1 || planes > p->Nr || p->Nr % planes != 0)
+    return fail(p, BSP_ERR_ARG, "slab planes must divide N'");
+  if (planes != p->slab) {
+    HIPCHK(hipStreamSynchronize(p->stream));
+    if (p->bslot.stream) HIPCHK(hipStreamSynchronize(p->bslot.stream));
+    p->bslot.release();  // a captured batch graph holds the launches of the old slabs
+    p->slab = planes;
+  }
   return BSP_OK;
 }
 
@@ -1471,7 +1552,7 @@ bsp_status bsp_sync(bsp_plan p) {
   if (e) {
     HIPCHK(hipMemset(p->d_err, 0, sizeof(int32_t)));
     if (e & 1) return fail(p, BSP_ERR_DEVICE, "particle outside [0, N) or not finite");
-    if (e & 4) return fail(p, BSP_ERR_NUMERIC, "triangle count residual >= 0.05");
+    if (e & 4) return fail(p, BSP_ERR_NUMERIC, "triangle count residual above 0.05 + rel |count| (or that bound >= 0.5)");
     if (e & 8) return fail(p, BSP_ERR_NUMERIC, "Gram matrix not positive definite");
     return fail(p, BSP_ERR_DEVICE, "device error");
   }
@@ -1636,7 +1717,7 @@ bsp_status bsp_fft_c2r(bsp_plan p, int32_t n, int32_t batch, const void* in_c64,
     py.in_rows = py.out_rows = n;
     set1d(py);
     HIPCHK(launch_c2c_f32(n, +1, tmp, tmp, py, nullptr, tw, p->stream));
-    HIPCHK(launch_inv_z_f32(n, tmp, out + (size_t)b * n * n * n, 1, h, h, 0, 0, tw, p->stream));
+    HIPCHK(launch_inv_z_f32(n, tmp, out + (size_t)b * n * n * n, 1, (int64_t)n * n, h, h, 0, 0, tw, p->stream));
   }
   return BSP_OK;
 }
@@ -1674,10 +1755,13 @@ bsp_status bsp_filter_fields(bsp_plan p, const void* delta_l, int32_t nfilt, con
     }
     fe[i] = li;
   }
+  // whole cubes into the caller's array (batches made smaller than the main
+  // pipeline's when its field stacks are x-slabs and the workspace is short)
   const Layout L = layout(p);
   const size_t meta = align_up(2 * (size_t)nfilt * sizeof(int32_t));
-  const int fb = std::min(L.fb, (nfilt + 1) / 2 * 2);
-  bsp_status s = need_ws(p, meta + inv_scratch(p, fb, sizeof(float2)));
+  int fb = std::min(L.fb, (nfilt + 1) / 2 * 2);
+  while (fb > 2 && meta + inv_scratch(p, fb, p->Nr, sizeof(float2)) > p->ws_bytes) fb -= 2;
+  bsp_status s = need_ws(p, meta + inv_scratch(p, fb, p->Nr, sizeof(float2)));
   if (s != BSP_OK) return s;
   int32_t* dmeta = reinterpret_cast<int32_t*>(p->ws);
   std::vector<int32_t> both(fe);
@@ -1749,15 +1833,14 @@ bsp_status bsp_precompute(bsp_plan p) {
   hipLaunchKernelGGL(k_fill_ones, dim3((unsigned)((p->spec + 255) / 256)), dim3(256), 0, p->stream, ones, p->spec);
   HIPCHK(hipGetLastError());
   // --- triangle counts: I_b for every shell, T[(b2,b3)][b1] over the candidates
-  s = inverse_fields<double>(p, ones, 0, p->nbins, p->d_ones_ell, p->d_pre_tab, p->d_tab64, p->d_rng64, f64, scr, L.fb64,
-                             std::vector<int>(p->row_c.begin(), p->row_c.begin() + p->nbins));
-  if (s != BSP_OK) return s;
-  s = run_reduce<double>(p, p->cnt_rp, f64, K, 3, nullptr, T64, scr, scr_bytes, 1.0);
+  s = slab_reduce<double>(p, p->cnt_rp, ones, 0, p->nbins, p->d_ones_ell, p->d_pre_tab, p->d_tab64, p->d_rng64,
+                          std::vector<int>(p->row_c.begin(), p->row_c.begin() + p->nbins), nullptr, L.fb64, f64, 3,
+                          nullptr, nullptr, T64, scr, scr, scr_bytes);
   if (s != BSP_OK) return s;
   int64_t* dc = reinterpret_cast<int64_t*>(scr);
   double* draw = reinterpret_cast<double*>(scr + align_up(p->cand.size() * sizeof(int64_t)));
-  HIPCHK(launch_counts_finalize(T64, p->d_cnt_tidx, (int)p->cand.size(), 1.0 / (double)K, dc, draw, p->d_err,
-                                p->stream));
+  HIPCHK(launch_counts_finalize(T64, p->d_cnt_tidx, (int)p->cand.size(), 1.0 / (double)K, count_rel_tol(K), dc, draw,
+                                p->d_err, p->stream));
   s = bsp_sync(p);
   if (s != BSP_OK) {
     // report the worst residual and its triangle
@@ -1796,10 +1879,9 @@ bsp_status bsp_precompute(bsp_plan p) {
   // --- modal geometry: Gram matrix, Cholesky factor, shot-noise integrals
   if (p->modal) {
     const int nm = p->nmodes;
-    s = inverse_fields<double>(p, ones, 0, p->nU, p->d_ones_ell, p->d_urow, p->d_tab64, p->d_rng64, f64, scr, L.fb64,
-                               std::vector<int>(p->nU, p->c));
-    if (s != BSP_OK) return s;
-    s = run_reduce<double>(p, p->gram_rp, f64, K, 3, nullptr, T64, scr, scr_bytes, 1.0);
+    s = slab_reduce<double>(p, p->gram_rp, ones, 0, p->nU, p->d_ones_ell, p->d_urow, p->d_tab64, p->d_rng64,
+                            std::vector<int>(p->nU, p->c), nullptr, L.fb64, f64, 3, nullptr, nullptr, T64, scr, scr,
+                            scr_bytes);
     if (s != BSP_OK) return s;
     HIPCHK(launch_gram_assemble(T64, p->d_gidx, nm, 1.0 / (6.0 * p->V * p->V * (double)K), p->d_L, p->stream));
     HIPCHK(hipStreamSynchronize(p->stream));
@@ -1815,10 +1897,9 @@ bsp_status bsp_precompute(bsp_plan p) {
     HIPCHK(hipMemcpy(p->piv_h.data(), p->d_piv, p->piv_h.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
     p->modal_rank = p->piv_h[nm];
     HIPCHK(launch_tri_inverse(p->d_L, p->d_piv, nm, p->d_Linv, p->stream));
-    s = inverse_fields<double>(p, ones, 0, 2 * p->P, p->d_ones_ell, p->d_grow, p->d_tab64, p->d_rng64, f64, scr, L.fb64,
-                               std::vector<int>(2 * p->P, p->c));
-    if (s != BSP_OK) return s;
-    s = run_reduce<double>(p, p->sn_rp, f64, K, 3, nullptr, T64, scr, scr_bytes, 1.0);
+    s = slab_reduce<double>(p, p->sn_rp, ones, 0, 2 * p->P, p->d_ones_ell, p->d_grow, p->d_tab64, p->d_rng64,
+                            std::vector<int>(2 * p->P, p->c), nullptr, L.fb64, f64, 3, nullptr, nullptr, T64, scr, scr,
+                            scr_bytes);
     if (s != BSP_OK) return s;
     HIPCHK(launch_sn_assemble(T64, p->d_sidx, nm, 1.0 / (p->V * p->V * (double)K), p->d_sn, p->stream));
     s = bsp_sync(p);
@@ -1980,7 +2061,8 @@ bsp_status bsp_autotune(bsp_plan p, bsp_precision prec, const char* db_path, int
   const bool timing = p->timing;
   p->timing = false;
   const int Nr = p->Nr;
-  const int64_t K = (int64_t)Nr * Nr * Nr;
+  // one x-slab of the field stack (every slab costs the same)
+  const int64_t K = (int64_t)p->slab * Nr * Nr;
   char* ws = p->ws;
   float2* dl = reinterpret_cast<float2*>(ws);
   float* fields = reinterpret_cast<float*>(ws + L.dl);
@@ -1999,7 +2081,7 @@ bsp_status bsp_autotune(bsp_plan p, bsp_precision prec, const char* db_path, int
     bsp_status st;
     const double ms = time_min(p, 3, [&]() {
       return inverse_fields<float>(p, dl, p->spec, p->F, p->d_field_ell, p->d_field_tab, p->d_tab32, p->d_rng32,
-                                   fields, scr, L.fb, p->field_c, p->field_row32.data());
+                                   fields, scr, L.fb, p->field_c, p->field_row32.data(), 0, p->slab);
     }, st);
     if (st != BSP_OK) {
       p->timing = timing;
@@ -2066,16 +2148,9 @@ bsp_status estimate_from_spectrum(bsp_plan p, const float2* dl, bsp_precision pr
   unsigned* tmpu = reinterpret_cast<unsigned*>(small + 3072);
   char* scr = ws + L.dl + L.fields + L.T + L.small;
   const size_t scr_bytes = p->ws_bytes - (L.dl + L.fields + L.T + L.small);
-  bsp_status s = inverse_fields<float>(p, dl, p->spec, p->F, p->d_field_ell, p->d_field_tab, p->d_tab32, p->d_rng32, fields, scr,
-                                       L.fb, p->field_c, p->field_row32.data());
-  if (s != BSP_OK) return s;
-  const float* sc = nullptr;
-  if (prec == BSP_FP16X3) {
-    s = field_scales(p, fields, p->F, K, scale, tmpu);
-    if (s != BSP_OK) return s;
-    sc = scale;
-  }
-  s = run_reduce<float>(p, p->main_rp, fields, K, kprec(prec), sc, T, scr, scr_bytes, 1.0);
+  bsp_status s = slab_reduce<float>(p, p->main_rp, dl, p->spec, p->F, p->d_field_ell, p->d_field_tab, p->d_tab32,
+                                    p->d_rng32, p->field_c, p->field_row32.data(), L.fb, fields, kprec(prec),
+                                    prec == BSP_FP16X3 ? scale : nullptr, tmpu, T, scr, scr, scr_bytes);
   if (s != BSP_OK) return s;
   HIPCHK(launch_fill_u32(psum, 0u, 2 * 64, p->stream));
   HIPCHK(launch_shell_power(dl, p->c, p->cz, p->d_bin_of_n2, p->n2max, p->nbins, psum, p->stream));
@@ -2231,7 +2306,7 @@ bsp_status bsp_skew_spectra(bsp_plan p, const void* delta_l, double* S, int32_t 
   const int Nr = p->Nr, c = p->c, cz = p->cz, w = 2 * c + 1;
   const size_t dbytes = align_up((size_t)Nr * Nr * Nr * sizeof(float));
   const size_t zb = align_up((size_t)Nr * Nr * cz * sizeof(float2)), yb = align_up((size_t)Nr * w * cz * sizeof(float2));
-  const size_t scr = std::max(inv_scratch(p, 2, sizeof(float2)), zb + yb);
+  const size_t scr = std::max(inv_scratch(p, 2, Nr, sizeof(float2)), zb + yb);
   const size_t acc = align_up((size_t)p->nl * p->nbins * sizeof(double));
   bsp_status s = need_ws(p, dbytes + scr + acc);
   if (s != BSP_OK) return s;
@@ -2451,6 +2526,7 @@ bsp_status bsp_bispectrum_full(bsp_plan p, const void* delta_l, bsp_precision pr
   if (s != BSP_OK) return s;
   const int Nr = p->Nr, nl = p->nl, nsh = p->nbins * nl;
   const int64_t K = (int64_t)Nr * Nr * Nr;
+  const int64_t Ks = (int64_t)p->slab * Nr * Nr;  // points of one x-slab
   char* ws = p->ws;
   float* fields = reinterpret_cast<float*>(ws + L.dl);
   double* small = reinterpret_cast<double*>(ws + L.dl + L.fields + L.T);
@@ -2458,28 +2534,23 @@ bsp_status bsp_bispectrum_full(bsp_plan p, const void* delta_l, bsp_precision pr
   unsigned* tmpu = reinterpret_cast<unsigned*>(small + 3072);
   char* scr = ws + L.dl + L.fields + L.T + L.small;
   const size_t scr_bytes = p->ws_bytes - (L.dl + L.fields + L.T + L.small);
-  // the shell fields D^l_b (the first nbins nl fields of the main numbering)
-  s = inverse_fields<float>(p, reinterpret_cast<const float2*>(delta_l), p->spec, nsh, p->d_field_ell,
-                            p->d_field_tab, p->d_tab32, p->d_rng32, fields, scr, L.fb, p->field_c,
-                            p->field_row32.data());
-  if (s != BSP_OK) return s;
-  const float* sc = nullptr;
-  if (prec == BSP_FP16X3) {
-    s = field_scales(p, fields, nsh, K, scale, tmpu);
-    if (s != BSP_OK) return s;
-    sc = scale;
-  }
   const ReducePlan& rp = p->full_rp;
+  // T first in the scratch (it accumulates over the slabs); the inverse
+  // passes and the reduction partials share the rest in turn
   double* T = reinterpret_cast<double*>(scr);
   const size_t tb = align_up((size_t)rp.npairs * rp.nthirds * sizeof(double));
-  if (scr_bytes <= tb) return fail(p, BSP_ERR_WORKSPACE, "workspace too small for the full multipoles");
+  if (scr_bytes <= tb + inv_scratch(p, L.fb, p->slab, sizeof(float2)))
+    return fail(p, BSP_ERR_WORKSPACE, "workspace too small for the full multipoles");
   // chunks long enough for the partials of every tile to fit the scratch
   const size_t avail = scr_bytes - tb;
   const int64_t per_chunk = (int64_t)rp.ntiles * 256 * (int64_t)sizeof(float);
   const int64_t max_chunks = std::max<int64_t>(1, (int64_t)(avail / std::max<int64_t>(per_chunk, 1)));
-  int64_t kc_min = (K + max_chunks - 1) / max_chunks;
+  int64_t kc_min = (Ks + max_chunks - 1) / max_chunks;
   kc_min = (kc_min + 63) / 64 * 64;
-  s = run_reduce<float>(p, rp, fields, K, kprec(prec), sc, T, scr + tb, avail, 1.0, kc_min);
+  // the shell fields D^l_b (the first nbins nl fields of the main numbering)
+  s = slab_reduce<float>(p, rp, reinterpret_cast<const float2*>(delta_l), p->spec, nsh, p->d_field_ell,
+                         p->d_field_tab, p->d_tab32, p->d_rng32, p->field_c, p->field_row32.data(), L.fb, fields,
+                         kprec(prec), prec == BSP_FP16X3 ? scale : nullptr, tmpu, T, scr + tb, scr + tb, avail, kc_min);
   if (s != BSP_OK) return s;
   const double N = p->N;
   const double norm_b = p->V * p->V / (std::pow(N, 9) * (double)K);
@@ -2595,6 +2666,7 @@ uint64_t config_hash(const bsp_plan p, bsp_precision prec) {
   mix(p->piv_h.data(), p->piv_h.size() * sizeof(int32_t));
   for (const auto& t : p->tri) mix(t.data(), 3 * sizeof(int));
   mixi((int)prec);
+  if (p->slab != p->Nr) mixi(p->slab);  // the slabs add T in another order (whole cubes keep their hash)
   return h;
 }
 

@@ -170,9 +170,10 @@ hipError_t launch_c2c_f32(int n, int sign, const float2* in, float2* out, const 
                           const FilterDesc* f, const float2* tw, hipStream_t s);
 hipError_t launch_c2c_f64(int n, int sign, const double2* in, double2* out, const PassDesc& p,
                           const FilterDesc* f, const double2* tw, hipStream_t s);
-hipError_t launch_inv_z_f32(int n, const float2* in, float* out, int nfields, int cin, int zs,
+// Last inverse pass (half complex along z to real), nlines lines per field.
+hipError_t launch_inv_z_f32(int n, const float2* in, float* out, int nfields, int64_t nlines, int cin, int zs,
                             int64_t in_field, int64_t out_field, const float2* tw, hipStream_t s);
-hipError_t launch_inv_z_f64(int n, const double2* in, double* out, int nfields, int cin, int zs,
+hipError_t launch_inv_z_f64(int n, const double2* in, double* out, int nfields, int64_t nlines, int cin, int zs,
                             int64_t in_field, int64_t out_field, const double2* tw, hipStream_t s);
 bool fft_size_supported(int n);
 
@@ -244,10 +245,11 @@ hipError_t launch_reduce(int prec, const float* fields, const ReduceDesc& d, flo
 hipError_t launch_reduce_f64(const double* fields, const ReduceDesc& d, double* partials,
                              hipStream_t s);
 // Adds the chunk partials in a fixed order (reproducible T); overwrites part
-// of the partials.
+// of the partials. accumulate = 1 adds the sums to T instead of storing them
+// (the x-slabs of one reduction, each combined in turn).
 hipError_t launch_combine_partials(void* partials, int is_f64, const ReduceDesc& d,
                                    int npairs, int nthirds, double* T, double tscale,
-                                   hipStream_t s);
+                                   int accumulate, hipStream_t s);
 int reduce_waves_per_group();
 // Register-budget shapes (rows, columns per wave) the kernel is instantiated for.
 struct ReduceShape { int maxr, maxcw; };
@@ -260,7 +262,8 @@ hipError_t launch_binned_finalize(const double* T, const int32_t* tri_tidx, int 
                                   const double* nbar, double* B, double* B0sub, double* Pbar, hipStream_t s);
 hipError_t launch_shot_noise(const double* Pl, int nbins, const int32_t* tri_bins, int ntri, int nl,
                              const double* ring, double nbar, double* SN, hipStream_t s);
-hipError_t launch_counts_finalize(const double* T, const int32_t* tidx, int ntri, double inv_k,
+// counts = rint(T * inv_k); residual bound 0.05 + rel |count| (latched as error bit 4)
+hipError_t launch_counts_finalize(const double* T, const int32_t* tidx, int ntri, double inv_k, double rel,
                                   int64_t* counts, double* raw, int32_t* err, hipStream_t s);
 hipError_t launch_modal_assemble(const double* T, const int32_t* combo, int nmodes, int nl,
                                  double scale, const double* sn, const double* nbar, double* bnum,

@@ -494,10 +494,12 @@ __global__ __launch_bounds__(BT) void k_c2c(const cplx_t<T>* __restrict__ in, cp
 
 // ---------------------------------------------------------------- inv_z
 // grid: blockIdx.x -> LZ_GROUPS consecutive groups of L lines, blockIdx.y -> field pair.
+// A field is nlines lines of zs inputs (N * N for a whole cube, fewer for an
+// x-slab of it) and nlines * N real outputs.
 template <typename T, int N>
 __global__ __launch_bounds__(256) void k_inv_z(const cplx_t<T>* __restrict__ in, T* __restrict__ out, int nfields,
-                                               int cin, int zs, int64_t in_field, int64_t out_field,
-                                               const cplx_t<T>* __restrict__ twg) {
+                                               int64_t nlines, int cin, int zs, int64_t in_field,
+                                               int64_t out_field, const cplx_t<T>* __restrict__ twg) {
   using V = cplx_t<T>;
   constexpr int NT = (N >= 8) ? N / 8 : 1;
   constexpr int L = 256 / NT;
@@ -507,7 +509,6 @@ __global__ __launch_bounds__(256) void k_inv_z(const cplx_t<T>* __restrict__ in,
   __shared__ V tw[N];
   for (int i = threadIdx.x; i < N; i += L * NT) tw[i] = twg[i];
   const int ll = threadIdx.x / NT, t = threadIdx.x % NT;
-  const int64_t nlines = (int64_t)N * N;
   const int f0 = 2 * blockIdx.y, f1 = f0 + 1;
   const bool has1 = f1 < nfields;
   V* b = buf + ll * PAD;
@@ -571,14 +572,14 @@ __global__ __launch_bounds__(256) void k_inv_z(const cplx_t<T>* __restrict__ in,
 
 bool fft_size_supported(int n) {
   switch (n) {
-    case 16: case 32: case 64: case 96: case 128: case 192: case 256: case 384: case 512:
+    case 16: case 32: case 64: case 96: case 128: case 192: case 256: case 384: case 512: case 1024:
       return true;
     default:
       return false;
   }
 }
 
-#define BSP_FOR_SIZES(X) X(16) X(32) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
+#define BSP_FOR_SIZES(X) X(16) X(32) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(1024)
 
 template <typename T>
 static hipError_t fwd_z_impl(int n, const T* in, cplx_t<T>* out, const FwdZDesc& d, const cplx_t<T>* tw,
@@ -626,14 +627,15 @@ static hipError_t c2c_launch(int sign, const cplx_t<T>* in, cplx_t<T>* out, cons
 }
 
 template <typename T>
-static hipError_t inv_z_impl(int n, const cplx_t<T>* in, T* out, int nfields, int cin, int zs,
+static hipError_t inv_z_impl(int n, const cplx_t<T>* in, T* out, int nfields, int64_t nlines, int cin, int zs,
                              int64_t in_field, int64_t out_field, const cplx_t<T>* tw, hipStream_t s) {
+  if (nlines < 1 || nlines > (int64_t)n * n || nfields < 1) return hipErrorInvalidValue;
 #define CASE(NN)                                                                                  \
   case NN: {                                                                                      \
     constexpr int NT = (NN >= 8) ? NN / 8 : 1;                                                    \
     constexpr int L = 256 / NT;                                                                   \
-    dim3 grid((unsigned)(((int64_t)NN * NN + L * LZ_GROUPS - 1) / (L * LZ_GROUPS)), (unsigned)((nfields + 1) / 2)); \
-    hipLaunchKernelGGL((k_inv_z<T, NN>), grid, dim3(L * NT), 0, s, in, out, nfields, cin, zs,     \
+    dim3 grid((unsigned)((nlines + L * LZ_GROUPS - 1) / (L * LZ_GROUPS)), (unsigned)((nfields + 1) / 2)); \
+    hipLaunchKernelGGL((k_inv_z<T, NN>), grid, dim3(L * NT), 0, s, in, out, nfields, nlines, cin, zs, \
                        in_field, out_field, tw);                                                  \
     return hipGetLastError();                                                                     \
   }
@@ -674,13 +676,13 @@ hipError_t launch_c2c_f64(int n, int sign, const double2* in, double2* out, cons
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_inv_z_f32(int n, const float2* in, float* out, int nfields, int cin, int zs,
+hipError_t launch_inv_z_f32(int n, const float2* in, float* out, int nfields, int64_t nlines, int cin, int zs,
                             int64_t in_field, int64_t out_field, const float2* tw, hipStream_t s) {
-  return inv_z_impl<float>(n, in, out, nfields, cin, zs, in_field, out_field, tw, s);
+  return inv_z_impl<float>(n, in, out, nfields, nlines, cin, zs, in_field, out_field, tw, s);
 }
-hipError_t launch_inv_z_f64(int n, const double2* in, double* out, int nfields, int cin, int zs,
+hipError_t launch_inv_z_f64(int n, const double2* in, double* out, int nfields, int64_t nlines, int cin, int zs,
                             int64_t in_field, int64_t out_field, const double2* tw, hipStream_t s) {
-  return inv_z_impl<double>(n, in, out, nfields, cin, zs, in_field, out_field, tw, s);
+  return inv_z_impl<double>(n, in, out, nfields, nlines, cin, zs, in_field, out_field, tw, s);
 }
 
 }  // namespace bsp

@@ -53,8 +53,11 @@ __global__ void k_shot_noise(const double* __restrict__ Pl, int nbins, const int
 // counts_i = round(T_i / N'^3); bit 2 of err if any |T/N'^3 - round| >= 0.05
 // (rounding is unambiguous below 0.5; FP64 sums of 1e8 terms of this dynamic
 // range leave ~1e-3 on counts of 1e10).
+// Counts round the FP64 sums; the residual from an integer must stay below
+// 0.05 + rel |c| (rel: the FP64 transforms' relative error, proportional to the
+// count), and that bound below 0.5, where the rounding is no longer certain.
 __global__ void k_counts_finalize(const double* __restrict__ T, const int32_t* __restrict__ tidx, int ntri,
-                                  double inv_k, int64_t* __restrict__ counts, double* __restrict__ raw,
+                                  double inv_k, double rel, int64_t* __restrict__ counts, double* __restrict__ raw,
                                   int32_t* __restrict__ err) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= ntri) return;
@@ -62,7 +65,8 @@ __global__ void k_counts_finalize(const double* __restrict__ T, const int32_t* _
   const double r = rint(c);
   counts[i] = (int64_t)r;
   raw[i] = c;
-  if (!(fabs(c - r) < 0.05)) atomicOr(err, 4);
+  const double tol = 0.05 + rel * fabs(c);
+  if (!(tol < 0.5 && fabs(c - r) < tol)) atomicOr(err, 4);
 }
 
 // bnum[l][m] = scale sum_{j<6, combo >= 0} T[combo[l][m][j]]  (minus shot noise for l = 0)
@@ -289,11 +293,11 @@ hipError_t launch_shot_noise(const double* Pl, int nbins, const int32_t* tri_bin
   return hipGetLastError();
 }
 
-hipError_t launch_counts_finalize(const double* T, const int32_t* tidx, int ntri, double inv_k, int64_t* counts,
-                                  double* raw, int32_t* err, hipStream_t s) {
+hipError_t launch_counts_finalize(const double* T, const int32_t* tidx, int ntri, double inv_k, double rel,
+                                  int64_t* counts, double* raw, int32_t* err, hipStream_t s) {
   if (ntri <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_counts_finalize, dim3(nblk(ntri, 256)), dim3(256), 0, s, T, tidx, ntri, inv_k, counts, raw,
-                     err);
+  hipLaunchKernelGGL(k_counts_finalize, dim3(nblk(ntri, 256)), dim3(256), 0, s, T, tidx, ntri, inv_k, rel, counts,
+                     raw, err);
   return hipGetLastError();
 }
 

@@ -200,14 +200,16 @@ __device__ __forceinline__ void write_t(double s, int tile, int e, const int32_t
                                         const int32_t* __restrict__ slot_pair, int npairs,
                                         int nthirds, const int32_t* __restrict__ pair_a,
                                         const int32_t* __restrict__ pair_b, const int32_t* __restrict__ third,
-                                        const float* __restrict__ scale, double tscale, double* __restrict__ T) {
+                                        const float* __restrict__ scale, double tscale, int accumulate,
+                                        double* __restrict__ T) {
   const int slot = tile_rc[2 * tile] * 16 + e / 16;
   const int th = tile_rc[2 * tile + 1] * 16 + e % 16;
   const int pr = slot_pair[slot];
   if (pr >= 0 && pr < npairs && th < nthirds) {
     double f = tscale;
     if (scale) f /= (double)scale[pair_a[slot]] * (double)scale[pair_b[slot]] * (double)scale[third[th]];
-    T[(int64_t)pr * nthirds + th] = s * f;
+    double* t = T + (int64_t)pr * nthirds + th;
+    *t = accumulate ? *t + s * f : s * f;
   }
 }
 
@@ -217,7 +219,7 @@ __global__ __launch_bounds__(256) void k_combine(PT* __restrict__ partials, int 
                                                  const int32_t* __restrict__ slot_pair, int npairs, int nthirds,
                                                  const int32_t* __restrict__ pair_a, const int32_t* __restrict__ pair_b,
                                                  const int32_t* __restrict__ third, const float* __restrict__ scale,
-                                                 double tscale, double* __restrict__ T) {
+                                                 double tscale, int accumulate, double* __restrict__ T) {
   const int tile = blockIdx.x;
   const int e = threadIdx.x;
   const int y = blockIdx.y;
@@ -226,7 +228,7 @@ __global__ __launch_bounds__(256) void k_combine(PT* __restrict__ partials, int 
   double s = 0.0;
   for (int c = c0; c < c1; ++c) s += (double)partials[((int64_t)c * ntiles + tile) * 256 + e];
   if (nranges == 1) {
-    write_t<PT>(s, tile, e, tile_rc, slot_pair, npairs, nthirds, pair_a, pair_b, third, scale, tscale, T);
+    write_t<PT>(s, tile, e, tile_rc, slot_pair, npairs, nthirds, pair_a, pair_b, third, scale, tscale, accumulate, T);
     return;
   }
   __syncthreads();  // every thread has read its values before the slots are overwritten
@@ -241,12 +243,12 @@ __global__ __launch_bounds__(256) void k_combine_ranges(PT* __restrict__ partial
                                                         const int32_t* __restrict__ pair_b,
                                                         const int32_t* __restrict__ third,
                                                         const float* __restrict__ scale, double tscale,
-                                                        double* __restrict__ T) {
+                                                        int accumulate, double* __restrict__ T) {
   const int tile = blockIdx.x;
   const int e = threadIdx.x;
   double s = 0.0;
   for (int y = 0; y < nranges; ++y) s += *park_slot(partials, y * cpb, ntiles, tile, e);
-  write_t<PT>(s, tile, e, tile_rc, slot_pair, npairs, nthirds, pair_a, pair_b, third, scale, tscale, T);
+  write_t<PT>(s, tile, e, tile_rc, slot_pair, npairs, nthirds, pair_a, pair_b, third, scale, tscale, accumulate, T);
 }
 
 int reduce_waves_per_group() { return WAVES; }
@@ -309,24 +311,24 @@ hipError_t launch_reduce_f64(const double* fields, const ReduceDesc& d, double* 
 }
 
 hipError_t launch_combine_partials(void* partials, int is_f64, const ReduceDesc& d, int npairs, int nthirds,
-                                   double* T, double tscale, hipStream_t s) {
+                                   double* T, double tscale, int accumulate, hipStream_t s) {
   const int cpb = 64;
   const int nranges = d.nchunks > cpb ? d.nchunks / cpb : 1;
   dim3 grid((unsigned)d.ntiles, (unsigned)nranges);
   if (is_f64) {
     double* pp = reinterpret_cast<double*>(partials);
     hipLaunchKernelGGL((k_combine<double>), grid, dim3(256), 0, s, pp, d.nchunks, d.ntiles, cpb, nranges, d.tile_rc, d.slot_pair,
-                       npairs, nthirds, d.pair_a, d.pair_b, d.third, d.scale, tscale, T);
+                       npairs, nthirds, d.pair_a, d.pair_b, d.third, d.scale, tscale, accumulate, T);
     if (nranges > 1)
       hipLaunchKernelGGL((k_combine_ranges<double>), dim3((unsigned)d.ntiles), dim3(256), 0, s, pp, d.ntiles, cpb,
-                         nranges, d.tile_rc, d.slot_pair, npairs, nthirds, d.pair_a, d.pair_b, d.third, d.scale, tscale, T);
+                         nranges, d.tile_rc, d.slot_pair, npairs, nthirds, d.pair_a, d.pair_b, d.third, d.scale, tscale, accumulate, T);
   } else {
     float* pp = reinterpret_cast<float*>(partials);
     hipLaunchKernelGGL((k_combine<float>), grid, dim3(256), 0, s, pp, d.nchunks, d.ntiles, cpb, nranges, d.tile_rc, d.slot_pair,
-                       npairs, nthirds, d.pair_a, d.pair_b, d.third, d.scale, tscale, T);
+                       npairs, nthirds, d.pair_a, d.pair_b, d.third, d.scale, tscale, accumulate, T);
     if (nranges > 1)
       hipLaunchKernelGGL((k_combine_ranges<float>), dim3((unsigned)d.ntiles), dim3(256), 0, s, pp, d.ntiles, cpb,
-                         nranges, d.tile_rc, d.slot_pair, npairs, nthirds, d.pair_a, d.pair_b, d.third, d.scale, tscale, T);
+                         nranges, d.tile_rc, d.slot_pair, npairs, nthirds, d.pair_a, d.pair_b, d.third, d.scale, tscale, accumulate, T);
   }
   return hipGetLastError();
 }

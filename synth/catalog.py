@@ -163,17 +163,21 @@ def quantise_grid_units(u: np.ndarray, n: int) -> np.ndarray:
     return q.astype(np.float32)
 
 
-def lognormal_catalogue(wl: Workload, seed: Optional[int] = None, observer=None):
-    """G1-G7 for one workload. Returns float32 arrays (ux, uy, uz) in grid units."""
+def lognormal_catalogue(wl: Workload, seed: Optional[int] = None, observer=None, log=None):
+    """G1-G7 for one workload. Returns float32 arrays (ux, uy, uz) in grid units.
+    log: optional callable given a line per generation step (large grids take minutes)."""
     n, box = wl.n, wl.box
     seed = wl.seed if seed is None else seed
+    say = log if log is not None else (lambda *_: None)
     g, G = gaussian_field(n, box, wl.ns, wl.sigma, seed, return_spectrum=True)
+    say("  gaussian field done")
     var = float(g.var())
     rho = np.exp(g - 0.5 * var)
     rho /= rho.mean()
     rng = np.random.Generator(np.random.PCG64(seed + 7_000_003))
     counts = rng.poisson(wl.nparticles * rho.ravel() / n ** 3)
     del rho
+    say("  poisson counts done")
     cells = np.repeat(np.arange(n ** 3, dtype=np.int64), counts)
     del counts
     ix = cells // (n * n)
@@ -196,6 +200,7 @@ def lognormal_catalogue(wl: Workload, seed: Optional[int] = None, observer=None)
         psi = sfft.irfftn(psi_k, s=(n, n, n), workers=-1) * (n / box)
         disp[a] = psi.ravel()[cells]
         del psi, psi_k
+        say(f"  displacement component {a} done")
     del G, g, cells
     if wl.los == 0:
         u[2] += wl.f * disp[2]

@@ -64,7 +64,7 @@ def test_fft_r2c_c2r_against_oracle(n):
 
 def _tiled_assign_bytes(npart, n):
     """Scratch the sorted, tiled assignment needs (8 x 8 x tz tiles, a 256-byte head)."""
-    tz = next(t for t in (64, 32, 16, 8) if n % t == 0 and n // t >= 2)
+    tz = next(t for t in (32, 16, 8) if n % t == 0 and n // t >= 2)
     nt = (n // 8) ** 2 * (n // tz)
     up = lambda b: (b + 255) // 256 * 256
     return 256 + up(npart * 16) + 2 * up((nt + 1) * 4) + up(npart * 4)
