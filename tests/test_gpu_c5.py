@@ -99,6 +99,8 @@ def c5_plan():
         f"count residual {plan.info.count_residual:.2e}")
     yield wl, plan
     plan.close()
+    plan.ws = None
+    torch.cuda.empty_cache()  # hand the 187 GiB workspace back before the next module's plans
 
 
 def test_c5_slab_precompute_counts(c5_plan):
@@ -132,6 +134,7 @@ def test_c5_mixed_against_fp32(c5_plan):
         plan.sync()
         say(f"c5 whole path prec {prec}: {time.time() - t0:.2f} s")
         out[prec] = (Bt.cpu().numpy(), al.cpu().numpy())
+    del u
     for li in range(nl):
         eb = rel_norm(out[B.BSP_BF16X3][0][li], out[B.BSP_FP32][0][li])
         ea = rel_norm(out[B.BSP_BF16X3][1][li], out[B.BSP_FP32][1][li])
