@@ -2535,11 +2535,16 @@ bsp_status bsp_bispectrum_full(bsp_plan p, const void* delta_l, bsp_precision pr
   char* scr = ws + L.dl + L.fields + L.T + L.small;
   const size_t scr_bytes = p->ws_bytes - (L.dl + L.fields + L.T + L.small);
   const ReducePlan& rp = p->full_rp;
-  // T first in the scratch (it accumulates over the slabs); the inverse
-  // passes and the reduction partials share the rest in turn
+  // T first in the scratch, the reduction partials after it. With one slab
+  // the inverse passes may use the whole scratch (T is zeroed after them);
+  // with several, T accumulates over the slabs and the inverse passes use the
+  // rest, in batches small enough to fit (the batching does not change a value)
   double* T = reinterpret_cast<double*>(scr);
   const size_t tb = align_up((size_t)rp.npairs * rp.nthirds * sizeof(double));
-  if (scr_bytes <= tb + inv_scratch(p, L.fb, p->slab, sizeof(float2)))
+  const bool one_slab = p->slab == Nr;
+  int fb = L.fb;
+  while (!one_slab && fb > 2 && tb + inv_scratch(p, fb, p->slab, sizeof(float2)) >= scr_bytes) fb -= 2;
+  if (scr_bytes <= tb || (!one_slab && scr_bytes <= tb + inv_scratch(p, fb, p->slab, sizeof(float2))))
     return fail(p, BSP_ERR_WORKSPACE, "workspace too small for the full multipoles");
   // chunks long enough for the partials of every tile to fit the scratch
   const size_t avail = scr_bytes - tb;
@@ -2549,8 +2554,9 @@ bsp_status bsp_bispectrum_full(bsp_plan p, const void* delta_l, bsp_precision pr
   kc_min = (kc_min + 63) / 64 * 64;
   // the shell fields D^l_b (the first nbins nl fields of the main numbering)
   s = slab_reduce<float>(p, rp, reinterpret_cast<const float2*>(delta_l), p->spec, nsh, p->d_field_ell,
-                         p->d_field_tab, p->d_tab32, p->d_rng32, p->field_c, p->field_row32.data(), L.fb, fields,
-                         kprec(prec), prec == BSP_FP16X3 ? scale : nullptr, tmpu, T, scr + tb, scr + tb, avail, kc_min);
+                         p->d_field_tab, p->d_tab32, p->d_rng32, p->field_c, p->field_row32.data(), fb, fields,
+                         kprec(prec), prec == BSP_FP16X3 ? scale : nullptr, tmpu, T, one_slab ? scr : scr + tb,
+                         scr + tb, avail, kc_min);
   if (s != BSP_OK) return s;
   const double N = p->N;
   const double norm_b = p->V * p->V / (std::pow(N, 9) * (double)K);
