@@ -260,9 +260,11 @@ def catalogue_case():
         del grids
         bn = torch.zeros((info.nl, wl.nmodes), dtype=torch.float64, device=DEV)
         B.bsp_modal_coeffs(plan.handle, dl, prec, 0.0, bn, None, None)
+        Bf = torch.zeros((info.nl ** 3, info.ntri), dtype=torch.float64, device=DEV)
+        B.bsp_bispectrum_full(plan.handle, dl, prec, Bf)
         plan.sync()
-        got[prec] = (Bt.cpu().numpy(), bn.cpu().numpy())
-        del dl
+        got[prec] = (Bt.cpu().numpy(), bn.cpu().numpy(), Bf.cpu().numpy())
+        del dl, Bf
     tri, counts = plan.tri.copy(), plan.counts.copy()
     del dv
     plan.close()
@@ -290,6 +292,20 @@ def test_full_size_catalogue_binned(catalogue_case):
             e = float(np.linalg.norm(got[prec][0][li, sel] - ref[li]) / np.linalg.norm(ref[li]))
             say("  catalogue B l", 2 * li, "prec", prec, "normwise err", e)
             assert e < tol, (li, prec, e)
+
+
+def test_full_size_catalogue_full_multipoles_contain_the_path(catalogue_case):
+    """B^(l00) of bsp_bispectrum_full at the bench plan (every (l1, l2, l3)
+    over the 90 shell fields, in the workspace the bench plan has) against the
+    whole path's B_l: the same sums, scheduled and chunked differently."""
+    _, _, _, _, got, _ = catalogue_case
+    nl = 3
+    for prec in (B.BSP_FP32, B.BSP_BF16X3):
+        Bl, _, Bf = got[prec]
+        for li in range(nl):
+            e = float(np.linalg.norm(Bf[li * nl * nl] - Bl[li]) / np.linalg.norm(Bl[li]))
+            say("  full multipoles B^(l00) vs path, l", 2 * li, "prec", prec, e)
+            assert e < 1e-12, (li, prec, e)
 
 
 def test_full_size_catalogue_modal_numerators(catalogue_case):
