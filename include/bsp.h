@@ -157,11 +157,14 @@ bsp_status bsp_set_workspace(bsp_plan plan, void* dev, size_t bytes);
  * `planes` x planes at a time, reduce it, and add its sums to T in slab order:
  * the stacks need planes / N' of the whole fields' memory (at 1024^3 the 114
  * FP32 fields of three multipoles, 30 shells and 8 modal functions take 490 GB
- * whole, 122 GB in slabs of 256 planes). The first inverse pass runs once per
- * slab (it transforms along x), so fewer, thicker slabs are faster. planes must
- * divide N'; 0 restores the plan's default, chosen at bsp_plan_create: N' when
- * the FP32 main stack and the FP64 precompute stack each fit in 128 GiB, else
- * the largest power-of-two fraction of N' for which both do. The results agree with whole cubes to the
+ * whole, 61 GB in slabs of 128 planes). The estimators' first inverse pass
+ * (along x) runs once per call into a resident buffer in the workspace (each
+ * batch of fields on its own band; 103 GB at 1024^3), whose rows the slabs'
+ * y passes read; the FP64 precompute repeats its x pass per slab instead.
+ * planes must divide N'; 0 restores the plan's default, chosen at
+ * bsp_plan_create: N' when the FP32 main stack and the FP64 precompute stack
+ * each fit in 64 GiB, else the largest power-of-two fraction of N' for which
+ * both do. The results agree with whole cubes to the
  * rounding of the FP64 sums of T (the slabs add in another order). Changes
  * bsp_workspace_size; call it between runs (it waits for the plan's streams
  * and drops a captured batch graph). */

@@ -528,6 +528,8 @@ struct Layout {
   size_t dl, fields, T, small, scratch, total;  // main pipeline
   size_t s_grid, s_Z, s_Y;                     // forward scratch pieces
   int fb;                                      // inverse batch
+  size_t xres;                                 // resident x-pass output (slabs only; 0 otherwise)
+  int fb_res;                                  // inverse batch with the resident x pass
   size_t pre_ones, pre_fields, pre_T, pre_scratch, pre_total;
   int fb64;
 };
@@ -535,7 +537,7 @@ struct Layout {
 // x planes per slab of the field stacks: all of N' when the FP32 main stack
 // and the FP64 precompute stack each stay within kSlabCap bytes, else the
 // largest power-of-two fraction of N' for which both do.
-constexpr size_t kSlabCap = 128ull << 30;
+constexpr size_t kSlabCap = 64ull << 30;
 int default_slab(const bsp_plan p) {
   const size_t plane = (size_t)p->Nr * p->Nr;
   const size_t nfp = std::max({p->nbins, p->modal ? p->nU : 0, p->modal ? 2 * p->P : 0});
@@ -558,6 +560,23 @@ double count_rel_tol(int64_t K) { return 32.0 * std::ldexp(1.0, -53) * std::log2
 size_t inv_scratch(const bsp_plan p, int fb, int S, size_t celem) {
   const size_t w = 2 * (size_t)p->c + 1;
   return align_up((size_t)fb * S * w * p->cz * celem) + align_up((size_t)fb * S * p->Nr * p->cz * celem);
+}
+
+std::vector<std::array<int, 2>> inverse_batches(int nf, int fb, int Nr, const std::vector<int>& cf);
+
+// The resident x-pass output of the main fields, batches of at most fb fields:
+// batch b holds [nb][N'][2 c_b + 1][cz_b] complex64 on its own band c_b (its
+// widest filter). Returns the bytes; offsets (optional) of each batch.
+size_t xres_bytes(const bsp_plan p, int fb, std::vector<size_t>* offsets = nullptr) {
+  size_t total = 0;
+  for (const auto& bt : inverse_batches(p->F, fb, p->Nr, p->field_c)) {
+    int cb = 0;
+    for (int f = bt[0]; f < bt[1]; ++f) cb = std::max(cb, p->field_c[f]);
+    const size_t czb = (size_t)(cb + 1 + 15) / 16 * 16, wb = 2 * (size_t)cb + 1;
+    if (offsets) offsets->push_back(total);
+    total += align_up((size_t)(bt[1] - bt[0]) * p->Nr * wb * czb * sizeof(float2));
+  }
+  return total;
 }
 
 Layout layout(const bsp_plan p) {
@@ -584,9 +603,23 @@ Layout layout(const bsp_plan p) {
   const size_t fullc2r = align_up((size_t)N * N * (N / 2 + 1) * sizeof(float2));
   // the grids plus the int64 node sums of the fixed-point assignment
   const size_t fixed = L.s_grid + align_up(assign_fixed_bytes(p->N, p->ngrid - 1));
+  // With x-slabs the main pipeline's x pass runs once per mock into a resident
+  // buffer (the forward scratch is dead by then), followed by the y-pass output
+  // of one batch (at most 8 GiB) or the reduction partials.
+  L.xres = 0;
+  L.fb_res = fb;
+  size_t res_need = 0;
+  if (p->slab < p->Nr) {
+    int fr = fb;
+    while (fr > 2 && (size_t)fr * S * Nr * p->cz * sizeof(float2) > (8ull << 30)) fr -= 2;
+    L.fb_res = fr;
+    L.xres = xres_bytes(p, fr);
+    res_need = L.xres + std::max(align_up((size_t)fr * S * Nr * p->cz * sizeof(float2)),
+                                 align_up(part) + align_up(1 << 20));
+  }
   // (two whole-cube fields: the single-field inverse of the skew spectra)
   L.scratch = std::max({fwd, inv_scratch(p, fb, p->slab, sizeof(float2)), inv_scratch(p, 2, p->Nr, sizeof(float2)),
-                        align_up(part) + align_up(1 << 20), fullc2r, fixed});
+                        align_up(part) + align_up(1 << 20), fullc2r, fixed, res_need});
   L.total = L.dl + L.fields + L.T + L.small + L.scratch;
   // FP64 precompute
   const int nfp = std::max({p->nbins, p->modal ? p->nU : 0, p->modal ? 2 * p->P : 0});
@@ -771,13 +804,23 @@ template <typename T>
 bsp_status inverse_fields(bsp_plan p, const cplx_t<T>* src, int64_t src_ell_stride, int nf,
                           const int32_t* d_field_ell, const int32_t* d_field_tab, const T* tables,
                           const int32_t* row_range, T* out, char* scratch, int fb, const std::vector<int>& cf,
-                          const int32_t* frow32 = nullptr, int x0 = 0, int S = 0) {
+                          const int32_t* frow32 = nullptr, int x0 = 0, int S = 0, cplx_t<T>* xres_out = nullptr,
+                          const cplx_t<T>* xres_in = nullptr) {
   const int Nr = p->Nr, c = p->c, cz = p->cz, w = 2 * c + 1;
   if (S == 0) S = Nr;
   if (S < 1 || x0 < 0 || x0 + S > Nr) return fail(p, BSP_ERR_ARG, "x-slab outside the grid");
+  // resident x pass (FP32 main fields, batches as xres_bytes lays them out):
+  // xres_out: only the x pass, all N' rows of every batch into the buffer;
+  // xres_in: no x pass, the y pass reads the slab's rows of the buffer
+  if (sizeof(T) != 4 && (xres_out || xres_in)) return fail(p, BSP_ERR_ARG, "resident x pass is FP32 only");
+  if (xres_out) {
+    x0 = 0;
+    S = Nr;
+  }
   using V = cplx_t<T>;
   V* Xb = reinterpret_cast<V*>(scratch);
-  V* Yb = reinterpret_cast<V*>(scratch + align_up((size_t)fb * S * w * cz * sizeof(V)));
+  V* Yb = reinterpret_cast<V*>(xres_in ? scratch : scratch + align_up((size_t)fb * S * w * cz * sizeof(V)));
+  size_t xoff = 0;  // offset (bytes) of the batch in the resident buffer
   for (const auto& bt : inverse_batches(nf, fb, Nr, cf)) {
     const int f0 = bt[0], nb = bt[1] - bt[0];
     int cb = 0;
@@ -844,11 +887,29 @@ bsp_status inverse_fields(bsp_plan p, const cplx_t<T>* src, int64_t src_ell_stri
         a6 += ((double)S * cols + (double)S * Nr * c1) * 8.0;
         a7 += (double)S * Nr * c1 * 8.0 + (double)S * Nr * Nr * 4.0;
       }
-      {
+      const size_t bbytes = align_up((size_t)nb * Nr * wb * czb * sizeof(V));
+      if (xres_out) {
         StageTimer t(p, 5, a5);
-        HIPCHK(launch_c2c_f32(Nr, +1, nullptr, Xb, px, &fd, p->tw32_Nr, p->stream));
+        HIPCHK(launch_c2c_f32(Nr, +1, nullptr, reinterpret_cast<V*>(reinterpret_cast<char*>(xres_out) + xoff), px, &fd,
+                              p->tw32_Nr, p->stream));
+        xoff += bbytes;
+        continue;
       }
-      {
+      if (xres_in) {
+        // one launch per field: its S rows x0.. are contiguous in [N'][wb][czb]
+        StageTimer t(p, 6, a6);
+        const V* xb = reinterpret_cast<const V*>(reinterpret_cast<const char*>(xres_in) + xoff);
+        PassDesc pf = py;
+        pf.nouter = S;
+        for (int f = 0; f < nb; ++f)
+          HIPCHK(launch_c2c_f32(Nr, +1, xb + ((int64_t)f * Nr + x0) * wb * czb, Yb + (int64_t)f * S * Nr * czb, pf,
+                                nullptr, p->tw32_Nr, p->stream));
+        xoff += bbytes;
+      } else {
+        {
+          StageTimer t(p, 5, a5);
+          HIPCHK(launch_c2c_f32(Nr, +1, nullptr, Xb, px, &fd, p->tw32_Nr, p->stream));
+        }
         StageTimer t(p, 6, a6);
         HIPCHK(launch_c2c_f32(Nr, +1, Xb, Yb, py, nullptr, p->tw32_Nr, p->stream));
       }
@@ -932,12 +993,18 @@ bsp_status slab_reduce(bsp_plan p, const ReducePlan& rp, const cplx_t<T>* src, i
                        const int32_t* d_field_ell, const int32_t* d_field_tab, const T* tables,
                        const int32_t* row_range, const std::vector<int>& cf, const int32_t* frow32, int fb,
                        T* fields, int prec, float* scale, unsigned* tmpu, double* Tout, char* inv_scr,
-                       char* red_scr, size_t red_bytes, int64_t kc_min = 0) {
+                       char* red_scr, size_t red_bytes, int64_t kc_min = 0, cplx_t<T>* xres = nullptr) {
   const int Nr = p->Nr, S = p->slab;
   const int64_t K = (int64_t)S * Nr * Nr;
+  if (xres) {
+    // the x pass once, all rows, into the resident buffer (not repeated per slab)
+    bsp_status s = inverse_fields<T>(p, src, src_ell_stride, nf, d_field_ell, d_field_tab, tables, row_range, fields,
+                                     inv_scr, fb, cf, frow32, 0, Nr, xres, nullptr);
+    if (s != BSP_OK) return s;
+  }
   for (int x0 = 0; x0 < Nr; x0 += S) {
     bsp_status s = inverse_fields<T>(p, src, src_ell_stride, nf, d_field_ell, d_field_tab, tables, row_range, fields,
-                                     inv_scr, fb, cf, frow32, x0, S);
+                                     inv_scr, fb, cf, frow32, x0, S, nullptr, xres);
     if (s != BSP_OK) return s;
     if constexpr (sizeof(T) == 4) {
       if (scale) {
@@ -2148,9 +2215,14 @@ bsp_status estimate_from_spectrum(bsp_plan p, const float2* dl, bsp_precision pr
   unsigned* tmpu = reinterpret_cast<unsigned*>(small + 3072);
   char* scr = ws + L.dl + L.fields + L.T + L.small;
   const size_t scr_bytes = p->ws_bytes - (L.dl + L.fields + L.T + L.small);
+  // with x-slabs the x pass is resident at the start of the scratch (the
+  // forward scratch is dead here), the y-pass batches and the partials after it
+  float2* xres = L.xres ? reinterpret_cast<float2*>(scr) : nullptr;
+  char* after = scr + L.xres;
   bsp_status s = slab_reduce<float>(p, p->main_rp, dl, p->spec, p->F, p->d_field_ell, p->d_field_tab, p->d_tab32,
-                                    p->d_rng32, p->field_c, p->field_row32.data(), L.fb, fields, kprec(prec),
-                                    prec == BSP_FP16X3 ? scale : nullptr, tmpu, T, scr, scr, scr_bytes);
+                                    p->d_rng32, p->field_c, p->field_row32.data(), L.xres ? L.fb_res : L.fb, fields,
+                                    kprec(prec), prec == BSP_FP16X3 ? scale : nullptr, tmpu, T, after, after,
+                                    scr_bytes - L.xres, 0, xres);
   if (s != BSP_OK) return s;
   HIPCHK(launch_fill_u32(psum, 0u, 2 * 64, p->stream));
   HIPCHK(launch_shell_power(dl, p->c, p->cz, p->d_bin_of_n2, p->n2max, p->nbins, psum, p->stream));

@@ -80,7 +80,7 @@ def test_fft_1024_sampled_parseval_round_trip():
         assert e.max() < 1e-5, e
     finally:
         plan.close()
-        torch.cuda.empty_cache()  # the 1024^3 plan below takes about 200 GB
+        torch.cuda.empty_cache()  # the 1024^3 plan below takes about 180 GB
 
 
 @pytest.fixture(scope="module")
@@ -100,12 +100,12 @@ def c5_plan():
     yield wl, plan
     plan.close()
     plan.ws = None
-    torch.cuda.empty_cache()  # hand the 187 GiB workspace back before the next module's plans
+    torch.cuda.empty_cache()  # hand the large workspace back before the next module's plans
 
 
 def test_c5_slab_precompute_counts(c5_plan):
     wl, plan = c5_plan
-    assert plan.info.slab_planes == 256
+    assert plan.info.slab_planes == 128
     # FP64 rounding of sums whose values are of the order of the count times
     # N'^3: the residual grows with the count (about 0.1 at 3e12), and the
     # rounding is certain while it stays below 0.5
